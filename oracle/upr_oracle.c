@@ -1,0 +1,514 @@
+/*
+ * CPU ORACLE for one synchronous round of penalised unconstrained refinement
+ * for balanced k-way graph partitioning (arXiv 2308.15494).
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product path may call, link or
+ * load this file: only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do. It is deliberately plain: one thread, straight loops,
+ * qsort where an order is needed, exact integer arithmetic (unsigned __int128
+ * where a product can exceed 64 bits), no blocking, fusion or reordering
+ * beyond what the definitions state. It shares no code or header with the GPU
+ * library.
+ *
+ * Notation follows Section 2 (Preliminaries): G = (V, E, c, omega), k blocks,
+ * Pi(v) the block of v, omega(v, V_j) the edge weight from v into block j
+ * ("conn[v][j]", the gain table), omega(I(v)) the weighted degree ("wdeg"),
+ * c(V_j) the block weight ("W[j]"), L_max = (1+eps) * ceil(c(V)/k).
+ *
+ * The paper's refinement (localized parallel FM with multi-queue rebalancing,
+ * Sections 5 and 7) is nondeterministic. The round computed here is the
+ * deterministic synchronous form of it, with every open choice fixed:
+ *
+ *   S0  L_max, penalty table PENQ[l] = floor(tau * (3/2)^l * 2^16)
+ *   S1  gain table and block weights from the partition; cut_before
+ *   S1b rebalance-available set V_r (t = t_num/t_den), slots, bucket
+ *       weights c(B_{l,j}) and their prefix sums (Section 5.3)
+ *   S2  per node, the target block maximising
+ *          s(v,j) = (omega(v,V_j) - omega(v,V_a)) * 2^16 - P(v,j)
+ *       where P is the Section 5.3 penalty in Q16 fixed point; a node is a
+ *       candidate iff the best s is > 0 (label-propagation style positive
+ *       moves, Section 6)
+ *   S3  conflict filter: order candidates by (s desc, id asc); for each
+ *       candidate recompute a pessimistic gain assuming every earlier
+ *       candidate neighbour ends in whichever of its two blocks is worse for
+ *       this move; accept iff that gain * 2^16 - P > 0. Applying the accepted
+ *       moves one by one in that order lowers the cut at every step.
+ *   S4  apply accepted moves; delta-update the gain table and block weights
+ *   S5  rebalance (Section 7.1) in synchronous sub-iterations
+ *   S6  final cut and statistics
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_SLOTS 54               /* slots 0..53; 1.5^53 > 2^31 covers any int32 ratio */
+#define ORC_RB_BUCKETS (2 * ORC_SLOTS + 1)
+#define ORC_PEN_CAP ((int64_t)1 << 62)
+
+typedef unsigned __int128 u128;
+
+typedef struct {
+    int64_t n;
+    const int64_t *xadj;
+    const int32_t *adjncy;
+    const int32_t *adjwgt; /* NULL: every edge weight is 1 */
+    const int32_t *vwgt;   /* NULL: every node weight is 1 */
+} orc_graph;
+
+typedef struct {
+    int32_t k;
+    int32_t eps_num, eps_den;
+    int32_t t_num, t_den;
+    int32_t tau_num, tau_den;
+    int32_t mode;            /* 0 penalised, 1 constrained, 2 penalty-free */
+    int32_t rebuild_table;   /* 1: conn and W are recomputed from part */
+    int32_t max_rebalance_iters; /* 0: default */
+} orc_params;
+
+/* Statistics, same order as the int64 slots the tests read. */
+enum {
+    ST_LMAX = 0, ST_CUT_BEFORE, ST_CUT_AFTER_MOVES, ST_CUT_AFTER, ST_CANDIDATES,
+    ST_ACCEPTED, ST_REBAL_MOVES, ST_REBAL_ITERS, ST_STATUS, ST_COUNT = 12
+};
+
+/* Optional per-node outputs of the move phase (any pointer may be NULL). */
+typedef struct {
+    int32_t *target;  /* best target if candidate, else -1 */
+    int64_t *score;   /* s(v, target) if candidate, else 0 */
+    int64_t *pen;     /* P(v, target) if candidate, else 0 */
+    uint8_t *accept;  /* 1 if the move survived the conflict filter */
+} orc_debug;
+
+static int64_t edge_w(const orc_graph *g, int64_t e) { return g->adjwgt ? g->adjwgt[e] : 1; }
+static int64_t node_c(const orc_graph *g, int64_t v) { return g->vwgt ? g->vwgt[v] : 1; }
+
+/* ---------------------------------------------------------------- S0 -- */
+
+/* Balance constraint of Section 2: L_max = (1 + eps) * ceil(c(V) / k), with
+ * eps = eps_num / eps_den rational and the product rounded down, since block
+ * weights are integers and c(V_i) <= L_max is the constraint. */
+int64_t orc_lmax(int64_t total, int32_t k, int32_t eps_num, int32_t eps_den)
+{
+    int64_t per = (total + k - 1) / k;                       /* ceil(c(V)/k) */
+    u128 num = (u128)per * (u128)((int64_t)eps_den + eps_num);
+    return (int64_t)(num / (u128)eps_den);
+}
+
+/* Slot of Section 5.3: slot = ceil(log_{3/2}(w / c)), i.e. the smallest l
+ * with (3/2)^l >= w/c, i.e. w * 2^l <= c * 3^l. Clamped to [0, 53]: ratios
+ * below 1 (and w = 0) land in slot 0, the sums of Section 5.3 start there. */
+int32_t orc_slot(int64_t w, int64_t c)
+{
+    u128 p3 = 1;
+    for (int l = 0; l < ORC_SLOTS; ++l) {
+        if (((u128)w << l) <= (u128)c * p3) return l;
+        p3 *= 3;
+    }
+    return ORC_SLOTS - 1;
+}
+
+/* Penalty factor of slot l (Section 5.3 penalty (3/2)^l * c(u), scaled by the
+ * round's tau from Section 5.5), in Q16 fixed point, rounded down:
+ * PENQ[l] = floor(tau_num * 3^l * 2^16 / (tau_den * 2^l)). */
+void orc_penq(int32_t tau_num, int32_t tau_den, int64_t *out)
+{
+    u128 p3 = 1;
+    for (int l = 0; l < ORC_SLOTS; ++l) {
+        u128 num = (u128)(uint64_t)tau_num * p3;
+        u128 den = (u128)(uint64_t)tau_den << l;
+        u128 q = num / den, r = num % den;
+        out[l] = (int64_t)(q * 65536 + (r * 65536) / den);
+        p3 *= 3;
+    }
+}
+
+int64_t orc_total_weight(const orc_graph *g)
+{
+    int64_t s = 0;
+    for (int64_t v = 0; v < g->n; ++v) s += node_c(g, v);
+    return s;
+}
+
+/* ---------------------------------------------------------------- S1 -- */
+
+/* Gain table of the shared-memory FM (Section 7.1): conn[v][j] = omega(v, V_j). */
+void orc_gain_table(const orc_graph *g, int32_t k, const int32_t *part, int32_t *conn)
+{
+    for (int64_t v = 0; v < g->n; ++v) {
+        int32_t *row = conn + v * (int64_t)k;
+        for (int32_t j = 0; j < k; ++j) row[j] = 0;
+        for (int64_t e = g->xadj[v]; e < g->xadj[v + 1]; ++e)
+            row[part[g->adjncy[e]]] += (int32_t)edge_w(g, e);
+    }
+}
+
+/* c(V_j) for every block. */
+void orc_block_weights(const orc_graph *g, int32_t k, const int32_t *part, int64_t *W)
+{
+    for (int32_t j = 0; j < k; ++j) W[j] = 0;
+    for (int64_t v = 0; v < g->n; ++v) W[part[v]] += node_c(g, v);
+}
+
+/* Edge cut straight from the definition of Section 2: total weight of edges
+ * whose endpoints lie in different blocks, each undirected edge once. */
+int64_t orc_cut_edges(const orc_graph *g, const int32_t *part)
+{
+    int64_t cut = 0;
+    for (int64_t v = 0; v < g->n; ++v)
+        for (int64_t e = g->xadj[v]; e < g->xadj[v + 1]; ++e) {
+            int64_t u = g->adjncy[e];
+            if (v < u && part[v] != part[u]) cut += edge_w(g, e);
+        }
+    return cut;
+}
+
+static int64_t wdeg(const orc_graph *g, int64_t v)
+{
+    int64_t s = 0;
+    for (int64_t e = g->xadj[v]; e < g->xadj[v + 1]; ++e) s += edge_w(g, e);
+    return s;
+}
+
+/* Cut from the gain table: every cut edge leaves its two endpoints' own
+ * blocks, so 2 * cut = sum_v (omega(I(v)) - omega(v, Pi(v))). */
+int64_t orc_cut_table(const orc_graph *g, int32_t k, const int32_t *part, const int32_t *conn)
+{
+    int64_t twice = 0;
+    for (int64_t v = 0; v < g->n; ++v) twice += wdeg(g, v) - conn[v * (int64_t)k + part[v]];
+    return twice / 2;
+}
+
+/* ---------------------------------------------------------------- S4 -- */
+
+/* Move v from its block to b, keeping conn and W consistent (Section 7.1:
+ * block weights and the gain table are updated as nodes move). */
+static void apply_move(const orc_graph *g, int32_t k, int32_t *part, int32_t *conn, int64_t *W,
+                       int64_t v, int32_t b)
+{
+    int32_t a = part[v];
+    if (a == b) return;
+    W[a] -= node_c(g, v);
+    W[b] += node_c(g, v);
+    for (int64_t e = g->xadj[v]; e < g->xadj[v + 1]; ++e) {
+        int64_t u = g->adjncy[e];
+        conn[u * (int64_t)k + a] -= (int32_t)edge_w(g, e);
+        conn[u * (int64_t)k + b] += (int32_t)edge_w(g, e);
+    }
+    part[v] = b;
+}
+
+/* ---------------------------------------------------------------- S5 -- */
+
+/* One node in a selection list: grouped by blk, then ordered by (beta, id). */
+typedef struct { int32_t blk; int32_t beta; int64_t id; int64_t c; } rb_item;
+
+static int rb_cmp(const void *x, const void *y)
+{
+    const rb_item *a = (const rb_item *)x, *b = (const rb_item *)y;
+    if (a->blk != b->blk) return a->blk < b->blk ? -1 : 1;
+    if (a->beta != b->beta) return a->beta < b->beta ? -1 : 1;
+    return a->id < b->id ? -1 : (a->id > b->id);
+}
+
+/* Rebalancing of Section 7.1, made synchronous.
+ *
+ * While some block is overloaded (W[j] > L_max), one sub-iteration:
+ *  1. Every node v of an overloaded block a (just-moved nodes included)
+ *     picks its move with the best gain among targets that stay balanced
+ *     (W[j] + c(v) <= L_max, j != a); if it is connected to none of them it
+ *     picks the lightest block (ties to the smaller id). No valid target:
+ *     v cannot move. Gain g = omega(v, target) - omega(v, a).
+ *     Priority (higher first): g * c(v) if g >= 0, g / c(v) if g < 0. It is
+ *     bucketed monotonically into beta (lower first):
+ *        g >  0: beta = S - 1 - slot(g * c(v), 1)
+ *        g == 0: beta = S
+ *        g <  0: beta = S + 1 + slot(-g, c(v))
+ *  2. Each overloaded block a selects the minimal prefix of its movable
+ *     nodes in (beta, id) order whose weight covers W[a] - L_max (all of
+ *     them if they do not suffice).
+ *  3. Each target j accepts the maximal prefix, in (beta, id) order, of the
+ *     selected nodes aiming at it whose weight fits L_max - W[j].
+ *  4. The accepted nodes move (as in S4). If nothing moved, stop stuck.
+ * All of 1-3 read the sub-iteration's starting W and conn.
+ */
+static int rebalance_iterate(const orc_graph *g, const orc_params *p, int64_t lmax, int32_t *part,
+                             int32_t *conn, int64_t *W, int64_t *moves_out, int64_t *iters_out)
+{
+    const int32_t k = p->k;
+    const int64_t n = g->n;
+    int64_t it_max = p->max_rebalance_iters > 0 ? p->max_rebalance_iters
+                     : (g->vwgt ? 4 * (int64_t)k : (int64_t)k + 1);
+    int32_t *tgt = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *beta = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    uint8_t *sel = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+    rb_item *items = (rb_item *)malloc(sizeof(rb_item) * (size_t)(n > 0 ? n : 1));
+    int64_t *W0 = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
+    int64_t moves = 0, iters = 0;
+    int status = 0;
+
+    for (;;) {
+        int any_over = 0;
+        for (int32_t j = 0; j < k; ++j) any_over |= (W[j] > lmax);
+        if (!any_over) break;
+        if (iters >= it_max) { status = 1; break; }
+        ++iters;
+        memcpy(W0, W, sizeof(int64_t) * (size_t)k);
+
+        /* step 1 */
+        for (int64_t v = 0; v < n; ++v) {
+            tgt[v] = -1;
+            sel[v] = 0;
+            int32_t a = part[v];
+            if (W0[a] <= lmax) continue;
+            int64_t cv = node_c(g, v);
+            const int32_t *row = conn + v * (int64_t)k;
+            int32_t best = -1;
+            for (int32_t j = 0; j < k; ++j) {
+                if (j == a || W0[j] + cv > lmax || row[j] <= 0) continue;
+                if (best < 0 || row[j] > row[best]) best = j;
+            }
+            if (best < 0) {
+                for (int32_t j = 0; j < k; ++j) {
+                    if (j == a || W0[j] + cv > lmax) continue;
+                    if (best < 0 || W0[j] < W0[best]) best = j;
+                }
+            }
+            if (best < 0) continue;
+            tgt[v] = best;
+            int64_t gain = (int64_t)row[best] - row[a];
+            if (gain > 0)
+                beta[v] = ORC_SLOTS - 1 - orc_slot(gain * cv, 1);
+            else if (gain == 0)
+                beta[v] = ORC_SLOTS;
+            else
+                beta[v] = ORC_SLOTS + 1 + orc_slot(-gain, cv);
+        }
+
+        /* step 2: per overloaded source block, minimal covering prefix */
+        int64_t cnt = 0;
+        for (int64_t v = 0; v < n; ++v)
+            if (tgt[v] >= 0) {
+                items[cnt].blk = part[v]; items[cnt].beta = beta[v];
+                items[cnt].id = v; items[cnt].c = node_c(g, v); ++cnt;
+            }
+        qsort(items, (size_t)cnt, sizeof(rb_item), rb_cmp);
+        for (int64_t i = 0; i < cnt;) {
+            int32_t a = items[i].blk;
+            int64_t need = W0[a] - lmax, got = 0;
+            for (; i < cnt && items[i].blk == a; ++i)
+                if (got < need) { sel[items[i].id] = 1; got += items[i].c; }
+        }
+
+        /* step 3: per target, maximal prefix within capacity */
+        int64_t moved_now = 0;
+        cnt = 0;
+        for (int64_t v = 0; v < n; ++v)
+            if (sel[v]) {
+                items[cnt].blk = tgt[v]; items[cnt].beta = beta[v];
+                items[cnt].id = v; items[cnt].c = node_c(g, v); ++cnt;
+            }
+        qsort(items, (size_t)cnt, sizeof(rb_item), rb_cmp);
+        for (int64_t i = 0; i < cnt;) {
+            int32_t j = items[i].blk;
+            int64_t cap = lmax - W0[j], used = 0;
+            int full = 0;
+            for (; i < cnt && items[i].blk == j; ++i) {
+                if (full || used + items[i].c > cap) { full = 1; continue; }
+                used += items[i].c;
+                sel[items[i].id] = 2; /* accepted */
+            }
+        }
+
+        /* step 4 */
+        for (int64_t v = 0; v < n; ++v)
+            if (sel[v] == 2) {
+                apply_move(g, k, part, conn, W, v, tgt[v]);
+                ++moved_now;
+            }
+        moves += moved_now;
+        if (moved_now == 0) { status = 1; break; }
+    }
+    free(tgt); free(beta); free(sel); free(items); free(W0);
+    *moves_out = moves;
+    *iters_out = iters;
+    return status;
+}
+
+/* --------------------------------------------------------------- S1b -- */
+
+/* Rebalance-available set and penalty buckets of Section 5.3: v is available
+ * iff omega(v, Pi(v)) >= t * omega(I(v)) (exact: t_den * inner >= t_num * wdeg);
+ * an available node goes to bucket (Pi(v), slot(omega(v, Pi(v)), c(v))), and
+ * bucket[j * 54 + l] = c(B_{l,j}) is the node weight collected there.
+ * avail[v] (optional) receives 1 + slot for available nodes, 0 otherwise. */
+void orc_penalty_buckets(const orc_graph *g, int32_t k, const int32_t *part, const int32_t *conn,
+                         int32_t t_num, int32_t t_den, int64_t *bucket, int32_t *avail)
+{
+    for (int64_t i = 0; i < (int64_t)k * ORC_SLOTS; ++i) bucket[i] = 0;
+    for (int64_t v = 0; v < g->n; ++v) {
+        int32_t a = part[v];
+        int64_t inner = conn[v * (int64_t)k + a];
+        int32_t s = -1;
+        if ((int64_t)t_den * inner >= (int64_t)t_num * wdeg(g, v)) {
+            s = orc_slot(inner, node_c(g, v));
+            bucket[(int64_t)a * ORC_SLOTS + s] += node_c(g, v);
+        }
+        if (avail) avail[v] = s + 1;
+    }
+}
+
+/* ------------------------------------------------------------- rounds -- */
+
+static int check_params(const orc_graph *g, const orc_params *p, const int32_t *part)
+{
+    if (p->k < 2 || p->eps_num <= 0 || p->eps_den <= 0) return -1;
+    if (p->t_num < 0 || p->t_den <= 0 || p->t_num > p->t_den) return -1;
+    if (p->tau_num < 0 || p->tau_den <= 0 || p->tau_num > p->tau_den) return -1;
+    if (p->mode < 0 || p->mode > 2) return -1;
+    for (int64_t v = 0; v < g->n; ++v)
+        if (part[v] < 0 || part[v] >= p->k) return -1;
+    return 0;
+}
+
+/* S0 + S1 shared by both entry points. */
+static void prepare(const orc_graph *g, const orc_params *p, const int32_t *part, int32_t *conn,
+                    int64_t *W, int64_t *stats, int64_t *lmax)
+{
+    for (int i = 0; i < ST_COUNT; ++i) stats[i] = 0;
+    *lmax = orc_lmax(orc_total_weight(g), p->k, p->eps_num, p->eps_den);
+    stats[ST_LMAX] = *lmax;
+    if (p->rebuild_table) {
+        orc_gain_table(g, p->k, part, conn);
+        orc_block_weights(g, p->k, part, W);
+    }
+    stats[ST_CUT_BEFORE] = orc_cut_table(g, p->k, part, conn);
+}
+
+int orc_refine_round(const orc_graph *g, const orc_params *p, int32_t *part, int32_t *conn,
+                     int64_t *W, int64_t *stats, const orc_debug *dbg)
+{
+    if (check_params(g, p, part)) return -1;
+    const int32_t k = p->k;
+    const int64_t n = g->n;
+    int64_t lmax;
+    prepare(g, p, part, conn, W, stats, &lmax);
+
+    /* S0 penalty table for this round's tau */
+    int64_t penq[ORC_SLOTS];
+    orc_penq(p->tau_num, p->tau_den, penq);
+
+    /* S1b */
+    int64_t *bucket = (int64_t *)calloc((size_t)k * ORC_SLOTS, sizeof(int64_t));
+    orc_penalty_buckets(g, k, part, conn, p->t_num, p->t_den, bucket, NULL);
+
+    /* S2: best penalised move per node, against the round-start W. */
+    int32_t *target = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *score = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *pen = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t candidates = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        int32_t a = part[v];
+        int64_t cv = node_c(g, v);
+        const int32_t *row = conn + v * (int64_t)k;
+        int32_t best = -1;
+        int64_t best_s = 0, best_p = 0;
+        for (int32_t j = 0; j < k; ++j) {
+            if (j == a || row[j] <= 0) continue;      /* adjacent blocks only */
+            int64_t delta = (int64_t)row[j] - row[a];  /* gain of the move v -> j */
+            int64_t excess = W[j] + cv - lmax;         /* c(V_j + v) - L_max */
+            int64_t P = 0;
+            if (excess > 0 && p->mode == 1) continue;  /* constrained: forbidden */
+            if (excess > 0 && p->mode == 0) {
+                /* minimal slot l with sum_{i<=l} c(B_{i,j}) >= excess */
+                int64_t acc = 0;
+                int l = -1;
+                for (int i = 0; i < ORC_SLOTS; ++i) {
+                    acc += bucket[(int64_t)j * ORC_SLOTS + i];
+                    if (acc >= excess) { l = i; break; }
+                }
+                if (l < 0) continue;                   /* no such slot: forbidden */
+                /* pen = tau * (3/2)^l * c(v), saturated */
+                if (penq[l] != 0 && cv > ORC_PEN_CAP / penq[l]) P = ORC_PEN_CAP;
+                else P = penq[l] * cv;
+                if (P > ORC_PEN_CAP) P = ORC_PEN_CAP;
+            }
+            int64_t s = delta * 65536 - P;
+            if (best < 0 || s > best_s) { best = j; best_s = s; best_p = P; }
+        }
+        if (best >= 0 && best_s > 0) {
+            target[v] = best; score[v] = best_s; pen[v] = best_p; ++candidates;
+        } else {
+            target[v] = -1; score[v] = 0; pen[v] = 0;
+        }
+    }
+    stats[ST_CANDIDATES] = candidates;
+
+    /* S3: conflict filter in (score desc, id asc) order. For candidate v
+     * moving a -> b, f(x) = +1 if x == b, -1 if x == a, else 0 is the change
+     * in v's internal edge weight contributed by a neighbour sitting in x.
+     * An earlier candidate neighbour u (before v in the order) may or may
+     * not move; take the worse of its two positions. */
+    uint8_t *accept = (uint8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
+    int64_t accepted = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        if (target[v] < 0) continue;
+        int32_t a = part[v], b = target[v];
+        int64_t gp = 0;
+        for (int64_t e = g->xadj[v]; e < g->xadj[v + 1]; ++e) {
+            int64_t u = g->adjncy[e];
+            int32_t pu = part[u];
+            int fu = pu == b ? 1 : (pu == a ? -1 : 0);
+            int earlier = target[u] >= 0 &&
+                          (score[u] > score[v] || (score[u] == score[v] && u < v));
+            if (earlier) {
+                int32_t tu = target[u];
+                int ft = tu == b ? 1 : (tu == a ? -1 : 0);
+                if (ft < fu) fu = ft;
+            }
+            gp += edge_w(g, e) * fu;
+        }
+        if (gp * 65536 - pen[v] > 0) { accept[v] = 1; ++accepted; }
+    }
+    stats[ST_ACCEPTED] = accepted;
+
+    /* S4: apply (commutative updates; the order does not matter). */
+    for (int64_t v = 0; v < n; ++v)
+        if (accept[v]) apply_move(g, k, part, conn, W, v, target[v]);
+    stats[ST_CUT_AFTER_MOVES] = orc_cut_table(g, k, part, conn);
+
+    /* S5 */
+    int64_t moves = 0, iters = 0;
+    stats[ST_STATUS] = rebalance_iterate(g, p, lmax, part, conn, W, &moves, &iters);
+    stats[ST_REBAL_MOVES] = moves;
+    stats[ST_REBAL_ITERS] = iters;
+
+    /* S6 */
+    stats[ST_CUT_AFTER] = orc_cut_table(g, k, part, conn);
+
+    if (dbg) {
+        for (int64_t v = 0; v < n; ++v) {
+            if (dbg->target) dbg->target[v] = target[v];
+            if (dbg->score) dbg->score[v] = score[v];
+            if (dbg->pen) dbg->pen[v] = pen[v];
+            if (dbg->accept) dbg->accept[v] = accept[v];
+        }
+    }
+    free(bucket); free(target); free(score); free(pen); free(accept);
+    return 0;
+}
+
+/* A standalone rebalancing call: S0, S1 (if rebuilding), S5, S6. */
+int orc_rebalance(const orc_graph *g, const orc_params *p, int32_t *part, int32_t *conn,
+                  int64_t *W, int64_t *stats)
+{
+    if (check_params(g, p, part)) return -1;
+    int64_t lmax;
+    prepare(g, p, part, conn, W, stats, &lmax);
+    stats[ST_CUT_AFTER_MOVES] = stats[ST_CUT_BEFORE];
+    int64_t moves = 0, iters = 0;
+    stats[ST_STATUS] = rebalance_iterate(g, p, lmax, part, conn, W, &moves, &iters);
+    stats[ST_REBAL_MOVES] = moves;
+    stats[ST_REBAL_ITERS] = iters;
+    stats[ST_CUT_AFTER] = orc_cut_table(g, p->k, part, conn);
+    return 0;
+}

@@ -1,0 +1,311 @@
+"""Seeded synthetic graph and partition generators.
+
+This module produces the *inputs* of a refinement round: an undirected graph
+G = (V, E, c, omega) with positive integer node weights c and edge weights
+omega (Section 2, Preliminaries), stored as a symmetric CSR, and an initial
+k-way partition. It holds none of the refinement arithmetic; both the CPU
+oracle and the HIP path consume what it produces.
+
+The paper evaluates on real graphs (Section 8.1, Table 1) split by the ratio of
+the standard deviation to the mean of the node degree: irregular graphs
+(social, web, power-law generators) and regular graphs (meshes, road networks,
+geometric graphs). Those datasets are stood in for by seeded generators with
+the same structure classes:
+
+* Chung-Lu expected-degree graphs with a power-law weight sequence
+  (irregular, like the paper's artificial power-law instances),
+* R-MAT (Chakrabarti, Zhan, Faloutsos 2004) with a seeded id permutation,
+* 2D 4-neighbour grids and 2D random geometric graphs (regular).
+
+CSR layout (all host numpy arrays):
+    xadj   int64[n+1], xadj[0] = 0, nondecreasing
+    adjncy int32[nnz], rows sorted ascending, symmetric, no self-loops,
+           no duplicates
+    adjwgt int32[nnz] or None (None = every edge weight 1)
+    vwgt   int32[n]   or None (None = every node weight 1)
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Graph:
+    n: int
+    xadj: np.ndarray
+    adjncy: np.ndarray
+    adjwgt: np.ndarray | None = None
+    vwgt: np.ndarray | None = None
+    name: str = ""
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.xadj[-1])
+
+    @property
+    def m(self) -> int:
+        """Number of undirected edges."""
+        return self.nnz // 2
+
+    def degrees(self) -> np.ndarray:
+        return np.diff(self.xadj)
+
+    def irregularity(self) -> float:
+        """Standard deviation over mean of the node degree (Section 8.1)."""
+        d = self.degrees().astype(np.float64)
+        mu = d.mean() if d.size else 0.0
+        return float(d.std() / mu) if mu > 0 else 0.0
+
+    def total_node_weight(self) -> int:
+        return int(self.n if self.vwgt is None else int(self.vwgt.astype(np.int64).sum()))
+
+
+def csr_from_undirected(n: int, u: np.ndarray, v: np.ndarray,
+                        w: np.ndarray | None = None) -> tuple:
+    """Symmetric CSR from undirected pairs.
+
+    Self-loops are dropped; duplicate pairs (in either orientation) are merged,
+    keeping the weight of the first occurrence. Rows come out sorted.
+    """
+    u = np.asarray(u, dtype=np.int64)
+    v = np.asarray(v, dtype=np.int64)
+    keep = u != v
+    u, v = u[keep], v[keep]
+    if w is not None:
+        w = np.asarray(w)[keep]
+    lo = np.minimum(u, v)
+    hi = np.maximum(u, v)
+    key = lo * n + hi
+    key, first = np.unique(key, return_index=True)
+    lo = key // n
+    hi = key % n
+    if w is not None:
+        w = w[first].astype(np.int32)
+    src = np.concatenate([lo, hi])
+    dst = np.concatenate([hi, lo])
+    order = np.argsort(src * n + dst, kind="stable")
+    src = src[order]
+    dst = dst[order]
+    counts = np.bincount(src, minlength=n) if n > 0 else np.zeros(0, np.int64)
+    xadj = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=xadj[1:])
+    adjncy = dst.astype(np.int32)
+    adjwgt = None
+    if w is not None:
+        adjwgt = np.concatenate([w, w])[order].astype(np.int32)
+    return xadj, adjncy, adjwgt
+
+
+def _finish(g: Graph) -> Graph:
+    d = g.degrees()
+    g.meta.setdefault("n", g.n)
+    g.meta["m"] = g.m
+    g.meta["nnz"] = g.nnz
+    g.meta["max_degree"] = int(d.max()) if d.size else 0
+    g.meta["irregularity"] = g.irregularity()
+    return g
+
+
+def _chung_lu_weights(n: int, avg_deg: float, beta: float, d_max: float) -> np.ndarray:
+    """Power-law weight sequence w_i = d_max * (i0 / (i + i0))^(1/(beta-1)).
+
+    i0 is found by bisection so that the mean weight equals avg_deg.
+    """
+    i = np.arange(n, dtype=np.float64)
+    gamma = 1.0 / (beta - 1.0)
+
+    def mean_for(i0: float) -> float:
+        return float((d_max * (i0 / (i + i0)) ** gamma).mean())
+
+    lo, hi = 1e-9, float(n) * 1e6
+    for _ in range(200):
+        mid = math.sqrt(lo * hi)
+        if mean_for(mid) < avg_deg:
+            lo = mid
+        else:
+            hi = mid
+    i0 = math.sqrt(lo * hi)
+    return d_max * (i0 / (i + i0)) ** gamma
+
+
+def chung_lu(n: int, avg_deg: float, beta: float, seed: int, d_max: float | None = None,
+             wmax: int = 0) -> Graph:
+    """Chung-Lu expected-degree graph in edge-sampling form.
+
+    floor(n*avg_deg/2) endpoint pairs are drawn with probability proportional
+    to the weight sequence; self-loops and duplicates are dropped. With
+    wmax > 0 every undirected edge gets a weight uniform in [1, wmax].
+    """
+    rng = np.random.default_rng(seed)
+    if d_max is None:
+        d_max = math.sqrt(n * avg_deg)
+    w = _chung_lu_weights(n, avg_deg, beta, d_max)
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    pairs = int(n * avg_deg // 2)
+    a = np.searchsorted(cdf, rng.random(pairs), side="right")
+    b = np.searchsorted(cdf, rng.random(pairs), side="right")
+    np.minimum(a, n - 1, out=a)
+    np.minimum(b, n - 1, out=b)
+    ew = rng.integers(1, wmax + 1, size=pairs, dtype=np.int32) if wmax > 0 else None
+    xadj, adjncy, adjwgt = csr_from_undirected(n, a, b, ew)
+    g = Graph(n, xadj, adjncy, adjwgt, None, name=f"chunglu_n{n}_d{avg_deg}_b{beta}_s{seed}")
+    g.meta.update(dict(kind="chung_lu", avg_deg=avg_deg, beta=beta, seed=seed,
+                       d_max=d_max, wmax=wmax, pairs=pairs))
+    return _finish(g)
+
+
+def rmat(scale: int, edge_factor: int, seed: int, a: float = 0.57, b: float = 0.19,
+         c: float = 0.19, permute: bool = True) -> Graph:
+    """R-MAT graph with 2^scale nodes and edge_factor * 2^scale draws.
+
+    Each draw descends scale levels of the adjacency matrix choosing the
+    quadrant with probabilities (a, b, c, d = 1 - a - b - c). Node ids are
+    passed through a seeded permutation so that hubs are not clustered at
+    small ids. Self-loops and duplicates are dropped.
+    """
+    rng = np.random.default_rng(seed)
+    n = 1 << scale
+    draws = edge_factor * n
+    src = np.zeros(draws, dtype=np.int64)
+    dst = np.zeros(draws, dtype=np.int64)
+    ab = a + b
+    abc = a + b + c
+    for lvl in range(scale):
+        r = rng.random(draws, dtype=np.float32)
+        bit = np.int64(1) << (scale - 1 - lvl)
+        row = r >= ab
+        col = ((r >= a) & (r < ab)) | (r >= abc)
+        src += row * bit
+        dst += col * bit
+    if permute:
+        perm = rng.permutation(n).astype(np.int64)
+        src = perm[src]
+        dst = perm[dst]
+    xadj, adjncy, _ = csr_from_undirected(n, src, dst)
+    g = Graph(n, xadj, adjncy, None, None, name=f"rmat_s{scale}_ef{edge_factor}_s{seed}")
+    g.meta.update(dict(kind="rmat", scale=scale, edge_factor=edge_factor, seed=seed,
+                       abcd=(a, b, c, 1 - a - b - c), draws=draws))
+    return _finish(g)
+
+
+def grid2d(rows: int, cols: int) -> Graph:
+    """4-neighbour grid, row-major ids."""
+    n = rows * cols
+    ids = np.arange(n, dtype=np.int64).reshape(rows, cols)
+    hu = ids[:, :-1].ravel()
+    hv = ids[:, 1:].ravel()
+    vu = ids[:-1, :].ravel()
+    vv = ids[1:, :].ravel()
+    xadj, adjncy, _ = csr_from_undirected(n, np.concatenate([hu, vu]), np.concatenate([hv, vv]))
+    g = Graph(n, xadj, adjncy, None, None, name=f"grid_{rows}x{cols}")
+    g.meta.update(dict(kind="grid2d", rows=rows, cols=cols))
+    return _finish(g)
+
+
+def rgg2d(n: int, seed: int, avg_deg: float = 8.0) -> Graph:
+    """2D random geometric graph in the unit square (no torus).
+
+    Radius r = sqrt(avg_deg / (pi * n)); the realised average degree is
+    slightly below avg_deg because of the boundary.
+    """
+    from scipy.spatial import cKDTree
+
+    rng = np.random.default_rng(seed)
+    pts = rng.random((n, 2))
+    r = math.sqrt(avg_deg / (math.pi * n))
+    pairs = cKDTree(pts).query_pairs(r, output_type="ndarray")
+    xadj, adjncy, _ = csr_from_undirected(n, pairs[:, 0], pairs[:, 1])
+    g = Graph(n, xadj, adjncy, None, None, name=f"rgg_n{n}_s{seed}")
+    g.meta.update(dict(kind="rgg2d", seed=seed, radius=r, target_avg_deg=avg_deg))
+    return _finish(g)
+
+
+def random_small(n: int, p: float, seed: int, wmax: int = 0, vmax: int = 0) -> Graph:
+    """Erdos-Renyi G(n, p) with optional uniform edge/node weights (for tests)."""
+    rng = np.random.default_rng(seed)
+    iu, ju = np.triu_indices(n, 1)
+    keep = rng.random(iu.size) < p
+    u, v = iu[keep], ju[keep]
+    ew = rng.integers(1, wmax + 1, size=u.size, dtype=np.int32) if wmax > 0 else None
+    xadj, adjncy, adjwgt = csr_from_undirected(n, u, v, ew)
+    vw = rng.integers(1, vmax + 1, size=n, dtype=np.int32) if vmax > 0 else None
+    g = Graph(n, xadj, adjncy, adjwgt, vw, name=f"er_n{n}_p{p}_s{seed}")
+    g.meta.update(dict(kind="erdos_renyi", p=p, seed=seed, wmax=wmax, vmax=vmax))
+    return _finish(g)
+
+
+def random_partition(n: int, k: int, seed: int) -> np.ndarray:
+    """Seeded uniform-random balanced assignment: part[perm[i]] = i mod k."""
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(n)
+    part = np.empty(n, dtype=np.int32)
+    part[perm] = (np.arange(n) % k).astype(np.int32)
+    return part
+
+
+def with_weights(g: Graph, seed: int, wmax: int = 0, vmax: int = 0) -> Graph:
+    """Copy of g with uniform random edge weights in [1, wmax] (symmetric) and
+    node weights in [1, vmax]; 0 keeps unit weights."""
+    rng = np.random.default_rng(seed)
+    adjwgt = g.adjwgt
+    if wmax > 0:
+        src = np.repeat(np.arange(g.n, dtype=np.int64), g.degrees())
+        dst = g.adjncy.astype(np.int64)
+        lo = np.minimum(src, dst)
+        hi = np.maximum(src, dst)
+        key = lo * g.n + hi
+        uk, inv = np.unique(key, return_inverse=True)
+        wu = rng.integers(1, wmax + 1, size=uk.size, dtype=np.int32)
+        adjwgt = wu[inv].astype(np.int32)
+    vwgt = g.vwgt
+    if vmax > 0:
+        vwgt = rng.integers(1, vmax + 1, size=g.n, dtype=np.int32)
+    h = Graph(g.n, g.xadj, g.adjncy, adjwgt, vwgt, name=g.name + f"_w{wmax}_v{vmax}",
+              meta=dict(g.meta))
+    return _finish(h)
+
+
+# ---------------------------------------------------------------------------
+# Named workloads (sizes of the paper-style configurations)
+# ---------------------------------------------------------------------------
+
+def workload(name: str) -> tuple:
+    """Return (graph, k, eps=(num, den), rounds, init_part_seed) for a named workload.
+
+    chunglu10k  : Chung-Lu n=10,000, avg degree 10, exponent 2.5, seed 1; k=8
+    rmat20      : R-MAT scale 20, 16 draws per node, seed 20; k=64
+    grid2048    : 2048 x 2048 4-neighbour grid; k=64
+    chunglu8m   : Chung-Lu n=8,000,000, avg degree 32, exponent 2.1,
+                  d_max=2e5, edge weights in [1,16], seed 3; k=256
+    """
+    if name == "chunglu10k":
+        return chung_lu(10_000, 10.0, 2.5, seed=1), 8, (3, 100), 10, 2
+    if name == "rmat20":
+        return rmat(20, 16, seed=20), 64, (3, 100), 20, 2
+    if name == "grid2048":
+        return grid2d(2048, 2048), 64, (3, 100), 20, 2
+    if name == "chunglu8m":
+        return chung_lu(8_000_000, 32.0, 2.1, seed=3, d_max=2e5, wmax=16), 256, (3, 100), 20, 2
+    raise KeyError(name)
+
+
+def tau_schedule(r: int, rounds: int) -> tuple:
+    """Penalty factor of round r (1-based) as a rational (num, den).
+
+    The paper interpolates linearly from a small tau_1 to tau_final = 1
+    (Section 5.5) without fixing tau_1; the value 1/2 is the one it uses
+    elsewhere (dynamic activation, constant-penalty variant). So
+    tau_r = 1/2 + (1/2)(r-1)/(R-1) = (R - 2 + r) / (2R - 2), clamped to r <= R.
+    """
+    if rounds <= 1:
+        return (1, 1)
+    r = max(1, min(r, rounds))
+    num = rounds - 2 + r
+    den = 2 * rounds - 2
+    gcd = math.gcd(num, den)
+    return (num // gcd, den // gcd)

@@ -1,0 +1,258 @@
+"""Slow, definition-level reference computations used to pin the oracle.
+
+Everything here is written from the problem statement of Section 2 and the
+penalty definitions of Section 5.3 with Python integers and Fractions, on
+tiny inputs: edge lists instead of tables, sets instead of histograms, cut
+differences instead of table lookups.
+"""
+from __future__ import annotations
+
+import itertools
+from fractions import Fraction
+
+import numpy as np
+
+
+def edges(g):
+    """Undirected edge list [(u, v, w)] with u < v."""
+    out = []
+    for v in range(g.n):
+        for e in range(int(g.xadj[v]), int(g.xadj[v + 1])):
+            u = int(g.adjncy[e])
+            if v < u:
+                out.append((v, u, 1 if g.adjwgt is None else int(g.adjwgt[e])))
+    return out
+
+
+def node_w(g, v):
+    return 1 if g.vwgt is None else int(g.vwgt[v])
+
+
+def cut(g, part):
+    return sum(w for u, v, w in edges(g) if part[u] != part[v])
+
+
+def omega(g, v, block, part):
+    """omega(v, V_block): edge weight from v into the block."""
+    s = 0
+    for e in range(int(g.xadj[v]), int(g.xadj[v + 1])):
+        if part[int(g.adjncy[e])] == block:
+            s += 1 if g.adjwgt is None else int(g.adjwgt[e])
+    return s
+
+
+def wdeg(g, v):
+    return sum(1 if g.adjwgt is None else int(g.adjwgt[e])
+               for e in range(int(g.xadj[v]), int(g.xadj[v + 1])))
+
+
+def block_weight(g, part, j):
+    return sum(node_w(g, v) for v in range(g.n) if part[v] == j)
+
+
+def move_gain(g, part, v, j):
+    """gain(m) = cut(Pi) - cut(Pi o m), by recomputing the cut."""
+    after = list(part)
+    after[v] = j
+    return cut(g, part) - cut(g, after)
+
+
+def lmax_exact(total, k, eps):
+    """L_max = (1 + eps) * ceil(c(V)/k), rounded down to an integer weight."""
+    per = -(-total // k)
+    return int((1 + Fraction(*eps)) * per // 1)
+
+
+def slot_exact(w, c, slots=54):
+    """ceil(log_{3/2}(w/c)) as the least integer l with (3/2)^l >= w/c,
+    clamped to [0, slots-1]."""
+    if w <= 0:
+        return 0
+    r = Fraction(w, c)
+    l = 0
+    while Fraction(3, 2) ** l < r:
+        l += 1
+    return min(max(l, 0), slots - 1)
+
+
+def available_sets(g, k, part, t):
+    """B[j][l] as Python sets of nodes available for rebalancing."""
+    B = [[set() for _ in range(54)] for _ in range(k)]
+    for v in range(g.n):
+        a = part[v]
+        inner = omega(g, v, a, part)
+        if Fraction(inner) >= Fraction(*t) * wdeg(g, v):
+            B[a][slot_exact(inner, node_w(g, v))].add(v)
+    return B
+
+
+def penalty_q16(g, k, part, t, tau, v, j, lmax):
+    """Penalty of moving v into V_j in Q16 (None = forbidden).
+
+    No penalty when V_j + v stays within L_max; otherwise l is the least slot
+    whose cumulative bucket weight covers c(V_j + v) - L_max and the penalty is
+    tau * (3/2)^l * c(v), the per-unit factor rounded down to Q16 first.
+    """
+    need = block_weight(g, part, j) + node_w(g, v) - lmax
+    if need <= 0:
+        return 0
+    B = available_sets(g, k, part, t)
+    acc = 0
+    for l in range(54):
+        acc += sum(node_w(g, u) for u in B[j][l])
+        if acc >= need:
+            per_unit = (Fraction(*tau) * Fraction(3, 2) ** l * 65536) // 1
+            return min(int(per_unit) * node_w(g, v), 1 << 62)
+    return None
+
+
+def best_moves(g, k, part, t, tau, eps, mode=0):
+    """S2 by brute force: for each v, argmax over blocks j != Pi(v) of
+    gain * 2^16 - penalty (ties to the smaller j); candidate iff > 0.
+    Returns dict v -> (target, score, pen)."""
+    total = sum(node_w(g, v) for v in range(g.n))
+    L = lmax_exact(total, k, eps)
+    out = {}
+    for v in range(g.n):
+        best = None
+        for j in range(k):
+            if j == part[v]:
+                continue
+            if omega(g, v, j, part) == 0:
+                continue
+            fits = block_weight(g, part, j) + node_w(g, v) <= L
+            if mode == 1 and not fits:
+                continue
+            P = 0 if mode == 2 else penalty_q16(g, k, part, t, tau, v, j, L)
+            if P is None:
+                continue
+            s = move_gain(g, part, v, j) * 65536 - P
+            if best is None or s > best[1]:
+                best = (j, s, P)
+        if best is not None and best[1] > 0:
+            out[v] = best
+    return out
+
+
+def all_partitions(n, k):
+    """Every assignment of n nodes to k blocks as an int8 array [k^n, n]."""
+    idx = np.arange(k ** n, dtype=np.int64)
+    digits = np.empty((k ** n, n), dtype=np.int8)
+    for i in range(n):
+        digits[:, i] = idx % k
+        idx //= k
+    return digits
+
+
+def optimum(g, k, eps):
+    """Minimum cut over all balanced k-way partitions (exhaustive)."""
+    P = all_partitions(g.n, k)
+    vw = np.ones(g.n, np.int64) if g.vwgt is None else g.vwgt.astype(np.int64)
+    total = int(vw.sum())
+    L = lmax_exact(total, k, eps)
+    ok = np.ones(P.shape[0], dtype=bool)
+    for j in range(k):
+        ok &= ((P == j).astype(np.int64) @ vw) <= L
+    best = None
+    E = edges(g)
+    cutv = np.zeros(P.shape[0], dtype=np.int64)
+    for u, v, w in E:
+        cutv += w * (P[:, u] != P[:, v])
+    cutv = np.where(ok, cutv, np.iinfo(np.int64).max)
+    i = int(np.argmin(cutv))
+    best = int(cutv[i])
+    return best, P[i].astype(np.int32), L
+
+
+def graph_from_edges(n, edge_list, vwgt=None, wts=None):
+    from paper_2308_15494_amd import graphgen as gg
+    e = np.asarray(edge_list, dtype=np.int64).reshape(-1, 2)
+    w = None if wts is None else np.asarray(wts, dtype=np.int32)
+    xadj, adjncy, adjwgt = gg.csr_from_undirected(n, e[:, 0], e[:, 1], w)
+    vw = None if vwgt is None else np.asarray(vwgt, dtype=np.int32)
+    return gg.Graph(n, xadj, adjncy, adjwgt, vw, name="fixture")
+
+
+def load_golden(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    with open(path) as f:
+        return json.load(f)
+
+
+def rebalance_bucket(gain, c, slots=54):
+    """Monotone bucket of the rebalancing priority of Section 7.1 (lower
+    first): gain*c for gain >= 0, gain/c for gain < 0, bucketed by
+    ceil(log_{3/2}) of the magnitude."""
+    if gain > 0:
+        return slots - 1 - slot_exact(gain * c, 1, slots)
+    if gain == 0:
+        return slots
+    return slots + 1 + slot_exact(-gain, c, slots)
+
+
+def rebalance_one_iteration(g, k, part, L):
+    """One synchronous rebalancing sub-iteration, from the rules of Section 7.1
+    on Python lists: nodes of overloaded blocks take their best-gain move into
+    a block that stays balanced (or, unconnected to any, the lightest such
+    block, smaller id on ties); each overloaded block releases its cheapest
+    nodes, in (priority bucket, id) order, until its excess is covered; each
+    target takes those aimed at it in the same order while they fit.
+    Returns the new partition (a list)."""
+    part = list(part)
+    W = [block_weight(g, part, j) for j in range(k)]
+    info = {}
+    for v in range(g.n):
+        a = part[v]
+        if W[a] <= L:
+            continue
+        cv = node_w(g, v)
+        valid = [j for j in range(k) if j != a and W[j] + cv <= L]
+        if not valid:
+            continue
+        conn = {j: omega(g, v, j, part) for j in valid}
+        connected = [j for j in valid if conn[j] > 0]
+        if connected:
+            tgt = max(connected, key=lambda j: (conn[j], -j))
+        else:
+            tgt = min(valid, key=lambda j: (W[j], j))
+        gain = move_gain(g, part, v, tgt)
+        info[v] = (tgt, rebalance_bucket(gain, cv))
+    selected = []
+    for a in range(k):
+        if W[a] <= L:
+            continue
+        nodes = sorted((v for v in info if part[v] == a), key=lambda v: (info[v][1], v))
+        got = 0
+        for v in nodes:
+            if got >= W[a] - L:
+                break
+            selected.append(v)
+            got += node_w(g, v)
+    out = list(part)
+    for j in range(k):
+        nodes = sorted((v for v in selected if info[v][0] == j), key=lambda v: (info[v][1], v))
+        room = L - W[j]
+        for v in nodes:
+            if node_w(g, v) > room:
+                break
+            room -= node_w(g, v)
+            out[v] = j
+    return out
+
+
+def pessimistic_gain(g, part, v, target, earlier):
+    """Worst true gain of moving v to `target` over every subset of the
+    earlier candidate neighbours `earlier` (dict u -> target_u) that may have
+    moved first; each subset's gain is a recomputed cut difference."""
+    nbrs = [u for u in earlier]
+    worst = None
+    for mask in range(1 << len(nbrs)):
+        cur = list(part)
+        for i, u in enumerate(nbrs):
+            if mask >> i & 1:
+                cur[u] = earlier[u]
+        gain = move_gain(g, cur, v, target)
+        worst = gain if worst is None else min(worst, gain)
+    return worst

@@ -1,0 +1,394 @@
+"""Pins of the oracle's round (S1-S6) and rebalancer against what the paper
+and the mathematics fix: brute-force best moves, the strict-decrease theorem
+of the conflict filter, the balance invariant, Lemma 1, exhaustive optima on
+tiny graphs, and hand-derived worked examples."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2308_15494_amd import graphgen as gg
+from tests import bruteforce as bf
+
+
+def skewed_partition(n, k, seed, heavy=0.5):
+    """Random partition with block 0 over-represented, so that full and
+    overloaded blocks (and thus penalties) occur."""
+    rng = np.random.default_rng(seed)
+    p = np.full(k, (1 - heavy) / (k - 1))
+    p[0] = heavy
+    return rng.choice(k, size=n, p=p).astype(np.int32)
+
+
+SMALL = [
+    ("er", lambda s: gg.random_small(24, 0.2, seed=s)),
+    ("er_w", lambda s: gg.random_small(22, 0.25, seed=s, wmax=6, vmax=3)),
+    ("cl", lambda s: gg.chung_lu(60, 4.0, 2.3, seed=s)),
+    ("grid", lambda s: gg.grid2d(5, 6)),
+]
+
+
+# ------------------------------------------------------------ S2 moves --
+
+@pytest.mark.parametrize("name,make", SMALL)
+@pytest.mark.parametrize("k", [2, 3, 5])
+@pytest.mark.parametrize("mode,tau", [(0, (1, 1)), (0, (1, 2)), (1, (1, 1)), (2, (1, 1)), (0, (0, 1))])
+def test_best_moves_bruteforce(orc, name, make, k, mode, tau):
+    for seed in range(3):
+        g = make(seed + 10 * k)
+        eps = (3, 100)
+        for part0 in [gg.random_partition(g.n, k, seed), skewed_partition(g.n, k, seed)]:
+            part = part0.copy()
+            p = orc.params(k, eps, t=(7, 10), tau=tau, mode=mode)
+            _, dbg = orc.refine_round(g, p, part, debug=True)
+            expect = bf.best_moves(g, k, list(part0), (7, 10), tau, eps, mode)
+            got = {v: (int(dbg["target"][v]), int(dbg["score"][v]), int(dbg["pen"][v]))
+                   for v in range(g.n) if dbg["target"][v] >= 0}
+            assert got == expect
+
+
+# ------------------------------------------ S3 filter: strict decrease --
+
+def seq_check(orc, g, k, part0, p):
+    part = part0.copy()
+    stats, dbg = orc.refine_round(g, p, part, debug=True)
+    cand = [v for v in range(g.n) if dbg["target"][v] >= 0]
+    order = sorted(cand, key=lambda v: (-int(dbg["score"][v]), v))
+    cur = list(part0)
+    c = bf.cut(g, cur)
+    assert stats[1] == c  # cut_before
+    total_gain = 0
+    for v in order:
+        if not dbg["accept"][v]:
+            continue
+        nxt = list(cur)
+        nxt[v] = int(dbg["target"][v])
+        c2 = bf.cut(g, nxt)
+        assert c2 < c, "an accepted move did not lower the cut when applied in order"
+        total_gain += c - c2
+        cur, c = nxt, c2
+    assert stats[2] == c  # cut_after_moves
+    assert stats[2] == stats[1] - total_gain
+    # the first candidate in the order has no earlier neighbour: always accepted
+    if order:
+        assert dbg["accept"][order[0]] == 1
+    # a candidate without candidate neighbours keeps its exact gain: accepted
+    cset = set(cand)
+    for v in cand:
+        nb = g.adjncy[g.xadj[v]:g.xadj[v + 1]]
+        if not any(int(u) in cset for u in nb):
+            assert dbg["accept"][v] == 1
+    assert stats[4] == len(cand) and stats[5] == int(dbg["accept"].sum())
+    return stats
+
+
+@pytest.mark.parametrize("name,make", SMALL)
+@pytest.mark.parametrize("k", [2, 4])
+def test_filter_strict_decrease(orc, name, make, k):
+    for seed in range(4):
+        g = make(100 + seed)
+        for part0 in [gg.random_partition(g.n, k, seed), skewed_partition(g.n, k, seed)]:
+            for tau in [(1, 2), (1, 1)]:
+                seq_check(orc, g, k, part0, orc.params(k, (3, 100), tau=tau))
+
+
+def test_filter_strict_decrease_larger(orc):
+    g = gg.chung_lu(400, 8.0, 2.2, seed=5)
+    k = 4
+    part = gg.random_partition(g.n, k, 1)
+    for r in range(1, 4):
+        st = seq_check(orc, g, k, part, orc.params(k, (3, 100), tau=gg.tau_schedule(r, 10)))
+        # continue from the round's output
+        orc.refine_round(g, orc.params(k, (3, 100), tau=gg.tau_schedule(r, 10)), part)
+        assert st[4] >= st[5]
+
+
+# -------------------------------------------- S4/S6: tables and cut stats --
+
+@pytest.mark.parametrize("name,make", SMALL + [("rmat", lambda s: gg.with_weights(gg.rmat(9, 8, seed=s), s, 5, 3))])
+def test_round_state_consistency(orc, name, make):
+    g = make(7)
+    k = 4
+    part = gg.random_partition(g.n, k, 3)
+    conn = np.zeros(g.n * k, np.int32)
+    W = np.zeros(k, np.int64)
+    L = orc.lmax(orc.total_weight(g), k)
+    for r in range(1, 6):
+        before = bf.cut(g, part)
+        st, _ = orc.refine_round(g, orc.params(k, tau=gg.tau_schedule(r, 5)), part, conn, W)
+        assert st[0] == L and st[1] == before
+        assert np.array_equal(conn.reshape(g.n, k), orc.gain_table(g, k, part))
+        assert np.array_equal(W, orc.block_weights(g, k, part))
+        assert st[3] == bf.cut(g, part)
+        if st[8] == 0:
+            assert W.max() <= L
+
+
+def test_resident_equals_rebuild(orc):
+    g = gg.with_weights(gg.chung_lu(500, 6.0, 2.4, seed=2), seed=3, wmax=4, vmax=2)
+    k = 5
+    pa = gg.random_partition(g.n, k, 4)
+    pb = pa.copy()
+    ca = np.zeros(g.n * k, np.int32)
+    Wa = np.zeros(k, np.int64)
+    cb = orc.gain_table(g, k, pb).reshape(-1).copy()
+    Wb = orc.block_weights(g, k, pb)
+    for r in range(1, 8):
+        tau = gg.tau_schedule(r, 7)
+        sa, _ = orc.refine_round(g, orc.params(k, tau=tau, rebuild_table=1), pa, ca, Wa)
+        sb, _ = orc.refine_round(g, orc.params(k, tau=tau, rebuild_table=0), pb, cb, Wb)
+        assert np.array_equal(sa, sb) and np.array_equal(pa, pb)
+        assert np.array_equal(ca, cb) and np.array_equal(Wa, Wb)
+
+
+def test_deterministic(orc):
+    g = gg.chung_lu(800, 6.0, 2.3, seed=9)
+    k = 6
+    outs = []
+    for _ in range(2):
+        part = gg.random_partition(g.n, k, 1)
+        s, _ = orc.refine_round(g, orc.params(k, tau=(1, 2)), part)
+        outs.append((s.copy(), part.copy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+# --------------------------------------------------------- S5 rebalance --
+
+def test_rebalance_invariants(orc):
+    for seed in range(12):
+        g = gg.with_weights(gg.chung_lu(300, 5.0, 2.3, seed=seed), seed,
+                            wmax=3 if seed % 2 else 0, vmax=4 if seed % 3 == 0 else 0)
+        k = 2 + seed % 5
+        part0 = skewed_partition(g.n, k, seed, heavy=0.6)
+        L = orc.lmax(orc.total_weight(g), k)
+        W0 = orc.block_weights(g, k, part0)
+        part = part0.copy()
+        st = orc.rebalance(g, orc.params(k), part)
+        W1 = orc.block_weights(g, k, part)
+        over = W0 > L
+        moved = np.nonzero(part != part0)[0]
+        assert st[6] >= len(moved)
+        # only nodes of initially overloaded blocks move
+        assert all(over[part0[v]] for v in moved)
+        # blocks that were not overloaded never become overloaded
+        assert np.all(W1[~over] <= L)
+        if st[8] == 0:
+            assert W1.max() <= L
+        if g.vwgt is None:
+            assert st[8] == 0 and st[7] <= k + 1
+        assert st[3] == bf.cut(g, part)
+
+
+def test_rebalance_two_blocks_lowest_loss(orc):
+    """k=2, unit weights: one sub-iteration moves exactly the excess, and the
+    moved nodes are a lowest-priority-bucket-first selection."""
+    for seed in range(10):
+        g = gg.chung_lu(200, 5.0, 2.5, seed=seed)
+        k = 2
+        part0 = skewed_partition(g.n, k, seed, heavy=0.62)
+        L = orc.lmax(g.n, k)
+        W0 = np.bincount(part0, minlength=2)
+        a = int(np.argmax(W0))
+        excess = int(W0[a] - L)
+        assert excess > 0
+        part = part0.copy()
+        st = orc.rebalance(g, orc.params(k), part)
+        assert st[8] == 0 and st[7] == 1 and st[6] == excess
+        moved = set(np.nonzero(part != part0)[0].tolist())
+        assert all(part0[v] == a for v in moved)
+        b = 1 - a
+
+        def key(v):
+            gain = bf.omega(g, v, b, list(part0)) - bf.omega(g, v, a, list(part0))
+            return (bf.rebalance_bucket(gain, 1), v)
+
+        members = sorted((v for v in range(g.n) if part0[v] == a), key=key)
+        assert moved == set(members[:excess])
+
+
+def test_rebalance_stuck(orc):
+    # Block 0 holds two nodes of weight 4; L_max = 5 and block 1 has weight 3:
+    # neither heavy node fits anywhere, so rebalancing is stuck.
+    g = bf.graph_from_edges(5, [[0, 1], [1, 2], [2, 3], [3, 4]], vwgt=[4, 4, 1, 1, 1])
+    part = np.array([0, 0, 1, 1, 1], np.int32)
+    st = orc.rebalance(g, orc.params(2, eps=(1, 10)), part)
+    assert st[0] == 6  # ceil(11/2)=6 -> floor(6.6) = 6
+    # weights: block 0 = 8 > 6; block 1 = 3; room 3 < 4
+    assert st[8] == 1 and st[6] == 0
+    assert list(part) == [0, 0, 1, 1, 1]
+
+
+def test_rebalance_iteration_cap(orc):
+    g = gg.chung_lu(300, 5.0, 2.3, seed=4)
+    k = 6
+    part = skewed_partition(g.n, k, 4, heavy=0.7)
+    st_full = orc.rebalance(g, orc.params(k), part.copy())
+    assert st_full[8] == 0
+    if st_full[7] > 1:
+        st1 = orc.rebalance(g, orc.params(k, max_rebalance_iters=1), part.copy())
+        assert st1[8] == 1 and st1[7] == 1
+
+
+# ---------------------------------------------------------------- Lemma 1 --
+
+def test_lemma1_bound(orc):
+    """Lemma 1 (Section 5.3), unit weights, tau = 1: moving U = {u_1..u_j}
+    into a balanced block V_1 can be undone by moving nodes of the smallest
+    available slots out of V_1, at a cut increase of at most
+    (1/t) * sum_i pen(u_i, V_1 + U^{i-1})."""
+    t = (7, 10)
+    hits = 0
+    for seed in range(30):
+        g = gg.chung_lu(150, 5.0, 2.5, seed=seed)
+        k = 3
+        part = gg.random_partition(g.n, k, seed)
+        conn = orc.gain_table(g, k, part)
+        bucket, avail = orc.penalty_buckets(g, k, part, conn, t)
+        L = orc.lmax(g.n, k)
+        W = np.bincount(part, minlength=k)
+        j1 = 0
+        rng = np.random.default_rng(seed)
+        outside = np.nonzero(part != j1)[0]
+        U = rng.choice(outside, size=min(6, outside.size), replace=False)
+        # sequential penalties against the round-start buckets
+        cb = np.cumsum(bucket[j1])
+        pen_sum = Fraction(0)
+        for i in range(1, len(U) + 1):
+            need = W[j1] + i - L
+            if need <= 0:
+                continue
+            l = int(np.argmax(cb >= need)) if cb[-1] >= need else None
+            if l is None:
+                break
+            pen_sum += Fraction(3, 2) ** l
+        else:
+            moved = list(part)
+            for u in U:
+                moved[u] = j1
+            excess = W[j1] + len(U) - L
+            if excess <= 0:
+                continue
+            # the proof's choice: smallest slots first, never a node of U
+            pool = sorted((int(avail[v]) - 1, v) for v in np.nonzero(avail)[0]
+                          if part[v] == j1)
+            chosen = [v for _, v in pool[:excess]]
+            if len(chosen) < excess:
+                continue
+            after = list(moved)
+            for b, u in zip(chosen, U):
+                after[b] = part[u]   # back to a block that lost a node of U
+            cost = bf.cut(g, after) - bf.cut(g, moved)
+            assert cost <= pen_sum / Fraction(*t)
+            hits += 1
+    assert hits >= 5
+
+
+# ------------------------------------------------------------ exhaustive --
+
+@pytest.mark.parametrize("n,k,p", [(10, 2, 0.35), (12, 2, 0.3), (9, 3, 0.4), (11, 2, 0.5)])
+def test_exhaustive_optimum(orc, n, k, p):
+    reached = 0
+    for seed in range(6):
+        g = gg.random_small(n, p, seed=seed)
+        eps = (3, 100)
+        opt, popt, L = bf.optimum(g, k, eps)
+        # (2) constrained round from an optimal partition changes nothing
+        part = popt.copy()
+        st, _ = orc.refine_round(g, orc.params(k, eps, mode=1), part)
+        assert st[4] == 0 and np.array_equal(part, popt) and st[3] == opt
+        # (3) penalised round from the optimum stays at or above it
+        part = popt.copy()
+        st, _ = orc.refine_round(g, orc.params(k, eps), part)
+        if st[8] == 0:
+            assert st[3] >= opt
+        # (1) rounds from random partitions never beat the optimum while balanced
+        part = gg.random_partition(n, k, seed)
+        for r in range(1, 11):
+            st, _ = orc.refine_round(g, orc.params(k, eps, tau=gg.tau_schedule(r, 10)), part)
+            assert st[3] == bf.cut(g, part)
+            if st[8] == 0:
+                assert np.bincount(part, minlength=k).max() <= L
+                assert st[3] >= opt
+        reached += int(st[3] == opt)
+    assert reached >= 1
+
+
+# --------------------------------------------------------------- golden --
+
+@pytest.mark.parametrize("fixture", ["full_block_escape.json", "filter_conflict.json"])
+def test_golden(orc, fixture):
+    fx = bf.load_golden(fixture)
+    g = bf.graph_from_edges(fx["n"], fx["edges"])
+    for case in fx["cases"]:
+        part = np.array(fx["part_in"], np.int32)
+        p = orc.params(fx["k"], tuple(fx["eps"]), t=tuple(fx["t"]), tau=tuple(case["tau"]),
+                       mode=case["mode"])
+        st, dbg = orc.refine_round(g, p, part, debug=True)
+        assert orc.stats_dict(st) == case["stats"]
+        assert part.tolist() == case["part_out"]
+        cands = {str(v): int(dbg["score"][v]) for v in range(g.n) if dbg["target"][v] >= 0}
+        assert cands == case["score"]
+        assert {str(v): int(dbg["pen"][v]) for v in range(g.n) if dbg["target"][v] >= 0} == case["pen"]
+        if "accept" in case:
+            assert {str(v): int(dbg["accept"][v]) for v in range(g.n)
+                    if dbg["target"][v] >= 0} == case["accept"]
+
+
+def test_full_block_escape_beats_constrained(orc):
+    fx = bf.load_golden("full_block_escape.json")
+    g = bf.graph_from_edges(fx["n"], fx["edges"])
+    res = {}
+    for mode in (0, 1):
+        part = np.array(fx["part_in"], np.int32)
+        st, _ = orc.refine_round(g, orc.params(2, (3, 100), mode=mode), part)
+        res[mode] = st[3]
+    assert res[0] < res[1]
+
+
+# -------------------------------------- brute-force single sub-iteration --
+
+def with_isolated(g, extra, seed):
+    """g plus `extra` isolated nodes (zero-cost rebalancing candidates)."""
+    n = g.n + extra
+    xadj = np.concatenate([g.xadj, np.full(extra, g.xadj[-1], np.int64)])
+    vw = None
+    if g.vwgt is not None:
+        rng = np.random.default_rng(seed)
+        vw = np.concatenate([g.vwgt, rng.integers(1, 4, extra).astype(np.int32)])
+    return gg.Graph(n, xadj, g.adjncy, g.adjwgt, vw)
+
+
+@pytest.mark.parametrize("k", [2, 3, 5])
+@pytest.mark.parametrize("weighted", [False, True])
+def test_rebalance_one_iteration_bruteforce(orc, k, weighted):
+    for seed in range(8):
+        base = gg.random_small(26, 0.12, seed=seed, wmax=4 if weighted else 0,
+                               vmax=5 if weighted else 0)
+        g = with_isolated(base, 4, seed)
+        part0 = skewed_partition(g.n, k, seed, heavy=0.55)
+        L = orc.lmax(orc.total_weight(g), k)
+        part = part0.copy()
+        orc.rebalance(g, orc.params(k, max_rebalance_iters=1), part)
+        assert part.tolist() == bf.rebalance_one_iteration(g, k, list(part0), L)
+
+
+@pytest.mark.parametrize("name,make", SMALL)
+@pytest.mark.parametrize("tau", [(1, 1), (1, 2)])
+def test_filter_bruteforce_subsets(orc, name, make, tau):
+    """Accept iff (worst gain over the moves earlier candidates may make) * 2^16
+    exceeds the penalty; checked on skewed partitions where penalties bite."""
+    k = 3
+    for seed in range(4):
+        g = make(200 + seed)
+        part0 = skewed_partition(g.n, k, seed, heavy=0.45)
+        part = part0.copy()
+        _, dbg = orc.refine_round(g, orc.params(k, tau=tau), part, debug=True)
+        tgt, sc, pen, acc = dbg["target"], dbg["score"], dbg["pen"], dbg["accept"]
+        for v in np.nonzero(tgt >= 0)[0]:
+            nb = set(int(u) for u in g.adjncy[g.xadj[v]:g.xadj[v + 1]])
+            earlier = {u: int(tgt[u]) for u in nb if tgt[u] >= 0 and
+                       (sc[u] > sc[v] or (sc[u] == sc[v] and u < v))}
+            if len(earlier) > 12:
+                continue
+            worst = bf.pessimistic_gain(g, list(part0), int(v), int(tgt[v]), earlier)
+            assert int(acc[v]) == int(worst * 65536 - int(pen[v]) > 0)
