@@ -1,0 +1,189 @@
+/*
+ * upr.h -- C ABI of the MI355X (gfx950) unconstrained partition refinement
+ * library, libupr.so.
+ *
+ * One call of upr_refine_round performs one deterministic synchronous round of
+ * penalised unconstrained refinement for balanced k-way graph partitioning
+ * (arXiv 2308.15494): build the gain table, pick every node's best penalised
+ * move, filter conflicting moves in a fixed (score, id) order, apply the
+ * survivors, then rebalance overloaded blocks. Every step runs in HIP kernels
+ * on the caller's stream; all arithmetic is integer, so results are exact and
+ * independent of launch geometry.
+ *
+ * Problem statement (Section 2): an undirected graph G = (V, E, c, omega) with
+ * node weights c(v) >= 1 and edge weights omega(e) >= 1, a number of blocks k
+ * and an imbalance eps > 0. A partition is balanced iff every block weight
+ * c(V_i) <= L_max = (1 + eps) * ceil(c(V) / k) (rounded down to an integer).
+ * The objective is the edge cut, the total weight of edges between blocks.
+ *
+ * Conventions for every entry point:
+ *  - Pointers marked "device" must be device memory of the context's device
+ *    (e.g. torch ROCm tensors). The caller owns all arrays it passes; the
+ *    library never frees them and keeps no pointer to them after the call
+ *    returns, except that a plan keeps the graph arrays it was created from
+ *    (they must outlive the plan and must not change).
+ *  - Work is enqueued on `stream` (0 = the null stream). Device outputs are
+ *    valid once the stream has been synchronised. Entry points that need a
+ *    host decision (the rebalancing loop) synchronise `stream` themselves.
+ *  - Return value: UPR_OK (0) or a negative UPR_E_* code; upr_last_error()
+ *    then describes it. On an argument error nothing is written.
+ *  - A context is not thread-safe: calls on one context must not overlap.
+ */
+#ifndef UPR_H
+#define UPR_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define UPR_OK            0
+#define UPR_E_ARG        -1   /* null pointer, bad k / eps / t / tau / mode, size out of range */
+#define UPR_E_GRAPH      -2   /* CSR violates the invariants (upr_validate_graph only) */
+#define UPR_E_INFEASIBLE -3   /* some node weight exceeds L_max: no balanced partition exists */
+#define UPR_E_NOMEM      -4   /* device workspace allocation failed */
+#define UPR_E_HIP        -5   /* a HIP runtime call or kernel launch failed */
+
+#define UPR_MAX_K 8192        /* largest supported number of blocks (a gain-table row fits LDS) */
+
+typedef struct upr_ctx upr_ctx;
+typedef struct upr_plan upr_plan;
+
+/* Graph in symmetric CSR form (Section 2: G = (V, E, c, omega)). */
+typedef struct {
+    int64_t n;               /* number of nodes, 0 <= n < 2^31 */
+    const int64_t *xadj;     /* device [n+1]; xadj[0] = 0, nondecreasing; nnz = xadj[n] */
+    const int32_t *adjncy;   /* device [nnz]; row v lists N(v); symmetric, no self-loops,
+                                no duplicates */
+    const int32_t *adjwgt;   /* device [nnz], omega of each directed entry, > 0 and symmetric;
+                                NULL means every edge weight is 1 */
+    const int32_t *vwgt;     /* device [n], c(v) > 0; NULL means every node weight is 1 */
+} upr_graph;
+
+/* Parameters of one round. */
+typedef struct {
+    int32_t k;                   /* number of blocks, 2 <= k <= UPR_MAX_K */
+    int32_t eps_num, eps_den;    /* eps = eps_num / eps_den > 0 (Section 8.1 uses 3/100) */
+    int32_t t_num, t_den;        /* availability threshold t in [0, 1] (Section 5.3, 0.7) */
+    int32_t tau_num, tau_den;    /* penalty factor tau in [0, 1] of this round (Section 5.5) */
+    int32_t mode;                /* 0 penalised unconstrained moves (Section 5.3),
+                                    1 constrained (moves that would overload are skipped),
+                                    2 penalty-free unconstrained (Section 8.2 variant) */
+    int32_t rebuild_table;       /* 1: conn and block_w are recomputed from part first;
+                                    0: conn and block_w are trusted resident state */
+    int32_t max_rebalance_iters; /* 0: k+1 for unit node weights, 4k otherwise */
+} upr_params;
+
+/* Round statistics, written to a device int64 array of UPR_STATS_LEN slots. */
+enum {
+    UPR_ST_LMAX = 0,          /* L_max */
+    UPR_ST_CUT_BEFORE,        /* cut of the input partition */
+    UPR_ST_CUT_AFTER_MOVES,   /* cut after the filtered moves, before rebalancing */
+    UPR_ST_CUT_AFTER,         /* cut of the output partition */
+    UPR_ST_CANDIDATES,        /* nodes whose best penalised score was > 0 */
+    UPR_ST_ACCEPTED,          /* moves that passed the conflict filter */
+    UPR_ST_REBAL_MOVES,       /* moves made by rebalancing */
+    UPR_ST_REBAL_ITERS,       /* rebalancing sub-iterations */
+    UPR_ST_STATUS,            /* 0 balanced; 1 rebalancing stuck or out of iterations */
+    UPR_STATS_LEN = 12
+};
+
+/* Context: owns the device workspace on one device. Returns UPR_OK or a code. */
+int upr_create(upr_ctx **out, int device);
+void upr_destroy(upr_ctx *ctx);
+/* Message for the last nonzero return on this context (never NULL). */
+const char *upr_last_error(const upr_ctx *ctx);
+
+/* Plan: the per-graph preparation of Section 2's input -- weighted degrees
+ * omega(I(v)), total node weight c(V), and the degree classes that decide how
+ * each node's adjacency is traversed (low- and mid-degree nodes by a lane
+ * group, hubs by several workgroups). Created once per graph; enqueued on
+ * `stream` and synchronised. The graph arrays must outlive the plan. */
+int upr_plan_create(upr_ctx *ctx, const upr_graph *graph, upr_plan **out, hipStream_t stream);
+void upr_plan_destroy(upr_plan *plan);
+/* Host-side facts of a plan (any output pointer may be NULL). */
+int upr_plan_info(const upr_plan *plan, int64_t *n, int64_t *nnz, int64_t *total_weight,
+                  int64_t *max_degree, int64_t *num_hubs);
+
+/* Check the CSR invariants on the device (xadj monotone, ids in range, no
+ * self-loops, rows strictly increasing so no duplicates, symmetric structure
+ * and weights, positive weights). Rows must be sorted for this check.
+ * Returns UPR_OK or UPR_E_GRAPH with the first violation in upr_last_error.
+ * Synchronises `stream`. */
+int upr_validate_graph(upr_ctx *ctx, const upr_graph *graph, hipStream_t stream);
+
+/* Gain table (Section 7.1, reused from the shared-memory FM):
+ * conn[v * k + j] = omega(v, V_j) for every node v and block j.
+ * part: device int32 [n], values in [0, k). conn: device int32 [n * k], out.
+ * Checks part first (one stream synchronisation); values outside [0, k)
+ * give UPR_E_ARG with nothing written. */
+int upr_gain_table(upr_ctx *ctx, const upr_plan *plan, int32_t k, const int32_t *part,
+                   int32_t *conn, hipStream_t stream);
+
+/* Block weights c(V_j): block_w device int64 [k], out. Checks part like
+ * upr_gain_table. */
+int upr_block_weights(upr_ctx *ctx, const upr_plan *plan, int32_t k, const int32_t *part,
+                      int64_t *block_w, hipStream_t stream);
+
+/* Edge cut of Section 2, sum over i < j of omega(E_ij), straight from the
+ * adjacency: cut device int64 [1], out. */
+int upr_edge_cut(upr_ctx *ctx, const upr_plan *plan, const int32_t *part, int64_t *cut,
+                 hipStream_t stream);
+
+/* One refinement round, in place on (part, conn, block_w):
+ *   S1 gain table and block weights (if params->rebuild_table), cut;
+ *   penalty buckets of the rebalance-available nodes (Section 5.3);
+ *   S2 best move per node maximising gain * 2^16 - penalty (Q16 fixed point;
+ *      penalty tau * (3/2)^l * c(v), l the least slot covering the target's
+ *      excess; moves with no covering slot are forbidden); candidates have a
+ *      positive best score;
+ *   S3 conflict filter: in (score desc, id asc) order, a candidate survives iff
+ *      its gain, recomputed assuming every earlier candidate neighbour ends in
+ *      the worse of its two blocks, times 2^16 still exceeds its penalty;
+ *   S4 apply survivors with delta updates of conn and block_w;
+ *   S5 rebalance (Section 7.1) while a block exceeds L_max;
+ *   S6 cut and statistics.
+ * part: device int32 [n] in/out; conn: device int32 [n * k] in/out;
+ * block_w: device int64 [k] in/out; stats: device int64 [UPR_STATS_LEN] out.
+ * Synchronises `stream` once per rebalancing decision. A part value outside
+ * [0, k) is detected on the device and reported as UPR_E_ARG at the first
+ * synchronisation; part, conn and block_w are then unspecified. */
+int upr_refine_round(upr_ctx *ctx, const upr_plan *plan, const upr_params *params, int32_t *part,
+                     int32_t *conn, int64_t *block_w, int64_t *stats, hipStream_t stream);
+
+/* Rebalancing alone (Section 7.1): S1 if params->rebuild_table, then S5 and
+ * S6. Same arrays as upr_refine_round; mode and tau are ignored. */
+int upr_rebalance(upr_ctx *ctx, const upr_plan *plan, const upr_params *params, int32_t *part,
+                  int32_t *conn, int64_t *block_w, int64_t *stats, hipStream_t stream);
+
+/* Per-node results of the last round's move phase on this context, copied to
+ * device arrays of length n (any may be NULL): target block of each candidate
+ * (-1 otherwise), its score, its penalty, and whether it passed the filter.
+ * Valid until the next call on the context. For diagnosis. */
+int upr_last_moves(upr_ctx *ctx, int64_t n, int32_t *target, int64_t *score, int64_t *pen,
+                   uint8_t *accept, hipStream_t stream);
+
+/* Host-side helpers (no device work). */
+/* L_max = floor((1 + eps) * ceil(total / k)) with eps = eps_num / eps_den. */
+int64_t upr_lmax(int64_t total, int32_t k, int32_t eps_num, int32_t eps_den);
+/* Q16 penalty factors floor(tau * (3/2)^l * 2^16), l = 0..53, into out[54]. */
+int upr_penalty_table(int32_t tau_num, int32_t tau_den, int64_t *out);
+
+/* Per-phase device time of the calls on this context, accumulated in
+ * milliseconds by HIP events while timing is enabled (enabling it records
+ * events between phases on the call's stream). Phases: 0 gain table,
+ * 1 penalty buckets, 2 best move, 3 filter, 4 apply, 5 rebalance, 6 cut,
+ * 7 whole call. Phase 0 is the gain-table tile kernel alone, 1 the hub rows
+ * and hub statistics (or, for a resident table, the penalty buckets).
+ * counts[p] = number of intervals accumulated. */
+#define UPR_NUM_PHASES 8
+int upr_timing_enable(upr_ctx *ctx, int enable);
+int upr_timing_read(upr_ctx *ctx, double *ms, int64_t *counts, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UPR_H */

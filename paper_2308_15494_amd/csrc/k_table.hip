@@ -1,0 +1,576 @@
+// Gain table, block weights, cut and per-graph preparation kernels.
+//
+// Gain table (Section 7.1, the shared-memory FM's table): conn[v][j] is the
+// edge weight from v into block j. It is built tile by tile: a workgroup owns
+// T consecutive nodes, zeroes their T x k rows in LDS, walks the tile's
+// adjacency edge-parallel (coalesced adjncy/adjwgt reads, one gather of
+// part[u] per edge, an LDS atomic per edge) and writes the rows back as one
+// contiguous, coalesced span of conn. Hubs (degree above the plan's hub
+// threshold) are left out of the tiles and accumulated by several
+// workgroups, each over a chunk of the hub's edges, into the row in global
+// memory.
+#include "upr_common.h"
+
+namespace upr {
+
+// ------------------------------------------------------------------ fill --
+
+template <typename T>
+__global__ void k_fill(T *p, int64_t count, T value)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+static int grid_for(int64_t items, int per_block, int cap = 8192)
+{
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+hipError_t launch_fill_i64(int64_t *p, int64_t count, int64_t value, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill<int64_t>, dim3(grid_for(count, kBlock * 4)), dim3(kBlock), 0, s, p,
+                       count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(count, kBlock * 4)), dim3(kBlock), 0, s, p,
+                       count, value);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ plan --
+
+// Per node: weighted degree (lane group of 64 for weighted rows), maximum
+// degree, hub list (unordered; the host sorts it).
+// counters[0] = number of hubs, [1] = max degree, [2] = max weighted degree,
+// [3] = total node weight, [4] = max node weight.
+__global__ __launch_bounds__(kBlock) void k_plan_scan(GraphView g, int32_t *wdeg, int64_t hub_t,
+                                                       int32_t *hub_list,
+                                                       unsigned long long *counters)
+{
+    const int lane = lane_id();
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
+    unsigned long long maxdeg = 0, maxw = 0, totw = 0, maxvw = 0;
+    for (int64_t v = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); v < g.n; v += waves) {
+        const int64_t e0 = g.xadj[v], e1 = g.xadj[v + 1];
+        const int64_t deg = e1 - e0;
+        int64_t w = deg;
+        if (g.adjwgt) {
+            int64_t s = 0;
+            for (int64_t e = e0 + lane; e < e1; e += 64) s += g.adjwgt[e];
+            w = wave_sum(s);
+        }
+        if (lane == 0) {
+            wdeg[v] = (int32_t)(w < 0x7fffffff ? w : 0x7fffffff);
+            if ((unsigned long long)deg > maxdeg) maxdeg = deg;
+            if ((unsigned long long)w > maxw) maxw = w;
+            const unsigned long long cv = g.vwgt ? (unsigned long long)g.vwgt[v] : 1ull;
+            totw += cv;
+            if (cv > maxvw) maxvw = cv;
+            if (deg > hub_t) {
+                unsigned long long slot = atomicAdd(&counters[0], 1ull);
+                hub_list[slot] = (int32_t)v;
+            }
+        }
+    }
+    // reduce (lane 0 of each wave holds values)
+    unsigned long long m1 = maxdeg, m2 = maxw, m3 = maxvw;
+    if (lane != 0) { m1 = 0; m2 = 0; m3 = 0; totw = 0; }
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long o1 = __shfl_xor(m1, off), o2 = __shfl_xor(m2, off);
+        unsigned long long o3 = __shfl_xor(m3, off);
+        m1 = o1 > m1 ? o1 : m1;
+        m2 = o2 > m2 ? o2 : m2;
+        m3 = o3 > m3 ? o3 : m3;
+    }
+    totw = wave_sum(totw);
+    if (lane == 0) {
+        atomicMax(&counters[1], m1);
+        atomicMax(&counters[2], m2);
+        atomicAdd(&counters[3], totw);
+        atomicMax(&counters[4], m3);
+    }
+}
+
+hipError_t launch_plan_scan(const GraphView &g, int32_t *wdeg, int64_t hub_t, int32_t *hub_list,
+                            unsigned long long *counters, hipStream_t s)
+{
+    if (g.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_plan_scan, dim3(grid_for(g.n, kBlock / 64, 16384)), dim3(kBlock), 0, s, g,
+                       wdeg, hub_t, hub_list, counters);
+    return hipGetLastError();
+}
+
+// CSR invariants. flags[0]: first bad xadj index + 1; flags[1]: bad entry
+// (out of range / self-loop / unsorted or duplicate) + 1; flags[2]:
+// asymmetric entry + 1; flags[3]: bad weight + 1. Each holds the minimum
+// offending index (atomicMin over index + 1, 0 = none is encoded as ~0).
+__device__ __forceinline__ bool has_entry(const GraphView &g, int64_t u, int64_t v, int32_t w,
+                                          bool *wmatch)
+{
+    int64_t lo = g.xadj[u], hi = g.xadj[u + 1];
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (g.adjncy[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo < g.xadj[u + 1] && g.adjncy[lo] == v) {
+        *wmatch = !g.adjwgt || g.adjwgt[lo] == w;
+        return true;
+    }
+    return false;
+}
+
+__global__ __launch_bounds__(kBlock) void k_validate(GraphView g, unsigned long long *flags)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += stride) {
+        if (g.xadj[v + 1] < g.xadj[v]) atomicMin(&flags[0], (unsigned long long)v);
+        if (g.vwgt && g.vwgt[v] <= 0) atomicMin(&flags[3], (unsigned long long)v);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && g.xadj[0] != 0) atomicMin(&flags[0], 0ull);
+}
+
+__global__ __launch_bounds__(kBlock) void k_validate_edges(GraphView g, unsigned long long *flags,
+                                                            int full)
+{
+    // one wave per node, lanes over the row
+    const int lane = lane_id();
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t v = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); v < g.n; v += waves) {
+        const int64_t e0 = g.xadj[v], e1 = g.xadj[v + 1];
+        for (int64_t e = e0 + lane; e < e1; e += 64) {
+            const int64_t u = g.adjncy[e];
+            if (u < 0 || u >= g.n) {
+                atomicMin(&flags[1], (unsigned long long)e);
+                continue;
+            }
+            const int32_t w = g.adjwgt ? g.adjwgt[e] : 1;
+            if (w <= 0) atomicMin(&flags[3], (unsigned long long)(g.n + e));
+            if (!full) continue;
+            if (u == v || (e > e0 && g.adjncy[e - 1] >= u)) {
+                atomicMin(&flags[1], (unsigned long long)e);
+                continue;
+            }
+            bool wm = true;
+            if (!has_entry(g, u, v, w, &wm) || !wm) atomicMin(&flags[2], (unsigned long long)e);
+        }
+    }
+}
+
+hipError_t launch_validate(const GraphView &g, unsigned long long *flags, int stage,
+                           hipStream_t s)
+{
+    if (g.n <= 0) return hipSuccess;
+    if (stage == 0)
+        hipLaunchKernelGGL(k_validate, dim3(grid_for(g.n, kBlock)), dim3(kBlock), 0, s, g, flags);
+    else
+        hipLaunchKernelGGL(k_validate_edges, dim3(grid_for(g.n, kBlock / 64, 16384)), dim3(kBlock),
+                           0, s, g, flags, stage == 2 ? 1 : 0);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- gain tile --
+
+constexpr int kTileInts = 8192;  // LDS ints of one tile's rows (32 KiB)
+constexpr int kTileMaxNodes = 1024;
+
+int gain_tile_nodes(int32_t k)
+{
+    int t = kTileInts / k;
+    if (t > kTileMaxNodes) t = kTileMaxNodes;
+    if (t < 1) t = 1;
+    return t;
+}
+
+static size_t gain_tile_lds(int32_t k, int T)
+{
+    size_t rows = (size_t)T * k * 4;
+    if (rows < 4) rows = 4;
+    return rows + (size_t)(T + 1) * 4 + (size_t)T * 8 + 64;
+}
+
+// Largest i in [0, cnt) with a[i] <= p (a nondecreasing, a[0] <= p).
+__device__ __forceinline__ int upper_index(const int32_t *a, int cnt, int32_t p)
+{
+    int lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (a[mid] <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// One workgroup per tile of T nodes. With with_stats, also: block weights
+// W[j] += c(v) (if W != null), 2*cut partial into counters[CNT_CUT2_BEFORE],
+// penalty bucket weights of the rebalance-available non-hub nodes (Section
+// 5.3: t_den * omega(v, Pi(v)) >= t_num * omega(I(v))).
+template <bool WEIGHTED>
+__global__ __launch_bounds__(kBlock) void k_gain_tile(GraphView g, int32_t k, int T,
+                                                       const int32_t *__restrict__ part,
+                                                       int32_t *__restrict__ conn,
+                                                       const int32_t *__restrict__ wdeg,
+                                                       int64_t hub_t, int64_t *W, int64_t *bucket,
+                                                       int32_t t_num, int32_t t_den,
+                                                       unsigned long long *counters, int with_stats)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    int32_t *tile = (int32_t *)lds_raw;
+    const size_t rows_bytes = ((size_t)T * k * 4 + 15) & ~(size_t)15;
+    int32_t *vstart = (int32_t *)(lds_raw + rows_bytes);
+    int64_t *gstart = (int64_t *)(lds_raw + rows_bytes + (((size_t)(T + 1) * 4 + 15) & ~(size_t)15));
+    __shared__ int32_t scan_lds[4];
+    __shared__ unsigned long long red_lds[4];
+
+    const int64_t v0 = (int64_t)blockIdx.x * T;
+    const int nt = (int)((g.n - v0) < T ? (g.n - v0) : T);
+    const int tid = threadIdx.x;
+    const int64_t kk = k;
+
+    for (int i = tid; i < nt * k; i += kBlock) tile[i] = 0;
+
+    // virtual degrees (hubs contribute none) and their exclusive prefix,
+    // in chunks of kBlock nodes
+    int32_t run = 0;
+    for (int base = 0; base < nt; base += kBlock) {
+        const int i = base + tid;
+        int32_t vd = 0;
+        if (i < nt) {
+            const int64_t a = g.xadj[v0 + i], b = g.xadj[v0 + i + 1];
+            gstart[i] = a;
+            vd = (b - a) > hub_t ? 0 : (int32_t)(b - a);
+        }
+        int32_t total;
+        const int32_t inc = block_incl_scan(vd, scan_lds, &total);
+        if (i < nt) vstart[i] = run + inc - vd;
+        run += total;
+    }
+    if (tid == 0) vstart[nt] = run;
+    __syncthreads();
+
+    const int32_t E = run;
+    for (int32_t p = tid; p < E; p += kBlock) {
+        const int node = upper_index(vstart, nt, p);
+        const int64_t e = gstart[node] + (p - vstart[node]);
+        const int32_t u = g.adjncy[e];
+        const int32_t pu = part[u];
+        if ((unsigned)pu < (unsigned)k) {
+            const int32_t w = WEIGHTED ? g.adjwgt[e] : 1;
+            atomicAdd(&tile[node * k + pu], w);
+        }
+    }
+    __syncthreads();
+
+    // coalesced write-back of the contiguous rows [v0, v0 + nt)
+    int32_t *dst = conn + v0 * kk;
+    const int64_t total_ints = (int64_t)nt * k;
+    if (((uintptr_t)dst & 15) == 0) {
+        const int64_t n4 = total_ints >> 2;
+        int4 *d4 = (int4 *)dst;
+        const int4 *s4 = (const int4 *)tile;
+        for (int64_t i = tid; i < n4; i += kBlock) d4[i] = s4[i];
+        for (int64_t i = (n4 << 2) + tid; i < total_ints; i += kBlock) dst[i] = tile[i];
+    } else {
+        for (int64_t i = tid; i < total_ints; i += kBlock) dst[i] = tile[i];
+    }
+
+    if (!with_stats) return;
+    unsigned long long cut2 = 0;
+    for (int i = tid; i < nt; i += kBlock) {
+        const int64_t v = v0 + i;
+        const int32_t a = part[v];
+        if ((unsigned)a >= (unsigned)k) {
+            atomicAdd(&counters[CNT_BAD_INPUT], 1ull);
+            continue;
+        }
+        const int64_t cv = g.vwgt ? (int64_t)g.vwgt[v] : 1;
+        if (W) atomic_add_i64(&W[a], cv);
+        const int64_t deg = g.xadj[v + 1] - gstart[i];
+        if (deg > hub_t) continue;  // hub: its row is finished by the hub kernels
+        const int64_t inner = tile[i * k + a];
+        const int64_t wd = wdeg[v];
+        cut2 += (unsigned long long)(wd - inner);
+        if ((int64_t)t_den * inner >= (int64_t)t_num * wd)
+            atomic_add_i64(&bucket[(int64_t)a * kSlots + slot_of(inner, cv)], cv);
+    }
+    cut2 = block_sum(cut2, red_lds);
+    if (tid == 0 && cut2) atomicAdd(&counters[CNT_CUT2_BEFORE], cut2);
+}
+
+hipError_t launch_gain_tile(const GraphView &g, int32_t k, const int32_t *part, int32_t *conn,
+                            const int32_t *wdeg, int64_t hub_t, int64_t *W, int64_t *bucket,
+                            int32_t t_num, int32_t t_den, unsigned long long *counters,
+                            int with_stats, hipStream_t s)
+{
+    if (g.n <= 0) return hipSuccess;
+    const int T = gain_tile_nodes(k);
+    const int64_t tiles = (g.n + T - 1) / T;
+    const size_t lds = gain_tile_lds(k, T);
+    if (g.adjwgt)
+        hipLaunchKernelGGL(k_gain_tile<true>, dim3((unsigned)tiles), dim3(kBlock), lds, s, g, k, T,
+                           part, conn, wdeg, hub_t, W, bucket, t_num, t_den, counters, with_stats);
+    else
+        hipLaunchKernelGGL(k_gain_tile<false>, dim3((unsigned)tiles), dim3(kBlock), lds, s, g, k,
+                           T, part, conn, wdeg, hub_t, W, bucket, t_num, t_den, counters,
+                           with_stats);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------- hub rows --
+
+// One workgroup per chunk of a hub's edges: accumulate into an LDS row, then
+// add the non-zero entries into the hub's row of conn (zeroed by the tile).
+__global__ __launch_bounds__(kBlock) void k_gain_hub(GraphView g, int32_t k,
+                                                      const int32_t *__restrict__ part,
+                                                      int32_t *conn, HubView h)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    int32_t *row = (int32_t *)lds_raw;
+    const HubChunk c = h.chunks[blockIdx.x];
+    const int64_t v = h.ids[c.hub];
+    for (int j = threadIdx.x; j < k; j += kBlock) row[j] = 0;
+    __syncthreads();
+    for (int64_t e = c.e0 + threadIdx.x; e < c.e1; e += kBlock) {
+        const int32_t pu = part[g.adjncy[e]];
+        if ((unsigned)pu < (unsigned)k) atomicAdd(&row[pu], edge_weight(g, e));
+    }
+    __syncthreads();
+    int32_t *dst = conn + v * (int64_t)k;
+    for (int j = threadIdx.x; j < k; j += kBlock)
+        if (row[j]) atomicAdd(&dst[j], row[j]);
+}
+
+hipError_t launch_gain_hub(const GraphView &g, int32_t k, const int32_t *part, int32_t *conn,
+                           const HubView &h, hipStream_t s)
+{
+    if (h.nchunks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gain_hub, dim3((unsigned)h.nchunks), dim3(kBlock), (size_t)k * 4, s, g, k,
+                       part, conn, h);
+    return hipGetLastError();
+}
+
+// Per hub: cut contribution and penalty bucket from the finished row.
+__global__ void k_hub_stats(GraphView g, int32_t k, const int32_t *part, const int32_t *conn,
+                            const int32_t *wdeg, HubView h, int64_t *bucket, int32_t t_num,
+                            int32_t t_den, unsigned long long *counters)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= h.nh) return;
+    const int64_t v = h.ids[i];
+    const int32_t a = part[v];
+    if ((unsigned)a >= (unsigned)k) return;  // reported by the tile kernel
+    const int64_t inner = conn[v * (int64_t)k + a];
+    const int64_t wd = wdeg[v];
+    const int64_t cv = node_weight(g, v);
+    atomicAdd(&counters[CNT_CUT2_BEFORE], (unsigned long long)(wd - inner));
+    if ((int64_t)t_den * inner >= (int64_t)t_num * wd)
+        atomic_add_i64(&bucket[(int64_t)a * kSlots + slot_of(inner, cv)], cv);
+}
+
+hipError_t launch_hub_stats(const GraphView &g, int32_t k, const int32_t *part, const int32_t *conn,
+                            const int32_t *wdeg, const HubView &h, int64_t *bucket, int32_t t_num,
+                            int32_t t_den, unsigned long long *counters, hipStream_t s)
+{
+    if (h.nh <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hub_stats, dim3((h.nh + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g, k,
+                       part, conn, wdeg, h, bucket, t_num, t_den, counters);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------- block weights --
+
+__global__ __launch_bounds__(kBlock) void k_block_weights(GraphView g, int32_t k,
+                                                           const int32_t *part, int64_t *W,
+                                                           unsigned long long *counters)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    int64_t *loc = (int64_t *)lds_raw;
+    const bool use_lds = k <= 2048;
+    if (use_lds) {
+        for (int j = threadIdx.x; j < k; j += kBlock) loc[j] = 0;
+        __syncthreads();
+    }
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += stride) {
+        const int32_t a = part[v];
+        if ((unsigned)a >= (unsigned)k) {
+            atomicAdd(&counters[CNT_BAD_INPUT], 1ull);
+            continue;
+        }
+        const int64_t c = node_weight(g, v);
+        if (use_lds) atomicAdd((unsigned long long *)&loc[a], (unsigned long long)c);
+        else atomic_add_i64(&W[a], c);
+    }
+    if (use_lds) {
+        __syncthreads();
+        for (int j = threadIdx.x; j < k; j += kBlock)
+            if (loc[j]) atomic_add_i64(&W[j], loc[j]);
+    }
+}
+
+hipError_t launch_block_weights(const GraphView &g, int32_t k, const int32_t *part, int64_t *W,
+                                unsigned long long *counters, hipStream_t s)
+{
+    if (g.n <= 0) return hipSuccess;
+    const size_t lds = k <= 2048 ? (size_t)k * 8 : 0;
+    hipLaunchKernelGGL(k_block_weights, dim3(grid_for(g.n, kBlock * 8, 2048)), dim3(kBlock), lds, s,
+                       g, k, part, W, counters);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------- cut --
+
+// 2 * cut = sum_v (omega(I(v)) - omega(v, Pi(v))) from the table.
+__global__ __launch_bounds__(kBlock) void k_cut_table(GraphView g, int32_t k,
+                                                       const int32_t *__restrict__ part,
+                                                       const int32_t *__restrict__ conn,
+                                                       const int32_t *__restrict__ wdeg,
+                                                       unsigned long long *acc)
+{
+    __shared__ unsigned long long red[4];
+    unsigned long long s = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += stride) {
+        const int32_t a = part[v];
+        if ((unsigned)a >= (unsigned)k) continue;
+        s += (unsigned long long)((int64_t)wdeg[v] - conn[v * (int64_t)k + a]);
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0 && s) atomicAdd(acc, s);
+}
+
+hipError_t launch_cut_table(const GraphView &g, int32_t k, const int32_t *part, const int32_t *conn,
+                            const int32_t *wdeg, unsigned long long *acc, hipStream_t s)
+{
+    if (g.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cut_table, dim3(grid_for(g.n, kBlock * 4, 4096)), dim3(kBlock), 0, s, g, k,
+                       part, conn, wdeg, acc);
+    return hipGetLastError();
+}
+
+// Resident form: 2 * cut and the penalty buckets from an existing table.
+__global__ __launch_bounds__(kBlock) void k_node_stats(GraphView g, int32_t k,
+                                                        const int32_t *__restrict__ part,
+                                                        const int32_t *__restrict__ conn,
+                                                        const int32_t *__restrict__ wdeg,
+                                                        int64_t *bucket, int32_t t_num,
+                                                        int32_t t_den, unsigned long long *counters)
+{
+    __shared__ unsigned long long red[4];
+    unsigned long long s = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += stride) {
+        const int32_t a = part[v];
+        if ((unsigned)a >= (unsigned)k) {
+            atomicAdd(&counters[CNT_BAD_INPUT], 1ull);
+            continue;
+        }
+        const int64_t inner = conn[v * (int64_t)k + a];
+        const int64_t wd = wdeg[v];
+        s += (unsigned long long)(wd - inner);
+        if ((int64_t)t_den * inner >= (int64_t)t_num * wd) {
+            const int64_t cv = node_weight(g, v);
+            atomic_add_i64(&bucket[(int64_t)a * kSlots + slot_of(inner, cv)], cv);
+        }
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0 && s) atomicAdd(&counters[CNT_CUT2_BEFORE], s);
+}
+
+hipError_t launch_node_stats(const GraphView &g, int32_t k, const int32_t *part,
+                             const int32_t *conn, const int32_t *wdeg, int64_t *bucket,
+                             int32_t t_num, int32_t t_den, unsigned long long *counters,
+                             hipStream_t s)
+{
+    if (g.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_node_stats, dim3(grid_for(g.n, kBlock * 4, 4096)), dim3(kBlock), 0, s, g,
+                       k, part, conn, wdeg, bucket, t_num, t_den, counters);
+    return hipGetLastError();
+}
+
+__global__ void k_store_half(const unsigned long long *acc, int64_t *out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = (int64_t)(*acc / 2);
+}
+
+hipError_t launch_store_half(const unsigned long long *acc, int64_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_store_half, dim3(1), dim3(64), 0, s, acc, out);
+    return hipGetLastError();
+}
+
+// Hub row ranges: e0[i] = xadj[ids[i]], e1[i] = xadj[ids[i] + 1].
+__global__ void k_hub_ranges(const int64_t *xadj, const int32_t *ids, int32_t nh, int64_t *e01)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nh) return;
+    e01[2 * i] = xadj[ids[i]];
+    e01[2 * i + 1] = xadj[ids[i] + 1];
+}
+
+hipError_t launch_hub_ranges(const int64_t *xadj, const int32_t *ids, int32_t nh, int64_t *e01,
+                             hipStream_t s)
+{
+    if (nh <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hub_ranges, dim3((nh + kBlock - 1) / kBlock), dim3(kBlock), 0, s, xadj,
+                       ids, nh, e01);
+    return hipGetLastError();
+}
+
+// 2 * cut straight from the adjacency (Section 2 definition): one wave per
+// node, lanes over the row.
+__global__ __launch_bounds__(kBlock) void k_cut_edges(GraphView g,
+                                                       const int32_t *__restrict__ part,
+                                                       unsigned long long *acc)
+{
+    __shared__ unsigned long long red[4];
+    const int lane = lane_id();
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
+    unsigned long long s = 0;
+    for (int64_t v = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); v < g.n; v += waves) {
+        const int32_t a = part[v];
+        for (int64_t e = g.xadj[v] + lane; e < g.xadj[v + 1]; e += 64)
+            if (part[g.adjncy[e]] != a) s += (unsigned long long)edge_weight(g, e);
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0 && s) atomicAdd(acc, s);
+}
+
+hipError_t launch_cut_edges(const GraphView &g, const int32_t *part, unsigned long long *acc,
+                            hipStream_t s)
+{
+    if (g.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cut_edges, dim3(grid_for(g.n, kBlock / 64, 16384)), dim3(kBlock), 0, s, g,
+                       part, acc);
+    return hipGetLastError();
+}
+
+__global__ void k_check_part(int64_t n, int32_t k, const int32_t *part, unsigned long long *counters)
+{
+    bool bad = false;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+        bad |= (unsigned)part[v] >= (unsigned)k;
+    if (__ballot(bad) && lane_id() == 0) atomicAdd(&counters[CNT_BAD_INPUT], 1ull);
+}
+
+hipError_t launch_check_part(int64_t n, int32_t k, const int32_t *part,
+                             unsigned long long *counters, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_part, dim3(grid_for(n, kBlock * 8, 2048)), dim3(kBlock), 0, s, n, k,
+                       part, counters);
+    return hipGetLastError();
+}
+
+}  // namespace upr

@@ -1,0 +1,735 @@
+// Host side of libupr: the C ABI declared in include/upr.h.
+//
+// A context owns the device workspace (grown on demand) and a small pinned
+// buffer for the counters the rebalancing loop decides on. A plan holds a
+// prepared graph: weighted degrees, total node weight and the hub list with
+// its edge chunks. Every round is a fixed sequence of kernels on the caller's
+// stream; the only host decisions are the rebalancing sub-iterations.
+#include "upr.h"
+#include "upr_common.h"
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace upr;
+
+namespace {
+
+constexpr int64_t kHubChunkEdges = 4096;
+constexpr int64_t kDefaultHubThreshold = 4096;
+constexpr int64_t kDefaultLowThreshold = 32;
+constexpr int64_t kChunkEntries = int64_t(1) << 20;  // rebalancing id-chunk sums per side
+
+struct Timing {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    struct Pending {
+        int phase;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    double ms[UPR_NUM_PHASES] = {0};
+    int64_t counts[UPR_NUM_PHASES] = {0};
+};
+
+int64_t env_int(const char *name, int64_t dflt)
+{
+    const char *s = getenv(name);
+    if (!s || !*s) return dflt;
+    return strtoll(s, nullptr, 10);
+}
+
+}  // namespace
+
+struct upr_ctx {
+    int device = 0;
+    std::string err;
+    // workspace
+    int64_t cap_n = 0, cap_k = 0;
+    int64_t *key = nullptr, *pen = nullptr;
+    uint8_t *accflag = nullptr;
+    int32_t *cl_low = nullptr, *cl_mid = nullptr;
+    Move *mv_low = nullptr, *mv_mid = nullptr;
+    int64_t *bucket = nullptr, *penq = nullptr;
+    unsigned long long *counters = nullptr;
+    unsigned long long *flags = nullptr;  // validation flags [4]
+    RebalWs rb{};
+    unsigned long long *pinned = nullptr;  // host mirror of counters
+    bool rb_dirty = false;
+    Timing timing;
+};
+
+struct upr_plan {
+    upr_ctx *ctx = nullptr;
+    GraphView g{};
+    int64_t nnz = 0, total = 0, maxdeg = 0, maxwdeg = 0, maxvw = 0;
+    int32_t *wdeg = nullptr;
+    int32_t nh = 0;
+    int32_t *hub_ids = nullptr;
+    HubChunk *chunks = nullptr;
+    int64_t nchunks = 0;
+    int32_t *hub_from = nullptr, *hub_to = nullptr;
+    int64_t *gacc = nullptr;
+    int64_t hub_t = kDefaultHubThreshold, low_t = kDefaultLowThreshold;
+
+    HubView hubs() const
+    {
+        return HubView{nh, hub_ids, chunks, nchunks, hub_from, hub_to, gacc};
+    }
+};
+
+namespace {
+
+int fail(upr_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                  \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((ctx), UPR_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));  \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(T **p, int64_t count)
+{
+    *p = nullptr;
+    if (count <= 0) count = 1;
+    return hipMalloc((void **)p, sizeof(T) * (size_t)count);
+}
+
+template <typename T>
+void dfree(T *&p)
+{
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+void free_workspace(upr_ctx *c)
+{
+    dfree(c->key);
+    dfree(c->pen);
+    dfree(c->accflag);
+    dfree(c->cl_low);
+    dfree(c->cl_mid);
+    dfree(c->mv_low);
+    dfree(c->mv_mid);
+    dfree(c->bucket);
+    dfree(c->rb.rtgt);
+    dfree(c->rb.rbeta);
+    dfree(c->rb.olist);
+    dfree(c->rb.W0);
+    dfree(c->rb.hist_src);
+    dfree(c->rb.hist_tgt);
+    dfree(c->rb.cbeta_src);
+    dfree(c->rb.cbeta_tgt);
+    dfree(c->rb.need_src);
+    dfree(c->rb.room_tgt);
+    dfree(c->rb.theta_src);
+    dfree(c->rb.theta_tgt);
+    dfree(c->rb.chunk_src);
+    dfree(c->rb.chunk_tgt);
+    c->cap_n = c->cap_k = 0;
+}
+
+// Grow the workspace to hold n nodes and k blocks.
+int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
+{
+    if (n <= c->cap_n && k <= c->cap_k && !c->rb_dirty) return UPR_OK;
+    const int64_t N = std::max<int64_t>(std::max(n, c->cap_n), 1);
+    const int64_t K = std::max<int64_t>(std::max<int64_t>(k, c->cap_k), 2);
+    HIP_TRY(c, hipDeviceSynchronize());
+    free_workspace(c);
+    bool ok = dalloc(&c->key, N) == hipSuccess && dalloc(&c->pen, N) == hipSuccess &&
+              dalloc(&c->accflag, N) == hipSuccess && dalloc(&c->cl_low, N) == hipSuccess &&
+              dalloc(&c->cl_mid, N) == hipSuccess && dalloc(&c->mv_low, N) == hipSuccess &&
+              dalloc(&c->mv_mid, N) == hipSuccess && dalloc(&c->bucket, K * kSlots) == hipSuccess &&
+              dalloc(&c->rb.rtgt, N) == hipSuccess && dalloc(&c->rb.rbeta, N) == hipSuccess &&
+              dalloc(&c->rb.olist, N) == hipSuccess && dalloc(&c->rb.W0, K) == hipSuccess &&
+              dalloc(&c->rb.hist_src, K * kRbBuckets) == hipSuccess &&
+              dalloc(&c->rb.hist_tgt, K * kRbBuckets) == hipSuccess &&
+              dalloc(&c->rb.cbeta_src, K) == hipSuccess && dalloc(&c->rb.cbeta_tgt, K) == hipSuccess &&
+              dalloc(&c->rb.need_src, K) == hipSuccess && dalloc(&c->rb.room_tgt, K) == hipSuccess &&
+              dalloc(&c->rb.theta_src, K) == hipSuccess && dalloc(&c->rb.theta_tgt, K) == hipSuccess &&
+              dalloc(&c->rb.chunk_src, kChunkEntries) == hipSuccess &&
+              dalloc(&c->rb.chunk_tgt, kChunkEntries) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        free_workspace(c);
+        return fail(c, UPR_E_NOMEM, "workspace allocation failed for n=%lld k=%lld", (long long)N,
+                    (long long)K);
+    }
+    HIP_TRY(c, hipMemset(c->rb.hist_src, 0, sizeof(int64_t) * K * kRbBuckets));
+    HIP_TRY(c, hipMemset(c->rb.hist_tgt, 0, sizeof(int64_t) * K * kRbBuckets));
+    HIP_TRY(c, hipMemset(c->rb.chunk_src, 0, sizeof(int64_t) * kChunkEntries));
+    HIP_TRY(c, hipMemset(c->rb.chunk_tgt, 0, sizeof(int64_t) * kChunkEntries));
+    HIP_TRY(c, hipMemset(c->key, 0xff, sizeof(int64_t) * N));
+    HIP_TRY(c, hipDeviceSynchronize());
+    c->cap_n = N;
+    c->cap_k = K;
+    c->rb_dirty = false;
+    return UPR_OK;
+}
+
+// Chunking of node ids for the rebalancer's in-bucket id bounds.
+void set_chunking(RebalWs &r, int64_t n, int32_t k)
+{
+    int64_t nch_max = kChunkEntries / std::max<int32_t>(k, 1);
+    if (nch_max > 4096) nch_max = 4096;
+    int shift = 0;
+    while (((n + ((int64_t)1 << shift) - 1) >> shift) > nch_max) ++shift;
+    r.chunk_shift = shift;
+    r.nchunks = std::max<int64_t>((n + ((int64_t)1 << shift) - 1) >> shift, 1);
+}
+
+hipEvent_t take_event(upr_ctx *c)
+{
+    if (!c->timing.pool.empty()) {
+        hipEvent_t e = c->timing.pool.back();
+        c->timing.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct PhaseTimer {
+    upr_ctx *c;
+    int phase;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    PhaseTimer(upr_ctx *c_, int p, hipStream_t s_) : c(c_), phase(p), s(s_)
+    {
+        if (c->timing.on && (a = take_event(c))) (void)hipEventRecord(a, s);
+    }
+    ~PhaseTimer()
+    {
+        if (!a) return;
+        hipEvent_t b = take_event(c);
+        if (!b) {
+            c->timing.pool.push_back(a);
+            return;
+        }
+        (void)hipEventRecord(b, s);
+        c->timing.pending.push_back({phase, a, b});
+    }
+};
+
+int check_params(upr_ctx *c, const upr_plan *p, const upr_params *q)
+{
+    if (!q) return fail(c, UPR_E_ARG, "params is NULL");
+    if (q->k < 2 || q->k > UPR_MAX_K) return fail(c, UPR_E_ARG, "k=%d outside [2, %d]", q->k, UPR_MAX_K);
+    if (q->eps_num <= 0 || q->eps_den <= 0) return fail(c, UPR_E_ARG, "eps must be > 0");
+    if (q->t_den <= 0 || q->t_num < 0 || q->t_num > q->t_den) return fail(c, UPR_E_ARG, "t must be in [0, 1]");
+    if (q->tau_den <= 0 || q->tau_num < 0 || q->tau_num > q->tau_den)
+        return fail(c, UPR_E_ARG, "tau must be in [0, 1]");
+    if (q->mode < 0 || q->mode > 2) return fail(c, UPR_E_ARG, "mode=%d not in {0,1,2}", q->mode);
+    if (q->max_rebalance_iters < 0) return fail(c, UPR_E_ARG, "max_rebalance_iters < 0");
+    (void)p;
+    return UPR_OK;
+}
+
+int check_plan(upr_ctx *c, const upr_plan *p)
+{
+    if (!c) return UPR_E_ARG;
+    if (!p) return fail(c, UPR_E_ARG, "plan is NULL");
+    if (p->ctx != c) return fail(c, UPR_E_ARG, "plan belongs to another context");
+    return UPR_OK;
+}
+
+// Copy the counters to the pinned mirror and wait.
+int sync_counters(upr_ctx *c, hipStream_t s)
+{
+    HIP_TRY(c, hipMemcpyAsync(c->pinned, c->counters, sizeof(unsigned long long) * CNT_COUNT,
+                              hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return UPR_OK;
+}
+
+int64_t default_iters(const upr_plan *p, int32_t k)
+{
+    return p->g.vwgt ? 4 * (int64_t)k : (int64_t)k + 1;
+}
+
+// S5: the host loop over synchronous sub-iterations.
+int rebalance_loop(upr_ctx *c, const upr_plan *p, int32_t k, int32_t *part, int32_t *conn,
+                   int64_t *W, int64_t lmax, int64_t it_max, int64_t *iters_out,
+                   int64_t *status_out, hipStream_t s)
+{
+    const HubView h = p->hubs();
+    int64_t iters = 0, status = 0;
+    c->rb_dirty = true;
+    HIP_TRY(c, launch_rb_begin(k, W, lmax, c->rb, c->counters, s));
+    int rc = sync_counters(c, s);
+    if (rc) return rc;
+    if (c->pinned[CNT_BAD_INPUT]) return fail(c, UPR_E_ARG, "part holds values outside [0, k)");
+    for (;;) {
+        if (c->pinned[CNT_OVER] == 0) break;
+        if (iters > 0 && c->pinned[CNT_MOVED_NOW] == 0) {
+            status = 1;
+            break;
+        }
+        if (iters >= it_max) {
+            status = 1;
+            break;
+        }
+        ++iters;
+        HIP_TRY(c, launch_rb_iteration(p->g, k, part, conn, lmax, p->hub_t, p->low_t, c->rb, h,
+                                       c->mv_low, c->mv_mid, c->counters, s));
+        HIP_TRY(c, launch_apply(p->g, k, part, conn, W, c->mv_low, c->mv_mid, h, c->counters, s));
+        HIP_TRY(c, launch_rb_begin(k, W, lmax, c->rb, c->counters, s));
+        rc = sync_counters(c, s);
+        if (rc) return rc;
+    }
+    c->rb_dirty = false;
+    *iters_out = iters;
+    *status_out = status;
+    return UPR_OK;
+}
+
+void host_penq(int32_t tau_num, int32_t tau_den, int64_t *out)
+{
+    // floor(tau_num * 3^l * 2^16 / (tau_den * 2^l)) by exact long division:
+    // numerator N = tau_num * 3^l (< 2^117), denominator D = tau_den * 2^l.
+    for (int l = 0; l < kSlots; ++l) {
+        unsigned __int128 N = (unsigned __int128)(uint32_t)tau_num;
+        for (int i = 0; i < l; ++i) N *= 3;
+        const unsigned __int128 D = (unsigned __int128)(uint32_t)tau_den << l;
+        const unsigned __int128 q = N / D;
+        const unsigned __int128 r = N - q * D;
+        out[l] = (int64_t)((q << 16) + ((r << 16) / D));
+    }
+}
+
+}  // namespace
+
+// ==================================================================== ABI ==
+
+extern "C" {
+
+int64_t upr_lmax(int64_t total, int32_t k, int32_t eps_num, int32_t eps_den)
+{
+    if (k <= 0 || eps_den <= 0 || total < 0) return -1;
+    const int64_t avg = total / k + (total % k != 0);
+    const unsigned __int128 x = (unsigned __int128)(uint64_t)avg * (uint64_t)((int64_t)eps_den + eps_num);
+    return (int64_t)(x / (uint64_t)eps_den);
+}
+
+int upr_penalty_table(int32_t tau_num, int32_t tau_den, int64_t *out)
+{
+    if (!out || tau_den <= 0 || tau_num < 0 || tau_num > tau_den) return UPR_E_ARG;
+    host_penq(tau_num, tau_den, out);
+    return UPR_OK;
+}
+
+int upr_create(upr_ctx **out, int device)
+{
+    if (!out) return UPR_E_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+        (void)hipGetLastError();
+        return UPR_E_HIP;
+    }
+    upr_ctx *c = new upr_ctx();
+    c->device = device;
+    if (hipSetDevice(device) != hipSuccess ||
+        hipMalloc((void **)&c->counters, sizeof(unsigned long long) * CNT_COUNT) != hipSuccess ||
+        hipMalloc((void **)&c->flags, sizeof(unsigned long long) * 8) != hipSuccess ||
+        hipMalloc((void **)&c->penq, sizeof(int64_t) * kSlots) != hipSuccess ||
+        hipHostMalloc((void **)&c->pinned, sizeof(unsigned long long) * CNT_COUNT) != hipSuccess) {
+        (void)hipGetLastError();
+        upr_destroy(c);
+        return UPR_E_NOMEM;
+    }
+    (void)hipMemset(c->counters, 0, sizeof(unsigned long long) * CNT_COUNT);
+    *out = c;
+    return UPR_OK;
+}
+
+void upr_destroy(upr_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    free_workspace(c);
+    dfree(c->counters);
+    dfree(c->flags);
+    dfree(c->penq);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    for (auto &p : c->timing.pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : c->timing.pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+const char *upr_last_error(const upr_ctx *c)
+{
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+int upr_validate_graph(upr_ctx *c, const upr_graph *graph, hipStream_t s)
+{
+    if (!c) return UPR_E_ARG;
+    if (!graph) return fail(c, UPR_E_ARG, "graph is NULL");
+    if (graph->n < 0 || graph->n >= ((int64_t)1 << 31)) return fail(c, UPR_E_ARG, "n out of range");
+    if (graph->n > 0 && (!graph->xadj || !graph->adjncy)) return fail(c, UPR_E_ARG, "xadj/adjncy NULL");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const GraphView g{graph->n, graph->xadj, graph->adjncy, graph->adjwgt, graph->vwgt};
+    if (g.n == 0) return UPR_OK;
+    unsigned long long init[4] = {~0ull, ~0ull, ~0ull, ~0ull}, got[4];
+    for (int stage = 0; stage < 3; ++stage) {
+        HIP_TRY(c, hipMemcpyAsync(c->flags, init, sizeof init, hipMemcpyHostToDevice, s));
+        HIP_TRY(c, launch_validate(g, c->flags, stage, s));
+        HIP_TRY(c, hipMemcpyAsync(got, c->flags, sizeof got, hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        if (stage == 0) {
+            int64_t x0 = -1;
+            HIP_TRY(c, hipMemcpy(&x0, g.xadj, sizeof x0, hipMemcpyDeviceToHost));
+            if (x0 != 0) return fail(c, UPR_E_GRAPH, "xadj[0] = %lld, expected 0", (long long)x0);
+            if (got[0] != ~0ull) return fail(c, UPR_E_GRAPH, "xadj decreases at %llu", got[0]);
+            if (got[3] != ~0ull) return fail(c, UPR_E_GRAPH, "node weight <= 0 at node %llu", got[3]);
+        } else {
+            if (got[1] != ~0ull)
+                return fail(c, UPR_E_GRAPH,
+                            stage == 1 ? "neighbour id out of range at entry %llu"
+                                       : "self-loop, unsorted row or duplicate at entry %llu",
+                            got[1]);
+            if (got[3] != ~0ull) return fail(c, UPR_E_GRAPH, "edge weight <= 0 at entry %llu", got[3] - g.n);
+            if (stage == 2 && got[2] != ~0ull)
+                return fail(c, UPR_E_GRAPH, "entry %llu has no symmetric counterpart (or its weight differs)",
+                            got[2]);
+        }
+    }
+    return UPR_OK;
+}
+
+int upr_plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipStream_t s)
+{
+    if (!c) return UPR_E_ARG;
+    if (!out) return fail(c, UPR_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!graph) return fail(c, UPR_E_ARG, "graph is NULL");
+    if (graph->n < 0 || graph->n >= ((int64_t)1 << 31)) return fail(c, UPR_E_ARG, "n out of range");
+    if (graph->n > 0 && (!graph->xadj || !graph->adjncy)) return fail(c, UPR_E_ARG, "xadj/adjncy NULL");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const GraphView g{graph->n, graph->xadj, graph->adjncy, graph->adjwgt, graph->vwgt};
+
+    // basic validation: xadj, ids in range, positive weights (kernels rely on it)
+    if (g.n > 0) {
+        unsigned long long init[4] = {~0ull, ~0ull, ~0ull, ~0ull}, got[4];
+        for (int stage = 0; stage < 2; ++stage) {
+            HIP_TRY(c, hipMemcpyAsync(c->flags, init, sizeof init, hipMemcpyHostToDevice, s));
+            HIP_TRY(c, launch_validate(g, c->flags, stage, s));
+            HIP_TRY(c, hipMemcpyAsync(got, c->flags, sizeof got, hipMemcpyDeviceToHost, s));
+            HIP_TRY(c, hipStreamSynchronize(s));
+            int64_t x0 = 0;
+            if (stage == 0) HIP_TRY(c, hipMemcpy(&x0, g.xadj, sizeof x0, hipMemcpyDeviceToHost));
+            if (x0 != 0 || got[0] != ~0ull) return fail(c, UPR_E_GRAPH, "xadj is not a valid offset array");
+            if (got[1] != ~0ull) return fail(c, UPR_E_GRAPH, "neighbour id out of range at entry %llu", got[1]);
+            if (got[3] != ~0ull) return fail(c, UPR_E_GRAPH, "non-positive node or edge weight");
+        }
+    }
+
+    upr_plan *p = new upr_plan();
+    p->ctx = c;
+    p->g = g;
+    p->hub_t = env_int("UPR_HUB_THRESHOLD", kDefaultHubThreshold);
+    p->low_t = env_int("UPR_LOW_THRESHOLD", kDefaultLowThreshold);
+    // a tile's edge count (nodes per tile x hub threshold) must fit int32
+    p->hub_t = std::min<int64_t>(std::max<int64_t>(p->hub_t, 1), (int64_t)1 << 20);
+    p->low_t = std::min<int64_t>(std::max<int64_t>(p->low_t, 0), p->hub_t);
+    int32_t *hub_list = nullptr;
+    auto bail = [&](int code, const char *msg) {
+        dfree(hub_list);
+        upr_plan_destroy(p);
+        return fail(c, code, "%s", msg);
+    };
+    if (g.n > 0) {
+        if (hipMemcpy(&p->nnz, g.xadj + g.n, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
+            return bail(UPR_E_HIP, "reading xadj[n] failed");
+        if (dalloc(&p->wdeg, g.n) != hipSuccess || dalloc(&hub_list, g.n) != hipSuccess)
+            return bail(UPR_E_NOMEM, "plan allocation failed");
+        unsigned long long zero[8] = {0}, res[8];
+        if (hipMemcpyAsync(c->flags, zero, sizeof zero, hipMemcpyHostToDevice, s) != hipSuccess ||
+            launch_plan_scan(g, p->wdeg, p->hub_t, hub_list, c->flags, s) != hipSuccess ||
+            hipMemcpyAsync(res, c->flags, sizeof res, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return bail(UPR_E_HIP, "plan scan failed");
+        p->nh = (int32_t)res[0];
+        p->maxdeg = (int64_t)res[1];
+        p->maxwdeg = (int64_t)res[2];
+        p->total = (int64_t)res[3];
+        p->maxvw = (int64_t)res[4];
+        if (p->maxwdeg >= ((int64_t)1 << 31) - 1)
+            return bail(UPR_E_GRAPH, "a weighted degree does not fit int32 (gain table entries are int32)");
+        if (p->total >= ((int64_t)1 << 62)) return bail(UPR_E_GRAPH, "total node weight >= 2^62");
+        if (p->nh > 0) {
+            std::vector<int32_t> ids(p->nh);
+            if (hipMemcpy(ids.data(), hub_list, sizeof(int32_t) * p->nh, hipMemcpyDeviceToHost) != hipSuccess)
+                return bail(UPR_E_HIP, "reading the hub list failed");
+            std::sort(ids.begin(), ids.end());
+            if (dalloc(&p->hub_ids, p->nh) != hipSuccess || dalloc(&p->hub_from, p->nh) != hipSuccess ||
+                dalloc(&p->hub_to, p->nh) != hipSuccess || dalloc(&p->gacc, p->nh) != hipSuccess)
+                return bail(UPR_E_NOMEM, "plan allocation failed");
+            std::vector<int64_t> e01(2 * (size_t)p->nh);
+            int64_t *d_e01 = nullptr;
+            if (dalloc(&d_e01, 2 * (int64_t)p->nh) != hipSuccess) return bail(UPR_E_NOMEM, "plan allocation failed");
+            bool ok = hipMemcpy(p->hub_ids, ids.data(), sizeof(int32_t) * p->nh, hipMemcpyHostToDevice) == hipSuccess &&
+                      launch_hub_ranges(g.xadj, p->hub_ids, p->nh, d_e01, s) == hipSuccess &&
+                      hipStreamSynchronize(s) == hipSuccess &&
+                      hipMemcpy(e01.data(), d_e01, sizeof(int64_t) * 2 * p->nh, hipMemcpyDeviceToHost) == hipSuccess;
+            dfree(d_e01);
+            if (!ok) return bail(UPR_E_HIP, "hub preparation failed");
+            std::vector<HubChunk> chunks;
+            for (int32_t i = 0; i < p->nh; ++i)
+                for (int64_t e = e01[2 * i]; e < e01[2 * i + 1]; e += kHubChunkEdges)
+                    chunks.push_back(HubChunk{i, 0, e, std::min(e + kHubChunkEdges, e01[2 * i + 1])});
+            p->nchunks = (int64_t)chunks.size();
+            if (dalloc(&p->chunks, p->nchunks) != hipSuccess) return bail(UPR_E_NOMEM, "plan allocation failed");
+            ok = hipMemcpy(p->chunks, chunks.data(), sizeof(HubChunk) * chunks.size(), hipMemcpyHostToDevice) == hipSuccess &&
+                 launch_fill_i32(p->hub_to, p->nh, -1, s) == hipSuccess &&
+                 launch_fill_i64(p->gacc, p->nh, 0, s) == hipSuccess &&
+                 hipStreamSynchronize(s) == hipSuccess;
+            if (!ok) return bail(UPR_E_HIP, "hub preparation failed");
+        }
+        dfree(hub_list);
+    }
+    *out = p;
+    return UPR_OK;
+}
+
+void upr_plan_destroy(upr_plan *p)
+{
+    if (!p) return;
+    if (p->ctx) (void)hipSetDevice(p->ctx->device);
+    (void)hipDeviceSynchronize();
+    dfree(p->wdeg);
+    dfree(p->hub_ids);
+    dfree(p->chunks);
+    dfree(p->hub_from);
+    dfree(p->hub_to);
+    dfree(p->gacc);
+    delete p;
+}
+
+int upr_plan_info(const upr_plan *p, int64_t *n, int64_t *nnz, int64_t *total, int64_t *maxdeg,
+                  int64_t *nh)
+{
+    if (!p) return UPR_E_ARG;
+    if (n) *n = p->g.n;
+    if (nnz) *nnz = p->nnz;
+    if (total) *total = p->total;
+    if (maxdeg) *maxdeg = p->maxdeg;
+    if (nh) *nh = p->nh;
+    return UPR_OK;
+}
+
+int upr_gain_table(upr_ctx *c, const upr_plan *p, int32_t k, const int32_t *part, int32_t *conn,
+                   hipStream_t s)
+{
+    int rc = check_plan(c, p);
+    if (rc) return rc;
+    if (k < 2 || k > UPR_MAX_K) return fail(c, UPR_E_ARG, "k=%d outside [2, %d]", k, UPR_MAX_K);
+    if (p->g.n > 0 && (!part || !conn)) return fail(c, UPR_E_ARG, "part/conn NULL");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipMemsetAsync(c->counters, 0, sizeof(unsigned long long) * CNT_COUNT, s));
+    HIP_TRY(c, launch_check_part(p->g.n, k, part, c->counters, s));
+    rc = sync_counters(c, s);
+    if (rc) return rc;
+    if (c->pinned[CNT_BAD_INPUT]) return fail(c, UPR_E_ARG, "part holds values outside [0, k)");
+    PhaseTimer t(c, 0, s);
+    HIP_TRY(c, launch_gain_tile(p->g, k, part, conn, p->wdeg, p->hub_t, nullptr, nullptr, 0, 1,
+                                c->counters, 0, s));
+    HIP_TRY(c, launch_gain_hub(p->g, k, part, conn, p->hubs(), s));
+    return UPR_OK;
+}
+
+int upr_block_weights(upr_ctx *c, const upr_plan *p, int32_t k, const int32_t *part, int64_t *W,
+                      hipStream_t s)
+{
+    int rc = check_plan(c, p);
+    if (rc) return rc;
+    if (k < 2 || k > UPR_MAX_K) return fail(c, UPR_E_ARG, "k=%d outside [2, %d]", k, UPR_MAX_K);
+    if (!W || (p->g.n > 0 && !part)) return fail(c, UPR_E_ARG, "part/block_w NULL");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipMemsetAsync(c->counters, 0, sizeof(unsigned long long) * CNT_COUNT, s));
+    HIP_TRY(c, launch_check_part(p->g.n, k, part, c->counters, s));
+    rc = sync_counters(c, s);
+    if (rc) return rc;
+    if (c->pinned[CNT_BAD_INPUT]) return fail(c, UPR_E_ARG, "part holds values outside [0, k)");
+    HIP_TRY(c, launch_fill_i64(W, k, 0, s));
+    HIP_TRY(c, launch_block_weights(p->g, k, part, W, c->counters, s));
+    return UPR_OK;
+}
+
+int upr_edge_cut(upr_ctx *c, const upr_plan *p, const int32_t *part, int64_t *cut, hipStream_t s)
+{
+    int rc = check_plan(c, p);
+    if (rc) return rc;
+    if (!cut || (p->g.n > 0 && !part)) return fail(c, UPR_E_ARG, "part/cut NULL");
+    HIP_TRY(c, hipSetDevice(c->device));
+    PhaseTimer t(c, 6, s);
+    HIP_TRY(c, hipMemsetAsync(c->counters + CNT_TMP, 0, sizeof(unsigned long long), s));
+    HIP_TRY(c, launch_cut_edges(p->g, part, c->counters + CNT_TMP, s));
+    HIP_TRY(c, launch_store_half(c->counters + CNT_TMP, cut, s));
+    return UPR_OK;
+}
+
+static int round_common(upr_ctx *c, const upr_plan *p, const upr_params *q, int32_t *part,
+                        int32_t *conn, int64_t *W, int64_t *stats, hipStream_t s, bool moves)
+{
+    int rc = check_plan(c, p);
+    if (rc) return rc;
+    rc = check_params(c, p, q);
+    if (rc) return rc;
+    const int64_t n = p->g.n;
+    const int32_t k = q->k;
+    if (!W || !stats || (n > 0 && (!part || !conn)))
+        return fail(c, UPR_E_ARG, "part/conn/block_w/stats NULL");
+    const int64_t lmax = upr_lmax(p->total, k, q->eps_num, q->eps_den);
+    if (p->maxvw > lmax)
+        return fail(c, UPR_E_INFEASIBLE, "node weight %lld exceeds L_max %lld", (long long)p->maxvw,
+                    (long long)lmax);
+    HIP_TRY(c, hipSetDevice(c->device));
+    rc = ensure_workspace(c, n, k);
+    if (rc) return rc;
+    set_chunking(c->rb, n, k);
+    const HubView h = p->hubs();
+    PhaseTimer whole(c, 7, s);
+
+    PenTable pq;
+    host_penq(q->tau_num, q->tau_den, pq.q);
+    HIP_TRY(c, launch_round_init(k, c->bucket, W, pq, c->penq, c->counters, q->rebuild_table, s));
+    if (q->rebuild_table) {
+        {
+            PhaseTimer t(c, 0, s);
+            HIP_TRY(c, launch_gain_tile(p->g, k, part, conn, p->wdeg, p->hub_t, W, c->bucket,
+                                        q->t_num, q->t_den, c->counters, 1, s));
+        }
+        if (p->nh > 0) {
+            PhaseTimer t(c, 1, s);
+            HIP_TRY(c, launch_gain_hub(p->g, k, part, conn, h, s));
+            HIP_TRY(c, launch_hub_stats(p->g, k, part, conn, p->wdeg, h, c->bucket, q->t_num,
+                                        q->t_den, c->counters, s));
+        }
+    } else {
+        PhaseTimer t(c, 1, s);
+        HIP_TRY(c, launch_node_stats(p->g, k, part, conn, p->wdeg, c->bucket, q->t_num, q->t_den,
+                                     c->counters, s));
+    }
+    if (moves) {
+        {
+            PhaseTimer t(c, 2, s);
+            HIP_TRY(c, launch_cb_prefix(k, c->bucket, s));
+            HIP_TRY(c, launch_best_move(p->g, k, part, conn, W, c->bucket, c->penq, lmax, q->mode,
+                                        p->low_t, p->hub_t, c->key, c->pen, c->cl_low, c->cl_mid,
+                                        c->counters, s));
+        }
+        {
+            PhaseTimer t(c, 3, s);
+            HIP_TRY(c, launch_filter(p->g, part, c->key, c->pen, c->cl_low, c->cl_mid, c->mv_low,
+                                     c->mv_mid, c->accflag, c->counters, s));
+            HIP_TRY(c, launch_filter_hub(p->g, part, c->key, c->pen, h, c->accflag, c->counters, s));
+        }
+        {
+            PhaseTimer t(c, 4, s);
+            HIP_TRY(c, launch_apply(p->g, k, part, conn, W, c->mv_low, c->mv_mid, h, c->counters, s));
+        }
+        {
+            PhaseTimer t(c, 6, s);
+            HIP_TRY(c, launch_cut_table(p->g, k, part, conn, p->wdeg, c->counters + CNT_CUT2_MOVES, s));
+        }
+    }
+    int64_t iters = 0, status = 0;
+    {
+        PhaseTimer t(c, 5, s);
+        const int64_t it_max = q->max_rebalance_iters > 0 ? q->max_rebalance_iters : default_iters(p, k);
+        rc = rebalance_loop(c, p, k, part, conn, W, lmax, it_max, &iters, &status, s);
+        if (rc) return rc;
+    }
+    {
+        PhaseTimer t(c, 6, s);
+        HIP_TRY(c, launch_cut_table(p->g, k, part, conn, p->wdeg, c->counters + CNT_CUT2_AFTER, s));
+    }
+    if (!moves) {
+        // standalone rebalancing: nothing moved before it
+        HIP_TRY(c, hipMemcpyAsync(c->counters + CNT_CUT2_MOVES, c->counters + CNT_CUT2_BEFORE,
+                                  sizeof(unsigned long long), hipMemcpyDeviceToDevice, s));
+    }
+    HIP_TRY(c, launch_stats_final(stats, c->counters, lmax, iters, status, s));
+    return UPR_OK;
+}
+
+int upr_refine_round(upr_ctx *c, const upr_plan *p, const upr_params *q, int32_t *part,
+                     int32_t *conn, int64_t *W, int64_t *stats, hipStream_t s)
+{
+    return round_common(c, p, q, part, conn, W, stats, s, true);
+}
+
+int upr_rebalance(upr_ctx *c, const upr_plan *p, const upr_params *q, int32_t *part, int32_t *conn,
+                  int64_t *W, int64_t *stats, hipStream_t s)
+{
+    return round_common(c, p, q, part, conn, W, stats, s, false);
+}
+
+int upr_last_moves(upr_ctx *c, int64_t n, int32_t *target, int64_t *score, int64_t *pen,
+                   uint8_t *accept, hipStream_t s)
+{
+    if (!c) return UPR_E_ARG;
+    if (n < 0 || n > c->cap_n) return fail(c, UPR_E_ARG, "n=%lld exceeds the last round's size", (long long)n);
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, launch_export_moves(n, c->key, c->pen, c->accflag, target, score, pen, accept, s));
+    return UPR_OK;
+}
+
+int upr_timing_enable(upr_ctx *c, int enable)
+{
+    if (!c) return UPR_E_ARG;
+    c->timing.on = enable != 0;
+    return UPR_OK;
+}
+
+int upr_timing_read(upr_ctx *c, double *ms, int64_t *counts, int reset)
+{
+    if (!c) return UPR_E_ARG;
+    for (auto &pd : c->timing.pending) {
+        float x = 0.f;
+        (void)hipEventSynchronize(pd.b);
+        if (hipEventElapsedTime(&x, pd.a, pd.b) == hipSuccess) {
+            c->timing.ms[pd.phase] += x;
+            c->timing.counts[pd.phase] += 1;
+        }
+        c->timing.pool.push_back(pd.a);
+        c->timing.pool.push_back(pd.b);
+    }
+    c->timing.pending.clear();
+    for (int i = 0; i < UPR_NUM_PHASES; ++i) {
+        if (ms) ms[i] = c->timing.ms[i];
+        if (counts) counts[i] = c->timing.counts[i];
+        if (reset) {
+            c->timing.ms[i] = 0;
+            c->timing.counts[i] = 0;
+        }
+    }
+    return UPR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,301 @@
+// Internal declarations of libupr: constants, device helpers and kernel
+// launchers shared by the HIP sources. Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace upr {
+
+constexpr int kSlots = 54;                  // penalty slots 0..53 (1.5^53 > 2^31)
+constexpr int kRbBuckets = 2 * kSlots + 1;  // rebalancing priority buckets
+constexpr int kBlock = 256;                 // threads per workgroup (4 wave64)
+constexpr int64_t kPenCap = int64_t(1) << 62;
+
+// Device counters (unsigned long long slots of ws.counters).
+enum Counter {
+    CNT_CL_LOW = 0,    // low-degree candidate list length
+    CNT_CL_MID,        // mid-degree candidate list length
+    CNT_MV_LOW,        // low-degree move list length
+    CNT_MV_MID,        // mid-degree move list length
+    CNT_CAND,          // candidates (all classes)
+    CNT_ACC,           // accepted moves
+    CNT_CUT2_BEFORE,   // 2 * cut before
+    CNT_CUT2_MOVES,    // 2 * cut after the filtered moves
+    CNT_CUT2_AFTER,    // 2 * cut after rebalancing
+    CNT_REBAL_MOVES,   // moves made by rebalancing
+    CNT_OLIST,         // nodes of overloaded blocks with a valid target
+    CNT_MOVED_NOW,     // moves of the current rebalancing sub-iteration
+    CNT_OVER,          // number of overloaded blocks
+    CNT_BAD_INPUT,     // nonzero: a part value was out of range
+    CNT_TMP,           // scratch accumulator for standalone calls
+    CNT_COUNT = 32
+};
+
+struct PenTable {
+    int64_t q[kSlots];
+};
+
+struct GraphView {
+    int64_t n;
+    const int64_t *xadj;
+    const int32_t *adjncy;
+    const int32_t *adjwgt;  // may be null: unit edge weights
+    const int32_t *vwgt;    // may be null: unit node weights
+};
+
+struct HubChunk {
+    int32_t hub;  // index into the sorted hub id list
+    int32_t pad;
+    int64_t e0, e1;
+};
+
+// Hub description handed to kernels.
+struct HubView {
+    int32_t nh;
+    const int32_t *ids;   // sorted node ids of hubs
+    const HubChunk *chunks;
+    int64_t nchunks;
+    int32_t *from;        // [nh] source block of a moving hub
+    int32_t *to;          // [nh] target block of a moving hub, -1 if not moving
+    int64_t *gacc;        // [nh] filter gain accumulator
+};
+
+struct Move {
+    int32_t v;
+    int32_t to;
+};
+
+// ---------------------------------------------------------------- device --
+
+__device__ __forceinline__ int64_t node_weight(const GraphView &g, int64_t v)
+{
+    return g.vwgt ? (int64_t)g.vwgt[v] : 1;
+}
+
+__device__ __forceinline__ int32_t edge_weight(const GraphView &g, int64_t e)
+{
+    return g.adjwgt ? g.adjwgt[e] : 1;
+}
+
+// 3^l for l < 54 as a 128-bit value.
+__device__ __forceinline__ unsigned __int128 pow3_u128(int l)
+{
+    unsigned __int128 r = 1, b = 3;
+    while (l) {
+        if (l & 1) r *= b;
+        b *= b;
+        l >>= 1;
+    }
+    return r;
+}
+
+// Least l in [0, 54) with w * 2^l <= c * 3^l (l = ceil(log_1.5(w / c)) for
+// w > c, 0 for w <= c), 53 if none. Binary search: the predicate is monotone
+// in l because 3^l / 2^l grows.
+__device__ __forceinline__ int slot_of(int64_t w, int64_t c)
+{
+    if (w <= c) return 0;
+    int lo = 1, hi = kSlots - 1;  // predicate false at 0, answer in [1, 53]
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (((unsigned __int128)(uint64_t)w << mid) <= (unsigned __int128)(uint64_t)c * pow3_u128(mid))
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// Rebalancing priority bucket (lower first): gain*c for gain >= 0 and gain/c
+// for gain < 0, higher priority first, bucketed by ceil(log_1.5).
+__device__ __forceinline__ int rebalance_bucket(int64_t gain, int64_t c)
+{
+    if (gain > 0) return kSlots - 1 - slot_of(gain * c, 1);
+    if (gain == 0) return kSlots;
+    return kSlots + 1 + slot_of(-gain, c);
+}
+
+__device__ __forceinline__ int64_t sat_mul_pen(int64_t q, int64_t c)
+{
+    if (q != 0 && c > kPenCap / q) return kPenCap;
+    int64_t p = q * c;
+    return p > kPenCap ? kPenCap : p;
+}
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Sum over an aligned group of G lanes (G a power of two <= 64).
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T x)
+{
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x)
+{
+    return group_sum<64, T>(x);
+}
+
+// Block-wide sum (blockDim.x == kBlock); result valid in every thread.
+template <typename T>
+__device__ __forceinline__ T block_sum(T x, T *lds /* >= 4 */)
+{
+    x = wave_sum(x);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane_id() == 0) lds[w] = x;
+    __syncthreads();
+    T s = lds[0] + lds[1] + lds[2] + lds[3];
+    __syncthreads();
+    return s;
+}
+
+// Inclusive scan over the wave.
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T x)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        T y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
+// Block-wide inclusive scan (blockDim.x == kBlock); returns the inclusive
+// prefix of the calling thread and the block total in *total.
+template <typename T>
+__device__ __forceinline__ T block_incl_scan(T x, T *lds /* >= 4 */, T *total)
+{
+    T inc = wave_incl_scan(x);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane_id() == 63) lds[w] = inc;
+    __syncthreads();
+    T base = 0;
+    for (int i = 0; i < w; ++i) base += lds[i];
+    *total = lds[0] + lds[1] + lds[2] + lds[3];
+    __syncthreads();
+    return base + inc;
+}
+
+// Wave-aggregated append: lanes with pred reserve consecutive slots of a
+// list whose length lives in *counter. Returns the slot (or -1).
+__device__ __forceinline__ int64_t wave_append(bool pred, unsigned long long *counter)
+{
+    const uint64_t mask = __ballot(pred);
+    if (mask == 0) return -1;
+    const int lane = lane_id();
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
+    base = __shfl(base, leader);
+    if (!pred) return -1;
+    const uint64_t below = lane == 0 ? 0 : (mask & ((~0ull) >> (64 - lane)));
+    return (int64_t)(base + __popcll(below));
+}
+
+__device__ __forceinline__ void atomic_add_i64(int64_t *p, int64_t v)
+{
+    atomicAdd((unsigned long long *)p, (unsigned long long)v);
+}
+
+// ------------------------------------------------------------ launchers --
+// Each returns hipGetLastError() after enqueueing on `s`.
+
+hipError_t launch_fill_i64(int64_t *p, int64_t count, int64_t value, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t s);
+
+// plan
+hipError_t launch_plan_scan(const GraphView &g, int32_t *wdeg, int64_t hub_t, int32_t *hub_list,
+                            unsigned long long *counters, hipStream_t s);
+// stage 0: xadj and node weights; 1: ids in range, edge weights; 2: also
+// self-loops, sorted rows, symmetry.
+hipError_t launch_validate(const GraphView &g, unsigned long long *flags, int stage,
+                           hipStream_t s);
+hipError_t launch_hub_ranges(const int64_t *xadj, const int32_t *ids, int32_t nh, int64_t *e01,
+                             hipStream_t s);
+
+// table (S1)
+int gain_tile_nodes(int32_t k);
+hipError_t launch_gain_tile(const GraphView &g, int32_t k, const int32_t *part, int32_t *conn,
+                            const int32_t *wdeg, int64_t hub_t, int64_t *W, int64_t *bucket,
+                            int32_t t_num, int32_t t_den, unsigned long long *counters,
+                            int with_stats, hipStream_t s);
+hipError_t launch_gain_hub(const GraphView &g, int32_t k, const int32_t *part, int32_t *conn,
+                           const HubView &h, hipStream_t s);
+hipError_t launch_hub_stats(const GraphView &g, int32_t k, const int32_t *part, const int32_t *conn,
+                            const int32_t *wdeg, const HubView &h, int64_t *bucket, int32_t t_num,
+                            int32_t t_den, unsigned long long *counters, hipStream_t s);
+hipError_t launch_block_weights(const GraphView &g, int32_t k, const int32_t *part, int64_t *W,
+                                unsigned long long *counters, hipStream_t s);
+hipError_t launch_cut_table(const GraphView &g, int32_t k, const int32_t *part, const int32_t *conn,
+                            const int32_t *wdeg, unsigned long long *acc, hipStream_t s);
+hipError_t launch_cut_edges(const GraphView &g, const int32_t *part, unsigned long long *acc,
+                            hipStream_t s);
+hipError_t launch_node_stats(const GraphView &g, int32_t k, const int32_t *part,
+                             const int32_t *conn, const int32_t *wdeg, int64_t *bucket,
+                             int32_t t_num, int32_t t_den, unsigned long long *counters,
+                             hipStream_t s);
+hipError_t launch_store_half(const unsigned long long *acc, int64_t *out, hipStream_t s);
+hipError_t launch_check_part(int64_t n, int32_t k, const int32_t *part,
+                             unsigned long long *counters, hipStream_t s);
+
+// moves (S0, S2-S4)
+hipError_t launch_round_init(int32_t k, int64_t *bucket, int64_t *W, const PenTable &pq,
+                             int64_t *penq, unsigned long long *counters, int zero_w, hipStream_t s);
+hipError_t launch_cb_prefix(int32_t k, int64_t *bucket, hipStream_t s);
+hipError_t launch_best_move(const GraphView &g, int32_t k, const int32_t *part, const int32_t *conn,
+                            const int64_t *W, const int64_t *cb, const int64_t *penq, int64_t lmax,
+                            int mode, int64_t low_t, int64_t hub_t, int64_t *key, int64_t *pen,
+                            int32_t *cl_low, int32_t *cl_mid, unsigned long long *counters,
+                            hipStream_t s);
+hipError_t launch_filter(const GraphView &g, const int32_t *part, const int64_t *key,
+                         const int64_t *pen, const int32_t *cl_low, const int32_t *cl_mid,
+                         Move *mv_low, Move *mv_mid, uint8_t *accflag,
+                         unsigned long long *counters, hipStream_t s);
+hipError_t launch_filter_hub(const GraphView &g, const int32_t *part, const int64_t *key,
+                             const int64_t *pen, const HubView &h, uint8_t *accflag,
+                             unsigned long long *counters, hipStream_t s);
+hipError_t launch_apply(const GraphView &g, int32_t k, int32_t *part, int32_t *conn, int64_t *W,
+                        const Move *mv_low, const Move *mv_mid, const HubView &h,
+                        unsigned long long *counters, hipStream_t s);
+hipError_t launch_stats_final(int64_t *stats, const unsigned long long *counters, int64_t lmax,
+                              int64_t iters, int64_t status, hipStream_t s);
+hipError_t launch_export_moves(int64_t n, const int64_t *key, const int64_t *pen,
+                               const uint8_t *accflag, int32_t *target, int64_t *score,
+                               int64_t *pen_out, uint8_t *accept, hipStream_t s);
+
+// rebalance (S5)
+struct RebalWs {
+    int32_t *rtgt;       // [n] target of a node of an overloaded block, -1 if none
+    uint8_t *rbeta;      // [n] its priority bucket
+    int32_t *olist;      // [n] nodes of overloaded blocks with a target
+    int64_t *W0;         // [k] block weights at sub-iteration start
+    int64_t *hist_src;   // [k * kRbBuckets]
+    int64_t *hist_tgt;   // [k * kRbBuckets]
+    int32_t *cbeta_src;  // [k] cutoff bucket per source block
+    int32_t *cbeta_tgt;  // [k] cutoff bucket per target block
+    int64_t *need_src;   // [k] weight still needed inside the cutoff bucket
+    int64_t *room_tgt;   // [k] capacity left inside the cutoff bucket
+    int32_t *theta_src;  // [k] id bound inside the cutoff bucket (exclusive)
+    int32_t *theta_tgt;  // [k]
+    int64_t *chunk_src;  // [k * nchunks]
+    int64_t *chunk_tgt;  // [k * nchunks]
+    int chunk_shift;
+    int64_t nchunks;
+};
+
+hipError_t launch_rb_begin(int32_t k, const int64_t *W, int64_t lmax, const RebalWs &r,
+                           unsigned long long *counters, hipStream_t s);
+hipError_t launch_rb_iteration(const GraphView &g, int32_t k, const int32_t *part,
+                               const int32_t *conn, int64_t lmax, int64_t hub_t, int64_t low_t,
+                               const RebalWs &r, const HubView &h, Move *mv_low, Move *mv_mid,
+                               unsigned long long *counters, hipStream_t s);
+
+}  // namespace upr

@@ -1,0 +1,294 @@
+"""Python binding of libupr (include/upr.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of libupr.so; this module passes
+device pointers of torch ROCm tensors and the current HIP stream through the
+C ABI. If the library is not built, loading fails with an error: there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libupr.so")
+
+UPR_OK = 0
+ERRORS = {-1: "UPR_E_ARG", -2: "UPR_E_GRAPH", -3: "UPR_E_INFEASIBLE", -4: "UPR_E_NOMEM",
+          -5: "UPR_E_HIP"}
+STATS_LEN = 12
+STAT_NAMES = ["l_max", "cut_before", "cut_after_moves", "cut_after", "candidates",
+              "accepted", "rebalance_moves", "rebalance_iters", "status"]
+PHASES = ["gain_tile", "gain_hub", "best_move", "filter", "apply", "rebalance", "cut", "call"]
+MODES = {"penalised": 0, "constrained": 1, "free": 2}
+
+
+class UprError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Graph(C.Structure):
+    _fields_ = [("n", C.c_int64), ("xadj", C.c_void_p), ("adjncy", C.c_void_p),
+                ("adjwgt", C.c_void_p), ("vwgt", C.c_void_p)]
+
+
+class Params(C.Structure):
+    """upr_params: k, eps, t, tau (rationals), mode, rebuild_table, max_rebalance_iters."""
+    _fields_ = [("k", C.c_int32), ("eps_num", C.c_int32), ("eps_den", C.c_int32),
+                ("t_num", C.c_int32), ("t_den", C.c_int32), ("tau_num", C.c_int32),
+                ("tau_den", C.c_int32), ("mode", C.c_int32), ("rebuild_table", C.c_int32),
+                ("max_rebalance_iters", C.c_int32)]
+
+
+def params(k, eps=(3, 100), t=(7, 10), tau=(1, 1), mode=0, rebuild_table=1,
+           max_rebalance_iters=0) -> Params:
+    if isinstance(mode, str):
+        mode = MODES[mode]
+    return Params(k, eps[0], eps[1], t[0], t[1], tau[0], tau[1], mode, rebuild_table,
+                  max_rebalance_iters)
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported function of include/upr.h
+_SIGS = [
+    ("upr_create", C.c_int, [C.POINTER(C.c_void_p), C.c_int]),
+    ("upr_destroy", None, [C.c_void_p]),
+    ("upr_last_error", C.c_char_p, [C.c_void_p]),
+    ("upr_plan_create", C.c_int, [C.c_void_p, C.POINTER(_Graph), C.POINTER(C.c_void_p), C.c_void_p]),
+    ("upr_plan_destroy", None, [C.c_void_p]),
+    ("upr_plan_info", C.c_int, [C.c_void_p] + [C.POINTER(C.c_int64)] * 5),
+    ("upr_validate_graph", C.c_int, [C.c_void_p, C.POINTER(_Graph), C.c_void_p]),
+    ("upr_gain_table", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                 C.c_void_p]),
+    ("upr_block_weights", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                    C.c_void_p]),
+    ("upr_edge_cut", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("upr_refine_round", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(Params), C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("upr_rebalance", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(Params), C.c_void_p,
+                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("upr_last_moves", C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_void_p]),
+    ("upr_lmax", C.c_int64, [C.c_int64, C.c_int32, C.c_int32, C.c_int32]),
+    ("upr_penalty_table", C.c_int, [C.c_int32, C.c_int32, C.c_void_p]),
+    ("upr_timing_enable", C.c_int, [C.c_void_p, C.c_int]),
+    ("upr_timing_read", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+]
+
+
+def lib():
+    """Load libupr.so (built by paper_2308_15494_amd.build); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                               "python -m paper_2308_15494_amd.build")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def lmax(total, k, eps=(3, 100)) -> int:
+    return int(lib().upr_lmax(total, k, eps[0], eps[1]))
+
+
+def penalty_table(tau) -> np.ndarray:
+    out = np.zeros(54, dtype=np.int64)
+    rc = lib().upr_penalty_table(tau[0], tau[1], out.ctypes.data)
+    if rc != UPR_OK:
+        raise UprError(rc, "bad tau")
+    return out
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """upr_ctx on one device; owns the device workspace."""
+
+    def __init__(self, device: int = 0):
+        self.handle = C.c_void_p()
+        rc = lib().upr_create(C.byref(self.handle), device)
+        if rc != UPR_OK:
+            raise UprError(rc, f"upr_create(device={device}) failed")
+        self.device = device
+
+    def check(self, rc):
+        if rc != UPR_OK:
+            raise UprError(rc, lib().upr_last_error(self.handle).decode())
+
+    def close(self):
+        if self.handle:
+            lib().upr_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def timing(self, enable: bool):
+        self.check(lib().upr_timing_enable(self.handle, int(enable)))
+
+    def timing_read(self, reset=True) -> dict:
+        ms = np.zeros(8, np.float64)
+        cnt = np.zeros(8, np.int64)
+        self.check(lib().upr_timing_read(self.handle, ms.ctypes.data, cnt.ctypes.data, int(reset)))
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(PHASES)}
+
+
+class DeviceGraph:
+    """A graphgen.Graph uploaded to device memory (torch tensors)."""
+
+    def __init__(self, g, device="cuda"):
+        import torch
+        self.n = int(g.n)
+        self.nnz = int(g.xadj[-1]) if g.n > 0 else 0
+        self.m = self.nnz // 2
+        self.xadj = torch.from_numpy(np.ascontiguousarray(g.xadj, np.int64)).to(device)
+        self.adjncy = torch.from_numpy(np.ascontiguousarray(g.adjncy, np.int32)).to(device)
+        self.adjwgt = None if g.adjwgt is None else torch.from_numpy(
+            np.ascontiguousarray(g.adjwgt, np.int32)).to(device)
+        self.vwgt = None if g.vwgt is None else torch.from_numpy(
+            np.ascontiguousarray(g.vwgt, np.int32)).to(device)
+        self.c = _Graph(self.n, self.xadj.data_ptr(), self.adjncy.data_ptr(),
+                        _ptr(self.adjwgt), _ptr(self.vwgt))
+
+
+class Plan:
+    """upr_plan: a prepared graph (degrees, hub chunks). Keeps the graph alive."""
+
+    def __init__(self, ctx: Context, dg: DeviceGraph, stream=None):
+        self.ctx = ctx
+        self.graph = dg
+        self.handle = C.c_void_p()
+        ctx.check(lib().upr_plan_create(ctx.handle, C.byref(dg.c), C.byref(self.handle),
+                                        _stream(stream)))
+
+    def info(self) -> dict:
+        vals = [C.c_int64() for _ in range(5)]
+        self.ctx.check(lib().upr_plan_info(self.handle, *[C.byref(v) for v in vals]))
+        return dict(zip(["n", "nnz", "total_weight", "max_degree", "num_hubs"],
+                        [v.value for v in vals]))
+
+    def close(self):
+        if self.handle:
+            lib().upr_plan_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def validate_graph(ctx: Context, dg: DeviceGraph, stream=None):
+    ctx.check(lib().upr_validate_graph(ctx.handle, C.byref(dg.c), _stream(stream)))
+
+
+def gain_table(ctx, plan, k, part, conn=None, stream=None):
+    import torch
+    if conn is None:
+        conn = torch.empty(plan.graph.n * k, dtype=torch.int32, device=part.device)
+    ctx.check(lib().upr_gain_table(ctx.handle, plan.handle, k, _ptr(part), _ptr(conn),
+                                   _stream(stream)))
+    return conn
+
+
+def block_weights(ctx, plan, k, part, W=None, stream=None):
+    import torch
+    if W is None:
+        W = torch.empty(k, dtype=torch.int64, device=part.device)
+    ctx.check(lib().upr_block_weights(ctx.handle, plan.handle, k, _ptr(part), _ptr(W),
+                                      _stream(stream)))
+    return W
+
+
+def edge_cut(ctx, plan, part, out=None, stream=None):
+    import torch
+    if out is None:
+        out = torch.empty(1, dtype=torch.int64, device=part.device)
+    ctx.check(lib().upr_edge_cut(ctx.handle, plan.handle, _ptr(part), _ptr(out), _stream(stream)))
+    return out
+
+
+def refine_round(ctx, plan, p: Params, part, conn, W, stats=None, stream=None):
+    """One round in place on (part, conn, W); returns the device stats tensor."""
+    import torch
+    if stats is None:
+        stats = torch.empty(STATS_LEN, dtype=torch.int64, device=part.device)
+    ctx.check(lib().upr_refine_round(ctx.handle, plan.handle, C.byref(p), _ptr(part), _ptr(conn),
+                                     _ptr(W), _ptr(stats), _stream(stream)))
+    return stats
+
+
+def rebalance(ctx, plan, p: Params, part, conn, W, stats=None, stream=None):
+    import torch
+    if stats is None:
+        stats = torch.empty(STATS_LEN, dtype=torch.int64, device=part.device)
+    ctx.check(lib().upr_rebalance(ctx.handle, plan.handle, C.byref(p), _ptr(part), _ptr(conn),
+                                  _ptr(W), _ptr(stats), _stream(stream)))
+    return stats
+
+
+def last_moves(ctx, n, device="cuda", stream=None) -> dict:
+    import torch
+    out = dict(target=torch.empty(n, dtype=torch.int32, device=device),
+               score=torch.empty(n, dtype=torch.int64, device=device),
+               pen=torch.empty(n, dtype=torch.int64, device=device),
+               accept=torch.empty(n, dtype=torch.uint8, device=device))
+    ctx.check(lib().upr_last_moves(ctx.handle, n, _ptr(out["target"]), _ptr(out["score"]),
+                                   _ptr(out["pen"]), _ptr(out["accept"]), _stream(stream)))
+    return out
+
+
+def stats_dict(stats) -> dict:
+    s = stats.cpu().numpy() if hasattr(stats, "cpu") else np.asarray(stats)
+    return {name: int(s[i]) for i, name in enumerate(STAT_NAMES)}
+
+
+class Refiner:
+    """Convenience holder: graph on device, plan, and (part, conn, W) state."""
+
+    def __init__(self, g, k, device=0, ctx=None):
+        import torch
+        self.ctx = ctx or Context(device)
+        self.dev = torch.device("cuda", device)
+        self.dg = DeviceGraph(g, self.dev)
+        self.plan = Plan(self.ctx, self.dg)
+        self.k = k
+        self.conn = torch.zeros(max(self.dg.n * k, 1), dtype=torch.int32, device=self.dev)
+        self.W = torch.zeros(k, dtype=torch.int64, device=self.dev)
+        self.stats = torch.zeros(STATS_LEN, dtype=torch.int64, device=self.dev)
+        self.part = None
+
+    def set_partition(self, part):
+        import torch
+        self.part = torch.from_numpy(np.ascontiguousarray(part, np.int32)).to(self.dev)
+
+    def round(self, p: Params):
+        refine_round(self.ctx, self.plan, p, self.part, self.conn, self.W, self.stats)
+        return self.stats
+
+    def rebalance(self, p: Params):
+        rebalance(self.ctx, self.plan, p, self.part, self.conn, self.W, self.stats)
+        return self.stats

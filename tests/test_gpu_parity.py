@@ -1,0 +1,377 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, element
+by element on the same seeded inputs. Everything is integer arithmetic, so
+the bar is bit-exact: gain table, block weights, partition, cut and
+statistics after every round, and the per-node move decisions."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2308_15494_amd import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def upr():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2308_15494_amd import upr as U
+    U.lib()
+    return U
+
+
+@pytest.fixture(scope="module")
+def ctx(upr):
+    c = upr.Context(0)
+    yield c
+    c.close()
+
+
+def skewed_partition(n, k, seed, heavy=0.5):
+    rng = np.random.default_rng(seed)
+    p = np.full(k, (1 - heavy) / (k - 1))
+    p[0] = heavy
+    return rng.choice(k, size=n, p=p).astype(np.int32)
+
+
+def to_dev(a, torch_dtype=None):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+class Pair:
+    """The same round state on the GPU and in the oracle."""
+
+    def __init__(self, upr, ctx, g, k, part0):
+        import torch
+        self.upr, self.ctx, self.g, self.k = upr, ctx, g, k
+        self.dg = upr.DeviceGraph(g)
+        self.plan = upr.Plan(ctx, self.dg)
+        self.part = to_dev(part0.astype(np.int32))
+        self.conn = torch.zeros(max(g.n * k, 1), dtype=torch.int32, device="cuda")
+        self.W = torch.zeros(k, dtype=torch.int64, device="cuda")
+        self.stats = torch.zeros(12, dtype=torch.int64, device="cuda")
+        self.G = O.Graph(g)
+        self.opart = part0.astype(np.int32).copy()
+        self.oconn = np.zeros(max(g.n * k, 1), np.int32)
+        self.oW = np.zeros(k, np.int64)
+
+    def round(self, **kw):
+        p = self.upr.params(self.k, **kw)
+        self.upr.refine_round(self.ctx, self.plan, p, self.part, self.conn, self.W, self.stats)
+        ost, odbg = O.refine_round(self.G, O.params(self.k, **kw), self.opart, self.oconn, self.oW,
+                                   debug=True)
+        return ost, odbg
+
+    def rebalance(self, **kw):
+        p = self.upr.params(self.k, **kw)
+        self.upr.rebalance(self.ctx, self.plan, p, self.part, self.conn, self.W, self.stats)
+        return O.rebalance(self.G, O.params(self.k, **kw), self.opart, self.oconn, self.oW)
+
+    def compare(self, ost, odbg=None, what=""):
+        import torch
+        torch.cuda.synchronize()
+        st = self.stats.cpu().numpy()
+        assert O.stats_dict(st) == O.stats_dict(ost), f"{what}: stats differ"
+        assert np.array_equal(self.part.cpu().numpy(), self.opart), f"{what}: part differs"
+        assert np.array_equal(self.W.cpu().numpy(), self.oW), f"{what}: block weights differ"
+        if self.g.n:
+            assert np.array_equal(self.conn.cpu().numpy()[: self.g.n * self.k],
+                                  self.oconn[: self.g.n * self.k]), f"{what}: gain table differs"
+        if odbg is not None and self.g.n:
+            mv = self.upr.last_moves(self.ctx, self.g.n)
+            torch.cuda.synchronize()
+            assert np.array_equal(mv["target"].cpu().numpy(), odbg["target"]), f"{what}: targets"
+            assert np.array_equal(mv["score"].cpu().numpy(), odbg["score"]), f"{what}: scores"
+            assert np.array_equal(mv["pen"].cpu().numpy(), odbg["pen"]), f"{what}: penalties"
+            assert np.array_equal(mv["accept"].cpu().numpy(), odbg["accept"]), f"{what}: accept"
+
+
+# ------------------------------------------------------------ S1 / cut --
+
+@pytest.mark.parametrize("case", [
+    ("er", lambda: gg.random_small(300, 0.05, seed=1), 2),
+    ("er_w", lambda: gg.random_small(400, 0.04, seed=2, wmax=9, vmax=5), 5),
+    ("cl", lambda: gg.chung_lu(5000, 10.0, 2.3, seed=3), 8),
+    ("cl_w", lambda: gg.chung_lu(3000, 12.0, 2.1, seed=4, wmax=16), 64),
+    ("grid", lambda: gg.grid2d(61, 77), 64),
+    ("rmat", lambda: gg.rmat(13, 16, seed=5), 256),
+    ("bigk", lambda: gg.chung_lu(700, 6.0, 2.5, seed=6), 3000),
+    ("kmax", lambda: gg.random_small(40, 0.2, seed=7), 8192),
+])
+def test_gain_table_and_cut(upr, ctx, case):
+    import torch
+    name, make, k = case
+    g = make()
+    say(f"gain table case={name} n={g.n} nnz={g.nnz} k={k}")
+    part = gg.random_partition(g.n, k, 3)
+    dg = upr.DeviceGraph(g)
+    plan = upr.Plan(ctx, dg)
+    dpart = to_dev(part)
+    conn = upr.gain_table(ctx, plan, k, dpart)
+    W = upr.block_weights(ctx, plan, k, dpart)
+    cut = upr.edge_cut(ctx, plan, dpart)
+    torch.cuda.synchronize()
+    assert np.array_equal(conn.cpu().numpy().reshape(g.n, k), O.gain_table(g, k, part))
+    assert np.array_equal(W.cpu().numpy(), O.block_weights(g, k, part))
+    assert int(cut.item()) == O.cut_edges(g, part)
+
+
+def test_hub_paths(upr, ctx, monkeypatch):
+    """Force a low hub threshold so the multi-workgroup hub kernels carry
+    real rows (and chunks span several workgroups)."""
+    import torch
+    monkeypatch.setenv("UPR_HUB_THRESHOLD", "40")
+    monkeypatch.setenv("UPR_LOW_THRESHOLD", "6")
+    for seed in range(3):
+        g = gg.with_weights(gg.chung_lu(6000, 12.0, 2.05, seed=seed, d_max=5000), seed, wmax=7,
+                            vmax=3 if seed == 2 else 0)
+        k = [8, 64, 5][seed]
+        say(f"hub case seed={seed} n={g.n} max_deg={g.meta['max_degree']} k={k}")
+        part = gg.random_partition(g.n, k, seed)
+        pr = Pair(upr, ctx, g, k, part)
+        assert pr.plan.info()["num_hubs"] > 0
+        for r in range(1, 5):
+            ost, odbg = pr.round(tau=gg.tau_schedule(r, 4))
+            pr.compare(ost, odbg, f"seed {seed} round {r}")
+
+
+# ------------------------------------------------------------ rounds --
+
+SMALL = [
+    ("er", lambda s: gg.random_small(60, 0.08, seed=s), 3),
+    ("er_w", lambda s: gg.random_small(80, 0.07, seed=s, wmax=6, vmax=4), 4),
+    ("cl", lambda s: gg.chung_lu(1500, 6.0, 2.3, seed=s), 8),
+    ("cl_w", lambda s: gg.with_weights(gg.chung_lu(2500, 8.0, 2.2, seed=s), s, wmax=9, vmax=3), 16),
+    ("grid", lambda s: gg.grid2d(40, 50), 64),
+    ("rgg", lambda s: gg.rgg2d(3000, seed=s), 32),
+    ("rmat", lambda s: gg.rmat(11, 16, seed=s), 64),
+]
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[c[0] for c in SMALL])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_round_parity_small(upr, ctx, case, mode):
+    name, make, k = case
+    for seed in range(2):
+        g = make(seed + 1)
+        for pname, part0 in [("random", gg.random_partition(g.n, k, seed)),
+                             ("skewed", skewed_partition(g.n, k, seed, 0.4))]:
+            say(f"round parity case={name} mode={mode} seed={seed} start={pname} n={g.n} k={k}")
+            pr = Pair(upr, ctx, g, k, part0)
+            for r in range(1, 5):
+                ost, odbg = pr.round(tau=gg.tau_schedule(r, 4), mode=mode)
+                pr.compare(ost, odbg, f"{name} mode {mode} seed {seed} {pname} round {r}")
+
+
+@pytest.mark.parametrize("t", [(7, 10), (2, 5), (0, 1), (1, 1)])
+def test_round_parity_threshold(upr, ctx, t):
+    g = gg.chung_lu(4000, 8.0, 2.2, seed=9)
+    k = 16
+    pr = Pair(upr, ctx, g, k, skewed_partition(g.n, k, 1, 0.3))
+    say(f"threshold t={t}")
+    for r in range(1, 4):
+        ost, odbg = pr.round(t=t, tau=(1, 1))
+        pr.compare(ost, odbg, f"t {t} round {r}")
+
+
+def test_round_parity_chunglu10k(upr, ctx):
+    """The 10k-node Chung-Lu workload: 10 rounds with tau (8+r)/18 and a
+    final rebalance, bit-exact after every round."""
+    g, k, eps, rounds, seed = gg.workload("chunglu10k")
+    pr = Pair(upr, ctx, g, k, gg.random_partition(g.n, k, seed))
+    for r in range(1, rounds + 1):
+        say(f"chunglu10k round {r}")
+        ost, odbg = pr.round(eps=eps, tau=gg.tau_schedule(r, rounds))
+        pr.compare(ost, odbg, f"round {r}")
+    ost = pr.rebalance(eps=eps)
+    pr.compare(ost, None, "final rebalance")
+
+
+def test_resident_equals_rebuild(upr, ctx):
+    g = gg.with_weights(gg.chung_lu(5000, 8.0, 2.3, seed=12), 3, wmax=5, vmax=2)
+    k = 12
+    part0 = gg.random_partition(g.n, k, 4)
+    a = Pair(upr, ctx, g, k, part0)
+    b = Pair(upr, ctx, g, k, part0)
+    for r in range(1, 6):
+        say(f"resident round {r}")
+        tau = gg.tau_schedule(r, 5)
+        ost, odbg = a.round(tau=tau, rebuild_table=1)
+        a.compare(ost, odbg, f"rebuild round {r}")
+        ost, odbg = b.round(tau=tau, rebuild_table=0 if r > 1 else 1)
+        b.compare(ost, odbg, f"resident round {r}")
+
+
+def test_rebalance_parity(upr, ctx):
+    for seed in range(4):
+        g = gg.with_weights(gg.chung_lu(3000, 6.0, 2.4, seed=seed), seed,
+                            wmax=4 if seed % 2 else 0, vmax=5 if seed >= 2 else 0)
+        k = [2, 7, 16, 64][seed]
+        say(f"rebalance seed={seed} k={k}")
+        pr = Pair(upr, ctx, g, k, skewed_partition(g.n, k, seed, 0.6))
+        ost = pr.rebalance()
+        pr.compare(ost, None, f"rebalance seed {seed}")
+        ost = pr.rebalance(max_rebalance_iters=1)
+        pr.compare(ost, None, f"rebalance again seed {seed}")
+
+
+def test_rebalance_iteration_cap_and_stuck(upr, ctx):
+    g = gg.chung_lu(2000, 5.0, 2.3, seed=4)
+    k = 6
+    part0 = skewed_partition(g.n, k, 4, heavy=0.7)
+    pr = Pair(upr, ctx, g, k, part0)
+    ost = pr.rebalance(max_rebalance_iters=1)
+    pr.compare(ost, None, "cap 1")
+    # stuck: two heavy nodes that fit nowhere
+    from tests import bruteforce as bf
+    g2 = bf.graph_from_edges(5, [[0, 1], [1, 2], [2, 3], [3, 4]], vwgt=[4, 4, 1, 1, 1])
+    pr2 = Pair(upr, ctx, g2, 2, np.array([0, 0, 1, 1, 1], np.int32))
+    ost = pr2.rebalance(eps=(1, 10))
+    pr2.compare(ost, None, "stuck")
+    assert ost[8] == 1
+
+
+def test_determinism_across_streams(upr, ctx):
+    import torch
+    g = gg.rmat(12, 16, seed=21)
+    k = 32
+    outs = []
+    for i in range(3):
+        s = torch.cuda.Stream() if i else torch.cuda.current_stream()
+        with torch.cuda.stream(s):
+            r = upr.Refiner(g, k, ctx=ctx)
+            r.set_partition(gg.random_partition(g.n, k, 1))
+            for rr in range(1, 4):
+                r.round(upr.params(k, tau=gg.tau_schedule(rr, 3)))
+            s.synchronize()
+            outs.append((r.part.cpu().numpy(), r.stats.cpu().numpy(), r.conn.cpu().numpy()))
+    for o in outs[1:]:
+        for x, y in zip(outs[0], o):
+            assert np.array_equal(x, y)
+
+
+# ------------------------------------------------------------ edge cases --
+
+def test_edge_cases(upr, ctx):
+    from tests import bruteforce as bf
+    cases = [
+        ("no edges", gg.Graph(50, np.zeros(51, np.int64), np.zeros(0, np.int32)), 4),
+        ("single node", gg.Graph(1, np.zeros(2, np.int64), np.zeros(0, np.int32)), 2),
+        ("one edge", bf.graph_from_edges(2, [[0, 1]]), 2),
+        ("k>n", gg.random_small(10, 0.4, seed=3), 17),
+        ("golden escape", bf.graph_from_edges(10, bf.load_golden("full_block_escape.json")["edges"]), 2),
+    ]
+    for name, g, k in cases:
+        say(f"edge case {name}")
+        for part0 in [gg.random_partition(g.n, k, 1), np.zeros(g.n, np.int32)]:
+            pr = Pair(upr, ctx, g, k, part0)
+            for r in range(1, 3):
+                ost, odbg = pr.round(tau=(1, r))
+                pr.compare(ost, odbg, f"{name} round {r}")
+
+
+def test_golden_fixtures_on_gpu(upr, ctx):
+    from tests import bruteforce as bf
+    for fname in ["full_block_escape.json", "filter_conflict.json"]:
+        fx = bf.load_golden(fname)
+        g = bf.graph_from_edges(fx["n"], fx["edges"])
+        for case in fx["cases"]:
+            say(f"golden {fname} mode={case['mode']} tau={case['tau']}")
+            pr = Pair(upr, ctx, g, fx["k"], np.array(fx["part_in"], np.int32))
+            ost, odbg = pr.round(eps=tuple(fx["eps"]), t=tuple(fx["t"]), tau=tuple(case["tau"]),
+                                 mode=case["mode"])
+            pr.compare(ost, odbg, fname)
+            assert upr.stats_dict(pr.stats) == case["stats"]
+            assert pr.part.cpu().numpy().tolist() == case["part_out"]
+
+
+def test_empty_graph(upr, ctx):
+    import torch
+    g = gg.Graph(0, np.zeros(1, np.int64), np.zeros(0, np.int32))
+    dg = upr.DeviceGraph(g)
+    plan = upr.Plan(ctx, dg)
+    part = torch.zeros(0, dtype=torch.int32, device="cuda")
+    conn = torch.zeros(0, dtype=torch.int32, device="cuda")
+    W = torch.zeros(4, dtype=torch.int64, device="cuda")
+    st = upr.refine_round(ctx, plan, upr.params(4), part, conn, W)
+    torch.cuda.synchronize()
+    assert upr.stats_dict(st) == {"l_max": 0, "cut_before": 0, "cut_after_moves": 0,
+                                  "cut_after": 0, "candidates": 0, "accepted": 0,
+                                  "rebalance_moves": 0, "rebalance_iters": 0, "status": 0}
+
+
+def test_errors(upr, ctx):
+    import torch
+    g = gg.random_small(30, 0.2, seed=1)
+    dg = upr.DeviceGraph(g)
+    plan = upr.Plan(ctx, dg)
+    k = 4
+    conn = torch.zeros(g.n * k, dtype=torch.int32, device="cuda")
+    W = torch.zeros(k, dtype=torch.int64, device="cuda")
+    good = to_dev(gg.random_partition(g.n, k, 1))
+    for bad in [dict(k=1), dict(k=8193), dict(k=4, eps=(0, 1)), dict(k=4, tau=(3, 2)), dict(k=4, t=(2, 1)),
+                dict(k=4, mode=7)]:
+        kk = bad.pop("k")
+        with pytest.raises(upr.UprError) as ei:
+            upr.refine_round(ctx, plan, upr.params(kk, **bad), good, conn, W)
+        assert ei.value.code == -1
+    badpart = good.clone()
+    badpart[3] = 9
+    with pytest.raises(upr.UprError) as ei:
+        upr.refine_round(ctx, plan, upr.params(k), badpart, conn, W)
+    assert ei.value.code == -1
+    with pytest.raises(upr.UprError) as ei:
+        upr.gain_table(ctx, plan, k, badpart, conn)
+    assert ei.value.code == -1
+    # infeasible: a node heavier than L_max
+    gw = gg.Graph(g.n, g.xadj, g.adjncy, None, np.full(g.n, 1, np.int32))
+    gw.vwgt[0] = 1000
+    planw = upr.Plan(ctx, upr.DeviceGraph(gw))
+    with pytest.raises(upr.UprError) as ei:
+        upr.refine_round(ctx, planw, upr.params(k), good, conn, W)
+    assert ei.value.code == -3
+    # malformed graph: neighbour id out of range is caught at plan creation
+    adj = g.adjncy.copy()
+    adj[5] = g.n + 3
+    with pytest.raises(upr.UprError) as ei:
+        upr.Plan(ctx, upr.DeviceGraph(gg.Graph(g.n, g.xadj, adj)))
+    assert ei.value.code == -2
+    # asymmetric structure is caught by validation
+    adj = g.adjncy.copy()
+    row = int(np.argmax(np.diff(g.xadj) >= 2))
+    e = int(g.xadj[row])
+    cand = [u for u in range(g.n) if u != row and u not in set(adj[g.xadj[row]:g.xadj[row + 1]].tolist())]
+    adj[e] = min(cand)
+    adj[g.xadj[row]:g.xadj[row + 1]].sort()
+    with pytest.raises(upr.UprError) as ei:
+        upr.validate_graph(ctx, upr.DeviceGraph(gg.Graph(g.n, g.xadj, adj)))
+    assert ei.value.code == -2
+    upr.validate_graph(ctx, dg)  # the generator's graph is valid
+    # the context still works after errors
+    pr = Pair(upr, ctx, g, k, gg.random_partition(g.n, k, 1))
+    ost, odbg = pr.round()
+    pr.compare(ost, odbg, "after errors")
+
+
+# ------------------------------------------------------------ full size --
+
+def test_rmat20_full_rounds(upr, ctx):
+    """R-MAT scale 20, k = 64: the benchmarked workload, bit-exact after every
+    round (first 6 of its 20 rounds; each oracle round is ~1 s on one core)."""
+    g, k, eps, rounds, seed = gg.workload("rmat20")
+    say(f"rmat20 n={g.n} m={g.m}")
+    pr = Pair(upr, ctx, g, k, gg.random_partition(g.n, k, seed))
+    for r in range(1, 7):
+        say(f"rmat20 round {r}")
+        ost, odbg = pr.round(eps=eps, tau=gg.tau_schedule(r, rounds))
+        pr.compare(ost, odbg, f"rmat20 round {r}")
