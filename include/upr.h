@@ -56,7 +56,7 @@ typedef struct {
     int64_t n;               /* number of nodes, 0 <= n < 2^31 */
     const int64_t *xadj;     /* device [n+1]; xadj[0] = 0, nondecreasing; nnz = xadj[n] */
     const int32_t *adjncy;   /* device [nnz]; row v lists N(v); symmetric, no self-loops,
-                                no duplicates */
+                                no duplicates; may be NULL when nnz = 0 */
     const int32_t *adjwgt;   /* device [nnz], omega of each directed entry, > 0 and symmetric;
                                 NULL means every edge weight is 1 */
     const int32_t *vwgt;     /* device [n], c(v) > 0; NULL means every node weight is 1 */

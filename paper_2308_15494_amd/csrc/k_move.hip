@@ -1,15 +1,18 @@
-// Move phase of one round: penalty buckets to prefix sums, penalised best
-// move, conflict filter and scatter-apply.
+// Move phase of one round: penalty prefix sums, penalised best move,
+// conflict filter and scatter-apply.
 //
-// Degree classes: low-degree nodes are handled by groups of 8 lanes,
-// mid-degree nodes by a whole wave64, hubs by several workgroups over chunks
-// of their edges (the chunk list is built once per graph).
+// Every per-node kernel scans node ids in wave-sized runs of 64 (coalesced
+// reads of the per-node arrays). Nodes that need work are compacted inside
+// the wave (ballot, then each lane group picks the n-th set bit) and handled
+// by lane groups sized to their degree class: 8 lanes for low-degree nodes,
+// the whole wave for mid-degree nodes; hubs are split into edge chunks
+// processed by whole workgroups. Counters are summed per workgroup in LDS and
+// added to global memory once per workgroup.
 #include "upr_common.h"
 
 namespace upr {
 
 constexpr int kLowLanes = 8;
-constexpr int kMidLanes = 64;
 
 static int grid_cap(int64_t items, int per_block, int cap)
 {
@@ -43,27 +46,6 @@ hipError_t launch_round_init(int32_t k, int64_t *bucket, int64_t *W, const PenTa
     return hipGetLastError();
 }
 
-// Prefix sums over slots: cb[j][l] = sum_{i <= l} c(B_{i,j}).
-__global__ void k_cb_prefix(int32_t k, int64_t *bucket)
-{
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= k) return;
-    int64_t *b = bucket + (int64_t)j * kSlots;
-    int64_t run = 0;
-    for (int l = 0; l < kSlots; ++l) {
-        run += b[l];
-        b[l] = run;
-    }
-}
-
-hipError_t launch_cb_prefix(int32_t k, int64_t *bucket, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_cb_prefix, dim3((k + kBlock - 1) / kBlock), dim3(kBlock), 0, s, k, bucket);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------------- best move --
-
 // Least l with cb[l] >= x (cb nondecreasing), kSlots if none.
 __device__ __forceinline__ int covering_slot(const int64_t *cb, int64_t x)
 {
@@ -77,52 +59,117 @@ __device__ __forceinline__ int covering_slot(const int64_t *cb, int64_t x)
     return lo;
 }
 
+// Per block j: prefix sums over slots, cb[j][l] = sum_{i <= l} c(B_{i,j}), and
+// the penalty a node of weight 1 pays to enter j: 0 if W[j] + 1 <= L_max;
+// otherwise constrained: -1 (forbidden); penalty-free: 0; penalised:
+// penq[l] for the least covering slot l, -1 if none.
+__global__ void k_cb_prefix(int32_t k, int64_t *bucket, const int64_t *W, int64_t lmax,
+                            const int64_t *penq, int mode, int64_t *pen1)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= k) return;
+    int64_t *b = bucket + (int64_t)j * kSlots;
+    int64_t run = 0;
+    for (int l = 0; l < kSlots; ++l) {
+        run += b[l];
+        b[l] = run;
+    }
+    const int64_t x = W[j] + 1 - lmax;
+    int64_t p = 0;
+    if (x > 0) {
+        if (mode == 1) p = -1;
+        else if (mode == 0) {
+            const int l = covering_slot(b, x);
+            p = l >= kSlots ? -1 : penq[l];
+        }
+    }
+    pen1[j] = p;
+}
+
+hipError_t launch_cb_prefix(int32_t k, int64_t *bucket, const int64_t *W, int64_t lmax,
+                            const int64_t *penq, int mode, int64_t *pen1, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cb_prefix, dim3((k + kBlock - 1) / kBlock), dim3(kBlock), 0, s, k, bucket,
+                       W, lmax, penq, mode, pen1);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- best move --
+
 // S2: per node v in block a, over blocks j != a with omega(v, V_j) >
-// omega(v, V_a) (only those can give a positive score):
+// omega(v, V_a) (only those can score above 0):
 //   X = W[j] + c(v) - L_max; P = 0 if X <= 0; constrained: skip if X > 0;
 //   penalised: l = least slot with cb[j][l] >= X (skip if none),
 //   P = min(penq[l] * c(v), 2^62); score = delta * 2^16 - P.
-// The best score (ties to the smaller j) is reduced over a group of G lanes
-// as the packed value (score << 16 | (0xFFFF - j)). key[v] = score << 16 | j
-// for candidates (score > 0), -1 otherwise.
-template <int G>
+// G lanes per node, each reading V consecutive ints of the row per step. The
+// best score (ties to the smaller j) is reduced as (score << 16 | 0xFFFF - j).
+// key[v] = score << 16 | j for candidates (score > 0), -1 otherwise.
+template <int G, int V>
 __global__ __launch_bounds__(kBlock) void k_best_move(
     GraphView g, int32_t k, const int32_t *__restrict__ part, const int32_t *__restrict__ conn,
     const int64_t *__restrict__ W, const int64_t *__restrict__ cb, const int64_t *__restrict__ penq,
-    int64_t lmax, int mode, int64_t low_t, int64_t hub_t, int64_t *__restrict__ key,
-    int64_t *__restrict__ pen, int32_t *cl_low, int32_t *cl_mid, unsigned long long *counters)
+    const int64_t *__restrict__ pen1, int64_t lmax, int mode, int64_t *__restrict__ key,
+    int64_t *__restrict__ pen, unsigned long long *counters)
 {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    int64_t *sW = (int64_t *)lds_raw;
+    int64_t *sP = sW + k;
+    __shared__ unsigned long long cand_lds;
+    const bool use_lds = k <= 2048;
+    const bool unit = g.vwgt == nullptr;
+    if (threadIdx.x == 0) cand_lds = 0;
+    if (use_lds)
+        for (int j = threadIdx.x; j < k; j += kBlock) {
+            sW[j] = W[j];
+            sP[j] = pen1[j];
+        }
+    __syncthreads();
+    const int64_t *Wr = use_lds ? sW : W;
+    const int64_t *Pr = use_lds ? sP : pen1;
+
     constexpr int GPB = kBlock / G;
     const int gl = threadIdx.x & (G - 1);
+    const int nvec = k / V;  // row length in vectors (V divides k)
     const int64_t stride = (int64_t)gridDim.x * GPB;
     const int64_t first = (int64_t)blockIdx.x * GPB + threadIdx.x / G;
-    // all groups of a wave iterate the same number of times (wave-uniform
-    // bound), so the wave-level append below sees every lane
-    const int64_t wave_first = (int64_t)blockIdx.x * GPB + (threadIdx.x & ~63) / G;
-    for (int64_t vb = wave_first; vb < g.n; vb += stride) {
-        const int64_t v = vb + (first - wave_first);
-        const bool valid = v < g.n;
+    for (int64_t v = first; v < g.n; v += stride) {
         int64_t best = 0, bestP = 0;
-        int32_t a = 0;
-        int64_t cv = 1;
-        if (valid) {
-            a = part[v];
-            cv = node_weight(g, v);
-            if ((unsigned)a < (unsigned)k) {
-                const int32_t *row = conn + v * (int64_t)k;
-                const int32_t ca = row[a];
-                for (int j = gl; j < k; j += G) {
-                    const int32_t cj = row[j];
+        const int32_t a = part[v];
+        const int64_t cv = node_weight(g, v);
+        if ((unsigned)a < (unsigned)k) {
+            const int32_t *row = conn + v * (int64_t)k;
+            const int32_t ca = row[a];
+            for (int q = gl; q < nvec; q += G) {
+                int32_t c4[V];
+                if constexpr (V == 4) {
+                    const int4 x = ((const int4 *)row)[q];
+                    c4[0] = x.x;
+                    c4[1] = x.y;
+                    c4[2] = x.z;
+                    c4[3] = x.w;
+                } else {
+                    c4[0] = row[q];
+                }
+#pragma unroll
+                for (int t = 0; t < V; ++t) {
+                    const int32_t cj = c4[t];
+                    const int j = q * V + t;
                     if (cj <= ca || j == a) continue;
                     const int64_t delta = (int64_t)cj - ca;
-                    const int64_t x = W[j] + cv - lmax;
-                    int64_t P = 0;
-                    if (x > 0) {
-                        if (mode == 1) continue;
-                        if (mode == 0) {
-                            const int l = covering_slot(cb + (int64_t)j * kSlots, x);
-                            if (l >= kSlots) continue;
-                            P = sat_mul_pen(penq[l], cv);
+                    int64_t P;
+                    if (unit) {
+                        P = Pr[j];
+                        if (P < 0) continue;
+                    } else {
+                        P = 0;
+                        const int64_t x = Wr[j] + cv - lmax;
+                        if (x > 0) {
+                            if (mode == 1) continue;
+                            if (mode == 0) {
+                                const int l = covering_slot(cb + (int64_t)j * kSlots, x);
+                                if (l >= kSlots) continue;
+                                P = sat_mul_pen(penq[l], cv);
+                            }
                         }
                     }
                     const int64_t sc = delta * 65536 - P;
@@ -144,47 +191,50 @@ __global__ __launch_bounds__(kBlock) void k_best_move(
                 bestP = op;
             }
         }
-        const bool leader = valid && gl == 0;
-        const bool cand = leader && best > 0;
-        int64_t deg = 0;
-        if (leader) {
-            if (cand) {
+        if (gl == 0) {
+            if (best > 0) {
                 const int64_t sc = best >> 16;
                 const int32_t j = 0xFFFF - (int32_t)(best & 0xFFFF);
                 key[v] = (sc << 16) | j;
                 pen[v] = bestP;
-                deg = g.xadj[v + 1] - g.xadj[v];
+                atomicAdd(&cand_lds, 1ull);
             } else {
                 key[v] = -1;
             }
         }
-        const bool is_low = cand && deg <= low_t;
-        const bool is_mid = cand && deg > low_t && deg <= hub_t;
-        const int64_t sl = wave_append(is_low, &counters[CNT_CL_LOW]);
-        if (is_low) cl_low[sl] = (int32_t)v;
-        const int64_t sm = wave_append(is_mid, &counters[CNT_CL_MID]);
-        if (is_mid) cl_mid[sm] = (int32_t)v;
-        const uint64_t cm = __ballot(cand);
-        if (lane_id() == 0 && cm) atomicAdd(&counters[CNT_CAND], (unsigned long long)__popcll(cm));
     }
+    __syncthreads();
+    if (threadIdx.x == 0 && cand_lds) atomicAdd(&counters[CNT_CAND], cand_lds);
 }
 
 hipError_t launch_best_move(const GraphView &g, int32_t k, const int32_t *part, const int32_t *conn,
-                            const int64_t *W, const int64_t *cb, const int64_t *penq, int64_t lmax,
-                            int mode, int64_t low_t, int64_t hub_t, int64_t *key, int64_t *pen,
-                            int32_t *cl_low, int32_t *cl_mid, unsigned long long *counters,
-                            hipStream_t s)
+                            const int64_t *W, const int64_t *cb, const int64_t *penq,
+                            const int64_t *pen1, int64_t lmax, int mode, int64_t *key,
+                            int64_t *pen, unsigned long long *counters, hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
-#define UPR_BM(GG)                                                                                \
-    hipLaunchKernelGGL(k_best_move<GG>, dim3(grid_cap(g.n, kBlock / GG, 16384)), dim3(kBlock), 0, \
-                       s, g, k, part, conn, W, cb, penq, lmax, mode, low_t, hub_t, key, pen,      \
-                       cl_low, cl_mid, counters)
-    if (k <= 4) UPR_BM(4);
-    else if (k <= 8) UPR_BM(8);
-    else if (k <= 16) UPR_BM(16);
-    else if (k <= 32) UPR_BM(32);
-    else UPR_BM(64);
+    const size_t lds = k <= 2048 ? (size_t)k * 16 : 0;
+    const bool vec = (k % 4) == 0;
+    const int nvec = vec ? k / 4 : k;
+#define UPR_BM(GG, VV)                                                                             \
+    hipLaunchKernelGGL((k_best_move<GG, VV>), dim3(grid_cap(g.n, kBlock / GG, 8192)), dim3(kBlock), \
+                       lds, s, g, k, part, conn, W, cb, penq, pen1, lmax, mode, key, pen, counters)
+    if (vec) {
+        if (nvec <= 1) UPR_BM(1, 4);
+        else if (nvec <= 2) UPR_BM(2, 4);
+        else if (nvec <= 4) UPR_BM(4, 4);
+        else if (nvec <= 8) UPR_BM(8, 4);
+        else if (nvec <= 16) UPR_BM(16, 4);
+        else if (nvec <= 32) UPR_BM(32, 4);
+        else UPR_BM(64, 4);
+    } else {
+        if (nvec <= 2) UPR_BM(2, 1);
+        else if (nvec <= 4) UPR_BM(4, 1);
+        else if (nvec <= 8) UPR_BM(8, 1);
+        else if (nvec <= 16) UPR_BM(16, 1);
+        else if (nvec <= 32) UPR_BM(32, 1);
+        else UPR_BM(64, 1);
+    }
 #undef UPR_BM
     return hipGetLastError();
 }
@@ -198,7 +248,9 @@ __device__ __forceinline__ int move_sign(int32_t x, int32_t a, int32_t b)
 }
 
 // S3 for candidate v (a -> b, score sv): pessimistic gain over its row
-// [e0, e1) strided by `step` starting at e0 + off.
+// [e0, e1) strided by `step` starting at e0 + off. An earlier candidate
+// neighbour u ((score, id) before v) contributes the worse of its current
+// and its target block.
 __device__ __forceinline__ int64_t pessimistic_part(const GraphView &g, const int32_t *part,
                                                     const int64_t *key, int64_t v, int32_t a,
                                                     int32_t b, int64_t sv, int64_t e0, int64_t e1,
@@ -221,59 +273,78 @@ __device__ __forceinline__ int64_t pessimistic_part(const GraphView &g, const in
     return acc;
 }
 
+// One class of a wave's compacted candidates: lane groups of G take the
+// set bits of mask in order; the node id / key of bit p sit in lane p.
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_filter(GraphView g, const int32_t *__restrict__ part,
-                                                    const int64_t *__restrict__ key,
-                                                    const int64_t *__restrict__ pen,
-                                                    const int32_t *__restrict__ list, int cnt_slot,
-                                                    Move *out, int out_slot, uint8_t *accflag,
-                                                    unsigned long long *counters)
+__device__ __forceinline__ void filter_class(const GraphView &g, const int32_t *part,
+                                             const int64_t *key, const int64_t *pen,
+                                             uint64_t mask, int64_t lane_v, int64_t lane_key,
+                                             int32_t *mvto, uint8_t *accflag,
+                                             unsigned long long *acc_lds)
 {
-    constexpr int GPB = kBlock / G;
-    const int gl = threadIdx.x & (G - 1);
-    const int64_t cnt = (int64_t)counters[cnt_slot];
-    const int64_t stride = (int64_t)gridDim.x * GPB;
-    const int64_t first = (int64_t)blockIdx.x * GPB + threadIdx.x / G;
-    const int64_t wave_first = (int64_t)blockIdx.x * GPB + (threadIdx.x & ~63) / G;
-    for (int64_t ib = wave_first; ib < cnt; ib += stride) {
-        const int64_t i = ib + (first - wave_first);
-        const bool valid = i < cnt;
-        int64_t acc = 0, v = 0, kv = 0;
-        int32_t a = 0, b = 0;
-        if (valid) {
-            v = list[i];
-            kv = key[v];
-            a = part[v];
+    const int cnt = __popcll(mask);
+    const int lane = lane_id();
+    const int grp = lane / G;
+    const int gl = lane & (G - 1);
+    for (int p0 = 0; p0 < cnt; p0 += 64 / G) {
+        const int p = p0 + grp;
+        const bool ok = p < cnt;
+        const int src = ok ? nth_set_bit(mask, p) : 0;
+        const int64_t v = __shfl(lane_v, src);
+        const int64_t kv = __shfl(lane_key, src);
+        int64_t acc = 0;
+        int32_t b = 0;
+        if (ok) {
+            const int32_t a = part[v];
             b = (int32_t)(kv & 0xFFFF);
-            acc = pessimistic_part(g, part, key, v, a, b, kv >> 16, g.xadj[v], g.xadj[v + 1], gl, G);
+            acc = pessimistic_part(g, part, key, v, a, b, kv >> 16, g.xadj[v], g.xadj[v + 1], gl,
+                                   G);
         }
         acc = group_sum<G>(acc);
-        bool ok = false;
-        if (valid && gl == 0) {
-            ok = acc * 65536 - pen[v] > 0;
-            accflag[v] = ok ? 1 : 0;
+        bool take = false;
+        if (ok && gl == 0) {
+            take = acc * 65536 - pen[v] > 0;
+            accflag[v] = take ? 1 : 0;
+            if (take) mvto[v] = b;
         }
-        const int64_t slot = wave_append(ok, &counters[out_slot]);
-        if (ok) out[slot] = Move{(int32_t)v, b};
-        const uint64_t am = __ballot(ok);
-        if (lane_id() == 0 && am) atomicAdd(&counters[CNT_ACC], (unsigned long long)__popcll(am));
+        wave_count(take, acc_lds);
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_filter(GraphView g, const int32_t *__restrict__ part,
+                                                    const int64_t *__restrict__ key,
+                                                    const int64_t *__restrict__ pen, int64_t low_t,
+                                                    int64_t hub_t, int32_t *mvto, uint8_t *accflag,
+                                                    unsigned long long *counters)
+{
+    __shared__ unsigned long long acc_lds;
+    if (threadIdx.x == 0) acc_lds = 0;
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < g.n;
+         base += stride) {
+        const int64_t v = base + lane_id();
+        int64_t kv = -1, deg = 0;
+        if (v < g.n) {
+            kv = key[v];
+            if (kv >= 0) deg = g.xadj[v + 1] - g.xadj[v];
+        }
+        const uint64_t mlow = __ballot(kv >= 0 && deg <= low_t);
+        const uint64_t mmid = __ballot(kv >= 0 && deg > low_t && deg <= hub_t);
+        if (mlow) filter_class<kLowLanes>(g, part, key, pen, mlow, v, kv, mvto, accflag, &acc_lds);
+        if (mmid) filter_class<64>(g, part, key, pen, mmid, v, kv, mvto, accflag, &acc_lds);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && acc_lds) atomicAdd(&counters[CNT_ACC], acc_lds);
+}
+
 hipError_t launch_filter(const GraphView &g, const int32_t *part, const int64_t *key,
-                         const int64_t *pen, const int32_t *cl_low, const int32_t *cl_mid,
-                         Move *mv_low, Move *mv_mid, uint8_t *accflag,
-                         unsigned long long *counters, hipStream_t s)
+                         const int64_t *pen, int64_t low_t, int64_t hub_t, int32_t *mvto,
+                         uint8_t *accflag, unsigned long long *counters, hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_filter<kLowLanes>, dim3(grid_cap(g.n, kBlock / kLowLanes, 4096)),
-                       dim3(kBlock), 0, s, g, part, key, pen, cl_low, (int)CNT_CL_LOW, mv_low,
-                       (int)CNT_MV_LOW, accflag, counters);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_filter<kMidLanes>, dim3(grid_cap(g.n, kBlock / kMidLanes, 4096)),
-                       dim3(kBlock), 0, s, g, part, key, pen, cl_mid, (int)CNT_CL_MID, mv_mid,
-                       (int)CNT_MV_MID, accflag, counters);
+    hipLaunchKernelGGL(k_filter, dim3(grid_cap(g.n, kBlock, 8192)), dim3(kBlock), 0, s, g, part,
+                       key, pen, low_t, hub_t, mvto, accflag, counters);
     return hipGetLastError();
 }
 
@@ -292,9 +363,9 @@ __global__ __launch_bounds__(kBlock) void k_filter_hub(GraphView g, const int32_
     if (threadIdx.x == 0 && acc) atomic_add_i64(&h.gacc[c.hub], acc);
 }
 
-// Hub candidates: decide, record the move for the apply step, reset gacc.
-__global__ void k_filter_hub_final(const int32_t *part, const int64_t *key, const int64_t *pen,
-                                   HubView h, uint8_t *accflag, unsigned long long *counters)
+// Hub candidates: decide, mark the move, reset the accumulator.
+__global__ void k_filter_hub_final(const int64_t *key, const int64_t *pen, HubView h,
+                                   int32_t *mvto, uint8_t *accflag, unsigned long long *counters)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= h.nh) return;
@@ -306,15 +377,14 @@ __global__ void k_filter_hub_final(const int32_t *part, const int64_t *key, cons
     const bool ok = acc * 65536 - pen[v] > 0;
     accflag[v] = ok ? 1 : 0;
     if (ok) {
-        h.from[i] = part[v];
-        h.to[i] = (int32_t)(kv & 0xFFFF);
+        mvto[v] = (int32_t)(kv & 0xFFFF);
         atomicAdd(&counters[CNT_ACC], 1ull);
     }
 }
 
 hipError_t launch_filter_hub(const GraphView &g, const int32_t *part, const int64_t *key,
-                             const int64_t *pen, const HubView &h, uint8_t *accflag,
-                             unsigned long long *counters, hipStream_t s)
+                             const int64_t *pen, const HubView &h, int32_t *mvto,
+                             uint8_t *accflag, unsigned long long *counters, hipStream_t s)
 {
     if (h.nh <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_filter_hub, dim3((unsigned)h.nchunks), dim3(kBlock), 0, s, g, part, key,
@@ -322,7 +392,7 @@ hipError_t launch_filter_hub(const GraphView &g, const int32_t *part, const int6
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_filter_hub_final, dim3((h.nh + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                       part, key, pen, h, accflag, counters);
+                       key, pen, h, mvto, accflag, counters);
     return hipGetLastError();
 }
 
@@ -333,32 +403,26 @@ hipError_t launch_filter_hub(const GraphView &g, const int32_t *part, const int6
 // conn[u][a] -= omega(v, u), conn[u][b] += omega(v, u). Integer atomics
 // commute, so the result does not depend on the order of the moves.
 template <int G>
-__global__ __launch_bounds__(kBlock) void k_apply(GraphView g, int32_t k, int32_t *part,
-                                                   int32_t *conn, int64_t *W,
-                                                   const Move *__restrict__ list, int cnt_slot,
-                                                   unsigned long long *counters)
+__device__ __forceinline__ void apply_class(const GraphView &g, int32_t k, int32_t *part,
+                                            int32_t *conn, int64_t *wdst, uint64_t mask,
+                                            int64_t lane_v, int32_t lane_to, int32_t *mvto)
 {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    int64_t *wloc = (int64_t *)lds_raw;
-    const bool use_lds = k <= 2048;
-    const int64_t cnt = (int64_t)counters[cnt_slot];
-    if (cnt == 0) return;  // uniform
-    if (use_lds) {
-        for (int j = threadIdx.x; j < k; j += kBlock) wloc[j] = 0;
-        __syncthreads();
-    }
-    constexpr int GPB = kBlock / G;
-    const int gl = threadIdx.x & (G - 1);
-    const int64_t stride = (int64_t)gridDim.x * GPB;
-    for (int64_t i = (int64_t)blockIdx.x * GPB + threadIdx.x / G; i < cnt; i += stride) {
-        const Move m = list[i];
-        const int64_t v = m.v;
-        const int32_t b = m.to;
+    const int cnt = __popcll(mask);
+    const int lane = lane_id();
+    const int grp = lane / G;
+    const int gl = lane & (G - 1);
+    for (int p0 = 0; p0 < cnt; p0 += 64 / G) {
+        const int p = p0 + grp;
+        const bool ok = p < cnt;
+        const int src = ok ? nth_set_bit(mask, p) : 0;
+        const int64_t v = __shfl(lane_v, src);
+        const int32_t b = __shfl(lane_to, src);
+        if (!ok) continue;
         int32_t a = 0;
         if (gl == 0) a = part[v];
-        a = __shfl(a, (int)(threadIdx.x & 63) & ~(G - 1));
-        const int64_t e0 = g.xadj[v], e1 = g.xadj[v + 1];
-        for (int64_t e = e0 + gl; e < e1; e += G) {
+        a = __shfl(a, lane & ~(G - 1));
+        const int64_t e1 = g.xadj[v + 1];
+        for (int64_t e = g.xadj[v] + gl; e < e1; e += G) {
             const int64_t u = g.adjncy[e];
             const int32_t w = edge_weight(g, e);
             atomicAdd(&conn[u * k + a], -w);
@@ -367,14 +431,39 @@ __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, int32_t k, int32_
         if (gl == 0) {
             const int64_t cv = node_weight(g, v);
             part[v] = b;
-            if (use_lds) {
-                atomicAdd((unsigned long long *)&wloc[a], (unsigned long long)(-cv));
-                atomicAdd((unsigned long long *)&wloc[b], (unsigned long long)cv);
-            } else {
-                atomic_add_i64(&W[a], -cv);
-                atomic_add_i64(&W[b], cv);
-            }
+            mvto[v] = -1;
+            atomicAdd((unsigned long long *)&wdst[a], (unsigned long long)(-cv));
+            atomicAdd((unsigned long long *)&wdst[b], (unsigned long long)cv);
         }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_apply(GraphView g, int32_t k, int32_t *part,
+                                                   int32_t *conn, int64_t *W, int32_t *mvto,
+                                                   int64_t low_t, int64_t hub_t)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    int64_t *wloc = (int64_t *)lds_raw;
+    const bool use_lds = k <= 2048;
+    if (use_lds) {
+        for (int j = threadIdx.x; j < k; j += kBlock) wloc[j] = 0;
+        __syncthreads();
+    }
+    int64_t *wdst = use_lds ? wloc : W;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < g.n;
+         base += stride) {
+        const int64_t v = base + lane_id();
+        int32_t to = -1;
+        int64_t deg = 0;
+        if (v < g.n) {
+            to = mvto[v];
+            if (to >= 0) deg = g.xadj[v + 1] - g.xadj[v];
+        }
+        const uint64_t mlow = __ballot(to >= 0 && deg <= low_t);
+        const uint64_t mmid = __ballot(to >= 0 && deg > low_t && deg <= hub_t);
+        if (mlow) apply_class<kLowLanes>(g, k, part, conn, wdst, mlow, v, to, mvto);
+        if (mmid) apply_class<64>(g, k, part, conn, wdst, mmid, v, to, mvto);
     }
     if (use_lds) {
         __syncthreads();
@@ -383,14 +472,17 @@ __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, int32_t k, int32_
     }
 }
 
-// Hub moves: each chunk updates the rows of its neighbours.
-__global__ __launch_bounds__(kBlock) void k_apply_hub(GraphView g, int32_t k, int32_t *conn,
+// Hub moves: each chunk updates the rows of its neighbours (part of the hub
+// is still its source block here).
+__global__ __launch_bounds__(kBlock) void k_apply_hub(GraphView g, int32_t k, const int32_t *part,
+                                                       int32_t *conn, const int32_t *mvto,
                                                        HubView h)
 {
     const HubChunk c = h.chunks[blockIdx.x];
-    const int32_t b = h.to[c.hub];
+    const int64_t v = h.ids[c.hub];
+    const int32_t b = mvto[v];
     if (b < 0) return;
-    const int32_t a = h.from[c.hub];
+    const int32_t a = part[v];
     for (int64_t e = c.e0 + threadIdx.x; e < c.e1; e += kBlock) {
         const int64_t u = g.adjncy[e];
         const int32_t w = edge_weight(g, e);
@@ -399,41 +491,38 @@ __global__ __launch_bounds__(kBlock) void k_apply_hub(GraphView g, int32_t k, in
     }
 }
 
-// Hub moves: part and block weights, then clear the move record.
-__global__ void k_apply_hub_final(GraphView g, int32_t *part, int64_t *W, HubView h)
+// Hub moves: part and block weights, then clear the mark.
+__global__ void k_apply_hub_final(GraphView g, int32_t *part, int64_t *W, int32_t *mvto, HubView h)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= h.nh) return;
-    const int32_t b = h.to[i];
-    if (b < 0) return;
     const int64_t v = h.ids[i];
-    const int32_t a = h.from[i];
+    const int32_t b = mvto[v];
+    if (b < 0) return;
+    const int32_t a = part[v];
     const int64_t cv = node_weight(g, v);
     part[v] = b;
+    mvto[v] = -1;
     atomic_add_i64(&W[a], -cv);
     atomic_add_i64(&W[b], cv);
-    h.to[i] = -1;
 }
 
 hipError_t launch_apply(const GraphView &g, int32_t k, int32_t *part, int32_t *conn, int64_t *W,
-                        const Move *mv_low, const Move *mv_mid, const HubView &h,
-                        unsigned long long *counters, hipStream_t s)
+                        int32_t *mvto, int64_t low_t, int64_t hub_t, const HubView &h,
+                        hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
     const size_t lds = k <= 2048 ? (size_t)k * 8 : 0;
-    hipLaunchKernelGGL(k_apply<kLowLanes>, dim3(grid_cap(g.n, kBlock / kLowLanes, 2048)),
-                       dim3(kBlock), lds, s, g, k, part, conn, W, mv_low, (int)CNT_MV_LOW, counters);
+    hipLaunchKernelGGL(k_apply, dim3(grid_cap(g.n, kBlock, 4096)), dim3(kBlock), lds, s, g, k, part,
+                       conn, W, mvto, low_t, hub_t);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_apply<kMidLanes>, dim3(grid_cap(g.n, kBlock / kMidLanes, 2048)),
-                       dim3(kBlock), lds, s, g, k, part, conn, W, mv_mid, (int)CNT_MV_MID, counters);
-    e = hipGetLastError();
     if (e != hipSuccess || h.nh <= 0) return e;
-    hipLaunchKernelGGL(k_apply_hub, dim3((unsigned)h.nchunks), dim3(kBlock), 0, s, g, k, conn, h);
+    hipLaunchKernelGGL(k_apply_hub, dim3((unsigned)h.nchunks), dim3(kBlock), 0, s, g, k, part, conn,
+                       mvto, h);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_apply_hub_final, dim3((h.nh + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g,
-                       part, W, h);
+                       part, W, mvto, h);
     return hipGetLastError();
 }
 

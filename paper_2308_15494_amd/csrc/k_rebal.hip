@@ -13,9 +13,11 @@
 //             one chunk give the id bound of the minimal covering prefix
 //   target    the same over the selected nodes aimed at each target: the
 //             maximal prefix that fits the target's remaining capacity
-//   moves     accepted nodes become moves, applied by the apply kernels
+//   moves     accepted nodes are marked (mvto) for the apply kernels
 // Histogram rows and chunk rows are cleared by the kernel that reads them,
-// so they are zero again at the start of the next sub-iteration.
+// so they are zero again at the start of the next sub-iteration. Node scans
+// run over all ids in wave-sized runs; membership of a node in an overloaded
+// block is re-derived from part and the sub-iteration's starting weights.
 #include "upr_common.h"
 
 namespace upr {
@@ -55,7 +57,7 @@ __device__ __forceinline__ bool rb_accepted(const RbView &r, int64_t v, int32_t 
 
 // ------------------------------------------------------------------ begin --
 
-// Count overloaded blocks, snapshot W, reset the overloaded-node list.
+// Count overloaded blocks and snapshot W.
 __global__ void k_rb_begin(int32_t k, const int64_t *W, int64_t lmax, int64_t *W0,
                            unsigned long long *counters)
 {
@@ -67,10 +69,7 @@ __global__ void k_rb_begin(int32_t k, const int64_t *W, int64_t lmax, int64_t *W
         over += w > lmax;
     }
     over = block_sum(over, red);
-    if (threadIdx.x == 0) {
-        counters[CNT_OVER] = over;
-        counters[CNT_OLIST] = 0;
-    }
+    if (threadIdx.x == 0) counters[CNT_OVER] = over;
 }
 
 hipError_t launch_rb_begin(int32_t k, const int64_t *W, int64_t lmax, const RebalWs &r,
@@ -82,83 +81,128 @@ hipError_t launch_rb_begin(int32_t k, const int64_t *W, int64_t lmax, const Reba
 
 // ---------------------------------------------------------------- prepare --
 
-template <int G>
+constexpr int kHistLdsBytes = 32768;
+
+__device__ __forceinline__ bool in_overloaded(const RebalWs &r, int32_t k, int32_t a, int64_t lmax)
+{
+    return (unsigned)a < (unsigned)k && r.W0[a] > lmax;
+}
+
+// Nodes of overloaded blocks: target and priority bucket. G lanes per node
+// scan its row (V ints per lane per step): best connected target that stays
+// balanced (max conn, ties to the smaller id) and the lightest such block
+// (min W, ties to the smaller id) as fallback.
+template <int G, int V>
 __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, int32_t k,
                                                         const int32_t *__restrict__ part,
                                                         const int32_t *__restrict__ conn,
-                                                        int64_t lmax, RebalWs r,
-                                                        unsigned long long *counters)
+                                                        int64_t lmax, RebalWs r)
 {
-    constexpr int GPB = kBlock / G;
-    const int gl = threadIdx.x & (G - 1);
-    const int64_t stride = (int64_t)gridDim.x * GPB;
-    const int64_t first = (int64_t)blockIdx.x * GPB + threadIdx.x / G;
-    const int64_t wave_first = (int64_t)blockIdx.x * GPB + (threadIdx.x & ~63) / G;
-    for (int64_t vb = wave_first; vb < g.n; vb += stride) {
-        const int64_t v = vb + (first - wave_first);
-        bool active = false;
-        int32_t a = 0;
-        int64_t cv = 1;
-        if (v < g.n) {
-            a = part[v];
-            if ((unsigned)a < (unsigned)k && r.W0[a] > lmax) {
-                active = true;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    int64_t *sW = (int64_t *)lds_raw;
+    const bool w_lds = (size_t)k * 8 <= 16384;
+    const bool h_lds = (size_t)k * kRbBuckets * 8 <= kHistLdsBytes;
+    int64_t *sH = sW + (w_lds ? k : 0);
+    if (w_lds)
+        for (int j = threadIdx.x; j < k; j += kBlock) sW[j] = r.W0[j];
+    if (h_lds)
+        for (int j = threadIdx.x; j < k * kRbBuckets; j += kBlock) sH[j] = 0;
+    __syncthreads();
+    const int64_t *W0 = w_lds ? sW : r.W0;
+
+    const int lane = lane_id();
+    const int grp = lane / G;
+    const int gl = lane & (G - 1);
+    const int nvec = k / V;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < g.n;
+         base += stride) {
+        const int64_t lv = base + lane;
+        int32_t la = -1;
+        if (lv < g.n) la = part[lv];
+        const uint64_t mask = __ballot(lv < g.n && (unsigned)la < (unsigned)k && W0[la] > lmax);
+        const int cnt = __popcll(mask);
+        for (int p0 = 0; p0 < cnt; p0 += 64 / G) {
+            const int p = p0 + grp;
+            const bool ok = p < cnt;
+            const int src = ok ? nth_set_bit(mask, p) : 0;
+            const int64_t v = __shfl(lv, src);
+            const int32_t a = __shfl(la, src);
+            int64_t best = -1, lw = INT64_MAX, cv = 1;
+            int32_t lj = 0x7fffffff;
+            if (ok) {
                 cv = node_weight(g, v);
-            }
-        }
-        // best connected valid target: max (conn, -j); lightest valid: min (W, j)
-        int64_t best = -1, lw = INT64_MAX;
-        int32_t lj = 0x7fffffff;
-        if (active) {
-            const int32_t *row = conn + v * (int64_t)k;
-            for (int j = gl; j < k; j += G) {
-                if (j == a) continue;
-                const int64_t wj = r.W0[j];
-                if (wj + cv > lmax) continue;
-                const int32_t cj = row[j];
-                if (cj > 0) {
-                    const int64_t p = ((int64_t)cj << 16) | (int64_t)(0xFFFF - j);
-                    if (p > best) best = p;
-                }
-                if (wj < lw || (wj == lw && j < lj)) {
-                    lw = wj;
-                    lj = j;
-                }
-            }
-        }
+                const int32_t *row = conn + v * (int64_t)k;
+                for (int q = gl; q < nvec; q += G) {
+                    int32_t c4[V];
+                    if constexpr (V == 4) {
+                        const int4 x = ((const int4 *)row)[q];
+                        c4[0] = x.x;
+                        c4[1] = x.y;
+                        c4[2] = x.z;
+                        c4[3] = x.w;
+                    } else {
+                        c4[0] = row[q];
+                    }
 #pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) {
-            const int64_t ob = __shfl_xor(best, off);
-            const int64_t ow = __shfl_xor(lw, off);
-            const int32_t oj = __shfl_xor(lj, off);
-            if (ob > best) best = ob;
-            if (ow < lw || (ow == lw && oj < lj)) {
-                lw = ow;
-                lj = oj;
+                    for (int t = 0; t < V; ++t) {
+                        const int j = q * V + t;
+                        if (j == a) continue;
+                        const int64_t wj = W0[j];
+                        if (wj + cv > lmax) continue;
+                        if (c4[t] > 0) {
+                            const int64_t pk = ((int64_t)c4[t] << 16) | (int64_t)(0xFFFF - j);
+                            if (pk > best) best = pk;
+                        }
+                        if (wj < lw || (wj == lw && j < lj)) {
+                            lw = wj;
+                            lj = j;
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int off = G / 2; off > 0; off >>= 1) {
+                const int64_t ob = __shfl_xor(best, off);
+                const int64_t ow = __shfl_xor(lw, off);
+                const int32_t oj = __shfl_xor(lj, off);
+                if (ob > best) best = ob;
+                if (ow < lw || (ow == lw && oj < lj)) {
+                    lw = ow;
+                    lj = oj;
+                }
+            }
+            bool push = false;
+            int64_t hkey = 0;
+            if (ok && gl == 0) {
+                int32_t tgt = -1;
+                int64_t ct = 0;
+                if (best >= 0) {
+                    tgt = 0xFFFF - (int32_t)(best & 0xFFFF);
+                    ct = best >> 16;
+                } else if (lj != 0x7fffffff) {
+                    tgt = lj;
+                }
+                r.rtgt[v] = tgt;
+                if (tgt >= 0) {
+                    const int64_t ca = conn[v * (int64_t)k + a];
+                    const int be = rebalance_bucket(ct - ca, cv);
+                    r.rbeta[v] = (uint8_t)be;
+                    hkey = (int64_t)a * kRbBuckets + be;
+                    push = true;
+                }
+            }
+            if (h_lds) {
+                if (push) atomicAdd((unsigned long long *)&sH[hkey], (unsigned long long)cv);
+            } else {
+                wave_hist_add(r.hist_src, hkey, cv, push);
             }
         }
-        bool push = false;
-        if (active && gl == 0) {
-            int32_t tgt = -1;
-            int64_t ct = 0;
-            if (best >= 0) {
-                tgt = 0xFFFF - (int32_t)(best & 0xFFFF);
-                ct = best >> 16;
-            } else if (lj != 0x7fffffff) {
-                tgt = lj;
-                ct = 0;
-            }
-            r.rtgt[v] = tgt;
-            if (tgt >= 0) {
-                const int64_t ca = conn[v * (int64_t)k + a];
-                const int be = rebalance_bucket(ct - ca, cv);
-                r.rbeta[v] = (uint8_t)be;
-                atomic_add_i64(&r.hist_src[(int64_t)a * kRbBuckets + be], cv);
-                push = true;
-            }
-        }
-        const int64_t slot = wave_append(push, &counters[CNT_OLIST]);
-        if (push) r.olist[slot] = (int32_t)v;
+    }
+    if (h_lds) {
+        __syncthreads();
+        for (int j = threadIdx.x; j < k * kRbBuckets; j += kBlock)
+            if (sH[j]) atomic_add_i64(&r.hist_src[j], sH[j]);
     }
 }
 
@@ -172,11 +216,7 @@ __global__ void k_rb_cutoffs(int32_t k, int64_t lmax, RebalWs r, int target_side
                              unsigned long long *counters)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (!target_side && j == 0) {
-        counters[CNT_MV_LOW] = 0;
-        counters[CNT_MV_MID] = 0;
-        counters[CNT_MOVED_NOW] = 0;
-    }
+    if (!target_side && j == 0) counters[CNT_MOVED_NOW] = 0;
     if (j >= k) return;
     int64_t *h = (target_side ? r.hist_tgt : r.hist_src) + (int64_t)j * kRbBuckets;
     const int64_t w0 = r.W0[j];
@@ -223,16 +263,23 @@ __global__ void k_rb_cutoffs(int32_t k, int64_t lmax, RebalWs r, int target_side
 
 // ------------------------------------------------------ chunk histograms --
 
-// Nodes in the cutoff bucket add their weight to the chunk of their id.
-__global__ __launch_bounds__(kBlock) void k_rb_chunks(GraphView g, const int32_t *part,
-                                                       RebalWs r, RbView rv, int target_side,
-                                                       const unsigned long long *counters)
+// Movable node of an overloaded block (its rtgt/rbeta are this
+// sub-iteration's).
+__device__ __forceinline__ bool rb_member(const RebalWs &r, int32_t k, int64_t lmax, int64_t v,
+                                          int32_t a)
 {
-    const int64_t cnt = (int64_t)counters[CNT_OLIST];
+    return (unsigned)a < (unsigned)k && r.W0[a] > lmax && r.rtgt[v] >= 0;
+}
+
+// Nodes in the cutoff bucket add their weight to the chunk of their id.
+__global__ __launch_bounds__(kBlock) void k_rb_chunks(GraphView g, int32_t k, const int32_t *part,
+                                                       int64_t lmax, RebalWs r, RbView rv,
+                                                       int target_side)
+{
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
-        const int64_t v = r.olist[i];
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += stride) {
         const int32_t a = part[v];
+        if (!rb_member(r, k, lmax, v, a)) continue;
         const int be = r.rbeta[v];
         if (!target_side) {
             if (be == r.cbeta_src[a])
@@ -248,18 +295,40 @@ __global__ __launch_bounds__(kBlock) void k_rb_chunks(GraphView g, const int32_t
 }
 
 // Selected nodes add their weight to their target's bucket histogram.
-__global__ __launch_bounds__(kBlock) void k_rb_tgt_hist(GraphView g, const int32_t *part,
-                                                         RebalWs r, RbView rv,
-                                                         const unsigned long long *counters)
+__global__ __launch_bounds__(kBlock) void k_rb_tgt_hist(GraphView g, int32_t k, const int32_t *part,
+                                                         int64_t lmax, RebalWs r, RbView rv)
 {
-    const int64_t cnt = (int64_t)counters[CNT_OLIST];
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
-        const int64_t v = r.olist[i];
-        const int32_t a = part[v];
-        if (rb_selected(rv, v, a))
-            atomic_add_i64(&r.hist_tgt[(int64_t)r.rtgt[v] * kRbBuckets + r.rbeta[v]],
-                           node_weight(g, v));
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    int64_t *sH = (int64_t *)lds_raw;
+    const bool h_lds = (size_t)k * kRbBuckets * 8 <= kHistLdsBytes;
+    if (h_lds) {
+        for (int j = threadIdx.x; j < k * kRbBuckets; j += kBlock) sH[j] = 0;
+        __syncthreads();
+    }
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < g.n;
+         base += stride) {
+        const int64_t v = base + lane_id();
+        bool sel = false;
+        int64_t hkey = 0, cv = 0;
+        if (v < g.n) {
+            const int32_t a = part[v];
+            if (rb_member(r, k, lmax, v, a) && rb_selected(rv, v, a)) {
+                sel = true;
+                hkey = (int64_t)r.rtgt[v] * kRbBuckets + r.rbeta[v];
+                cv = node_weight(g, v);
+            }
+        }
+        if (h_lds) {
+            if (sel) atomicAdd((unsigned long long *)&sH[hkey], (unsigned long long)cv);
+        } else {
+            wave_hist_add(r.hist_tgt, hkey, cv, sel);
+        }
+    }
+    if (h_lds) {
+        __syncthreads();
+        for (int j = threadIdx.x; j < k * kRbBuckets; j += kBlock)
+            if (sH[j]) atomic_add_i64(&r.hist_tgt[j], sH[j]);
     }
 }
 
@@ -360,97 +429,91 @@ __global__ __launch_bounds__(kBlock) void k_rb_theta(GraphView g, int32_t k, con
 
 // ------------------------------------------------------------------ moves --
 
-__device__ __forceinline__ int hub_index(const HubView &h, int64_t v)
+// Accepted nodes get mvto[v] = target; counts per workgroup.
+__global__ __launch_bounds__(kBlock) void k_rb_moves(GraphView g, int32_t k, const int32_t *part,
+                                                      int64_t lmax, RebalWs r, RbView rv,
+                                                      int32_t *mvto, unsigned long long *counters)
 {
-    int lo = 0, hi = h.nh - 1;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if ((int64_t)h.ids[mid] < v) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-__global__ __launch_bounds__(kBlock) void k_rb_moves(GraphView g, const int32_t *part, RebalWs r,
-                                                      RbView rv, HubView h, int64_t hub_t,
-                                                      int64_t low_t, Move *mv_low, Move *mv_mid,
-                                                      unsigned long long *counters)
-{
-    const int64_t cnt = (int64_t)counters[CNT_OLIST];
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t wave_base = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
-    for (int64_t ib = wave_base; ib < cnt; ib += stride) {
-        const int64_t i = ib + (threadIdx.x & 63);
-        bool acc = false, lo = false, mid = false;
-        int64_t v = 0;
-        int32_t j = 0;
-        if (i < cnt) {
-            v = r.olist[i];
+    __shared__ unsigned long long moved;
+    if (threadIdx.x == 0) moved = 0;
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < g.n;
+         base += stride) {
+        const int64_t v = base + lane_id();
+        bool acc = false;
+        if (v < g.n) {
             const int32_t a = part[v];
-            j = r.rtgt[v];
-            acc = rb_accepted(rv, v, a, j);
-            if (acc) {
-                const int64_t deg = g.xadj[v + 1] - g.xadj[v];
-                if (deg > hub_t) {
-                    const int hi = hub_index(h, v);
-                    h.from[hi] = a;
-                    h.to[hi] = j;
-                } else if (deg > low_t) {
-                    mid = true;
-                } else {
-                    lo = true;
+            if (rb_member(r, k, lmax, v, a)) {
+                const int32_t j = r.rtgt[v];
+                if (rb_accepted(rv, v, a, j)) {
+                    mvto[v] = j;
+                    acc = true;
                 }
             }
         }
-        const int64_t sl = wave_append(lo, &counters[CNT_MV_LOW]);
-        if (lo) mv_low[sl] = Move{(int32_t)v, j};
-        const int64_t sm = wave_append(mid, &counters[CNT_MV_MID]);
-        if (mid) mv_mid[sm] = Move{(int32_t)v, j};
-        const uint64_t am = __ballot(acc);
-        if (lane_id() == 0 && am) {
-            atomicAdd(&counters[CNT_MOVED_NOW], (unsigned long long)__popcll(am));
-            atomicAdd(&counters[CNT_REBAL_MOVES], (unsigned long long)__popcll(am));
-        }
+        wave_count(acc, &moved);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && moved) {
+        atomicAdd(&counters[CNT_MOVED_NOW], moved);
+        atomicAdd(&counters[CNT_REBAL_MOVES], moved);
     }
 }
 
 // --------------------------------------------------------------- sequence --
 
 hipError_t launch_rb_iteration(const GraphView &g, int32_t k, const int32_t *part,
-                               const int32_t *conn, int64_t lmax, int64_t hub_t, int64_t low_t,
-                               const RebalWs &r, const HubView &h, Move *mv_low, Move *mv_mid,
-                               unsigned long long *counters, hipStream_t s)
+                               const int32_t *conn, int64_t lmax, const RebalWs &r,
+                               int32_t *mvto, unsigned long long *counters, hipStream_t s)
 {
     hipError_t e;
     const RbView rv{r.rtgt, r.rbeta, r.W0, r.cbeta_src, r.theta_src, r.cbeta_tgt, r.theta_tgt};
-#define UPR_RP(GG)                                                                                 \
-    hipLaunchKernelGGL(k_rb_prepare<GG>, dim3(grid_cap(g.n, kBlock / GG, 16384)), dim3(kBlock), 0, \
-                       s, g, k, part, conn, lmax, r, counters)
-    if (k <= 4) UPR_RP(4);
-    else if (k <= 8) UPR_RP(8);
-    else if (k <= 16) UPR_RP(16);
-    else if (k <= 32) UPR_RP(32);
-    else UPR_RP(64);
+    const int lg = grid_cap(g.n, kBlock, 4096);
+    const bool h_lds = (size_t)k * kRbBuckets * 8 <= kHistLdsBytes;
+    const size_t plds = ((size_t)k * 8 <= 16384 ? (size_t)k * 8 : 0) +
+                        (h_lds ? (size_t)k * kRbBuckets * 8 : 0);
+    const bool vec = (k % 4) == 0;
+    const int nvec = vec ? k / 4 : k;
+#define UPR_RP(GG, VV)                                                                          \
+    hipLaunchKernelGGL((k_rb_prepare<GG, VV>), dim3(lg), dim3(kBlock), plds, s, g, k, part, conn, \
+                       lmax, r)
+    if (vec) {
+        if (nvec <= 1) UPR_RP(1, 4);
+        else if (nvec <= 2) UPR_RP(2, 4);
+        else if (nvec <= 4) UPR_RP(4, 4);
+        else if (nvec <= 8) UPR_RP(8, 4);
+        else if (nvec <= 16) UPR_RP(16, 4);
+        else if (nvec <= 32) UPR_RP(32, 4);
+        else UPR_RP(64, 4);
+    } else {
+        if (nvec <= 2) UPR_RP(2, 1);
+        else if (nvec <= 4) UPR_RP(4, 1);
+        else if (nvec <= 8) UPR_RP(8, 1);
+        else if (nvec <= 16) UPR_RP(16, 1);
+        else if (nvec <= 32) UPR_RP(32, 1);
+        else UPR_RP(64, 1);
+    }
 #undef UPR_RP
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const dim3 kg((k + kBlock - 1) / kBlock);
-    const int lg = grid_cap(g.n, kBlock, 2048);
     hipLaunchKernelGGL(k_rb_cutoffs, kg, dim3(kBlock), 0, s, k, lmax, r, 0, counters);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rb_chunks, dim3(lg), dim3(kBlock), 0, s, g, part, r, rv, 0, counters);
+    hipLaunchKernelGGL(k_rb_chunks, dim3(lg), dim3(kBlock), 0, s, g, k, part, lmax, r, rv, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rb_theta, dim3(k), dim3(kBlock), 0, s, g, k, part, lmax, r, rv, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rb_tgt_hist, dim3(lg), dim3(kBlock), 0, s, g, part, r, rv, counters);
+    hipLaunchKernelGGL(k_rb_tgt_hist, dim3(lg), dim3(kBlock), h_lds ? (size_t)k * kRbBuckets * 8 : 0,
+                       s, g, k, part, lmax, r, rv);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rb_cutoffs, kg, dim3(kBlock), 0, s, k, lmax, r, 1, counters);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rb_chunks, dim3(lg), dim3(kBlock), 0, s, g, part, r, rv, 1, counters);
+    hipLaunchKernelGGL(k_rb_chunks, dim3(lg), dim3(kBlock), 0, s, g, k, part, lmax, r, rv, 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rb_theta, dim3(k), dim3(kBlock), 0, s, g, k, part, lmax, r, rv, 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rb_moves, dim3(lg), dim3(kBlock), 0, s, g, part, r, rv, h, hub_t, low_t,
-                       mv_low, mv_mid, counters);
+    hipLaunchKernelGGL(k_rb_moves, dim3(lg), dim3(kBlock), 0, s, g, k, part, lmax, r, rv, mvto,
+                       counters);
     return hipGetLastError();
 }
 

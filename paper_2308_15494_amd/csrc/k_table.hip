@@ -211,18 +211,15 @@ __device__ __forceinline__ int upper_index(const int32_t *a, int cnt, int32_t p)
     return lo;
 }
 
-// One workgroup per tile of T nodes. With with_stats, also: block weights
-// W[j] += c(v) (if W != null), 2*cut partial into counters[CNT_CUT2_BEFORE],
-// penalty bucket weights of the rebalance-available non-hub nodes (Section
-// 5.3: t_den * omega(v, Pi(v)) >= t_num * omega(I(v))).
+// One workgroup per tile of T consecutive nodes: zero the T x k rows in
+// LDS, accumulate every non-hub edge of the tile (edge-parallel; the edge ->
+// node map is a binary search over the tile's degree prefix), write the rows
+// back as one contiguous span. Hub rows are written as zeros here and filled
+// by k_gain_hub.
 template <bool WEIGHTED>
 __global__ __launch_bounds__(kBlock) void k_gain_tile(GraphView g, int32_t k, int T,
                                                        const int32_t *__restrict__ part,
-                                                       int32_t *__restrict__ conn,
-                                                       const int32_t *__restrict__ wdeg,
-                                                       int64_t hub_t, int64_t *W, int64_t *bucket,
-                                                       int32_t t_num, int32_t t_den,
-                                                       unsigned long long *counters, int with_stats)
+                                                       int32_t *__restrict__ conn, int64_t hub_t)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     int32_t *tile = (int32_t *)lds_raw;
@@ -230,14 +227,18 @@ __global__ __launch_bounds__(kBlock) void k_gain_tile(GraphView g, int32_t k, in
     int32_t *vstart = (int32_t *)(lds_raw + rows_bytes);
     int64_t *gstart = (int64_t *)(lds_raw + rows_bytes + (((size_t)(T + 1) * 4 + 15) & ~(size_t)15));
     __shared__ int32_t scan_lds[4];
-    __shared__ unsigned long long red_lds[4];
 
     const int64_t v0 = (int64_t)blockIdx.x * T;
     const int nt = (int)((g.n - v0) < T ? (g.n - v0) : T);
     const int tid = threadIdx.x;
     const int64_t kk = k;
 
-    for (int i = tid; i < nt * k; i += kBlock) tile[i] = 0;
+    {
+        int4 *t4 = (int4 *)tile;
+        const int n4 = (nt * k) >> 2;
+        for (int i = tid; i < n4; i += kBlock) t4[i] = make_int4(0, 0, 0, 0);
+        for (int i = (n4 << 2) + tid; i < nt * k; i += kBlock) tile[i] = 0;
+    }
 
     // virtual degrees (hubs contribute none) and their exclusive prefix,
     // in chunks of kBlock nodes
@@ -283,34 +284,10 @@ __global__ __launch_bounds__(kBlock) void k_gain_tile(GraphView g, int32_t k, in
     } else {
         for (int64_t i = tid; i < total_ints; i += kBlock) dst[i] = tile[i];
     }
-
-    if (!with_stats) return;
-    unsigned long long cut2 = 0;
-    for (int i = tid; i < nt; i += kBlock) {
-        const int64_t v = v0 + i;
-        const int32_t a = part[v];
-        if ((unsigned)a >= (unsigned)k) {
-            atomicAdd(&counters[CNT_BAD_INPUT], 1ull);
-            continue;
-        }
-        const int64_t cv = g.vwgt ? (int64_t)g.vwgt[v] : 1;
-        if (W) atomic_add_i64(&W[a], cv);
-        const int64_t deg = g.xadj[v + 1] - gstart[i];
-        if (deg > hub_t) continue;  // hub: its row is finished by the hub kernels
-        const int64_t inner = tile[i * k + a];
-        const int64_t wd = wdeg[v];
-        cut2 += (unsigned long long)(wd - inner);
-        if ((int64_t)t_den * inner >= (int64_t)t_num * wd)
-            atomic_add_i64(&bucket[(int64_t)a * kSlots + slot_of(inner, cv)], cv);
-    }
-    cut2 = block_sum(cut2, red_lds);
-    if (tid == 0 && cut2) atomicAdd(&counters[CNT_CUT2_BEFORE], cut2);
 }
 
 hipError_t launch_gain_tile(const GraphView &g, int32_t k, const int32_t *part, int32_t *conn,
-                            const int32_t *wdeg, int64_t hub_t, int64_t *W, int64_t *bucket,
-                            int32_t t_num, int32_t t_den, unsigned long long *counters,
-                            int with_stats, hipStream_t s)
+                            int64_t hub_t, hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
     const int T = gain_tile_nodes(k);
@@ -318,11 +295,10 @@ hipError_t launch_gain_tile(const GraphView &g, int32_t k, const int32_t *part, 
     const size_t lds = gain_tile_lds(k, T);
     if (g.adjwgt)
         hipLaunchKernelGGL(k_gain_tile<true>, dim3((unsigned)tiles), dim3(kBlock), lds, s, g, k, T,
-                           part, conn, wdeg, hub_t, W, bucket, t_num, t_den, counters, with_stats);
+                           part, conn, hub_t);
     else
         hipLaunchKernelGGL(k_gain_tile<false>, dim3((unsigned)tiles), dim3(kBlock), lds, s, g, k,
-                           T, part, conn, wdeg, hub_t, W, bucket, t_num, t_den, counters,
-                           with_stats);
+                           T, part, conn, hub_t);
     return hipGetLastError();
 }
 
@@ -356,34 +332,6 @@ hipError_t launch_gain_hub(const GraphView &g, int32_t k, const int32_t *part, i
     if (h.nchunks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_gain_hub, dim3((unsigned)h.nchunks), dim3(kBlock), (size_t)k * 4, s, g, k,
                        part, conn, h);
-    return hipGetLastError();
-}
-
-// Per hub: cut contribution and penalty bucket from the finished row.
-__global__ void k_hub_stats(GraphView g, int32_t k, const int32_t *part, const int32_t *conn,
-                            const int32_t *wdeg, HubView h, int64_t *bucket, int32_t t_num,
-                            int32_t t_den, unsigned long long *counters)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= h.nh) return;
-    const int64_t v = h.ids[i];
-    const int32_t a = part[v];
-    if ((unsigned)a >= (unsigned)k) return;  // reported by the tile kernel
-    const int64_t inner = conn[v * (int64_t)k + a];
-    const int64_t wd = wdeg[v];
-    const int64_t cv = node_weight(g, v);
-    atomicAdd(&counters[CNT_CUT2_BEFORE], (unsigned long long)(wd - inner));
-    if ((int64_t)t_den * inner >= (int64_t)t_num * wd)
-        atomic_add_i64(&bucket[(int64_t)a * kSlots + slot_of(inner, cv)], cv);
-}
-
-hipError_t launch_hub_stats(const GraphView &g, int32_t k, const int32_t *part, const int32_t *conn,
-                            const int32_t *wdeg, const HubView &h, int64_t *bucket, int32_t t_num,
-                            int32_t t_den, unsigned long long *counters, hipStream_t s)
-{
-    if (h.nh <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_hub_stats, dim3((h.nh + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g, k,
-                       part, conn, wdeg, h, bucket, t_num, t_den, counters);
     return hipGetLastError();
 }
 
@@ -430,71 +378,98 @@ hipError_t launch_block_weights(const GraphView &g, int32_t k, const int32_t *pa
 
 // ------------------------------------------------------------------- cut --
 
-// 2 * cut = sum_v (omega(I(v)) - omega(v, Pi(v))) from the table.
-__global__ __launch_bounds__(kBlock) void k_cut_table(GraphView g, int32_t k,
-                                                       const int32_t *__restrict__ part,
-                                                       const int32_t *__restrict__ conn,
-                                                       const int32_t *__restrict__ wdeg,
-                                                       unsigned long long *acc)
-{
-    __shared__ unsigned long long red[4];
-    unsigned long long s = 0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += stride) {
-        const int32_t a = part[v];
-        if ((unsigned)a >= (unsigned)k) continue;
-        s += (unsigned long long)((int64_t)wdeg[v] - conn[v * (int64_t)k + a]);
-    }
-    s = block_sum(s, red);
-    if (threadIdx.x == 0 && s) atomicAdd(acc, s);
-}
+// Per node, from a finished table: 2 * cut contribution
+// omega(I(v)) - omega(v, Pi(v)), block weight (if W), and the penalty bucket
+// of rebalance-available nodes (Section 5.3: t_den * omega(v, Pi(v)) >=
+// t_num * omega(I(v)); slot(omega(v, Pi(v)), c(v))). Block weights and
+// buckets are accumulated in LDS when they fit, else by wave-aggregated
+// global atomics.
+constexpr int kStatsLdsBytes = 32768;
 
-hipError_t launch_cut_table(const GraphView &g, int32_t k, const int32_t *part, const int32_t *conn,
-                            const int32_t *wdeg, unsigned long long *acc, hipStream_t s)
-{
-    if (g.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cut_table, dim3(grid_for(g.n, kBlock * 4, 4096)), dim3(kBlock), 0, s, g, k,
-                       part, conn, wdeg, acc);
-    return hipGetLastError();
-}
-
-// Resident form: 2 * cut and the penalty buckets from an existing table.
 __global__ __launch_bounds__(kBlock) void k_node_stats(GraphView g, int32_t k,
                                                         const int32_t *__restrict__ part,
                                                         const int32_t *__restrict__ conn,
                                                         const int32_t *__restrict__ wdeg,
-                                                        int64_t *bucket, int32_t t_num,
-                                                        int32_t t_den, unsigned long long *counters)
+                                                        int64_t *W, int64_t *bucket,
+                                                        int32_t t_num, int32_t t_den,
+                                                        unsigned long long *counters, int cut_slot)
 {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ unsigned long long red[4];
+    __shared__ unsigned long long bad;
+    const bool w_lds = W && (size_t)k * 8 <= 16384;
+    const bool b_lds = bucket && (size_t)k * kSlots * 8 <= kStatsLdsBytes;
+    int64_t *lw = (int64_t *)lds_raw;
+    int64_t *lb = (int64_t *)(lds_raw + (w_lds ? (size_t)k * 8 : 0));
+    if (threadIdx.x == 0) bad = 0;
+    if (w_lds)
+        for (int j = threadIdx.x; j < k; j += kBlock) lw[j] = 0;
+    if (b_lds)
+        for (int j = threadIdx.x; j < k * kSlots; j += kBlock) lb[j] = 0;
+    __syncthreads();
+
     unsigned long long s = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += stride) {
-        const int32_t a = part[v];
-        if ((unsigned)a >= (unsigned)k) {
-            atomicAdd(&counters[CNT_BAD_INPUT], 1ull);
-            continue;
+    const int64_t nn = g.n;
+    // loop bound uniform per wave (wave_hist_add needs whole waves)
+    for (int64_t vb = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); vb < nn; vb += stride) {
+        const int64_t v = vb + lane_id();
+        bool ok = v < nn;
+        int32_t a = 0;
+        int64_t cv = 1, inner = 0, wd = 0;
+        if (ok) {
+            a = part[v];
+            if ((unsigned)a >= (unsigned)k) {
+                atomicAdd(&bad, 1ull);
+                ok = false;
+            } else {
+                inner = conn[v * (int64_t)k + a];
+                wd = wdeg[v];
+                cv = node_weight(g, v);
+                s += (unsigned long long)(wd - inner);
+            }
         }
-        const int64_t inner = conn[v * (int64_t)k + a];
-        const int64_t wd = wdeg[v];
-        s += (unsigned long long)(wd - inner);
-        if ((int64_t)t_den * inner >= (int64_t)t_num * wd) {
-            const int64_t cv = node_weight(g, v);
-            atomic_add_i64(&bucket[(int64_t)a * kSlots + slot_of(inner, cv)], cv);
+        if (W) {
+            if (w_lds) {
+                if (ok) atomicAdd((unsigned long long *)&lw[a], (unsigned long long)cv);
+            } else {
+                wave_hist_add(W, a, cv, ok);
+            }
+        }
+        if (bucket) {
+            const bool avail = ok && (int64_t)t_den * inner >= (int64_t)t_num * wd;
+            const int64_t key = (int64_t)a * kSlots + (avail ? slot_of(inner, cv) : 0);
+            if (b_lds) {
+                if (avail) atomicAdd((unsigned long long *)&lb[key], (unsigned long long)cv);
+            } else {
+                wave_hist_add(bucket, key, cv, avail);
+            }
         }
     }
     s = block_sum(s, red);
-    if (threadIdx.x == 0 && s) atomicAdd(&counters[CNT_CUT2_BEFORE], s);
+    if (threadIdx.x == 0) {
+        if (s) atomicAdd(&counters[cut_slot], s);
+        if (bad) atomicAdd(&counters[CNT_BAD_INPUT], bad);
+    }
+    if (w_lds)
+        for (int j = threadIdx.x; j < k; j += kBlock)
+            if (lw[j]) atomic_add_i64(&W[j], lw[j]);
+    if (b_lds)
+        for (int j = threadIdx.x; j < k * kSlots; j += kBlock)
+            if (lb[j]) atomic_add_i64(&bucket[j], lb[j]);
 }
 
 hipError_t launch_node_stats(const GraphView &g, int32_t k, const int32_t *part,
-                             const int32_t *conn, const int32_t *wdeg, int64_t *bucket,
-                             int32_t t_num, int32_t t_den, unsigned long long *counters,
-                             hipStream_t s)
+                             const int32_t *conn, const int32_t *wdeg, int64_t *W,
+                             int64_t *bucket, int32_t t_num, int32_t t_den,
+                             unsigned long long *counters, int cut_slot, hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_node_stats, dim3(grid_for(g.n, kBlock * 4, 4096)), dim3(kBlock), 0, s, g,
-                       k, part, conn, wdeg, bucket, t_num, t_den, counters);
+    size_t lds = 0;
+    if (W && (size_t)k * 8 <= 16384) lds += (size_t)k * 8;
+    if (bucket && (size_t)k * kSlots * 8 <= kStatsLdsBytes) lds += (size_t)k * kSlots * 8;
+    hipLaunchKernelGGL(k_node_stats, dim3(grid_for(g.n, kBlock * 8, 2048)), dim3(kBlock), lds, s,
+                       g, k, part, conn, wdeg, W, bucket, t_num, t_den, counters, cut_slot);
     return hipGetLastError();
 }
 

@@ -53,9 +53,9 @@ struct upr_ctx {
     int64_t cap_n = 0, cap_k = 0;
     int64_t *key = nullptr, *pen = nullptr;
     uint8_t *accflag = nullptr;
-    int32_t *cl_low = nullptr, *cl_mid = nullptr;
-    Move *mv_low = nullptr, *mv_mid = nullptr;
+    int32_t *mvto = nullptr;     // [n] pending move target, -1 = none
     int64_t *bucket = nullptr, *penq = nullptr;
+    int64_t *pen1 = nullptr;     // [k] unit-weight penalty per target block
     unsigned long long *counters = nullptr;
     unsigned long long *flags = nullptr;  // validation flags [4]
     RebalWs rb{};
@@ -73,13 +73,12 @@ struct upr_plan {
     int32_t *hub_ids = nullptr;
     HubChunk *chunks = nullptr;
     int64_t nchunks = 0;
-    int32_t *hub_from = nullptr, *hub_to = nullptr;
     int64_t *gacc = nullptr;
     int64_t hub_t = kDefaultHubThreshold, low_t = kDefaultLowThreshold;
 
     HubView hubs() const
     {
-        return HubView{nh, hub_ids, chunks, nchunks, hub_from, hub_to, gacc};
+        return HubView{nh, hub_ids, chunks, nchunks, gacc};
     }
 };
 
@@ -123,14 +122,11 @@ void free_workspace(upr_ctx *c)
     dfree(c->key);
     dfree(c->pen);
     dfree(c->accflag);
-    dfree(c->cl_low);
-    dfree(c->cl_mid);
-    dfree(c->mv_low);
-    dfree(c->mv_mid);
+    dfree(c->mvto);
     dfree(c->bucket);
+    dfree(c->pen1);
     dfree(c->rb.rtgt);
     dfree(c->rb.rbeta);
-    dfree(c->rb.olist);
     dfree(c->rb.W0);
     dfree(c->rb.hist_src);
     dfree(c->rb.hist_tgt);
@@ -154,11 +150,10 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
     HIP_TRY(c, hipDeviceSynchronize());
     free_workspace(c);
     bool ok = dalloc(&c->key, N) == hipSuccess && dalloc(&c->pen, N) == hipSuccess &&
-              dalloc(&c->accflag, N) == hipSuccess && dalloc(&c->cl_low, N) == hipSuccess &&
-              dalloc(&c->cl_mid, N) == hipSuccess && dalloc(&c->mv_low, N) == hipSuccess &&
-              dalloc(&c->mv_mid, N) == hipSuccess && dalloc(&c->bucket, K * kSlots) == hipSuccess &&
+              dalloc(&c->accflag, N) == hipSuccess && dalloc(&c->mvto, N) == hipSuccess &&
+              dalloc(&c->bucket, K * kSlots) == hipSuccess && dalloc(&c->pen1, K) == hipSuccess &&
               dalloc(&c->rb.rtgt, N) == hipSuccess && dalloc(&c->rb.rbeta, N) == hipSuccess &&
-              dalloc(&c->rb.olist, N) == hipSuccess && dalloc(&c->rb.W0, K) == hipSuccess &&
+              dalloc(&c->rb.W0, K) == hipSuccess &&
               dalloc(&c->rb.hist_src, K * kRbBuckets) == hipSuccess &&
               dalloc(&c->rb.hist_tgt, K * kRbBuckets) == hipSuccess &&
               dalloc(&c->rb.cbeta_src, K) == hipSuccess && dalloc(&c->rb.cbeta_tgt, K) == hipSuccess &&
@@ -177,6 +172,7 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
     HIP_TRY(c, hipMemset(c->rb.chunk_src, 0, sizeof(int64_t) * kChunkEntries));
     HIP_TRY(c, hipMemset(c->rb.chunk_tgt, 0, sizeof(int64_t) * kChunkEntries));
     HIP_TRY(c, hipMemset(c->key, 0xff, sizeof(int64_t) * N));
+    HIP_TRY(c, hipMemset(c->mvto, 0xff, sizeof(int32_t) * N));
     HIP_TRY(c, hipDeviceSynchronize());
     c->cap_n = N;
     c->cap_k = K;
@@ -288,9 +284,8 @@ int rebalance_loop(upr_ctx *c, const upr_plan *p, int32_t k, int32_t *part, int3
             break;
         }
         ++iters;
-        HIP_TRY(c, launch_rb_iteration(p->g, k, part, conn, lmax, p->hub_t, p->low_t, c->rb, h,
-                                       c->mv_low, c->mv_mid, c->counters, s));
-        HIP_TRY(c, launch_apply(p->g, k, part, conn, W, c->mv_low, c->mv_mid, h, c->counters, s));
+        HIP_TRY(c, launch_rb_iteration(p->g, k, part, conn, lmax, c->rb, c->mvto, c->counters, s));
+        HIP_TRY(c, launch_apply(p->g, k, part, conn, W, c->mvto, p->low_t, p->hub_t, h, s));
         HIP_TRY(c, launch_rb_begin(k, W, lmax, c->rb, c->counters, s));
         rc = sync_counters(c, s);
         if (rc) return rc;
@@ -390,10 +385,15 @@ int upr_validate_graph(upr_ctx *c, const upr_graph *graph, hipStream_t s)
     if (!c) return UPR_E_ARG;
     if (!graph) return fail(c, UPR_E_ARG, "graph is NULL");
     if (graph->n < 0 || graph->n >= ((int64_t)1 << 31)) return fail(c, UPR_E_ARG, "n out of range");
-    if (graph->n > 0 && (!graph->xadj || !graph->adjncy)) return fail(c, UPR_E_ARG, "xadj/adjncy NULL");
+    if (graph->n > 0 && !graph->xadj) return fail(c, UPR_E_ARG, "xadj NULL");
     HIP_TRY(c, hipSetDevice(c->device));
     const GraphView g{graph->n, graph->xadj, graph->adjncy, graph->adjwgt, graph->vwgt};
     if (g.n == 0) return UPR_OK;
+    {
+        int64_t nnz = 0;
+        HIP_TRY(c, hipMemcpy(&nnz, g.xadj + g.n, sizeof nnz, hipMemcpyDeviceToHost));
+        if (nnz > 0 && !g.adjncy) return fail(c, UPR_E_ARG, "adjncy NULL with %lld entries", (long long)nnz);
+    }
     unsigned long long init[4] = {~0ull, ~0ull, ~0ull, ~0ull}, got[4];
     for (int stage = 0; stage < 3; ++stage) {
         HIP_TRY(c, hipMemcpyAsync(c->flags, init, sizeof init, hipMemcpyHostToDevice, s));
@@ -428,9 +428,15 @@ int upr_plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipStrea
     *out = nullptr;
     if (!graph) return fail(c, UPR_E_ARG, "graph is NULL");
     if (graph->n < 0 || graph->n >= ((int64_t)1 << 31)) return fail(c, UPR_E_ARG, "n out of range");
-    if (graph->n > 0 && (!graph->xadj || !graph->adjncy)) return fail(c, UPR_E_ARG, "xadj/adjncy NULL");
+    if (graph->n > 0 && !graph->xadj) return fail(c, UPR_E_ARG, "xadj NULL");
     HIP_TRY(c, hipSetDevice(c->device));
     const GraphView g{graph->n, graph->xadj, graph->adjncy, graph->adjwgt, graph->vwgt};
+    if (g.n > 0) {
+        int64_t nnz = 0;
+        HIP_TRY(c, hipMemcpy(&nnz, g.xadj + g.n, sizeof nnz, hipMemcpyDeviceToHost));
+        if (nnz < 0) return fail(c, UPR_E_GRAPH, "xadj[n] < 0");
+        if (nnz > 0 && !g.adjncy) return fail(c, UPR_E_ARG, "adjncy NULL with %lld entries", (long long)nnz);
+    }
 
     // basic validation: xadj, ids in range, positive weights (kernels rely on it)
     if (g.n > 0) {
@@ -486,8 +492,7 @@ int upr_plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipStrea
             if (hipMemcpy(ids.data(), hub_list, sizeof(int32_t) * p->nh, hipMemcpyDeviceToHost) != hipSuccess)
                 return bail(UPR_E_HIP, "reading the hub list failed");
             std::sort(ids.begin(), ids.end());
-            if (dalloc(&p->hub_ids, p->nh) != hipSuccess || dalloc(&p->hub_from, p->nh) != hipSuccess ||
-                dalloc(&p->hub_to, p->nh) != hipSuccess || dalloc(&p->gacc, p->nh) != hipSuccess)
+            if (dalloc(&p->hub_ids, p->nh) != hipSuccess || dalloc(&p->gacc, p->nh) != hipSuccess)
                 return bail(UPR_E_NOMEM, "plan allocation failed");
             std::vector<int64_t> e01(2 * (size_t)p->nh);
             int64_t *d_e01 = nullptr;
@@ -505,7 +510,6 @@ int upr_plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipStrea
             p->nchunks = (int64_t)chunks.size();
             if (dalloc(&p->chunks, p->nchunks) != hipSuccess) return bail(UPR_E_NOMEM, "plan allocation failed");
             ok = hipMemcpy(p->chunks, chunks.data(), sizeof(HubChunk) * chunks.size(), hipMemcpyHostToDevice) == hipSuccess &&
-                 launch_fill_i32(p->hub_to, p->nh, -1, s) == hipSuccess &&
                  launch_fill_i64(p->gacc, p->nh, 0, s) == hipSuccess &&
                  hipStreamSynchronize(s) == hipSuccess;
             if (!ok) return bail(UPR_E_HIP, "hub preparation failed");
@@ -524,8 +528,6 @@ void upr_plan_destroy(upr_plan *p)
     dfree(p->wdeg);
     dfree(p->hub_ids);
     dfree(p->chunks);
-    dfree(p->hub_from);
-    dfree(p->hub_to);
     dfree(p->gacc);
     delete p;
 }
@@ -556,8 +558,7 @@ int upr_gain_table(upr_ctx *c, const upr_plan *p, int32_t k, const int32_t *part
     if (rc) return rc;
     if (c->pinned[CNT_BAD_INPUT]) return fail(c, UPR_E_ARG, "part holds values outside [0, k)");
     PhaseTimer t(c, 0, s);
-    HIP_TRY(c, launch_gain_tile(p->g, k, part, conn, p->wdeg, p->hub_t, nullptr, nullptr, 0, 1,
-                                c->counters, 0, s));
+    HIP_TRY(c, launch_gain_tile(p->g, k, part, conn, p->hub_t, s));
     HIP_TRY(c, launch_gain_hub(p->g, k, part, conn, p->hubs(), s));
     return UPR_OK;
 }
@@ -621,41 +622,41 @@ static int round_common(upr_ctx *c, const upr_plan *p, const upr_params *q, int3
     if (q->rebuild_table) {
         {
             PhaseTimer t(c, 0, s);
-            HIP_TRY(c, launch_gain_tile(p->g, k, part, conn, p->wdeg, p->hub_t, W, c->bucket,
-                                        q->t_num, q->t_den, c->counters, 1, s));
+            HIP_TRY(c, launch_gain_tile(p->g, k, part, conn, p->hub_t, s));
         }
         if (p->nh > 0) {
             PhaseTimer t(c, 1, s);
             HIP_TRY(c, launch_gain_hub(p->g, k, part, conn, h, s));
-            HIP_TRY(c, launch_hub_stats(p->g, k, part, conn, p->wdeg, h, c->bucket, q->t_num,
-                                        q->t_den, c->counters, s));
         }
-    } else {
+    }
+    {
         PhaseTimer t(c, 1, s);
-        HIP_TRY(c, launch_node_stats(p->g, k, part, conn, p->wdeg, c->bucket, q->t_num, q->t_den,
-                                     c->counters, s));
+        HIP_TRY(c, launch_node_stats(p->g, k, part, conn, p->wdeg, q->rebuild_table ? W : nullptr,
+                                     moves ? c->bucket : nullptr, q->t_num, q->t_den, c->counters,
+                                     CNT_CUT2_BEFORE, s));
     }
     if (moves) {
         {
             PhaseTimer t(c, 2, s);
-            HIP_TRY(c, launch_cb_prefix(k, c->bucket, s));
-            HIP_TRY(c, launch_best_move(p->g, k, part, conn, W, c->bucket, c->penq, lmax, q->mode,
-                                        p->low_t, p->hub_t, c->key, c->pen, c->cl_low, c->cl_mid,
-                                        c->counters, s));
+            HIP_TRY(c, launch_cb_prefix(k, c->bucket, W, lmax, c->penq, q->mode, c->pen1, s));
+            HIP_TRY(c, launch_best_move(p->g, k, part, conn, W, c->bucket, c->penq, c->pen1, lmax,
+                                        q->mode, c->key, c->pen, c->counters, s));
         }
         {
             PhaseTimer t(c, 3, s);
-            HIP_TRY(c, launch_filter(p->g, part, c->key, c->pen, c->cl_low, c->cl_mid, c->mv_low,
-                                     c->mv_mid, c->accflag, c->counters, s));
-            HIP_TRY(c, launch_filter_hub(p->g, part, c->key, c->pen, h, c->accflag, c->counters, s));
+            HIP_TRY(c, launch_filter(p->g, part, c->key, c->pen, p->low_t, p->hub_t, c->mvto,
+                                     c->accflag, c->counters, s));
+            HIP_TRY(c, launch_filter_hub(p->g, part, c->key, c->pen, h, c->mvto, c->accflag,
+                                         c->counters, s));
         }
         {
             PhaseTimer t(c, 4, s);
-            HIP_TRY(c, launch_apply(p->g, k, part, conn, W, c->mv_low, c->mv_mid, h, c->counters, s));
+            HIP_TRY(c, launch_apply(p->g, k, part, conn, W, c->mvto, p->low_t, p->hub_t, h, s));
         }
         {
             PhaseTimer t(c, 6, s);
-            HIP_TRY(c, launch_cut_table(p->g, k, part, conn, p->wdeg, c->counters + CNT_CUT2_MOVES, s));
+            HIP_TRY(c, launch_node_stats(p->g, k, part, conn, p->wdeg, nullptr, nullptr, 0, 1,
+                                         c->counters, CNT_CUT2_MOVES, s));
         }
     }
     int64_t iters = 0, status = 0;
@@ -667,7 +668,8 @@ static int round_common(upr_ctx *c, const upr_plan *p, const upr_params *q, int3
     }
     {
         PhaseTimer t(c, 6, s);
-        HIP_TRY(c, launch_cut_table(p->g, k, part, conn, p->wdeg, c->counters + CNT_CUT2_AFTER, s));
+        HIP_TRY(c, launch_node_stats(p->g, k, part, conn, p->wdeg, nullptr, nullptr, 0, 1,
+                                     c->counters, CNT_CUT2_AFTER, s));
     }
     if (!moves) {
         // standalone rebalancing: nothing moved before it

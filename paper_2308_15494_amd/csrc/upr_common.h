@@ -56,14 +56,7 @@ struct HubView {
     const int32_t *ids;   // sorted node ids of hubs
     const HubChunk *chunks;
     int64_t nchunks;
-    int32_t *from;        // [nh] source block of a moving hub
-    int32_t *to;          // [nh] target block of a moving hub, -1 if not moving
     int64_t *gacc;        // [nh] filter gain accumulator
-};
-
-struct Move {
-    int32_t v;
-    int32_t to;
 };
 
 // ---------------------------------------------------------------- device --
@@ -205,6 +198,46 @@ __device__ __forceinline__ void atomic_add_i64(int64_t *p, int64_t v)
     atomicAdd((unsigned long long *)p, (unsigned long long)v);
 }
 
+// Position of the n-th (0-based) set bit of mask (n < popcount(mask)).
+__device__ __forceinline__ int nth_set_bit(uint64_t mask, int n)
+{
+    int pos = 0;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const int c = __popcll((mask >> pos) & ((1ull << w) - 1));
+        if (n >= c) {
+            n -= c;
+            pos += w;
+        }
+    }
+    return pos;
+}
+
+// base[key] += val for every active lane, one global atomic per distinct key
+// of the wave (lanes with equal keys are summed first).
+__device__ __forceinline__ void wave_hist_add(int64_t *base, int64_t key, int64_t val, bool active)
+{
+    uint64_t pending = __ballot(active);
+    const int lane = lane_id();
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int64_t lk = __shfl(key, leader);
+        const bool same = active && key == lk;
+        const uint64_t sm = __ballot(same);
+        const int64_t sum = wave_sum(same ? val : (int64_t)0);
+        if (lane == leader) atomic_add_i64(base + lk, sum);
+        pending &= ~sm;
+        active = active && !same;
+    }
+}
+
+// Add the number of lanes with pred to an LDS counter (lane 0 of the wave).
+__device__ __forceinline__ void wave_count(bool pred, unsigned long long *lds_counter)
+{
+    const uint64_t m = __ballot(pred);
+    if (lane_id() == 0 && m) atomicAdd(lds_counter, (unsigned long long)__popcll(m));
+}
+
 // ------------------------------------------------------------ launchers --
 // Each returns hipGetLastError() after enqueueing on `s`.
 
@@ -224,24 +257,19 @@ hipError_t launch_hub_ranges(const int64_t *xadj, const int32_t *ids, int32_t nh
 // table (S1)
 int gain_tile_nodes(int32_t k);
 hipError_t launch_gain_tile(const GraphView &g, int32_t k, const int32_t *part, int32_t *conn,
-                            const int32_t *wdeg, int64_t hub_t, int64_t *W, int64_t *bucket,
-                            int32_t t_num, int32_t t_den, unsigned long long *counters,
-                            int with_stats, hipStream_t s);
+                            int64_t hub_t, hipStream_t s);
 hipError_t launch_gain_hub(const GraphView &g, int32_t k, const int32_t *part, int32_t *conn,
                            const HubView &h, hipStream_t s);
-hipError_t launch_hub_stats(const GraphView &g, int32_t k, const int32_t *part, const int32_t *conn,
-                            const int32_t *wdeg, const HubView &h, int64_t *bucket, int32_t t_num,
-                            int32_t t_den, unsigned long long *counters, hipStream_t s);
+// Per node: 2*cut into counters[cut_slot], penalty buckets of the available
+// nodes (bucket may be null), block weights W[part] += c (W may be null).
+hipError_t launch_node_stats(const GraphView &g, int32_t k, const int32_t *part,
+                             const int32_t *conn, const int32_t *wdeg, int64_t *W,
+                             int64_t *bucket, int32_t t_num, int32_t t_den,
+                             unsigned long long *counters, int cut_slot, hipStream_t s);
 hipError_t launch_block_weights(const GraphView &g, int32_t k, const int32_t *part, int64_t *W,
                                 unsigned long long *counters, hipStream_t s);
-hipError_t launch_cut_table(const GraphView &g, int32_t k, const int32_t *part, const int32_t *conn,
-                            const int32_t *wdeg, unsigned long long *acc, hipStream_t s);
 hipError_t launch_cut_edges(const GraphView &g, const int32_t *part, unsigned long long *acc,
                             hipStream_t s);
-hipError_t launch_node_stats(const GraphView &g, int32_t k, const int32_t *part,
-                             const int32_t *conn, const int32_t *wdeg, int64_t *bucket,
-                             int32_t t_num, int32_t t_den, unsigned long long *counters,
-                             hipStream_t s);
 hipError_t launch_store_half(const unsigned long long *acc, int64_t *out, hipStream_t s);
 hipError_t launch_check_part(int64_t n, int32_t k, const int32_t *part,
                              unsigned long long *counters, hipStream_t s);
@@ -249,22 +277,24 @@ hipError_t launch_check_part(int64_t n, int32_t k, const int32_t *part,
 // moves (S0, S2-S4)
 hipError_t launch_round_init(int32_t k, int64_t *bucket, int64_t *W, const PenTable &pq,
                              int64_t *penq, unsigned long long *counters, int zero_w, hipStream_t s);
-hipError_t launch_cb_prefix(int32_t k, int64_t *bucket, hipStream_t s);
+// Prefix sums of the buckets; pen1[j] = penalty of a unit-weight node moving
+// into j (0 if it fits, -1 if forbidden).
+hipError_t launch_cb_prefix(int32_t k, int64_t *bucket, const int64_t *W, int64_t lmax,
+                            const int64_t *penq, int mode, int64_t *pen1, hipStream_t s);
 hipError_t launch_best_move(const GraphView &g, int32_t k, const int32_t *part, const int32_t *conn,
-                            const int64_t *W, const int64_t *cb, const int64_t *penq, int64_t lmax,
-                            int mode, int64_t low_t, int64_t hub_t, int64_t *key, int64_t *pen,
-                            int32_t *cl_low, int32_t *cl_mid, unsigned long long *counters,
-                            hipStream_t s);
+                            const int64_t *W, const int64_t *cb, const int64_t *penq,
+                            const int64_t *pen1, int64_t lmax, int mode, int64_t *key,
+                            int64_t *pen, unsigned long long *counters, hipStream_t s);
 hipError_t launch_filter(const GraphView &g, const int32_t *part, const int64_t *key,
-                         const int64_t *pen, const int32_t *cl_low, const int32_t *cl_mid,
-                         Move *mv_low, Move *mv_mid, uint8_t *accflag,
-                         unsigned long long *counters, hipStream_t s);
+                         const int64_t *pen, int64_t low_t, int64_t hub_t, int32_t *mvto,
+                         uint8_t *accflag, unsigned long long *counters, hipStream_t s);
 hipError_t launch_filter_hub(const GraphView &g, const int32_t *part, const int64_t *key,
-                             const int64_t *pen, const HubView &h, uint8_t *accflag,
-                             unsigned long long *counters, hipStream_t s);
+                             const int64_t *pen, const HubView &h, int32_t *mvto,
+                             uint8_t *accflag, unsigned long long *counters, hipStream_t s);
+// Apply every move recorded in mvto (target block, -1 = none) and clear it.
 hipError_t launch_apply(const GraphView &g, int32_t k, int32_t *part, int32_t *conn, int64_t *W,
-                        const Move *mv_low, const Move *mv_mid, const HubView &h,
-                        unsigned long long *counters, hipStream_t s);
+                        int32_t *mvto, int64_t low_t, int64_t hub_t, const HubView &h,
+                        hipStream_t s);
 hipError_t launch_stats_final(int64_t *stats, const unsigned long long *counters, int64_t lmax,
                               int64_t iters, int64_t status, hipStream_t s);
 hipError_t launch_export_moves(int64_t n, const int64_t *key, const int64_t *pen,
@@ -275,7 +305,6 @@ hipError_t launch_export_moves(int64_t n, const int64_t *key, const int64_t *pen
 struct RebalWs {
     int32_t *rtgt;       // [n] target of a node of an overloaded block, -1 if none
     uint8_t *rbeta;      // [n] its priority bucket
-    int32_t *olist;      // [n] nodes of overloaded blocks with a target
     int64_t *W0;         // [k] block weights at sub-iteration start
     int64_t *hist_src;   // [k * kRbBuckets]
     int64_t *hist_tgt;   // [k * kRbBuckets]
@@ -293,9 +322,10 @@ struct RebalWs {
 
 hipError_t launch_rb_begin(int32_t k, const int64_t *W, int64_t lmax, const RebalWs &r,
                            unsigned long long *counters, hipStream_t s);
+// One sub-iteration up to the move marks: targets and buckets, source and
+// target selection; accepted nodes get mvto[v] = target.
 hipError_t launch_rb_iteration(const GraphView &g, int32_t k, const int32_t *part,
-                               const int32_t *conn, int64_t lmax, int64_t hub_t, int64_t low_t,
-                               const RebalWs &r, const HubView &h, Move *mv_low, Move *mv_mid,
-                               unsigned long long *counters, hipStream_t s);
+                               const int32_t *conn, int64_t lmax, const RebalWs &r,
+                               int32_t *mvto, unsigned long long *counters, hipStream_t s);
 
 }  // namespace upr
