@@ -280,7 +280,8 @@ __device__ __forceinline__ void filter_class(const GraphView &g, const int32_t *
                                              const int64_t *key, const int64_t *pen,
                                              uint64_t mask, int64_t lane_v, int64_t lane_key,
                                              int32_t *mvto, uint8_t *accflag,
-                                             unsigned long long *acc_lds)
+                                             unsigned long long *acc_lds,
+                                             unsigned long long *deg_lds)
 {
     const int cnt = __popcll(mask);
     const int lane = lane_id();
@@ -305,7 +306,10 @@ __device__ __forceinline__ void filter_class(const GraphView &g, const int32_t *
         if (ok && gl == 0) {
             take = acc * 65536 - pen[v] > 0;
             accflag[v] = take ? 1 : 0;
-            if (take) mvto[v] = b;
+            if (take) {
+                mvto[v] = b;
+                atomicAdd(deg_lds, (unsigned long long)(g.xadj[v + 1] - g.xadj[v]));
+            }
         }
         wave_count(take, acc_lds);
     }
@@ -317,8 +321,11 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, const int32_t *_
                                                     int64_t hub_t, int32_t *mvto, uint8_t *accflag,
                                                     unsigned long long *counters)
 {
-    __shared__ unsigned long long acc_lds;
-    if (threadIdx.x == 0) acc_lds = 0;
+    __shared__ unsigned long long acc_lds, deg_lds;
+    if (threadIdx.x == 0) {
+        acc_lds = 0;
+        deg_lds = 0;
+    }
     __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < g.n;
@@ -331,11 +338,17 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, const int32_t *_
         }
         const uint64_t mlow = __ballot(kv >= 0 && deg <= low_t);
         const uint64_t mmid = __ballot(kv >= 0 && deg > low_t && deg <= hub_t);
-        if (mlow) filter_class<kLowLanes>(g, part, key, pen, mlow, v, kv, mvto, accflag, &acc_lds);
-        if (mmid) filter_class<64>(g, part, key, pen, mmid, v, kv, mvto, accflag, &acc_lds);
+        if (mlow)
+            filter_class<kLowLanes>(g, part, key, pen, mlow, v, kv, mvto, accflag, &acc_lds,
+                                    &deg_lds);
+        if (mmid)
+            filter_class<64>(g, part, key, pen, mmid, v, kv, mvto, accflag, &acc_lds, &deg_lds);
     }
     __syncthreads();
-    if (threadIdx.x == 0 && acc_lds) atomicAdd(&counters[CNT_ACC], acc_lds);
+    if (threadIdx.x == 0) {
+        if (acc_lds) atomicAdd(&counters[CNT_ACC], acc_lds);
+        if (deg_lds) atomicAdd(&counters[CNT_MOVED_DEG], deg_lds);
+    }
 }
 
 hipError_t launch_filter(const GraphView &g, const int32_t *part, const int64_t *key,
@@ -382,6 +395,15 @@ __global__ void k_filter_hub_final(const int64_t *key, const int64_t *pen, HubVi
     }
 }
 
+__global__ void k_hub_moved_deg(GraphView g, const int32_t *mvto, HubView h,
+                                unsigned long long *counters)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= h.nh) return;
+    const int64_t v = h.ids[i];
+    if (mvto[v] >= 0) atomicAdd(&counters[CNT_MOVED_DEG], (unsigned long long)(g.xadj[v + 1] - g.xadj[v]));
+}
+
 hipError_t launch_filter_hub(const GraphView &g, const int32_t *part, const int64_t *key,
                              const int64_t *pen, const HubView &h, int32_t *mvto,
                              uint8_t *accflag, unsigned long long *counters, hipStream_t s)
@@ -405,7 +427,8 @@ hipError_t launch_filter_hub(const GraphView &g, const int32_t *part, const int6
 template <int G>
 __device__ __forceinline__ void apply_class(const GraphView &g, int32_t k, int32_t *part,
                                             int32_t *conn, int64_t *wdst, uint64_t mask,
-                                            int64_t lane_v, int32_t lane_to, int32_t *mvto)
+                                            int64_t lane_v, int32_t lane_to, int32_t *mvto,
+                                            const HubView &h, uint8_t *dirty, int T)
 {
     const int cnt = __popcll(mask);
     const int lane = lane_id();
@@ -422,11 +445,16 @@ __device__ __forceinline__ void apply_class(const GraphView &g, int32_t k, int32
         if (gl == 0) a = part[v];
         a = __shfl(a, lane & ~(G - 1));
         const int64_t e1 = g.xadj[v + 1];
-        for (int64_t e = g.xadj[v] + gl; e < e1; e += G) {
-            const int64_t u = g.adjncy[e];
-            const int32_t w = edge_weight(g, e);
-            atomicAdd(&conn[u * k + a], -w);
-            atomicAdd(&conn[u * k + b], w);
+        if (dirty) {
+            for (int64_t e = g.xadj[v] + gl; e < e1; e += G) dirty[g.adjncy[e] / T] = 1;
+        } else {
+            for (int64_t e = g.xadj[v] + gl; e < e1; e += G) {
+                const int64_t u = g.adjncy[e];
+                if (is_hub(h, u)) continue;  // hub rows are rebuilt after the apply
+                const int32_t w = edge_weight(g, e);
+                atomicAdd(&conn[u * k + a], -w);
+                atomicAdd(&conn[u * k + b], w);
+            }
         }
         if (gl == 0) {
             const int64_t cv = node_weight(g, v);
@@ -440,8 +468,13 @@ __device__ __forceinline__ void apply_class(const GraphView &g, int32_t k, int32
 
 __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, int32_t k, int32_t *part,
                                                    int32_t *conn, int64_t *W, int32_t *mvto,
-                                                   int64_t low_t, int64_t hub_t)
+                                                   int64_t low_t, int64_t hub_t, HubView h,
+                                                   const unsigned long long *counters,
+                                                   int64_t dirty_threshold, uint8_t *dirty_flags,
+                                                   int T)
 {
+    uint8_t *dirty =
+        (int64_t)counters[CNT_MOVED_DEG] > dirty_threshold ? dirty_flags : (uint8_t *)nullptr;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     int64_t *wloc = (int64_t *)lds_raw;
     const bool use_lds = k <= 2048;
@@ -462,8 +495,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, int32_t k, int32_
         }
         const uint64_t mlow = __ballot(to >= 0 && deg <= low_t);
         const uint64_t mmid = __ballot(to >= 0 && deg > low_t && deg <= hub_t);
-        if (mlow) apply_class<kLowLanes>(g, k, part, conn, wdst, mlow, v, to, mvto);
-        if (mmid) apply_class<64>(g, k, part, conn, wdst, mmid, v, to, mvto);
+        if (mlow) apply_class<kLowLanes>(g, k, part, conn, wdst, mlow, v, to, mvto, h, dirty, T);
+        if (mmid) apply_class<64>(g, k, part, conn, wdst, mmid, v, to, mvto, h, dirty, T);
     }
     if (use_lds) {
         __syncthreads();
@@ -476,15 +509,22 @@ __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, int32_t k, int32_
 // is still its source block here).
 __global__ __launch_bounds__(kBlock) void k_apply_hub(GraphView g, int32_t k, const int32_t *part,
                                                        int32_t *conn, const int32_t *mvto,
-                                                       HubView h)
+                                                       HubView h, const unsigned long long *counters,
+                                                       int64_t dirty_threshold, uint8_t *dirty,
+                                                       int T)
 {
     const HubChunk c = h.chunks[blockIdx.x];
     const int64_t v = h.ids[c.hub];
     const int32_t b = mvto[v];
     if (b < 0) return;
+    if ((int64_t)counters[CNT_MOVED_DEG] > dirty_threshold) {
+        for (int64_t e = c.e0 + threadIdx.x; e < c.e1; e += kBlock) dirty[g.adjncy[e] / T] = 1;
+        return;
+    }
     const int32_t a = part[v];
     for (int64_t e = c.e0 + threadIdx.x; e < c.e1; e += kBlock) {
         const int64_t u = g.adjncy[e];
+        if (is_hub(h, u)) continue;
         const int32_t w = edge_weight(g, e);
         atomicAdd(&conn[u * k + a], -w);
         atomicAdd(&conn[u * k + b], w);
@@ -509,21 +549,32 @@ __global__ void k_apply_hub_final(GraphView g, int32_t *part, int64_t *W, int32_
 
 hipError_t launch_apply(const GraphView &g, int32_t k, int32_t *part, int32_t *conn, int64_t *W,
                         int32_t *mvto, int64_t low_t, int64_t hub_t, const HubView &h,
-                        hipStream_t s)
+                        const unsigned long long *counters, int64_t dirty_threshold,
+                        uint8_t *dirty, hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
+    const int T = gain_tile_nodes(k);
     const size_t lds = k <= 2048 ? (size_t)k * 8 : 0;
+    hipError_t e;
+    if (h.nh > 0) {  // hub degrees join the moved-degree sum first
+        hipLaunchKernelGGL(k_hub_moved_deg, dim3((h.nh + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                           g, mvto, h, (unsigned long long *)counters);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_apply, dim3(grid_cap(g.n, kBlock, 4096)), dim3(kBlock), lds, s, g, k, part,
-                       conn, W, mvto, low_t, hub_t);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || h.nh <= 0) return e;
-    hipLaunchKernelGGL(k_apply_hub, dim3((unsigned)h.nchunks), dim3(kBlock), 0, s, g, k, part, conn,
-                       mvto, h);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_apply_hub_final, dim3((h.nh + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g,
-                       part, W, mvto, h);
-    return hipGetLastError();
+                       conn, W, mvto, low_t, hub_t, h, counters, dirty_threshold, dirty, T);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (h.nh > 0) {
+        hipLaunchKernelGGL(k_apply_hub, dim3((unsigned)h.nchunks), dim3(kBlock), 0, s, g, k, part,
+                           conn, mvto, h, counters, dirty_threshold, dirty, T);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_apply_hub_final, dim3((h.nh + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                           s, g, part, W, mvto, h);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    // rebuild the marked tiles (none are marked in the delta mode)
+    if ((e = launch_gain_tile(g, k, part, conn, hub_t, dirty, s)) != hipSuccess) return e;
+    return launch_rebuild_hub_rows(g, k, part, conn, h, s);
 }
 
 // ----------------------------------------------------------------- stats --

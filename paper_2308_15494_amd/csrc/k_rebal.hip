@@ -81,7 +81,7 @@ hipError_t launch_rb_begin(int32_t k, const int64_t *W, int64_t lmax, const Reba
 
 // ---------------------------------------------------------------- prepare --
 
-constexpr int kHistLdsBytes = 32768;
+constexpr int kHistLdsBytes = 49152;
 
 __device__ __forceinline__ bool in_overloaded(const RebalWs &r, int32_t k, int32_t a, int64_t lmax)
 {
@@ -96,13 +96,13 @@ template <int G, int V>
 __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, int32_t k,
                                                         const int32_t *__restrict__ part,
                                                         const int32_t *__restrict__ conn,
-                                                        int64_t lmax, RebalWs r)
+                                                        int64_t lmax, RebalWs r, int hist32)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     int64_t *sW = (int64_t *)lds_raw;
     const bool w_lds = (size_t)k * 8 <= 16384;
-    const bool h_lds = (size_t)k * kRbBuckets * 8 <= kHistLdsBytes;
-    int64_t *sH = sW + (w_lds ? k : 0);
+    const bool h_lds = hist32 && (size_t)k * kRbBuckets * 4 <= kHistLdsBytes;
+    uint32_t *sH = (uint32_t *)(sW + (w_lds ? k : 0));
     if (w_lds)
         for (int j = threadIdx.x; j < k; j += kBlock) sW[j] = r.W0[j];
     if (h_lds)
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, int32_t k,
                 }
             }
             if (h_lds) {
-                if (push) atomicAdd((unsigned long long *)&sH[hkey], (unsigned long long)cv);
+                if (push) atomicAdd(&sH[hkey], (uint32_t)cv);
             } else {
                 wave_hist_add(r.hist_src, hkey, cv, push);
             }
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, int32_t k,
     if (h_lds) {
         __syncthreads();
         for (int j = threadIdx.x; j < k * kRbBuckets; j += kBlock)
-            if (sH[j]) atomic_add_i64(&r.hist_src[j], sH[j]);
+            if (sH[j]) atomic_add_i64(&r.hist_src[j], (int64_t)sH[j]);
     }
 }
 
@@ -210,54 +210,60 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, int32_t k,
 
 // Source: first bucket whose cumulative weight covers the excess.
 // Target: first bucket whose cumulative weight exceeds the capacity.
-// Rows are cleared after reading. Also resets the per-sub-iteration move
-// counters (their previous users have finished).
-__global__ void k_rb_cutoffs(int32_t k, int64_t lmax, RebalWs r, int target_side,
-                             unsigned long long *counters)
+// One wave per block: each lane holds buckets lane and lane + 64, a wave scan
+// gives the cumulative weights. Rows are cleared after reading. The source
+// pass also resets the sub-iteration's move counter.
+__global__ __launch_bounds__(kBlock) void k_rb_cutoffs(int32_t k, int64_t lmax, RebalWs r,
+                                                        int target_side,
+                                                        unsigned long long *counters)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (!target_side && j == 0) counters[CNT_MOVED_NOW] = 0;
-    if (j >= k) return;
-    int64_t *h = (target_side ? r.hist_tgt : r.hist_src) + (int64_t)j * kRbBuckets;
+    const int j = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = lane_id();
+    if (!target_side && j == 0 && lane == 0) {
+        counters[CNT_MOVED_NOW] = 0;
+        counters[CNT_MOVED_DEG] = 0;
+    }
+    if (j >= k) return;  // wave-uniform
     const int64_t w0 = r.W0[j];
+    if (!target_side ? (w0 <= lmax) : (w0 > lmax)) {
+        // not a source / not a target: the row was never filled
+        if (lane == 0) {
+            if (!target_side) r.cbeta_src[j] = kRbBuckets;
+            else r.cbeta_tgt[j] = kRbBuckets;
+        }
+        return;
+    }
+    int64_t *h = (target_side ? r.hist_tgt : r.hist_src) + (int64_t)j * kRbBuckets;
+    const int64_t limit = !target_side ? w0 - lmax : lmax - w0;  // excess or capacity
+    const int b1 = lane + 64;
+    const int64_t x0 = h[lane];
+    const int64_t x1 = b1 < kRbBuckets ? h[b1] : 0;
+    if (x0) h[lane] = 0;
+    if (x1) h[b1] = 0;
+    const int64_t c0 = wave_incl_scan(x0);
+    const int64_t t0 = __shfl(c0, 63);
+    const int64_t c1 = t0 + wave_incl_scan(x1);
+    const bool h0 = !target_side ? c0 >= limit : c0 > limit;
+    const bool h1 = b1 < kRbBuckets && (!target_side ? c1 >= limit : c1 > limit);
+    const uint64_t m0 = __ballot(h0), m1 = __ballot(h1);
     int cut = kRbBuckets;
-    int64_t rest = 0;
-    if (!target_side) {
-        if (w0 <= lmax) {
-            r.cbeta_src[j] = kRbBuckets;
-            return;
-        }
-        const int64_t excess = w0 - lmax;
-        int64_t cum = 0;
-        for (int b = 0; b < kRbBuckets; ++b) {
-            const int64_t x = h[b];
-            if (x) h[b] = 0;
-            if (cut == kRbBuckets && cum + x >= excess) {
-                cut = b;
-                rest = excess - cum;
+    if (m0) cut = __ffsll((unsigned long long)m0) - 1;
+    else if (m1) cut = 64 + __ffsll((unsigned long long)m1) - 1;
+    if (cut < kRbBuckets) {
+        const bool mine = (cut < 64) ? lane == cut : lane == cut - 64;
+        if (mine) {
+            const int64_t before = (cut < 64) ? c0 - x0 : c1 - x1;
+            if (!target_side) {
+                r.cbeta_src[j] = cut;
+                r.need_src[j] = limit - before;
+            } else {
+                r.cbeta_tgt[j] = cut;
+                r.room_tgt[j] = limit - before;
             }
-            cum += x;
         }
-        r.cbeta_src[j] = cut;
-        r.need_src[j] = rest;
-    } else {
-        if (w0 > lmax) {  // an overloaded block is never a target
-            r.cbeta_tgt[j] = kRbBuckets;
-            return;
-        }
-        const int64_t cap = lmax - w0;
-        int64_t cum = 0;
-        for (int b = 0; b < kRbBuckets; ++b) {
-            const int64_t x = h[b];
-            if (x) h[b] = 0;
-            if (cut == kRbBuckets && cum + x > cap) {
-                cut = b;
-                rest = cap - cum;
-            }
-            cum += x;
-        }
-        r.cbeta_tgt[j] = cut;
-        r.room_tgt[j] = rest;
+    } else if (lane == 0) {
+        if (!target_side) r.cbeta_src[j] = kRbBuckets;
+        else r.cbeta_tgt[j] = kRbBuckets;
     }
 }
 
@@ -296,11 +302,12 @@ __global__ __launch_bounds__(kBlock) void k_rb_chunks(GraphView g, int32_t k, co
 
 // Selected nodes add their weight to their target's bucket histogram.
 __global__ __launch_bounds__(kBlock) void k_rb_tgt_hist(GraphView g, int32_t k, const int32_t *part,
-                                                         int64_t lmax, RebalWs r, RbView rv)
+                                                         int64_t lmax, RebalWs r, RbView rv,
+                                                         int hist32)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    int64_t *sH = (int64_t *)lds_raw;
-    const bool h_lds = (size_t)k * kRbBuckets * 8 <= kHistLdsBytes;
+    uint32_t *sH = (uint32_t *)lds_raw;
+    const bool h_lds = hist32 && (size_t)k * kRbBuckets * 4 <= kHistLdsBytes;
     if (h_lds) {
         for (int j = threadIdx.x; j < k * kRbBuckets; j += kBlock) sH[j] = 0;
         __syncthreads();
@@ -320,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_tgt_hist(GraphView g, int32_t k, 
             }
         }
         if (h_lds) {
-            if (sel) atomicAdd((unsigned long long *)&sH[hkey], (unsigned long long)cv);
+            if (sel) atomicAdd(&sH[hkey], (uint32_t)cv);
         } else {
             wave_hist_add(r.hist_tgt, hkey, cv, sel);
         }
@@ -328,7 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_tgt_hist(GraphView g, int32_t k, 
     if (h_lds) {
         __syncthreads();
         for (int j = threadIdx.x; j < k * kRbBuckets; j += kBlock)
-            if (sH[j]) atomic_add_i64(&r.hist_tgt[j], sH[j]);
+            if (sH[j]) atomic_add_i64(&r.hist_tgt[j], (int64_t)sH[j]);
     }
 }
 
@@ -357,31 +364,34 @@ __global__ __launch_bounds__(kBlock) void k_rb_theta(GraphView g, int32_t k, con
     }
     if (cb >= kRbBuckets) return;
     int64_t *row = (target_side ? r.chunk_tgt : r.chunk_src) + (int64_t)j * r.nchunks;
-    // reached(x): source x >= need, target x > room
+    // reached(x): source x >= need, target x > room. Each thread owns a run
+    // of consecutive chunks (reads and clears them); one block scan of the
+    // run totals locates the chunk where the bound is first reached.
     if (threadIdx.x == 0) {
         found_lds[0] = -1;
         found_lds[1] = 0;
     }
-    __syncthreads();
-    int64_t base = 0;
-    for (int64_t c0 = 0; c0 < r.nchunks; c0 += kBlock) {
-        const int64_t c = c0 + threadIdx.x;
-        int64_t x = 0;
-        if (c < r.nchunks) {
-            x = row[c];
-            if (x) row[c] = 0;
+    const int64_t per = (r.nchunks + kBlock - 1) / kBlock;
+    const int64_t c_lo = threadIdx.x * per;
+    const int64_t c_hi = (c_lo + per) < r.nchunks ? (c_lo + per) : r.nchunks;
+    int64_t run_sum = 0;
+    for (int64_t c = c_lo; c < c_hi; ++c) run_sum += row[c];
+    int64_t total;
+    const int64_t incl = block_incl_scan(run_sum, scan_lds, &total);
+    int64_t cum = incl - run_sum;
+    for (int64_t c = c_lo; c < c_hi; ++c) {
+        const int64_t x = row[c];
+        if (x) {
+            row[c] = 0;
+            const int64_t nxt = cum + x;
+            const bool reach = target_side ? (nxt > limit) : (nxt >= limit);
+            const bool before = target_side ? (cum > limit) : (cum >= limit);
+            if (reach && !before) {
+                found_lds[0] = c;
+                found_lds[1] = cum;
+            }
+            cum = nxt;
         }
-        int64_t total;
-        const int64_t inc = block_incl_scan(x, scan_lds, &total);
-        const int64_t cum = base + inc;
-        const bool hit = c < r.nchunks && x > 0 &&
-                         (target_side ? (cum > limit) : (cum >= limit)) &&
-                         !(target_side ? (cum - x > limit) : (cum - x >= limit));
-        if (hit) {
-            found_lds[0] = c;       // unique: the first chunk where the bound is reached
-            found_lds[1] = cum - x; // weight before this chunk
-        }
-        base += total;
     }
     __syncthreads();
     const int64_t chunk = found_lds[0];
@@ -432,10 +442,14 @@ __global__ __launch_bounds__(kBlock) void k_rb_theta(GraphView g, int32_t k, con
 // Accepted nodes get mvto[v] = target; counts per workgroup.
 __global__ __launch_bounds__(kBlock) void k_rb_moves(GraphView g, int32_t k, const int32_t *part,
                                                       int64_t lmax, RebalWs r, RbView rv,
-                                                      int32_t *mvto, unsigned long long *counters)
+                                                      int32_t *mvto, int64_t hub_t,
+                                                      unsigned long long *counters)
 {
-    __shared__ unsigned long long moved;
-    if (threadIdx.x == 0) moved = 0;
+    __shared__ unsigned long long moved, mdeg;
+    if (threadIdx.x == 0) {
+        moved = 0;
+        mdeg = 0;
+    }
     __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < g.n;
@@ -449,6 +463,8 @@ __global__ __launch_bounds__(kBlock) void k_rb_moves(GraphView g, int32_t k, con
                 if (rb_accepted(rv, v, a, j)) {
                     mvto[v] = j;
                     acc = true;
+                    const int64_t deg = g.xadj[v + 1] - g.xadj[v];
+                    if (deg <= hub_t) atomicAdd(&mdeg, (unsigned long long)deg);  // hubs: apply
                 }
             }
         }
@@ -458,26 +474,30 @@ __global__ __launch_bounds__(kBlock) void k_rb_moves(GraphView g, int32_t k, con
     if (threadIdx.x == 0 && moved) {
         atomicAdd(&counters[CNT_MOVED_NOW], moved);
         atomicAdd(&counters[CNT_REBAL_MOVES], moved);
+        atomicAdd(&counters[CNT_MOVED_DEG], mdeg);
     }
 }
 
 // --------------------------------------------------------------- sequence --
 
+int rb_scan_grid(int64_t n) { return grid_cap(n, kBlock, 4096); }
+
 hipError_t launch_rb_iteration(const GraphView &g, int32_t k, const int32_t *part,
                                const int32_t *conn, int64_t lmax, const RebalWs &r,
-                               int32_t *mvto, unsigned long long *counters, hipStream_t s)
+                               int32_t *mvto, int hist32, int64_t hub_t,
+                               unsigned long long *counters, hipStream_t s)
 {
     hipError_t e;
     const RbView rv{r.rtgt, r.rbeta, r.W0, r.cbeta_src, r.theta_src, r.cbeta_tgt, r.theta_tgt};
-    const int lg = grid_cap(g.n, kBlock, 4096);
-    const bool h_lds = (size_t)k * kRbBuckets * 8 <= kHistLdsBytes;
+    const int lg = rb_scan_grid(g.n);
+    const bool h_lds = hist32 && (size_t)k * kRbBuckets * 4 <= kHistLdsBytes;
     const size_t plds = ((size_t)k * 8 <= 16384 ? (size_t)k * 8 : 0) +
-                        (h_lds ? (size_t)k * kRbBuckets * 8 : 0);
+                        (h_lds ? (size_t)k * kRbBuckets * 4 : 0);
     const bool vec = (k % 4) == 0;
     const int nvec = vec ? k / 4 : k;
 #define UPR_RP(GG, VV)                                                                          \
     hipLaunchKernelGGL((k_rb_prepare<GG, VV>), dim3(lg), dim3(kBlock), plds, s, g, k, part, conn, \
-                       lmax, r)
+                       lmax, r, hist32)
     if (vec) {
         if (nvec <= 1) UPR_RP(1, 4);
         else if (nvec <= 2) UPR_RP(2, 4);
@@ -496,15 +516,15 @@ hipError_t launch_rb_iteration(const GraphView &g, int32_t k, const int32_t *par
     }
 #undef UPR_RP
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const dim3 kg((k + kBlock - 1) / kBlock);
+    const dim3 kg((k + 3) / 4);  // one wave per block
     hipLaunchKernelGGL(k_rb_cutoffs, kg, dim3(kBlock), 0, s, k, lmax, r, 0, counters);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rb_chunks, dim3(lg), dim3(kBlock), 0, s, g, k, part, lmax, r, rv, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rb_theta, dim3(k), dim3(kBlock), 0, s, g, k, part, lmax, r, rv, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rb_tgt_hist, dim3(lg), dim3(kBlock), h_lds ? (size_t)k * kRbBuckets * 8 : 0,
-                       s, g, k, part, lmax, r, rv);
+    hipLaunchKernelGGL(k_rb_tgt_hist, dim3(lg), dim3(kBlock), h_lds ? (size_t)k * kRbBuckets * 4 : 0,
+                       s, g, k, part, lmax, r, rv, hist32);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rb_cutoffs, kg, dim3(kBlock), 0, s, k, lmax, r, 1, counters);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -513,7 +533,7 @@ hipError_t launch_rb_iteration(const GraphView &g, int32_t k, const int32_t *par
     hipLaunchKernelGGL(k_rb_theta, dim3(k), dim3(kBlock), 0, s, g, k, part, lmax, r, rv, 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rb_moves, dim3(lg), dim3(kBlock), 0, s, g, k, part, lmax, r, rv, mvto,
-                       counters);
+                       hub_t, counters);
     return hipGetLastError();
 }
 

@@ -217,9 +217,9 @@ __device__ __forceinline__ int upper_index(const int32_t *a, int cnt, int32_t p)
 // back as one contiguous span. Hub rows are written as zeros here and filled
 // by k_gain_hub.
 template <bool WEIGHTED>
-__global__ __launch_bounds__(kBlock) void k_gain_tile(GraphView g, int32_t k, int T,
-                                                       const int32_t *__restrict__ part,
-                                                       int32_t *__restrict__ conn, int64_t hub_t)
+__device__ __forceinline__ void gain_tile_body(const GraphView &g, int32_t k, int T,
+                                               const int32_t *__restrict__ part,
+                                               int32_t *__restrict__ conn, int64_t hub_t)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     int32_t *tile = (int32_t *)lds_raw;
@@ -259,16 +259,30 @@ __global__ __launch_bounds__(kBlock) void k_gain_tile(GraphView g, int32_t k, in
     if (tid == 0) vstart[nt] = run;
     __syncthreads();
 
+    // kUnroll independent edges per thread and step, so that their loads
+    // (adjncy, then the part gathers) are in flight together
+    constexpr int kUnroll = 4;
     const int32_t E = run;
-    for (int32_t p = tid; p < E; p += kBlock) {
-        const int node = upper_index(vstart, nt, p);
-        const int64_t e = gstart[node] + (p - vstart[node]);
-        const int32_t u = g.adjncy[e];
-        const int32_t pu = part[u];
-        if ((unsigned)pu < (unsigned)k) {
-            const int32_t w = WEIGHTED ? g.adjwgt[e] : 1;
-            atomicAdd(&tile[node * k + pu], w);
+    for (int32_t p0 = tid; p0 < E; p0 += kBlock * kUnroll) {
+        int node[kUnroll];
+        int64_t e[kUnroll];
+        int32_t u[kUnroll], w[kUnroll], pu[kUnroll];
+#pragma unroll
+        for (int i = 0; i < kUnroll; ++i) {
+            const int32_t p = p0 + i * kBlock;
+            node[i] = p < E ? upper_index(vstart, nt, p) : -1;
+            e[i] = node[i] >= 0 ? gstart[node[i]] + (p - vstart[node[i]]) : 0;
         }
+#pragma unroll
+        for (int i = 0; i < kUnroll; ++i) {
+            u[i] = node[i] >= 0 ? g.adjncy[e[i]] : 0;
+            w[i] = (WEIGHTED && node[i] >= 0) ? g.adjwgt[e[i]] : 1;
+        }
+#pragma unroll
+        for (int i = 0; i < kUnroll; ++i) pu[i] = node[i] >= 0 ? part[u[i]] : -1;
+#pragma unroll
+        for (int i = 0; i < kUnroll; ++i)
+            if ((unsigned)pu[i] < (unsigned)k) atomicAdd(&tile[node[i] * k + pu[i]], w[i]);
     }
     __syncthreads();
 
@@ -286,19 +300,49 @@ __global__ __launch_bounds__(kBlock) void k_gain_tile(GraphView g, int32_t k, in
     }
 }
 
+template <bool WEIGHTED>
+__global__ __launch_bounds__(kBlock) void k_gain_tile(GraphView g, int32_t k, int T,
+                                                       const int32_t *__restrict__ part,
+                                                       int32_t *__restrict__ conn, int64_t hub_t)
+{
+    gain_tile_body<WEIGHTED>(g, k, T, part, conn, hub_t);
+}
+
+// Same tiles, rebuilt only where a flag is set (flags are cleared).
+template <bool WEIGHTED>
+__global__ __launch_bounds__(kBlock) void k_gain_refresh(GraphView g, int32_t k, int T,
+                                                          const int32_t *__restrict__ part,
+                                                          int32_t *__restrict__ conn,
+                                                          int64_t hub_t, uint8_t *dirty)
+{
+    if (!dirty[blockIdx.x]) return;
+    __syncthreads();
+    if (threadIdx.x == 0) dirty[blockIdx.x] = 0;
+    gain_tile_body<WEIGHTED>(g, k, T, part, conn, hub_t);
+}
+
 hipError_t launch_gain_tile(const GraphView &g, int32_t k, const int32_t *part, int32_t *conn,
-                            int64_t hub_t, hipStream_t s)
+                            int64_t hub_t, uint8_t *dirty, hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
     const int T = gain_tile_nodes(k);
     const int64_t tiles = (g.n + T - 1) / T;
     const size_t lds = gain_tile_lds(k, T);
-    if (g.adjwgt)
-        hipLaunchKernelGGL(k_gain_tile<true>, dim3((unsigned)tiles), dim3(kBlock), lds, s, g, k, T,
-                           part, conn, hub_t);
-    else
-        hipLaunchKernelGGL(k_gain_tile<false>, dim3((unsigned)tiles), dim3(kBlock), lds, s, g, k,
-                           T, part, conn, hub_t);
+    if (dirty) {
+        if (g.adjwgt)
+            hipLaunchKernelGGL(k_gain_refresh<true>, dim3((unsigned)tiles), dim3(kBlock), lds, s, g,
+                               k, T, part, conn, hub_t, dirty);
+        else
+            hipLaunchKernelGGL(k_gain_refresh<false>, dim3((unsigned)tiles), dim3(kBlock), lds, s, g,
+                               k, T, part, conn, hub_t, dirty);
+    } else {
+        if (g.adjwgt)
+            hipLaunchKernelGGL(k_gain_tile<true>, dim3((unsigned)tiles), dim3(kBlock), lds, s, g, k,
+                               T, part, conn, hub_t);
+        else
+            hipLaunchKernelGGL(k_gain_tile<false>, dim3((unsigned)tiles), dim3(kBlock), lds, s, g, k,
+                               T, part, conn, hub_t);
+    }
     return hipGetLastError();
 }
 
@@ -324,6 +368,37 @@ __global__ __launch_bounds__(kBlock) void k_gain_hub(GraphView g, int32_t k,
     int32_t *dst = conn + v * (int64_t)k;
     for (int j = threadIdx.x; j < k; j += kBlock)
         if (row[j]) atomicAdd(&dst[j], row[j]);
+}
+
+__global__ void k_zero_hub_rows(int32_t k, int32_t *conn, HubView h)
+{
+    int32_t *row = conn + (int64_t)h.ids[blockIdx.x] * k;
+    for (int j = threadIdx.x; j < k; j += kBlock) row[j] = 0;
+}
+
+__global__ void k_hub_bits(HubView h, uint32_t *bits)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= h.nh) return;
+    const int32_t v = h.ids[i];
+    atomicOr(&bits[v >> 5], 1u << (v & 31));
+}
+
+hipError_t launch_hub_bits(const HubView &h, uint32_t *bits, hipStream_t s)
+{
+    if (h.nh <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hub_bits, dim3((h.nh + kBlock - 1) / kBlock), dim3(kBlock), 0, s, h, bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_rebuild_hub_rows(const GraphView &g, int32_t k, const int32_t *part,
+                                   int32_t *conn, const HubView &h, hipStream_t s)
+{
+    if (h.nh <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_hub_rows, dim3(h.nh), dim3(kBlock), 0, s, k, conn, h);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_gain_hub(g, k, part, conn, h, s);
 }
 
 hipError_t launch_gain_hub(const GraphView &g, int32_t k, const int32_t *part, int32_t *conn,

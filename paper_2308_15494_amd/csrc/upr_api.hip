@@ -54,6 +54,7 @@ struct upr_ctx {
     int64_t *key = nullptr, *pen = nullptr;
     uint8_t *accflag = nullptr;
     int32_t *mvto = nullptr;     // [n] pending move target, -1 = none
+    uint8_t *dirty = nullptr;    // [n] gain-table tiles to rebuild
     int64_t *bucket = nullptr, *penq = nullptr;
     int64_t *pen1 = nullptr;     // [k] unit-weight penalty per target block
     unsigned long long *counters = nullptr;
@@ -74,11 +75,13 @@ struct upr_plan {
     HubChunk *chunks = nullptr;
     int64_t nchunks = 0;
     int64_t *gacc = nullptr;
+    uint32_t *hub_bits = nullptr;  // [ceil(n/32)]
     int64_t hub_t = kDefaultHubThreshold, low_t = kDefaultLowThreshold;
+    int64_t dirty_threshold = 0;  // moved-degree sum above which tiles are rebuilt
 
     HubView hubs() const
     {
-        return HubView{nh, hub_ids, chunks, nchunks, gacc};
+        return HubView{nh, hub_ids, chunks, nchunks, gacc, hub_bits};
     }
 };
 
@@ -123,6 +126,7 @@ void free_workspace(upr_ctx *c)
     dfree(c->pen);
     dfree(c->accflag);
     dfree(c->mvto);
+    dfree(c->dirty);
     dfree(c->bucket);
     dfree(c->pen1);
     dfree(c->rb.rtgt);
@@ -151,6 +155,7 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
     free_workspace(c);
     bool ok = dalloc(&c->key, N) == hipSuccess && dalloc(&c->pen, N) == hipSuccess &&
               dalloc(&c->accflag, N) == hipSuccess && dalloc(&c->mvto, N) == hipSuccess &&
+              dalloc(&c->dirty, N) == hipSuccess &&
               dalloc(&c->bucket, K * kSlots) == hipSuccess && dalloc(&c->pen1, K) == hipSuccess &&
               dalloc(&c->rb.rtgt, N) == hipSuccess && dalloc(&c->rb.rbeta, N) == hipSuccess &&
               dalloc(&c->rb.W0, K) == hipSuccess &&
@@ -173,6 +178,7 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
     HIP_TRY(c, hipMemset(c->rb.chunk_tgt, 0, sizeof(int64_t) * kChunkEntries));
     HIP_TRY(c, hipMemset(c->key, 0xff, sizeof(int64_t) * N));
     HIP_TRY(c, hipMemset(c->mvto, 0xff, sizeof(int32_t) * N));
+    HIP_TRY(c, hipMemset(c->dirty, 0, N));
     HIP_TRY(c, hipDeviceSynchronize());
     c->cap_n = N;
     c->cap_k = K;
@@ -268,6 +274,12 @@ int rebalance_loop(upr_ctx *c, const upr_plan *p, int32_t k, int32_t *part, int3
 {
     const HubView h = p->hubs();
     int64_t iters = 0, status = 0;
+    // 32-bit per-workgroup histograms are exact when no workgroup can add up
+    // 2^32 of node weight: nodes scanned per workgroup times the largest c(v)
+    const int64_t per_wg = ((p->g.n + (int64_t)rb_scan_grid(p->g.n) * kBlock - 1) /
+                            ((int64_t)rb_scan_grid(p->g.n) * kBlock)) * kBlock;
+    const int hist32 = (unsigned __int128)per_wg * (uint64_t)std::max<int64_t>(p->maxvw, 1) <
+                       ((unsigned __int128)1 << 32);
     c->rb_dirty = true;
     HIP_TRY(c, launch_rb_begin(k, W, lmax, c->rb, c->counters, s));
     int rc = sync_counters(c, s);
@@ -284,8 +296,10 @@ int rebalance_loop(upr_ctx *c, const upr_plan *p, int32_t k, int32_t *part, int3
             break;
         }
         ++iters;
-        HIP_TRY(c, launch_rb_iteration(p->g, k, part, conn, lmax, c->rb, c->mvto, c->counters, s));
-        HIP_TRY(c, launch_apply(p->g, k, part, conn, W, c->mvto, p->low_t, p->hub_t, h, s));
+        HIP_TRY(c, launch_rb_iteration(p->g, k, part, conn, lmax, c->rb, c->mvto, hist32, p->hub_t,
+                                       c->counters, s));
+        HIP_TRY(c, launch_apply(p->g, k, part, conn, W, c->mvto, p->low_t, p->hub_t, h, c->counters,
+                                p->dirty_threshold, c->dirty, s));
         HIP_TRY(c, launch_rb_begin(k, W, lmax, c->rb, c->counters, s));
         rc = sync_counters(c, s);
         if (rc) return rc;
@@ -471,6 +485,9 @@ int upr_plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipStrea
     if (g.n > 0) {
         if (hipMemcpy(&p->nnz, g.xadj + g.n, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
             return bail(UPR_E_HIP, "reading xadj[n] failed");
+        // integer-atomic deltas cost about as much per moved edge as a
+        // rebuild costs per edge of the whole graph divided by this factor
+        p->dirty_threshold = p->nnz / std::max<int64_t>(env_int("UPR_DIRTY_DIV", 8), 1);
         if (dalloc(&p->wdeg, g.n) != hipSuccess || dalloc(&hub_list, g.n) != hipSuccess)
             return bail(UPR_E_NOMEM, "plan allocation failed");
         unsigned long long zero[8] = {0}, res[8];
@@ -508,9 +525,14 @@ int upr_plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipStrea
                 for (int64_t e = e01[2 * i]; e < e01[2 * i + 1]; e += kHubChunkEdges)
                     chunks.push_back(HubChunk{i, 0, e, std::min(e + kHubChunkEdges, e01[2 * i + 1])});
             p->nchunks = (int64_t)chunks.size();
-            if (dalloc(&p->chunks, p->nchunks) != hipSuccess) return bail(UPR_E_NOMEM, "plan allocation failed");
+            const int64_t words = (g.n + 31) / 32;
+            if (dalloc(&p->chunks, p->nchunks) != hipSuccess || dalloc(&p->hub_bits, words) != hipSuccess)
+                return bail(UPR_E_NOMEM, "plan allocation failed");
+            if (hipMemset(p->hub_bits, 0, sizeof(uint32_t) * words) != hipSuccess)
+                return bail(UPR_E_HIP, "hub bitmap clear failed");
             ok = hipMemcpy(p->chunks, chunks.data(), sizeof(HubChunk) * chunks.size(), hipMemcpyHostToDevice) == hipSuccess &&
                  launch_fill_i64(p->gacc, p->nh, 0, s) == hipSuccess &&
+                 launch_hub_bits(p->hubs(), p->hub_bits, s) == hipSuccess &&
                  hipStreamSynchronize(s) == hipSuccess;
             if (!ok) return bail(UPR_E_HIP, "hub preparation failed");
         }
@@ -529,6 +551,7 @@ void upr_plan_destroy(upr_plan *p)
     dfree(p->hub_ids);
     dfree(p->chunks);
     dfree(p->gacc);
+    dfree(p->hub_bits);
     delete p;
 }
 
@@ -558,7 +581,7 @@ int upr_gain_table(upr_ctx *c, const upr_plan *p, int32_t k, const int32_t *part
     if (rc) return rc;
     if (c->pinned[CNT_BAD_INPUT]) return fail(c, UPR_E_ARG, "part holds values outside [0, k)");
     PhaseTimer t(c, 0, s);
-    HIP_TRY(c, launch_gain_tile(p->g, k, part, conn, p->hub_t, s));
+    HIP_TRY(c, launch_gain_tile(p->g, k, part, conn, p->hub_t, nullptr, s));
     HIP_TRY(c, launch_gain_hub(p->g, k, part, conn, p->hubs(), s));
     return UPR_OK;
 }
@@ -622,7 +645,7 @@ static int round_common(upr_ctx *c, const upr_plan *p, const upr_params *q, int3
     if (q->rebuild_table) {
         {
             PhaseTimer t(c, 0, s);
-            HIP_TRY(c, launch_gain_tile(p->g, k, part, conn, p->hub_t, s));
+            HIP_TRY(c, launch_gain_tile(p->g, k, part, conn, p->hub_t, nullptr, s));
         }
         if (p->nh > 0) {
             PhaseTimer t(c, 1, s);
@@ -651,7 +674,8 @@ static int round_common(upr_ctx *c, const upr_plan *p, const upr_params *q, int3
         }
         {
             PhaseTimer t(c, 4, s);
-            HIP_TRY(c, launch_apply(p->g, k, part, conn, W, c->mvto, p->low_t, p->hub_t, h, s));
+            HIP_TRY(c, launch_apply(p->g, k, part, conn, W, c->mvto, p->low_t, p->hub_t, h,
+                                    c->counters, p->dirty_threshold, c->dirty, s));
         }
         {
             PhaseTimer t(c, 6, s);

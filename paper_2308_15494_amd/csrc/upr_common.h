@@ -29,6 +29,7 @@ enum Counter {
     CNT_OVER,          // number of overloaded blocks
     CNT_BAD_INPUT,     // nonzero: a part value was out of range
     CNT_TMP,           // scratch accumulator for standalone calls
+    CNT_MOVED_DEG,     // sum of the degrees of the nodes marked to move
     CNT_COUNT = 32
 };
 
@@ -57,7 +58,13 @@ struct HubView {
     const HubChunk *chunks;
     int64_t nchunks;
     int64_t *gacc;        // [nh] filter gain accumulator
+    const uint32_t *bits; // [ceil(n/32)] bit v set iff v is a hub
 };
+
+__device__ __forceinline__ bool is_hub(const HubView &h, int64_t u)
+{
+    return h.nh > 0 && ((h.bits[u >> 5] >> (u & 31)) & 1u);
+}
 
 // ---------------------------------------------------------------- device --
 
@@ -256,10 +263,16 @@ hipError_t launch_hub_ranges(const int64_t *xadj, const int32_t *ids, int32_t nh
 
 // table (S1)
 int gain_tile_nodes(int32_t k);
+// With dirty != null only tiles whose flag is set are rebuilt (flags are
+// cleared).
 hipError_t launch_gain_tile(const GraphView &g, int32_t k, const int32_t *part, int32_t *conn,
-                            int64_t hub_t, hipStream_t s);
+                            int64_t hub_t, uint8_t *dirty, hipStream_t s);
 hipError_t launch_gain_hub(const GraphView &g, int32_t k, const int32_t *part, int32_t *conn,
                            const HubView &h, hipStream_t s);
+// Zero the hub rows and accumulate them again from the hubs' edge chunks.
+hipError_t launch_rebuild_hub_rows(const GraphView &g, int32_t k, const int32_t *part,
+                                   int32_t *conn, const HubView &h, hipStream_t s);
+hipError_t launch_hub_bits(const HubView &h, uint32_t *bits, hipStream_t s);
 // Per node: 2*cut into counters[cut_slot], penalty buckets of the available
 // nodes (bucket may be null), block weights W[part] += c (W may be null).
 hipError_t launch_node_stats(const GraphView &g, int32_t k, const int32_t *part,
@@ -292,9 +305,14 @@ hipError_t launch_filter_hub(const GraphView &g, const int32_t *part, const int6
                              const int64_t *pen, const HubView &h, int32_t *mvto,
                              uint8_t *accflag, unsigned long long *counters, hipStream_t s);
 // Apply every move recorded in mvto (target block, -1 = none) and clear it.
+// If the moving nodes' degrees sum to at most dirty_threshold
+// (counters[CNT_MOVED_DEG]) the neighbours' rows get integer-atomic deltas;
+// otherwise their gain-table tiles are marked and rebuilt from the new
+// partition. Hub rows are always rebuilt.
 hipError_t launch_apply(const GraphView &g, int32_t k, int32_t *part, int32_t *conn, int64_t *W,
                         int32_t *mvto, int64_t low_t, int64_t hub_t, const HubView &h,
-                        hipStream_t s);
+                        const unsigned long long *counters, int64_t dirty_threshold,
+                        uint8_t *dirty, hipStream_t s);
 hipError_t launch_stats_final(int64_t *stats, const unsigned long long *counters, int64_t lmax,
                               int64_t iters, int64_t status, hipStream_t s);
 hipError_t launch_export_moves(int64_t n, const int64_t *key, const int64_t *pen,
@@ -323,9 +341,12 @@ struct RebalWs {
 hipError_t launch_rb_begin(int32_t k, const int64_t *W, int64_t lmax, const RebalWs &r,
                            unsigned long long *counters, hipStream_t s);
 // One sub-iteration up to the move marks: targets and buckets, source and
-// target selection; accepted nodes get mvto[v] = target.
+// target selection; accepted nodes get mvto[v] = target. hist32: the
+// per-workgroup histograms may use 32-bit LDS counters (no overflow).
 hipError_t launch_rb_iteration(const GraphView &g, int32_t k, const int32_t *part,
                                const int32_t *conn, int64_t lmax, const RebalWs &r,
-                               int32_t *mvto, unsigned long long *counters, hipStream_t s);
+                               int32_t *mvto, int hist32, int64_t hub_t,
+                               unsigned long long *counters, hipStream_t s);
+int rb_scan_grid(int64_t n);
 
 }  // namespace upr

@@ -375,3 +375,19 @@ def test_rmat20_full_rounds(upr, ctx):
         say(f"rmat20 round {r}")
         ost, odbg = pr.round(eps=eps, tau=gg.tau_schedule(r, rounds))
         pr.compare(ost, odbg, f"rmat20 round {r}")
+
+
+@pytest.mark.parametrize("div", ["1", "100000000"], ids=["delta", "rebuild"])
+def test_apply_modes(upr, ctx, monkeypatch, div):
+    """Both ways of updating the table after moves (integer-atomic deltas, or
+    marking and rebuilding tiles) give the oracle's table."""
+    monkeypatch.setenv("UPR_DIRTY_DIV", div)
+    monkeypatch.setenv("UPR_HUB_THRESHOLD", "64")
+    for name, g, k in [("rmat", gg.rmat(12, 16, seed=31), 32),
+                       ("cl_w", gg.with_weights(gg.chung_lu(4000, 8.0, 2.1, seed=5), 5, 6, 3), 8),
+                       ("grid", gg.grid2d(50, 60), 16)]:
+        say(f"apply mode div={div} case={name}")
+        pr = Pair(upr, ctx, g, k, skewed_partition(g.n, k, 3, 0.35))
+        for r in range(1, 5):
+            ost, odbg = pr.round(tau=gg.tau_schedule(r, 4))
+            pr.compare(ost, odbg, f"{name} round {r}")
