@@ -45,12 +45,12 @@ class _Params(C.Structure):
     _fields_ = [("k", C.c_int32), ("eps_num", C.c_int32), ("eps_den", C.c_int32),
                 ("t_num", C.c_int32), ("t_den", C.c_int32), ("tau_num", C.c_int32),
                 ("tau_den", C.c_int32), ("mode", C.c_int32), ("rebuild_table", C.c_int32),
-                ("max_rebalance_iters", C.c_int32)]
+                ("max_rebalance_iters", C.c_int32), ("seq_penalty", C.c_int32)]
 
 
 class _Debug(C.Structure):
     _fields_ = [("target", C.c_void_p), ("score", C.c_void_p), ("pen", C.c_void_p),
-                ("accept", C.c_void_p)]
+                ("accept", C.c_void_p), ("pen_seq", C.c_void_p)]
 
 
 _lib = None
@@ -116,9 +116,9 @@ class Graph:
 
 
 def params(k, eps=(3, 100), t=(7, 10), tau=(1, 1), mode=0, rebuild_table=1,
-           max_rebalance_iters=0) -> _Params:
+           max_rebalance_iters=0, seq_penalty=1) -> _Params:
     return _Params(k, eps[0], eps[1], t[0], t[1], tau[0], tau[1], mode, rebuild_table,
-                   max_rebalance_iters)
+                   max_rebalance_iters, seq_penalty)
 
 
 def lmax(total, k, eps=(3, 100)):
@@ -199,9 +199,11 @@ def refine_round(g, p: _Params, part, conn=None, W=None, debug=False):
     dstruct = None
     if debug:
         dbg = dict(target=np.zeros(G.n, np.int32), score=np.zeros(G.n, np.int64),
-                   pen=np.zeros(G.n, np.int64), accept=np.zeros(G.n, np.uint8))
+                   pen=np.zeros(G.n, np.int64), accept=np.zeros(G.n, np.uint8),
+                   pen_seq=np.zeros(G.n, np.int64))
         dstruct = _Debug(dbg["target"].ctypes.data, dbg["score"].ctypes.data,
-                         dbg["pen"].ctypes.data, dbg["accept"].ctypes.data)
+                         dbg["pen"].ctypes.data, dbg["accept"].ctypes.data,
+                         dbg["pen_seq"].ctypes.data)
     rc = lib().orc_refine_round(C.byref(G.c), C.byref(p), part.ctypes.data, conn.ctypes.data,
                                 W.ctypes.data, stats.ctypes.data,
                                 C.byref(dstruct) if dstruct is not None else None)

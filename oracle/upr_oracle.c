@@ -31,8 +31,15 @@
  *   S3  conflict filter: order candidates by (s desc, id asc); for each
  *       candidate recompute a pessimistic gain assuming every earlier
  *       candidate neighbour ends in whichever of its two blocks is worse for
- *       this move; accept iff that gain * 2^16 - P > 0. Applying the accepted
- *       moves one by one in that order lowers the cut at every step.
+ *       this move (the candidate is eligible if that gain is > 0); with the
+ *       sequence-aware penalty, price the move against its target's weight
+ *       as changed by the eligible earlier candidates: plus those moving in,
+ *       minus those moving out unless they are available for rebalancing
+ *       (Section 5.3 prices a move by c(V_j + u) + c~_j when it is made, and
+ *       c~_j keeps the weight of available nodes that left; Lemma 1 sums
+ *       pen(u_i, V_1 + U^{i-1})); accept iff gain * 2^16 - P > 0.
+ *       Applying the accepted moves one by one in that order lowers the
+ *       cut at every step.
  *   S4  apply accepted moves; delta-update the gain table and block weights
  *   S5  rebalance (Section 7.1) in synchronous sub-iterations
  *   S6  final cut and statistics
@@ -63,6 +70,7 @@ typedef struct {
     int32_t mode;            /* 0 penalised, 1 constrained, 2 penalty-free */
     int32_t rebuild_table;   /* 1: conn and W are recomputed from part */
     int32_t max_rebalance_iters; /* 0: default */
+    int32_t seq_penalty;     /* 1: S3 re-prices moves with earlier candidates' inflow */
 } orc_params;
 
 /* Statistics, same order as the int64 slots the tests read. */
@@ -77,6 +85,7 @@ typedef struct {
     int64_t *score;   /* s(v, target) if candidate, else 0 */
     int64_t *pen;     /* P(v, target) if candidate, else 0 */
     uint8_t *accept;  /* 1 if the move survived the conflict filter */
+    int64_t *pen_seq; /* S3 penalty of a candidate (-1: forbidden), else 0 */
 } orc_debug;
 
 static int64_t edge_w(const orc_graph *g, int64_t e) { return g->adjwgt ? g->adjwgt[e] : 1; }
@@ -223,13 +232,16 @@ static int rb_cmp(const void *x, const void *y)
  *        g >  0: beta = S - 1 - slot(g * c(v), 1)
  *        g == 0: beta = S
  *        g <  0: beta = S + 1 + slot(-g, c(v))
- *  2. Each overloaded block a selects the minimal prefix of its movable
- *     nodes in (beta, id) order whose weight covers W[a] - L_max (all of
- *     them if they do not suffice).
+ *  2. Every movable node of an overloaded block is offered to its target.
  *  3. Each target j accepts the maximal prefix, in (beta, id) order, of the
- *     selected nodes aiming at it whose weight fits L_max - W[j].
- *  4. The accepted nodes move (as in S4). If nothing moved, stop stuck.
- * All of 1-3 read the sub-iteration's starting W and conn.
+ *     offers aimed at it whose weight fits L_max - W[j] (a target is never
+ *     overloaded, like the atomic weight check of Section 7.1).
+ *  4. Each source a keeps the minimal prefix, in (beta, id) order, of its
+ *     accepted nodes whose weight covers W[a] - L_max (all of them if they do
+ *     not suffice): like the priority queue, the cheapest nodes go first and
+ *     nodes of a block that is balanced again stay.
+ *  5. The kept nodes move (as in S4). If nothing moved, stop stuck.
+ * All of 1-4 read the sub-iteration's starting W and conn.
  */
 static int rebalance_iterate(const orc_graph *g, const orc_params *p, int64_t lmax, int32_t *part,
                              int32_t *conn, int64_t *W, int64_t *moves_out, int64_t *iters_out)
@@ -284,26 +296,12 @@ static int rebalance_iterate(const orc_graph *g, const orc_params *p, int64_t lm
                 beta[v] = ORC_SLOTS + 1 + orc_slot(-gain, cv);
         }
 
-        /* step 2: per overloaded source block, minimal covering prefix */
+        /* steps 2-3: every movable node is offered; per target, the maximal
+         * prefix within capacity is accepted */
+        int64_t moved_now = 0;
         int64_t cnt = 0;
         for (int64_t v = 0; v < n; ++v)
             if (tgt[v] >= 0) {
-                items[cnt].blk = part[v]; items[cnt].beta = beta[v];
-                items[cnt].id = v; items[cnt].c = node_c(g, v); ++cnt;
-            }
-        qsort(items, (size_t)cnt, sizeof(rb_item), rb_cmp);
-        for (int64_t i = 0; i < cnt;) {
-            int32_t a = items[i].blk;
-            int64_t need = W0[a] - lmax, got = 0;
-            for (; i < cnt && items[i].blk == a; ++i)
-                if (got < need) { sel[items[i].id] = 1; got += items[i].c; }
-        }
-
-        /* step 3: per target, maximal prefix within capacity */
-        int64_t moved_now = 0;
-        cnt = 0;
-        for (int64_t v = 0; v < n; ++v)
-            if (sel[v]) {
                 items[cnt].blk = tgt[v]; items[cnt].beta = beta[v];
                 items[cnt].id = v; items[cnt].c = node_c(g, v); ++cnt;
             }
@@ -315,11 +313,26 @@ static int rebalance_iterate(const orc_graph *g, const orc_params *p, int64_t lm
             for (; i < cnt && items[i].blk == j; ++i) {
                 if (full || used + items[i].c > cap) { full = 1; continue; }
                 used += items[i].c;
-                sel[items[i].id] = 2; /* accepted */
+                sel[items[i].id] = 1; /* accepted by its target */
             }
         }
 
-        /* step 4 */
+        /* step 4: per source, the minimal covering prefix of its accepted nodes */
+        cnt = 0;
+        for (int64_t v = 0; v < n; ++v)
+            if (sel[v]) {
+                items[cnt].blk = part[v]; items[cnt].beta = beta[v];
+                items[cnt].id = v; items[cnt].c = node_c(g, v); ++cnt;
+            }
+        qsort(items, (size_t)cnt, sizeof(rb_item), rb_cmp);
+        for (int64_t i = 0; i < cnt;) {
+            int32_t a = items[i].blk;
+            int64_t need = W0[a] - lmax, got = 0;
+            for (; i < cnt && items[i].blk == a; ++i)
+                if (got < need) { sel[items[i].id] = 2; got += items[i].c; }
+        }
+
+        /* step 5 */
         for (int64_t v = 0; v < n; ++v)
             if (sel[v] == 2) {
                 apply_move(g, k, part, conn, W, v, tgt[v]);
@@ -355,6 +368,40 @@ void orc_penalty_buckets(const orc_graph *g, int32_t k, const int32_t *part, con
         }
         if (avail) avail[v] = s + 1;
     }
+}
+
+/* Penalty of Section 5.3 for a node of weight cv whose move leaves its target
+ * with excess X = c(V_j + v) - L_max, given the target's bucket weights:
+ * 0 if X <= 0; otherwise constrained (mode 1): forbidden; penalty-free
+ * (mode 2): 0; penalised (mode 0): tau * (3/2)^l * c(v) in Q16 (saturated at
+ * 2^62) for the least slot l whose cumulative bucket weight covers X,
+ * forbidden if none. Returns 0 when the move is forbidden. */
+static int move_penalty(const int64_t *bucket_row, const int64_t *penq, int mode, int64_t X,
+                        int64_t cv, int64_t *P)
+{
+    *P = 0;
+    if (X <= 0 || mode == 2) return 1;
+    if (mode == 1) return 0;
+    int64_t acc = 0;
+    for (int i = 0; i < ORC_SLOTS; ++i) {
+        acc += bucket_row[i];
+        if (acc >= X) {
+            if (penq[i] != 0 && cv > ORC_PEN_CAP / penq[i]) *P = ORC_PEN_CAP;
+            else *P = penq[i] * cv;
+            if (*P > ORC_PEN_CAP) *P = ORC_PEN_CAP;
+            return 1;
+        }
+    }
+    return 0;
+}
+
+/* Candidate order of S3: score descending, then id ascending. */
+static const int64_t *cmp_score;
+static int cand_cmp(const void *x, const void *y)
+{
+    const int64_t u = *(const int64_t *)x, v = *(const int64_t *)y;
+    if (cmp_score[u] != cmp_score[v]) return cmp_score[u] > cmp_score[v] ? -1 : 1;
+    return u < v ? -1 : (u > v);
 }
 
 /* ------------------------------------------------------------- rounds -- */
@@ -399,7 +446,8 @@ int orc_refine_round(const orc_graph *g, const orc_params *p, int32_t *part, int
 
     /* S1b */
     int64_t *bucket = (int64_t *)calloc((size_t)k * ORC_SLOTS, sizeof(int64_t));
-    orc_penalty_buckets(g, k, part, conn, p->t_num, p->t_den, bucket, NULL);
+    int32_t *avail = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    orc_penalty_buckets(g, k, part, conn, p->t_num, p->t_den, bucket, avail);
 
     /* S2: best penalised move per node, against the round-start W. */
     int32_t *target = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
@@ -416,22 +464,9 @@ int orc_refine_round(const orc_graph *g, const orc_params *p, int32_t *part, int
             if (j == a || row[j] <= 0) continue;      /* adjacent blocks only */
             int64_t delta = (int64_t)row[j] - row[a];  /* gain of the move v -> j */
             int64_t excess = W[j] + cv - lmax;         /* c(V_j + v) - L_max */
-            int64_t P = 0;
-            if (excess > 0 && p->mode == 1) continue;  /* constrained: forbidden */
-            if (excess > 0 && p->mode == 0) {
-                /* minimal slot l with sum_{i<=l} c(B_{i,j}) >= excess */
-                int64_t acc = 0;
-                int l = -1;
-                for (int i = 0; i < ORC_SLOTS; ++i) {
-                    acc += bucket[(int64_t)j * ORC_SLOTS + i];
-                    if (acc >= excess) { l = i; break; }
-                }
-                if (l < 0) continue;                   /* no such slot: forbidden */
-                /* pen = tau * (3/2)^l * c(v), saturated */
-                if (penq[l] != 0 && cv > ORC_PEN_CAP / penq[l]) P = ORC_PEN_CAP;
-                else P = penq[l] * cv;
-                if (P > ORC_PEN_CAP) P = ORC_PEN_CAP;
-            }
+            int64_t P;
+            if (!move_penalty(bucket + (int64_t)j * ORC_SLOTS, penq, p->mode, excess, cv, &P))
+                continue;                              /* forbidden */
             int64_t s = delta * 65536 - P;
             if (best < 0 || s > best_s) { best = j; best_s = s; best_p = P; }
         }
@@ -447,11 +482,24 @@ int orc_refine_round(const orc_graph *g, const orc_params *p, int32_t *part, int
      * moving a -> b, f(x) = +1 if x == b, -1 if x == a, else 0 is the change
      * in v's internal edge weight contributed by a neighbour sitting in x.
      * An earlier candidate neighbour u (before v in the order) may or may
-     * not move; take the worse of its two positions. */
+     * not move; take the worse of its two positions. With the
+     * sequence-aware penalty, each block's weight is tracked along the
+     * order: an eligible candidate (pessimistic gain > 0) adds its weight to
+     * its target and, unless it is available for rebalancing, removes it
+     * from its own block; every move is priced against the weight reached
+     * before it. */
     uint8_t *accept = (uint8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
+    int64_t *pen_seq = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(candidates > 0 ? candidates : 1));
+    int64_t *net = (int64_t *)calloc((size_t)k, sizeof(int64_t));
+    int64_t nc = 0;
+    for (int64_t v = 0; v < n; ++v)
+        if (target[v] >= 0) order[nc++] = v;
+    cmp_score = score;
+    qsort(order, (size_t)nc, sizeof(int64_t), cand_cmp);
     int64_t accepted = 0;
-    for (int64_t v = 0; v < n; ++v) {
-        if (target[v] < 0) continue;
+    for (int64_t i = 0; i < nc; ++i) {
+        const int64_t v = order[i];
         int32_t a = part[v], b = target[v];
         int64_t gp = 0;
         for (int64_t e = g->xadj[v]; e < g->xadj[v + 1]; ++e) {
@@ -467,8 +515,26 @@ int orc_refine_round(const orc_graph *g, const orc_params *p, int32_t *part, int
             }
             gp += edge_w(g, e) * fu;
         }
-        if (gp * 65536 - pen[v] > 0) { accept[v] = 1; ++accepted; }
+        int64_t P = pen[v];
+        int allowed = 1;
+        const int eligible = gp > 0;
+        if (p->seq_penalty) {
+            const int64_t cv = node_c(g, v);
+            allowed = move_penalty(bucket + (int64_t)b * ORC_SLOTS, penq, p->mode,
+                                   W[b] + net[b] + cv - lmax, cv, &P);
+            pen_seq[v] = allowed ? P : -1;
+            if (eligible) {
+                net[b] += cv;
+                if (!avail[v]) net[a] -= cv;
+            }
+        } else {
+            pen_seq[v] = P;
+        }
+        if (eligible && allowed && gp * 65536 - P > 0) { accept[v] = 1; ++accepted; }
     }
+    free(order);
+    free(net);
+    free(avail);
     stats[ST_ACCEPTED] = accepted;
 
     /* S4: apply (commutative updates; the order does not matter). */
@@ -491,9 +557,10 @@ int orc_refine_round(const orc_graph *g, const orc_params *p, int32_t *part, int
             if (dbg->score) dbg->score[v] = score[v];
             if (dbg->pen) dbg->pen[v] = pen[v];
             if (dbg->accept) dbg->accept[v] = accept[v];
+            if (dbg->pen_seq) dbg->pen_seq[v] = pen_seq[v];
         }
     }
-    free(bucket); free(target); free(score); free(pen); free(accept);
+    free(bucket); free(target); free(score); free(pen); free(accept); free(pen_seq);
     return 0;
 }
 

@@ -196,9 +196,9 @@ def rebalance_one_iteration(g, k, part, L):
     """One synchronous rebalancing sub-iteration, from the rules of Section 7.1
     on Python lists: nodes of overloaded blocks take their best-gain move into
     a block that stays balanced (or, unconnected to any, the lightest such
-    block, smaller id on ties); each overloaded block releases its cheapest
-    nodes, in (priority bucket, id) order, until its excess is covered; each
-    target takes those aimed at it in the same order while they fit.
+    block, smaller id on ties); each target takes the offers aimed at it in
+    (priority bucket, id) order while they fit; each overloaded block keeps,
+    in the same order, its accepted nodes until its excess is covered.
     Returns the new partition (a list)."""
     part = list(part)
     W = [block_weight(g, part, j) for j in range(k)]
@@ -219,26 +219,26 @@ def rebalance_one_iteration(g, k, part, L):
             tgt = min(valid, key=lambda j: (W[j], j))
         gain = move_gain(g, part, v, tgt)
         info[v] = (tgt, rebalance_bucket(gain, cv))
-    selected = []
-    for a in range(k):
-        if W[a] <= L:
-            continue
-        nodes = sorted((v for v in info if part[v] == a), key=lambda v: (info[v][1], v))
-        got = 0
-        for v in nodes:
-            if got >= W[a] - L:
-                break
-            selected.append(v)
-            got += node_w(g, v)
-    out = list(part)
+    accepted = []
     for j in range(k):
-        nodes = sorted((v for v in selected if info[v][0] == j), key=lambda v: (info[v][1], v))
+        nodes = sorted((v for v in info if info[v][0] == j), key=lambda v: (info[v][1], v))
         room = L - W[j]
         for v in nodes:
             if node_w(g, v) > room:
                 break
             room -= node_w(g, v)
-            out[v] = j
+            accepted.append(v)
+    out = list(part)
+    for a in range(k):
+        if W[a] <= L:
+            continue
+        nodes = sorted((v for v in accepted if part[v] == a), key=lambda v: (info[v][1], v))
+        got = 0
+        for v in nodes:
+            if got >= W[a] - L:
+                break
+            got += node_w(g, v)
+            out[v] = info[v][0]
     return out
 
 
@@ -256,3 +256,56 @@ def pessimistic_gain(g, part, v, target, earlier):
         gain = move_gain(g, cur, v, target)
         worst = gain if worst is None else min(worst, gain)
     return worst
+
+
+def penalty_for_excess(g, k, part, t, tau, j, X, cv, mode):
+    """Section 5.3 penalty (Q16) of a node of weight cv whose move leaves
+    block j with excess X over L_max; None if forbidden."""
+    if X <= 0 or mode == 2:
+        return 0
+    if mode == 1:
+        return None
+    B = available_sets(g, k, part, t)
+    acc = 0
+    for l in range(54):
+        acc += sum(node_w(g, u) for u in B[j][l])
+        if acc >= X:
+            per_unit = (Fraction(*tau) * Fraction(3, 2) ** l * 65536) // 1
+            return min(int(per_unit) * cv, 1 << 62)
+    return None
+
+
+def filter_decisions(g, k, part, t, tau, eps, mode=0, seq=True):
+    """S3 by brute force. Candidates from best_moves, in (score desc, id asc)
+    order; pessimistic gain as the worst true gain over the moves earlier
+    candidate neighbours may make; with seq, each block's weight is tracked
+    along the order (eligible candidates, i.e. positive pessimistic gain, add
+    their weight to their target and, unless available for rebalancing,
+    remove it from their block) and every move is priced against it.
+    Returns {v: (accepted, pen_seq)} with pen_seq None when forbidden."""
+    total = sum(node_w(g, v) for v in range(g.n))
+    L = lmax_exact(total, k, eps)
+    moves = best_moves(g, k, part, t, tau, eps, mode)
+    order = sorted(moves, key=lambda v: (-moves[v][1], v))
+    W = [block_weight(g, part, j) for j in range(k)]
+    B = available_sets(g, k, part, t)
+    avail = {u for j in range(k) for l in range(54) for u in B[j][l]}
+    net = [0] * k
+    out = {}
+    pos = {v: i for i, v in enumerate(order)}
+    for v in order:
+        b, _, pen = moves[v]
+        nb = set(int(u) for u in g.adjncy[g.xadj[v]:g.xadj[v + 1]])
+        earlier = {u: moves[u][0] for u in nb if u in moves and pos[u] < pos[v]}
+        gp = pessimistic_gain(g, list(part), v, b, earlier)
+        cv = node_w(g, v)
+        P = pen
+        if seq:
+            P = penalty_for_excess(g, k, part, t, tau, b, W[b] + net[b] + cv - L, cv, mode)
+            if gp > 0:
+                net[b] += cv
+                if v not in avail:
+                    net[part[v]] -= cv
+        acc = P is not None and gp > 0 and gp * 65536 - P > 0
+        out[v] = (acc, P)
+    return out
