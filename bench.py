@@ -55,6 +55,80 @@ def stored_traffic():
     return t.get("bytes_per_launch")
 
 
+COPY_BYTES = 1 << 30  # calibration copy: reads and writes this many bytes
+
+
+def pmc_run(args):
+    """Workload for the counter runs: a few gain-table builds of the benchmark
+    graph, then a plain device copy of COPY_BYTES (the calibration kernel)."""
+    import torch
+    from paper_2308_15494_amd import graphgen as gg
+    from paper_2308_15494_amd import upr
+    g, k, eps, rounds, seed = gg.workload(args.workload)
+    ctx = upr.Context(0)
+    r = upr.Refiner(g, k, ctx=ctx)
+    r.set_partition(gg.random_partition(g.n, k, seed))
+    for _ in range(5):
+        upr.gain_table(ctx, r.plan, k, r.part, r.conn)
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("pmc run done")
+
+
+def _pmc_dispatches(path, counter):
+    """Per-kernel lists of per-dispatch counter values (summed over the
+    counter's instances) from a rocprofv3 counter_collection CSV."""
+    import csv
+    sums = {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") != counter:
+                continue
+            key = (row["Kernel_Name"], row.get("Dispatch_Id") or row.get("Correlation_Id"))
+            sums[key] = sums.get(key, 0.0) + float(row["Counter_Value"])
+    per = {}
+    for (name, _), v in sums.items():
+        per.setdefault(name, []).append(v)
+    return per
+
+
+def ingest_pmc(fetch_csv, write_csv):
+    """Write the traffic record of k_gain_tile from the two counter runs. The
+    calibration is the largest dispatch of the device copy kernel, which reads
+    and writes COPY_BYTES."""
+    fetch = _pmc_dispatches(fetch_csv, "FETCH_SIZE")
+    write = _pmc_dispatches(write_csv, "WRITE_SIZE")
+
+    def kernel(tab, needles):
+        for needle in needles:
+            keys = [k_ for k_ in tab if needle in k_]
+            if keys:
+                return keys[0]
+        raise SystemExit(f"no kernel matching {needles} in counters")
+
+    tile = kernel(fetch, ["k_gain_tile"])
+    copy = kernel(fetch, ["copyBuffer", "elementwise_kernel"])
+    tile_f = sum(fetch[tile]) / len(fetch[tile])
+    tile_w = sum(write[tile]) / len(write[tile])
+    copy_f = max(fetch[copy])
+    copy_w = max(write[kernel(write, [copy])])
+    f_scale = COPY_BYTES / copy_f   # bytes per counter unit (reads)
+    w_scale = COPY_BYTES / copy_w   # bytes per counter unit (writes)
+    rec = {"kernel": tile, "kernel_sha": kernel_sha(), "copy_kernel": copy,
+           "copy_bytes_each_way": COPY_BYTES, "fetch_counter": tile_f, "write_counter": tile_w,
+           "copy_fetch_counter": copy_f, "copy_write_counter": copy_w,
+           "fetch_scale": f_scale, "write_scale": w_scale,
+           "bytes_per_launch": tile_f * f_scale + tile_w * w_scale,
+           "fetch_bytes": tile_f * f_scale, "write_bytes": tile_w * w_scale}
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
 def cpu_baseline(g, k, eps, rounds, part0, seconds):
     """The oracle, single-threaded on a host core, on the first rounds of the
     same workload until about `seconds` of work; returns (baseline, stats list)."""
@@ -87,12 +161,23 @@ def main():
     ap.add_argument("--resident", action="store_true", help="time the resident-table form")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--pmc-run", action="store_true",
+                    help="counter-collection workload: gain-table builds + a calibration copy")
+    ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the gain-table traffic record from two rocprofv3 --pmc CSVs")
     args = ap.parse_args()
+    if args.ingest_pmc:
+        ingest_pmc(*args.ingest_pmc)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(graphs of this size fit one MI355X; multi-GPU sharding is not built)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.pmc_run:
+        pmc_run(args)
+        return
 
     import torch
     from paper_2308_15494_amd import graphgen as gg

@@ -74,6 +74,9 @@ typedef struct {
     int32_t rebuild_table;       /* 1: conn and block_w are recomputed from part first;
                                     0: conn and block_w are trusted resident state */
     int32_t max_rebalance_iters; /* 0: k+1 for unit node weights, 4k otherwise */
+    int32_t seq_penalty;         /* 1: the conflict filter prices each move against its target's
+                                    weight as changed by the eligible earlier candidates
+                                    (Section 5.3); 0: against the round-start weight only */
 } upr_params;
 
 /* Round statistics, written to a device int64 array of UPR_STATS_LEN slots. */
@@ -141,7 +144,9 @@ int upr_edge_cut(upr_ctx *ctx, const upr_plan *plan, const int32_t *part, int64_
  *      positive best score;
  *   S3 conflict filter: in (score desc, id asc) order, a candidate survives iff
  *      its gain, recomputed assuming every earlier candidate neighbour ends in
- *      the worse of its two blocks, times 2^16 still exceeds its penalty;
+ *      the worse of its two blocks, times 2^16 still exceeds its penalty
+ *      (with seq_penalty, the penalty for the target's weight after the
+ *      eligible earlier candidates' moves in and out);
  *   S4 apply survivors with delta updates of conn and block_w;
  *   S5 rebalance (Section 7.1) while a block exceeds L_max;
  *   S6 cut and statistics.

@@ -281,7 +281,7 @@ __device__ __forceinline__ void filter_class(const GraphView &g, const int32_t *
                                              uint64_t mask, int64_t lane_v, int64_t lane_key,
                                              int32_t *mvto, uint8_t *accflag,
                                              unsigned long long *acc_lds,
-                                             unsigned long long *deg_lds)
+                                             unsigned long long *deg_lds, int64_t *gp_out)
 {
     const int cnt = __popcll(mask);
     const int lane = lane_id();
@@ -303,7 +303,9 @@ __device__ __forceinline__ void filter_class(const GraphView &g, const int32_t *
         }
         acc = group_sum<G>(acc);
         bool take = false;
-        if (ok && gl == 0) {
+        if (ok && gl == 0 && gp_out) {
+            gp_out[v] = acc;  // decided later against the sequence-aware price
+        } else if (ok && gl == 0) {
             take = acc * 65536 - pen[v] > 0;
             accflag[v] = take ? 1 : 0;
             if (take) {
@@ -319,7 +321,7 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, const int32_t *_
                                                     const int64_t *__restrict__ key,
                                                     const int64_t *__restrict__ pen, int64_t low_t,
                                                     int64_t hub_t, int32_t *mvto, uint8_t *accflag,
-                                                    unsigned long long *counters)
+                                                    unsigned long long *counters, int64_t *gp_out)
 {
     __shared__ unsigned long long acc_lds, deg_lds;
     if (threadIdx.x == 0) {
@@ -340,9 +342,10 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, const int32_t *_
         const uint64_t mmid = __ballot(kv >= 0 && deg > low_t && deg <= hub_t);
         if (mlow)
             filter_class<kLowLanes>(g, part, key, pen, mlow, v, kv, mvto, accflag, &acc_lds,
-                                    &deg_lds);
+                                    &deg_lds, gp_out);
         if (mmid)
-            filter_class<64>(g, part, key, pen, mmid, v, kv, mvto, accflag, &acc_lds, &deg_lds);
+            filter_class<64>(g, part, key, pen, mmid, v, kv, mvto, accflag, &acc_lds, &deg_lds,
+                             gp_out);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -353,11 +356,12 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, const int32_t *_
 
 hipError_t launch_filter(const GraphView &g, const int32_t *part, const int64_t *key,
                          const int64_t *pen, int64_t low_t, int64_t hub_t, int32_t *mvto,
-                         uint8_t *accflag, unsigned long long *counters, hipStream_t s)
+                         uint8_t *accflag, unsigned long long *counters, int64_t *gp_out,
+                         hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_filter, dim3(grid_cap(g.n, kBlock, 8192)), dim3(kBlock), 0, s, g, part,
-                       key, pen, low_t, hub_t, mvto, accflag, counters);
+                       key, pen, low_t, hub_t, mvto, accflag, counters, gp_out);
     return hipGetLastError();
 }
 
@@ -376,9 +380,11 @@ __global__ __launch_bounds__(kBlock) void k_filter_hub(GraphView g, const int32_
     if (threadIdx.x == 0 && acc) atomic_add_i64(&h.gacc[c.hub], acc);
 }
 
-// Hub candidates: decide, mark the move, reset the accumulator.
+// Hub candidates: decide (or, with the sequence-aware price, store the
+// pessimistic gain), mark the move, reset the accumulator.
 __global__ void k_filter_hub_final(const int64_t *key, const int64_t *pen, HubView h,
-                                   int32_t *mvto, uint8_t *accflag, unsigned long long *counters)
+                                   int32_t *mvto, uint8_t *accflag, unsigned long long *counters,
+                                   int64_t *gp_out)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= h.nh) return;
@@ -387,6 +393,10 @@ __global__ void k_filter_hub_final(const int64_t *key, const int64_t *pen, HubVi
     const int64_t acc = h.gacc[i];
     h.gacc[i] = 0;
     if (kv < 0) return;
+    if (gp_out) {
+        gp_out[v] = acc;
+        return;
+    }
     const bool ok = acc * 65536 - pen[v] > 0;
     accflag[v] = ok ? 1 : 0;
     if (ok) {
@@ -406,7 +416,8 @@ __global__ void k_hub_moved_deg(GraphView g, const int32_t *mvto, HubView h,
 
 hipError_t launch_filter_hub(const GraphView &g, const int32_t *part, const int64_t *key,
                              const int64_t *pen, const HubView &h, int32_t *mvto,
-                             uint8_t *accflag, unsigned long long *counters, hipStream_t s)
+                             uint8_t *accflag, unsigned long long *counters, int64_t *gp_out,
+                             hipStream_t s)
 {
     if (h.nh <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_filter_hub, dim3((unsigned)h.nchunks), dim3(kBlock), 0, s, g, part, key,
@@ -414,7 +425,82 @@ hipError_t launch_filter_hub(const GraphView &g, const int32_t *part, const int6
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_filter_hub_final, dim3((h.nh + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                       key, pen, h, mvto, accflag, counters);
+                       key, pen, h, mvto, accflag, counters, gp_out);
+    return hipGetLastError();
+}
+
+// Sequence-aware decision for each candidate of the id-ordered list: the
+// move into b is priced against W[b] plus the weight change netpre[v]
+// accumulated by the eligible candidates before v (Section 5.3: the penalty
+// of a move depends on c(V_j + u) when it is made). Accept iff the
+// pessimistic gain is positive, the move is not forbidden, and
+// gain * 2^16 - P > 0.
+__global__ __launch_bounds__(kBlock) void k_filter_seq(
+    GraphView g, int32_t k, const int32_t *__restrict__ cand, const int32_t *__restrict__ count,
+    const int64_t *__restrict__ key, const int64_t *__restrict__ gp,
+    const int64_t *__restrict__ netpre, const int64_t *__restrict__ W,
+    const int64_t *__restrict__ cb, const int64_t *__restrict__ penq, int64_t lmax, int mode,
+    int64_t hub_t, int32_t *mvto, uint8_t *accflag, unsigned long long *counters)
+{
+    __shared__ unsigned long long acc_lds, deg_lds;
+    if (threadIdx.x == 0) {
+        acc_lds = 0;
+        deg_lds = 0;
+    }
+    __syncthreads();
+    const int64_t nc = *count;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < nc;
+         base += stride) {
+        const int64_t i = base + lane_id();
+        bool take = false;
+        if (i < nc) {
+            const int64_t v = cand[i];
+            const int64_t kv = key[v];
+            const int32_t b = (int32_t)(kv & 0xFFFF);
+            const int64_t gv = gp[v];
+            bool allowed = gv > 0;
+            int64_t P = 0;
+            if (allowed) {
+                const int64_t cv = node_weight(g, v);
+                const int64_t x = W[b] + netpre[v] + cv - lmax;
+                if (x > 0) {
+                    if (mode == 1) allowed = false;
+                    else if (mode == 0) {
+                        const int l = covering_slot(cb + (int64_t)b * kSlots, x);
+                        if (l >= kSlots) allowed = false;
+                        else P = sat_mul_pen(penq[l], cv);
+                    }
+                }
+            }
+            take = allowed && gv * 65536 - P > 0;
+            accflag[v] = take ? 1 : 0;
+            if (take) {
+                mvto[v] = b;
+                const int64_t deg = g.xadj[v + 1] - g.xadj[v];
+                if (deg <= hub_t) atomicAdd(&deg_lds, (unsigned long long)deg);
+            }
+        }
+        wave_count(take, &acc_lds);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (acc_lds) atomicAdd(&counters[CNT_ACC], acc_lds);
+        if (deg_lds) atomicAdd(&counters[CNT_MOVED_DEG], deg_lds);
+    }
+}
+
+hipError_t launch_filter_seq(const GraphView &g, int32_t k, const int32_t *cand,
+                             const int32_t *count, int64_t nc, const int64_t *key,
+                             const int64_t *gp, const int64_t *netpre, const int64_t *W,
+                             const int64_t *cb, const int64_t *penq, int64_t lmax, int mode,
+                             int64_t hub_t, int32_t *mvto, uint8_t *accflag,
+                             unsigned long long *counters, hipStream_t s)
+{
+    if (nc <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_filter_seq, dim3(grid_cap(nc, kBlock, 8192)), dim3(kBlock), 0, s, g, k,
+                       cand, count, key, gp, netpre, W, cb, penq, lmax, mode, hub_t, mvto, accflag,
+                       counters);
     return hipGetLastError();
 }
 

@@ -6,14 +6,15 @@
 // order "bucket, then node id" is realised without sorting:
 //   prepare   every node of an overloaded block picks its best-gain target
 //             among blocks that stay balanced (or the lightest such block if
-//             it is connected to none) and its priority bucket; per source
-//             block a histogram of node weight over buckets
-//   source    the cutoff bucket is the first whose cumulative weight covers
-//             the excess; inside it, chunk sums over id ranges and a scan of
-//             one chunk give the id bound of the minimal covering prefix
-//   target    the same over the selected nodes aimed at each target: the
-//             maximal prefix that fits the target's remaining capacity
-//   moves     accepted nodes are marked (mvto) for the apply kernels
+//             it is connected to none) and its priority bucket, and offers
+//             itself: per target a histogram of offered weight over buckets
+//   target    the cutoff bucket is the first whose cumulative weight exceeds
+//             the target's capacity; inside it, chunk sums over id ranges and
+//             a scan of one chunk give the id bound of the maximal prefix
+//             that fits
+//   source    the same over each overloaded block's accepted nodes: the
+//             minimal prefix that covers the block's excess is kept
+//   moves     kept nodes are marked (mvto) for the apply kernels
 // Histogram rows and chunk rows are cleared by the kernel that reads them,
 // so they are zero again at the start of the next sub-iteration. Node scans
 // run over all ids in wave-sized runs; membership of a node in an overloaded
@@ -40,19 +41,21 @@ struct RbView {
     const int32_t *theta_tgt;
 };
 
-__device__ __forceinline__ bool rb_selected(const RbView &r, int64_t v, int32_t a)
+// Accepted by its target j (offers are ordered by (bucket, id)).
+__device__ __forceinline__ bool rb_accepted(const RbView &r, int64_t v, int32_t j)
 {
-    const int cb = r.cbeta_src[a];
-    const int be = r.rbeta[v];
-    return be < cb || (be == cb && v < (int64_t)r.theta_src[a]);
-}
-
-__device__ __forceinline__ bool rb_accepted(const RbView &r, int64_t v, int32_t a, int32_t j)
-{
-    if (!rb_selected(r, v, a)) return false;
     const int cb = r.cbeta_tgt[j];
     const int be = r.rbeta[v];
     return be < cb || (be == cb && v < (int64_t)r.theta_tgt[j]);
+}
+
+// Accepted and kept by its source a.
+__device__ __forceinline__ bool rb_kept(const RbView &r, int64_t v, int32_t a, int32_t j)
+{
+    if (!rb_accepted(r, v, j)) return false;
+    const int cb = r.cbeta_src[a];
+    const int be = r.rbeta[v];
+    return be < cb || (be == cb && v < (int64_t)r.theta_src[a]);
 }
 
 // ------------------------------------------------------------------ begin --
@@ -188,21 +191,21 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, int32_t k,
                     const int64_t ca = conn[v * (int64_t)k + a];
                     const int be = rebalance_bucket(ct - ca, cv);
                     r.rbeta[v] = (uint8_t)be;
-                    hkey = (int64_t)a * kRbBuckets + be;
+                    hkey = (int64_t)tgt * kRbBuckets + be;
                     push = true;
                 }
             }
             if (h_lds) {
                 if (push) atomicAdd(&sH[hkey], (uint32_t)cv);
             } else {
-                wave_hist_add(r.hist_src, hkey, cv, push);
+                wave_hist_add(r.hist_tgt, hkey, cv, push);
             }
         }
     }
     if (h_lds) {
         __syncthreads();
         for (int j = threadIdx.x; j < k * kRbBuckets; j += kBlock)
-            if (sH[j]) atomic_add_i64(&r.hist_src[j], (int64_t)sH[j]);
+            if (sH[j]) atomic_add_i64(&r.hist_tgt[j], (int64_t)sH[j]);
     }
 }
 
@@ -211,15 +214,15 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, int32_t k,
 // Source: first bucket whose cumulative weight covers the excess.
 // Target: first bucket whose cumulative weight exceeds the capacity.
 // One wave per block: each lane holds buckets lane and lane + 64, a wave scan
-// gives the cumulative weights. Rows are cleared after reading. The source
-// pass also resets the sub-iteration's move counter.
+// gives the cumulative weights. Rows are cleared after reading. The target
+// pass (the first) also resets the sub-iteration's move counters.
 __global__ __launch_bounds__(kBlock) void k_rb_cutoffs(int32_t k, int64_t lmax, RebalWs r,
                                                         int target_side,
                                                         unsigned long long *counters)
 {
     const int j = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = lane_id();
-    if (!target_side && j == 0 && lane == 0) {
+    if (target_side && j == 0 && lane == 0) {
         counters[CNT_MOVED_NOW] = 0;
         counters[CNT_MOVED_DEG] = 0;
     }
@@ -277,7 +280,8 @@ __device__ __forceinline__ bool rb_member(const RebalWs &r, int32_t k, int64_t l
     return (unsigned)a < (unsigned)k && r.W0[a] > lmax && r.rtgt[v] >= 0;
 }
 
-// Nodes in the cutoff bucket add their weight to the chunk of their id.
+// Nodes in the cutoff bucket add their weight to the chunk of their id
+// (target side: every offer; source side: accepted offers).
 __global__ __launch_bounds__(kBlock) void k_rb_chunks(GraphView g, int32_t k, const int32_t *part,
                                                        int64_t lmax, RebalWs r, RbView rv,
                                                        int target_side)
@@ -287,21 +291,21 @@ __global__ __launch_bounds__(kBlock) void k_rb_chunks(GraphView g, int32_t k, co
         const int32_t a = part[v];
         if (!rb_member(r, k, lmax, v, a)) continue;
         const int be = r.rbeta[v];
-        if (!target_side) {
-            if (be == r.cbeta_src[a])
-                atomic_add_i64(&r.chunk_src[(int64_t)a * r.nchunks + (v >> r.chunk_shift)],
+        const int32_t j = r.rtgt[v];
+        if (target_side) {
+            if (be == r.cbeta_tgt[j])
+                atomic_add_i64(&r.chunk_tgt[(int64_t)j * r.nchunks + (v >> r.chunk_shift)],
                                node_weight(g, v));
         } else {
-            const int32_t j = r.rtgt[v];
-            if (be == r.cbeta_tgt[j] && rb_selected(rv, v, a))
-                atomic_add_i64(&r.chunk_tgt[(int64_t)j * r.nchunks + (v >> r.chunk_shift)],
+            if (be == r.cbeta_src[a] && rb_accepted(rv, v, j))
+                atomic_add_i64(&r.chunk_src[(int64_t)a * r.nchunks + (v >> r.chunk_shift)],
                                node_weight(g, v));
         }
     }
 }
 
-// Selected nodes add their weight to their target's bucket histogram.
-__global__ __launch_bounds__(kBlock) void k_rb_tgt_hist(GraphView g, int32_t k, const int32_t *part,
+// Accepted nodes add their weight to their source's bucket histogram.
+__global__ __launch_bounds__(kBlock) void k_rb_src_hist(GraphView g, int32_t k, const int32_t *part,
                                                          int64_t lmax, RebalWs r, RbView rv,
                                                          int hist32)
 {
@@ -320,22 +324,22 @@ __global__ __launch_bounds__(kBlock) void k_rb_tgt_hist(GraphView g, int32_t k, 
         int64_t hkey = 0, cv = 0;
         if (v < g.n) {
             const int32_t a = part[v];
-            if (rb_member(r, k, lmax, v, a) && rb_selected(rv, v, a)) {
+            if (rb_member(r, k, lmax, v, a) && rb_accepted(rv, v, r.rtgt[v])) {
                 sel = true;
-                hkey = (int64_t)r.rtgt[v] * kRbBuckets + r.rbeta[v];
+                hkey = (int64_t)a * kRbBuckets + r.rbeta[v];
                 cv = node_weight(g, v);
             }
         }
         if (h_lds) {
             if (sel) atomicAdd(&sH[hkey], (uint32_t)cv);
         } else {
-            wave_hist_add(r.hist_tgt, hkey, cv, sel);
+            wave_hist_add(r.hist_src, hkey, cv, sel);
         }
     }
     if (h_lds) {
         __syncthreads();
         for (int j = threadIdx.x; j < k * kRbBuckets; j += kBlock)
-            if (sH[j]) atomic_add_i64(&r.hist_tgt[j], (int64_t)sH[j]);
+            if (sH[j]) atomic_add_i64(&r.hist_src[j], (int64_t)sH[j]);
     }
 }
 
@@ -410,10 +414,10 @@ __global__ __launch_bounds__(kBlock) void k_rb_theta(GraphView g, int32_t k, con
             const int32_t a = part[v];
             if ((unsigned)a < (unsigned)k && r.W0[a] > lmax && r.rtgt[v] >= 0 &&
                 (int)r.rbeta[v] == cb) {
-                if (!target_side) {
-                    if (a == j) x = node_weight(g, v);
+                if (target_side) {
+                    if (r.rtgt[v] == j) x = node_weight(g, v);
                 } else {
-                    if (r.rtgt[v] == j && rb_selected(rv, v, a)) x = node_weight(g, v);
+                    if (a == j && rb_accepted(rv, v, r.rtgt[v])) x = node_weight(g, v);
                 }
             }
         }
@@ -460,7 +464,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_moves(GraphView g, int32_t k, con
             const int32_t a = part[v];
             if (rb_member(r, k, lmax, v, a)) {
                 const int32_t j = r.rtgt[v];
-                if (rb_accepted(rv, v, a, j)) {
+                if (rb_kept(rv, v, a, j)) {
                     mvto[v] = j;
                     acc = true;
                     const int64_t deg = g.xadj[v + 1] - g.xadj[v];
@@ -517,20 +521,22 @@ hipError_t launch_rb_iteration(const GraphView &g, int32_t k, const int32_t *par
 #undef UPR_RP
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const dim3 kg((k + 3) / 4);  // one wave per block
-    hipLaunchKernelGGL(k_rb_cutoffs, kg, dim3(kBlock), 0, s, k, lmax, r, 0, counters);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rb_chunks, dim3(lg), dim3(kBlock), 0, s, g, k, part, lmax, r, rv, 0);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rb_theta, dim3(k), dim3(kBlock), 0, s, g, k, part, lmax, r, rv, 0);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rb_tgt_hist, dim3(lg), dim3(kBlock), h_lds ? (size_t)k * kRbBuckets * 4 : 0,
-                       s, g, k, part, lmax, r, rv, hist32);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // target side over all offers
     hipLaunchKernelGGL(k_rb_cutoffs, kg, dim3(kBlock), 0, s, k, lmax, r, 1, counters);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rb_chunks, dim3(lg), dim3(kBlock), 0, s, g, k, part, lmax, r, rv, 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rb_theta, dim3(k), dim3(kBlock), 0, s, g, k, part, lmax, r, rv, 1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // source side over the accepted offers
+    hipLaunchKernelGGL(k_rb_src_hist, dim3(lg), dim3(kBlock), h_lds ? (size_t)k * kRbBuckets * 4 : 0,
+                       s, g, k, part, lmax, r, rv, hist32);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rb_cutoffs, kg, dim3(kBlock), 0, s, k, lmax, r, 0, counters);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rb_chunks, dim3(lg), dim3(kBlock), 0, s, g, k, part, lmax, r, rv, 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rb_theta, dim3(k), dim3(kBlock), 0, s, g, k, part, lmax, r, rv, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rb_moves, dim3(lg), dim3(kBlock), 0, s, g, k, part, lmax, r, rv, mvto,
                        hub_t, counters);

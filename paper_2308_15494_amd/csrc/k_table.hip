@@ -467,7 +467,8 @@ __global__ __launch_bounds__(kBlock) void k_node_stats(GraphView g, int32_t k,
                                                         const int32_t *__restrict__ wdeg,
                                                         int64_t *W, int64_t *bucket,
                                                         int32_t t_num, int32_t t_den,
-                                                        unsigned long long *counters, int cut_slot)
+                                                        unsigned long long *counters, int cut_slot,
+                                                        uint8_t *avail_out)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ unsigned long long red[4];
@@ -513,6 +514,7 @@ __global__ __launch_bounds__(kBlock) void k_node_stats(GraphView g, int32_t k,
         }
         if (bucket) {
             const bool avail = ok && (int64_t)t_den * inner >= (int64_t)t_num * wd;
+            if (avail_out && v < nn) avail_out[v] = avail ? 1 : 0;
             const int64_t key = (int64_t)a * kSlots + (avail ? slot_of(inner, cv) : 0);
             if (b_lds) {
                 if (avail) atomicAdd((unsigned long long *)&lb[key], (unsigned long long)cv);
@@ -537,14 +539,15 @@ __global__ __launch_bounds__(kBlock) void k_node_stats(GraphView g, int32_t k,
 hipError_t launch_node_stats(const GraphView &g, int32_t k, const int32_t *part,
                              const int32_t *conn, const int32_t *wdeg, int64_t *W,
                              int64_t *bucket, int32_t t_num, int32_t t_den,
-                             unsigned long long *counters, int cut_slot, hipStream_t s)
+                             unsigned long long *counters, int cut_slot, uint8_t *avail,
+                             hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
     size_t lds = 0;
     if (W && (size_t)k * 8 <= 16384) lds += (size_t)k * 8;
     if (bucket && (size_t)k * kSlots * 8 <= kStatsLdsBytes) lds += (size_t)k * kSlots * 8;
     hipLaunchKernelGGL(k_node_stats, dim3(grid_for(g.n, kBlock * 8, 2048)), dim3(kBlock), lds, s,
-                       g, k, part, conn, wdeg, W, bucket, t_num, t_den, counters, cut_slot);
+                       g, k, part, conn, wdeg, W, bucket, t_num, t_den, counters, cut_slot, avail);
     return hipGetLastError();
 }
 

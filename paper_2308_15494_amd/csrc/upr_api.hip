@@ -55,6 +55,17 @@ struct upr_ctx {
     uint8_t *accflag = nullptr;
     int32_t *mvto = nullptr;     // [n] pending move target, -1 = none
     uint8_t *dirty = nullptr;    // [n] gain-table tiles to rebuild
+    // sequence-aware penalty
+    int64_t *gp = nullptr;       // [n] pessimistic gains of candidates
+    uint8_t *avail = nullptr;    // [n] available for rebalancing
+    int32_t *cand = nullptr;     // [n] candidates in id order
+    int32_t *cand_count = nullptr;
+    uint64_t *ev_key = nullptr, *ev_key2 = nullptr;  // [2n]
+    uint32_t *ev_val = nullptr, *ev_val2 = nullptr;  // [2n]
+    int64_t *ev_prefix = nullptr;                     // [2n]
+    int64_t *netpre = nullptr;                        // [n]
+    void *seq_temp = nullptr;
+    size_t seq_temp_size = 0;
     int64_t *bucket = nullptr, *penq = nullptr;
     int64_t *pen1 = nullptr;     // [k] unit-weight penalty per target block
     unsigned long long *counters = nullptr;
@@ -127,6 +138,19 @@ void free_workspace(upr_ctx *c)
     dfree(c->accflag);
     dfree(c->mvto);
     dfree(c->dirty);
+    dfree(c->gp);
+    dfree(c->avail);
+    dfree(c->cand);
+    dfree(c->cand_count);
+    dfree(c->ev_key);
+    dfree(c->ev_key2);
+    dfree(c->ev_val);
+    dfree(c->ev_val2);
+    dfree(c->ev_prefix);
+    dfree(c->netpre);
+    if (c->seq_temp) (void)hipFree(c->seq_temp);
+    c->seq_temp = nullptr;
+    c->seq_temp_size = 0;
     dfree(c->bucket);
     dfree(c->pen1);
     dfree(c->rb.rtgt);
@@ -155,7 +179,12 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
     free_workspace(c);
     bool ok = dalloc(&c->key, N) == hipSuccess && dalloc(&c->pen, N) == hipSuccess &&
               dalloc(&c->accflag, N) == hipSuccess && dalloc(&c->mvto, N) == hipSuccess &&
-              dalloc(&c->dirty, N) == hipSuccess &&
+              dalloc(&c->dirty, N) == hipSuccess && dalloc(&c->gp, N) == hipSuccess &&
+              dalloc(&c->avail, N) == hipSuccess && dalloc(&c->cand, N) == hipSuccess &&
+              dalloc(&c->cand_count, 1) == hipSuccess && dalloc(&c->ev_key, 2 * N) == hipSuccess &&
+              dalloc(&c->ev_key2, 2 * N) == hipSuccess && dalloc(&c->ev_val, 2 * N) == hipSuccess &&
+              dalloc(&c->ev_val2, 2 * N) == hipSuccess && dalloc(&c->ev_prefix, 2 * N) == hipSuccess &&
+              dalloc(&c->netpre, N) == hipSuccess &&
               dalloc(&c->bucket, K * kSlots) == hipSuccess && dalloc(&c->pen1, K) == hipSuccess &&
               dalloc(&c->rb.rtgt, N) == hipSuccess && dalloc(&c->rb.rbeta, N) == hipSuccess &&
               dalloc(&c->rb.W0, K) == hipSuccess &&
@@ -179,6 +208,13 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
     HIP_TRY(c, hipMemset(c->key, 0xff, sizeof(int64_t) * N));
     HIP_TRY(c, hipMemset(c->mvto, 0xff, sizeof(int32_t) * N));
     HIP_TRY(c, hipMemset(c->dirty, 0, N));
+    c->seq_temp_size = seq_temp_bytes(N);
+    if (hipMalloc(&c->seq_temp, c->seq_temp_size) != hipSuccess) {
+        (void)hipGetLastError();
+        c->seq_temp = nullptr;
+        free_workspace(c);
+        return fail(c, UPR_E_NOMEM, "workspace allocation failed for n=%lld", (long long)N);
+    }
     HIP_TRY(c, hipDeviceSynchronize());
     c->cap_n = N;
     c->cap_k = K;
@@ -241,6 +277,7 @@ int check_params(upr_ctx *c, const upr_plan *p, const upr_params *q)
         return fail(c, UPR_E_ARG, "tau must be in [0, 1]");
     if (q->mode < 0 || q->mode > 2) return fail(c, UPR_E_ARG, "mode=%d not in {0,1,2}", q->mode);
     if (q->max_rebalance_iters < 0) return fail(c, UPR_E_ARG, "max_rebalance_iters < 0");
+    if (q->seq_penalty != 0 && q->seq_penalty != 1) return fail(c, UPR_E_ARG, "seq_penalty not 0/1");
     (void)p;
     return UPR_OK;
 }
@@ -656,7 +693,8 @@ static int round_common(upr_ctx *c, const upr_plan *p, const upr_params *q, int3
         PhaseTimer t(c, 1, s);
         HIP_TRY(c, launch_node_stats(p->g, k, part, conn, p->wdeg, q->rebuild_table ? W : nullptr,
                                      moves ? c->bucket : nullptr, q->t_num, q->t_den, c->counters,
-                                     CNT_CUT2_BEFORE, s));
+                                     CNT_CUT2_BEFORE, moves && q->seq_penalty ? c->avail : nullptr,
+                                     s));
     }
     if (moves) {
         {
@@ -665,22 +703,44 @@ static int round_common(upr_ctx *c, const upr_plan *p, const upr_params *q, int3
             HIP_TRY(c, launch_best_move(p->g, k, part, conn, W, c->bucket, c->penq, c->pen1, lmax,
                                         q->mode, c->key, c->pen, c->counters, s));
         }
-        {
-            PhaseTimer t(c, 3, s);
-            HIP_TRY(c, launch_filter(p->g, part, c->key, c->pen, p->low_t, p->hub_t, c->mvto,
-                                     c->accflag, c->counters, s));
-            HIP_TRY(c, launch_filter_hub(p->g, part, c->key, c->pen, h, c->mvto, c->accflag,
-                                         c->counters, s));
-        }
-        {
-            PhaseTimer t(c, 4, s);
-            HIP_TRY(c, launch_apply(p->g, k, part, conn, W, c->mvto, p->low_t, p->hub_t, h,
-                                    c->counters, p->dirty_threshold, c->dirty, s));
-        }
-        {
-            PhaseTimer t(c, 6, s);
-            HIP_TRY(c, launch_node_stats(p->g, k, part, conn, p->wdeg, nullptr, nullptr, 0, 1,
-                                         c->counters, CNT_CUT2_MOVES, s));
+        // one host decision: are there candidates at all (also reports bad input)
+        rc = sync_counters(c, s);
+        if (rc) return rc;
+        if (c->pinned[CNT_BAD_INPUT]) return fail(c, UPR_E_ARG, "part holds values outside [0, k)");
+        const int64_t nc = (int64_t)c->pinned[CNT_CAND];
+        if (nc > 0) {
+            {
+                PhaseTimer t(c, 3, s);
+                int64_t *gp_out = q->seq_penalty ? c->gp : nullptr;
+                HIP_TRY(c, launch_filter(p->g, part, c->key, c->pen, p->low_t, p->hub_t, c->mvto,
+                                         c->accflag, c->counters, gp_out, s));
+                HIP_TRY(c, launch_filter_hub(p->g, part, c->key, c->pen, h, c->mvto, c->accflag,
+                                             c->counters, gp_out, s));
+                if (q->seq_penalty) {
+                    HIP_TRY(c, launch_seq_select(n, c->key, c->cand, c->cand_count, c->seq_temp,
+                                                 c->seq_temp_size, s));
+                    HIP_TRY(c, launch_seq_net(nc, c->cand, c->key, part, p->g.vwgt, c->gp, c->avail,
+                                              c->ev_key, c->ev_key2, c->ev_val, c->ev_val2,
+                                              c->ev_prefix, c->netpre, c->seq_temp,
+                                              c->seq_temp_size, s));
+                    HIP_TRY(c, launch_filter_seq(p->g, k, c->cand, c->cand_count, nc, c->key, c->gp,
+                                                 c->netpre, W, c->bucket, c->penq, lmax, q->mode,
+                                                 p->hub_t, c->mvto, c->accflag, c->counters, s));
+                }
+            }
+            {
+                PhaseTimer t(c, 4, s);
+                HIP_TRY(c, launch_apply(p->g, k, part, conn, W, c->mvto, p->low_t, p->hub_t, h,
+                                        c->counters, p->dirty_threshold, c->dirty, s));
+            }
+            {
+                PhaseTimer t(c, 6, s);
+                HIP_TRY(c, launch_node_stats(p->g, k, part, conn, p->wdeg, nullptr, nullptr, 0, 1,
+                                             c->counters, CNT_CUT2_MOVES, nullptr, s));
+            }
+        } else {
+            HIP_TRY(c, hipMemcpyAsync(c->counters + CNT_CUT2_MOVES, c->counters + CNT_CUT2_BEFORE,
+                                      sizeof(unsigned long long), hipMemcpyDeviceToDevice, s));
         }
     }
     int64_t iters = 0, status = 0;
@@ -693,7 +753,7 @@ static int round_common(upr_ctx *c, const upr_plan *p, const upr_params *q, int3
     {
         PhaseTimer t(c, 6, s);
         HIP_TRY(c, launch_node_stats(p->g, k, part, conn, p->wdeg, nullptr, nullptr, 0, 1,
-                                     c->counters, CNT_CUT2_AFTER, s));
+                                     c->counters, CNT_CUT2_AFTER, nullptr, s));
     }
     if (!moves) {
         // standalone rebalancing: nothing moved before it

@@ -274,11 +274,13 @@ hipError_t launch_rebuild_hub_rows(const GraphView &g, int32_t k, const int32_t 
                                    int32_t *conn, const HubView &h, hipStream_t s);
 hipError_t launch_hub_bits(const HubView &h, uint32_t *bits, hipStream_t s);
 // Per node: 2*cut into counters[cut_slot], penalty buckets of the available
-// nodes (bucket may be null), block weights W[part] += c (W may be null).
+// nodes (bucket may be null), block weights W[part] += c (W may be null),
+// availability for rebalancing (avail may be null).
 hipError_t launch_node_stats(const GraphView &g, int32_t k, const int32_t *part,
                              const int32_t *conn, const int32_t *wdeg, int64_t *W,
                              int64_t *bucket, int32_t t_num, int32_t t_den,
-                             unsigned long long *counters, int cut_slot, hipStream_t s);
+                             unsigned long long *counters, int cut_slot, uint8_t *avail,
+                             hipStream_t s);
 hipError_t launch_block_weights(const GraphView &g, int32_t k, const int32_t *part, int64_t *W,
                                 unsigned long long *counters, hipStream_t s);
 hipError_t launch_cut_edges(const GraphView &g, const int32_t *part, unsigned long long *acc,
@@ -298,12 +300,32 @@ hipError_t launch_best_move(const GraphView &g, int32_t k, const int32_t *part, 
                             const int64_t *W, const int64_t *cb, const int64_t *penq,
                             const int64_t *pen1, int64_t lmax, int mode, int64_t *key,
                             int64_t *pen, unsigned long long *counters, hipStream_t s);
+// With gp_out the pessimistic gains are stored (decided by launch_filter_seq).
 hipError_t launch_filter(const GraphView &g, const int32_t *part, const int64_t *key,
                          const int64_t *pen, int64_t low_t, int64_t hub_t, int32_t *mvto,
-                         uint8_t *accflag, unsigned long long *counters, hipStream_t s);
+                         uint8_t *accflag, unsigned long long *counters, int64_t *gp_out,
+                         hipStream_t s);
 hipError_t launch_filter_hub(const GraphView &g, const int32_t *part, const int64_t *key,
                              const int64_t *pen, const HubView &h, int32_t *mvto,
-                             uint8_t *accflag, unsigned long long *counters, hipStream_t s);
+                             uint8_t *accflag, unsigned long long *counters, int64_t *gp_out,
+                             hipStream_t s);
+hipError_t launch_filter_seq(const GraphView &g, int32_t k, const int32_t *cand,
+                             const int32_t *count, int64_t nc, const int64_t *key,
+                             const int64_t *gp, const int64_t *netpre, const int64_t *W,
+                             const int64_t *cb, const int64_t *penq, int64_t lmax, int mode,
+                             int64_t hub_t, int32_t *mvto, uint8_t *accflag,
+                             unsigned long long *counters, hipStream_t s);
+
+// Sequence-aware penalty (k_seq.hip): candidate list in id order, then the
+// weight change of each candidate's target accumulated before it.
+size_t seq_temp_bytes(int64_t n);
+hipError_t launch_seq_select(int64_t n, const int64_t *key, int32_t *cand, int32_t *count,
+                             void *temp, size_t temp_bytes, hipStream_t s);
+hipError_t launch_seq_net(int64_t nc, const int32_t *cand, const int64_t *key, const int32_t *part,
+                          const int32_t *vwgt, const int64_t *gp, const uint8_t *avail,
+                          uint64_t *ev_key, uint64_t *ev_key2, uint32_t *ev_val,
+                          uint32_t *ev_val2, int64_t *prefix, int64_t *netpre, void *temp,
+                          size_t temp_bytes, hipStream_t s);
 // Apply every move recorded in mvto (target block, -1 = none) and clear it.
 // If the moving nodes' degrees sum to at most dirty_threshold
 // (counters[CNT_MOVED_DEG]) the neighbours' rows get integer-atomic deltas;

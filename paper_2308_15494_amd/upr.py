@@ -37,19 +37,20 @@ class _Graph(C.Structure):
 
 
 class Params(C.Structure):
-    """upr_params: k, eps, t, tau (rationals), mode, rebuild_table, max_rebalance_iters."""
+    """upr_params: k, eps, t, tau (rationals), mode, rebuild_table, max_rebalance_iters,
+    seq_penalty."""
     _fields_ = [("k", C.c_int32), ("eps_num", C.c_int32), ("eps_den", C.c_int32),
                 ("t_num", C.c_int32), ("t_den", C.c_int32), ("tau_num", C.c_int32),
                 ("tau_den", C.c_int32), ("mode", C.c_int32), ("rebuild_table", C.c_int32),
-                ("max_rebalance_iters", C.c_int32)]
+                ("max_rebalance_iters", C.c_int32), ("seq_penalty", C.c_int32)]
 
 
 def params(k, eps=(3, 100), t=(7, 10), tau=(1, 1), mode=0, rebuild_table=1,
-           max_rebalance_iters=0) -> Params:
+           max_rebalance_iters=0, seq_penalty=1) -> Params:
     if isinstance(mode, str):
         mode = MODES[mode]
     return Params(k, eps[0], eps[1], t[0], t[1], tau[0], tau[1], mode, rebuild_table,
-                  max_rebalance_iters)
+                  max_rebalance_iters, seq_penalty)
 
 
 _lib = None

@@ -160,17 +160,19 @@ SMALL = [
 
 @pytest.mark.parametrize("case", SMALL, ids=[c[0] for c in SMALL])
 @pytest.mark.parametrize("mode", [0, 1, 2])
-def test_round_parity_small(upr, ctx, case, mode):
+@pytest.mark.parametrize("seq", [1, 0])
+def test_round_parity_small(upr, ctx, case, mode, seq):
     name, make, k = case
     for seed in range(2):
         g = make(seed + 1)
         for pname, part0 in [("random", gg.random_partition(g.n, k, seed)),
                              ("skewed", skewed_partition(g.n, k, seed, 0.4))]:
-            say(f"round parity case={name} mode={mode} seed={seed} start={pname} n={g.n} k={k}")
+            say(f"round parity case={name} mode={mode} seq={seq} seed={seed} start={pname} "
+                f"n={g.n} k={k}")
             pr = Pair(upr, ctx, g, k, part0)
             for r in range(1, 5):
-                ost, odbg = pr.round(tau=gg.tau_schedule(r, 4), mode=mode)
-                pr.compare(ost, odbg, f"{name} mode {mode} seed {seed} {pname} round {r}")
+                ost, odbg = pr.round(tau=gg.tau_schedule(r, 4), mode=mode, seq_penalty=seq)
+                pr.compare(ost, odbg, f"{name} mode {mode} seq {seq} seed {seed} {pname} round {r}")
 
 
 @pytest.mark.parametrize("t", [(7, 10), (2, 5), (0, 1), (1, 1)])
