@@ -251,7 +251,7 @@ __device__ __forceinline__ int move_sign(int32_t x, int32_t a, int32_t b)
 // [e0, e1) strided by `step` starting at e0 + off. An earlier candidate
 // neighbour u ((score, id) before v) contributes the worse of its current
 // and its target block.
-__device__ __forceinline__ int64_t pessimistic_part(const GraphView &g, const int32_t *part,
+__device__ __forceinline__ int64_t pessimistic_part(const GraphView &g, const PartView &part,
                                                     const int64_t *key, int64_t v, int32_t a,
                                                     int32_t b, int64_t sv, int64_t e0, int64_t e1,
                                                     int off, int step)
@@ -259,7 +259,7 @@ __device__ __forceinline__ int64_t pessimistic_part(const GraphView &g, const in
     int64_t acc = 0;
     for (int64_t e = e0 + off; e < e1; e += step) {
         const int32_t u = g.adjncy[e];
-        int f = move_sign(part[u], a, b);
+        int f = move_sign(pget(part, u), a, b);
         const int64_t ku = key[u];
         if (ku >= 0) {
             const int64_t su = ku >> 16;
@@ -277,7 +277,8 @@ __device__ __forceinline__ int64_t pessimistic_part(const GraphView &g, const in
 // set bits of mask in order; the node id / key of bit p sit in lane p.
 template <int G>
 __device__ __forceinline__ void filter_class(const GraphView &g, const int32_t *part,
-                                             const int64_t *key, const int64_t *pen,
+                                             const PartView &pv, const int64_t *key,
+                                             const int64_t *pen,
                                              uint64_t mask, int64_t lane_v, int64_t lane_key,
                                              int32_t *mvto, uint8_t *accflag,
                                              unsigned long long *acc_lds,
@@ -298,8 +299,7 @@ __device__ __forceinline__ void filter_class(const GraphView &g, const int32_t *
         if (ok) {
             const int32_t a = part[v];
             b = (int32_t)(kv & 0xFFFF);
-            acc = pessimistic_part(g, part, key, v, a, b, kv >> 16, g.xadj[v], g.xadj[v + 1], gl,
-                                   G);
+            acc = pessimistic_part(g, pv, key, v, a, b, kv >> 16, g.xadj[v], g.xadj[v + 1], gl, G);
         }
         acc = group_sum<G>(acc);
         bool take = false;
@@ -318,7 +318,7 @@ __device__ __forceinline__ void filter_class(const GraphView &g, const int32_t *
 }
 
 __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, const int32_t *__restrict__ part,
-                                                    const int64_t *__restrict__ key,
+                                                    PartView pv, const int64_t *__restrict__ key,
                                                     const int64_t *__restrict__ pen, int64_t low_t,
                                                     int64_t hub_t, int32_t *mvto, uint8_t *accflag,
                                                     unsigned long long *counters, int64_t *gp_out)
@@ -341,10 +341,10 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, const int32_t *_
         const uint64_t mlow = __ballot(kv >= 0 && deg <= low_t);
         const uint64_t mmid = __ballot(kv >= 0 && deg > low_t && deg <= hub_t);
         if (mlow)
-            filter_class<kLowLanes>(g, part, key, pen, mlow, v, kv, mvto, accflag, &acc_lds,
+            filter_class<kLowLanes>(g, part, pv, key, pen, mlow, v, kv, mvto, accflag, &acc_lds,
                                     &deg_lds, gp_out);
         if (mmid)
-            filter_class<64>(g, part, key, pen, mmid, v, kv, mvto, accflag, &acc_lds, &deg_lds,
+            filter_class<64>(g, part, pv, key, pen, mmid, v, kv, mvto, accflag, &acc_lds, &deg_lds,
                              gp_out);
     }
     __syncthreads();
@@ -354,20 +354,20 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, const int32_t *_
     }
 }
 
-hipError_t launch_filter(const GraphView &g, const int32_t *part, const int64_t *key,
-                         const int64_t *pen, int64_t low_t, int64_t hub_t, int32_t *mvto,
-                         uint8_t *accflag, unsigned long long *counters, int64_t *gp_out,
-                         hipStream_t s)
+hipError_t launch_filter(const GraphView &g, const int32_t *part, const PartView &pv,
+                         const int64_t *key, const int64_t *pen, int64_t low_t, int64_t hub_t,
+                         int32_t *mvto, uint8_t *accflag, unsigned long long *counters,
+                         int64_t *gp_out, hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_filter, dim3(grid_cap(g.n, kBlock, 8192)), dim3(kBlock), 0, s, g, part,
+    hipLaunchKernelGGL(k_filter, dim3(grid_cap(g.n, kBlock, 8192)), dim3(kBlock), 0, s, g, part, pv,
                        key, pen, low_t, hub_t, mvto, accflag, counters, gp_out);
     return hipGetLastError();
 }
 
 // Hub candidates: each chunk adds its part of the pessimistic gain.
 __global__ __launch_bounds__(kBlock) void k_filter_hub(GraphView g, const int32_t *part,
-                                                        const int64_t *key, HubView h)
+                                                        PartView pv, const int64_t *key, HubView h)
 {
     __shared__ int64_t red[4];
     const HubChunk c = h.chunks[blockIdx.x];
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_hub(GraphView g, const int32_
     const int64_t kv = key[v];
     if (kv < 0) return;  // uniform over the workgroup
     const int32_t a = part[v], b = (int32_t)(kv & 0xFFFF);
-    int64_t acc = pessimistic_part(g, part, key, v, a, b, kv >> 16, c.e0, c.e1, threadIdx.x, kBlock);
+    int64_t acc = pessimistic_part(g, pv, key, v, a, b, kv >> 16, c.e0, c.e1, threadIdx.x, kBlock);
     acc = block_sum(acc, red);
     if (threadIdx.x == 0 && acc) atomic_add_i64(&h.gacc[c.hub], acc);
 }
@@ -414,14 +414,14 @@ __global__ void k_hub_moved_deg(GraphView g, const int32_t *mvto, HubView h,
     if (mvto[v] >= 0) atomicAdd(&counters[CNT_MOVED_DEG], (unsigned long long)(g.xadj[v + 1] - g.xadj[v]));
 }
 
-hipError_t launch_filter_hub(const GraphView &g, const int32_t *part, const int64_t *key,
-                             const int64_t *pen, const HubView &h, int32_t *mvto,
-                             uint8_t *accflag, unsigned long long *counters, int64_t *gp_out,
-                             hipStream_t s)
+hipError_t launch_filter_hub(const GraphView &g, const int32_t *part, const PartView &pv,
+                             const int64_t *key, const int64_t *pen, const HubView &h,
+                             int32_t *mvto, uint8_t *accflag, unsigned long long *counters,
+                             int64_t *gp_out, hipStream_t s)
 {
     if (h.nh <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_filter_hub, dim3((unsigned)h.nchunks), dim3(kBlock), 0, s, g, part, key,
-                       h);
+    hipLaunchKernelGGL(k_filter_hub, dim3((unsigned)h.nchunks), dim3(kBlock), 0, s, g, part, pv,
+                       key, h);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_filter_hub_final, dim3((h.nh + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
@@ -512,7 +512,8 @@ hipError_t launch_filter_seq(const GraphView &g, int32_t k, const int32_t *cand,
 // commute, so the result does not depend on the order of the moves.
 template <int G>
 __device__ __forceinline__ void apply_class(const GraphView &g, int32_t k, int32_t *part,
-                                            int32_t *conn, int64_t *wdst, uint64_t mask,
+                                            const PartView &pv, int32_t *conn, int64_t *wdst,
+                                            uint64_t mask,
                                             int64_t lane_v, int32_t lane_to, int32_t *mvto,
                                             const HubView &h, uint8_t *dirty, int T)
 {
@@ -545,6 +546,7 @@ __device__ __forceinline__ void apply_class(const GraphView &g, int32_t k, int32
         if (gl == 0) {
             const int64_t cv = node_weight(g, v);
             part[v] = b;
+            pset((void *)pv.p, pv.bytes, v, b);
             mvto[v] = -1;
             atomicAdd((unsigned long long *)&wdst[a], (unsigned long long)(-cv));
             atomicAdd((unsigned long long *)&wdst[b], (unsigned long long)cv);
@@ -553,7 +555,8 @@ __device__ __forceinline__ void apply_class(const GraphView &g, int32_t k, int32
 }
 
 __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, int32_t k, int32_t *part,
-                                                   int32_t *conn, int64_t *W, int32_t *mvto,
+                                                   PartView pv, int32_t *conn, int64_t *W,
+                                                   int32_t *mvto,
                                                    int64_t low_t, int64_t hub_t, HubView h,
                                                    const unsigned long long *counters,
                                                    int64_t dirty_threshold, uint8_t *dirty_flags,
@@ -581,8 +584,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, int32_t k, int32_
         }
         const uint64_t mlow = __ballot(to >= 0 && deg <= low_t);
         const uint64_t mmid = __ballot(to >= 0 && deg > low_t && deg <= hub_t);
-        if (mlow) apply_class<kLowLanes>(g, k, part, conn, wdst, mlow, v, to, mvto, h, dirty, T);
-        if (mmid) apply_class<64>(g, k, part, conn, wdst, mmid, v, to, mvto, h, dirty, T);
+        if (mlow) apply_class<kLowLanes>(g, k, part, pv, conn, wdst, mlow, v, to, mvto, h, dirty, T);
+        if (mmid) apply_class<64>(g, k, part, pv, conn, wdst, mmid, v, to, mvto, h, dirty, T);
     }
     if (use_lds) {
         __syncthreads();
@@ -618,7 +621,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_hub(GraphView g, int32_t k, co
 }
 
 // Hub moves: part and block weights, then clear the mark.
-__global__ void k_apply_hub_final(GraphView g, int32_t *part, int64_t *W, int32_t *mvto, HubView h)
+__global__ void k_apply_hub_final(GraphView g, int32_t *part, PartView pv, int64_t *W,
+                                  int32_t *mvto, HubView h)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= h.nh) return;
@@ -628,15 +632,16 @@ __global__ void k_apply_hub_final(GraphView g, int32_t *part, int64_t *W, int32_
     const int32_t a = part[v];
     const int64_t cv = node_weight(g, v);
     part[v] = b;
+    pset((void *)pv.p, pv.bytes, v, b);
     mvto[v] = -1;
     atomic_add_i64(&W[a], -cv);
     atomic_add_i64(&W[b], cv);
 }
 
-hipError_t launch_apply(const GraphView &g, int32_t k, int32_t *part, int32_t *conn, int64_t *W,
-                        int32_t *mvto, int64_t low_t, int64_t hub_t, const HubView &h,
-                        const unsigned long long *counters, int64_t dirty_threshold,
-                        uint8_t *dirty, hipStream_t s)
+hipError_t launch_apply(const GraphView &g, int32_t k, int32_t *part, const PartView &pv,
+                        int32_t *conn, int64_t *W, int32_t *mvto, int64_t low_t, int64_t hub_t,
+                        const HubView &h, const unsigned long long *counters,
+                        int64_t dirty_threshold, uint8_t *dirty, hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
     const int T = gain_tile_nodes(k);
@@ -648,19 +653,19 @@ hipError_t launch_apply(const GraphView &g, int32_t k, int32_t *part, int32_t *c
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_apply, dim3(grid_cap(g.n, kBlock, 4096)), dim3(kBlock), lds, s, g, k, part,
-                       conn, W, mvto, low_t, hub_t, h, counters, dirty_threshold, dirty, T);
+                       pv, conn, W, mvto, low_t, hub_t, h, counters, dirty_threshold, dirty, T);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (h.nh > 0) {
         hipLaunchKernelGGL(k_apply_hub, dim3((unsigned)h.nchunks), dim3(kBlock), 0, s, g, k, part,
                            conn, mvto, h, counters, dirty_threshold, dirty, T);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         hipLaunchKernelGGL(k_apply_hub_final, dim3((h.nh + kBlock - 1) / kBlock), dim3(kBlock), 0,
-                           s, g, part, W, mvto, h);
+                           s, g, part, pv, W, mvto, h);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     // rebuild the marked tiles (none are marked in the delta mode)
-    if ((e = launch_gain_tile(g, k, part, conn, hub_t, dirty, s)) != hipSuccess) return e;
-    return launch_rebuild_hub_rows(g, k, part, conn, h, s);
+    if ((e = launch_gain_tile(g, k, pv, conn, hub_t, dirty, s)) != hipSuccess) return e;
+    return launch_rebuild_hub_rows(g, k, pv, conn, h, s);
 }
 
 // ----------------------------------------------------------------- stats --

@@ -218,7 +218,7 @@ __device__ __forceinline__ int upper_index(const int32_t *a, int cnt, int32_t p)
 // by k_gain_hub.
 template <bool WEIGHTED>
 __device__ __forceinline__ void gain_tile_body(const GraphView &g, int32_t k, int T,
-                                               const int32_t *__restrict__ part,
+                                               const PartView &part,
                                                int32_t *__restrict__ conn, int64_t hub_t)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -279,7 +279,7 @@ __device__ __forceinline__ void gain_tile_body(const GraphView &g, int32_t k, in
             w[i] = (WEIGHTED && node[i] >= 0) ? g.adjwgt[e[i]] : 1;
         }
 #pragma unroll
-        for (int i = 0; i < kUnroll; ++i) pu[i] = node[i] >= 0 ? part[u[i]] : -1;
+        for (int i = 0; i < kUnroll; ++i) pu[i] = node[i] >= 0 ? pget(part, u[i]) : -1;
 #pragma unroll
         for (int i = 0; i < kUnroll; ++i)
             if ((unsigned)pu[i] < (unsigned)k) atomicAdd(&tile[node[i] * k + pu[i]], w[i]);
@@ -301,8 +301,7 @@ __device__ __forceinline__ void gain_tile_body(const GraphView &g, int32_t k, in
 }
 
 template <bool WEIGHTED>
-__global__ __launch_bounds__(kBlock) void k_gain_tile(GraphView g, int32_t k, int T,
-                                                       const int32_t *__restrict__ part,
+__global__ __launch_bounds__(kBlock) void k_gain_tile(GraphView g, int32_t k, int T, PartView part,
                                                        int32_t *__restrict__ conn, int64_t hub_t)
 {
     gain_tile_body<WEIGHTED>(g, k, T, part, conn, hub_t);
@@ -311,7 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_gain_tile(GraphView g, int32_t k, in
 // Same tiles, rebuilt only where a flag is set (flags are cleared).
 template <bool WEIGHTED>
 __global__ __launch_bounds__(kBlock) void k_gain_refresh(GraphView g, int32_t k, int T,
-                                                          const int32_t *__restrict__ part,
+                                                          PartView part,
                                                           int32_t *__restrict__ conn,
                                                           int64_t hub_t, uint8_t *dirty)
 {
@@ -321,7 +320,7 @@ __global__ __launch_bounds__(kBlock) void k_gain_refresh(GraphView g, int32_t k,
     gain_tile_body<WEIGHTED>(g, k, T, part, conn, hub_t);
 }
 
-hipError_t launch_gain_tile(const GraphView &g, int32_t k, const int32_t *part, int32_t *conn,
+hipError_t launch_gain_tile(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,
                             int64_t hub_t, uint8_t *dirty, hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
@@ -350,8 +349,7 @@ hipError_t launch_gain_tile(const GraphView &g, int32_t k, const int32_t *part, 
 
 // One workgroup per chunk of a hub's edges: accumulate into an LDS row, then
 // add the non-zero entries into the hub's row of conn (zeroed by the tile).
-__global__ __launch_bounds__(kBlock) void k_gain_hub(GraphView g, int32_t k,
-                                                      const int32_t *__restrict__ part,
+__global__ __launch_bounds__(kBlock) void k_gain_hub(GraphView g, int32_t k, PartView part,
                                                       int32_t *conn, HubView h)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -361,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_gain_hub(GraphView g, int32_t k,
     for (int j = threadIdx.x; j < k; j += kBlock) row[j] = 0;
     __syncthreads();
     for (int64_t e = c.e0 + threadIdx.x; e < c.e1; e += kBlock) {
-        const int32_t pu = part[g.adjncy[e]];
+        const int32_t pu = pget(part, g.adjncy[e]);
         if ((unsigned)pu < (unsigned)k) atomicAdd(&row[pu], edge_weight(g, e));
     }
     __syncthreads();
@@ -391,7 +389,7 @@ hipError_t launch_hub_bits(const HubView &h, uint32_t *bits, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_rebuild_hub_rows(const GraphView &g, int32_t k, const int32_t *part,
+hipError_t launch_rebuild_hub_rows(const GraphView &g, int32_t k, const PartView &part,
                                    int32_t *conn, const HubView &h, hipStream_t s)
 {
     if (h.nh <= 0) return hipSuccess;
@@ -401,7 +399,7 @@ hipError_t launch_rebuild_hub_rows(const GraphView &g, int32_t k, const int32_t 
     return launch_gain_hub(g, k, part, conn, h, s);
 }
 
-hipError_t launch_gain_hub(const GraphView &g, int32_t k, const int32_t *part, int32_t *conn,
+hipError_t launch_gain_hub(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,
                            const HubView &h, hipStream_t s)
 {
     if (h.nchunks <= 0) return hipSuccess;
@@ -605,6 +603,21 @@ hipError_t launch_cut_edges(const GraphView &g, const int32_t *part, unsigned lo
     if (g.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_cut_edges, dim3(grid_for(g.n, kBlock / 64, 16384)), dim3(kBlock), 0, s, g,
                        part, acc);
+    return hipGetLastError();
+}
+
+__global__ void k_pack_part(int64_t n, const int32_t *part, void *pc, int bytes)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+        pset(pc, bytes, v, part[v]);  // out-of-range values are reported by k_node_stats
+}
+
+hipError_t launch_pack_part(int64_t n, const int32_t *part, void *pc, int bytes, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_part, dim3(grid_for(n, kBlock * 4, 4096)), dim3(kBlock), 0, s, n, part,
+                       pc, bytes);
     return hipGetLastError();
 }
 

@@ -55,6 +55,7 @@ struct upr_ctx {
     uint8_t *accflag = nullptr;
     int32_t *mvto = nullptr;     // [n] pending move target, -1 = none
     uint8_t *dirty = nullptr;    // [n] gain-table tiles to rebuild
+    uint16_t *pc = nullptr;      // [n] compact copy of part for neighbour gathers
     // sequence-aware penalty
     int64_t *gp = nullptr;       // [n] pessimistic gains of candidates
     uint8_t *avail = nullptr;    // [n] available for rebalancing
@@ -138,6 +139,7 @@ void free_workspace(upr_ctx *c)
     dfree(c->accflag);
     dfree(c->mvto);
     dfree(c->dirty);
+    dfree(c->pc);
     dfree(c->gp);
     dfree(c->avail);
     dfree(c->cand);
@@ -180,6 +182,7 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
     bool ok = dalloc(&c->key, N) == hipSuccess && dalloc(&c->pen, N) == hipSuccess &&
               dalloc(&c->accflag, N) == hipSuccess && dalloc(&c->mvto, N) == hipSuccess &&
               dalloc(&c->dirty, N) == hipSuccess && dalloc(&c->gp, N) == hipSuccess &&
+              dalloc(&c->pc, N) == hipSuccess &&
               dalloc(&c->avail, N) == hipSuccess && dalloc(&c->cand, N) == hipSuccess &&
               dalloc(&c->cand_count, 1) == hipSuccess && dalloc(&c->ev_key, 2 * N) == hipSuccess &&
               dalloc(&c->ev_key2, 2 * N) == hipSuccess && dalloc(&c->ev_val, 2 * N) == hipSuccess &&
@@ -305,7 +308,8 @@ int64_t default_iters(const upr_plan *p, int32_t k)
 }
 
 // S5: the host loop over synchronous sub-iterations.
-int rebalance_loop(upr_ctx *c, const upr_plan *p, int32_t k, int32_t *part, int32_t *conn,
+int rebalance_loop(upr_ctx *c, const upr_plan *p, int32_t k, int32_t *part, const PartView &pv,
+                   int32_t *conn,
                    int64_t *W, int64_t lmax, int64_t it_max, int64_t *iters_out,
                    int64_t *status_out, hipStream_t s)
 {
@@ -335,7 +339,7 @@ int rebalance_loop(upr_ctx *c, const upr_plan *p, int32_t k, int32_t *part, int3
         ++iters;
         HIP_TRY(c, launch_rb_iteration(p->g, k, part, conn, lmax, c->rb, c->mvto, hist32, p->hub_t,
                                        c->counters, s));
-        HIP_TRY(c, launch_apply(p->g, k, part, conn, W, c->mvto, p->low_t, p->hub_t, h, c->counters,
+        HIP_TRY(c, launch_apply(p->g, k, part, pv, conn, W, c->mvto, p->low_t, p->hub_t, h, c->counters,
                                 p->dirty_threshold, c->dirty, s));
         HIP_TRY(c, launch_rb_begin(k, W, lmax, c->rb, c->counters, s));
         rc = sync_counters(c, s);
@@ -618,8 +622,9 @@ int upr_gain_table(upr_ctx *c, const upr_plan *p, int32_t k, const int32_t *part
     if (rc) return rc;
     if (c->pinned[CNT_BAD_INPUT]) return fail(c, UPR_E_ARG, "part holds values outside [0, k)");
     PhaseTimer t(c, 0, s);
-    HIP_TRY(c, launch_gain_tile(p->g, k, part, conn, p->hub_t, nullptr, s));
-    HIP_TRY(c, launch_gain_hub(p->g, k, part, conn, p->hubs(), s));
+    const PartView pv{part, 4};
+    HIP_TRY(c, launch_gain_tile(p->g, k, pv, conn, p->hub_t, nullptr, s));
+    HIP_TRY(c, launch_gain_hub(p->g, k, pv, conn, p->hubs(), s));
     return UPR_OK;
 }
 
@@ -679,14 +684,17 @@ static int round_common(upr_ctx *c, const upr_plan *p, const upr_params *q, int3
     PenTable pq;
     host_penq(q->tau_num, q->tau_den, pq.q);
     HIP_TRY(c, launch_round_init(k, c->bucket, W, pq, c->penq, c->counters, q->rebuild_table, s));
+    // compact partition copy for the neighbour gathers (kept in step by the apply)
+    const PartView pv{c->pc, k <= 256 ? 1 : 2};
+    HIP_TRY(c, launch_pack_part(n, part, c->pc, pv.bytes, s));
     if (q->rebuild_table) {
         {
             PhaseTimer t(c, 0, s);
-            HIP_TRY(c, launch_gain_tile(p->g, k, part, conn, p->hub_t, nullptr, s));
+            HIP_TRY(c, launch_gain_tile(p->g, k, pv, conn, p->hub_t, nullptr, s));
         }
         if (p->nh > 0) {
             PhaseTimer t(c, 1, s);
-            HIP_TRY(c, launch_gain_hub(p->g, k, part, conn, h, s));
+            HIP_TRY(c, launch_gain_hub(p->g, k, pv, conn, h, s));
         }
     }
     {
@@ -712,9 +720,9 @@ static int round_common(upr_ctx *c, const upr_plan *p, const upr_params *q, int3
             {
                 PhaseTimer t(c, 3, s);
                 int64_t *gp_out = q->seq_penalty ? c->gp : nullptr;
-                HIP_TRY(c, launch_filter(p->g, part, c->key, c->pen, p->low_t, p->hub_t, c->mvto,
+                HIP_TRY(c, launch_filter(p->g, part, pv, c->key, c->pen, p->low_t, p->hub_t, c->mvto,
                                          c->accflag, c->counters, gp_out, s));
-                HIP_TRY(c, launch_filter_hub(p->g, part, c->key, c->pen, h, c->mvto, c->accflag,
+                HIP_TRY(c, launch_filter_hub(p->g, part, pv, c->key, c->pen, h, c->mvto, c->accflag,
                                              c->counters, gp_out, s));
                 if (q->seq_penalty) {
                     HIP_TRY(c, launch_seq_select(n, c->key, c->cand, c->cand_count, c->seq_temp,
@@ -730,7 +738,7 @@ static int round_common(upr_ctx *c, const upr_plan *p, const upr_params *q, int3
             }
             {
                 PhaseTimer t(c, 4, s);
-                HIP_TRY(c, launch_apply(p->g, k, part, conn, W, c->mvto, p->low_t, p->hub_t, h,
+                HIP_TRY(c, launch_apply(p->g, k, part, pv, conn, W, c->mvto, p->low_t, p->hub_t, h,
                                         c->counters, p->dirty_threshold, c->dirty, s));
             }
             {
@@ -747,7 +755,7 @@ static int round_common(upr_ctx *c, const upr_plan *p, const upr_params *q, int3
     {
         PhaseTimer t(c, 5, s);
         const int64_t it_max = q->max_rebalance_iters > 0 ? q->max_rebalance_iters : default_iters(p, k);
-        rc = rebalance_loop(c, p, k, part, conn, W, lmax, it_max, &iters, &status, s);
+        rc = rebalance_loop(c, p, k, part, pv, conn, W, lmax, it_max, &iters, &status, s);
         if (rc) return rc;
     }
     {

@@ -45,6 +45,27 @@ struct GraphView {
     const int32_t *vwgt;    // may be null: unit node weights
 };
 
+// Read-only view of the partition for neighbour gathers: the caller's int32
+// array, or a compact copy with 1 (k <= 256) or 2 bytes per node that stays
+// resident in L2.
+struct PartView {
+    const void *p;
+    int bytes;
+};
+
+__device__ __forceinline__ int32_t pget(const PartView &pv, int64_t u)
+{
+    if (pv.bytes == 1) return ((const uint8_t *)pv.p)[u];
+    if (pv.bytes == 2) return ((const uint16_t *)pv.p)[u];
+    return ((const int32_t *)pv.p)[u];
+}
+
+__device__ __forceinline__ void pset(void *pc, int bytes, int64_t v, int32_t b)
+{
+    if (bytes == 1) ((uint8_t *)pc)[v] = (uint8_t)b;
+    else if (bytes == 2) ((uint16_t *)pc)[v] = (uint16_t)b;
+}
+
 struct HubChunk {
     int32_t hub;  // index into the sorted hub id list
     int32_t pad;
@@ -265,13 +286,15 @@ hipError_t launch_hub_ranges(const int64_t *xadj, const int32_t *ids, int32_t nh
 int gain_tile_nodes(int32_t k);
 // With dirty != null only tiles whose flag is set are rebuilt (flags are
 // cleared).
-hipError_t launch_gain_tile(const GraphView &g, int32_t k, const int32_t *part, int32_t *conn,
+hipError_t launch_gain_tile(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,
                             int64_t hub_t, uint8_t *dirty, hipStream_t s);
-hipError_t launch_gain_hub(const GraphView &g, int32_t k, const int32_t *part, int32_t *conn,
+hipError_t launch_gain_hub(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,
                            const HubView &h, hipStream_t s);
 // Zero the hub rows and accumulate them again from the hubs' edge chunks.
-hipError_t launch_rebuild_hub_rows(const GraphView &g, int32_t k, const int32_t *part,
+hipError_t launch_rebuild_hub_rows(const GraphView &g, int32_t k, const PartView &part,
                                    int32_t *conn, const HubView &h, hipStream_t s);
+// Compact copy of part (bytes = 1 or 2).
+hipError_t launch_pack_part(int64_t n, const int32_t *part, void *pc, int bytes, hipStream_t s);
 hipError_t launch_hub_bits(const HubView &h, uint32_t *bits, hipStream_t s);
 // Per node: 2*cut into counters[cut_slot], penalty buckets of the available
 // nodes (bucket may be null), block weights W[part] += c (W may be null),
@@ -301,14 +324,14 @@ hipError_t launch_best_move(const GraphView &g, int32_t k, const int32_t *part, 
                             const int64_t *pen1, int64_t lmax, int mode, int64_t *key,
                             int64_t *pen, unsigned long long *counters, hipStream_t s);
 // With gp_out the pessimistic gains are stored (decided by launch_filter_seq).
-hipError_t launch_filter(const GraphView &g, const int32_t *part, const int64_t *key,
-                         const int64_t *pen, int64_t low_t, int64_t hub_t, int32_t *mvto,
-                         uint8_t *accflag, unsigned long long *counters, int64_t *gp_out,
-                         hipStream_t s);
-hipError_t launch_filter_hub(const GraphView &g, const int32_t *part, const int64_t *key,
-                             const int64_t *pen, const HubView &h, int32_t *mvto,
-                             uint8_t *accflag, unsigned long long *counters, int64_t *gp_out,
-                             hipStream_t s);
+hipError_t launch_filter(const GraphView &g, const int32_t *part, const PartView &pv,
+                         const int64_t *key, const int64_t *pen, int64_t low_t, int64_t hub_t,
+                         int32_t *mvto, uint8_t *accflag, unsigned long long *counters,
+                         int64_t *gp_out, hipStream_t s);
+hipError_t launch_filter_hub(const GraphView &g, const int32_t *part, const PartView &pv,
+                             const int64_t *key, const int64_t *pen, const HubView &h,
+                             int32_t *mvto, uint8_t *accflag, unsigned long long *counters,
+                             int64_t *gp_out, hipStream_t s);
 hipError_t launch_filter_seq(const GraphView &g, int32_t k, const int32_t *cand,
                              const int32_t *count, int64_t nc, const int64_t *key,
                              const int64_t *gp, const int64_t *netpre, const int64_t *W,
@@ -331,10 +354,11 @@ hipError_t launch_seq_net(int64_t nc, const int32_t *cand, const int64_t *key, c
 // (counters[CNT_MOVED_DEG]) the neighbours' rows get integer-atomic deltas;
 // otherwise their gain-table tiles are marked and rebuilt from the new
 // partition. Hub rows are always rebuilt.
-hipError_t launch_apply(const GraphView &g, int32_t k, int32_t *part, int32_t *conn, int64_t *W,
-                        int32_t *mvto, int64_t low_t, int64_t hub_t, const HubView &h,
-                        const unsigned long long *counters, int64_t dirty_threshold,
-                        uint8_t *dirty, hipStream_t s);
+// pv: the compact partition copy to keep in step (pv.p writable, or bytes 4).
+hipError_t launch_apply(const GraphView &g, int32_t k, int32_t *part, const PartView &pv,
+                        int32_t *conn, int64_t *W, int32_t *mvto, int64_t low_t, int64_t hub_t,
+                        const HubView &h, const unsigned long long *counters,
+                        int64_t dirty_threshold, uint8_t *dirty, hipStream_t s);
 hipError_t launch_stats_final(int64_t *stats, const unsigned long long *counters, int64_t lmax,
                               int64_t iters, int64_t status, hipStream_t s);
 hipError_t launch_export_moves(int64_t n, const int64_t *key, const int64_t *pen,
