@@ -250,25 +250,42 @@ __device__ __forceinline__ int move_sign(int32_t x, int32_t a, int32_t b)
 // S3 for candidate v (a -> b, score sv): pessimistic gain over its row
 // [e0, e1) strided by `step` starting at e0 + off. An earlier candidate
 // neighbour u ((score, id) before v) contributes the worse of its current
-// and its target block.
+// and its target block. kEdgeUnroll edges per lane are loaded before their
+// gathers, so their latencies overlap.
+constexpr int kEdgeUnroll = 4;
 __device__ __forceinline__ int64_t pessimistic_part(const GraphView &g, const PartView &part,
                                                     const int64_t *key, int64_t v, int32_t a,
                                                     int32_t b, int64_t sv, int64_t e0, int64_t e1,
                                                     int off, int step)
 {
     int64_t acc = 0;
-    for (int64_t e = e0 + off; e < e1; e += step) {
-        const int32_t u = g.adjncy[e];
-        int f = move_sign(pget(part, u), a, b);
-        const int64_t ku = key[u];
-        if (ku >= 0) {
-            const int64_t su = ku >> 16;
-            if (su > sv || (su == sv && (int64_t)u < v)) {
-                const int ft = move_sign((int32_t)(ku & 0xFFFF), a, b);
-                f = ft < f ? ft : f;
-            }
+    for (int64_t e = e0 + off; e < e1; e += (int64_t)kEdgeUnroll * step) {
+        int32_t u[kEdgeUnroll], w[kEdgeUnroll];
+#pragma unroll
+        for (int i = 0; i < kEdgeUnroll; ++i) {
+            const int64_t ei = e + (int64_t)i * step;
+            u[i] = ei < e1 ? g.adjncy[ei] : -1;
+            w[i] = ei < e1 ? edge_weight(g, ei) : 0;
         }
-        acc += (int64_t)edge_weight(g, e) * f;
+        int32_t pu[kEdgeUnroll];
+        int64_t ku[kEdgeUnroll];
+#pragma unroll
+        for (int i = 0; i < kEdgeUnroll; ++i) {
+            pu[i] = u[i] >= 0 ? pget(part, u[i]) : -1;
+            ku[i] = u[i] >= 0 ? key[u[i]] : -1;
+        }
+#pragma unroll
+        for (int i = 0; i < kEdgeUnroll; ++i) {
+            int f = move_sign(pu[i], a, b);
+            if (ku[i] >= 0) {
+                const int64_t su = ku[i] >> 16;
+                if (su > sv || (su == sv && (int64_t)u[i] < v)) {
+                    const int ft = move_sign((int32_t)(ku[i] & 0xFFFF), a, b);
+                    f = ft < f ? ft : f;
+                }
+            }
+            acc += (int64_t)w[i] * f;
+        }
     }
     return acc;
 }
@@ -304,7 +321,8 @@ __device__ __forceinline__ void filter_class(const GraphView &g, const int32_t *
         acc = group_sum<G>(acc);
         bool take = false;
         if (ok && gl == 0 && gp_out) {
-            gp_out[v] = acc;  // decided later against the sequence-aware price
+            gp_out[v] = acc;  // eligible ones are decided against the sequence-aware price
+            accflag[v] = 0;
         } else if (ok && gl == 0) {
             take = acc * 65536 - pen[v] > 0;
             accflag[v] = take ? 1 : 0;
@@ -395,6 +413,7 @@ __global__ void k_filter_hub_final(const int64_t *key, const int64_t *pen, HubVi
     if (kv < 0) return;
     if (gp_out) {
         gp_out[v] = acc;
+        accflag[v] = 0;
         return;
     }
     const bool ok = acc * 65536 - pen[v] > 0;
@@ -429,14 +448,15 @@ hipError_t launch_filter_hub(const GraphView &g, const int32_t *part, const Part
     return hipGetLastError();
 }
 
-// Sequence-aware decision for each candidate of the id-ordered list: the
+// Sequence-aware decision for each eligible candidate (id-ordered list; the
+// filter pass already rejected the others): the
 // move into b is priced against W[b] plus the weight change netpre[v]
 // accumulated by the eligible candidates before v (Section 5.3: the penalty
 // of a move depends on c(V_j + u) when it is made). Accept iff the
 // pessimistic gain is positive, the move is not forbidden, and
 // gain * 2^16 - P > 0.
 __global__ __launch_bounds__(kBlock) void k_filter_seq(
-    GraphView g, int32_t k, const int32_t *__restrict__ cand, const int32_t *__restrict__ count,
+    GraphView g, int32_t k, const int32_t *__restrict__ cand, int64_t nc,
     const int64_t *__restrict__ key, const int64_t *__restrict__ gp,
     const int64_t *__restrict__ netpre, const int64_t *__restrict__ W,
     const int64_t *__restrict__ cb, const int64_t *__restrict__ penq, int64_t lmax, int mode,
@@ -448,7 +468,6 @@ __global__ __launch_bounds__(kBlock) void k_filter_seq(
         deg_lds = 0;
     }
     __syncthreads();
-    const int64_t nc = *count;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < nc;
          base += stride) {
@@ -490,16 +509,15 @@ __global__ __launch_bounds__(kBlock) void k_filter_seq(
     }
 }
 
-hipError_t launch_filter_seq(const GraphView &g, int32_t k, const int32_t *cand,
-                             const int32_t *count, int64_t nc, const int64_t *key,
-                             const int64_t *gp, const int64_t *netpre, const int64_t *W,
-                             const int64_t *cb, const int64_t *penq, int64_t lmax, int mode,
-                             int64_t hub_t, int32_t *mvto, uint8_t *accflag,
-                             unsigned long long *counters, hipStream_t s)
+hipError_t launch_filter_seq(const GraphView &g, int32_t k, const int32_t *cand, int64_t ne,
+                             const int64_t *key, const int64_t *gp, const int64_t *netpre,
+                             const int64_t *W, const int64_t *cb, const int64_t *penq,
+                             int64_t lmax, int mode, int64_t hub_t, int32_t *mvto,
+                             uint8_t *accflag, unsigned long long *counters, hipStream_t s)
 {
-    if (nc <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_filter_seq, dim3(grid_cap(nc, kBlock, 8192)), dim3(kBlock), 0, s, g, k,
-                       cand, count, key, gp, netpre, W, cb, penq, lmax, mode, hub_t, mvto, accflag,
+    if (ne <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_filter_seq, dim3(grid_cap(ne, kBlock, 8192)), dim3(kBlock), 0, s, g, k,
+                       cand, ne, key, gp, netpre, W, cb, penq, lmax, mode, hub_t, mvto, accflag,
                        counters);
     return hipGetLastError();
 }
@@ -532,15 +550,33 @@ __device__ __forceinline__ void apply_class(const GraphView &g, int32_t k, int32
         if (gl == 0) a = part[v];
         a = __shfl(a, lane & ~(G - 1));
         const int64_t e1 = g.xadj[v + 1];
-        if (dirty) {
-            for (int64_t e = g.xadj[v] + gl; e < e1; e += G) dirty[g.adjncy[e] / T] = 1;
-        } else {
-            for (int64_t e = g.xadj[v] + gl; e < e1; e += G) {
-                const int64_t u = g.adjncy[e];
-                if (is_hub(h, u)) continue;  // hub rows are rebuilt after the apply
-                const int32_t w = edge_weight(g, e);
-                atomicAdd(&conn[u * k + a], -w);
-                atomicAdd(&conn[u * k + b], w);
+        // kEdgeUnroll neighbours per lane are loaded before they are used
+        for (int64_t e = g.xadj[v] + gl; e < e1; e += (int64_t)kEdgeUnroll * G) {
+            int32_t u[kEdgeUnroll];
+#pragma unroll
+            for (int i = 0; i < kEdgeUnroll; ++i) {
+                const int64_t ei = e + (int64_t)i * G;
+                u[i] = ei < e1 ? g.adjncy[ei] : -1;
+            }
+            if (dirty) {
+#pragma unroll
+                for (int i = 0; i < kEdgeUnroll; ++i)
+                    if (u[i] >= 0) dirty[u[i] / T] = 1;
+            } else {
+                int32_t w[kEdgeUnroll];
+                bool hub[kEdgeUnroll];
+#pragma unroll
+                for (int i = 0; i < kEdgeUnroll; ++i) {
+                    const int64_t ei = e + (int64_t)i * G;
+                    w[i] = u[i] >= 0 ? edge_weight(g, ei) : 0;
+                    hub[i] = u[i] >= 0 && is_hub(h, u[i]);  // hub rows are rebuilt afterwards
+                }
+#pragma unroll
+                for (int i = 0; i < kEdgeUnroll; ++i) {
+                    if (u[i] < 0 || hub[i]) continue;
+                    atomicAdd(&conn[(int64_t)u[i] * k + a], -w[i]);
+                    atomicAdd(&conn[(int64_t)u[i] * k + b], w[i]);
+                }
             }
         }
         if (gl == 0) {

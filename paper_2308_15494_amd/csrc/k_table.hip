@@ -192,9 +192,9 @@ int gain_tile_nodes(int32_t k)
     return t;
 }
 
-static size_t gain_tile_lds(int32_t k, int T)
+static size_t gain_tile_lds(int32_t k, int T, bool p16)
 {
-    size_t rows = (size_t)T * k * 4;
+    size_t rows = (size_t)T * k * (p16 ? 2 : 4);
     if (rows < 4) rows = 4;
     return rows + (size_t)(T + 1) * 4 + (size_t)T * 8 + 64;
 }
@@ -216,14 +216,20 @@ __device__ __forceinline__ int upper_index(const int32_t *a, int cnt, int32_t p)
 // node map is a binary search over the tile's degree prefix), write the rows
 // back as one contiguous span. Hub rows are written as zeros here and filled
 // by k_gain_hub.
-template <bool WEIGHTED>
+//
+// P16: when every tiled row sum fits 16 bits (non-hub weighted degrees below
+// 2^16), two counters share an LDS word (entry i in the low half of word
+// i / 2 if i is even, the high half otherwise). A sum never carries into the
+// neighbouring half, the tile takes half the LDS and twice as many
+// workgroups stay resident per CU to hide the gathers' latency.
+template <bool WEIGHTED, bool P16>
 __device__ __forceinline__ void gain_tile_body(const GraphView &g, int32_t k, int T,
                                                const PartView &part,
                                                int32_t *__restrict__ conn, int64_t hub_t)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     int32_t *tile = (int32_t *)lds_raw;
-    const size_t rows_bytes = ((size_t)T * k * 4 + 15) & ~(size_t)15;
+    const size_t rows_bytes = ((size_t)T * k * (P16 ? 2 : 4) + 15) & ~(size_t)15;
     int32_t *vstart = (int32_t *)(lds_raw + rows_bytes);
     int64_t *gstart = (int64_t *)(lds_raw + rows_bytes + (((size_t)(T + 1) * 4 + 15) & ~(size_t)15));
     __shared__ int32_t scan_lds[4];
@@ -232,12 +238,14 @@ __device__ __forceinline__ void gain_tile_body(const GraphView &g, int32_t k, in
     const int nt = (int)((g.n - v0) < T ? (g.n - v0) : T);
     const int tid = threadIdx.x;
     const int64_t kk = k;
+    const int entries = nt * k;
 
     {
         int4 *t4 = (int4 *)tile;
-        const int n4 = (nt * k) >> 2;
+        const int words = P16 ? (entries + 1) >> 1 : entries;
+        const int n4 = words >> 2;
         for (int i = tid; i < n4; i += kBlock) t4[i] = make_int4(0, 0, 0, 0);
-        for (int i = (n4 << 2) + tid; i < nt * k; i += kBlock) tile[i] = 0;
+        for (int i = (n4 << 2) + tid; i < words; i += kBlock) tile[i] = 0;
     }
 
     // virtual degrees (hubs contribute none) and their exclusive prefix,
@@ -282,33 +290,48 @@ __device__ __forceinline__ void gain_tile_body(const GraphView &g, int32_t k, in
         for (int i = 0; i < kUnroll; ++i) pu[i] = node[i] >= 0 ? pget(part, u[i]) : -1;
 #pragma unroll
         for (int i = 0; i < kUnroll; ++i)
-            if ((unsigned)pu[i] < (unsigned)k) atomicAdd(&tile[node[i] * k + pu[i]], w[i]);
+            if ((unsigned)pu[i] < (unsigned)k) {
+                const int idx = node[i] * k + pu[i];
+                if (P16) atomicAdd(&tile[idx >> 1], w[i] << ((idx & 1) << 4));
+                else atomicAdd(&tile[idx], w[i]);
+            }
     }
     __syncthreads();
 
     // coalesced write-back of the contiguous rows [v0, v0 + nt)
     int32_t *dst = conn + v0 * kk;
-    const int64_t total_ints = (int64_t)nt * k;
+    const int64_t total_ints = entries;
+    int64_t done = 0;
     if (((uintptr_t)dst & 15) == 0) {
         const int64_t n4 = total_ints >> 2;
         int4 *d4 = (int4 *)dst;
-        const int4 *s4 = (const int4 *)tile;
-        for (int64_t i = tid; i < n4; i += kBlock) d4[i] = s4[i];
-        for (int64_t i = (n4 << 2) + tid; i < total_ints; i += kBlock) dst[i] = tile[i];
+        if (P16) {
+            const uint2 *s2 = (const uint2 *)tile;
+            for (int64_t i = tid; i < n4; i += kBlock) {
+                const uint2 x = s2[i];
+                d4[i] = make_int4((int)(x.x & 0xFFFF), (int)(x.x >> 16), (int)(x.y & 0xFFFF),
+                                  (int)(x.y >> 16));
+            }
+        } else {
+            const int4 *s4 = (const int4 *)tile;
+            for (int64_t i = tid; i < n4; i += kBlock) d4[i] = s4[i];
+        }
+        done = n4 << 2;
+    }
+    if (P16) {
+        const uint16_t *t16 = (const uint16_t *)tile;
+        for (int64_t i = done + tid; i < total_ints; i += kBlock) dst[i] = t16[i];
     } else {
-        for (int64_t i = tid; i < total_ints; i += kBlock) dst[i] = tile[i];
+        for (int64_t i = done + tid; i < total_ints; i += kBlock) dst[i] = tile[i];
     }
 }
-
-template <bool WEIGHTED>
+template <bool WEIGHTED, bool P16>
 __global__ __launch_bounds__(kBlock) void k_gain_tile(GraphView g, int32_t k, int T, PartView part,
                                                        int32_t *__restrict__ conn, int64_t hub_t)
 {
-    gain_tile_body<WEIGHTED>(g, k, T, part, conn, hub_t);
+    gain_tile_body<WEIGHTED, P16>(g, k, T, part, conn, hub_t);
 }
-
-// Same tiles, rebuilt only where a flag is set (flags are cleared).
-template <bool WEIGHTED>
+template <bool WEIGHTED, bool P16>
 __global__ __launch_bounds__(kBlock) void k_gain_refresh(GraphView g, int32_t k, int T,
                                                           PartView part,
                                                           int32_t *__restrict__ conn,
@@ -317,7 +340,7 @@ __global__ __launch_bounds__(kBlock) void k_gain_refresh(GraphView g, int32_t k,
     if (!dirty[blockIdx.x]) return;
     __syncthreads();
     if (threadIdx.x == 0) dirty[blockIdx.x] = 0;
-    gain_tile_body<WEIGHTED>(g, k, T, part, conn, hub_t);
+    gain_tile_body<WEIGHTED, P16>(g, k, T, part, conn, hub_t);
 }
 
 hipError_t launch_gain_tile(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,
@@ -326,22 +349,24 @@ hipError_t launch_gain_tile(const GraphView &g, int32_t k, const PartView &part,
     if (g.n <= 0) return hipSuccess;
     const int T = gain_tile_nodes(k);
     const int64_t tiles = (g.n + T - 1) / T;
-    const size_t lds = gain_tile_lds(k, T);
-    if (dirty) {
-        if (g.adjwgt)
-            hipLaunchKernelGGL(k_gain_refresh<true>, dim3((unsigned)tiles), dim3(kBlock), lds, s, g,
-                               k, T, part, conn, hub_t, dirty);
-        else
-            hipLaunchKernelGGL(k_gain_refresh<false>, dim3((unsigned)tiles), dim3(kBlock), lds, s, g,
-                               k, T, part, conn, hub_t, dirty);
-    } else {
-        if (g.adjwgt)
-            hipLaunchKernelGGL(k_gain_tile<true>, dim3((unsigned)tiles), dim3(kBlock), lds, s, g, k,
-                               T, part, conn, hub_t);
-        else
-            hipLaunchKernelGGL(k_gain_tile<false>, dim3((unsigned)tiles), dim3(kBlock), lds, s, g, k,
-                               T, part, conn, hub_t);
-    }
+    const size_t lds = gain_tile_lds(k, T, g.tile16 != 0);
+#define UPR_TILE(KERN, WW, PP, ...)                                                                 \
+    hipLaunchKernelGGL((KERN<WW, PP>), dim3((unsigned)tiles), dim3(kBlock), lds, s, g, k, T, part, \
+                       conn, hub_t __VA_ARGS__)
+#define UPR_TILE_ALL(KERN, ...)                                                                     \
+    do {                                                                                            \
+        if (g.adjwgt) {                                                                             \
+            if (g.tile16) UPR_TILE(KERN, true, true, __VA_ARGS__);                                  \
+            else UPR_TILE(KERN, true, false, __VA_ARGS__);                                          \
+        } else {                                                                                    \
+            if (g.tile16) UPR_TILE(KERN, false, true, __VA_ARGS__);                                 \
+            else UPR_TILE(KERN, false, false, __VA_ARGS__);                                         \
+        }                                                                                           \
+    } while (0)
+    if (dirty) UPR_TILE_ALL(k_gain_refresh, , dirty);
+    else UPR_TILE_ALL(k_gain_tile, );
+#undef UPR_TILE_ALL
+#undef UPR_TILE
     return hipGetLastError();
 }
 

@@ -59,8 +59,7 @@ struct upr_ctx {
     // sequence-aware penalty
     int64_t *gp = nullptr;       // [n] pessimistic gains of candidates
     uint8_t *avail = nullptr;    // [n] available for rebalancing
-    int32_t *cand = nullptr;     // [n] candidates in id order
-    int32_t *cand_count = nullptr;
+    int32_t *cand = nullptr;     // [n] eligible candidates in id order
     uint64_t *ev_key = nullptr, *ev_key2 = nullptr;  // [2n]
     uint32_t *ev_val = nullptr, *ev_val2 = nullptr;  // [2n]
     int64_t *ev_prefix = nullptr;                     // [2n]
@@ -143,7 +142,6 @@ void free_workspace(upr_ctx *c)
     dfree(c->gp);
     dfree(c->avail);
     dfree(c->cand);
-    dfree(c->cand_count);
     dfree(c->ev_key);
     dfree(c->ev_key2);
     dfree(c->ev_val);
@@ -184,7 +182,7 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
               dalloc(&c->dirty, N) == hipSuccess && dalloc(&c->gp, N) == hipSuccess &&
               dalloc(&c->pc, N) == hipSuccess &&
               dalloc(&c->avail, N) == hipSuccess && dalloc(&c->cand, N) == hipSuccess &&
-              dalloc(&c->cand_count, 1) == hipSuccess && dalloc(&c->ev_key, 2 * N) == hipSuccess &&
+              dalloc(&c->ev_key, 2 * N) == hipSuccess &&
               dalloc(&c->ev_key2, 2 * N) == hipSuccess && dalloc(&c->ev_val, 2 * N) == hipSuccess &&
               dalloc(&c->ev_val2, 2 * N) == hipSuccess && dalloc(&c->ev_prefix, 2 * N) == hipSuccess &&
               dalloc(&c->netpre, N) == hipSuccess &&
@@ -545,6 +543,9 @@ int upr_plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipStrea
         if (p->maxwdeg >= ((int64_t)1 << 31) - 1)
             return bail(UPR_E_GRAPH, "a weighted degree does not fit int32 (gain table entries are int32)");
         if (p->total >= ((int64_t)1 << 62)) return bail(UPR_E_GRAPH, "total node weight >= 2^62");
+        // 16-bit gain-table counters in LDS: unit weights and a hub threshold
+        // below 2^16 bound every tiled row sum, else the largest weighted degree
+        p->g.tile16 = ((!g.adjwgt && p->hub_t < 65536) || p->maxwdeg < 65536) ? 1 : 0;
         if (p->nh > 0) {
             std::vector<int32_t> ids(p->nh);
             if (hipMemcpy(ids.data(), hub_list, sizeof(int32_t) * p->nh, hipMemcpyDeviceToHost) != hipSuccess)
@@ -725,15 +726,20 @@ static int round_common(upr_ctx *c, const upr_plan *p, const upr_params *q, int3
                 HIP_TRY(c, launch_filter_hub(p->g, part, pv, c->key, c->pen, h, c->mvto, c->accflag,
                                              c->counters, gp_out, s));
                 if (q->seq_penalty) {
-                    HIP_TRY(c, launch_seq_select(n, c->key, c->cand, c->cand_count, c->seq_temp,
+                    // eligible candidates in id order; their number sizes the sort
+                    HIP_TRY(c, launch_seq_select(n, c->key, c->gp, c->cand,
+                                                 c->counters + CNT_ELIG, c->seq_temp,
                                                  c->seq_temp_size, s));
-                    HIP_TRY(c, launch_seq_net(nc, c->cand, c->key, part, p->g.vwgt, c->gp, c->avail,
-                                              c->ev_key, c->ev_key2, c->ev_val, c->ev_val2,
-                                              c->ev_prefix, c->netpre, c->seq_temp,
-                                              c->seq_temp_size, s));
-                    HIP_TRY(c, launch_filter_seq(p->g, k, c->cand, c->cand_count, nc, c->key, c->gp,
-                                                 c->netpre, W, c->bucket, c->penq, lmax, q->mode,
-                                                 p->hub_t, c->mvto, c->accflag, c->counters, s));
+                    rc = sync_counters(c, s);
+                    if (rc) return rc;
+                    const int64_t ne = (int64_t)c->pinned[CNT_ELIG];
+                    HIP_TRY(c, launch_seq_net(ne, c->cand, c->key, part, p->g.vwgt, c->avail, k,
+                                              seq_score_bits(p->maxwdeg), c->ev_key, c->ev_key2,
+                                              c->ev_val, c->ev_val2, c->ev_prefix, c->netpre,
+                                              c->seq_temp, c->seq_temp_size, s));
+                    HIP_TRY(c, launch_filter_seq(p->g, k, c->cand, ne, c->key, c->gp, c->netpre, W,
+                                                 c->bucket, c->penq, lmax, q->mode, p->hub_t,
+                                                 c->mvto, c->accflag, c->counters, s));
                 }
             }
             {

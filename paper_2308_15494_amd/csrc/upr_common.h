@@ -30,6 +30,7 @@ enum Counter {
     CNT_BAD_INPUT,     // nonzero: a part value was out of range
     CNT_TMP,           // scratch accumulator for standalone calls
     CNT_MOVED_DEG,     // sum of the degrees of the nodes marked to move
+    CNT_ELIG,          // eligible candidates (pessimistic gain > 0), sequence-aware filter
     CNT_COUNT = 32
 };
 
@@ -43,6 +44,7 @@ struct GraphView {
     const int32_t *adjncy;
     const int32_t *adjwgt;  // may be null: unit edge weights
     const int32_t *vwgt;    // may be null: unit node weights
+    int32_t tile16 = 0;     // every non-hub weighted degree is below 2^16
 };
 
 // Read-only view of the partition for neighbour gathers: the caller's int32
@@ -332,20 +334,22 @@ hipError_t launch_filter_hub(const GraphView &g, const int32_t *part, const Part
                              const int64_t *key, const int64_t *pen, const HubView &h,
                              int32_t *mvto, uint8_t *accflag, unsigned long long *counters,
                              int64_t *gp_out, hipStream_t s);
-hipError_t launch_filter_seq(const GraphView &g, int32_t k, const int32_t *cand,
-                             const int32_t *count, int64_t nc, const int64_t *key,
-                             const int64_t *gp, const int64_t *netpre, const int64_t *W,
-                             const int64_t *cb, const int64_t *penq, int64_t lmax, int mode,
-                             int64_t hub_t, int32_t *mvto, uint8_t *accflag,
-                             unsigned long long *counters, hipStream_t s);
+hipError_t launch_filter_seq(const GraphView &g, int32_t k, const int32_t *cand, int64_t ne,
+                             const int64_t *key, const int64_t *gp, const int64_t *netpre,
+                             const int64_t *W, const int64_t *cb, const int64_t *penq,
+                             int64_t lmax, int mode, int64_t hub_t, int32_t *mvto,
+                             uint8_t *accflag, unsigned long long *counters, hipStream_t s);
 
-// Sequence-aware penalty (k_seq.hip): candidate list in id order, then the
-// weight change of each candidate's target accumulated before it.
+// Sequence-aware penalty (k_seq.hip): the eligible candidates (pessimistic
+// gain > 0) in id order, then the weight change of each one's target
+// accumulated before it. Score bits: scores are below 2^seq_score_bits.
+int seq_score_bits(int64_t max_wdeg);
 size_t seq_temp_bytes(int64_t n);
-hipError_t launch_seq_select(int64_t n, const int64_t *key, int32_t *cand, int32_t *count,
-                             void *temp, size_t temp_bytes, hipStream_t s);
-hipError_t launch_seq_net(int64_t nc, const int32_t *cand, const int64_t *key, const int32_t *part,
-                          const int32_t *vwgt, const int64_t *gp, const uint8_t *avail,
+hipError_t launch_seq_select(int64_t n, const int64_t *key, const int64_t *gp, int32_t *cand,
+                             unsigned long long *count, void *temp, size_t temp_bytes,
+                             hipStream_t s);
+hipError_t launch_seq_net(int64_t ne, const int32_t *cand, const int64_t *key, const int32_t *part,
+                          const int32_t *vwgt, const uint8_t *avail, int32_t k, int sb,
                           uint64_t *ev_key, uint64_t *ev_key2, uint32_t *ev_val,
                           uint32_t *ev_val2, int64_t *prefix, int64_t *netpre, void *temp,
                           size_t temp_bytes, hipStream_t s);

@@ -126,6 +126,64 @@ def test_gain_table_and_cut(upr, ctx, case):
     assert int(cut.item()) == O.cut_edges(g, part)
 
 
+def star_graph(n, centers, total, seed):
+    """Random light edges (weights 1..50) away from the centers plus, at each
+    center, a star of 16 leaves whose edge weights add up to exactly `total`."""
+    rng = np.random.default_rng(seed)
+    u = rng.integers(0, n, size=4 * n)
+    v = rng.integers(0, n, size=4 * n)
+    w = rng.integers(1, 51, size=4 * n)
+    keep = ~(np.isin(u, centers) | np.isin(v, centers))
+    u, v, w = u[keep], v[keep], w[keep]
+    nr = u.size
+    eu, ev, ew = [u], [v], [w]
+    nxt = max(centers) + 1
+    for c in centers:
+        leaves = 16
+        wt = np.full(leaves, total // leaves, np.int64)
+        wt[: total % leaves] += 1
+        eu.append(np.full(leaves, c))
+        ev.append(np.arange(nxt, nxt + leaves))
+        ew.append(wt)
+        nxt += leaves
+    u, v, w = np.concatenate(eu), np.concatenate(ev), np.concatenate(ew)
+    # star edges first so that duplicates keep the star weight
+    order = np.r_[np.arange(nr, u.size), np.arange(nr)]
+    xadj, adjncy, adjwgt = gg.csr_from_undirected(n, u[order], v[order], w[order])
+    return gg._finish(gg.Graph(n, xadj, adjncy, adjwgt, None, name=f"star{total}"))
+
+
+@pytest.mark.parametrize("total", [65535, 65536, 200000])
+def test_gain_table_counter_width(upr, ctx, total):
+    """Tiled rows count in 16-bit LDS halves while every weighted degree is
+    below 2^16 and in 32-bit words otherwise. Stars whose weights add up to
+    2^16 - 1 (the largest packed count, no carry into the neighbour entry),
+    2^16 and more, with their leaves all in one block, then rounds."""
+    import torch
+    n = 3000
+    centers = [0, 1001, 1502]
+    g = star_graph(n, centers, total, seed=total % 97)
+    for k in (2, 3, 64):
+        part = gg.random_partition(g.n, k, 5)
+        nxt = max(centers) + 1
+        for i, c in enumerate(centers):
+            part[nxt + 16 * i: nxt + 16 * (i + 1)] = (i + 1) % k
+        wdeg = np.bincount(np.repeat(np.arange(g.n), g.degrees()), weights=g.adjwgt, minlength=g.n)
+        say(f"counter width total={total} k={k} max_wdeg={int(wdeg.max())}")
+        dg = upr.DeviceGraph(g)
+        plan = upr.Plan(ctx, dg)
+        conn = upr.gain_table(ctx, plan, k, to_dev(part))
+        torch.cuda.synchronize()
+        ref = O.gain_table(g, k, part)
+        for i, c in enumerate(centers):
+            assert ref[c, (i + 1) % k] == total
+        assert np.array_equal(conn.cpu().numpy().reshape(g.n, k), ref)
+        pr = Pair(upr, ctx, g, k, part)
+        for r in range(1, 4):
+            ost, odbg = pr.round(tau=gg.tau_schedule(r, 3))
+            pr.compare(ost, odbg, f"total {total} k {k} round {r}")
+
+
 def test_hub_paths(upr, ctx, monkeypatch):
     """Force a low hub threshold so the multi-workgroup hub kernels carry
     real rows (and chunks span several workgroups)."""
