@@ -142,13 +142,13 @@ __global__ __launch_bounds__(kBlock) void k_best_move(
             for (int q = gl; q < nvec; q += G) {
                 int32_t c4[V];
                 if constexpr (V == 4) {
-                    const int4 x = ((const int4 *)row)[q];
+                    const v4i32 x = stream_load4(row + 4 * q);
                     c4[0] = x.x;
                     c4[1] = x.y;
                     c4[2] = x.z;
                     c4[3] = x.w;
                 } else {
-                    c4[0] = row[q];
+                    c4[0] = stream_load(row + q);
                 }
 #pragma unroll
                 for (int t = 0; t < V; ++t) {
@@ -264,8 +264,8 @@ __device__ __forceinline__ int64_t pessimistic_part(const GraphView &g, const Pa
 #pragma unroll
         for (int i = 0; i < kEdgeUnroll; ++i) {
             const int64_t ei = e + (int64_t)i * step;
-            u[i] = ei < e1 ? g.adjncy[ei] : -1;
-            w[i] = ei < e1 ? edge_weight(g, ei) : 0;
+            u[i] = ei < e1 ? stream_load(g.adjncy + ei) : -1;
+            w[i] = ei < e1 ? stream_edge_weight(g, ei) : 0;
         }
         int32_t pu[kEdgeUnroll];
         int64_t ku[kEdgeUnroll];

@@ -101,6 +101,23 @@ __device__ __forceinline__ int32_t edge_weight(const GraphView &g, int64_t e)
     return g.adjwgt ? g.adjwgt[e] : 1;
 }
 
+// Streaming reads: data read once per pass (adjacency, table rows) carry the
+// non-temporal hint, so that the L2 favours the small arrays gathered at
+// random (compact partition, keys).
+typedef int32_t v4i32 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ int32_t stream_load(const int32_t *p)
+{
+    return __builtin_nontemporal_load(p);
+}
+__device__ __forceinline__ v4i32 stream_load4(const int32_t *p16)
+{
+    return __builtin_nontemporal_load((const v4i32 *)p16);
+}
+__device__ __forceinline__ int32_t stream_edge_weight(const GraphView &g, int64_t e)
+{
+    return g.adjwgt ? stream_load(g.adjwgt + e) : 1;
+}
+
 // 3^l for l < 54 as a 128-bit value.
 __device__ __forceinline__ unsigned __int128 pow3_u128(int l)
 {
