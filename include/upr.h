@@ -47,9 +47,11 @@ extern "C" {
 #define UPR_E_HIP        -5   /* a HIP runtime call or kernel launch failed */
 
 #define UPR_MAX_K 8192        /* largest supported number of blocks (a gain-table row fits LDS) */
+#define UPR_MAX_BATCH_BLOCKS 65536  /* largest graphs-times-k of a batch (sort key width) */
 
 typedef struct upr_ctx upr_ctx;
 typedef struct upr_plan upr_plan;
+typedef struct upr_batch upr_batch;
 
 /* Graph in symmetric CSR form (Section 2: G = (V, E, c, omega)). */
 typedef struct {
@@ -169,6 +171,42 @@ int upr_rebalance(upr_ctx *ctx, const upr_plan *plan, const upr_params *params, 
  * Valid until the next call on the context. For diagnosis. */
 int upr_last_moves(upr_ctx *ctx, int64_t n, int32_t *target, int64_t *score, int64_t *pen,
                    uint8_t *accept, hipStream_t stream);
+
+/* Batches: many independent graphs refined by the same kernel launches.
+ *
+ * The batch holds the disjoint union of ng graphs with a common k and eps:
+ * node v of graph g is node off[g] + v of the union (off from
+ * upr_batch_info), and the union is refined as one graph whose blocks are
+ * numbered globally: block j of graph g is g * k + j. Each graph keeps its
+ * own L_max (from its own total node weight), its own penalty factor tau and
+ * its own statistics, and no kernel lets two graphs interact, so every
+ * graph's results are exactly those of upr_refine_round on it alone.
+ * upr_batch_create copies the graphs into the union (the inputs may be
+ * freed afterwards) and plans it; it validates like upr_plan_create, plus
+ * that every graph names only its own nodes. Enqueued on `stream` and
+ * synchronised. ng * k <= UPR_MAX_BATCH_BLOCKS. */
+int upr_batch_create(upr_ctx *ctx, const upr_graph *graphs, int32_t ng, int32_t k,
+                     int32_t eps_num, int32_t eps_den, upr_batch **out, hipStream_t stream);
+void upr_batch_destroy(upr_batch *batch);
+/* Union size, node offsets off[ng + 1] and L_max[ng] (any pointer may be NULL). */
+int upr_batch_info(const upr_batch *batch, int64_t *n_total, int64_t *nnz_total, int64_t *node_off,
+                   int64_t *lmax);
+/* One round of every graph of the batch (the steps of upr_refine_round).
+ * params: k and eps must be the batch's; tau_num / tau_den: host arrays [ng]
+ * with each graph's penalty factor, or both NULL for params->tau everywhere.
+ * part: device int32 [n_total], global block ids (graph g's nodes hold values
+ * in [g*k, g*k + k)); conn: device int32 [n_total * k], row v indexed by the
+ * local block j; block_w: device int64 [ng * k], indexed by global block;
+ * stats: device int64 [ng * UPR_STATS_LEN], graph g's statistics at
+ * g * UPR_STATS_LEN. A part value outside its graph's range is reported as
+ * UPR_E_ARG. Rebalancing stops per graph as in upr_refine_round; the call
+ * synchronises once per sub-iteration of the slowest graph. */
+int upr_batch_refine_round(upr_ctx *ctx, upr_batch *batch, const upr_params *params,
+                           const int32_t *tau_num, const int32_t *tau_den, int32_t *part,
+                           int32_t *conn, int64_t *block_w, int64_t *stats, hipStream_t stream);
+/* Rebalancing alone of every graph of the batch (as upr_rebalance). */
+int upr_batch_rebalance(upr_ctx *ctx, upr_batch *batch, const upr_params *params, int32_t *part,
+                        int32_t *conn, int64_t *block_w, int64_t *stats, hipStream_t stream);
 
 /* Host-side helpers (no device work). */
 /* L_max = floor((1 + eps) * ceil(total / k)) with eps = eps_num / eps_den. */

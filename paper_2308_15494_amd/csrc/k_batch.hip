@@ -1,0 +1,154 @@
+// Batches: many independent graphs refined by the same launches.
+//
+// A batch is the disjoint union of its graphs, built once: node ids of graph
+// g are shifted by its node offset, so the union is an ordinary CSR graph and
+// every kernel of the round runs over it unchanged except for the block ids
+// (global id g*k + j, see Blocks). This file holds the union construction and
+// the per-graph statistics.
+#include "upr_common.h"
+
+#include <algorithm>
+
+namespace upr {
+
+namespace {
+
+int grid_for(int64_t items, int per_block, int cap)
+{
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+}  // namespace
+
+// Copy graph g into the union: rows shifted by the edge offset, neighbour
+// ids by the node offset; missing weights become 1.
+__global__ void k_batch_copy(GraphView src, int64_t node_off, int64_t edge_off, int64_t *xadj,
+                             int32_t *adjncy, int32_t *adjwgt, int32_t *vwgt, int last)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t v = t; v < src.n; v += stride) {
+        xadj[node_off + v] = edge_off + src.xadj[v];
+        if (vwgt) vwgt[node_off + v] = src.vwgt ? src.vwgt[v] : 1;
+    }
+    if (last && t == 0 && src.n > 0) xadj[node_off + src.n] = edge_off + src.xadj[src.n];
+    const int64_t nnz = src.n > 0 ? src.xadj[src.n] : 0;
+    for (int64_t e = t; e < nnz; e += stride) {
+        adjncy[edge_off + e] = (int32_t)(node_off + src.adjncy[e]);
+        if (adjwgt) adjwgt[edge_off + e] = src.adjwgt ? src.adjwgt[e] : 1;
+    }
+}
+
+hipError_t launch_batch_copy(const GraphView &src, int64_t node_off, int64_t edge_off,
+                             int64_t nnz, int64_t *xadj, int32_t *adjncy, int32_t *adjwgt,
+                             int32_t *vwgt, int last, hipStream_t s)
+{
+    const int64_t items = std::max<int64_t>(src.n, nnz);
+    hipLaunchKernelGGL(k_batch_copy, dim3(grid_for(items, kBlock, 4096)), dim3(kBlock), 0, s, src,
+                       node_off, edge_off, xadj, adjncy, adjwgt, vwgt, last);
+    return hipGetLastError();
+}
+
+// Per graph (one workgroup each): total node weight and the largest one.
+__global__ void k_batch_totals(const int64_t *goff, const int32_t *vwgt, int64_t *out)
+{
+    __shared__ int64_t red[4];
+    const int g = blockIdx.x;
+    const int64_t v0 = goff[g], v1 = goff[g + 1];
+    int64_t sum = 0, mx = 0;
+    for (int64_t v = v0 + threadIdx.x; v < v1; v += kBlock) {
+        const int64_t c = vwgt ? vwgt[v] : 1;
+        sum += c;
+        mx = c > mx ? c : mx;
+    }
+    sum = block_sum(sum, red);
+    for (int off = 32; off > 0; off >>= 1) {
+        const int64_t o = __shfl_xor(mx, off);
+        mx = o > mx ? o : mx;
+    }
+    __shared__ int64_t mred[4];
+    if (lane_id() == 0) mred[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t m = mred[0];
+        for (int i = 1; i < kBlock / 64; ++i) m = mred[i] > m ? mred[i] : m;
+        out[2 * g] = sum;
+        out[2 * g + 1] = m;
+    }
+}
+
+hipError_t launch_batch_totals(const int64_t *goff, int32_t ng, const int32_t *vwgt, int64_t *out,
+                               hipStream_t s)
+{
+    if (ng <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_totals, dim3(ng), dim3(kBlock), 0, s, goff, vwgt, out);
+    return hipGetLastError();
+}
+
+// Per-graph candidate and accepted counts after the filter.
+__global__ __launch_bounds__(kBlock) void k_batch_move_stats(int64_t n, Blocks bk,
+                                                              const int32_t *part,
+                                                              const int64_t *key,
+                                                              const uint8_t *accflag,
+                                                              int64_t *gstat)
+{
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < n;
+         base += stride) {
+        const int64_t v = base + lane_id();
+        bool cand = false, acc = false;
+        int64_t gk = 0;
+        if (v < n) {
+            cand = key[v] >= 0;
+            acc = cand && accflag[v];
+            gk = (int64_t)bk.graph(part[v]) * GS_COUNT;
+        }
+        wave_hist_add(gstat, gk + GS_CAND, 1, cand);
+        wave_hist_add(gstat, gk + GS_ACC, 1, acc);
+    }
+}
+
+hipError_t launch_batch_move_stats(int64_t n, const Blocks &bk, const int32_t *part,
+                                   const int64_t *key, const uint8_t *accflag, int64_t *gstat,
+                                   hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_move_stats, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, s, n,
+                       bk, part, key, accflag, gstat);
+    return hipGetLastError();
+}
+
+// Per-graph round statistics (UPR_STATS_LEN = 12 per graph, same slots as a
+// single graph's). host3[g] = {rebalancing sub-iterations, status, moves}.
+__global__ void k_batch_stats_final(int32_t ng, const int64_t *gstat, const int64_t *lmax,
+                                    const int64_t *host3, int moved, int64_t *stats)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ng) return;
+    const int64_t *gs = gstat + (int64_t)g * GS_COUNT;
+    int64_t *st = stats + (int64_t)g * 12;
+    st[0] = lmax[g];
+    st[1] = gs[GS_CUT2_BEFORE] / 2;
+    st[2] = (moved ? gs[GS_CUT2_MOVES] : gs[GS_CUT2_BEFORE]) / 2;
+    st[3] = gs[GS_CUT2_AFTER] / 2;
+    st[4] = gs[GS_CAND];
+    st[5] = gs[GS_ACC];
+    st[6] = host3[3 * g + 2];
+    st[7] = host3[3 * g];
+    st[8] = host3[3 * g + 1];
+    for (int i = 9; i < 12; ++i) st[i] = 0;
+}
+
+hipError_t launch_batch_stats_final(int32_t ng, const int64_t *gstat, const int64_t *lmax,
+                                    const int64_t *host3, int moved, int64_t *stats, hipStream_t s)
+{
+    if (ng <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_stats_final, dim3((ng + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                       ng, gstat, lmax, host3, moved, stats);
+    return hipGetLastError();
+}
+
+}  // namespace upr

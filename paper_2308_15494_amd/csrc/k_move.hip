@@ -25,24 +25,32 @@ static int grid_cap(int64_t items, int per_block, int cap)
 // ----------------------------------------------------------- round init --
 
 // Zero the counters, the penalty buckets and (rebuild form) the block
-// weights; publish the round's Q16 penalty table.
-__global__ void k_round_init(int32_t k, int64_t *bucket, int64_t *W, PenTable pq, int64_t *penq,
-                             unsigned long long *counters, int zero_w)
+// weights; for a single graph publish the round's Q16 penalty table and L_max.
+__global__ void k_round_init(Blocks bk, int64_t *bucket, int64_t *W, PenTable pq, int64_t lmax,
+                             int single, unsigned long long *counters, int zero_w)
 {
+    const int64_t K = bk.total();
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = tid; i < (int64_t)k * kSlots; i += stride) bucket[i] = 0;
+    for (int64_t i = tid; i < K * kSlots; i += stride) bucket[i] = 0;
     if (zero_w)
-        for (int64_t i = tid; i < k; i += stride) W[i] = 0;
-    if (tid < kSlots) penq[tid] = pq.q[tid];
+        for (int64_t i = tid; i < K; i += stride) W[i] = 0;
+    if (single) {
+        if (tid < kSlots) ((int64_t *)bk.penq)[tid] = pq.q[tid];
+        if (tid == 0) {
+            ((int64_t *)bk.lmax)[0] = lmax;
+            ((int64_t *)bk.src_lmax)[0] = lmax;
+        }
+    }
     if (tid < CNT_COUNT) counters[tid] = 0;
 }
 
-hipError_t launch_round_init(int32_t k, int64_t *bucket, int64_t *W, const PenTable &pq,
-                             int64_t *penq, unsigned long long *counters, int zero_w, hipStream_t s)
+hipError_t launch_round_init(const Blocks &bk, int64_t *bucket, int64_t *W, const PenTable &pq,
+                             int64_t lmax, int single, unsigned long long *counters, int zero_w,
+                             hipStream_t s)
 {
-    hipLaunchKernelGGL(k_round_init, dim3(grid_cap((int64_t)k * kSlots, kBlock * 4, 1024)),
-                       dim3(kBlock), 0, s, k, bucket, W, pq, penq, counters, zero_w);
+    hipLaunchKernelGGL(k_round_init, dim3(grid_cap((int64_t)bk.total() * kSlots, kBlock * 4, 1024)),
+                       dim3(kBlock), 0, s, bk, bucket, W, pq, lmax, single, counters, zero_w);
     return hipGetLastError();
 }
 
@@ -59,38 +67,37 @@ __device__ __forceinline__ int covering_slot(const int64_t *cb, int64_t x)
     return lo;
 }
 
-// Per block j: prefix sums over slots, cb[j][l] = sum_{i <= l} c(B_{i,j}), and
-// the penalty a node of weight 1 pays to enter j: 0 if W[j] + 1 <= L_max;
+// Per block B: prefix sums over slots, cb[B][l] = sum_{i <= l} c(B_{i,B}), and
+// the penalty a node of weight 1 pays to enter B: 0 if W[B] + 1 <= L_max;
 // otherwise constrained: -1 (forbidden); penalty-free: 0; penalised:
 // penq[l] for the least covering slot l, -1 if none.
-__global__ void k_cb_prefix(int32_t k, int64_t *bucket, const int64_t *W, int64_t lmax,
-                            const int64_t *penq, int mode, int64_t *pen1)
+__global__ void k_cb_prefix(Blocks bk, int64_t *bucket, const int64_t *W, int mode, int64_t *pen1)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= k) return;
+    if (j >= bk.total()) return;
     int64_t *b = bucket + (int64_t)j * kSlots;
     int64_t run = 0;
     for (int l = 0; l < kSlots; ++l) {
         run += b[l];
         b[l] = run;
     }
-    const int64_t x = W[j] + 1 - lmax;
+    const int64_t x = W[j] + 1 - bk.lmax_of(j);
     int64_t p = 0;
     if (x > 0) {
         if (mode == 1) p = -1;
         else if (mode == 0) {
             const int l = covering_slot(b, x);
-            p = l >= kSlots ? -1 : penq[l];
+            p = l >= kSlots ? -1 : bk.penq_of(j)[l];
         }
     }
     pen1[j] = p;
 }
 
-hipError_t launch_cb_prefix(int32_t k, int64_t *bucket, const int64_t *W, int64_t lmax,
-                            const int64_t *penq, int mode, int64_t *pen1, hipStream_t s)
+hipError_t launch_cb_prefix(const Blocks &bk, int64_t *bucket, const int64_t *W, int mode,
+                            int64_t *pen1, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cb_prefix, dim3((k + kBlock - 1) / kBlock), dim3(kBlock), 0, s, k, bucket,
-                       W, lmax, penq, mode, pen1);
+    hipLaunchKernelGGL(k_cb_prefix, dim3((bk.total() + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                       bk, bucket, W, mode, pen1);
     return hipGetLastError();
 }
 
@@ -103,23 +110,26 @@ hipError_t launch_cb_prefix(int32_t k, int64_t *bucket, const int64_t *W, int64_
 //   P = min(penq[l] * c(v), 2^62); score = delta * 2^16 - P.
 // G lanes per node, each reading V consecutive ints of the row per step. The
 // best score (ties to the smaller j) is reduced as (score << 16 | 0xFFFF - j).
-// key[v] = score << 16 | j for candidates (score > 0), -1 otherwise.
+// key[v] = score << 16 | j for candidates (score > 0), -1 otherwise. j is the
+// local block (row index); W, cb and pen1 are read at the global id base + j.
 template <int G, int V>
 __global__ __launch_bounds__(kBlock) void k_best_move(
-    GraphView g, int32_t k, const int32_t *__restrict__ part, const int32_t *__restrict__ conn,
-    const int64_t *__restrict__ W, const int64_t *__restrict__ cb, const int64_t *__restrict__ penq,
-    const int64_t *__restrict__ pen1, int64_t lmax, int mode, int64_t *__restrict__ key,
+    GraphView g, Blocks bk, const int32_t *__restrict__ part, const int32_t *__restrict__ conn,
+    const int64_t *__restrict__ W, const int64_t *__restrict__ cb,
+    const int64_t *__restrict__ pen1, int mode, int64_t *__restrict__ key,
     int64_t *__restrict__ pen, unsigned long long *counters)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int32_t k = bk.k;
+    const int32_t K = bk.total();
     int64_t *sW = (int64_t *)lds_raw;
-    int64_t *sP = sW + k;
+    int64_t *sP = sW + K;
     __shared__ unsigned long long cand_lds;
-    const bool use_lds = k <= 2048;
+    const bool use_lds = K <= 2048;
     const bool unit = g.vwgt == nullptr;
     if (threadIdx.x == 0) cand_lds = 0;
     if (use_lds)
-        for (int j = threadIdx.x; j < k; j += kBlock) {
+        for (int j = threadIdx.x; j < K; j += kBlock) {
             sW[j] = W[j];
             sP[j] = pen1[j];
         }
@@ -134,9 +144,13 @@ __global__ __launch_bounds__(kBlock) void k_best_move(
     const int64_t first = (int64_t)blockIdx.x * GPB + threadIdx.x / G;
     for (int64_t v = first; v < g.n; v += stride) {
         int64_t best = 0, bestP = 0;
-        const int32_t a = part[v];
+        const int32_t A = part[v];
         const int64_t cv = node_weight(g, v);
-        if ((unsigned)a < (unsigned)k) {
+        if ((unsigned)A < (unsigned)K) {
+            const int32_t a = bk.local(A);
+            const int32_t base = bk.base(A);
+            const int64_t lmax = bk.lmax_of(A);
+            const int64_t *penq = bk.penq_of(A);
             const int32_t *row = conn + v * (int64_t)k;
             const int32_t ca = row[a];
             for (int q = gl; q < nvec; q += G) {
@@ -158,15 +172,15 @@ __global__ __launch_bounds__(kBlock) void k_best_move(
                     const int64_t delta = (int64_t)cj - ca;
                     int64_t P;
                     if (unit) {
-                        P = Pr[j];
+                        P = Pr[base + j];
                         if (P < 0) continue;
                     } else {
                         P = 0;
-                        const int64_t x = Wr[j] + cv - lmax;
+                        const int64_t x = Wr[base + j] + cv - lmax;
                         if (x > 0) {
                             if (mode == 1) continue;
                             if (mode == 0) {
-                                const int l = covering_slot(cb + (int64_t)j * kSlots, x);
+                                const int l = covering_slot(cb + (int64_t)(base + j) * kSlots, x);
                                 if (l >= kSlots) continue;
                                 P = sat_mul_pen(penq[l], cv);
                             }
@@ -207,18 +221,19 @@ __global__ __launch_bounds__(kBlock) void k_best_move(
     if (threadIdx.x == 0 && cand_lds) atomicAdd(&counters[CNT_CAND], cand_lds);
 }
 
-hipError_t launch_best_move(const GraphView &g, int32_t k, const int32_t *part, const int32_t *conn,
-                            const int64_t *W, const int64_t *cb, const int64_t *penq,
-                            const int64_t *pen1, int64_t lmax, int mode, int64_t *key,
-                            int64_t *pen, unsigned long long *counters, hipStream_t s)
+hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t *part,
+                            const int32_t *conn, const int64_t *W, const int64_t *cb,
+                            const int64_t *pen1, int mode, int64_t *key, int64_t *pen,
+                            unsigned long long *counters, hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
-    const size_t lds = k <= 2048 ? (size_t)k * 16 : 0;
+    const int32_t k = bk.k;
+    const size_t lds = bk.total() <= 2048 ? (size_t)bk.total() * 16 : 0;
     const bool vec = (k % 4) == 0;
     const int nvec = vec ? k / 4 : k;
 #define UPR_BM(GG, VV)                                                                             \
     hipLaunchKernelGGL((k_best_move<GG, VV>), dim3(grid_cap(g.n, kBlock / GG, 8192)), dim3(kBlock), \
-                       lds, s, g, k, part, conn, W, cb, penq, pen1, lmax, mode, key, pen, counters)
+                       lds, s, g, bk, part, conn, W, cb, pen1, mode, key, pen, counters)
     if (vec) {
         if (nvec <= 1) UPR_BM(1, 4);
         else if (nvec <= 2) UPR_BM(2, 4);
@@ -293,7 +308,8 @@ __device__ __forceinline__ int64_t pessimistic_part(const GraphView &g, const Pa
 // One class of a wave's compacted candidates: lane groups of G take the
 // set bits of mask in order; the node id / key of bit p sit in lane p.
 template <int G>
-__device__ __forceinline__ void filter_class(const GraphView &g, const int32_t *part,
+__device__ __forceinline__ void filter_class(const GraphView &g, const Blocks &bk,
+                                             const int32_t *part,
                                              const PartView &pv, const int64_t *key,
                                              const int64_t *pen,
                                              uint64_t mask, int64_t lane_v, int64_t lane_key,
@@ -312,11 +328,12 @@ __device__ __forceinline__ void filter_class(const GraphView &g, const int32_t *
         const int64_t v = __shfl(lane_v, src);
         const int64_t kv = __shfl(lane_key, src);
         int64_t acc = 0;
-        int32_t b = 0;
+        int32_t b = 0, A = 0;
         if (ok) {
-            const int32_t a = part[v];
+            A = part[v];
             b = (int32_t)(kv & 0xFFFF);
-            acc = pessimistic_part(g, pv, key, v, a, b, kv >> 16, g.xadj[v], g.xadj[v + 1], gl, G);
+            acc = pessimistic_part(g, pv, key, v, bk.local(A), b, kv >> 16, g.xadj[v], g.xadj[v + 1],
+                                   gl, G);
         }
         acc = group_sum<G>(acc);
         bool take = false;
@@ -327,7 +344,7 @@ __device__ __forceinline__ void filter_class(const GraphView &g, const int32_t *
             take = acc * 65536 - pen[v] > 0;
             accflag[v] = take ? 1 : 0;
             if (take) {
-                mvto[v] = b;
+                mvto[v] = bk.base(A) + b;
                 atomicAdd(deg_lds, (unsigned long long)(g.xadj[v + 1] - g.xadj[v]));
             }
         }
@@ -335,7 +352,8 @@ __device__ __forceinline__ void filter_class(const GraphView &g, const int32_t *
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_filter(GraphView g, const int32_t *__restrict__ part,
+__global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk,
+                                                    const int32_t *__restrict__ part,
                                                     PartView pv, const int64_t *__restrict__ key,
                                                     const int64_t *__restrict__ pen, int64_t low_t,
                                                     int64_t hub_t, int32_t *mvto, uint8_t *accflag,
@@ -359,11 +377,11 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, const int32_t *_
         const uint64_t mlow = __ballot(kv >= 0 && deg <= low_t);
         const uint64_t mmid = __ballot(kv >= 0 && deg > low_t && deg <= hub_t);
         if (mlow)
-            filter_class<kLowLanes>(g, part, pv, key, pen, mlow, v, kv, mvto, accflag, &acc_lds,
-                                    &deg_lds, gp_out);
+            filter_class<kLowLanes>(g, bk, part, pv, key, pen, mlow, v, kv, mvto, accflag,
+                                    &acc_lds, &deg_lds, gp_out);
         if (mmid)
-            filter_class<64>(g, part, pv, key, pen, mmid, v, kv, mvto, accflag, &acc_lds, &deg_lds,
-                             gp_out);
+            filter_class<64>(g, bk, part, pv, key, pen, mmid, v, kv, mvto, accflag, &acc_lds,
+                             &deg_lds, gp_out);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -372,19 +390,19 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, const int32_t *_
     }
 }
 
-hipError_t launch_filter(const GraphView &g, const int32_t *part, const PartView &pv,
-                         const int64_t *key, const int64_t *pen, int64_t low_t, int64_t hub_t,
-                         int32_t *mvto, uint8_t *accflag, unsigned long long *counters,
-                         int64_t *gp_out, hipStream_t s)
+hipError_t launch_filter(const GraphView &g, const Blocks &bk, const int32_t *part,
+                         const PartView &pv, const int64_t *key, const int64_t *pen, int64_t low_t,
+                         int64_t hub_t, int32_t *mvto, uint8_t *accflag,
+                         unsigned long long *counters, int64_t *gp_out, hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_filter, dim3(grid_cap(g.n, kBlock, 8192)), dim3(kBlock), 0, s, g, part, pv,
-                       key, pen, low_t, hub_t, mvto, accflag, counters, gp_out);
+    hipLaunchKernelGGL(k_filter, dim3(grid_cap(g.n, kBlock, 8192)), dim3(kBlock), 0, s, g, bk, part,
+                       pv, key, pen, low_t, hub_t, mvto, accflag, counters, gp_out);
     return hipGetLastError();
 }
 
 // Hub candidates: each chunk adds its part of the pessimistic gain.
-__global__ __launch_bounds__(kBlock) void k_filter_hub(GraphView g, const int32_t *part,
+__global__ __launch_bounds__(kBlock) void k_filter_hub(GraphView g, Blocks bk, const int32_t *part,
                                                         PartView pv, const int64_t *key, HubView h)
 {
     __shared__ int64_t red[4];
@@ -392,7 +410,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_hub(GraphView g, const int32_
     const int64_t v = h.ids[c.hub];
     const int64_t kv = key[v];
     if (kv < 0) return;  // uniform over the workgroup
-    const int32_t a = part[v], b = (int32_t)(kv & 0xFFFF);
+    const int32_t a = bk.local(part[v]), b = (int32_t)(kv & 0xFFFF);
     int64_t acc = pessimistic_part(g, pv, key, v, a, b, kv >> 16, c.e0, c.e1, threadIdx.x, kBlock);
     acc = block_sum(acc, red);
     if (threadIdx.x == 0 && acc) atomic_add_i64(&h.gacc[c.hub], acc);
@@ -400,9 +418,9 @@ __global__ __launch_bounds__(kBlock) void k_filter_hub(GraphView g, const int32_
 
 // Hub candidates: decide (or, with the sequence-aware price, store the
 // pessimistic gain), mark the move, reset the accumulator.
-__global__ void k_filter_hub_final(const int64_t *key, const int64_t *pen, HubView h,
-                                   int32_t *mvto, uint8_t *accflag, unsigned long long *counters,
-                                   int64_t *gp_out)
+__global__ void k_filter_hub_final(Blocks bk, const int32_t *part, const int64_t *key,
+                                   const int64_t *pen, HubView h, int32_t *mvto, uint8_t *accflag,
+                                   unsigned long long *counters, int64_t *gp_out)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= h.nh) return;
@@ -419,7 +437,7 @@ __global__ void k_filter_hub_final(const int64_t *key, const int64_t *pen, HubVi
     const bool ok = acc * 65536 - pen[v] > 0;
     accflag[v] = ok ? 1 : 0;
     if (ok) {
-        mvto[v] = (int32_t)(kv & 0xFFFF);
+        mvto[v] = bk.base(part[v]) + (int32_t)(kv & 0xFFFF);
         atomicAdd(&counters[CNT_ACC], 1ull);
     }
 }
@@ -433,18 +451,18 @@ __global__ void k_hub_moved_deg(GraphView g, const int32_t *mvto, HubView h,
     if (mvto[v] >= 0) atomicAdd(&counters[CNT_MOVED_DEG], (unsigned long long)(g.xadj[v + 1] - g.xadj[v]));
 }
 
-hipError_t launch_filter_hub(const GraphView &g, const int32_t *part, const PartView &pv,
-                             const int64_t *key, const int64_t *pen, const HubView &h,
-                             int32_t *mvto, uint8_t *accflag, unsigned long long *counters,
-                             int64_t *gp_out, hipStream_t s)
+hipError_t launch_filter_hub(const GraphView &g, const Blocks &bk, const int32_t *part,
+                             const PartView &pv, const int64_t *key, const int64_t *pen,
+                             const HubView &h, int32_t *mvto, uint8_t *accflag,
+                             unsigned long long *counters, int64_t *gp_out, hipStream_t s)
 {
     if (h.nh <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_filter_hub, dim3((unsigned)h.nchunks), dim3(kBlock), 0, s, g, part, pv,
-                       key, h);
+    hipLaunchKernelGGL(k_filter_hub, dim3((unsigned)h.nchunks), dim3(kBlock), 0, s, g, bk, part,
+                       pv, key, h);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_filter_hub_final, dim3((h.nh + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                       key, pen, h, mvto, accflag, counters, gp_out);
+                       bk, part, key, pen, h, mvto, accflag, counters, gp_out);
     return hipGetLastError();
 }
 
@@ -456,11 +474,11 @@ hipError_t launch_filter_hub(const GraphView &g, const int32_t *part, const Part
 // pessimistic gain is positive, the move is not forbidden, and
 // gain * 2^16 - P > 0.
 __global__ __launch_bounds__(kBlock) void k_filter_seq(
-    GraphView g, int32_t k, const int32_t *__restrict__ cand, int64_t nc,
-    const int64_t *__restrict__ key, const int64_t *__restrict__ gp,
+    GraphView g, Blocks bk, const int32_t *__restrict__ part, const int32_t *__restrict__ cand,
+    int64_t nc, const int64_t *__restrict__ key, const int64_t *__restrict__ gp,
     const int64_t *__restrict__ netpre, const int64_t *__restrict__ W,
-    const int64_t *__restrict__ cb, const int64_t *__restrict__ penq, int64_t lmax, int mode,
-    int64_t hub_t, int32_t *mvto, uint8_t *accflag, unsigned long long *counters)
+    const int64_t *__restrict__ cb, int mode, int64_t hub_t, int32_t *mvto, uint8_t *accflag,
+    unsigned long long *counters)
 {
     __shared__ unsigned long long acc_lds, deg_lds;
     if (threadIdx.x == 0) {
@@ -476,19 +494,20 @@ __global__ __launch_bounds__(kBlock) void k_filter_seq(
         if (i < nc) {
             const int64_t v = cand[i];
             const int64_t kv = key[v];
-            const int32_t b = (int32_t)(kv & 0xFFFF);
+            const int32_t A = part[v];
+            const int32_t b = bk.base(A) + (int32_t)(kv & 0xFFFF);  // global target
             const int64_t gv = gp[v];
             bool allowed = gv > 0;
             int64_t P = 0;
             if (allowed) {
                 const int64_t cv = node_weight(g, v);
-                const int64_t x = W[b] + netpre[v] + cv - lmax;
+                const int64_t x = W[b] + netpre[v] + cv - bk.lmax_of(A);
                 if (x > 0) {
                     if (mode == 1) allowed = false;
                     else if (mode == 0) {
                         const int l = covering_slot(cb + (int64_t)b * kSlots, x);
                         if (l >= kSlots) allowed = false;
-                        else P = sat_mul_pen(penq[l], cv);
+                        else P = sat_mul_pen(bk.penq_of(A)[l], cv);
                     }
                 }
             }
@@ -509,15 +528,15 @@ __global__ __launch_bounds__(kBlock) void k_filter_seq(
     }
 }
 
-hipError_t launch_filter_seq(const GraphView &g, int32_t k, const int32_t *cand, int64_t ne,
-                             const int64_t *key, const int64_t *gp, const int64_t *netpre,
-                             const int64_t *W, const int64_t *cb, const int64_t *penq,
-                             int64_t lmax, int mode, int64_t hub_t, int32_t *mvto,
+hipError_t launch_filter_seq(const GraphView &g, const Blocks &bk, const int32_t *part,
+                             const int32_t *cand, int64_t ne, const int64_t *key,
+                             const int64_t *gp, const int64_t *netpre, const int64_t *W,
+                             const int64_t *cb, int mode, int64_t hub_t, int32_t *mvto,
                              uint8_t *accflag, unsigned long long *counters, hipStream_t s)
 {
     if (ne <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_filter_seq, dim3(grid_cap(ne, kBlock, 8192)), dim3(kBlock), 0, s, g, k,
-                       cand, ne, key, gp, netpre, W, cb, penq, lmax, mode, hub_t, mvto, accflag,
+    hipLaunchKernelGGL(k_filter_seq, dim3(grid_cap(ne, kBlock, 8192)), dim3(kBlock), 0, s, g, bk,
+                       part, cand, ne, key, gp, netpre, W, cb, mode, hub_t, mvto, accflag,
                        counters);
     return hipGetLastError();
 }
@@ -527,9 +546,10 @@ hipError_t launch_filter_seq(const GraphView &g, int32_t k, const int32_t *cand,
 // S4 (and the rebalancing moves): for a move v: a -> b, part[v] = b,
 // W[a] -= c(v), W[b] += c(v), and for every neighbour u
 // conn[u][a] -= omega(v, u), conn[u][b] += omega(v, u). Integer atomics
-// commute, so the result does not depend on the order of the moves.
+// commute, so the result does not depend on the order of the moves. a and b
+// are global block ids (W); the rows use their local ids.
 template <int G>
-__device__ __forceinline__ void apply_class(const GraphView &g, int32_t k, int32_t *part,
+__device__ __forceinline__ void apply_class(const GraphView &g, const Blocks &bk, int32_t *part,
                                             const PartView &pv, int32_t *conn, int64_t *wdst,
                                             uint64_t mask,
                                             int64_t lane_v, int32_t lane_to, int32_t *mvto,
@@ -546,9 +566,11 @@ __device__ __forceinline__ void apply_class(const GraphView &g, int32_t k, int32
         const int64_t v = __shfl(lane_v, src);
         const int32_t b = __shfl(lane_to, src);
         if (!ok) continue;
-        int32_t a = 0;
-        if (gl == 0) a = part[v];
-        a = __shfl(a, lane & ~(G - 1));
+        int32_t A = 0;
+        if (gl == 0) A = part[v];
+        A = __shfl(A, lane & ~(G - 1));
+        const int32_t k = bk.k;
+        const int32_t a = bk.local(A), lb = bk.local(b);  // row indices
         const int64_t e1 = g.xadj[v + 1];
         // kEdgeUnroll neighbours per lane are loaded before they are used
         for (int64_t e = g.xadj[v] + gl; e < e1; e += (int64_t)kEdgeUnroll * G) {
@@ -575,22 +597,22 @@ __device__ __forceinline__ void apply_class(const GraphView &g, int32_t k, int32
                 for (int i = 0; i < kEdgeUnroll; ++i) {
                     if (u[i] < 0 || hub[i]) continue;
                     atomicAdd(&conn[(int64_t)u[i] * k + a], -w[i]);
-                    atomicAdd(&conn[(int64_t)u[i] * k + b], w[i]);
+                    atomicAdd(&conn[(int64_t)u[i] * k + lb], w[i]);
                 }
             }
         }
         if (gl == 0) {
             const int64_t cv = node_weight(g, v);
             part[v] = b;
-            pset((void *)pv.p, pv.bytes, v, b);
+            pset((void *)pv.p, pv.bytes, v, lb);
             mvto[v] = -1;
-            atomicAdd((unsigned long long *)&wdst[a], (unsigned long long)(-cv));
+            atomicAdd((unsigned long long *)&wdst[A], (unsigned long long)(-cv));
             atomicAdd((unsigned long long *)&wdst[b], (unsigned long long)cv);
         }
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_apply(GraphView g, int32_t k, int32_t *part,
+__global__ __launch_bounds__(kBlock) void k_apply(GraphView g, Blocks bk, int32_t *part,
                                                    PartView pv, int32_t *conn, int64_t *W,
                                                    int32_t *mvto,
                                                    int64_t low_t, int64_t hub_t, HubView h,
@@ -602,9 +624,10 @@ __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, int32_t k, int32_
         (int64_t)counters[CNT_MOVED_DEG] > dirty_threshold ? dirty_flags : (uint8_t *)nullptr;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     int64_t *wloc = (int64_t *)lds_raw;
-    const bool use_lds = k <= 2048;
+    const int32_t K = bk.total();
+    const bool use_lds = K <= 2048;
     if (use_lds) {
-        for (int j = threadIdx.x; j < k; j += kBlock) wloc[j] = 0;
+        for (int j = threadIdx.x; j < K; j += kBlock) wloc[j] = 0;
         __syncthreads();
     }
     int64_t *wdst = use_lds ? wloc : W;
@@ -620,19 +643,19 @@ __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, int32_t k, int32_
         }
         const uint64_t mlow = __ballot(to >= 0 && deg <= low_t);
         const uint64_t mmid = __ballot(to >= 0 && deg > low_t && deg <= hub_t);
-        if (mlow) apply_class<kLowLanes>(g, k, part, pv, conn, wdst, mlow, v, to, mvto, h, dirty, T);
-        if (mmid) apply_class<64>(g, k, part, pv, conn, wdst, mmid, v, to, mvto, h, dirty, T);
+        if (mlow) apply_class<kLowLanes>(g, bk, part, pv, conn, wdst, mlow, v, to, mvto, h, dirty, T);
+        if (mmid) apply_class<64>(g, bk, part, pv, conn, wdst, mmid, v, to, mvto, h, dirty, T);
     }
     if (use_lds) {
         __syncthreads();
-        for (int j = threadIdx.x; j < k; j += kBlock)
+        for (int j = threadIdx.x; j < K; j += kBlock)
             if (wloc[j]) atomic_add_i64(&W[j], wloc[j]);
     }
 }
 
 // Hub moves: each chunk updates the rows of its neighbours (part of the hub
 // is still its source block here).
-__global__ __launch_bounds__(kBlock) void k_apply_hub(GraphView g, int32_t k, const int32_t *part,
+__global__ __launch_bounds__(kBlock) void k_apply_hub(GraphView g, Blocks bk, const int32_t *part,
                                                        int32_t *conn, const int32_t *mvto,
                                                        HubView h, const unsigned long long *counters,
                                                        int64_t dirty_threshold, uint8_t *dirty,
@@ -640,13 +663,14 @@ __global__ __launch_bounds__(kBlock) void k_apply_hub(GraphView g, int32_t k, co
 {
     const HubChunk c = h.chunks[blockIdx.x];
     const int64_t v = h.ids[c.hub];
-    const int32_t b = mvto[v];
-    if (b < 0) return;
+    const int32_t B = mvto[v];
+    if (B < 0) return;
     if ((int64_t)counters[CNT_MOVED_DEG] > dirty_threshold) {
         for (int64_t e = c.e0 + threadIdx.x; e < c.e1; e += kBlock) dirty[g.adjncy[e] / T] = 1;
         return;
     }
-    const int32_t a = part[v];
+    const int32_t k = bk.k;
+    const int32_t a = bk.local(part[v]), b = bk.local(B);
     for (int64_t e = c.e0 + threadIdx.x; e < c.e1; e += kBlock) {
         const int64_t u = g.adjncy[e];
         if (is_hub(h, u)) continue;
@@ -657,7 +681,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_hub(GraphView g, int32_t k, co
 }
 
 // Hub moves: part and block weights, then clear the mark.
-__global__ void k_apply_hub_final(GraphView g, int32_t *part, PartView pv, int64_t *W,
+__global__ void k_apply_hub_final(GraphView g, Blocks bk, int32_t *part, PartView pv, int64_t *W,
                                   int32_t *mvto, HubView h)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -668,35 +692,36 @@ __global__ void k_apply_hub_final(GraphView g, int32_t *part, PartView pv, int64
     const int32_t a = part[v];
     const int64_t cv = node_weight(g, v);
     part[v] = b;
-    pset((void *)pv.p, pv.bytes, v, b);
+    pset((void *)pv.p, pv.bytes, v, bk.local(b));
     mvto[v] = -1;
     atomic_add_i64(&W[a], -cv);
     atomic_add_i64(&W[b], cv);
 }
 
-hipError_t launch_apply(const GraphView &g, int32_t k, int32_t *part, const PartView &pv,
+hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, const PartView &pv,
                         int32_t *conn, int64_t *W, int32_t *mvto, int64_t low_t, int64_t hub_t,
                         const HubView &h, const unsigned long long *counters,
                         int64_t dirty_threshold, uint8_t *dirty, hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
+    const int32_t k = bk.k;
     const int T = gain_tile_nodes(k);
-    const size_t lds = k <= 2048 ? (size_t)k * 8 : 0;
+    const size_t lds = bk.total() <= 2048 ? (size_t)bk.total() * 8 : 0;
     hipError_t e;
     if (h.nh > 0) {  // hub degrees join the moved-degree sum first
         hipLaunchKernelGGL(k_hub_moved_deg, dim3((h.nh + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
                            g, mvto, h, (unsigned long long *)counters);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_apply, dim3(grid_cap(g.n, kBlock, 4096)), dim3(kBlock), lds, s, g, k, part,
-                       pv, conn, W, mvto, low_t, hub_t, h, counters, dirty_threshold, dirty, T);
+    hipLaunchKernelGGL(k_apply, dim3(grid_cap(g.n, kBlock, 4096)), dim3(kBlock), lds, s, g, bk,
+                       part, pv, conn, W, mvto, low_t, hub_t, h, counters, dirty_threshold, dirty, T);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (h.nh > 0) {
-        hipLaunchKernelGGL(k_apply_hub, dim3((unsigned)h.nchunks), dim3(kBlock), 0, s, g, k, part,
+        hipLaunchKernelGGL(k_apply_hub, dim3((unsigned)h.nchunks), dim3(kBlock), 0, s, g, bk, part,
                            conn, mvto, h, counters, dirty_threshold, dirty, T);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         hipLaunchKernelGGL(k_apply_hub_final, dim3((h.nh + kBlock - 1) / kBlock), dim3(kBlock), 0,
-                           s, g, part, pv, W, mvto, h);
+                           s, g, bk, part, pv, W, mvto, h);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     // rebuild the marked tiles (none are marked in the delta mode)

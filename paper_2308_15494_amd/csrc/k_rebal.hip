@@ -15,6 +15,10 @@
 //   source    the same over each overloaded block's accepted nodes: the
 //             minimal prefix that covers the block's excess is kept
 //   moves     kept nodes are marked (mvto) for the apply kernels
+// Blocks are global ids (a batch's graphs have disjoint blocks); a node's row
+// is indexed by its local block. A block is a source iff its weight exceeds
+// src_lmax of its graph (L_max, or "never" once that graph has stopped);
+// targets must stay within L_max.
 // Histogram rows and chunk rows are cleared by the kernel that reads them,
 // so they are zero again at the start of the next sub-iteration. Node scans
 // run over all ids in wave-sized runs; membership of a node in an overloaded
@@ -60,25 +64,33 @@ __device__ __forceinline__ bool rb_kept(const RbView &r, int64_t v, int32_t a, i
 
 // ------------------------------------------------------------------ begin --
 
-// Count overloaded blocks and snapshot W.
-__global__ void k_rb_begin(int32_t k, const int64_t *W, int64_t lmax, int64_t *W0,
-                           unsigned long long *counters)
+// Count source blocks and snapshot W (one workgroup). For a batch, also per
+// graph: gstat[g][GS_OVER].
+__global__ void k_rb_begin(Blocks bk, const int64_t *W, int64_t *W0, unsigned long long *counters,
+                           int64_t *gstat)
 {
     __shared__ unsigned long long red[4];
+    const int32_t K = bk.total();
+    if (gstat) {
+        for (int gi = threadIdx.x; gi < bk.ng; gi += kBlock) gstat[(int64_t)gi * GS_COUNT + GS_OVER] = 0;
+        __syncthreads();
+    }
     unsigned long long over = 0;
-    for (int j = threadIdx.x; j < k; j += kBlock) {
+    for (int j = threadIdx.x; j < K; j += kBlock) {
         const int64_t w = W[j];
         W0[j] = w;
-        over += w > lmax;
+        const bool o = w > bk.src_lmax_of(j);
+        over += o;
+        if (gstat && o) atomic_add_i64(&gstat[(int64_t)bk.graph(j) * GS_COUNT + GS_OVER], 1);
     }
     over = block_sum(over, red);
     if (threadIdx.x == 0) counters[CNT_OVER] = over;
 }
 
-hipError_t launch_rb_begin(int32_t k, const int64_t *W, int64_t lmax, const RebalWs &r,
-                           unsigned long long *counters, hipStream_t s)
+hipError_t launch_rb_begin(const Blocks &bk, const int64_t *W, const RebalWs &r,
+                           unsigned long long *counters, int64_t *gstat, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_rb_begin, dim3(1), dim3(kBlock), 0, s, k, W, lmax, r.W0, counters);
+    hipLaunchKernelGGL(k_rb_begin, dim3(1), dim3(kBlock), 0, s, bk, W, r.W0, counters, gstat);
     return hipGetLastError();
 }
 
@@ -86,30 +98,27 @@ hipError_t launch_rb_begin(int32_t k, const int64_t *W, int64_t lmax, const Reba
 
 constexpr int kHistLdsBytes = 49152;
 
-__device__ __forceinline__ bool in_overloaded(const RebalWs &r, int32_t k, int32_t a, int64_t lmax)
-{
-    return (unsigned)a < (unsigned)k && r.W0[a] > lmax;
-}
-
 // Nodes of overloaded blocks: target and priority bucket. G lanes per node
 // scan its row (V ints per lane per step): best connected target that stays
 // balanced (max conn, ties to the smaller id) and the lightest such block
 // (min W, ties to the smaller id) as fallback.
 template <int G, int V>
-__global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, int32_t k,
+__global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
                                                         const int32_t *__restrict__ part,
                                                         const int32_t *__restrict__ conn,
-                                                        int64_t lmax, RebalWs r, int hist32)
+                                                        RebalWs r, int hist32)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int32_t k = bk.k;
+    const int32_t K = bk.total();
     int64_t *sW = (int64_t *)lds_raw;
-    const bool w_lds = (size_t)k * 8 <= 16384;
-    const bool h_lds = hist32 && (size_t)k * kRbBuckets * 4 <= kHistLdsBytes;
-    uint32_t *sH = (uint32_t *)(sW + (w_lds ? k : 0));
+    const bool w_lds = (size_t)K * 8 <= 16384;
+    const bool h_lds = hist32 && (size_t)K * kRbBuckets * 4 <= kHistLdsBytes;
+    uint32_t *sH = (uint32_t *)(sW + (w_lds ? K : 0));
     if (w_lds)
-        for (int j = threadIdx.x; j < k; j += kBlock) sW[j] = r.W0[j];
+        for (int j = threadIdx.x; j < K; j += kBlock) sW[j] = r.W0[j];
     if (h_lds)
-        for (int j = threadIdx.x; j < k * kRbBuckets; j += kBlock) sH[j] = 0;
+        for (int j = threadIdx.x; j < K * kRbBuckets; j += kBlock) sH[j] = 0;
     __syncthreads();
     const int64_t *W0 = w_lds ? sW : r.W0;
 
@@ -123,14 +132,18 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, int32_t k,
         const int64_t lv = base + lane;
         int32_t la = -1;
         if (lv < g.n) la = part[lv];
-        const uint64_t mask = __ballot(lv < g.n && (unsigned)la < (unsigned)k && W0[la] > lmax);
+        const uint64_t mask =
+            __ballot(lv < g.n && (unsigned)la < (unsigned)K && W0[la] > bk.src_lmax_of(la));
         const int cnt = __popcll(mask);
         for (int p0 = 0; p0 < cnt; p0 += 64 / G) {
             const int p = p0 + grp;
             const bool ok = p < cnt;
             const int src = ok ? nth_set_bit(mask, p) : 0;
             const int64_t v = __shfl(lv, src);
-            const int32_t a = __shfl(la, src);
+            const int32_t A = __shfl(la, src);
+            const int32_t a = ok ? bk.local(A) : 0;     // row index of the source
+            const int32_t base = ok ? bk.base(A) : 0;  // global id of local block 0
+            const int64_t lmax = ok ? bk.lmax_of(A) : 0;
             int64_t best = -1, lw = INT64_MAX, cv = 1;
             int32_t lj = 0x7fffffff;
             if (ok) {
@@ -151,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, int32_t k,
                     for (int t = 0; t < V; ++t) {
                         const int j = q * V + t;
                         if (j == a) continue;
-                        const int64_t wj = W0[j];
+                        const int64_t wj = W0[base + j];
                         if (wj + cv > lmax) continue;
                         if (c4[t] > 0) {
                             const int64_t pk = ((int64_t)c4[t] << 16) | (int64_t)(0xFFFF - j);
@@ -186,12 +199,12 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, int32_t k,
                 } else if (lj != 0x7fffffff) {
                     tgt = lj;
                 }
-                r.rtgt[v] = tgt;
+                r.rtgt[v] = tgt >= 0 ? base + tgt : -1;
                 if (tgt >= 0) {
                     const int64_t ca = conn[v * (int64_t)k + a];
                     const int be = rebalance_bucket(ct - ca, cv);
                     r.rbeta[v] = (uint8_t)be;
-                    hkey = (int64_t)tgt * kRbBuckets + be;
+                    hkey = (int64_t)(base + tgt) * kRbBuckets + be;
                     push = true;
                 }
             }
@@ -204,7 +217,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, int32_t k,
     }
     if (h_lds) {
         __syncthreads();
-        for (int j = threadIdx.x; j < k * kRbBuckets; j += kBlock)
+        for (int j = threadIdx.x; j < K * kRbBuckets; j += kBlock)
             if (sH[j]) atomic_add_i64(&r.hist_tgt[j], (int64_t)sH[j]);
     }
 }
@@ -216,9 +229,9 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, int32_t k,
 // One wave per block: each lane holds buckets lane and lane + 64, a wave scan
 // gives the cumulative weights. Rows are cleared after reading. The target
 // pass (the first) also resets the sub-iteration's move counters.
-__global__ __launch_bounds__(kBlock) void k_rb_cutoffs(int32_t k, int64_t lmax, RebalWs r,
-                                                        int target_side,
-                                                        unsigned long long *counters)
+__global__ __launch_bounds__(kBlock) void k_rb_cutoffs(Blocks bk, RebalWs r, int target_side,
+                                                        unsigned long long *counters,
+                                                        int64_t *gstat)
 {
     const int j = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = lane_id();
@@ -226,9 +239,12 @@ __global__ __launch_bounds__(kBlock) void k_rb_cutoffs(int32_t k, int64_t lmax, 
         counters[CNT_MOVED_NOW] = 0;
         counters[CNT_MOVED_DEG] = 0;
     }
-    if (j >= k) return;  // wave-uniform
+    if (j >= bk.total()) return;  // wave-uniform
+    if (target_side && gstat && lane == 0 && bk.local(j) == 0)
+        gstat[(int64_t)bk.graph(j) * GS_COUNT + GS_MOVED_NOW] = 0;
     const int64_t w0 = r.W0[j];
-    if (!target_side ? (w0 <= lmax) : (w0 > lmax)) {
+    const int64_t lmax = bk.lmax_of(j);
+    if (!target_side ? (w0 <= bk.src_lmax_of(j)) : (w0 > lmax)) {
         // not a source / not a target: the row was never filled
         if (lane == 0) {
             if (!target_side) r.cbeta_src[j] = kRbBuckets;
@@ -274,46 +290,44 @@ __global__ __launch_bounds__(kBlock) void k_rb_cutoffs(int32_t k, int64_t lmax, 
 
 // Movable node of an overloaded block (its rtgt/rbeta are this
 // sub-iteration's).
-__device__ __forceinline__ bool rb_member(const RebalWs &r, int32_t k, int64_t lmax, int64_t v,
-                                          int32_t a)
+__device__ __forceinline__ bool rb_member(const RebalWs &r, const Blocks &bk, int64_t v, int32_t a)
 {
-    return (unsigned)a < (unsigned)k && r.W0[a] > lmax && r.rtgt[v] >= 0;
+    return (unsigned)a < (unsigned)bk.total() && r.W0[a] > bk.src_lmax_of(a) && r.rtgt[v] >= 0;
 }
 
 // Nodes in the cutoff bucket add their weight to the chunk of their id
 // (target side: every offer; source side: accepted offers).
-__global__ __launch_bounds__(kBlock) void k_rb_chunks(GraphView g, int32_t k, const int32_t *part,
-                                                       int64_t lmax, RebalWs r, RbView rv,
-                                                       int target_side)
+__global__ __launch_bounds__(kBlock) void k_rb_chunks(GraphView g, Blocks bk, const int32_t *part,
+                                                       RebalWs r, RbView rv, int target_side)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += stride) {
         const int32_t a = part[v];
-        if (!rb_member(r, k, lmax, v, a)) continue;
+        if (!rb_member(r, bk, v, a)) continue;
         const int be = r.rbeta[v];
         const int32_t j = r.rtgt[v];
+        // chunks count node ids from the start of the node's graph
+        const int64_t c = (v - (r.goff ? r.goff[bk.graph(a)] : 0)) >> r.chunk_shift;
         if (target_side) {
             if (be == r.cbeta_tgt[j])
-                atomic_add_i64(&r.chunk_tgt[(int64_t)j * r.nchunks + (v >> r.chunk_shift)],
-                               node_weight(g, v));
+                atomic_add_i64(&r.chunk_tgt[(int64_t)j * r.nchunks + c], node_weight(g, v));
         } else {
             if (be == r.cbeta_src[a] && rb_accepted(rv, v, j))
-                atomic_add_i64(&r.chunk_src[(int64_t)a * r.nchunks + (v >> r.chunk_shift)],
-                               node_weight(g, v));
+                atomic_add_i64(&r.chunk_src[(int64_t)a * r.nchunks + c], node_weight(g, v));
         }
     }
 }
 
 // Accepted nodes add their weight to their source's bucket histogram.
-__global__ __launch_bounds__(kBlock) void k_rb_src_hist(GraphView g, int32_t k, const int32_t *part,
-                                                         int64_t lmax, RebalWs r, RbView rv,
-                                                         int hist32)
+__global__ __launch_bounds__(kBlock) void k_rb_src_hist(GraphView g, Blocks bk, const int32_t *part,
+                                                         RebalWs r, RbView rv, int hist32)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     uint32_t *sH = (uint32_t *)lds_raw;
-    const bool h_lds = hist32 && (size_t)k * kRbBuckets * 4 <= kHistLdsBytes;
+    const int32_t K = bk.total();
+    const bool h_lds = hist32 && (size_t)K * kRbBuckets * 4 <= kHistLdsBytes;
     if (h_lds) {
-        for (int j = threadIdx.x; j < k * kRbBuckets; j += kBlock) sH[j] = 0;
+        for (int j = threadIdx.x; j < K * kRbBuckets; j += kBlock) sH[j] = 0;
         __syncthreads();
     }
     const int64_t stride = (int64_t)gridDim.x * kBlock;
@@ -324,7 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_src_hist(GraphView g, int32_t k, 
         int64_t hkey = 0, cv = 0;
         if (v < g.n) {
             const int32_t a = part[v];
-            if (rb_member(r, k, lmax, v, a) && rb_accepted(rv, v, r.rtgt[v])) {
+            if (rb_member(r, bk, v, a) && rb_accepted(rv, v, r.rtgt[v])) {
                 sel = true;
                 hkey = (int64_t)a * kRbBuckets + r.rbeta[v];
                 cv = node_weight(g, v);
@@ -338,7 +352,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_src_hist(GraphView g, int32_t k, 
     }
     if (h_lds) {
         __syncthreads();
-        for (int j = threadIdx.x; j < k * kRbBuckets; j += kBlock)
+        for (int j = threadIdx.x; j < K * kRbBuckets; j += kBlock)
             if (sH[j]) atomic_add_i64(&r.hist_src[j], (int64_t)sH[j]);
     }
 }
@@ -349,9 +363,8 @@ __global__ __launch_bounds__(kBlock) void k_rb_src_hist(GraphView g, int32_t k, 
 //   source: theta = (first id at which the cumulative weight reaches need) + 1
 //   target: theta = first id at which the cumulative weight exceeds room
 // First over chunk sums (clearing the row), then over the ids of one chunk.
-__global__ __launch_bounds__(kBlock) void k_rb_theta(GraphView g, int32_t k, const int32_t *part,
-                                                      int64_t lmax, RebalWs r, RbView rv,
-                                                      int target_side)
+__global__ __launch_bounds__(kBlock) void k_rb_theta(GraphView g, Blocks bk, const int32_t *part,
+                                                      RebalWs r, RbView rv, int target_side)
 {
     __shared__ int64_t scan_lds[4];
     __shared__ int64_t found_lds[2];
@@ -359,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_theta(GraphView g, int32_t k, con
     int cb;
     int64_t limit;
     if (!target_side) {
-        if (r.W0[j] <= lmax) return;
+        if (r.W0[j] <= bk.src_lmax_of(j)) return;
         cb = r.cbeta_src[j];
         limit = r.need_src[j];
     } else {
@@ -402,9 +415,11 @@ __global__ __launch_bounds__(kBlock) void k_rb_theta(GraphView g, int32_t k, con
     int64_t before = found_lds[1];
     __syncthreads();
     if (chunk < 0) return;  // cannot happen when cb < kRbBuckets
-    const int64_t id0 = chunk << r.chunk_shift;
-    int64_t id1 = (chunk + 1) << r.chunk_shift;
-    if (id1 > g.n) id1 = g.n;
+    const int64_t off = r.goff ? r.goff[bk.graph(j)] : 0;
+    const int64_t end = r.goff ? r.goff[bk.graph(j) + 1] : g.n;
+    const int64_t id0 = off + (chunk << r.chunk_shift);
+    int64_t id1 = off + ((chunk + 1) << r.chunk_shift);
+    if (id1 > end) id1 = end;
     if (threadIdx.x == 0) found_lds[0] = -1;
     __syncthreads();
     for (int64_t b0 = id0; b0 < id1; b0 += kBlock) {
@@ -412,8 +427,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_theta(GraphView g, int32_t k, con
         int64_t x = 0;
         if (v < id1) {
             const int32_t a = part[v];
-            if ((unsigned)a < (unsigned)k && r.W0[a] > lmax && r.rtgt[v] >= 0 &&
-                (int)r.rbeta[v] == cb) {
+            if (rb_member(r, bk, v, a) && (int)r.rbeta[v] == cb) {
                 if (target_side) {
                     if (r.rtgt[v] == j) x = node_weight(g, v);
                 } else {
@@ -444,10 +458,10 @@ __global__ __launch_bounds__(kBlock) void k_rb_theta(GraphView g, int32_t k, con
 // ------------------------------------------------------------------ moves --
 
 // Accepted nodes get mvto[v] = target; counts per workgroup.
-__global__ __launch_bounds__(kBlock) void k_rb_moves(GraphView g, int32_t k, const int32_t *part,
-                                                      int64_t lmax, RebalWs r, RbView rv,
-                                                      int32_t *mvto, int64_t hub_t,
-                                                      unsigned long long *counters)
+__global__ __launch_bounds__(kBlock) void k_rb_moves(GraphView g, Blocks bk, const int32_t *part,
+                                                      RebalWs r, RbView rv, int32_t *mvto,
+                                                      int64_t hub_t, unsigned long long *counters,
+                                                      int64_t *gstat)
 {
     __shared__ unsigned long long moved, mdeg;
     if (threadIdx.x == 0) {
@@ -460,9 +474,10 @@ __global__ __launch_bounds__(kBlock) void k_rb_moves(GraphView g, int32_t k, con
          base += stride) {
         const int64_t v = base + lane_id();
         bool acc = false;
+        int32_t a = 0;
         if (v < g.n) {
-            const int32_t a = part[v];
-            if (rb_member(r, k, lmax, v, a)) {
+            a = part[v];
+            if (rb_member(r, bk, v, a)) {
                 const int32_t j = r.rtgt[v];
                 if (rb_kept(rv, v, a, j)) {
                     mvto[v] = j;
@@ -473,6 +488,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_moves(GraphView g, int32_t k, con
             }
         }
         wave_count(acc, &moved);
+        if (gstat) wave_hist_add(gstat, (int64_t)bk.graph(a) * GS_COUNT + GS_MOVED_NOW, 1, acc);
     }
     __syncthreads();
     if (threadIdx.x == 0 && moved) {
@@ -486,22 +502,24 @@ __global__ __launch_bounds__(kBlock) void k_rb_moves(GraphView g, int32_t k, con
 
 int rb_scan_grid(int64_t n) { return grid_cap(n, kBlock, 4096); }
 
-hipError_t launch_rb_iteration(const GraphView &g, int32_t k, const int32_t *part,
-                               const int32_t *conn, int64_t lmax, const RebalWs &r,
-                               int32_t *mvto, int hist32, int64_t hub_t,
-                               unsigned long long *counters, hipStream_t s)
+hipError_t launch_rb_iteration(const GraphView &g, const Blocks &bk, const int32_t *part,
+                               const int32_t *conn, const RebalWs &r, int32_t *mvto, int hist32,
+                               int64_t hub_t, unsigned long long *counters, int64_t *gstat,
+                               hipStream_t s)
 {
     hipError_t e;
     const RbView rv{r.rtgt, r.rbeta, r.W0, r.cbeta_src, r.theta_src, r.cbeta_tgt, r.theta_tgt};
+    const int32_t k = bk.k;
+    const int32_t K = bk.total();
     const int lg = rb_scan_grid(g.n);
-    const bool h_lds = hist32 && (size_t)k * kRbBuckets * 4 <= kHistLdsBytes;
-    const size_t plds = ((size_t)k * 8 <= 16384 ? (size_t)k * 8 : 0) +
-                        (h_lds ? (size_t)k * kRbBuckets * 4 : 0);
+    const bool h_lds = hist32 && (size_t)K * kRbBuckets * 4 <= kHistLdsBytes;
+    const size_t plds = ((size_t)K * 8 <= 16384 ? (size_t)K * 8 : 0) +
+                        (h_lds ? (size_t)K * kRbBuckets * 4 : 0);
     const bool vec = (k % 4) == 0;
     const int nvec = vec ? k / 4 : k;
 #define UPR_RP(GG, VV)                                                                          \
-    hipLaunchKernelGGL((k_rb_prepare<GG, VV>), dim3(lg), dim3(kBlock), plds, s, g, k, part, conn, \
-                       lmax, r, hist32)
+    hipLaunchKernelGGL((k_rb_prepare<GG, VV>), dim3(lg), dim3(kBlock), plds, s, g, bk, part, conn, \
+                       r, hist32)
     if (vec) {
         if (nvec <= 1) UPR_RP(1, 4);
         else if (nvec <= 2) UPR_RP(2, 4);
@@ -520,26 +538,26 @@ hipError_t launch_rb_iteration(const GraphView &g, int32_t k, const int32_t *par
     }
 #undef UPR_RP
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const dim3 kg((k + 3) / 4);  // one wave per block
+    const dim3 kg((K + 3) / 4);  // one wave per block
     // target side over all offers
-    hipLaunchKernelGGL(k_rb_cutoffs, kg, dim3(kBlock), 0, s, k, lmax, r, 1, counters);
+    hipLaunchKernelGGL(k_rb_cutoffs, kg, dim3(kBlock), 0, s, bk, r, 1, counters, gstat);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rb_chunks, dim3(lg), dim3(kBlock), 0, s, g, k, part, lmax, r, rv, 1);
+    hipLaunchKernelGGL(k_rb_chunks, dim3(lg), dim3(kBlock), 0, s, g, bk, part, r, rv, 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rb_theta, dim3(k), dim3(kBlock), 0, s, g, k, part, lmax, r, rv, 1);
+    hipLaunchKernelGGL(k_rb_theta, dim3(K), dim3(kBlock), 0, s, g, bk, part, r, rv, 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // source side over the accepted offers
-    hipLaunchKernelGGL(k_rb_src_hist, dim3(lg), dim3(kBlock), h_lds ? (size_t)k * kRbBuckets * 4 : 0,
-                       s, g, k, part, lmax, r, rv, hist32);
+    hipLaunchKernelGGL(k_rb_src_hist, dim3(lg), dim3(kBlock), h_lds ? (size_t)K * kRbBuckets * 4 : 0,
+                       s, g, bk, part, r, rv, hist32);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rb_cutoffs, kg, dim3(kBlock), 0, s, k, lmax, r, 0, counters);
+    hipLaunchKernelGGL(k_rb_cutoffs, kg, dim3(kBlock), 0, s, bk, r, 0, counters, gstat);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rb_chunks, dim3(lg), dim3(kBlock), 0, s, g, k, part, lmax, r, rv, 0);
+    hipLaunchKernelGGL(k_rb_chunks, dim3(lg), dim3(kBlock), 0, s, g, bk, part, r, rv, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rb_theta, dim3(k), dim3(kBlock), 0, s, g, k, part, lmax, r, rv, 0);
+    hipLaunchKernelGGL(k_rb_theta, dim3(K), dim3(kBlock), 0, s, g, bk, part, r, rv, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rb_moves, dim3(lg), dim3(kBlock), 0, s, g, k, part, lmax, r, rv, mvto,
-                       hub_t, counters);
+    hipLaunchKernelGGL(k_rb_moves, dim3(lg), dim3(kBlock), 0, s, g, bk, part, r, rv, mvto, hub_t,
+                       counters, gstat);
     return hipGetLastError();
 }
 

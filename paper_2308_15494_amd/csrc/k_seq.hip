@@ -26,7 +26,8 @@ namespace {
 
 // Events are sorted on (block << sb | order) with sb = score bits: a score
 // is below (max weighted degree + 1) * 2^16, and order = 2^sb - 1 - score
-// puts higher scores first. The block field also holds the sentinel k for
+// puts higher scores first. Blocks are global ids (a batch's graphs never
+// share one). The block field also holds the sentinel K (number of blocks) for
 // the outflow events of available candidates (they change no block).
 // rocPRIM's merge-sort path costs about ten passes on mid-sized inputs; the
 // onesweep radix path is used from the single-block size up.
@@ -57,7 +58,7 @@ struct EventDelta {
 // Two events per eligible candidate: inflow at its target, outflow at its
 // own block (the sentinel block if it is available for rebalancing).
 __global__ void k_seq_events(int64_t ne, const int32_t *cand, const int64_t *key,
-                             const int32_t *part, const uint8_t *avail, int sb,
+                             const int32_t *part, const uint8_t *avail, Blocks bk, int sb,
                              uint64_t sentinel, uint64_t *ev_key, uint32_t *ev_val)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -66,8 +67,9 @@ __global__ void k_seq_events(int64_t ne, const int32_t *cand, const int64_t *key
         const int32_t v = cand[i];
         const int64_t kv = key[v];
         const uint64_t order = top - (uint64_t)(kv >> 16);  // score desc
-        const uint64_t b = (uint64_t)(kv & 0xFFFF);
-        const uint64_t a = (uint64_t)part[v];
+        const int32_t A = part[v];
+        const uint64_t b = (uint64_t)(bk.base(A) + (int32_t)(kv & 0xFFFF));
+        const uint64_t a = (uint64_t)A;
         ev_key[2 * i] = (b << sb) | order;
         ev_val[2 * i] = ((uint32_t)v << 1);
         ev_key[2 * i + 1] = avail[v] ? sentinel : ((a << sb) | order);
@@ -143,17 +145,18 @@ hipError_t launch_seq_select(int64_t n, const int64_t *key, const int64_t *gp, i
 }
 
 hipError_t launch_seq_net(int64_t ne, const int32_t *cand, const int64_t *key, const int32_t *part,
-                          const int32_t *vwgt, const uint8_t *avail, int32_t k, int sb,
+                          const int32_t *vwgt, const uint8_t *avail, const Blocks &bk, int sb,
                           uint64_t *ev_key, uint64_t *ev_key2, uint32_t *ev_val,
                           uint32_t *ev_val2, int64_t *prefix, int64_t *netpre, void *temp,
                           size_t temp_bytes, hipStream_t s)
 {
     if (ne <= 0) return hipSuccess;
     const int64_t nev = 2 * ne;
-    const uint64_t sentinel = (uint64_t)k << sb;
-    const int end_bit = sb + bit_width((uint64_t)k);
+    const uint64_t K = (uint64_t)bk.total();
+    const uint64_t sentinel = K << sb;
+    const int end_bit = sb + bit_width(K);
     hipLaunchKernelGGL(k_seq_events, dim3(grid_for(ne)), dim3(kBlock), 0, s, ne, cand, key, part,
-                       avail, sb, sentinel, ev_key, ev_val);
+                       avail, bk, sb, sentinel, ev_key, ev_val);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     size_t bytes = temp_bytes;

@@ -484,27 +484,30 @@ hipError_t launch_block_weights(const GraphView &g, int32_t k, const int32_t *pa
 // global atomics.
 constexpr int kStatsLdsBytes = 32768;
 
-__global__ __launch_bounds__(kBlock) void k_node_stats(GraphView g, int32_t k,
+__global__ __launch_bounds__(kBlock) void k_node_stats(GraphView g, Blocks bk,
                                                         const int32_t *__restrict__ part,
                                                         const int32_t *__restrict__ conn,
                                                         const int32_t *__restrict__ wdeg,
                                                         int64_t *W, int64_t *bucket,
                                                         int32_t t_num, int32_t t_den,
                                                         unsigned long long *counters, int cut_slot,
-                                                        uint8_t *avail_out)
+                                                        uint8_t *avail_out, int64_t *gstat,
+                                                        int gs_slot)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ unsigned long long red[4];
     __shared__ unsigned long long bad;
-    const bool w_lds = W && (size_t)k * 8 <= 16384;
-    const bool b_lds = bucket && (size_t)k * kSlots * 8 <= kStatsLdsBytes;
+    const int32_t K = bk.total();
+    const int32_t k = bk.k;
+    const bool w_lds = W && (size_t)K * 8 <= 16384;
+    const bool b_lds = bucket && (size_t)K * kSlots * 8 <= kStatsLdsBytes;
     int64_t *lw = (int64_t *)lds_raw;
-    int64_t *lb = (int64_t *)(lds_raw + (w_lds ? (size_t)k * 8 : 0));
+    int64_t *lb = (int64_t *)(lds_raw + (w_lds ? (size_t)K * 8 : 0));
     if (threadIdx.x == 0) bad = 0;
     if (w_lds)
-        for (int j = threadIdx.x; j < k; j += kBlock) lw[j] = 0;
+        for (int j = threadIdx.x; j < K; j += kBlock) lw[j] = 0;
     if (b_lds)
-        for (int j = threadIdx.x; j < k * kSlots; j += kBlock) lb[j] = 0;
+        for (int j = threadIdx.x; j < K * kSlots; j += kBlock) lb[j] = 0;
     __syncthreads();
 
     unsigned long long s = 0;
@@ -518,16 +521,17 @@ __global__ __launch_bounds__(kBlock) void k_node_stats(GraphView g, int32_t k,
         int64_t cv = 1, inner = 0, wd = 0;
         if (ok) {
             a = part[v];
-            if ((unsigned)a >= (unsigned)k) {
+            if ((unsigned)a >= (unsigned)K) {
                 atomicAdd(&bad, 1ull);
                 ok = false;
             } else {
-                inner = conn[v * (int64_t)k + a];
+                inner = conn[v * (int64_t)k + bk.local(a)];
                 wd = wdeg[v];
                 cv = node_weight(g, v);
                 s += (unsigned long long)(wd - inner);
             }
         }
+        if (gstat) wave_hist_add(gstat, (int64_t)bk.graph(a) * GS_COUNT + gs_slot, wd - inner, ok);
         if (W) {
             if (w_lds) {
                 if (ok) atomicAdd((unsigned long long *)&lw[a], (unsigned long long)cv);
@@ -552,25 +556,27 @@ __global__ __launch_bounds__(kBlock) void k_node_stats(GraphView g, int32_t k,
         if (bad) atomicAdd(&counters[CNT_BAD_INPUT], bad);
     }
     if (w_lds)
-        for (int j = threadIdx.x; j < k; j += kBlock)
+        for (int j = threadIdx.x; j < K; j += kBlock)
             if (lw[j]) atomic_add_i64(&W[j], lw[j]);
     if (b_lds)
-        for (int j = threadIdx.x; j < k * kSlots; j += kBlock)
+        for (int j = threadIdx.x; j < K * kSlots; j += kBlock)
             if (lb[j]) atomic_add_i64(&bucket[j], lb[j]);
 }
 
-hipError_t launch_node_stats(const GraphView &g, int32_t k, const int32_t *part,
+hipError_t launch_node_stats(const GraphView &g, const Blocks &bk, const int32_t *part,
                              const int32_t *conn, const int32_t *wdeg, int64_t *W,
                              int64_t *bucket, int32_t t_num, int32_t t_den,
                              unsigned long long *counters, int cut_slot, uint8_t *avail,
-                             hipStream_t s)
+                             int64_t *gstat, int gs_slot, hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
+    const int32_t K = bk.total();
     size_t lds = 0;
-    if (W && (size_t)k * 8 <= 16384) lds += (size_t)k * 8;
-    if (bucket && (size_t)k * kSlots * 8 <= kStatsLdsBytes) lds += (size_t)k * kSlots * 8;
+    if (W && (size_t)K * 8 <= 16384) lds += (size_t)K * 8;
+    if (bucket && (size_t)K * kSlots * 8 <= kStatsLdsBytes) lds += (size_t)K * kSlots * 8;
     hipLaunchKernelGGL(k_node_stats, dim3(grid_for(g.n, kBlock * 8, 2048)), dim3(kBlock), lds, s,
-                       g, k, part, conn, wdeg, W, bucket, t_num, t_den, counters, cut_slot, avail);
+                       g, bk, part, conn, wdeg, W, bucket, t_num, t_den, counters, cut_slot, avail,
+                       gstat, gs_slot);
     return hipGetLastError();
 }
 
@@ -631,18 +637,42 @@ hipError_t launch_cut_edges(const GraphView &g, const int32_t *part, unsigned lo
     return hipGetLastError();
 }
 
-__global__ void k_pack_part(int64_t n, const int32_t *part, void *pc, int bytes)
+// Graph of node v in a batch: the g with goff[g] <= v < goff[g + 1].
+__device__ __forceinline__ int32_t graph_of_node(const int64_t *goff, int32_t ng, int64_t v)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
-        pset(pc, bytes, v, part[v]);  // out-of-range values are reported by k_node_stats
+    int lo = 0, hi = ng - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (goff[mid] <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
 }
 
-hipError_t launch_pack_part(int64_t n, const int32_t *part, void *pc, int bytes, hipStream_t s)
+__global__ void k_pack_part(int64_t n, Blocks bk, const int64_t *goff, const int32_t *part,
+                            void *pc, int bytes, unsigned long long *counters)
+{
+    const int32_t K = bk.total();
+    bool bad = false;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+        const int32_t B = part[v];
+        if ((unsigned)B >= (unsigned)K) {
+            bad = true;
+            continue;
+        }
+        if (goff && bk.graph(B) != graph_of_node(goff, bk.ng, v)) bad = true;
+        pset(pc, bytes, v, bk.local(B));
+    }
+    if (__ballot(bad) && lane_id() == 0) atomicAdd(&counters[CNT_BAD_INPUT], 1ull);
+}
+
+hipError_t launch_pack_part(int64_t n, const Blocks &bk, const int64_t *goff, const int32_t *part,
+                            void *pc, int bytes, unsigned long long *counters, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pack_part, dim3(grid_for(n, kBlock * 4, 4096)), dim3(kBlock), 0, s, n, part,
-                       pc, bytes);
+    hipLaunchKernelGGL(k_pack_part, dim3(grid_for(n, kBlock * 4, 4096)), dim3(kBlock), 0, s, n, bk,
+                       goff, part, pc, bytes, counters);
     return hipGetLastError();
 }
 

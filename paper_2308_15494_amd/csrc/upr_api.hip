@@ -67,7 +67,8 @@ struct upr_ctx {
     void *seq_temp = nullptr;
     size_t seq_temp_size = 0;
     int64_t *bucket = nullptr, *penq = nullptr;
-    int64_t *pen1 = nullptr;     // [k] unit-weight penalty per target block
+    int64_t *lmax1 = nullptr, *srcl1 = nullptr;  // one graph: its L_max (device, one entry each)
+    int64_t *pen1 = nullptr;     // [K] unit-weight penalty per target block
     unsigned long long *counters = nullptr;
     unsigned long long *flags = nullptr;  // validation flags [4]
     RebalWs rb{};
@@ -94,6 +95,27 @@ struct upr_plan {
     {
         return HubView{nh, hub_ids, chunks, nchunks, gacc, hub_bits};
     }
+};
+
+// A batch: the disjoint union of ng graphs with k blocks each (see Blocks),
+// its plan, and the per-graph constants and statistics.
+struct upr_batch {
+    upr_ctx *ctx = nullptr;
+    upr_plan *plan = nullptr;  // plan of the union graph
+    int32_t ng = 0, k = 0, eps_num = 0, eps_den = 0;
+    int64_t n = 0, nnz = 0, max_n = 0;
+    // the union CSR (owned)
+    int64_t *xadj = nullptr;
+    int32_t *adjncy = nullptr, *adjwgt = nullptr, *vwgt = nullptr;
+    // host copies: node offsets [ng + 1], L_max, largest node weight, node-weighted flag
+    std::vector<int64_t> off, lmax, maxvw;
+    std::vector<uint8_t> weighted;
+    // device: node offsets, L_max, rebalancing source bound, penalty tables,
+    // statistics [ng][GS_COUNT], per-graph rebalancing results [ng][3]
+    int64_t *goff_d = nullptr, *lmax_d = nullptr, *srcl_d = nullptr, *penq_d = nullptr;
+    int64_t *gstat_d = nullptr, *host3_d = nullptr;
+    // pinned mirrors
+    int64_t *gstat_h = nullptr, *srcl_h = nullptr, *penq_h = nullptr, *host3_h = nullptr;
 };
 
 namespace {
@@ -169,7 +191,8 @@ void free_workspace(upr_ctx *c)
     c->cap_n = c->cap_k = 0;
 }
 
-// Grow the workspace to hold n nodes and k blocks.
+// Grow the workspace to hold n nodes and k blocks (all graphs' blocks for a
+// batch).
 int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
 {
     if (n <= c->cap_n && k <= c->cap_k && !c->rb_dirty) return UPR_OK;
@@ -223,7 +246,8 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
     return UPR_OK;
 }
 
-// Chunking of node ids for the rebalancer's in-bucket id bounds.
+// Chunking of node ids for the rebalancer's in-bucket id bounds: n = the
+// largest graph's node count, k = number of blocks.
 void set_chunking(RebalWs &r, int64_t n, int32_t k)
 {
     int64_t nch_max = kChunkEntries / std::max<int32_t>(k, 1);
@@ -305,22 +329,26 @@ int64_t default_iters(const upr_plan *p, int32_t k)
     return p->g.vwgt ? 4 * (int64_t)k : (int64_t)k + 1;
 }
 
-// S5: the host loop over synchronous sub-iterations.
-int rebalance_loop(upr_ctx *c, const upr_plan *p, int32_t k, int32_t *part, const PartView &pv,
-                   int32_t *conn,
-                   int64_t *W, int64_t lmax, int64_t it_max, int64_t *iters_out,
-                   int64_t *status_out, hipStream_t s)
+// 32-bit per-workgroup histograms are exact when no workgroup can add up
+// 2^32 of node weight: nodes scanned per workgroup times the largest c(v).
+int hist32_ok(const upr_plan *p)
+{
+    const int64_t per_wg = ((p->g.n + (int64_t)rb_scan_grid(p->g.n) * kBlock - 1) /
+                            ((int64_t)rb_scan_grid(p->g.n) * kBlock)) * kBlock;
+    return (unsigned __int128)per_wg * (uint64_t)std::max<int64_t>(p->maxvw, 1) <
+           ((unsigned __int128)1 << 32);
+}
+
+// S5: the host loop over synchronous sub-iterations (one graph).
+int rebalance_loop(upr_ctx *c, const upr_plan *p, const Blocks &bk, int32_t *part,
+                   const PartView &pv, int32_t *conn, int64_t *W, int64_t it_max,
+                   int64_t *iters_out, int64_t *status_out, hipStream_t s)
 {
     const HubView h = p->hubs();
     int64_t iters = 0, status = 0;
-    // 32-bit per-workgroup histograms are exact when no workgroup can add up
-    // 2^32 of node weight: nodes scanned per workgroup times the largest c(v)
-    const int64_t per_wg = ((p->g.n + (int64_t)rb_scan_grid(p->g.n) * kBlock - 1) /
-                            ((int64_t)rb_scan_grid(p->g.n) * kBlock)) * kBlock;
-    const int hist32 = (unsigned __int128)per_wg * (uint64_t)std::max<int64_t>(p->maxvw, 1) <
-                       ((unsigned __int128)1 << 32);
+    const int hist32 = hist32_ok(p);
     c->rb_dirty = true;
-    HIP_TRY(c, launch_rb_begin(k, W, lmax, c->rb, c->counters, s));
+    HIP_TRY(c, launch_rb_begin(bk, W, c->rb, c->counters, nullptr, s));
     int rc = sync_counters(c, s);
     if (rc) return rc;
     if (c->pinned[CNT_BAD_INPUT]) return fail(c, UPR_E_ARG, "part holds values outside [0, k)");
@@ -335,17 +363,87 @@ int rebalance_loop(upr_ctx *c, const upr_plan *p, int32_t k, int32_t *part, cons
             break;
         }
         ++iters;
-        HIP_TRY(c, launch_rb_iteration(p->g, k, part, conn, lmax, c->rb, c->mvto, hist32, p->hub_t,
-                                       c->counters, s));
-        HIP_TRY(c, launch_apply(p->g, k, part, pv, conn, W, c->mvto, p->low_t, p->hub_t, h, c->counters,
-                                p->dirty_threshold, c->dirty, s));
-        HIP_TRY(c, launch_rb_begin(k, W, lmax, c->rb, c->counters, s));
+        HIP_TRY(c, launch_rb_iteration(p->g, bk, part, conn, c->rb, c->mvto, hist32, p->hub_t,
+                                       c->counters, nullptr, s));
+        HIP_TRY(c, launch_apply(p->g, bk, part, pv, conn, W, c->mvto, p->low_t, p->hub_t, h,
+                                c->counters, p->dirty_threshold, c->dirty, s));
+        HIP_TRY(c, launch_rb_begin(bk, W, c->rb, c->counters, nullptr, s));
         rc = sync_counters(c, s);
         if (rc) return rc;
     }
     c->rb_dirty = false;
     *iters_out = iters;
     *status_out = status;
+    return UPR_OK;
+}
+
+// Counters and per-graph statistics to the pinned mirrors, then wait.
+int sync_batch(upr_ctx *c, const upr_batch *b, hipStream_t s)
+{
+    HIP_TRY(c, hipMemcpyAsync(c->pinned, c->counters, sizeof(unsigned long long) * CNT_COUNT,
+                              hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(b->gstat_h, b->gstat_d, sizeof(int64_t) * GS_COUNT * b->ng,
+                              hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return UPR_OK;
+}
+
+// S5 for a batch: every graph follows the single-graph loop on its own (stop
+// when balanced, when a sub-iteration moved nothing, or at its iteration
+// cap); a graph that stopped is excluded from later sub-iterations by
+// raising its source bound. Results per graph go to b->host3_h.
+int rebalance_loop_batch(upr_ctx *c, const upr_plan *p, upr_batch *b, const Blocks &bk,
+                         int32_t *part, const PartView &pv, int32_t *conn, int64_t *W,
+                         int64_t it_user, hipStream_t s)
+{
+    const HubView h = p->hubs();
+    const int32_t ng = b->ng, k = b->k;
+    const int hist32 = hist32_ok(p);
+    c->rb_dirty = true;
+    HIP_TRY(c, hipMemcpyAsync(b->srcl_d, b->lmax_d, sizeof(int64_t) * ng, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(c, launch_rb_begin(bk, W, c->rb, c->counters, b->gstat_d, s));
+    int rc = sync_batch(c, b, s);
+    if (rc) return rc;
+    if (c->pinned[CNT_BAD_INPUT]) return fail(c, UPR_E_ARG, "part holds a block outside its graph's range");
+    std::vector<int64_t> iters(ng, 0), status(ng, 0), moves(ng, 0);
+    std::vector<uint8_t> active(ng, 1);
+    for (;;) {
+        bool any = false;
+        for (int32_t g = 0; g < ng; ++g) {
+            if (!active[g]) continue;
+            const int64_t *gs = b->gstat_h + (int64_t)g * GS_COUNT;
+            if (iters[g] > 0) moves[g] += gs[GS_MOVED_NOW];
+            const int64_t cap = it_user > 0 ? it_user : (b->weighted[g] ? 4 * (int64_t)k : (int64_t)k + 1);
+            if (gs[GS_OVER] == 0) {
+                active[g] = 0;
+            } else if (iters[g] > 0 && gs[GS_MOVED_NOW] == 0) {
+                status[g] = 1;
+                active[g] = 0;
+            } else if (iters[g] >= cap) {
+                status[g] = 1;
+                active[g] = 0;
+            } else {
+                ++iters[g];
+                any = true;
+            }
+        }
+        if (!any) break;
+        for (int32_t g = 0; g < ng; ++g) b->srcl_h[g] = active[g] ? b->lmax[g] : INT64_MAX;
+        HIP_TRY(c, hipMemcpyAsync(b->srcl_d, b->srcl_h, sizeof(int64_t) * ng, hipMemcpyHostToDevice, s));
+        HIP_TRY(c, launch_rb_iteration(p->g, bk, part, conn, c->rb, c->mvto, hist32, p->hub_t,
+                                       c->counters, b->gstat_d, s));
+        HIP_TRY(c, launch_apply(p->g, bk, part, pv, conn, W, c->mvto, p->low_t, p->hub_t, h,
+                                c->counters, p->dirty_threshold, c->dirty, s));
+        HIP_TRY(c, launch_rb_begin(bk, W, c->rb, c->counters, b->gstat_d, s));
+        rc = sync_batch(c, b, s);
+        if (rc) return rc;
+    }
+    c->rb_dirty = false;
+    for (int32_t g = 0; g < ng; ++g) {
+        b->host3_h[3 * g] = iters[g];
+        b->host3_h[3 * g + 1] = status[g];
+        b->host3_h[3 * g + 2] = moves[g];
+    }
     return UPR_OK;
 }
 
@@ -399,6 +497,8 @@ int upr_create(upr_ctx **out, int device)
         hipMalloc((void **)&c->counters, sizeof(unsigned long long) * CNT_COUNT) != hipSuccess ||
         hipMalloc((void **)&c->flags, sizeof(unsigned long long) * 8) != hipSuccess ||
         hipMalloc((void **)&c->penq, sizeof(int64_t) * kSlots) != hipSuccess ||
+        hipMalloc((void **)&c->lmax1, sizeof(int64_t)) != hipSuccess ||
+        hipMalloc((void **)&c->srcl1, sizeof(int64_t)) != hipSuccess ||
         hipHostMalloc((void **)&c->pinned, sizeof(unsigned long long) * CNT_COUNT) != hipSuccess) {
         (void)hipGetLastError();
         upr_destroy(c);
@@ -418,6 +518,8 @@ void upr_destroy(upr_ctx *c)
     dfree(c->counters);
     dfree(c->flags);
     dfree(c->penq);
+    dfree(c->lmax1);
+    dfree(c->srcl1);
     if (c->pinned) (void)hipHostFree(c->pinned);
     for (auto &p : c->timing.pending) {
         (void)hipEventDestroy(p.a);
@@ -660,34 +762,50 @@ int upr_edge_cut(upr_ctx *c, const upr_plan *p, const int32_t *part, int64_t *cu
     return UPR_OK;
 }
 
-static int round_common(upr_ctx *c, const upr_plan *p, const upr_params *q, int32_t *part,
-                        int32_t *conn, int64_t *W, int64_t *stats, hipStream_t s, bool moves)
+// One round (moves = true) or a standalone rebalancing (moves = false) of a
+// single graph (b == null) or of every graph of a batch.
+static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_params *q,
+                      int32_t *part, int32_t *conn, int64_t *W, int64_t *stats, hipStream_t s,
+                      bool moves)
 {
-    int rc = check_plan(c, p);
-    if (rc) return rc;
-    rc = check_params(c, p, q);
-    if (rc) return rc;
     const int64_t n = p->g.n;
     const int32_t k = q->k;
-    if (!W || !stats || (n > 0 && (!part || !conn)))
-        return fail(c, UPR_E_ARG, "part/conn/block_w/stats NULL");
-    const int64_t lmax = upr_lmax(p->total, k, q->eps_num, q->eps_den);
-    if (p->maxvw > lmax)
-        return fail(c, UPR_E_INFEASIBLE, "node weight %lld exceeds L_max %lld", (long long)p->maxvw,
-                    (long long)lmax);
+    const int32_t ng = b ? b->ng : 1;
+    int64_t lmax = 0;
+    Blocks bk;
+    bk.k = k;
+    bk.ng = ng;
+    if (b) {
+        bk.lmax = b->lmax_d;
+        bk.src_lmax = b->srcl_d;
+        bk.penq = b->penq_d;
+    } else {
+        lmax = upr_lmax(p->total, k, q->eps_num, q->eps_den);
+        if (p->maxvw > lmax)
+            return fail(c, UPR_E_INFEASIBLE, "node weight %lld exceeds L_max %lld",
+                        (long long)p->maxvw, (long long)lmax);
+        bk.lmax = c->lmax1;
+        bk.src_lmax = c->srcl1;
+        bk.penq = c->penq;
+    }
+    const int32_t K = bk.total();
+    int64_t *gstat = b ? b->gstat_d : nullptr;
     HIP_TRY(c, hipSetDevice(c->device));
-    rc = ensure_workspace(c, n, k);
+    int rc = ensure_workspace(c, n, K);
     if (rc) return rc;
-    set_chunking(c->rb, n, k);
+    set_chunking(c->rb, b ? b->max_n : n, K);
+    c->rb.goff = b ? b->goff_d : nullptr;
     const HubView h = p->hubs();
     PhaseTimer whole(c, 7, s);
 
     PenTable pq;
-    host_penq(q->tau_num, q->tau_den, pq.q);
-    HIP_TRY(c, launch_round_init(k, c->bucket, W, pq, c->penq, c->counters, q->rebuild_table, s));
+    if (!b) host_penq(q->tau_num, q->tau_den, pq.q);
+    HIP_TRY(c, launch_round_init(bk, c->bucket, W, pq, lmax, b ? 0 : 1, c->counters,
+                                 q->rebuild_table, s));
+    if (b) HIP_TRY(c, launch_fill_i64(gstat, (int64_t)GS_COUNT * ng, 0, s));
     // compact partition copy for the neighbour gathers (kept in step by the apply)
     const PartView pv{c->pc, k <= 256 ? 1 : 2};
-    HIP_TRY(c, launch_pack_part(n, part, c->pc, pv.bytes, s));
+    HIP_TRY(c, launch_pack_part(n, bk, b ? b->goff_d : nullptr, part, c->pc, pv.bytes, c->counters, s));
     if (q->rebuild_table) {
         {
             PhaseTimer t(c, 0, s);
@@ -700,31 +818,35 @@ static int round_common(upr_ctx *c, const upr_plan *p, const upr_params *q, int3
     }
     {
         PhaseTimer t(c, 1, s);
-        HIP_TRY(c, launch_node_stats(p->g, k, part, conn, p->wdeg, q->rebuild_table ? W : nullptr,
+        HIP_TRY(c, launch_node_stats(p->g, bk, part, conn, p->wdeg, q->rebuild_table ? W : nullptr,
                                      moves ? c->bucket : nullptr, q->t_num, q->t_den, c->counters,
                                      CNT_CUT2_BEFORE, moves && q->seq_penalty ? c->avail : nullptr,
-                                     s));
+                                     gstat, GS_CUT2_BEFORE, s));
     }
+    bool moved = false;
     if (moves) {
         {
             PhaseTimer t(c, 2, s);
-            HIP_TRY(c, launch_cb_prefix(k, c->bucket, W, lmax, c->penq, q->mode, c->pen1, s));
-            HIP_TRY(c, launch_best_move(p->g, k, part, conn, W, c->bucket, c->penq, c->pen1, lmax,
-                                        q->mode, c->key, c->pen, c->counters, s));
+            HIP_TRY(c, launch_cb_prefix(bk, c->bucket, W, q->mode, c->pen1, s));
+            HIP_TRY(c, launch_best_move(p->g, bk, part, conn, W, c->bucket, c->pen1, q->mode,
+                                        c->key, c->pen, c->counters, s));
         }
         // one host decision: are there candidates at all (also reports bad input)
         rc = sync_counters(c, s);
         if (rc) return rc;
-        if (c->pinned[CNT_BAD_INPUT]) return fail(c, UPR_E_ARG, "part holds values outside [0, k)");
+        if (c->pinned[CNT_BAD_INPUT])
+            return fail(c, UPR_E_ARG, b ? "part holds a block outside its graph's range"
+                                        : "part holds values outside [0, k)");
         const int64_t nc = (int64_t)c->pinned[CNT_CAND];
         if (nc > 0) {
+            moved = true;
             {
                 PhaseTimer t(c, 3, s);
                 int64_t *gp_out = q->seq_penalty ? c->gp : nullptr;
-                HIP_TRY(c, launch_filter(p->g, part, pv, c->key, c->pen, p->low_t, p->hub_t, c->mvto,
-                                         c->accflag, c->counters, gp_out, s));
-                HIP_TRY(c, launch_filter_hub(p->g, part, pv, c->key, c->pen, h, c->mvto, c->accflag,
-                                             c->counters, gp_out, s));
+                HIP_TRY(c, launch_filter(p->g, bk, part, pv, c->key, c->pen, p->low_t, p->hub_t,
+                                         c->mvto, c->accflag, c->counters, gp_out, s));
+                HIP_TRY(c, launch_filter_hub(p->g, bk, part, pv, c->key, c->pen, h, c->mvto,
+                                             c->accflag, c->counters, gp_out, s));
                 if (q->seq_penalty) {
                     // eligible candidates in id order; their number sizes the sort
                     HIP_TRY(c, launch_seq_select(n, c->key, c->gp, c->cand,
@@ -733,26 +855,28 @@ static int round_common(upr_ctx *c, const upr_plan *p, const upr_params *q, int3
                     rc = sync_counters(c, s);
                     if (rc) return rc;
                     const int64_t ne = (int64_t)c->pinned[CNT_ELIG];
-                    HIP_TRY(c, launch_seq_net(ne, c->cand, c->key, part, p->g.vwgt, c->avail, k,
+                    HIP_TRY(c, launch_seq_net(ne, c->cand, c->key, part, p->g.vwgt, c->avail, bk,
                                               seq_score_bits(p->maxwdeg), c->ev_key, c->ev_key2,
                                               c->ev_val, c->ev_val2, c->ev_prefix, c->netpre,
                                               c->seq_temp, c->seq_temp_size, s));
-                    HIP_TRY(c, launch_filter_seq(p->g, k, c->cand, ne, c->key, c->gp, c->netpre, W,
-                                                 c->bucket, c->penq, lmax, q->mode, p->hub_t,
+                    HIP_TRY(c, launch_filter_seq(p->g, bk, part, c->cand, ne, c->key, c->gp,
+                                                 c->netpre, W, c->bucket, q->mode, p->hub_t,
                                                  c->mvto, c->accflag, c->counters, s));
                 }
+                if (b) HIP_TRY(c, launch_batch_move_stats(n, bk, part, c->key, c->accflag, gstat, s));
             }
             {
                 PhaseTimer t(c, 4, s);
-                HIP_TRY(c, launch_apply(p->g, k, part, pv, conn, W, c->mvto, p->low_t, p->hub_t, h,
-                                        c->counters, p->dirty_threshold, c->dirty, s));
+                HIP_TRY(c, launch_apply(p->g, bk, part, pv, conn, W, c->mvto, p->low_t, p->hub_t,
+                                        h, c->counters, p->dirty_threshold, c->dirty, s));
             }
             {
                 PhaseTimer t(c, 6, s);
-                HIP_TRY(c, launch_node_stats(p->g, k, part, conn, p->wdeg, nullptr, nullptr, 0, 1,
-                                             c->counters, CNT_CUT2_MOVES, nullptr, s));
+                HIP_TRY(c, launch_node_stats(p->g, bk, part, conn, p->wdeg, nullptr, nullptr, 0, 1,
+                                             c->counters, CNT_CUT2_MOVES, nullptr, gstat,
+                                             GS_CUT2_MOVES, s));
             }
-        } else {
+        } else if (!b) {
             HIP_TRY(c, hipMemcpyAsync(c->counters + CNT_CUT2_MOVES, c->counters + CNT_CUT2_BEFORE,
                                       sizeof(unsigned long long), hipMemcpyDeviceToDevice, s));
         }
@@ -760,14 +884,25 @@ static int round_common(upr_ctx *c, const upr_plan *p, const upr_params *q, int3
     int64_t iters = 0, status = 0;
     {
         PhaseTimer t(c, 5, s);
-        const int64_t it_max = q->max_rebalance_iters > 0 ? q->max_rebalance_iters : default_iters(p, k);
-        rc = rebalance_loop(c, p, k, part, pv, conn, W, lmax, it_max, &iters, &status, s);
+        if (b) {
+            rc = rebalance_loop_batch(c, p, b, bk, part, pv, conn, W, q->max_rebalance_iters, s);
+        } else {
+            const int64_t it_max =
+                q->max_rebalance_iters > 0 ? q->max_rebalance_iters : default_iters(p, k);
+            rc = rebalance_loop(c, p, bk, part, pv, conn, W, it_max, &iters, &status, s);
+        }
         if (rc) return rc;
     }
     {
         PhaseTimer t(c, 6, s);
-        HIP_TRY(c, launch_node_stats(p->g, k, part, conn, p->wdeg, nullptr, nullptr, 0, 1,
-                                     c->counters, CNT_CUT2_AFTER, nullptr, s));
+        HIP_TRY(c, launch_node_stats(p->g, bk, part, conn, p->wdeg, nullptr, nullptr, 0, 1,
+                                     c->counters, CNT_CUT2_AFTER, nullptr, gstat, GS_CUT2_AFTER, s));
+    }
+    if (b) {
+        HIP_TRY(c, hipMemcpyAsync(b->host3_d, b->host3_h, sizeof(int64_t) * 3 * ng,
+                                  hipMemcpyHostToDevice, s));
+        HIP_TRY(c, launch_batch_stats_final(ng, gstat, b->lmax_d, b->host3_d, moved ? 1 : 0, stats, s));
+        return UPR_OK;
     }
     if (!moves) {
         // standalone rebalancing: nothing moved before it
@@ -776,6 +911,18 @@ static int round_common(upr_ctx *c, const upr_plan *p, const upr_params *q, int3
     }
     HIP_TRY(c, launch_stats_final(stats, c->counters, lmax, iters, status, s));
     return UPR_OK;
+}
+
+static int round_common(upr_ctx *c, const upr_plan *p, const upr_params *q, int32_t *part,
+                        int32_t *conn, int64_t *W, int64_t *stats, hipStream_t s, bool moves)
+{
+    int rc = check_plan(c, p);
+    if (rc) return rc;
+    rc = check_params(c, p, q);
+    if (rc) return rc;
+    if (!W || !stats || (p->g.n > 0 && (!part || !conn)))
+        return fail(c, UPR_E_ARG, "part/conn/block_w/stats NULL");
+    return round_core(c, p, nullptr, q, part, conn, W, stats, s, moves);
 }
 
 int upr_refine_round(upr_ctx *c, const upr_plan *p, const upr_params *q, int32_t *part,
@@ -788,6 +935,214 @@ int upr_rebalance(upr_ctx *c, const upr_plan *p, const upr_params *q, int32_t *p
                   int64_t *W, int64_t *stats, hipStream_t s)
 {
     return round_common(c, p, q, part, conn, W, stats, s, false);
+}
+
+// ------------------------------------------------------------- batches --
+
+void upr_batch_destroy(upr_batch *b)
+{
+    if (!b) return;
+    if (b->ctx) (void)hipSetDevice(b->ctx->device);
+    (void)hipDeviceSynchronize();
+    if (b->plan) upr_plan_destroy(b->plan);
+    dfree(b->xadj);
+    dfree(b->adjncy);
+    dfree(b->adjwgt);
+    dfree(b->vwgt);
+    dfree(b->goff_d);
+    dfree(b->lmax_d);
+    dfree(b->srcl_d);
+    dfree(b->penq_d);
+    dfree(b->gstat_d);
+    dfree(b->host3_d);
+    for (int64_t *h : {b->gstat_h, b->srcl_h, b->penq_h, b->host3_h})
+        if (h) (void)hipHostFree(h);
+    delete b;
+}
+
+int upr_batch_create(upr_ctx *c, const upr_graph *graphs, int32_t ng, int32_t k, int32_t eps_num,
+                     int32_t eps_den, upr_batch **out, hipStream_t s)
+{
+    if (!c) return UPR_E_ARG;
+    if (!out) return fail(c, UPR_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!graphs || ng < 1) return fail(c, UPR_E_ARG, "need at least one graph");
+    if (k < 2 || k > UPR_MAX_K) return fail(c, UPR_E_ARG, "k=%d outside [2, %d]", k, UPR_MAX_K);
+    if ((int64_t)ng * k > UPR_MAX_BATCH_BLOCKS)
+        return fail(c, UPR_E_ARG, "ng*k = %lld blocks exceeds %d", (long long)ng * k,
+                    UPR_MAX_BATCH_BLOCKS);
+    if (eps_num <= 0 || eps_den <= 0) return fail(c, UPR_E_ARG, "eps must be > 0");
+    HIP_TRY(c, hipSetDevice(c->device));
+    upr_batch *b = new upr_batch();
+    b->ctx = c;
+    b->ng = ng;
+    b->k = k;
+    b->eps_num = eps_num;
+    b->eps_den = eps_den;
+    auto bail = [&](int code, const char *msg) {
+        upr_batch_destroy(b);
+        return fail(c, code, "%s", msg);
+    };
+    // sizes and offsets
+    std::vector<int64_t> eoff(ng + 1, 0);
+    b->off.assign(ng + 1, 0);
+    b->weighted.assign(ng, 0);
+    bool any_ew = false, any_vw = false;
+    for (int32_t g = 0; g < ng; ++g) {
+        const upr_graph &G = graphs[g];
+        if (G.n < 0 || (G.n > 0 && !G.xadj)) return bail(UPR_E_ARG, "a graph has n < 0 or xadj NULL");
+        int64_t nnz = 0;
+        if (G.n > 0 && hipMemcpy(&nnz, G.xadj + G.n, sizeof nnz, hipMemcpyDeviceToHost) != hipSuccess)
+            return bail(UPR_E_HIP, "reading xadj[n] failed");
+        if (nnz < 0 || (nnz > 0 && !G.adjncy)) return bail(UPR_E_GRAPH, "a graph has xadj[n] < 0 or adjncy NULL");
+        b->off[g + 1] = b->off[g] + G.n;
+        eoff[g + 1] = eoff[g] + nnz;
+        b->max_n = std::max<int64_t>(b->max_n, G.n);
+        any_ew |= G.adjwgt != nullptr;
+        any_vw |= G.vwgt != nullptr;
+        b->weighted[g] = G.vwgt != nullptr;
+    }
+    b->n = b->off[ng];
+    b->nnz = eoff[ng];
+    if (b->n >= ((int64_t)1 << 31) - 1) return bail(UPR_E_ARG, "the batch has 2^31 nodes or more");
+    // the union CSR
+    if (dalloc(&b->xadj, b->n + 1) != hipSuccess || dalloc(&b->adjncy, b->nnz) != hipSuccess ||
+        (any_ew && dalloc(&b->adjwgt, b->nnz) != hipSuccess) ||
+        (any_vw && dalloc(&b->vwgt, b->n) != hipSuccess) || dalloc(&b->goff_d, ng + 1) != hipSuccess ||
+        dalloc(&b->lmax_d, ng) != hipSuccess || dalloc(&b->srcl_d, ng) != hipSuccess ||
+        dalloc(&b->penq_d, (int64_t)ng * kSlots) != hipSuccess ||
+        dalloc(&b->gstat_d, (int64_t)ng * GS_COUNT) != hipSuccess ||
+        dalloc(&b->host3_d, 3 * (int64_t)ng) != hipSuccess)
+        return bail(UPR_E_NOMEM, "batch allocation failed");
+    if (hipHostMalloc((void **)&b->gstat_h, sizeof(int64_t) * GS_COUNT * ng) != hipSuccess ||
+        hipHostMalloc((void **)&b->srcl_h, sizeof(int64_t) * ng) != hipSuccess ||
+        hipHostMalloc((void **)&b->penq_h, sizeof(int64_t) * kSlots * ng) != hipSuccess ||
+        hipHostMalloc((void **)&b->host3_h, sizeof(int64_t) * 3 * ng) != hipSuccess)
+        return bail(UPR_E_NOMEM, "pinned batch allocation failed");
+    // every graph: rows well formed (xadj from 0, nondecreasing; positive node
+    // weights) before anything reads its adjacency, then neighbour ids inside
+    // the graph and positive edge weights
+    unsigned long long init[4] = {~0ull, ~0ull, ~0ull, ~0ull}, got[4];
+    HIP_TRY(c, hipMemcpyAsync(c->flags, init, sizeof init, hipMemcpyHostToDevice, s));
+    for (int32_t g = 0; g < ng; ++g) {
+        const upr_graph &G = graphs[g];
+        if (G.n > 0)
+            HIP_TRY(c, launch_validate(GraphView{G.n, G.xadj, G.adjncy, G.adjwgt, G.vwgt}, c->flags, 0, s));
+    }
+    HIP_TRY(c, hipMemcpyAsync(got, c->flags, sizeof got, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if (got[0] != ~0ull) return bail(UPR_E_GRAPH, "a graph's xadj does not start at 0 or decreases");
+    if (got[3] != ~0ull) return bail(UPR_E_GRAPH, "a graph has a non-positive node weight");
+    for (int32_t g = 0; g < ng; ++g) {
+        const upr_graph &G = graphs[g];
+        const GraphView src{G.n, G.xadj, G.adjncy, G.adjwgt, G.vwgt};
+        if (G.n == 0) continue;
+        HIP_TRY(c, launch_validate(src, c->flags, 1, s));
+        if (launch_batch_copy(src, b->off[g], eoff[g], eoff[g + 1] - eoff[g], b->xadj, b->adjncy,
+                              b->adjwgt, b->vwgt, 0, s) != hipSuccess)
+            return bail(UPR_E_HIP, "copying a graph into the batch failed");
+    }
+    // the closing offset xadj[n] (from pageable memory: the copy completes before returning)
+    HIP_TRY(c, hipMemcpyAsync(b->xadj + b->n, &eoff[ng], sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(got, c->flags, sizeof got, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if (got[1] != ~0ull) return bail(UPR_E_GRAPH, "a graph names a neighbour outside its own nodes");
+    if (got[3] != ~0ull) return bail(UPR_E_GRAPH, "a graph has a non-positive edge weight");
+    const upr_graph ug{b->n, b->xadj, b->adjncy, b->adjwgt, b->vwgt};
+    int rc = upr_plan_create(c, &ug, &b->plan, s);
+    if (rc) {
+        const std::string msg = c->err;
+        upr_batch_destroy(b);
+        return fail(c, rc, "batch plan: %s", msg.c_str());
+    }
+    // per-graph L_max from the graphs' total node weights
+    std::vector<int64_t> tot(2 * (size_t)ng);
+    int64_t *d_tot = nullptr;
+    if (dalloc(&d_tot, 2 * (int64_t)ng) != hipSuccess) return bail(UPR_E_NOMEM, "batch allocation failed");
+    bool ok = hipMemcpy(b->goff_d, b->off.data(), sizeof(int64_t) * (ng + 1), hipMemcpyHostToDevice) == hipSuccess &&
+              launch_batch_totals(b->goff_d, ng, b->vwgt, d_tot, s) == hipSuccess &&
+              hipStreamSynchronize(s) == hipSuccess &&
+              hipMemcpy(tot.data(), d_tot, sizeof(int64_t) * 2 * ng, hipMemcpyDeviceToHost) == hipSuccess;
+    dfree(d_tot);
+    if (!ok) return bail(UPR_E_HIP, "batch totals failed");
+    b->lmax.resize(ng);
+    b->maxvw.resize(ng);
+    for (int32_t g = 0; g < ng; ++g) {
+        b->lmax[g] = upr_lmax(tot[2 * g], k, eps_num, eps_den);
+        b->maxvw[g] = tot[2 * g + 1];
+        if (b->maxvw[g] > b->lmax[g]) {
+            upr_batch_destroy(b);
+            return fail(c, UPR_E_INFEASIBLE, "graph %d: node weight %lld exceeds L_max %lld", g,
+                        (long long)tot[2 * g + 1], (long long)b->lmax[g]);
+        }
+    }
+    if (hipMemcpy(b->lmax_d, b->lmax.data(), sizeof(int64_t) * ng, hipMemcpyHostToDevice) != hipSuccess)
+        return bail(UPR_E_HIP, "batch upload failed");
+    *out = b;
+    return UPR_OK;
+}
+
+int upr_batch_info(const upr_batch *b, int64_t *n_total, int64_t *nnz_total, int64_t *node_off,
+                   int64_t *lmax)
+{
+    if (!b) return UPR_E_ARG;
+    if (n_total) *n_total = b->n;
+    if (nnz_total) *nnz_total = b->nnz;
+    if (node_off) std::copy(b->off.begin(), b->off.end(), node_off);
+    if (lmax) std::copy(b->lmax.begin(), b->lmax.end(), lmax);
+    return UPR_OK;
+}
+
+static int batch_common(upr_ctx *c, upr_batch *b, const upr_params *q, const int32_t *tau_num,
+                        const int32_t *tau_den, int32_t *part, int32_t *conn, int64_t *W,
+                        int64_t *stats, hipStream_t s, bool moves)
+{
+    if (!c) return UPR_E_ARG;
+    if (!b) return fail(c, UPR_E_ARG, "batch is NULL");
+    if (b->ctx != c) return fail(c, UPR_E_ARG, "batch belongs to another context");
+    int rc = check_params(c, b->plan, q);
+    if (rc) return rc;
+    if (q->k != b->k) return fail(c, UPR_E_ARG, "k=%d but the batch was built for k=%d", q->k, b->k);
+    if ((int64_t)q->eps_num * b->eps_den != (int64_t)b->eps_num * q->eps_den)
+        return fail(c, UPR_E_ARG, "eps differs from the batch's");
+    if (!W || !stats || (b->n > 0 && (!part || !conn)))
+        return fail(c, UPR_E_ARG, "part/conn/block_w/stats NULL");
+    if ((tau_num == nullptr) != (tau_den == nullptr))
+        return fail(c, UPR_E_ARG, "give both tau arrays or neither");
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (moves) {
+        // per-graph penalty tables; graphs in the same round share one
+        int64_t last_num = -1, last_den = -1;
+        for (int32_t g = 0; g < b->ng; ++g) {
+            const int32_t tn = tau_num ? tau_num[g] : q->tau_num;
+            const int32_t td = tau_den ? tau_den[g] : q->tau_den;
+            if (td <= 0 || tn < 0 || tn > td) return fail(c, UPR_E_ARG, "graph %d: tau must be in [0, 1]", g);
+            int64_t *row = b->penq_h + (int64_t)g * kSlots;
+            if (g > 0 && tn == last_num && td == last_den) {
+                std::copy(row - kSlots, row, row);
+            } else {
+                host_penq(tn, td, row);
+                last_num = tn;
+                last_den = td;
+            }
+        }
+        HIP_TRY(c, hipMemcpyAsync(b->penq_d, b->penq_h, sizeof(int64_t) * kSlots * b->ng,
+                                  hipMemcpyHostToDevice, s));
+    }
+    return round_core(c, b->plan, b, q, part, conn, W, stats, s, moves);
+}
+
+int upr_batch_refine_round(upr_ctx *c, upr_batch *b, const upr_params *q, const int32_t *tau_num,
+                           const int32_t *tau_den, int32_t *part, int32_t *conn, int64_t *W,
+                           int64_t *stats, hipStream_t s)
+{
+    return batch_common(c, b, q, tau_num, tau_den, part, conn, W, stats, s, true);
+}
+
+int upr_batch_rebalance(upr_ctx *c, upr_batch *b, const upr_params *q, int32_t *part,
+                        int32_t *conn, int64_t *W, int64_t *stats, hipStream_t s)
+{
+    return batch_common(c, b, q, nullptr, nullptr, part, conn, W, stats, s, false);
 }
 
 int upr_last_moves(upr_ctx *c, int64_t n, int32_t *target, int64_t *score, int64_t *pen,

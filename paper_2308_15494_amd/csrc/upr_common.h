@@ -38,6 +38,40 @@ struct PenTable {
     int64_t q[kSlots];
 };
 
+// The blocks a round works on. One graph: k blocks, block id B = j. A batch:
+// the disjoint union of ng graphs with k blocks each, refined together. Node
+// v of graph g lies in the global block B = g*k + j, and its gain-table row
+// (k wide) is indexed by the local block j. Block weights, penalty buckets
+// and rebalancing state are indexed by B. Every graph has its own L_max and
+// penalty table; the rounds of different graphs never interact.
+struct Blocks {
+    int32_t k = 0;
+    int32_t ng = 1;
+    const int64_t *lmax = nullptr;      // [ng] L_max of each graph
+    const int64_t *src_lmax = nullptr;  // [ng] rebalancing: a block is a source iff heavier
+    const int64_t *penq = nullptr;      // [ng * kSlots] Q16 penalty table of each graph
+    __host__ __device__ int32_t total() const { return k * ng; }
+    __device__ int32_t graph(int32_t B) const { return ng == 1 ? 0 : B / k; }
+    __device__ int32_t base(int32_t B) const { return ng == 1 ? 0 : (B / k) * k; }
+    __device__ int32_t local(int32_t B) const { return ng == 1 ? B : B % k; }
+    __device__ int64_t lmax_of(int32_t B) const { return lmax[graph(B)]; }
+    __device__ int64_t src_lmax_of(int32_t B) const { return src_lmax[graph(B)]; }
+    __device__ const int64_t *penq_of(int32_t B) const { return penq + (int64_t)graph(B) * kSlots; }
+};
+
+// Per-graph statistics of a batch (int64 [ng][GS_COUNT]).
+enum GraphStat {
+    GS_CUT2_BEFORE = 0,
+    GS_CUT2_MOVES,
+    GS_CUT2_AFTER,
+    GS_CAND,
+    GS_ACC,
+    GS_REBAL_MOVES,
+    GS_MOVED_NOW,  // moves of the current rebalancing sub-iteration
+    GS_OVER,       // overloaded blocks at the start of a sub-iteration
+    GS_COUNT
+};
+
 struct GraphView {
     int64_t n;
     const int64_t *xadj;
@@ -313,16 +347,22 @@ hipError_t launch_gain_hub(const GraphView &g, int32_t k, const PartView &part, 
 hipError_t launch_rebuild_hub_rows(const GraphView &g, int32_t k, const PartView &part,
                                    int32_t *conn, const HubView &h, hipStream_t s);
 // Compact copy of part (bytes = 1 or 2).
-hipError_t launch_pack_part(int64_t n, const int32_t *part, void *pc, int bytes, hipStream_t s);
+// Compact copy of the local blocks (bytes = 1 or 2). Checks every value: a
+// global block id below bk.total() and, for a batch (goff = node offsets of
+// the graphs, ng + 1 entries), a block of the node's own graph; violations
+// count in counters[CNT_BAD_INPUT].
+hipError_t launch_pack_part(int64_t n, const Blocks &bk, const int64_t *goff, const int32_t *part,
+                            void *pc, int bytes, unsigned long long *counters, hipStream_t s);
 hipError_t launch_hub_bits(const HubView &h, uint32_t *bits, hipStream_t s);
 // Per node: 2*cut into counters[cut_slot], penalty buckets of the available
 // nodes (bucket may be null), block weights W[part] += c (W may be null),
 // availability for rebalancing (avail may be null).
-hipError_t launch_node_stats(const GraphView &g, int32_t k, const int32_t *part,
+// gstat (batch): the cut also goes to gstat[graph][gs_slot].
+hipError_t launch_node_stats(const GraphView &g, const Blocks &bk, const int32_t *part,
                              const int32_t *conn, const int32_t *wdeg, int64_t *W,
                              int64_t *bucket, int32_t t_num, int32_t t_den,
                              unsigned long long *counters, int cut_slot, uint8_t *avail,
-                             hipStream_t s);
+                             int64_t *gstat, int gs_slot, hipStream_t s);
 hipError_t launch_block_weights(const GraphView &g, int32_t k, const int32_t *part, int64_t *W,
                                 unsigned long long *counters, hipStream_t s);
 hipError_t launch_cut_edges(const GraphView &g, const int32_t *part, unsigned long long *acc,
@@ -332,29 +372,35 @@ hipError_t launch_check_part(int64_t n, int32_t k, const int32_t *part,
                              unsigned long long *counters, hipStream_t s);
 
 // moves (S0, S2-S4)
-hipError_t launch_round_init(int32_t k, int64_t *bucket, int64_t *W, const PenTable &pq,
-                             int64_t *penq, unsigned long long *counters, int zero_w, hipStream_t s);
-// Prefix sums of the buckets; pen1[j] = penalty of a unit-weight node moving
-// into j (0 if it fits, -1 if forbidden).
-hipError_t launch_cb_prefix(int32_t k, int64_t *bucket, const int64_t *W, int64_t lmax,
-                            const int64_t *penq, int mode, int64_t *pen1, hipStream_t s);
-hipError_t launch_best_move(const GraphView &g, int32_t k, const int32_t *part, const int32_t *conn,
-                            const int64_t *W, const int64_t *cb, const int64_t *penq,
-                            const int64_t *pen1, int64_t lmax, int mode, int64_t *key,
-                            int64_t *pen, unsigned long long *counters, hipStream_t s);
+// Zero the counters, the buckets ([K][kSlots]) and, if zero_w, W ([K]).
+// With single (one graph) also publish its penalty table and L_max into
+// bk.penq / bk.lmax / bk.src_lmax (writable workspace).
+hipError_t launch_round_init(const Blocks &bk, int64_t *bucket, int64_t *W, const PenTable &pq,
+                             int64_t lmax, int single, unsigned long long *counters, int zero_w,
+                             hipStream_t s);
+// Prefix sums of the buckets; pen1[B] = penalty of a unit-weight node moving
+// into B (0 if it fits, -1 if forbidden).
+hipError_t launch_cb_prefix(const Blocks &bk, int64_t *bucket, const int64_t *W, int mode,
+                            int64_t *pen1, hipStream_t s);
+hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t *part,
+                            const int32_t *conn, const int64_t *W, const int64_t *cb,
+                            const int64_t *pen1, int mode, int64_t *key, int64_t *pen,
+                            unsigned long long *counters, hipStream_t s);
 // With gp_out the pessimistic gains are stored (decided by launch_filter_seq).
-hipError_t launch_filter(const GraphView &g, const int32_t *part, const PartView &pv,
+hipError_t launch_filter(const GraphView &g, const Blocks &bk, const int32_t *part,
+                         const PartView &pv,
                          const int64_t *key, const int64_t *pen, int64_t low_t, int64_t hub_t,
                          int32_t *mvto, uint8_t *accflag, unsigned long long *counters,
                          int64_t *gp_out, hipStream_t s);
-hipError_t launch_filter_hub(const GraphView &g, const int32_t *part, const PartView &pv,
+hipError_t launch_filter_hub(const GraphView &g, const Blocks &bk, const int32_t *part,
+                             const PartView &pv,
                              const int64_t *key, const int64_t *pen, const HubView &h,
                              int32_t *mvto, uint8_t *accflag, unsigned long long *counters,
                              int64_t *gp_out, hipStream_t s);
-hipError_t launch_filter_seq(const GraphView &g, int32_t k, const int32_t *cand, int64_t ne,
-                             const int64_t *key, const int64_t *gp, const int64_t *netpre,
-                             const int64_t *W, const int64_t *cb, const int64_t *penq,
-                             int64_t lmax, int mode, int64_t hub_t, int32_t *mvto,
+hipError_t launch_filter_seq(const GraphView &g, const Blocks &bk, const int32_t *part,
+                             const int32_t *cand, int64_t ne, const int64_t *key,
+                             const int64_t *gp, const int64_t *netpre, const int64_t *W,
+                             const int64_t *cb, int mode, int64_t hub_t, int32_t *mvto,
                              uint8_t *accflag, unsigned long long *counters, hipStream_t s);
 
 // Sequence-aware penalty (k_seq.hip): the eligible candidates (pessimistic
@@ -366,7 +412,7 @@ hipError_t launch_seq_select(int64_t n, const int64_t *key, const int64_t *gp, i
                              unsigned long long *count, void *temp, size_t temp_bytes,
                              hipStream_t s);
 hipError_t launch_seq_net(int64_t ne, const int32_t *cand, const int64_t *key, const int32_t *part,
-                          const int32_t *vwgt, const uint8_t *avail, int32_t k, int sb,
+                          const int32_t *vwgt, const uint8_t *avail, const Blocks &bk, int sb,
                           uint64_t *ev_key, uint64_t *ev_key2, uint32_t *ev_val,
                           uint32_t *ev_val2, int64_t *prefix, int64_t *netpre, void *temp,
                           size_t temp_bytes, hipStream_t s);
@@ -376,7 +422,7 @@ hipError_t launch_seq_net(int64_t ne, const int32_t *cand, const int64_t *key, c
 // otherwise their gain-table tiles are marked and rebuilt from the new
 // partition. Hub rows are always rebuilt.
 // pv: the compact partition copy to keep in step (pv.p writable, or bytes 4).
-hipError_t launch_apply(const GraphView &g, int32_t k, int32_t *part, const PartView &pv,
+hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, const PartView &pv,
                         int32_t *conn, int64_t *W, int32_t *mvto, int64_t low_t, int64_t hub_t,
                         const HubView &h, const unsigned long long *counters,
                         int64_t dirty_threshold, uint8_t *dirty, hipStream_t s);
@@ -387,33 +433,52 @@ hipError_t launch_export_moves(int64_t n, const int64_t *key, const int64_t *pen
                                int64_t *pen_out, uint8_t *accept, hipStream_t s);
 
 // rebalance (S5)
+// Rebalancing workspace; K = bk.total() blocks (global block ids).
 struct RebalWs {
-    int32_t *rtgt;       // [n] target of a node of an overloaded block, -1 if none
+    int32_t *rtgt;       // [n] target block of a node of an overloaded block, -1 if none
     uint8_t *rbeta;      // [n] its priority bucket
-    int64_t *W0;         // [k] block weights at sub-iteration start
-    int64_t *hist_src;   // [k * kRbBuckets]
-    int64_t *hist_tgt;   // [k * kRbBuckets]
-    int32_t *cbeta_src;  // [k] cutoff bucket per source block
-    int32_t *cbeta_tgt;  // [k] cutoff bucket per target block
-    int64_t *need_src;   // [k] weight still needed inside the cutoff bucket
-    int64_t *room_tgt;   // [k] capacity left inside the cutoff bucket
-    int32_t *theta_src;  // [k] id bound inside the cutoff bucket (exclusive)
-    int32_t *theta_tgt;  // [k]
-    int64_t *chunk_src;  // [k * nchunks]
-    int64_t *chunk_tgt;  // [k * nchunks]
-    int chunk_shift;
+    int64_t *W0;         // [K] block weights at sub-iteration start
+    int64_t *hist_src;   // [K * kRbBuckets]
+    int64_t *hist_tgt;   // [K * kRbBuckets]
+    int32_t *cbeta_src;  // [K] cutoff bucket per source block
+    int32_t *cbeta_tgt;  // [K] cutoff bucket per target block
+    int64_t *need_src;   // [K] weight still needed inside the cutoff bucket
+    int64_t *room_tgt;   // [K] capacity left inside the cutoff bucket
+    int32_t *theta_src;  // [K] id bound inside the cutoff bucket (exclusive)
+    int32_t *theta_tgt;  // [K]
+    int64_t *chunk_src;  // [K * nchunks]
+    int64_t *chunk_tgt;  // [K * nchunks]
+    int chunk_shift;     // a chunk holds 2^chunk_shift consecutive node ids of one graph
     int64_t nchunks;
+    const int64_t *goff;  // batch: node offset of each graph (ng + 1 entries); null: one graph
 };
 
-hipError_t launch_rb_begin(int32_t k, const int64_t *W, int64_t lmax, const RebalWs &r,
-                           unsigned long long *counters, hipStream_t s);
+// Snapshot W and count the source blocks (weight above src_lmax): in total
+// (counters[CNT_OVER]) and, for a batch, per graph (gstat[g][GS_OVER]).
+hipError_t launch_rb_begin(const Blocks &bk, const int64_t *W, const RebalWs &r,
+                           unsigned long long *counters, int64_t *gstat, hipStream_t s);
 // One sub-iteration up to the move marks: targets and buckets, source and
 // target selection; accepted nodes get mvto[v] = target. hist32: the
 // per-workgroup histograms may use 32-bit LDS counters (no overflow).
-hipError_t launch_rb_iteration(const GraphView &g, int32_t k, const int32_t *part,
-                               const int32_t *conn, int64_t lmax, const RebalWs &r,
-                               int32_t *mvto, int hist32, int64_t hub_t,
-                               unsigned long long *counters, hipStream_t s);
+// gstat (batch): moves per graph in gstat[g][GS_MOVED_NOW] (reset first) and
+// gstat[g][GS_REBAL_MOVES].
+hipError_t launch_rb_iteration(const GraphView &g, const Blocks &bk, const int32_t *part,
+                               const int32_t *conn, const RebalWs &r, int32_t *mvto, int hist32,
+                               int64_t hub_t, unsigned long long *counters, int64_t *gstat,
+                               hipStream_t s);
 int rb_scan_grid(int64_t n);
+
+// batches (k_batch.hip)
+hipError_t launch_batch_copy(const GraphView &src, int64_t node_off, int64_t edge_off,
+                             int64_t nnz, int64_t *xadj, int32_t *adjncy, int32_t *adjwgt,
+                             int32_t *vwgt, int last, hipStream_t s);
+// out[2g] = total node weight of graph g, out[2g + 1] = its largest node weight.
+hipError_t launch_batch_totals(const int64_t *goff, int32_t ng, const int32_t *vwgt, int64_t *out,
+                               hipStream_t s);
+hipError_t launch_batch_move_stats(int64_t n, const Blocks &bk, const int32_t *part,
+                                   const int64_t *key, const uint8_t *accflag, int64_t *gstat,
+                                   hipStream_t s);
+hipError_t launch_batch_stats_final(int32_t ng, const int64_t *gstat, const int64_t *lmax,
+                                    const int64_t *host3, int moved, int64_t *stats, hipStream_t s);
 
 }  // namespace upr

@@ -1,0 +1,208 @@
+"""Serving: refinement requests admitted by HBM footprint and refined with
+continuous batching.
+
+Every request is one graph with its k, eps and number of rounds; it starts
+from a seeded random balanced partition and runs its own tau schedule. The
+server keeps the admitted requests' state (partition, gain table, block
+weights) on the device. Requests with the same (k, eps) share a batch (the
+disjoint union of their graphs, refined by the same launches); at every step
+each batch runs one round of all its requests, finished requests leave, and
+requests that have arrived are admitted as long as their footprint fits the
+budget. When a batch's membership changes it is rebuilt from the surviving
+requests' partitions, and that step recomputes the tables (a table is a
+function of the partition, so the result is the same as keeping it).
+
+Because no kernel lets two graphs of a batch interact, each request's result
+is exactly what it gets when refined alone.
+
+The refinement arithmetic runs in libupr (upr_batch_*); this module only
+schedules, moves partitions between batches and measures latency.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+
+import numpy as np
+
+from . import graphgen as gg
+from . import upr
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    graph: gg.Graph
+    k: int
+    eps: tuple = (3, 100)
+    rounds: int = 10
+    arrival: float = 0.0      # seconds after the start of the stream
+    part_seed: int = 0
+
+    def footprint(self) -> int:
+        """HBM bytes held while admitted: the graph (as uploaded and in the
+        batch union), the n x k gain table, block weights and per-node
+        workspace of the round."""
+        g = self.graph
+        csr = 8 * (g.n + 1) + 4 * g.nnz * (2 if g.adjwgt is not None else 1)
+        csr += 4 * g.n if g.vwgt is not None else 0
+        return 2 * csr + 4 * g.n * self.k + 8 * self.k + 96 * g.n
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    part: np.ndarray          # final partition (local block ids)
+    stats: list               # per-round statistics dicts
+    arrival: float
+    admitted: float
+    done: float
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class _Job:
+    def __init__(self, req: Request, dg, admitted: float):
+        self.req = req
+        self.dg = dg
+        self.round = 0
+        self.part = gg.random_partition(req.graph.n, req.k, req.part_seed)  # local ids, host
+        self.stats = []
+        self.admitted = admitted
+
+
+class _Group:
+    """The batch of the admitted requests with one (k, eps)."""
+
+    def __init__(self, ctx, k, eps):
+        self.ctx, self.k, self.eps = ctx, k, eps
+        self.jobs: list[_Job] = []
+        self.members: list[_Job] = []
+        self.batch = None
+        self.dirty = True
+        self.fresh = True
+
+    def rebuild(self):
+        """New union of the current jobs, carrying their partitions."""
+        import torch
+        old = self.batch
+        if old is not None:
+            torch.cuda.synchronize()
+            parts = old.local_partitions()
+            for j, p in zip(self.members, parts):
+                j.part = p
+            old.close()
+        self.batch = None
+        self.members = list(self.jobs)
+        if self.members:
+            self.batch = upr.Batch(self.ctx, [j.dg for j in self.members], self.k, self.eps)
+            self.batch.set_partitions([j.part for j in self.members])
+        self.dirty = False
+
+    def step(self):
+        """One round of every member; returns the members that finished."""
+        b = self.batch
+        rebuild = 1 if self.fresh else 0
+        taus = [gg.tau_schedule(j.round + 1, j.req.rounds) for j in self.members]
+        b.round(upr.params(self.k, self.eps, tau=(1, 1), rebuild_table=rebuild), taus=taus)
+        self.fresh = False
+        st = b.stats.cpu().numpy().reshape(b.ng, upr.STATS_LEN)  # synchronises
+        finished = []
+        for i, j in enumerate(self.members):
+            j.round += 1
+            j.stats.append(upr.stats_dict(st[i]))
+            if j.round >= j.req.rounds:
+                finished.append((i, j))
+        return finished
+
+
+class Server:
+    """Admission by footprint, continuous batching, latency bookkeeping."""
+
+    def __init__(self, ctx: upr.Context, budget_bytes: int):
+        self.ctx = ctx
+        self.budget = budget_bytes
+
+    def run(self, requests, clock=time.perf_counter, on_done=None):
+        import torch
+        pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        groups: dict = {}
+        used = 0
+        results = []
+        t0 = clock()
+        pi = 0
+        active = 0
+        while pi < len(pending) or active:
+            now = clock() - t0
+            # admission: arrived requests in arrival order while they fit
+            while pi < len(pending) and pending[pi].arrival <= now:
+                req = pending[pi]
+                need = req.footprint()
+                if active and used + need > self.budget:
+                    break  # wait for memory to free up (arrival order is kept)
+                dg = upr.DeviceGraph(req.graph, torch.device("cuda", self.ctx.device))
+                key = (req.k, tuple(req.eps))
+                grp = groups.get(key)
+                if grp is None:
+                    grp = groups[key] = _Group(self.ctx, req.k, req.eps)
+                grp.jobs.append(_Job(req, dg, clock() - t0))
+                grp.dirty = True
+                used += need
+                active += 1
+                pi += 1
+                now = clock() - t0
+            if not active:
+                # idle until the next arrival
+                wait = pending[pi].arrival - (clock() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 0.01))
+                continue
+            for grp in groups.values():
+                if grp.dirty:
+                    grp.rebuild()
+                    grp.fresh = True
+                if not grp.members:
+                    continue
+                finished = grp.step()
+                if finished:
+                    parts = grp.batch.local_partitions()
+                    done = clock() - t0
+                    for i, j in finished:
+                        res = Result(j.req.rid, parts[i], j.stats, j.req.arrival, j.admitted, done)
+                        results.append(res)
+                        if on_done:
+                            on_done(res)
+                        grp.jobs.remove(j)
+                        used -= j.req.footprint()
+                        active -= 1
+                    grp.dirty = True
+        for grp in groups.values():
+            if grp.batch is not None:
+                grp.batch.close()
+        return sorted(results, key=lambda r: r.rid)
+
+
+def refine_alone(ctx, req: Request):
+    """The same request refined by itself (plain per-graph calls)."""
+    r = upr.Refiner(req.graph, req.k, ctx=ctx)
+    r.set_partition(gg.random_partition(req.graph.n, req.k, req.part_seed))
+    stats = []
+    for i in range(1, req.rounds + 1):
+        r.round(upr.params(req.k, req.eps, tau=gg.tau_schedule(i, req.rounds)))
+        stats.append(upr.stats_dict(r.stats))
+    return r.part.cpu().numpy(), stats
+
+
+def poisson_arrivals(count, rate, seed):
+    """Arrival times of a Poisson process with `rate` per second."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))
+
+
+def percentile(xs, q):
+    xs = np.sort(np.asarray(xs, dtype=np.float64))
+    if xs.size == 0:
+        return float("nan")
+    return float(np.percentile(xs, q))

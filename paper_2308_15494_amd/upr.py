@@ -77,6 +77,16 @@ _SIGS = [
                                  C.c_void_p, C.c_void_p]),
     ("upr_lmax", C.c_int64, [C.c_int64, C.c_int32, C.c_int32, C.c_int32]),
     ("upr_penalty_table", C.c_int, [C.c_int32, C.c_int32, C.c_void_p]),
+    ("upr_batch_create", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                   C.c_int32, C.POINTER(C.c_void_p), C.c_void_p]),
+    ("upr_batch_destroy", None, [C.c_void_p]),
+    ("upr_batch_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                 C.c_void_p, C.c_void_p]),
+    ("upr_batch_refine_round", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(Params), C.c_void_p,
+                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_void_p, C.c_void_p]),
+    ("upr_batch_rebalance", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(Params), C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("upr_timing_enable", C.c_int, [C.c_void_p, C.c_int]),
     ("upr_timing_read", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
 ]
@@ -293,3 +303,81 @@ class Refiner:
     def rebalance(self, p: Params):
         rebalance(self.ctx, self.plan, p, self.part, self.conn, self.W, self.stats)
         return self.stats
+
+
+class Batch:
+    """upr_batch: graphs with a common k and eps refined by the same launches.
+
+    The library copies the graphs into one union (graph g's nodes at
+    off[g]..off[g+1]); part holds global block ids g*k + j, W is [ng * k],
+    stats [ng, STATS_LEN]. The input DeviceGraphs may be dropped after
+    construction."""
+
+    def __init__(self, ctx: Context, graphs, k, eps=(3, 100), stream=None):
+        import torch
+        self.ctx, self.k, self.eps = ctx, k, eps
+        self.ng = len(graphs)
+        dgs = [g if isinstance(g, DeviceGraph) else DeviceGraph(g) for g in graphs]
+        arr = (_Graph * self.ng)(*[d.c for d in dgs])
+        self.handle = C.c_void_p()
+        ctx.check(lib().upr_batch_create(ctx.handle, C.cast(arr, C.c_void_p), self.ng, k, eps[0],
+                                         eps[1], C.byref(self.handle), _stream(stream)))
+        torch.cuda.synchronize()
+        n, nnz = C.c_int64(), C.c_int64()
+        self.off = np.zeros(self.ng + 1, np.int64)
+        self.lmax = np.zeros(self.ng, np.int64)
+        ctx.check(lib().upr_batch_info(self.handle, C.byref(n), C.byref(nnz),
+                                       self.off.ctypes.data, self.lmax.ctypes.data))
+        self.n, self.nnz = n.value, nnz.value
+        dev = torch.device("cuda", ctx.device)
+        self.dev = dev
+        self.conn = torch.zeros(max(self.n * k, 1), dtype=torch.int32, device=dev)
+        self.W = torch.zeros(self.ng * k, dtype=torch.int64, device=dev)
+        self.stats = torch.zeros(self.ng * STATS_LEN, dtype=torch.int64, device=dev)
+        self.part = None
+
+    def set_partitions(self, parts):
+        """parts: one local partition (values in [0, k)) per graph."""
+        import torch
+        glob = np.zeros(max(self.n, 1), np.int32)
+        for g, p in enumerate(parts):
+            glob[self.off[g]:self.off[g + 1]] = np.asarray(p, np.int64) + g * self.k
+        self.part = torch.from_numpy(glob[: self.n] if self.n else glob[:0]).to(self.dev)
+
+    def local_partitions(self):
+        p = self.part.cpu().numpy().astype(np.int64)
+        return [(p[self.off[g]:self.off[g + 1]] - g * self.k).astype(np.int32)
+                for g in range(self.ng)]
+
+    def graph_stats(self) -> list:
+        st = self.stats.cpu().numpy().reshape(self.ng, STATS_LEN)
+        return [stats_dict(st[g]) for g in range(self.ng)]
+
+    def round(self, p: Params, taus=None, stream=None):
+        """taus: one (num, den) per graph, or None for p's tau everywhere."""
+        tn = td = None
+        if taus is not None:
+            tn = np.ascontiguousarray([t[0] for t in taus], np.int32)
+            td = np.ascontiguousarray([t[1] for t in taus], np.int32)
+        self.ctx.check(lib().upr_batch_refine_round(
+            self.ctx.handle, self.handle, C.byref(p),
+            None if tn is None else tn.ctypes.data, None if td is None else td.ctypes.data,
+            _ptr(self.part), _ptr(self.conn), _ptr(self.W), _ptr(self.stats), _stream(stream)))
+        return self.stats
+
+    def rebalance(self, p: Params, stream=None):
+        self.ctx.check(lib().upr_batch_rebalance(self.ctx.handle, self.handle, C.byref(p),
+                                                 _ptr(self.part), _ptr(self.conn), _ptr(self.W),
+                                                 _ptr(self.stats), _stream(stream)))
+        return self.stats
+
+    def close(self):
+        if self.handle:
+            lib().upr_batch_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
