@@ -152,6 +152,104 @@ def cpu_baseline(g, k, eps, rounds, part0, seconds):
             "sample": f"first {r} of {rounds} rounds of the same workload, one thread"}, stats
 
 
+def batched_vs_plain(ctx, spec, eps=(3, 100), rounds=10):
+    """The many-graphs workload refined twice: plain (one graph after the
+    other, upr_refine_round per graph and round) and batched (one batch per k,
+    upr_batch_refine_round per round). Plans and batches are built and warmed
+    up before the timed regions; both start from the same partitions and
+    must end with identical partitions and statistics."""
+    import torch
+    from paper_2308_15494_amd import graphgen as gg
+    from paper_2308_15494_amd import upr
+    refs = []
+    for g, k, seed in spec:
+        r = upr.Refiner(g, k, ctx=ctx)
+        refs.append(r)
+    groups = {}
+    for i, (g, k, seed) in enumerate(spec):
+        groups.setdefault(k, []).append(i)
+    batches = {k: upr.Batch(ctx, [refs[i].dg for i in idx], k, eps) for k, idx in groups.items()}
+
+    def reset():
+        for r, (g, k, seed) in zip(refs, spec):
+            r.set_partition(gg.random_partition(g.n, k, seed))
+        for k, idx in groups.items():
+            batches[k].set_partitions([gg.random_partition(spec[i][0].n, k, spec[i][2]) for i in idx])
+        torch.cuda.synchronize()
+
+    def run_plain():
+        for r, (g, k, seed) in zip(refs, spec):
+            for i in range(1, rounds + 1):
+                r.round(upr.params(k, eps, tau=gg.tau_schedule(i, rounds)))
+
+    def run_batched():
+        for k, b in batches.items():
+            for i in range(1, rounds + 1):
+                b.round(upr.params(k, eps, tau=gg.tau_schedule(i, rounds)))
+
+    out = {}
+    for name, fn in (("plain", run_plain), ("batched", run_batched)):
+        reset()
+        fn()  # warm-up pass (workspace sizes, code paths)
+        reset()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        out[name] = time.perf_counter() - t0
+    # identical results, graph by graph
+    same = True
+    for k, idx in groups.items():
+        b = batches[k]
+        parts = b.local_partitions()
+        st = b.stats.cpu().numpy().reshape(b.ng, upr.STATS_LEN)
+        for j, i in enumerate(idx):
+            same &= bool(np.array_equal(parts[j], refs[i].part.cpu().numpy()))
+            same &= bool(np.array_equal(st[j], refs[i].stats.cpu().numpy()))
+    for b in batches.values():
+        b.close()
+    ng = len(spec)
+    return {"graphs": ng, "rounds": rounds, "batches": len(batches),
+            "nodes": int(sum(g.n for g, _, _ in spec)), "edges": int(sum(g.m for g, _, _ in spec)),
+            "plain_graphs_per_s": ng / out["plain"], "batched_graphs_per_s": ng / out["batched"],
+            "plain_s": out["plain"], "batched_s": out["batched"],
+            "speedup": out["plain"] / out["batched"], "identical_results": same}
+
+
+def serving(ctx, spec, eps=(3, 100), rounds=10, load=0.7, budget_gb=200.0, check=4, seed=7):
+    """Poisson stream of refinement requests through the continuous-batching
+    server. The capacity is measured first with every request arriving at
+    time 0; the stream then arrives at `load` times that rate. Reports
+    latency percentiles (completion minus arrival) and throughput; a few
+    requests are also refined alone and must give the same result."""
+    from paper_2308_15494_amd import serve
+    reqs0 = [serve.Request(j, g, k, eps, rounds=rounds, arrival=0.0, part_seed=s)
+             for j, (g, k, s) in enumerate(spec)]
+    budget = int(budget_gb * (1 << 30))
+    srv = serve.Server(ctx, budget)
+    srv.run(reqs0[: min(8, len(reqs0))])  # warm-up
+    t0 = time.perf_counter()
+    srv.run(reqs0)
+    cap = len(reqs0) / (time.perf_counter() - t0)
+    rate = load * cap
+    arr = serve.poisson_arrivals(len(spec), rate, seed)
+    reqs = [serve.Request(j, g, k, eps, rounds=rounds, arrival=float(arr[j]), part_seed=s)
+            for j, (g, k, s) in enumerate(spec)]
+    t0 = time.perf_counter()
+    res = srv.run(reqs)
+    span = time.perf_counter() - t0
+    lat = [r.latency for r in res]
+    same = True
+    for r in res[:check]:
+        part, stats = serve.refine_alone(ctx, reqs[r.rid])
+        same &= bool(np.array_equal(part, r.part)) and stats == r.stats
+    return {"requests": len(spec), "rounds": rounds, "capacity_graphs_per_s": cap,
+            "arrival_rate_per_s": rate, "graphs_per_s": len(res) / span,
+            "p50_latency_ms": 1e3 * float(np.percentile(lat, 50)),
+            "p99_latency_ms": 1e3 * float(np.percentile(lat, 99)),
+            "mean_latency_ms": 1e3 * float(np.mean(lat)),
+            "budget_gb": budget_gb, "same_as_alone_checked": check, "same_as_alone": same}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,6 +263,11 @@ def main():
                     help="counter-collection workload: gain-table builds + a calibration copy")
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the gain-table traffic record from two rocprofv3 --pmc CSVs")
+    ap.add_argument("--batch-graphs", type=int, default=512,
+                    help="graphs of the batched-vs-plain leg (0 skips it)")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests of the serving leg (0 skips it)")
+    ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1))
     args = ap.parse_args()
     if args.ingest_pmc:
         ingest_pmc(*args.ingest_pmc)
@@ -179,8 +282,19 @@ def main():
         pmc_run(args)
         return
 
-    import torch
+    # the many-graphs inputs are generated first, in forked workers, before
+    # anything touches the GPU
     from paper_2308_15494_amd import graphgen as gg
+    t0 = time.perf_counter()
+    bspec = gg.generate_parallel(gg.batch_set, args.batch_graphs, args.gen_workers, seed0=1000) \
+        if args.batch_graphs > 0 else []
+    sspec = gg.generate_parallel(gg.serve_set, args.serve_requests, args.gen_workers, seed0=100_000) \
+        if args.serve_requests > 0 else []
+    if bspec or sspec:
+        log(f"generated {len(bspec)} batch graphs and {len(sspec)} requests in "
+            f"{time.perf_counter() - t0:.1f}s")
+
+    import torch
     from paper_2308_15494_amd import upr
 
     t0 = time.perf_counter()
@@ -240,7 +354,7 @@ def main():
                 "avg_launch_us": avg_tile_s * 1e6}
 
     out = {
-        "metric": "edges/s per refine round (gain+move+rebalance)",
+        "metric": "edges/s per refine round (gain+move+rebalance), batched vs plain; p99 latency",
         "value": value,
         "unit": "edges/s",
         "n_gpus": 1,
@@ -260,6 +374,13 @@ def main():
         "phases_ms_per_round": {k_: round(v[0] / max(args.steps, 1), 4) for k_, v in phases.items()},
         "final_stats": final,
     }
+
+    if bspec:
+        out["batched"] = batched_vs_plain(ctx, bspec)
+        log(f"batched: {out['batched']}")
+    if sspec:
+        out["serving"] = serving(ctx, sspec)
+        log(f"serving: {out['serving']}")
 
     if not args.no_cpu:
         base, ostats = cpu_baseline(g, k, eps, rounds, part0, args.cpu_seconds)

@@ -294,6 +294,69 @@ def workload(name: str) -> tuple:
     raise KeyError(name)
 
 
+def batch_set(count: int = 512, seed0: int = 1000, n_min: int = 1000, n_max: int = 200_000):
+    """The many-graphs workload: `count` graphs (seeds seed0 + i), sizes
+    log-uniform in [n_min, n_max]; even i Chung-Lu (exponent uniform in
+    [2.1, 2.8], mean degree uniform in [8, 24]), odd i 2D random geometric
+    (mean degree 8); k drawn from {2, 4, 8, 16, 32, 64}; eps 3/100; 10
+    rounds each. Returns a list of (graph, k, part0_seed)."""
+    out = []
+    ks = [2, 4, 8, 16, 32, 64]
+    for i in range(count):
+        rng = np.random.default_rng(seed0 + i)
+        n = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+        k = int(ks[rng.integers(0, len(ks))])
+        if i % 2 == 0:
+            beta = float(rng.uniform(2.1, 2.8))
+            d = float(rng.uniform(8.0, 24.0))
+            g = chung_lu(n, d, beta, seed=seed0 + i)
+        else:
+            g = rgg2d(n, seed=seed0 + i)
+        out.append((g, k, seed0 + i))
+    return out
+
+
+def serve_set(count: int = 200, seed0: int = 100_000, m_min: float = 1e4, m_max: float = 1e6):
+    """The serving workload: `count` requests (seeds seed0 + j), edge counts
+    log-uniform in [m_min, m_max]; Chung-Lu with n = m/8 (mean degree 16,
+    exponent uniform in [2.1, 2.8]) or R-MAT with scale ceil(log2(m/16)) and
+    16 draws per node, with equal probability; k drawn from {8, 32, 128};
+    eps 3/100; 10 rounds. Returns a list of (graph, k, part0_seed)."""
+    out = []
+    for j in range(count):
+        rng = np.random.default_rng(seed0 + j)
+        m = math.exp(rng.uniform(math.log(m_min), math.log(m_max)))
+        k = int([8, 32, 128][rng.integers(0, 3)])
+        if rng.random() < 0.5:
+            n = max(int(m / 8), 64)
+            g = chung_lu(n, 16.0, float(rng.uniform(2.1, 2.8)), seed=seed0 + j)
+        else:
+            g = rmat(max(int(math.ceil(math.log2(max(m / 16, 16)))), 4), 16, seed=seed0 + j)
+        out.append((g, k, seed0 + j))
+    return out
+
+
+def generate_parallel(fn, count: int, workers: int, **kw):
+    """fn(count, ...) split over worker processes by index ranges (forked;
+    call before any GPU use)."""
+    import multiprocessing as mp
+    if workers <= 1 or count < 2 * workers:
+        return fn(count, **kw)
+    seed_key = "seed0"
+    seed0 = kw.pop(seed_key)
+    chunks = [(i, min(i + (count + workers - 1) // workers, count))
+              for i in range(0, count, (count + workers - 1) // workers)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(len(chunks)) as pool:
+        parts = pool.starmap(_gen_range, [(fn.__name__, a, b, seed0, kw) for a, b in chunks])
+    return [x for part in parts for x in part]
+
+
+def _gen_range(name, a, b, seed0, kw):
+    fn = globals()[name]
+    return fn(b - a, seed0=seed0 + a, **kw)
+
+
 def tau_schedule(r: int, rounds: int) -> tuple:
     """Penalty factor of round r (1-based) as a rational (num, den).
 
