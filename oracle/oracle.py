@@ -45,7 +45,8 @@ class _Params(C.Structure):
     _fields_ = [("k", C.c_int32), ("eps_num", C.c_int32), ("eps_den", C.c_int32),
                 ("t_num", C.c_int32), ("t_den", C.c_int32), ("tau_num", C.c_int32),
                 ("tau_den", C.c_int32), ("mode", C.c_int32), ("rebuild_table", C.c_int32),
-                ("max_rebalance_iters", C.c_int32), ("seq_penalty", C.c_int32)]
+                ("max_rebalance_iters", C.c_int32), ("seq_penalty", C.c_int32),
+                ("alpha_num", C.c_int32), ("alpha_den", C.c_int32), ("variant", C.c_int32)]
 
 
 class _Debug(C.Structure):
@@ -115,10 +116,14 @@ class Graph:
                         _ptr(self.vwgt))
 
 
+OPTIMISTIC = 1        # variant bit: optimistic conflict filter
+PLAIN_PRIORITY = 2    # variant bit: rebalancing priority by the plain gain
+
+
 def params(k, eps=(3, 100), t=(7, 10), tau=(1, 1), mode=0, rebuild_table=1,
-           max_rebalance_iters=0, seq_penalty=1) -> _Params:
+           max_rebalance_iters=0, seq_penalty=1, alpha=(1, 1), variant=0) -> _Params:
     return _Params(k, eps[0], eps[1], t[0], t[1], tau[0], tau[1], mode, rebuild_table,
-                   max_rebalance_iters, seq_penalty)
+                   max_rebalance_iters, seq_penalty, alpha[0], alpha[1], variant)
 
 
 def lmax(total, k, eps=(3, 100)):

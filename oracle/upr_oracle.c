@@ -67,11 +67,20 @@ typedef struct {
     int32_t eps_num, eps_den;
     int32_t t_num, t_den;
     int32_t tau_num, tau_den;
-    int32_t mode;            /* 0 penalised, 1 constrained, 2 penalty-free */
+    int32_t mode;            /* 0 penalised, 1 constrained, 2 penalty-free,
+                                3 limited imbalance: no penalty, targets capped at
+                                floor(alpha * L_max) (Section 8.2) */
     int32_t rebuild_table;   /* 1: conn and W are recomputed from part */
     int32_t max_rebalance_iters; /* 0: default */
     int32_t seq_penalty;     /* 1: S3 re-prices moves with earlier candidates' inflow */
+    int32_t alpha_num, alpha_den; /* mode 3: alpha = alpha_num / alpha_den >= 1 */
+    int32_t variant;         /* bit 0: optimistic filter (an earlier candidate neighbour
+                                counts in its target block); bit 1: rebalancing priority
+                                by the plain gain, without the node weight (Section 8.2) */
 } orc_params;
+
+#define ORC_VAR_OPTIMISTIC 1
+#define ORC_VAR_PLAIN_PRIORITY 2
 
 /* Statistics, same order as the int64 slots the tests read. */
 enum {
@@ -288,12 +297,14 @@ static int rebalance_iterate(const orc_graph *g, const orc_params *p, int64_t lm
             if (best < 0) continue;
             tgt[v] = best;
             int64_t gain = (int64_t)row[best] - row[a];
+            /* the plain-gain variant ranks by the gain alone: as if c(v) = 1 */
+            const int64_t cp = (p->variant & ORC_VAR_PLAIN_PRIORITY) ? 1 : cv;
             if (gain > 0)
-                beta[v] = ORC_SLOTS - 1 - orc_slot(gain * cv, 1);
+                beta[v] = ORC_SLOTS - 1 - orc_slot(gain * cp, 1);
             else if (gain == 0)
                 beta[v] = ORC_SLOTS;
             else
-                beta[v] = ORC_SLOTS + 1 + orc_slot(-gain, cv);
+                beta[v] = ORC_SLOTS + 1 + orc_slot(-gain, cp);
         }
 
         /* steps 2-3: every movable node is offered; per target, the maximal
@@ -371,17 +382,18 @@ void orc_penalty_buckets(const orc_graph *g, int32_t k, const int32_t *part, con
 }
 
 /* Penalty of Section 5.3 for a node of weight cv whose move leaves its target
- * with excess X = c(V_j + v) - L_max, given the target's bucket weights:
- * 0 if X <= 0; otherwise constrained (mode 1): forbidden; penalty-free
- * (mode 2): 0; penalised (mode 0): tau * (3/2)^l * c(v) in Q16 (saturated at
- * 2^62) for the least slot l whose cumulative bucket weight covers X,
- * forbidden if none. Returns 0 when the move is forbidden. */
+ * with excess X = c(V_j + v) - bound (bound = L_max, or the cap of mode 3),
+ * given the target's bucket weights: 0 if X <= 0; otherwise constrained
+ * (mode 1) and limited imbalance (mode 3): forbidden; penalty-free (mode 2):
+ * 0; penalised (mode 0): tau * (3/2)^l * c(v) in Q16 (saturated at 2^62) for
+ * the least slot l whose cumulative bucket weight covers X, forbidden if none.
+ * Returns 0 when the move is forbidden. */
 static int move_penalty(const int64_t *bucket_row, const int64_t *penq, int mode, int64_t X,
                         int64_t cv, int64_t *P)
 {
     *P = 0;
     if (X <= 0 || mode == 2) return 1;
-    if (mode == 1) return 0;
+    if (mode == 1 || mode == 3) return 0;
     int64_t acc = 0;
     for (int i = 0; i < ORC_SLOTS; ++i) {
         acc += bucket_row[i];
@@ -393,6 +405,16 @@ static int move_penalty(const int64_t *bucket_row, const int64_t *penq, int mode
         }
     }
     return 0;
+}
+
+/* The weight a move may bring its target to before it is penalised or
+ * forbidden: L_max, or in the limited-imbalance variant of Section 8.2 the
+ * round's cap floor(alpha * L_max). */
+static int64_t move_bound(const orc_params *p, int64_t lmax)
+{
+    if (p->mode != 3) return lmax;
+    return (int64_t)(((unsigned __int128)(uint64_t)lmax * (uint32_t)p->alpha_num) /
+                     (uint32_t)p->alpha_den);
 }
 
 /* Candidate order of S3: score descending, then id ascending. */
@@ -411,7 +433,9 @@ static int check_params(const orc_graph *g, const orc_params *p, const int32_t *
     if (p->k < 2 || p->eps_num <= 0 || p->eps_den <= 0) return -1;
     if (p->t_num < 0 || p->t_den <= 0 || p->t_num > p->t_den) return -1;
     if (p->tau_num < 0 || p->tau_den <= 0 || p->tau_num > p->tau_den) return -1;
-    if (p->mode < 0 || p->mode > 2) return -1;
+    if (p->mode < 0 || p->mode > 3) return -1;
+    if (p->mode == 3 && (p->alpha_den <= 0 || p->alpha_num < p->alpha_den)) return -1;
+    if (p->variant & ~(ORC_VAR_OPTIMISTIC | ORC_VAR_PLAIN_PRIORITY)) return -1;
     for (int64_t v = 0; v < g->n; ++v)
         if (part[v] < 0 || part[v] >= p->k) return -1;
     return 0;
@@ -450,6 +474,7 @@ int orc_refine_round(const orc_graph *g, const orc_params *p, int32_t *part, int
     orc_penalty_buckets(g, k, part, conn, p->t_num, p->t_den, bucket, avail);
 
     /* S2: best penalised move per node, against the round-start W. */
+    const int64_t bound = move_bound(p, lmax);
     int32_t *target = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     int64_t *score = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     int64_t *pen = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
@@ -463,7 +488,7 @@ int orc_refine_round(const orc_graph *g, const orc_params *p, int32_t *part, int
         for (int32_t j = 0; j < k; ++j) {
             if (j == a || row[j] <= 0) continue;      /* adjacent blocks only */
             int64_t delta = (int64_t)row[j] - row[a];  /* gain of the move v -> j */
-            int64_t excess = W[j] + cv - lmax;         /* c(V_j + v) - L_max */
+            int64_t excess = W[j] + cv - bound;        /* c(V_j + v) - L_max (or the cap) */
             int64_t P;
             if (!move_penalty(bucket + (int64_t)j * ORC_SLOTS, penq, p->mode, excess, cv, &P))
                 continue;                              /* forbidden */
@@ -511,7 +536,9 @@ int orc_refine_round(const orc_graph *g, const orc_params *p, int32_t *part, int
             if (earlier) {
                 int32_t tu = target[u];
                 int ft = tu == b ? 1 : (tu == a ? -1 : 0);
-                if (ft < fu) fu = ft;
+                /* pessimistic: the worse of its two blocks; optimistic
+                 * variant: the neighbour is assumed to have moved */
+                if ((p->variant & ORC_VAR_OPTIMISTIC) || ft < fu) fu = ft;
             }
             gp += edge_w(g, e) * fu;
         }
@@ -521,7 +548,7 @@ int orc_refine_round(const orc_graph *g, const orc_params *p, int32_t *part, int
         if (p->seq_penalty) {
             const int64_t cv = node_c(g, v);
             allowed = move_penalty(bucket + (int64_t)b * ORC_SLOTS, penq, p->mode,
-                                   W[b] + net[b] + cv - lmax, cv, &P);
+                                   W[b] + net[b] + cv - bound, cv, &P);
             pen_seq[v] = allowed ? P : -1;
             if (eligible) {
                 net[b] += cv;

@@ -357,6 +357,15 @@ def _gen_range(name, a, b, seed0, kw):
     return fn(b - a, seed0=seed0 + a, **kw)
 
 
+def alpha_schedule(r: int, rounds: int) -> tuple:
+    """Block-weight cap factor of round r (1-based) of the limited-imbalance
+    variant, as a rational (num, den): linear from alpha_1 = 2 down to
+    alpha_final = 1.1 (Section 8.2); a single round uses 1.1."""
+    if rounds <= 1:
+        return (11, 10)
+    return (20 * (rounds - 1) - 9 * (r - 1), 10 * (rounds - 1))
+
+
 def tau_schedule(r: int, rounds: int) -> tuple:
     """Penalty factor of round r (1-based) as a rational (num, den).
 

@@ -106,12 +106,20 @@ def penalty_q16(g, k, part, t, tau, v, j, lmax):
     return None
 
 
-def best_moves(g, k, part, t, tau, eps, mode=0):
+def move_cap(L, mode, alpha):
+    """Largest weight a move may bring its target to without penalty:
+    L_max, or floor(alpha * L_max) in the limited-imbalance variant."""
+    return int(Fraction(*alpha) * L // 1) if mode == 3 else L
+
+
+def best_moves(g, k, part, t, tau, eps, mode=0, alpha=(1, 1)):
     """S2 by brute force: for each v, argmax over blocks j != Pi(v) of
     gain * 2^16 - penalty (ties to the smaller j); candidate iff > 0.
-    Returns dict v -> (target, score, pen)."""
+    Mode 3 (limited imbalance): no penalty, and only targets that stay within
+    floor(alpha * L_max). Returns dict v -> (target, score, pen)."""
     total = sum(node_w(g, v) for v in range(g.n))
     L = lmax_exact(total, k, eps)
+    cap = move_cap(L, mode, alpha)
     out = {}
     for v in range(g.n):
         best = None
@@ -120,10 +128,10 @@ def best_moves(g, k, part, t, tau, eps, mode=0):
                 continue
             if omega(g, v, j, part) == 0:
                 continue
-            fits = block_weight(g, part, j) + node_w(g, v) <= L
-            if mode == 1 and not fits:
+            fits = block_weight(g, part, j) + node_w(g, v) <= cap
+            if mode in (1, 3) and not fits:
                 continue
-            P = 0 if mode == 2 else penalty_q16(g, k, part, t, tau, v, j, L)
+            P = 0 if mode in (2, 3) else penalty_q16(g, k, part, t, tau, v, j, L)
             if P is None:
                 continue
             s = move_gain(g, part, v, j) * 65536 - P
@@ -192,13 +200,14 @@ def rebalance_bucket(gain, c, slots=54):
     return slots + 1 + slot_exact(-gain, c, slots)
 
 
-def rebalance_one_iteration(g, k, part, L):
+def rebalance_one_iteration(g, k, part, L, plain=False):
     """One synchronous rebalancing sub-iteration, from the rules of Section 7.1
     on Python lists: nodes of overloaded blocks take their best-gain move into
     a block that stays balanced (or, unconnected to any, the lightest such
     block, smaller id on ties); each target takes the offers aimed at it in
     (priority bucket, id) order while they fit; each overloaded block keeps,
-    in the same order, its accepted nodes until its excess is covered.
+    in the same order, its accepted nodes until its excess is covered. With
+    plain, the priority is the gain itself (node weights left out).
     Returns the new partition (a list)."""
     part = list(part)
     W = [block_weight(g, part, j) for j in range(k)]
@@ -218,7 +227,7 @@ def rebalance_one_iteration(g, k, part, L):
         else:
             tgt = min(valid, key=lambda j: (W[j], j))
         gain = move_gain(g, part, v, tgt)
-        info[v] = (tgt, rebalance_bucket(gain, cv))
+        info[v] = (tgt, rebalance_bucket(gain, 1 if plain else cv))
     accepted = []
     for j in range(k):
         nodes = sorted((v for v in info if info[v][0] == j), key=lambda v: (info[v][1], v))
@@ -260,10 +269,11 @@ def pessimistic_gain(g, part, v, target, earlier):
 
 def penalty_for_excess(g, k, part, t, tau, j, X, cv, mode):
     """Section 5.3 penalty (Q16) of a node of weight cv whose move leaves
-    block j with excess X over L_max; None if forbidden."""
+    block j with excess X over L_max (over the cap in mode 3); None if
+    forbidden."""
     if X <= 0 or mode == 2:
         return 0
-    if mode == 1:
+    if mode in (1, 3):
         return None
     B = available_sets(g, k, part, t)
     acc = 0
@@ -275,7 +285,16 @@ def penalty_for_excess(g, k, part, t, tau, j, X, cv, mode):
     return None
 
 
-def filter_decisions(g, k, part, t, tau, eps, mode=0, seq=True):
+def optimistic_gain(g, part, v, target, earlier):
+    """True gain of moving v to `target` once every earlier candidate
+    neighbour (dict u -> target_u) has made its move."""
+    cur = list(part)
+    for u, tu in earlier.items():
+        cur[u] = tu
+    return move_gain(g, cur, v, target)
+
+
+def filter_decisions(g, k, part, t, tau, eps, mode=0, seq=True, alpha=(1, 1), optimistic=False):
     """S3 by brute force. Candidates from best_moves, in (score desc, id asc)
     order; pessimistic gain as the worst true gain over the moves earlier
     candidate neighbours may make; with seq, each block's weight is tracked
@@ -285,7 +304,8 @@ def filter_decisions(g, k, part, t, tau, eps, mode=0, seq=True):
     Returns {v: (accepted, pen_seq)} with pen_seq None when forbidden."""
     total = sum(node_w(g, v) for v in range(g.n))
     L = lmax_exact(total, k, eps)
-    moves = best_moves(g, k, part, t, tau, eps, mode)
+    cap = move_cap(L, mode, alpha)
+    moves = best_moves(g, k, part, t, tau, eps, mode, alpha)
     order = sorted(moves, key=lambda v: (-moves[v][1], v))
     W = [block_weight(g, part, j) for j in range(k)]
     B = available_sets(g, k, part, t)
@@ -297,11 +317,14 @@ def filter_decisions(g, k, part, t, tau, eps, mode=0, seq=True):
         b, _, pen = moves[v]
         nb = set(int(u) for u in g.adjncy[g.xadj[v]:g.xadj[v + 1]])
         earlier = {u: moves[u][0] for u in nb if u in moves and pos[u] < pos[v]}
-        gp = pessimistic_gain(g, list(part), v, b, earlier)
+        if optimistic:
+            gp = optimistic_gain(g, list(part), v, b, earlier)
+        else:
+            gp = pessimistic_gain(g, list(part), v, b, earlier)
         cv = node_w(g, v)
         P = pen
         if seq:
-            P = penalty_for_excess(g, k, part, t, tau, b, W[b] + net[b] + cv - L, cv, mode)
+            P = penalty_for_excess(g, k, part, t, tau, b, W[b] + net[b] + cv - cap, cv, mode)
             if gp > 0:
                 net[b] += cv
                 if v not in avail:
