@@ -85,6 +85,10 @@ def lib():
         L.orc_refine_round.restype = C.c_int
         L.orc_refine_round.argtypes = [C.POINTER(_Graph), C.POINTER(_Params), C.c_void_p,
                                        C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(_Debug)]
+        L.orc_refine_round_active.restype = C.c_int
+        L.orc_refine_round_active.argtypes = [C.POINTER(_Graph), C.POINTER(_Params), C.c_void_p,
+                                              C.c_void_p, C.c_void_p, C.c_void_p,
+                                              C.POINTER(_Debug), C.c_void_p]
         L.orc_rebalance.restype = C.c_int
         L.orc_rebalance.argtypes = [C.POINTER(_Graph), C.POINTER(_Params), C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_void_p]
@@ -187,9 +191,10 @@ def penalty_buckets(g, k, part, conn, t=(7, 10)):
     return bucket.reshape(k, SLOTS), avail
 
 
-def refine_round(g, p: _Params, part, conn=None, W=None, debug=False):
+def refine_round(g, p: _Params, part, conn=None, W=None, debug=False, active=None):
     """Run one round in place on (part, conn, W). Returns (stats, dbg) where dbg
-    is a dict of per-node arrays (target, score, pen, accept) or None."""
+    is a dict of per-node arrays (target, score, pen, accept) or None. active:
+    optional uint8 mask of the nodes that may look for a move."""
     G = g if isinstance(g, Graph) else Graph(g)
     k = p.k
     _check(part, np.int32, G.n, "part")
@@ -209,9 +214,12 @@ def refine_round(g, p: _Params, part, conn=None, W=None, debug=False):
         dstruct = _Debug(dbg["target"].ctypes.data, dbg["score"].ctypes.data,
                          dbg["pen"].ctypes.data, dbg["accept"].ctypes.data,
                          dbg["pen_seq"].ctypes.data)
-    rc = lib().orc_refine_round(C.byref(G.c), C.byref(p), part.ctypes.data, conn.ctypes.data,
-                                W.ctypes.data, stats.ctypes.data,
-                                C.byref(dstruct) if dstruct is not None else None)
+    if active is not None:
+        _check(active, np.uint8, G.n, "active")
+    rc = lib().orc_refine_round_active(C.byref(G.c), C.byref(p), part.ctypes.data,
+                                       conn.ctypes.data, W.ctypes.data, stats.ctypes.data,
+                                       C.byref(dstruct) if dstruct is not None else None,
+                                       None if active is None else active.ctypes.data)
     if rc != 0:
         raise ValueError(f"oracle refine_round rejected its arguments (rc={rc})")
     return stats, dbg

@@ -455,8 +455,11 @@ static void prepare(const orc_graph *g, const orc_params *p, const int32_t *part
     stats[ST_CUT_BEFORE] = orc_cut_table(g, p->k, part, conn);
 }
 
-int orc_refine_round(const orc_graph *g, const orc_params *p, int32_t *part, int32_t *conn,
-                     int64_t *W, int64_t *stats, const orc_debug *dbg)
+/* One round. active (may be NULL: every node): only nodes with active[v] != 0
+ * look for a move in S2 (the active set of Section 6's label propagation). */
+int orc_refine_round_active(const orc_graph *g, const orc_params *p, int32_t *part,
+                            int32_t *conn, int64_t *W, int64_t *stats, const orc_debug *dbg,
+                            const uint8_t *active)
 {
     if (check_params(g, p, part)) return -1;
     const int32_t k = p->k;
@@ -485,7 +488,7 @@ int orc_refine_round(const orc_graph *g, const orc_params *p, int32_t *part, int
         const int32_t *row = conn + v * (int64_t)k;
         int32_t best = -1;
         int64_t best_s = 0, best_p = 0;
-        for (int32_t j = 0; j < k; ++j) {
+        for (int32_t j = 0; j < k && (!active || active[v]); ++j) {
             if (j == a || row[j] <= 0) continue;      /* adjacent blocks only */
             int64_t delta = (int64_t)row[j] - row[a];  /* gain of the move v -> j */
             int64_t excess = W[j] + cv - bound;        /* c(V_j + v) - L_max (or the cap) */
@@ -592,6 +595,12 @@ int orc_refine_round(const orc_graph *g, const orc_params *p, int32_t *part, int
 }
 
 /* A standalone rebalancing call: S0, S1 (if rebuilding), S5, S6. */
+int orc_refine_round(const orc_graph *g, const orc_params *p, int32_t *part, int32_t *conn,
+                     int64_t *W, int64_t *stats, const orc_debug *dbg)
+{
+    return orc_refine_round_active(g, p, part, conn, W, stats, dbg, NULL);
+}
+
 int orc_rebalance(const orc_graph *g, const orc_params *p, int32_t *part, int32_t *conn,
                   int64_t *W, int64_t *stats)
 {
