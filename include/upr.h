@@ -72,14 +72,27 @@ typedef struct {
     int32_t tau_num, tau_den;    /* penalty factor tau in [0, 1] of this round (Section 5.5) */
     int32_t mode;                /* 0 penalised unconstrained moves (Section 5.3),
                                     1 constrained (moves that would overload are skipped),
-                                    2 penalty-free unconstrained (Section 8.2 variant) */
+                                    2 penalty-free unconstrained (Section 8.2 variant),
+                                    3 limited imbalance (Section 8.2 variant): no penalty,
+                                      moves may fill a target up to floor(alpha * L_max) */
     int32_t rebuild_table;       /* 1: conn and block_w are recomputed from part first;
                                     0: conn and block_w are trusted resident state */
     int32_t max_rebalance_iters; /* 0: k+1 for unit node weights, 4k otherwise */
     int32_t seq_penalty;         /* 1: the conflict filter prices each move against its target's
                                     weight as changed by the eligible earlier candidates
                                     (Section 5.3); 0: against the round-start weight only */
+    int32_t alpha_num, alpha_den; /* mode 3: alpha = alpha_num / alpha_den >= 1 (the paper
+                                    shrinks it from 2 to 1.1 over the rounds); else ignored */
+    int32_t variant;             /* bit flags, 0 for the main configuration:
+                                    UPR_VAR_OPTIMISTIC: the conflict filter counts an earlier
+                                      candidate neighbour in its target block (moved) instead
+                                      of the worse of its two blocks;
+                                    UPR_VAR_PLAIN_PRIORITY: rebalancing ranks nodes by the
+                                      gain alone, without the node weight (Section 8.2) */
 } upr_params;
+
+#define UPR_VAR_OPTIMISTIC 1
+#define UPR_VAR_PLAIN_PRIORITY 2
 
 /* Round statistics, written to a device int64 array of UPR_STATS_LEN slots. */
 enum {
@@ -207,6 +220,41 @@ int upr_batch_refine_round(upr_ctx *ctx, upr_batch *batch, const upr_params *par
 /* Rebalancing alone of every graph of the batch (as upr_rebalance). */
 int upr_batch_rebalance(upr_ctx *ctx, upr_batch *batch, const upr_params *params, int32_t *part,
                         int32_t *conn, int64_t *block_w, int64_t *stats, hipStream_t stream);
+
+/* Refinement driver: the rounds around the round (Sections 5.5 and 6).
+ *   Label propagation: penalty-free rounds (mode 2) on an active set, which
+ *   starts as the boundary nodes (a neighbour in another block) and then holds
+ *   every node that did not move and has a neighbour that moved; a round that
+ *   does not lower the cut (rebalancing included) is rolled back and ends the
+ *   phase, as do lp_rounds rounds, an empty active set, or an improvement
+ *   below lp_min (a fraction of the cut before the round).
+ *   FM: at most fm_rounds rounds; penalised (mode 0) while unconstrained, with
+ *   tau rising linearly from tau_1 to 1 over fm_rounds - 1 rounds; a round that
+ *   improves by less than fm_switch (a fraction of its starting cut) switches
+ *   to constrained rounds (mode 1), which stop at the first one that improves
+ *   by less than fm_switch; the last round of the budget is always
+ *   constrained. Every round rebuilds the table. */
+typedef struct {
+    int32_t k, eps_num, eps_den, t_num, t_den;  /* as in upr_params */
+    int32_t lp_rounds;                         /* paper: 5 */
+    int32_t lp_min_num, lp_min_den;            /* paper: 1/1000 */
+    int32_t fm_rounds;                         /* e.g. 10 */
+    int32_t tau1_num, tau1_den;                /* tau_1, e.g. 1/2 */
+    int32_t fm_switch_num, fm_switch_den;      /* paper: 2/1000 */
+    int32_t seq_penalty;                       /* as in upr_params */
+} upr_driver;
+
+/* Kinds of the driver's log entries. */
+enum { UPR_LOG_LP = 0, UPR_LOG_ROLLBACK = 1, UPR_LOG_UNCONSTRAINED = 2, UPR_LOG_CONSTRAINED = 3 };
+
+/* Run the driver in place on (part, conn, block_w) of one graph. log_stats:
+ * device int64 [(lp_rounds + 1 + fm_rounds) * UPR_STATS_LEN], one entry per
+ * round (a rollback repeats the rolled-back round's entry); log_kind: host
+ * int32 of the same count; *n_log: host, entries written. conn and block_w
+ * end consistent with part. Synchronises `stream` after every round. */
+int upr_refine(upr_ctx *ctx, const upr_plan *plan, const upr_driver *driver, int32_t *part,
+               int32_t *conn, int64_t *block_w, int64_t *log_stats, int32_t *log_kind,
+               int32_t *n_log, hipStream_t stream);
 
 /* Host-side helpers (no device work). */
 /* L_max = floor((1 + eps) * ceil(total / k)) with eps = eps_num / eps_den. */

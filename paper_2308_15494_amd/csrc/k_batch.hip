@@ -151,4 +151,76 @@ hipError_t launch_batch_stats_final(int32_t ng, const int64_t *gstat, const int6
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ driver --
+
+// Active set of the label-propagation rounds (Section 6): the boundary nodes
+// (a neighbour in another block), one wave per node over its row.
+__global__ __launch_bounds__(kBlock) void k_boundary(GraphView g, const int32_t *part,
+                                                      uint8_t *active)
+{
+    const int lane = lane_id();
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t v = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); v < g.n; v += waves) {
+        const int32_t a = part[v];
+        bool diff = false;
+        for (int64_t e = g.xadj[v] + lane; e < g.xadj[v + 1] && !diff; e += 64)
+            diff = part[g.adjncy[e]] != a;
+        const bool any = __ballot(diff) != 0;
+        if (lane == 0) active[v] = any ? 1 : 0;
+    }
+}
+
+// Next active set: nodes that did not move and have a neighbour that moved
+// (before / after: the partition at the start and at the end of the round).
+__global__ __launch_bounds__(kBlock) void k_next_active(GraphView g, const int32_t *before,
+                                                         const int32_t *after, uint8_t *active)
+{
+    const int lane = lane_id();
+    const int64_t waves = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t v = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); v < g.n; v += waves) {
+        const bool moved = before[v] != after[v];
+        bool nb = false;
+        if (!moved)
+            for (int64_t e = g.xadj[v] + lane; e < g.xadj[v + 1] && !nb; e += 64) {
+                const int64_t u = g.adjncy[e];
+                nb = before[u] != after[u];
+            }
+        const bool any = __ballot(nb) != 0;
+        if (lane == 0) active[v] = any ? 1 : 0;
+    }
+}
+
+// out[0] = number of nonzero bytes of a[0, n) (one workgroup).
+__global__ void k_count_u8(const uint8_t *a, int64_t n, int64_t *out)
+{
+    __shared__ int64_t red[4];
+    int64_t c = 0;
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) c += a[i] != 0;
+    c = block_sum(c, red);
+    if (threadIdx.x == 0) out[0] = c;
+}
+
+hipError_t launch_count_u8(const uint8_t *a, int64_t n, int64_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_count_u8, dim3(1), dim3(kBlock), 0, s, a, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_boundary(const GraphView &g, const int32_t *part, uint8_t *active, hipStream_t s)
+{
+    if (g.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_boundary, dim3(grid_for(g.n, kBlock / 64, 16384)), dim3(kBlock), 0, s, g,
+                       part, active);
+    return hipGetLastError();
+}
+
+hipError_t launch_next_active(const GraphView &g, const int32_t *before, const int32_t *after,
+                              uint8_t *active, hipStream_t s)
+{
+    if (g.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_next_active, dim3(grid_for(g.n, kBlock / 64, 16384)), dim3(kBlock), 0, s,
+                       g, before, after, active);
+    return hipGetLastError();
+}
+
 }  // namespace upr

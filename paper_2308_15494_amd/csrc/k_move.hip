@@ -68,9 +68,10 @@ __device__ __forceinline__ int covering_slot(const int64_t *cb, int64_t x)
 }
 
 // Per block B: prefix sums over slots, cb[B][l] = sum_{i <= l} c(B_{i,B}), and
-// the penalty a node of weight 1 pays to enter B: 0 if W[B] + 1 <= L_max;
-// otherwise constrained: -1 (forbidden); penalty-free: 0; penalised:
-// penq[l] for the least covering slot l, -1 if none.
+// the penalty a node of weight 1 pays to enter B: 0 if W[B] + 1 <= L_max
+// (limited imbalance: the cap floor(alpha * L_max)); otherwise constrained and
+// limited imbalance: -1 (forbidden); penalty-free: 0; penalised: penq[l] for
+// the least covering slot l, -1 if none.
 __global__ void k_cb_prefix(Blocks bk, int64_t *bucket, const int64_t *W, int mode, int64_t *pen1)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -81,10 +82,10 @@ __global__ void k_cb_prefix(Blocks bk, int64_t *bucket, const int64_t *W, int mo
         run += b[l];
         b[l] = run;
     }
-    const int64_t x = W[j] + 1 - bk.lmax_of(j);
+    const int64_t x = W[j] + 1 - bk.move_lmax_of(j);
     int64_t p = 0;
     if (x > 0) {
-        if (mode == 1) p = -1;
+        if (mode == 1 || mode == 3) p = -1;
         else if (mode == 0) {
             const int l = covering_slot(b, x);
             p = l >= kSlots ? -1 : bk.penq_of(j)[l];
@@ -116,8 +117,8 @@ template <int G, int V>
 __global__ __launch_bounds__(kBlock) void k_best_move(
     GraphView g, Blocks bk, const int32_t *__restrict__ part, const int32_t *__restrict__ conn,
     const int64_t *__restrict__ W, const int64_t *__restrict__ cb,
-    const int64_t *__restrict__ pen1, int mode, int64_t *__restrict__ key,
-    int64_t *__restrict__ pen, unsigned long long *counters)
+    const int64_t *__restrict__ pen1, int mode, const uint8_t *__restrict__ active,
+    int64_t *__restrict__ key, int64_t *__restrict__ pen, unsigned long long *counters)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int32_t k = bk.k;
@@ -146,10 +147,10 @@ __global__ __launch_bounds__(kBlock) void k_best_move(
         int64_t best = 0, bestP = 0;
         const int32_t A = part[v];
         const int64_t cv = node_weight(g, v);
-        if ((unsigned)A < (unsigned)K) {
+        if ((unsigned)A < (unsigned)K && (!active || active[v])) {
             const int32_t a = bk.local(A);
             const int32_t base = bk.base(A);
-            const int64_t lmax = bk.lmax_of(A);
+            const int64_t lmax = bk.move_lmax_of(A);  // L_max, or the limited-imbalance cap
             const int64_t *penq = bk.penq_of(A);
             const int32_t *row = conn + v * (int64_t)k;
             const int32_t ca = row[a];
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void k_best_move(
                         P = 0;
                         const int64_t x = Wr[base + j] + cv - lmax;
                         if (x > 0) {
-                            if (mode == 1) continue;
+                            if (mode == 1 || mode == 3) continue;
                             if (mode == 0) {
                                 const int l = covering_slot(cb + (int64_t)(base + j) * kSlots, x);
                                 if (l >= kSlots) continue;
@@ -223,8 +224,8 @@ __global__ __launch_bounds__(kBlock) void k_best_move(
 
 hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t *part,
                             const int32_t *conn, const int64_t *W, const int64_t *cb,
-                            const int64_t *pen1, int mode, int64_t *key, int64_t *pen,
-                            unsigned long long *counters, hipStream_t s)
+                            const int64_t *pen1, int mode, const uint8_t *active, int64_t *key,
+                            int64_t *pen, unsigned long long *counters, hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
     const int32_t k = bk.k;
@@ -233,7 +234,7 @@ hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t 
     const int nvec = vec ? k / 4 : k;
 #define UPR_BM(GG, VV)                                                                             \
     hipLaunchKernelGGL((k_best_move<GG, VV>), dim3(grid_cap(g.n, kBlock / GG, 8192)), dim3(kBlock), \
-                       lds, s, g, bk, part, conn, W, cb, pen1, mode, key, pen, counters)
+                       lds, s, g, bk, part, conn, W, cb, pen1, mode, active, key, pen, counters)
     if (vec) {
         if (nvec <= 1) UPR_BM(1, 4);
         else if (nvec <= 2) UPR_BM(2, 4);
@@ -265,13 +266,13 @@ __device__ __forceinline__ int move_sign(int32_t x, int32_t a, int32_t b)
 // S3 for candidate v (a -> b, score sv): pessimistic gain over its row
 // [e0, e1) strided by `step` starting at e0 + off. An earlier candidate
 // neighbour u ((score, id) before v) contributes the worse of its current
-// and its target block. kEdgeUnroll edges per lane are loaded before their
-// gathers, so their latencies overlap.
+// and its target block (optimistic variant: its target block). kEdgeUnroll
+// edges per lane are loaded before their gathers, so their latencies overlap.
 constexpr int kEdgeUnroll = 4;
 __device__ __forceinline__ int64_t pessimistic_part(const GraphView &g, const PartView &part,
                                                     const int64_t *key, int64_t v, int32_t a,
                                                     int32_t b, int64_t sv, int64_t e0, int64_t e1,
-                                                    int off, int step)
+                                                    int off, int step, int optimistic)
 {
     int64_t acc = 0;
     for (int64_t e = e0 + off; e < e1; e += (int64_t)kEdgeUnroll * step) {
@@ -296,7 +297,7 @@ __device__ __forceinline__ int64_t pessimistic_part(const GraphView &g, const Pa
                 const int64_t su = ku[i] >> 16;
                 if (su > sv || (su == sv && (int64_t)u[i] < v)) {
                     const int ft = move_sign((int32_t)(ku[i] & 0xFFFF), a, b);
-                    f = ft < f ? ft : f;
+                    f = (optimistic || ft < f) ? ft : f;
                 }
             }
             acc += (int64_t)w[i] * f;
@@ -308,7 +309,7 @@ __device__ __forceinline__ int64_t pessimistic_part(const GraphView &g, const Pa
 // One class of a wave's compacted candidates: lane groups of G take the
 // set bits of mask in order; the node id / key of bit p sit in lane p.
 template <int G>
-__device__ __forceinline__ void filter_class(const GraphView &g, const Blocks &bk,
+__device__ __forceinline__ void filter_class(const GraphView &g, const Blocks &bk, int optimistic,
                                              const int32_t *part,
                                              const PartView &pv, const int64_t *key,
                                              const int64_t *pen,
@@ -333,7 +334,7 @@ __device__ __forceinline__ void filter_class(const GraphView &g, const Blocks &b
             A = part[v];
             b = (int32_t)(kv & 0xFFFF);
             acc = pessimistic_part(g, pv, key, v, bk.local(A), b, kv >> 16, g.xadj[v], g.xadj[v + 1],
-                                   gl, G);
+                                   gl, G, optimistic);
         }
         acc = group_sum<G>(acc);
         bool take = false;
@@ -352,7 +353,7 @@ __device__ __forceinline__ void filter_class(const GraphView &g, const Blocks &b
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk,
+__global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int optimistic,
                                                     const int32_t *__restrict__ part,
                                                     PartView pv, const int64_t *__restrict__ key,
                                                     const int64_t *__restrict__ pen, int64_t low_t,
@@ -377,11 +378,11 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk,
         const uint64_t mlow = __ballot(kv >= 0 && deg <= low_t);
         const uint64_t mmid = __ballot(kv >= 0 && deg > low_t && deg <= hub_t);
         if (mlow)
-            filter_class<kLowLanes>(g, bk, part, pv, key, pen, mlow, v, kv, mvto, accflag,
-                                    &acc_lds, &deg_lds, gp_out);
+            filter_class<kLowLanes>(g, bk, optimistic, part, pv, key, pen, mlow, v, kv, mvto,
+                                    accflag, &acc_lds, &deg_lds, gp_out);
         if (mmid)
-            filter_class<64>(g, bk, part, pv, key, pen, mmid, v, kv, mvto, accflag, &acc_lds,
-                             &deg_lds, gp_out);
+            filter_class<64>(g, bk, optimistic, part, pv, key, pen, mmid, v, kv, mvto, accflag,
+                             &acc_lds, &deg_lds, gp_out);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -390,20 +391,22 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk,
     }
 }
 
-hipError_t launch_filter(const GraphView &g, const Blocks &bk, const int32_t *part,
+hipError_t launch_filter(const GraphView &g, const Blocks &bk, int optimistic, const int32_t *part,
                          const PartView &pv, const int64_t *key, const int64_t *pen, int64_t low_t,
                          int64_t hub_t, int32_t *mvto, uint8_t *accflag,
                          unsigned long long *counters, int64_t *gp_out, hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_filter, dim3(grid_cap(g.n, kBlock, 8192)), dim3(kBlock), 0, s, g, bk, part,
-                       pv, key, pen, low_t, hub_t, mvto, accflag, counters, gp_out);
+    hipLaunchKernelGGL(k_filter, dim3(grid_cap(g.n, kBlock, 8192)), dim3(kBlock), 0, s, g, bk,
+                       optimistic, part, pv, key, pen, low_t, hub_t, mvto, accflag, counters,
+                       gp_out);
     return hipGetLastError();
 }
 
 // Hub candidates: each chunk adds its part of the pessimistic gain.
-__global__ __launch_bounds__(kBlock) void k_filter_hub(GraphView g, Blocks bk, const int32_t *part,
-                                                        PartView pv, const int64_t *key, HubView h)
+__global__ __launch_bounds__(kBlock) void k_filter_hub(GraphView g, Blocks bk, int optimistic,
+                                                        const int32_t *part, PartView pv,
+                                                        const int64_t *key, HubView h)
 {
     __shared__ int64_t red[4];
     const HubChunk c = h.chunks[blockIdx.x];
@@ -411,7 +414,8 @@ __global__ __launch_bounds__(kBlock) void k_filter_hub(GraphView g, Blocks bk, c
     const int64_t kv = key[v];
     if (kv < 0) return;  // uniform over the workgroup
     const int32_t a = bk.local(part[v]), b = (int32_t)(kv & 0xFFFF);
-    int64_t acc = pessimistic_part(g, pv, key, v, a, b, kv >> 16, c.e0, c.e1, threadIdx.x, kBlock);
+    int64_t acc = pessimistic_part(g, pv, key, v, a, b, kv >> 16, c.e0, c.e1, threadIdx.x, kBlock,
+                                   optimistic);
     acc = block_sum(acc, red);
     if (threadIdx.x == 0 && acc) atomic_add_i64(&h.gacc[c.hub], acc);
 }
@@ -451,14 +455,14 @@ __global__ void k_hub_moved_deg(GraphView g, const int32_t *mvto, HubView h,
     if (mvto[v] >= 0) atomicAdd(&counters[CNT_MOVED_DEG], (unsigned long long)(g.xadj[v + 1] - g.xadj[v]));
 }
 
-hipError_t launch_filter_hub(const GraphView &g, const Blocks &bk, const int32_t *part,
-                             const PartView &pv, const int64_t *key, const int64_t *pen,
-                             const HubView &h, int32_t *mvto, uint8_t *accflag,
+hipError_t launch_filter_hub(const GraphView &g, const Blocks &bk, int optimistic,
+                             const int32_t *part, const PartView &pv, const int64_t *key,
+                             const int64_t *pen, const HubView &h, int32_t *mvto, uint8_t *accflag,
                              unsigned long long *counters, int64_t *gp_out, hipStream_t s)
 {
     if (h.nh <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_filter_hub, dim3((unsigned)h.nchunks), dim3(kBlock), 0, s, g, bk, part,
-                       pv, key, h);
+    hipLaunchKernelGGL(k_filter_hub, dim3((unsigned)h.nchunks), dim3(kBlock), 0, s, g, bk,
+                       optimistic, part, pv, key, h);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_filter_hub_final, dim3((h.nh + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
@@ -501,9 +505,9 @@ __global__ __launch_bounds__(kBlock) void k_filter_seq(
             int64_t P = 0;
             if (allowed) {
                 const int64_t cv = node_weight(g, v);
-                const int64_t x = W[b] + netpre[v] + cv - bk.lmax_of(A);
+                const int64_t x = W[b] + netpre[v] + cv - bk.move_lmax_of(A);
                 if (x > 0) {
-                    if (mode == 1) allowed = false;
+                    if (mode == 1 || mode == 3) allowed = false;
                     else if (mode == 0) {
                         const int l = covering_slot(cb + (int64_t)b * kSlots, x);
                         if (l >= kSlots) allowed = false;

@@ -106,7 +106,7 @@ template <int G, int V>
 __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
                                                         const int32_t *__restrict__ part,
                                                         const int32_t *__restrict__ conn,
-                                                        RebalWs r, int hist32)
+                                                        RebalWs r, int hist32, int plain)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int32_t k = bk.k;
@@ -202,7 +202,8 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
                 r.rtgt[v] = tgt >= 0 ? base + tgt : -1;
                 if (tgt >= 0) {
                     const int64_t ca = conn[v * (int64_t)k + a];
-                    const int be = rebalance_bucket(ct - ca, cv);
+                    // the plain-gain variant ranks by the gain alone (c(v) = 1)
+                    const int be = rebalance_bucket(ct - ca, plain ? 1 : cv);
                     r.rbeta[v] = (uint8_t)be;
                     hkey = (int64_t)(base + tgt) * kRbBuckets + be;
                     push = true;
@@ -504,8 +505,8 @@ int rb_scan_grid(int64_t n) { return grid_cap(n, kBlock, 4096); }
 
 hipError_t launch_rb_iteration(const GraphView &g, const Blocks &bk, const int32_t *part,
                                const int32_t *conn, const RebalWs &r, int32_t *mvto, int hist32,
-                               int64_t hub_t, unsigned long long *counters, int64_t *gstat,
-                               hipStream_t s)
+                               int plain, int64_t hub_t, unsigned long long *counters,
+                               int64_t *gstat, hipStream_t s)
 {
     hipError_t e;
     const RbView rv{r.rtgt, r.rbeta, r.W0, r.cbeta_src, r.theta_src, r.cbeta_tgt, r.theta_tgt};
@@ -519,7 +520,7 @@ hipError_t launch_rb_iteration(const GraphView &g, const Blocks &bk, const int32
     const int nvec = vec ? k / 4 : k;
 #define UPR_RP(GG, VV)                                                                          \
     hipLaunchKernelGGL((k_rb_prepare<GG, VV>), dim3(lg), dim3(kBlock), plds, s, g, bk, part, conn, \
-                       r, hist32)
+                       r, hist32, plain)
     if (vec) {
         if (nvec <= 1) UPR_RP(1, 4);
         else if (nvec <= 2) UPR_RP(2, 4);

@@ -300,7 +300,11 @@ int check_params(upr_ctx *c, const upr_plan *p, const upr_params *q)
     if (q->t_den <= 0 || q->t_num < 0 || q->t_num > q->t_den) return fail(c, UPR_E_ARG, "t must be in [0, 1]");
     if (q->tau_den <= 0 || q->tau_num < 0 || q->tau_num > q->tau_den)
         return fail(c, UPR_E_ARG, "tau must be in [0, 1]");
-    if (q->mode < 0 || q->mode > 2) return fail(c, UPR_E_ARG, "mode=%d not in {0,1,2}", q->mode);
+    if (q->mode < 0 || q->mode > 3) return fail(c, UPR_E_ARG, "mode=%d not in {0,1,2,3}", q->mode);
+    if (q->mode == 3 && (q->alpha_den <= 0 || q->alpha_num < q->alpha_den))
+        return fail(c, UPR_E_ARG, "alpha must be a rational >= 1");
+    if (q->variant & ~(UPR_VAR_OPTIMISTIC | UPR_VAR_PLAIN_PRIORITY))
+        return fail(c, UPR_E_ARG, "unknown variant bits 0x%x", q->variant);
     if (q->max_rebalance_iters < 0) return fail(c, UPR_E_ARG, "max_rebalance_iters < 0");
     if (q->seq_penalty != 0 && q->seq_penalty != 1) return fail(c, UPR_E_ARG, "seq_penalty not 0/1");
     (void)p;
@@ -340,7 +344,7 @@ int hist32_ok(const upr_plan *p)
 }
 
 // S5: the host loop over synchronous sub-iterations (one graph).
-int rebalance_loop(upr_ctx *c, const upr_plan *p, const Blocks &bk, int32_t *part,
+int rebalance_loop(upr_ctx *c, const upr_plan *p, const Blocks &bk, int plain, int32_t *part,
                    const PartView &pv, int32_t *conn, int64_t *W, int64_t it_max,
                    int64_t *iters_out, int64_t *status_out, hipStream_t s)
 {
@@ -363,8 +367,8 @@ int rebalance_loop(upr_ctx *c, const upr_plan *p, const Blocks &bk, int32_t *par
             break;
         }
         ++iters;
-        HIP_TRY(c, launch_rb_iteration(p->g, bk, part, conn, c->rb, c->mvto, hist32, p->hub_t,
-                                       c->counters, nullptr, s));
+        HIP_TRY(c, launch_rb_iteration(p->g, bk, part, conn, c->rb, c->mvto, hist32, plain,
+                                       p->hub_t, c->counters, nullptr, s));
         HIP_TRY(c, launch_apply(p->g, bk, part, pv, conn, W, c->mvto, p->low_t, p->hub_t, h,
                                 c->counters, p->dirty_threshold, c->dirty, s));
         HIP_TRY(c, launch_rb_begin(bk, W, c->rb, c->counters, nullptr, s));
@@ -392,7 +396,7 @@ int sync_batch(upr_ctx *c, const upr_batch *b, hipStream_t s)
 // when balanced, when a sub-iteration moved nothing, or at its iteration
 // cap); a graph that stopped is excluded from later sub-iterations by
 // raising its source bound. Results per graph go to b->host3_h.
-int rebalance_loop_batch(upr_ctx *c, const upr_plan *p, upr_batch *b, const Blocks &bk,
+int rebalance_loop_batch(upr_ctx *c, const upr_plan *p, upr_batch *b, const Blocks &bk, int plain,
                          int32_t *part, const PartView &pv, int32_t *conn, int64_t *W,
                          int64_t it_user, hipStream_t s)
 {
@@ -430,8 +434,8 @@ int rebalance_loop_batch(upr_ctx *c, const upr_plan *p, upr_batch *b, const Bloc
         if (!any) break;
         for (int32_t g = 0; g < ng; ++g) b->srcl_h[g] = active[g] ? b->lmax[g] : INT64_MAX;
         HIP_TRY(c, hipMemcpyAsync(b->srcl_d, b->srcl_h, sizeof(int64_t) * ng, hipMemcpyHostToDevice, s));
-        HIP_TRY(c, launch_rb_iteration(p->g, bk, part, conn, c->rb, c->mvto, hist32, p->hub_t,
-                                       c->counters, b->gstat_d, s));
+        HIP_TRY(c, launch_rb_iteration(p->g, bk, part, conn, c->rb, c->mvto, hist32, plain,
+                                       p->hub_t, c->counters, b->gstat_d, s));
         HIP_TRY(c, launch_apply(p->g, bk, part, pv, conn, W, c->mvto, p->low_t, p->hub_t, h,
                                 c->counters, p->dirty_threshold, c->dirty, s));
         HIP_TRY(c, launch_rb_begin(bk, W, c->rb, c->counters, b->gstat_d, s));
@@ -766,7 +770,7 @@ int upr_edge_cut(upr_ctx *c, const upr_plan *p, const int32_t *part, int64_t *cu
 // single graph (b == null) or of every graph of a batch.
 static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_params *q,
                       int32_t *part, int32_t *conn, int64_t *W, int64_t *stats, hipStream_t s,
-                      bool moves)
+                      bool moves, const uint8_t *active = nullptr)
 {
     const int64_t n = p->g.n;
     const int32_t k = q->k;
@@ -788,6 +792,12 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
         bk.src_lmax = c->srcl1;
         bk.penq = c->penq;
     }
+    if (q->mode == 3) {
+        bk.alpha_num = q->alpha_num;
+        bk.alpha_den = q->alpha_den;
+    }
+    const int optimistic = (q->variant & UPR_VAR_OPTIMISTIC) ? 1 : 0;
+    const int plain = (q->variant & UPR_VAR_PLAIN_PRIORITY) ? 1 : 0;
     const int32_t K = bk.total();
     int64_t *gstat = b ? b->gstat_d : nullptr;
     HIP_TRY(c, hipSetDevice(c->device));
@@ -829,7 +839,7 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
             PhaseTimer t(c, 2, s);
             HIP_TRY(c, launch_cb_prefix(bk, c->bucket, W, q->mode, c->pen1, s));
             HIP_TRY(c, launch_best_move(p->g, bk, part, conn, W, c->bucket, c->pen1, q->mode,
-                                        c->key, c->pen, c->counters, s));
+                                        active, c->key, c->pen, c->counters, s));
         }
         // one host decision: are there candidates at all (also reports bad input)
         rc = sync_counters(c, s);
@@ -843,10 +853,10 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
             {
                 PhaseTimer t(c, 3, s);
                 int64_t *gp_out = q->seq_penalty ? c->gp : nullptr;
-                HIP_TRY(c, launch_filter(p->g, bk, part, pv, c->key, c->pen, p->low_t, p->hub_t,
-                                         c->mvto, c->accflag, c->counters, gp_out, s));
-                HIP_TRY(c, launch_filter_hub(p->g, bk, part, pv, c->key, c->pen, h, c->mvto,
-                                             c->accflag, c->counters, gp_out, s));
+                HIP_TRY(c, launch_filter(p->g, bk, optimistic, part, pv, c->key, c->pen, p->low_t,
+                                         p->hub_t, c->mvto, c->accflag, c->counters, gp_out, s));
+                HIP_TRY(c, launch_filter_hub(p->g, bk, optimistic, part, pv, c->key, c->pen, h,
+                                             c->mvto, c->accflag, c->counters, gp_out, s));
                 if (q->seq_penalty) {
                     // eligible candidates in id order; their number sizes the sort
                     HIP_TRY(c, launch_seq_select(n, c->key, c->gp, c->cand,
@@ -885,11 +895,11 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
     {
         PhaseTimer t(c, 5, s);
         if (b) {
-            rc = rebalance_loop_batch(c, p, b, bk, part, pv, conn, W, q->max_rebalance_iters, s);
+            rc = rebalance_loop_batch(c, p, b, bk, plain, part, pv, conn, W, q->max_rebalance_iters, s);
         } else {
             const int64_t it_max =
                 q->max_rebalance_iters > 0 ? q->max_rebalance_iters : default_iters(p, k);
-            rc = rebalance_loop(c, p, bk, part, pv, conn, W, it_max, &iters, &status, s);
+            rc = rebalance_loop(c, p, bk, plain, part, pv, conn, W, it_max, &iters, &status, s);
         }
         if (rc) return rc;
     }
@@ -1143,6 +1153,160 @@ int upr_batch_rebalance(upr_ctx *c, upr_batch *b, const upr_params *q, int32_t *
                         int32_t *conn, int64_t *W, int64_t *stats, hipStream_t s)
 {
     return batch_common(c, b, q, nullptr, nullptr, part, conn, W, stats, s, false);
+}
+
+// --------------------------------------------------------------- driver --
+
+namespace {
+
+// (x) < (num / den) * y for nonnegative integers, exactly.
+bool below(int64_t x, int32_t num, int32_t den, int64_t y)
+{
+    return (__int128)x * den < (__int128)num * y;
+}
+
+// tau_1 + (1 - tau_1) (i - 1) / (rounds - 1), reduced to num / den.
+void tau_linear(int64_t i, int64_t rounds, int32_t t1n, int32_t t1d, int32_t *num, int32_t *den)
+{
+    int64_t n, d;
+    if (rounds <= 1) {
+        n = t1n;
+        d = t1d;
+    } else {
+        // (t1n (R-1) + (t1d - t1n)(i-1)) / (t1d (R-1))
+        n = (int64_t)t1n * (rounds - 1) + (int64_t)(t1d - t1n) * (i - 1);
+        d = (int64_t)t1d * (rounds - 1);
+    }
+    int64_t a = n, b = d;
+    while (b) {
+        const int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    if (a == 0) a = 1;
+    *num = (int32_t)(n / a);
+    *den = (int32_t)(d / a);
+}
+
+}  // namespace
+
+int upr_refine(upr_ctx *c, const upr_plan *p, const upr_driver *d, int32_t *part, int32_t *conn,
+               int64_t *W, int64_t *log_stats, int32_t *log_kind, int32_t *n_log, hipStream_t s)
+{
+    int rc = check_plan(c, p);
+    if (rc) return rc;
+    if (!d || !n_log || !log_kind || !log_stats) return fail(c, UPR_E_ARG, "driver/log NULL");
+    if (d->lp_rounds < 0 || d->fm_rounds < 0 || d->lp_min_den <= 0 || d->lp_min_num < 0 ||
+        d->fm_switch_den <= 0 || d->fm_switch_num < 0 || d->tau1_den <= 0 || d->tau1_num < 0 ||
+        d->tau1_num > d->tau1_den)
+        return fail(c, UPR_E_ARG, "driver parameters out of range");
+    upr_params q{};
+    q.k = d->k;
+    q.eps_num = d->eps_num;
+    q.eps_den = d->eps_den;
+    q.t_num = d->t_num;
+    q.t_den = d->t_den;
+    q.tau_num = 1;
+    q.tau_den = 1;
+    q.rebuild_table = 1;
+    q.seq_penalty = d->seq_penalty;
+    q.alpha_num = q.alpha_den = 1;
+    rc = check_params(c, p, &q);
+    if (rc) return rc;
+    const int64_t n = p->g.n;
+    if (!W || (n > 0 && (!part || !conn))) return fail(c, UPR_E_ARG, "part/conn/block_w NULL");
+    HIP_TRY(c, hipSetDevice(c->device));
+    int32_t nl = 0;  // log entries: at most lp_rounds + 1 + fm_rounds
+    int64_t st[UPR_STATS_LEN];
+    uint8_t *active = nullptr;
+    int32_t *start = nullptr;
+    if (dalloc(&active, n) != hipSuccess || dalloc(&start, n) != hipSuccess) {
+        dfree(active);
+        dfree(start);
+        return fail(c, UPR_E_NOMEM, "driver allocation failed");
+    }
+    auto done = [&](int code) {
+        (void)hipStreamSynchronize(s);
+        dfree(active);
+        dfree(start);
+        *n_log = nl;
+        return code;
+    };
+    auto read_stats = [&](int32_t i) -> int {
+        HIP_TRY(c, hipMemcpyAsync(st, log_stats + (int64_t)i * UPR_STATS_LEN, sizeof st,
+                                  hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        return UPR_OK;
+    };
+    // label propagation (Section 6): penalty-free rounds on the active set,
+    // rollback and stop when a round does not improve
+    if (d->lp_rounds > 0 && n > 0) HIP_TRY(c, launch_boundary(p->g, part, active, s));
+    for (int32_t r = 0; r < d->lp_rounds && n > 0; ++r) {
+        // an empty active set ends the phase
+        HIP_TRY(c, launch_count_u8(active, n, (int64_t *)(c->counters + CNT_TMP), s));
+        int64_t nact = 0;
+        HIP_TRY(c, hipMemcpyAsync(&nact, c->counters + CNT_TMP, sizeof nact, hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        if (nact == 0) break;
+        HIP_TRY(c, hipMemcpyAsync(start, part, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+        upr_params ql = q;
+        ql.mode = 2;
+        rc = round_core(c, p, nullptr, &ql, part, conn, W, log_stats + (int64_t)nl * UPR_STATS_LEN, s,
+                        true, active);
+        if (rc) return done(rc);
+        if ((rc = read_stats(nl)) != UPR_OK) return done(rc);
+        log_kind[nl++] = UPR_LOG_LP;
+        const int64_t before = st[UPR_ST_CUT_BEFORE], after = st[UPR_ST_CUT_AFTER];
+        if (after >= before) {
+            // no net improvement: restore the round's starting partition
+            HIP_TRY(c, hipMemcpyAsync(part, start, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(c, hipMemcpyAsync(log_stats + (int64_t)nl * UPR_STATS_LEN,
+                                      log_stats + (int64_t)(nl - 1) * UPR_STATS_LEN,
+                                      sizeof(int64_t) * UPR_STATS_LEN, hipMemcpyDeviceToDevice, s));
+            log_kind[nl++] = UPR_LOG_ROLLBACK;
+            break;
+        }
+        HIP_TRY(c, launch_next_active(p->g, start, part, active, s));
+        if (below(before - after, d->lp_min_num, d->lp_min_den, before)) break;
+    }
+    // FM rounds (Section 5.5): penalised rounds with tau rising linearly from
+    // tau_1, a switch to constrained rounds once a round improves the cut by
+    // less than the threshold, and a constrained round at the end
+    bool unconstrained = true;
+    const int64_t n_unc = std::max<int64_t>(d->fm_rounds - 1, 1);
+    int64_t i_unc = 0;
+    for (int32_t r = 0; r < d->fm_rounds; ++r) {
+        const bool last = r == d->fm_rounds - 1;
+        upr_params qf = q;
+        int32_t kind;
+        if (unconstrained && !last) {
+            ++i_unc;
+            qf.mode = 0;
+            tau_linear(i_unc, n_unc, d->tau1_num, d->tau1_den, &qf.tau_num, &qf.tau_den);
+            kind = UPR_LOG_UNCONSTRAINED;
+        } else {
+            unconstrained = false;
+            qf.mode = 1;
+            kind = UPR_LOG_CONSTRAINED;
+        }
+        rc = round_core(c, p, nullptr, &qf, part, conn, W, log_stats + (int64_t)nl * UPR_STATS_LEN,
+                        s, true);
+        if (rc) return done(rc);
+        if ((rc = read_stats(nl)) != UPR_OK) return done(rc);
+        log_kind[nl++] = kind;
+        const int64_t before = st[UPR_ST_CUT_BEFORE], after = st[UPR_ST_CUT_AFTER];
+        const bool small = below(before - after, d->fm_switch_num, d->fm_switch_den, std::max<int64_t>(before, 1));
+        if (kind == UPR_LOG_UNCONSTRAINED && small) unconstrained = false;
+        else if (kind == UPR_LOG_CONSTRAINED && small) break;
+    }
+    if (d->fm_rounds == 0 && n > 0) {
+        // the table and block weights of the final partition
+        HIP_TRY(c, launch_gain_tile(p->g, d->k, PartView{part, 4}, conn, p->hub_t, nullptr, s));
+        HIP_TRY(c, launch_gain_hub(p->g, d->k, PartView{part, 4}, conn, p->hubs(), s));
+        HIP_TRY(c, launch_fill_i64(W, d->k, 0, s));
+        HIP_TRY(c, launch_block_weights(p->g, d->k, part, W, c->counters, s));
+    }
+    return done(UPR_OK);
 }
 
 int upr_last_moves(upr_ctx *c, int64_t n, int32_t *target, int64_t *score, int64_t *pen,

@@ -50,6 +50,9 @@ struct Blocks {
     const int64_t *lmax = nullptr;      // [ng] L_max of each graph
     const int64_t *src_lmax = nullptr;  // [ng] rebalancing: a block is a source iff heavier
     const int64_t *penq = nullptr;      // [ng * kSlots] Q16 penalty table of each graph
+    // moves may fill a target up to floor(alpha * L_max) before they are
+    // penalised or forbidden (alpha = 1 except in the limited-imbalance mode)
+    int32_t alpha_num = 1, alpha_den = 1;
     __host__ __device__ int32_t total() const { return k * ng; }
     __device__ int32_t graph(int32_t B) const { return ng == 1 ? 0 : B / k; }
     __device__ int32_t base(int32_t B) const { return ng == 1 ? 0 : (B / k) * k; }
@@ -57,7 +60,17 @@ struct Blocks {
     __device__ int64_t lmax_of(int32_t B) const { return lmax[graph(B)]; }
     __device__ int64_t src_lmax_of(int32_t B) const { return src_lmax[graph(B)]; }
     __device__ const int64_t *penq_of(int32_t B) const { return penq + (int64_t)graph(B) * kSlots; }
+    __device__ int64_t move_lmax_of(int32_t B) const
+    {
+        const int64_t L = lmax_of(B);
+        if (alpha_num == alpha_den) return L;
+        return (int64_t)(((unsigned __int128)(uint64_t)L * (uint32_t)alpha_num) / (uint32_t)alpha_den);
+    }
 };
+
+// Bit flags of upr_params.variant.
+constexpr int kVarOptimistic = 1;
+constexpr int kVarPlainPriority = 2;
 
 // Per-graph statistics of a batch (int64 [ng][GS_COUNT]).
 enum GraphStat {
@@ -382,18 +395,21 @@ hipError_t launch_round_init(const Blocks &bk, int64_t *bucket, int64_t *W, cons
 // into B (0 if it fits, -1 if forbidden).
 hipError_t launch_cb_prefix(const Blocks &bk, int64_t *bucket, const int64_t *W, int mode,
                             int64_t *pen1, hipStream_t s);
+// active (may be null: every node): only nodes with active[v] != 0 look for
+// a move.
 hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t *part,
                             const int32_t *conn, const int64_t *W, const int64_t *cb,
-                            const int64_t *pen1, int mode, int64_t *key, int64_t *pen,
-                            unsigned long long *counters, hipStream_t s);
+                            const int64_t *pen1, int mode, const uint8_t *active, int64_t *key,
+                            int64_t *pen, unsigned long long *counters, hipStream_t s);
 // With gp_out the pessimistic gains are stored (decided by launch_filter_seq).
-hipError_t launch_filter(const GraphView &g, const Blocks &bk, const int32_t *part,
+// optimistic: an earlier candidate neighbour counts in its target block.
+hipError_t launch_filter(const GraphView &g, const Blocks &bk, int optimistic, const int32_t *part,
                          const PartView &pv,
                          const int64_t *key, const int64_t *pen, int64_t low_t, int64_t hub_t,
                          int32_t *mvto, uint8_t *accflag, unsigned long long *counters,
                          int64_t *gp_out, hipStream_t s);
-hipError_t launch_filter_hub(const GraphView &g, const Blocks &bk, const int32_t *part,
-                             const PartView &pv,
+hipError_t launch_filter_hub(const GraphView &g, const Blocks &bk, int optimistic,
+                             const int32_t *part, const PartView &pv,
                              const int64_t *key, const int64_t *pen, const HubView &h,
                              int32_t *mvto, uint8_t *accflag, unsigned long long *counters,
                              int64_t *gp_out, hipStream_t s);
@@ -462,10 +478,11 @@ hipError_t launch_rb_begin(const Blocks &bk, const int64_t *W, const RebalWs &r,
 // per-workgroup histograms may use 32-bit LDS counters (no overflow).
 // gstat (batch): moves per graph in gstat[g][GS_MOVED_NOW] (reset first) and
 // gstat[g][GS_REBAL_MOVES].
+// plain: rebalancing priority by the gain alone (node weight left out).
 hipError_t launch_rb_iteration(const GraphView &g, const Blocks &bk, const int32_t *part,
                                const int32_t *conn, const RebalWs &r, int32_t *mvto, int hist32,
-                               int64_t hub_t, unsigned long long *counters, int64_t *gstat,
-                               hipStream_t s);
+                               int plain, int64_t hub_t, unsigned long long *counters,
+                               int64_t *gstat, hipStream_t s);
 int rb_scan_grid(int64_t n);
 
 // batches (k_batch.hip)
@@ -480,5 +497,11 @@ hipError_t launch_batch_move_stats(int64_t n, const Blocks &bk, const int32_t *p
                                    hipStream_t s);
 hipError_t launch_batch_stats_final(int32_t ng, const int64_t *gstat, const int64_t *lmax,
                                     const int64_t *host3, int moved, int64_t *stats, hipStream_t s);
+// driver: count of nonzero bytes; boundary nodes; nodes that did not move
+// with a neighbour that moved
+hipError_t launch_count_u8(const uint8_t *a, int64_t n, int64_t *out, hipStream_t s);
+hipError_t launch_boundary(const GraphView &g, const int32_t *part, uint8_t *active, hipStream_t s);
+hipError_t launch_next_active(const GraphView &g, const int32_t *before, const int32_t *after,
+                              uint8_t *active, hipStream_t s);
 
 }  // namespace upr

@@ -22,7 +22,7 @@ STATS_LEN = 12
 STAT_NAMES = ["l_max", "cut_before", "cut_after_moves", "cut_after", "candidates",
               "accepted", "rebalance_moves", "rebalance_iters", "status"]
 PHASES = ["gain_tile", "gain_hub", "best_move", "filter", "apply", "rebalance", "cut", "call"]
-MODES = {"penalised": 0, "constrained": 1, "free": 2}
+MODES = {"penalised": 0, "constrained": 1, "free": 2, "limited": 3}
 
 
 class UprError(RuntimeError):
@@ -38,19 +38,24 @@ class _Graph(C.Structure):
 
 class Params(C.Structure):
     """upr_params: k, eps, t, tau (rationals), mode, rebuild_table, max_rebalance_iters,
-    seq_penalty."""
+    seq_penalty, alpha (rational, mode 3), variant (bit flags)."""
     _fields_ = [("k", C.c_int32), ("eps_num", C.c_int32), ("eps_den", C.c_int32),
                 ("t_num", C.c_int32), ("t_den", C.c_int32), ("tau_num", C.c_int32),
                 ("tau_den", C.c_int32), ("mode", C.c_int32), ("rebuild_table", C.c_int32),
-                ("max_rebalance_iters", C.c_int32), ("seq_penalty", C.c_int32)]
+                ("max_rebalance_iters", C.c_int32), ("seq_penalty", C.c_int32),
+                ("alpha_num", C.c_int32), ("alpha_den", C.c_int32), ("variant", C.c_int32)]
+
+
+VAR_OPTIMISTIC = 1
+VAR_PLAIN_PRIORITY = 2
 
 
 def params(k, eps=(3, 100), t=(7, 10), tau=(1, 1), mode=0, rebuild_table=1,
-           max_rebalance_iters=0, seq_penalty=1) -> Params:
+           max_rebalance_iters=0, seq_penalty=1, alpha=(1, 1), variant=0) -> Params:
     if isinstance(mode, str):
         mode = MODES[mode]
     return Params(k, eps[0], eps[1], t[0], t[1], tau[0], tau[1], mode, rebuild_table,
-                  max_rebalance_iters, seq_penalty)
+                  max_rebalance_iters, seq_penalty, alpha[0], alpha[1], variant)
 
 
 _lib = None
@@ -87,6 +92,9 @@ _SIGS = [
                                          C.c_void_p, C.c_void_p]),
     ("upr_batch_rebalance", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(Params), C.c_void_p,
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("upr_refine", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                             C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32),
+                             C.c_void_p]),
     ("upr_timing_enable", C.c_int, [C.c_void_p, C.c_int]),
     ("upr_timing_read", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
 ]
@@ -106,6 +114,38 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+class Driver(C.Structure):
+    """upr_driver: label propagation then FM rounds (Sections 5.5 and 6)."""
+    _fields_ = [("k", C.c_int32), ("eps_num", C.c_int32), ("eps_den", C.c_int32),
+                ("t_num", C.c_int32), ("t_den", C.c_int32), ("lp_rounds", C.c_int32),
+                ("lp_min_num", C.c_int32), ("lp_min_den", C.c_int32), ("fm_rounds", C.c_int32),
+                ("tau1_num", C.c_int32), ("tau1_den", C.c_int32), ("fm_switch_num", C.c_int32),
+                ("fm_switch_den", C.c_int32), ("seq_penalty", C.c_int32)]
+
+
+LOG_KINDS = {0: "lp", 1: "rollback", 2: "unconstrained", 3: "constrained"}
+
+
+def driver(k, eps=(3, 100), t=(7, 10), lp_rounds=5, lp_min=(1, 1000), fm_rounds=10,
+           tau1=(1, 2), fm_switch=(2, 1000), seq_penalty=1) -> Driver:
+    return Driver(k, eps[0], eps[1], t[0], t[1], lp_rounds, lp_min[0], lp_min[1], fm_rounds,
+                  tau1[0], tau1[1], fm_switch[0], fm_switch[1], seq_penalty)
+
+
+def refine(ctx, plan, d: Driver, part, conn, W, stream=None):
+    """Run the driver in place; returns [(kind, stats ndarray)] per round."""
+    import torch
+    cap = d.lp_rounds + 1 + d.fm_rounds
+    log = torch.zeros(max(cap, 1) * STATS_LEN, dtype=torch.int64, device=part.device)
+    kinds = np.zeros(max(cap, 1), np.int32)
+    nl = C.c_int32(0)
+    ctx.check(lib().upr_refine(ctx.handle, plan.handle, C.byref(d), _ptr(part), _ptr(conn),
+                               _ptr(W), _ptr(log), kinds.ctypes.data, C.byref(nl),
+                               _stream(stream)))
+    st = log.cpu().numpy().reshape(-1, STATS_LEN)
+    return [(LOG_KINDS[int(kinds[i])], st[i].copy()) for i in range(nl.value)]
 
 
 def lmax(total, k, eps=(3, 100)) -> int:

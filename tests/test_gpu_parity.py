@@ -233,6 +233,35 @@ def test_round_parity_small(upr, ctx, case, mode, seq):
                 pr.compare(ost, odbg, f"{name} mode {mode} seq {seq} seed {seed} {pname} round {r}")
 
 
+VARIANTS = [
+    ("limited", dict(mode=3), True),
+    ("optimistic", dict(variant=1), False),
+    ("plain_priority", dict(variant=2), False),
+    ("optimistic_plain_limited", dict(mode=3, variant=3), True),
+]
+
+
+@pytest.mark.parametrize("case", SMALL[:5] + SMALL[6:], ids=[c[0] for c in SMALL[:5] + SMALL[6:]])
+@pytest.mark.parametrize("var", VARIANTS, ids=[v[0] for v in VARIANTS])
+@pytest.mark.parametrize("seq", [1, 0])
+def test_round_parity_variants(upr, ctx, case, var, seq):
+    """The Section 8.2 variants: limited imbalance (alpha from 2 down to 1.1),
+    optimistic filter, plain-gain rebalancing priority."""
+    name, make, k = case
+    vname, kw, uses_alpha = var
+    for seed in range(2):
+        g = make(seed + 11)
+        part0 = skewed_partition(g.n, k, seed, 0.4)
+        say(f"variant {vname} case={name} seq={seq} seed={seed} n={g.n} k={k}")
+        pr = Pair(upr, ctx, g, k, part0)
+        for r in range(1, 5):
+            extra = dict(kw)
+            if uses_alpha:
+                extra["alpha"] = gg.alpha_schedule(r, 4)
+            ost, odbg = pr.round(tau=gg.tau_schedule(r, 4), seq_penalty=seq, **extra)
+            pr.compare(ost, odbg, f"{vname} {name} seq {seq} seed {seed} round {r}")
+
+
 @pytest.mark.parametrize("t", [(7, 10), (2, 5), (0, 1), (1, 1)])
 def test_round_parity_threshold(upr, ctx, t):
     g = gg.chung_lu(4000, 8.0, 2.2, seed=9)
@@ -380,7 +409,8 @@ def test_errors(upr, ctx):
     W = torch.zeros(k, dtype=torch.int64, device="cuda")
     good = to_dev(gg.random_partition(g.n, k, 1))
     for bad in [dict(k=1), dict(k=8193), dict(k=4, eps=(0, 1)), dict(k=4, tau=(3, 2)), dict(k=4, t=(2, 1)),
-                dict(k=4, mode=7)]:
+                dict(k=4, mode=7), dict(k=4, mode=3, alpha=(9, 10)), dict(k=4, mode=3, alpha=(1, 0)),
+                dict(k=4, variant=4)]:
         kk = bad.pop("k")
         with pytest.raises(upr.UprError) as ei:
             upr.refine_round(ctx, plan, upr.params(kk, **bad), good, conn, W)
@@ -451,3 +481,37 @@ def test_apply_modes(upr, ctx, monkeypatch, div):
         for r in range(1, 5):
             ost, odbg = pr.round(tau=gg.tau_schedule(r, 4))
             pr.compare(ost, odbg, f"{name} round {r}")
+
+
+# ------------------------------------------------------------ driver --
+
+@pytest.mark.parametrize("case", [("cl", 8), ("rgg", 16), ("rmat", 8), ("cl_w", 4)])
+def test_driver_parity(upr, ctx, case):
+    """The refinement driver (label propagation with rollback and active
+    sets, then FM rounds with the tau schedule and the switch to constrained
+    rounds): every round's statistics, its kind and the final partition,
+    table and block weights equal the oracle driver's."""
+    import torch
+    from oracle import driver as D
+    name, k = case
+    g = {"cl": lambda: gg.chung_lu(3000, 8.0, 2.3, seed=5),
+         "rgg": lambda: gg.rgg2d(3000, seed=6),
+         "rmat": lambda: gg.rmat(11, 16, seed=7),
+         "cl_w": lambda: gg.with_weights(gg.chung_lu(2000, 8.0, 2.2, seed=8), 8, wmax=9, vmax=3)}[name]()
+    for start in (gg.random_partition(g.n, k, 1), skewed_partition(g.n, k, 2, 0.3)):
+        say(f"driver case={name} n={g.n} k={k}")
+        opart = start.copy()
+        olog = D.refine(g, k, opart)
+        dg = upr.DeviceGraph(g)
+        plan = upr.Plan(ctx, dg)
+        part = to_dev(start)
+        conn = torch.zeros(g.n * k, dtype=torch.int32, device="cuda")
+        W = torch.zeros(k, dtype=torch.int64, device="cuda")
+        glog = upr.refine(ctx, plan, upr.driver(k), part, conn, W)
+        assert [x[0] for x in glog] == [x[1] for x in olog], "round kinds"
+        for i, ((gk, gst), (_, ok, ost)) in enumerate(zip(glog, olog)):
+            assert O.stats_dict(gst) == O.stats_dict(ost), f"round {i} ({gk}) stats"
+        torch.cuda.synchronize()
+        assert np.array_equal(part.cpu().numpy(), opart)
+        assert np.array_equal(conn.cpu().numpy().reshape(g.n, k), O.gain_table(g, k, opart))
+        assert np.array_equal(W.cpu().numpy(), O.block_weights(g, k, opart))
