@@ -170,9 +170,12 @@ def batched_vs_plain(ctx, spec, eps=(3, 100), rounds=10):
         groups.setdefault(k, []).append(i)
     batches = {k: upr.Batch(ctx, [refs[i].dg for i in idx], k, eps) for k, idx in groups.items()}
 
-    def reset():
+    def reset_plain():
         for r, (g, k, seed) in zip(refs, spec):
             r.set_partition(gg.random_partition(g.n, k, seed))
+        torch.cuda.synchronize()
+
+    def reset_batched():
         for k, idx in groups.items():
             batches[k].set_partitions([gg.random_partition(spec[i][0].n, k, spec[i][2]) for i in idx])
         torch.cuda.synchronize()
@@ -188,7 +191,8 @@ def batched_vs_plain(ctx, spec, eps=(3, 100), rounds=10):
                 b.round(upr.params(k, eps, tau=gg.tau_schedule(i, rounds)))
 
     out = {}
-    for name, fn in (("plain", run_plain), ("batched", run_batched)):
+    for name, fn, reset in (("plain", run_plain, reset_plain),
+                            ("batched", run_batched, reset_batched)):
         reset()
         fn()  # warm-up pass (workspace sizes, code paths)
         reset()
@@ -234,9 +238,11 @@ def serving(ctx, spec, eps=(3, 100), rounds=10, load=0.7, budget_gb=200.0, check
     arr = serve.poisson_arrivals(len(spec), rate, seed)
     reqs = [serve.Request(j, g, k, eps, rounds=rounds, arrival=float(arr[j]), part_seed=s)
             for j, (g, k, s) in enumerate(spec)]
+    srv.timings = {}
     t0 = time.perf_counter()
     res = srv.run(reqs)
     span = time.perf_counter() - t0
+    tim = {k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in srv.timings.items()}
     lat = [r.latency for r in res]
     same = True
     for r in res[:check]:
@@ -247,7 +253,8 @@ def serving(ctx, spec, eps=(3, 100), rounds=10, load=0.7, budget_gb=200.0, check
             "p50_latency_ms": 1e3 * float(np.percentile(lat, 50)),
             "p99_latency_ms": 1e3 * float(np.percentile(lat, 99)),
             "mean_latency_ms": 1e3 * float(np.mean(lat)),
-            "budget_gb": budget_gb, "same_as_alone_checked": check, "same_as_alone": same}
+            "budget_gb": budget_gb, "same_as_alone_checked": check, "same_as_alone": same,
+            "server_time_s": tim}
 
 
 def main():

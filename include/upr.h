@@ -108,7 +108,9 @@ enum {
     UPR_STATS_LEN = 12
 };
 
-/* Context: owns the device workspace on one device. Returns UPR_OK or a code. */
+/* Context: owns the device workspace on one device. Returns UPR_OK or a code.
+ * A context serves one call at a time (its workspace is shared by the calls);
+ * use one context per host thread or stream for concurrent work. */
 int upr_create(upr_ctx **out, int device);
 void upr_destroy(upr_ctx *ctx);
 /* Message for the last nonzero return on this context (never NULL). */
@@ -196,10 +198,16 @@ int upr_last_moves(upr_ctx *ctx, int64_t n, int32_t *target, int64_t *score, int
  * graph's results are exactly those of upr_refine_round on it alone.
  * upr_batch_create copies the graphs into the union (the inputs may be
  * freed afterwards) and plans it; it validates like upr_plan_create, plus
- * that every graph names only its own nodes. Enqueued on `stream` and
- * synchronised. ng * k <= UPR_MAX_BATCH_BLOCKS. */
-int upr_batch_create(upr_ctx *ctx, const upr_graph *graphs, int32_t ng, int32_t k,
-                     int32_t eps_num, int32_t eps_den, upr_batch **out, hipStream_t stream);
+ * that every graph names only its own nodes (unless trusted, below).
+ * Enqueued on `stream` and synchronised. ng * k <= UPR_MAX_BATCH_BLOCKS. */
+int upr_batch_create(upr_ctx *ctx, const upr_graph *graphs, const int64_t *nnz, int32_t ng,
+                     int32_t k, int32_t eps_num, int32_t eps_den, int32_t flags, upr_batch **out,
+                     hipStream_t stream);
+/* upr_batch_create arguments: nnz, a host array [ng] of each graph's xadj[n]
+ * (or NULL to read them from the device); flags: 0, or UPR_BATCH_TRUSTED when
+ * every graph has passed upr_validate_graph or an earlier batch (a server
+ * rebuilding batches of admitted graphs): the checks are skipped. */
+#define UPR_BATCH_TRUSTED 1
 void upr_batch_destroy(upr_batch *batch);
 /* Union size, node offsets off[ng + 1] and L_max[ng] (any pointer may be NULL). */
 int upr_batch_info(const upr_batch *batch, int64_t *n_total, int64_t *nnz_total, int64_t *node_off,

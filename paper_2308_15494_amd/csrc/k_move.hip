@@ -42,7 +42,7 @@ __global__ void k_round_init(Blocks bk, int64_t *bucket, int64_t *W, PenTable pq
             ((int64_t *)bk.src_lmax)[0] = lmax;
         }
     }
-    if (tid < CNT_COUNT) counters[tid] = 0;
+    for (int64_t i = tid; i < kCntWords; i += stride) counters[i] = 0;
 }
 
 hipError_t launch_round_init(const Blocks &bk, int64_t *bucket, int64_t *W, const PenTable &pq,
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_best_move(
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0 && cand_lds) atomicAdd(&counters[CNT_CAND], cand_lds);
+    if (threadIdx.x == 0 && cand_lds) cnt_add(counters, CNT_CAND, cand_lds);
 }
 
 hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t *part,
@@ -386,8 +386,8 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int o
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        if (acc_lds) atomicAdd(&counters[CNT_ACC], acc_lds);
-        if (deg_lds) atomicAdd(&counters[CNT_MOVED_DEG], deg_lds);
+        if (acc_lds) cnt_add(counters, CNT_ACC, acc_lds);
+        if (deg_lds) cnt_add(counters, CNT_MOVED_DEG, deg_lds);
     }
 }
 
@@ -442,7 +442,7 @@ __global__ void k_filter_hub_final(Blocks bk, const int32_t *part, const int64_t
     accflag[v] = ok ? 1 : 0;
     if (ok) {
         mvto[v] = bk.base(part[v]) + (int32_t)(kv & 0xFFFF);
-        atomicAdd(&counters[CNT_ACC], 1ull);
+        cnt_add(counters, CNT_ACC, 1ull);
     }
 }
 
@@ -452,7 +452,7 @@ __global__ void k_hub_moved_deg(GraphView g, const int32_t *mvto, HubView h,
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= h.nh) return;
     const int64_t v = h.ids[i];
-    if (mvto[v] >= 0) atomicAdd(&counters[CNT_MOVED_DEG], (unsigned long long)(g.xadj[v + 1] - g.xadj[v]));
+    if (mvto[v] >= 0) cnt_add(counters, CNT_MOVED_DEG, (unsigned long long)(g.xadj[v + 1] - g.xadj[v]));
 }
 
 hipError_t launch_filter_hub(const GraphView &g, const Blocks &bk, int optimistic,
@@ -527,8 +527,8 @@ __global__ __launch_bounds__(kBlock) void k_filter_seq(
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        if (acc_lds) atomicAdd(&counters[CNT_ACC], acc_lds);
-        if (deg_lds) atomicAdd(&counters[CNT_MOVED_DEG], deg_lds);
+        if (acc_lds) cnt_add(counters, CNT_ACC, acc_lds);
+        if (deg_lds) cnt_add(counters, CNT_MOVED_DEG, deg_lds);
     }
 }
 
@@ -625,7 +625,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, Blocks bk, int32_
                                                    int T)
 {
     uint8_t *dirty =
-        (int64_t)counters[CNT_MOVED_DEG] > dirty_threshold ? dirty_flags : (uint8_t *)nullptr;
+        (int64_t)cnt_get(counters, CNT_MOVED_DEG) > dirty_threshold ? dirty_flags : (uint8_t *)nullptr;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     int64_t *wloc = (int64_t *)lds_raw;
     const int32_t K = bk.total();
@@ -669,7 +669,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_hub(GraphView g, Blocks bk, co
     const int64_t v = h.ids[c.hub];
     const int32_t B = mvto[v];
     if (B < 0) return;
-    if ((int64_t)counters[CNT_MOVED_DEG] > dirty_threshold) {
+    if ((int64_t)cnt_get(counters, CNT_MOVED_DEG) > dirty_threshold) {
         for (int64_t e = c.e0 + threadIdx.x; e < c.e1; e += kBlock) dirty[g.adjncy[e] / T] = 1;
         return;
     }
@@ -740,15 +740,27 @@ __global__ void k_stats_final(int64_t *stats, const unsigned long long *c, int64
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     stats[0] = lmax;
-    stats[1] = (int64_t)c[CNT_CUT2_BEFORE] / 2;
-    stats[2] = (int64_t)c[CNT_CUT2_MOVES] / 2;
-    stats[3] = (int64_t)c[CNT_CUT2_AFTER] / 2;
-    stats[4] = (int64_t)c[CNT_CAND];
-    stats[5] = (int64_t)c[CNT_ACC];
-    stats[6] = (int64_t)c[CNT_REBAL_MOVES];
+    stats[1] = (int64_t)cnt_get(c, CNT_CUT2_BEFORE) / 2;
+    stats[2] = (int64_t)cnt_get(c, CNT_CUT2_MOVES) / 2;
+    stats[3] = (int64_t)cnt_get(c, CNT_CUT2_AFTER) / 2;
+    stats[4] = (int64_t)cnt_get(c, CNT_CAND);
+    stats[5] = (int64_t)cnt_get(c, CNT_ACC);
+    stats[6] = (int64_t)cnt_get(c, CNT_REBAL_MOVES);
     stats[7] = iters;
     stats[8] = status;
     for (int i = 9; i < 12; ++i) stats[i] = 0;
+}
+
+// dst = src (summed over the copies) for a spread counter.
+__global__ void k_cnt_copy(unsigned long long *c, int dst, int src)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) cnt_set(c, dst, cnt_get(c, src));
+}
+
+hipError_t launch_cnt_copy(unsigned long long *counters, int dst, int src, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cnt_copy, dim3(1), dim3(64), 0, s, counters, dst, src);
+    return hipGetLastError();
 }
 
 hipError_t launch_stats_final(int64_t *stats, const unsigned long long *counters, int64_t lmax,

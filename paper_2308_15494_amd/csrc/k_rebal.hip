@@ -84,7 +84,7 @@ __global__ void k_rb_begin(Blocks bk, const int64_t *W, int64_t *W0, unsigned lo
         if (gstat && o) atomic_add_i64(&gstat[(int64_t)bk.graph(j) * GS_COUNT + GS_OVER], 1);
     }
     over = block_sum(over, red);
-    if (threadIdx.x == 0) counters[CNT_OVER] = over;
+    if (threadIdx.x == 0) cnt_set(counters, CNT_OVER, over);
 }
 
 hipError_t launch_rb_begin(const Blocks &bk, const int64_t *W, const RebalWs &r,
@@ -237,8 +237,8 @@ __global__ __launch_bounds__(kBlock) void k_rb_cutoffs(Blocks bk, RebalWs r, int
     const int j = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int lane = lane_id();
     if (target_side && j == 0 && lane == 0) {
-        counters[CNT_MOVED_NOW] = 0;
-        counters[CNT_MOVED_DEG] = 0;
+        cnt_set(counters, CNT_MOVED_NOW, 0);
+        cnt_set(counters, CNT_MOVED_DEG, 0);
     }
     if (j >= bk.total()) return;  // wave-uniform
     if (target_side && gstat && lane == 0 && bk.local(j) == 0)
@@ -493,15 +493,17 @@ __global__ __launch_bounds__(kBlock) void k_rb_moves(GraphView g, Blocks bk, con
     }
     __syncthreads();
     if (threadIdx.x == 0 && moved) {
-        atomicAdd(&counters[CNT_MOVED_NOW], moved);
-        atomicAdd(&counters[CNT_REBAL_MOVES], moved);
-        atomicAdd(&counters[CNT_MOVED_DEG], mdeg);
+        cnt_add(counters, CNT_MOVED_NOW, moved);
+        cnt_add(counters, CNT_REBAL_MOVES, moved);
+        cnt_add(counters, CNT_MOVED_DEG, mdeg);
     }
 }
 
 // --------------------------------------------------------------- sequence --
 
-int rb_scan_grid(int64_t n) { return grid_cap(n, kBlock, 4096); }
+// Node scans of the rebalancer: few enough workgroups that the per-workgroup
+// histogram flushes do not pile up on the same addresses.
+int rb_scan_grid(int64_t n) { return grid_cap(n, kBlock, 1024); }
 
 hipError_t launch_rb_iteration(const GraphView &g, const Blocks &bk, const int32_t *part,
                                const int32_t *conn, const RebalWs &r, int32_t *mvto, int hist32,

@@ -105,7 +105,7 @@ hipError_t launch_plan_scan(const GraphView &g, int32_t *wdeg, int64_t hub_t, in
                             unsigned long long *counters, hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_plan_scan, dim3(grid_for(g.n, kBlock / 64, 16384)), dim3(kBlock), 0, s, g,
+    hipLaunchKernelGGL(k_plan_scan, dim3(grid_for(g.n, kBlock / 64, 2048)), dim3(kBlock), 0, s, g,
                        wdeg, hub_t, hub_list, counters);
     return hipGetLastError();
 }
@@ -450,7 +450,7 @@ __global__ __launch_bounds__(kBlock) void k_block_weights(GraphView g, int32_t k
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += stride) {
         const int32_t a = part[v];
         if ((unsigned)a >= (unsigned)k) {
-            atomicAdd(&counters[CNT_BAD_INPUT], 1ull);
+            cnt_add(counters, CNT_BAD_INPUT, 1ull);
             continue;
         }
         const int64_t c = node_weight(g, v);
@@ -552,8 +552,8 @@ __global__ __launch_bounds__(kBlock) void k_node_stats(GraphView g, Blocks bk,
     }
     s = block_sum(s, red);
     if (threadIdx.x == 0) {
-        if (s) atomicAdd(&counters[cut_slot], s);
-        if (bad) atomicAdd(&counters[CNT_BAD_INPUT], bad);
+        if (s) cnt_add(counters, cut_slot, s);
+        if (bad) cnt_add(counters, CNT_BAD_INPUT, bad);
     }
     if (w_lds)
         for (int j = threadIdx.x; j < K; j += kBlock)
@@ -580,14 +580,15 @@ hipError_t launch_node_stats(const GraphView &g, const Blocks &bk, const int32_t
     return hipGetLastError();
 }
 
-__global__ void k_store_half(const unsigned long long *acc, int64_t *out)
+__global__ void k_store_half(const unsigned long long *counters, int slot, int64_t *out)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = (int64_t)(*acc / 2);
+    if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = (int64_t)(cnt_get(counters, slot) / 2);
 }
 
-hipError_t launch_store_half(const unsigned long long *acc, int64_t *out, hipStream_t s)
+hipError_t launch_store_half(const unsigned long long *counters, int slot, int64_t *out,
+                             hipStream_t s)
 {
-    hipLaunchKernelGGL(k_store_half, dim3(1), dim3(64), 0, s, acc, out);
+    hipLaunchKernelGGL(k_store_half, dim3(1), dim3(64), 0, s, counters, slot, out);
     return hipGetLastError();
 }
 
@@ -613,7 +614,7 @@ hipError_t launch_hub_ranges(const int64_t *xadj, const int32_t *ids, int32_t nh
 // node, lanes over the row.
 __global__ __launch_bounds__(kBlock) void k_cut_edges(GraphView g,
                                                        const int32_t *__restrict__ part,
-                                                       unsigned long long *acc)
+                                                       unsigned long long *counters, int slot)
 {
     __shared__ unsigned long long red[4];
     const int lane = lane_id();
@@ -625,15 +626,15 @@ __global__ __launch_bounds__(kBlock) void k_cut_edges(GraphView g,
             if (part[g.adjncy[e]] != a) s += (unsigned long long)edge_weight(g, e);
     }
     s = block_sum(s, red);
-    if (threadIdx.x == 0 && s) atomicAdd(acc, s);
+    if (threadIdx.x == 0 && s) cnt_add(counters, slot, s);
 }
 
-hipError_t launch_cut_edges(const GraphView &g, const int32_t *part, unsigned long long *acc,
-                            hipStream_t s)
+hipError_t launch_cut_edges(const GraphView &g, const int32_t *part, unsigned long long *counters,
+                            int slot, hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_cut_edges, dim3(grid_for(g.n, kBlock / 64, 16384)), dim3(kBlock), 0, s, g,
-                       part, acc);
+                       part, counters, slot);
     return hipGetLastError();
 }
 
@@ -664,7 +665,7 @@ __global__ void k_pack_part(int64_t n, Blocks bk, const int64_t *goff, const int
         if (goff && bk.graph(B) != graph_of_node(goff, bk.ng, v)) bad = true;
         pset(pc, bytes, v, bk.local(B));
     }
-    if (__ballot(bad) && lane_id() == 0) atomicAdd(&counters[CNT_BAD_INPUT], 1ull);
+    if (__ballot(bad) && lane_id() == 0) cnt_add(counters, CNT_BAD_INPUT, 1ull);
 }
 
 hipError_t launch_pack_part(int64_t n, const Blocks &bk, const int64_t *goff, const int32_t *part,
@@ -682,7 +683,7 @@ __global__ void k_check_part(int64_t n, int32_t k, const int32_t *part, unsigned
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
         bad |= (unsigned)part[v] >= (unsigned)k;
-    if (__ballot(bad) && lane_id() == 0) atomicAdd(&counters[CNT_BAD_INPUT], 1ull);
+    if (__ballot(bad) && lane_id() == 0) cnt_add(counters, CNT_BAD_INPUT, 1ull);
 }
 
 hipError_t launch_check_part(int64_t n, int32_t k, const int32_t *part,

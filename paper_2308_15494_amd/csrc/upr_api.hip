@@ -72,7 +72,12 @@ struct upr_ctx {
     unsigned long long *counters = nullptr;
     unsigned long long *flags = nullptr;  // validation flags [4]
     RebalWs rb{};
-    unsigned long long *pinned = nullptr;  // host mirror of counters
+    unsigned long long *pinned = nullptr;  // host mirror of the counters' copies
+    unsigned long long cnt[CNT_COUNT] = {0};  // their sums, after sync_counters
+    // pinned host area of the batches run on this context (grown on demand;
+    // pinned allocations are slow, and batches are rebuilt often by a server)
+    int64_t *bpinned = nullptr;
+    int64_t bpinned_cap = 0;  // int64 entries
     bool rb_dirty = false;
     Timing timing;
 };
@@ -114,7 +119,7 @@ struct upr_batch {
     // statistics [ng][GS_COUNT], per-graph rebalancing results [ng][3]
     int64_t *goff_d = nullptr, *lmax_d = nullptr, *srcl_d = nullptr, *penq_d = nullptr;
     int64_t *gstat_d = nullptr, *host3_d = nullptr;
-    // pinned mirrors
+    // pinned mirrors (in the context's batch area, valid while the batch runs)
     int64_t *gstat_h = nullptr, *srcl_h = nullptr, *penq_h = nullptr, *host3_h = nullptr;
 };
 
@@ -319,12 +324,22 @@ int check_plan(upr_ctx *c, const upr_plan *p)
     return UPR_OK;
 }
 
-// Copy the counters to the pinned mirror and wait.
+void sum_counters(upr_ctx *c)
+{
+    for (int j = 0; j < CNT_COUNT; ++j) {
+        unsigned long long t = 0;
+        for (int i = 0; i < kCntCopies; ++i) t += c->pinned[i * CNT_COUNT + j];
+        c->cnt[j] = t;
+    }
+}
+
+// Copy the counters to the pinned mirror, wait, and sum the copies.
 int sync_counters(upr_ctx *c, hipStream_t s)
 {
-    HIP_TRY(c, hipMemcpyAsync(c->pinned, c->counters, sizeof(unsigned long long) * CNT_COUNT,
+    HIP_TRY(c, hipMemcpyAsync(c->pinned, c->counters, sizeof(unsigned long long) * kCntWords,
                               hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
+    sum_counters(c);
     return UPR_OK;
 }
 
@@ -355,10 +370,10 @@ int rebalance_loop(upr_ctx *c, const upr_plan *p, const Blocks &bk, int plain, i
     HIP_TRY(c, launch_rb_begin(bk, W, c->rb, c->counters, nullptr, s));
     int rc = sync_counters(c, s);
     if (rc) return rc;
-    if (c->pinned[CNT_BAD_INPUT]) return fail(c, UPR_E_ARG, "part holds values outside [0, k)");
+    if (c->cnt[CNT_BAD_INPUT]) return fail(c, UPR_E_ARG, "part holds values outside [0, k)");
     for (;;) {
-        if (c->pinned[CNT_OVER] == 0) break;
-        if (iters > 0 && c->pinned[CNT_MOVED_NOW] == 0) {
+        if (c->cnt[CNT_OVER] == 0) break;
+        if (iters > 0 && c->cnt[CNT_MOVED_NOW] == 0) {
             status = 1;
             break;
         }
@@ -381,14 +396,40 @@ int rebalance_loop(upr_ctx *c, const upr_plan *p, const Blocks &bk, int plain, i
     return UPR_OK;
 }
 
+// Point a batch's host mirrors into the context's pinned area, growing it.
+int bind_batch_pinned(upr_ctx *c, upr_batch *b)
+{
+    const int64_t need = (int64_t)b->ng * (GS_COUNT + 1 + kSlots + 3);
+    if (need > c->bpinned_cap) {
+        if (c->bpinned) {
+            (void)hipDeviceSynchronize();
+            (void)hipHostFree(c->bpinned);
+        }
+        c->bpinned = nullptr;
+        c->bpinned_cap = 0;
+        const int64_t cap = std::max<int64_t>(need, 4096);
+        if (hipHostMalloc((void **)&c->bpinned, sizeof(int64_t) * cap) != hipSuccess) {
+            (void)hipGetLastError();
+            return UPR_E_NOMEM;
+        }
+        c->bpinned_cap = cap;
+    }
+    b->gstat_h = c->bpinned;
+    b->srcl_h = b->gstat_h + (int64_t)b->ng * GS_COUNT;
+    b->penq_h = b->srcl_h + b->ng;
+    b->host3_h = b->penq_h + (int64_t)b->ng * kSlots;
+    return UPR_OK;
+}
+
 // Counters and per-graph statistics to the pinned mirrors, then wait.
 int sync_batch(upr_ctx *c, const upr_batch *b, hipStream_t s)
 {
-    HIP_TRY(c, hipMemcpyAsync(c->pinned, c->counters, sizeof(unsigned long long) * CNT_COUNT,
+    HIP_TRY(c, hipMemcpyAsync(c->pinned, c->counters, sizeof(unsigned long long) * kCntWords,
                               hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipMemcpyAsync(b->gstat_h, b->gstat_d, sizeof(int64_t) * GS_COUNT * b->ng,
                               hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
+    sum_counters(c);
     return UPR_OK;
 }
 
@@ -408,7 +449,7 @@ int rebalance_loop_batch(upr_ctx *c, const upr_plan *p, upr_batch *b, const Bloc
     HIP_TRY(c, launch_rb_begin(bk, W, c->rb, c->counters, b->gstat_d, s));
     int rc = sync_batch(c, b, s);
     if (rc) return rc;
-    if (c->pinned[CNT_BAD_INPUT]) return fail(c, UPR_E_ARG, "part holds a block outside its graph's range");
+    if (c->cnt[CNT_BAD_INPUT]) return fail(c, UPR_E_ARG, "part holds a block outside its graph's range");
     std::vector<int64_t> iters(ng, 0), status(ng, 0), moves(ng, 0);
     std::vector<uint8_t> active(ng, 1);
     for (;;) {
@@ -498,17 +539,17 @@ int upr_create(upr_ctx **out, int device)
     upr_ctx *c = new upr_ctx();
     c->device = device;
     if (hipSetDevice(device) != hipSuccess ||
-        hipMalloc((void **)&c->counters, sizeof(unsigned long long) * CNT_COUNT) != hipSuccess ||
+        hipMalloc((void **)&c->counters, sizeof(unsigned long long) * kCntWords) != hipSuccess ||
         hipMalloc((void **)&c->flags, sizeof(unsigned long long) * 8) != hipSuccess ||
         hipMalloc((void **)&c->penq, sizeof(int64_t) * kSlots) != hipSuccess ||
         hipMalloc((void **)&c->lmax1, sizeof(int64_t)) != hipSuccess ||
         hipMalloc((void **)&c->srcl1, sizeof(int64_t)) != hipSuccess ||
-        hipHostMalloc((void **)&c->pinned, sizeof(unsigned long long) * CNT_COUNT) != hipSuccess) {
+        hipHostMalloc((void **)&c->pinned, sizeof(unsigned long long) * kCntWords) != hipSuccess) {
         (void)hipGetLastError();
         upr_destroy(c);
         return UPR_E_NOMEM;
     }
-    (void)hipMemset(c->counters, 0, sizeof(unsigned long long) * CNT_COUNT);
+    (void)hipMemset(c->counters, 0, sizeof(unsigned long long) * kCntWords);
     *out = c;
     return UPR_OK;
 }
@@ -525,6 +566,7 @@ void upr_destroy(upr_ctx *c)
     dfree(c->lmax1);
     dfree(c->srcl1);
     if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->bpinned) (void)hipHostFree(c->bpinned);
     for (auto &p : c->timing.pending) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
@@ -580,7 +622,18 @@ int upr_validate_graph(upr_ctx *c, const upr_graph *graph, hipStream_t s)
     return UPR_OK;
 }
 
+static int plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipStream_t s,
+                       bool validate, int64_t known_nnz);
+
 int upr_plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipStream_t s)
+{
+    return plan_create(c, graph, out, s, true, -1);
+}
+
+// validate = false: the caller has checked the graph already (a batch of
+// graphs validated before); known_nnz >= 0: xadj[n], known on the host.
+static int plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipStream_t s,
+                       bool validate, int64_t known_nnz)
 {
     if (!c) return UPR_E_ARG;
     if (!out) return fail(c, UPR_E_ARG, "out is NULL");
@@ -590,7 +643,7 @@ int upr_plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipStrea
     if (graph->n > 0 && !graph->xadj) return fail(c, UPR_E_ARG, "xadj NULL");
     HIP_TRY(c, hipSetDevice(c->device));
     const GraphView g{graph->n, graph->xadj, graph->adjncy, graph->adjwgt, graph->vwgt};
-    if (g.n > 0) {
+    if (g.n > 0 && known_nnz < 0) {
         int64_t nnz = 0;
         HIP_TRY(c, hipMemcpy(&nnz, g.xadj + g.n, sizeof nnz, hipMemcpyDeviceToHost));
         if (nnz < 0) return fail(c, UPR_E_GRAPH, "xadj[n] < 0");
@@ -598,7 +651,7 @@ int upr_plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipStrea
     }
 
     // basic validation: xadj, ids in range, positive weights (kernels rely on it)
-    if (g.n > 0) {
+    if (g.n > 0 && validate) {
         unsigned long long init[4] = {~0ull, ~0ull, ~0ull, ~0ull}, got[4];
         for (int stage = 0; stage < 2; ++stage) {
             HIP_TRY(c, hipMemcpyAsync(c->flags, init, sizeof init, hipMemcpyHostToDevice, s));
@@ -628,7 +681,8 @@ int upr_plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipStrea
         return fail(c, code, "%s", msg);
     };
     if (g.n > 0) {
-        if (hipMemcpy(&p->nnz, g.xadj + g.n, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
+        if (known_nnz >= 0) p->nnz = known_nnz;
+        else if (hipMemcpy(&p->nnz, g.xadj + g.n, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
             return bail(UPR_E_HIP, "reading xadj[n] failed");
         // integer-atomic deltas cost about as much per moved edge as a
         // rebuild costs per edge of the whole graph divided by this factor
@@ -723,11 +777,11 @@ int upr_gain_table(upr_ctx *c, const upr_plan *p, int32_t k, const int32_t *part
     if (k < 2 || k > UPR_MAX_K) return fail(c, UPR_E_ARG, "k=%d outside [2, %d]", k, UPR_MAX_K);
     if (p->g.n > 0 && (!part || !conn)) return fail(c, UPR_E_ARG, "part/conn NULL");
     HIP_TRY(c, hipSetDevice(c->device));
-    HIP_TRY(c, hipMemsetAsync(c->counters, 0, sizeof(unsigned long long) * CNT_COUNT, s));
+    HIP_TRY(c, hipMemsetAsync(c->counters, 0, sizeof(unsigned long long) * kCntWords, s));
     HIP_TRY(c, launch_check_part(p->g.n, k, part, c->counters, s));
     rc = sync_counters(c, s);
     if (rc) return rc;
-    if (c->pinned[CNT_BAD_INPUT]) return fail(c, UPR_E_ARG, "part holds values outside [0, k)");
+    if (c->cnt[CNT_BAD_INPUT]) return fail(c, UPR_E_ARG, "part holds values outside [0, k)");
     PhaseTimer t(c, 0, s);
     const PartView pv{part, 4};
     HIP_TRY(c, launch_gain_tile(p->g, k, pv, conn, p->hub_t, nullptr, s));
@@ -743,11 +797,11 @@ int upr_block_weights(upr_ctx *c, const upr_plan *p, int32_t k, const int32_t *p
     if (k < 2 || k > UPR_MAX_K) return fail(c, UPR_E_ARG, "k=%d outside [2, %d]", k, UPR_MAX_K);
     if (!W || (p->g.n > 0 && !part)) return fail(c, UPR_E_ARG, "part/block_w NULL");
     HIP_TRY(c, hipSetDevice(c->device));
-    HIP_TRY(c, hipMemsetAsync(c->counters, 0, sizeof(unsigned long long) * CNT_COUNT, s));
+    HIP_TRY(c, hipMemsetAsync(c->counters, 0, sizeof(unsigned long long) * kCntWords, s));
     HIP_TRY(c, launch_check_part(p->g.n, k, part, c->counters, s));
     rc = sync_counters(c, s);
     if (rc) return rc;
-    if (c->pinned[CNT_BAD_INPUT]) return fail(c, UPR_E_ARG, "part holds values outside [0, k)");
+    if (c->cnt[CNT_BAD_INPUT]) return fail(c, UPR_E_ARG, "part holds values outside [0, k)");
     HIP_TRY(c, launch_fill_i64(W, k, 0, s));
     HIP_TRY(c, launch_block_weights(p->g, k, part, W, c->counters, s));
     return UPR_OK;
@@ -760,9 +814,9 @@ int upr_edge_cut(upr_ctx *c, const upr_plan *p, const int32_t *part, int64_t *cu
     if (!cut || (p->g.n > 0 && !part)) return fail(c, UPR_E_ARG, "part/cut NULL");
     HIP_TRY(c, hipSetDevice(c->device));
     PhaseTimer t(c, 6, s);
-    HIP_TRY(c, hipMemsetAsync(c->counters + CNT_TMP, 0, sizeof(unsigned long long), s));
-    HIP_TRY(c, launch_cut_edges(p->g, part, c->counters + CNT_TMP, s));
-    HIP_TRY(c, launch_store_half(c->counters + CNT_TMP, cut, s));
+    HIP_TRY(c, hipMemsetAsync(c->counters, 0, sizeof(unsigned long long) * kCntWords, s));
+    HIP_TRY(c, launch_cut_edges(p->g, part, c->counters, CNT_TMP, s));
+    HIP_TRY(c, launch_store_half(c->counters, CNT_TMP, cut, s));
     return UPR_OK;
 }
 
@@ -844,10 +898,10 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
         // one host decision: are there candidates at all (also reports bad input)
         rc = sync_counters(c, s);
         if (rc) return rc;
-        if (c->pinned[CNT_BAD_INPUT])
+        if (c->cnt[CNT_BAD_INPUT])
             return fail(c, UPR_E_ARG, b ? "part holds a block outside its graph's range"
                                         : "part holds values outside [0, k)");
-        const int64_t nc = (int64_t)c->pinned[CNT_CAND];
+        const int64_t nc = (int64_t)c->cnt[CNT_CAND];
         if (nc > 0) {
             moved = true;
             {
@@ -864,7 +918,7 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
                                                  c->seq_temp_size, s));
                     rc = sync_counters(c, s);
                     if (rc) return rc;
-                    const int64_t ne = (int64_t)c->pinned[CNT_ELIG];
+                    const int64_t ne = (int64_t)c->cnt[CNT_ELIG];
                     HIP_TRY(c, launch_seq_net(ne, c->cand, c->key, part, p->g.vwgt, c->avail, bk,
                                               seq_score_bits(p->maxwdeg), c->ev_key, c->ev_key2,
                                               c->ev_val, c->ev_val2, c->ev_prefix, c->netpre,
@@ -887,8 +941,7 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
                                              GS_CUT2_MOVES, s));
             }
         } else if (!b) {
-            HIP_TRY(c, hipMemcpyAsync(c->counters + CNT_CUT2_MOVES, c->counters + CNT_CUT2_BEFORE,
-                                      sizeof(unsigned long long), hipMemcpyDeviceToDevice, s));
+            HIP_TRY(c, launch_cnt_copy(c->counters, CNT_CUT2_MOVES, CNT_CUT2_BEFORE, s));
         }
     }
     int64_t iters = 0, status = 0;
@@ -916,8 +969,7 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
     }
     if (!moves) {
         // standalone rebalancing: nothing moved before it
-        HIP_TRY(c, hipMemcpyAsync(c->counters + CNT_CUT2_MOVES, c->counters + CNT_CUT2_BEFORE,
-                                  sizeof(unsigned long long), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(c, launch_cnt_copy(c->counters, CNT_CUT2_MOVES, CNT_CUT2_BEFORE, s));
     }
     HIP_TRY(c, launch_stats_final(stats, c->counters, lmax, iters, status, s));
     return UPR_OK;
@@ -965,13 +1017,12 @@ void upr_batch_destroy(upr_batch *b)
     dfree(b->penq_d);
     dfree(b->gstat_d);
     dfree(b->host3_d);
-    for (int64_t *h : {b->gstat_h, b->srcl_h, b->penq_h, b->host3_h})
-        if (h) (void)hipHostFree(h);
     delete b;
 }
 
-int upr_batch_create(upr_ctx *c, const upr_graph *graphs, int32_t ng, int32_t k, int32_t eps_num,
-                     int32_t eps_den, upr_batch **out, hipStream_t s)
+int upr_batch_create(upr_ctx *c, const upr_graph *graphs, const int64_t *nnz_host, int32_t ng,
+                     int32_t k, int32_t eps_num, int32_t eps_den, int32_t flags, upr_batch **out,
+                     hipStream_t s)
 {
     if (!c) return UPR_E_ARG;
     if (!out) return fail(c, UPR_E_ARG, "out is NULL");
@@ -982,6 +1033,8 @@ int upr_batch_create(upr_ctx *c, const upr_graph *graphs, int32_t ng, int32_t k,
         return fail(c, UPR_E_ARG, "ng*k = %lld blocks exceeds %d", (long long)ng * k,
                     UPR_MAX_BATCH_BLOCKS);
     if (eps_num <= 0 || eps_den <= 0) return fail(c, UPR_E_ARG, "eps must be > 0");
+    if (flags & ~UPR_BATCH_TRUSTED) return fail(c, UPR_E_ARG, "unknown batch flags 0x%x", flags);
+    const bool trusted = (flags & UPR_BATCH_TRUSTED) != 0;
     HIP_TRY(c, hipSetDevice(c->device));
     upr_batch *b = new upr_batch();
     b->ctx = c;
@@ -1002,7 +1055,8 @@ int upr_batch_create(upr_ctx *c, const upr_graph *graphs, int32_t ng, int32_t k,
         const upr_graph &G = graphs[g];
         if (G.n < 0 || (G.n > 0 && !G.xadj)) return bail(UPR_E_ARG, "a graph has n < 0 or xadj NULL");
         int64_t nnz = 0;
-        if (G.n > 0 && hipMemcpy(&nnz, G.xadj + G.n, sizeof nnz, hipMemcpyDeviceToHost) != hipSuccess)
+        if (nnz_host) nnz = G.n > 0 ? nnz_host[g] : 0;
+        else if (G.n > 0 && hipMemcpy(&nnz, G.xadj + G.n, sizeof nnz, hipMemcpyDeviceToHost) != hipSuccess)
             return bail(UPR_E_HIP, "reading xadj[n] failed");
         if (nnz < 0 || (nnz > 0 && !G.adjncy)) return bail(UPR_E_GRAPH, "a graph has xadj[n] < 0 or adjncy NULL");
         b->off[g + 1] = b->off[g] + G.n;
@@ -1024,30 +1078,28 @@ int upr_batch_create(upr_ctx *c, const upr_graph *graphs, int32_t ng, int32_t k,
         dalloc(&b->gstat_d, (int64_t)ng * GS_COUNT) != hipSuccess ||
         dalloc(&b->host3_d, 3 * (int64_t)ng) != hipSuccess)
         return bail(UPR_E_NOMEM, "batch allocation failed");
-    if (hipHostMalloc((void **)&b->gstat_h, sizeof(int64_t) * GS_COUNT * ng) != hipSuccess ||
-        hipHostMalloc((void **)&b->srcl_h, sizeof(int64_t) * ng) != hipSuccess ||
-        hipHostMalloc((void **)&b->penq_h, sizeof(int64_t) * kSlots * ng) != hipSuccess ||
-        hipHostMalloc((void **)&b->host3_h, sizeof(int64_t) * 3 * ng) != hipSuccess)
-        return bail(UPR_E_NOMEM, "pinned batch allocation failed");
+    if (bind_batch_pinned(c, b) != UPR_OK) return bail(UPR_E_NOMEM, "pinned batch allocation failed");
     // every graph: rows well formed (xadj from 0, nondecreasing; positive node
     // weights) before anything reads its adjacency, then neighbour ids inside
     // the graph and positive edge weights
     unsigned long long init[4] = {~0ull, ~0ull, ~0ull, ~0ull}, got[4];
     HIP_TRY(c, hipMemcpyAsync(c->flags, init, sizeof init, hipMemcpyHostToDevice, s));
-    for (int32_t g = 0; g < ng; ++g) {
-        const upr_graph &G = graphs[g];
-        if (G.n > 0)
-            HIP_TRY(c, launch_validate(GraphView{G.n, G.xadj, G.adjncy, G.adjwgt, G.vwgt}, c->flags, 0, s));
+    if (!trusted) {
+        for (int32_t g = 0; g < ng; ++g) {
+            const upr_graph &G = graphs[g];
+            if (G.n > 0)
+                HIP_TRY(c, launch_validate(GraphView{G.n, G.xadj, G.adjncy, G.adjwgt, G.vwgt}, c->flags, 0, s));
+        }
+        HIP_TRY(c, hipMemcpyAsync(got, c->flags, sizeof got, hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        if (got[0] != ~0ull) return bail(UPR_E_GRAPH, "a graph's xadj does not start at 0 or decreases");
+        if (got[3] != ~0ull) return bail(UPR_E_GRAPH, "a graph has a non-positive node weight");
     }
-    HIP_TRY(c, hipMemcpyAsync(got, c->flags, sizeof got, hipMemcpyDeviceToHost, s));
-    HIP_TRY(c, hipStreamSynchronize(s));
-    if (got[0] != ~0ull) return bail(UPR_E_GRAPH, "a graph's xadj does not start at 0 or decreases");
-    if (got[3] != ~0ull) return bail(UPR_E_GRAPH, "a graph has a non-positive node weight");
     for (int32_t g = 0; g < ng; ++g) {
         const upr_graph &G = graphs[g];
         const GraphView src{G.n, G.xadj, G.adjncy, G.adjwgt, G.vwgt};
         if (G.n == 0) continue;
-        HIP_TRY(c, launch_validate(src, c->flags, 1, s));
+        if (!trusted) HIP_TRY(c, launch_validate(src, c->flags, 1, s));
         if (launch_batch_copy(src, b->off[g], eoff[g], eoff[g + 1] - eoff[g], b->xadj, b->adjncy,
                               b->adjwgt, b->vwgt, 0, s) != hipSuccess)
             return bail(UPR_E_HIP, "copying a graph into the batch failed");
@@ -1059,7 +1111,7 @@ int upr_batch_create(upr_ctx *c, const upr_graph *graphs, int32_t ng, int32_t k,
     if (got[1] != ~0ull) return bail(UPR_E_GRAPH, "a graph names a neighbour outside its own nodes");
     if (got[3] != ~0ull) return bail(UPR_E_GRAPH, "a graph has a non-positive edge weight");
     const upr_graph ug{b->n, b->xadj, b->adjncy, b->adjwgt, b->vwgt};
-    int rc = upr_plan_create(c, &ug, &b->plan, s);
+    int rc = plan_create(c, &ug, &b->plan, s, !trusted, b->nnz);
     if (rc) {
         const std::string msg = c->err;
         upr_batch_destroy(b);
@@ -1120,6 +1172,10 @@ static int batch_common(upr_ctx *c, upr_batch *b, const upr_params *q, const int
     if ((tau_num == nullptr) != (tau_den == nullptr))
         return fail(c, UPR_E_ARG, "give both tau arrays or neither");
     HIP_TRY(c, hipSetDevice(c->device));
+    // the host mirrors live in the context's pinned area, shared by its
+    // batches: the previous call's last copy out of it must have completed
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if (bind_batch_pinned(c, b) != UPR_OK) return fail(c, UPR_E_NOMEM, "pinned batch allocation failed");
     if (moves) {
         // per-graph penalty tables; graphs in the same round share one
         int64_t last_num = -1, last_den = -1;

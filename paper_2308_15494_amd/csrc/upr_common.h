@@ -34,6 +34,14 @@ enum Counter {
     CNT_COUNT = 32
 };
 
+// The counters are kept in kCntCopies copies (CNT_COUNT slots each, 256 bytes
+// apart): a workgroup adds to the copy of its blockIdx.x modulo kCntCopies.
+// Atomics on one address serialise in the L2 at about 12 ns each, so a
+// single copy costs about 100 us for 8192 workgroups; spread over 64 copies
+// it costs nothing measurable. Readers sum the copies.
+constexpr int kCntCopies = 64;
+constexpr int kCntWords = kCntCopies * CNT_COUNT;
+
 struct PenTable {
     int64_t q[kSlots];
 };
@@ -325,6 +333,24 @@ __device__ __forceinline__ void wave_hist_add(int64_t *base, int64_t key, int64_
     }
 }
 
+// Spread counters (see kCntCopies).
+__device__ __forceinline__ void cnt_add(unsigned long long *c, int slot, unsigned long long v)
+{
+    atomicAdd(&c[(blockIdx.x & (kCntCopies - 1)) * CNT_COUNT + slot], v);
+}
+__device__ __forceinline__ unsigned long long cnt_get(const unsigned long long *c, int slot)
+{
+    unsigned long long s = 0;
+#pragma unroll 16
+    for (int i = 0; i < kCntCopies; ++i) s += c[i * CNT_COUNT + slot];
+    return s;
+}
+// One thread sets a counter: copy 0 holds the value, the others 0.
+__device__ __forceinline__ void cnt_set(unsigned long long *c, int slot, unsigned long long v)
+{
+    for (int i = 0; i < kCntCopies; ++i) c[i * CNT_COUNT + slot] = i == 0 ? v : 0ull;
+}
+
 // Add the number of lanes with pred to an LDS counter (lane 0 of the wave).
 __device__ __forceinline__ void wave_count(bool pred, unsigned long long *lds_counter)
 {
@@ -378,9 +404,13 @@ hipError_t launch_node_stats(const GraphView &g, const Blocks &bk, const int32_t
                              int64_t *gstat, int gs_slot, hipStream_t s);
 hipError_t launch_block_weights(const GraphView &g, int32_t k, const int32_t *part, int64_t *W,
                                 unsigned long long *counters, hipStream_t s);
-hipError_t launch_cut_edges(const GraphView &g, const int32_t *part, unsigned long long *acc,
-                            hipStream_t s);
-hipError_t launch_store_half(const unsigned long long *acc, int64_t *out, hipStream_t s);
+// 2 * cut from the adjacency into the spread counter `slot`; out = that / 2.
+hipError_t launch_cut_edges(const GraphView &g, const int32_t *part, unsigned long long *counters,
+                            int slot, hipStream_t s);
+hipError_t launch_store_half(const unsigned long long *counters, int slot, int64_t *out,
+                             hipStream_t s);
+// Spread counter dst = src.
+hipError_t launch_cnt_copy(unsigned long long *counters, int dst, int src, hipStream_t s);
 hipError_t launch_check_part(int64_t n, int32_t k, const int32_t *part,
                              unsigned long long *counters, hipStream_t s);
 

@@ -8,7 +8,9 @@ weights) on the device. Requests with the same (k, eps) share a batch (the
 disjoint union of their graphs, refined by the same launches); at every step
 each batch runs one round of all its requests, finished requests leave, and
 requests that have arrived are admitted as long as their footprint fits the
-budget. When a batch's membership changes it is rebuilt from the surviving
+budget; a running batch takes newcomers at most every `admit_every` steps,
+since each change of membership rebuilds it. When a batch's membership
+changes it is rebuilt from the surviving
 requests' partitions, and that step recomputes the tables (a table is a
 function of the partition, so the result is the same as keeping it).
 
@@ -83,6 +85,8 @@ class _Group:
         self.batch = None
         self.dirty = True
         self.fresh = True
+        self.waiting: list[_Job] = []   # admitted, joining at the next rebuild
+        self.since_rebuild = 0
 
     def rebuild(self):
         """New union of the current jobs, carrying their partitions."""
@@ -97,7 +101,9 @@ class _Group:
         self.batch = None
         self.members = list(self.jobs)
         if self.members:
-            self.batch = upr.Batch(self.ctx, [j.dg for j in self.members], self.k, self.eps)
+            # admitted graphs were validated on admission
+            self.batch = upr.Batch(self.ctx, [j.dg for j in self.members], self.k, self.eps,
+                                   trusted=True)
             self.batch.set_partitions([j.part for j in self.members])
         self.dirty = False
 
@@ -121,9 +127,14 @@ class _Group:
 class Server:
     """Admission by footprint, continuous batching, latency bookkeeping."""
 
-    def __init__(self, ctx: upr.Context, budget_bytes: int):
+    def __init__(self, ctx: upr.Context, budget_bytes: int, admit_every: int = 3):
         self.ctx = ctx
         self.budget = budget_bytes
+        self.admit_every = max(int(admit_every), 1)
+        self.timings = {}
+
+    def _tick(self, name, t):
+        self.timings[name] = self.timings.get(name, 0.0) + t
 
     def run(self, requests, clock=time.perf_counter, on_done=None):
         import torch
@@ -142,13 +153,15 @@ class Server:
                 need = req.footprint()
                 if active and used + need > self.budget:
                     break  # wait for memory to free up (arrival order is kept)
+                t1 = clock()
                 dg = upr.DeviceGraph(req.graph, torch.device("cuda", self.ctx.device))
+                upr.validate_graph(self.ctx, dg)
+                self._tick("admit_s", clock() - t1)
                 key = (req.k, tuple(req.eps))
                 grp = groups.get(key)
                 if grp is None:
                     grp = groups[key] = _Group(self.ctx, req.k, req.eps)
-                grp.jobs.append(_Job(req, dg, clock() - t0))
-                grp.dirty = True
+                grp.waiting.append(_Job(req, dg, clock() - t0))
                 used += need
                 active += 1
                 pi += 1
@@ -160,12 +173,28 @@ class Server:
                     time.sleep(min(wait, 0.01))
                 continue
             for grp in groups.values():
+                # newcomers join an idle batch at once, a running one every
+                # admit_every steps or whenever it is rebuilt anyway (each
+                # change of membership rebuilds the batch)
+                if grp.waiting and (not grp.members or grp.dirty
+                                    or grp.since_rebuild >= self.admit_every):
+                    grp.jobs.extend(grp.waiting)
+                    grp.waiting = []
+                    grp.dirty = True
                 if grp.dirty:
+                    t1 = clock()
                     grp.rebuild()
                     grp.fresh = True
+                    grp.since_rebuild = 0
+                    self._tick("rebuild_s", clock() - t1)
+                    self._tick("rebuilds", 1)
                 if not grp.members:
                     continue
+                t1 = clock()
                 finished = grp.step()
+                grp.since_rebuild += 1
+                self._tick("step_s", clock() - t1)
+                self._tick("steps", 1)
                 if finished:
                     parts = grp.batch.local_partitions()
                     done = clock() - t0

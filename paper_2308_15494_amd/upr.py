@@ -82,8 +82,9 @@ _SIGS = [
                                  C.c_void_p, C.c_void_p]),
     ("upr_lmax", C.c_int64, [C.c_int64, C.c_int32, C.c_int32, C.c_int32]),
     ("upr_penalty_table", C.c_int, [C.c_int32, C.c_int32, C.c_void_p]),
-    ("upr_batch_create", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
-                                   C.c_int32, C.POINTER(C.c_void_p), C.c_void_p]),
+    ("upr_batch_create", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                   C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_void_p),
+                                   C.c_void_p]),
     ("upr_batch_destroy", None, [C.c_void_p]),
     ("upr_batch_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                  C.c_void_p, C.c_void_p]),
@@ -353,15 +354,18 @@ class Batch:
     stats [ng, STATS_LEN]. The input DeviceGraphs may be dropped after
     construction."""
 
-    def __init__(self, ctx: Context, graphs, k, eps=(3, 100), stream=None):
+    def __init__(self, ctx: Context, graphs, k, eps=(3, 100), stream=None, trusted=False):
+        """trusted: every graph was validated before (UPR_BATCH_TRUSTED)."""
         import torch
         self.ctx, self.k, self.eps = ctx, k, eps
         self.ng = len(graphs)
         dgs = [g if isinstance(g, DeviceGraph) else DeviceGraph(g) for g in graphs]
         arr = (_Graph * self.ng)(*[d.c for d in dgs])
+        nnz = np.ascontiguousarray([d.nnz for d in dgs], np.int64)
         self.handle = C.c_void_p()
-        ctx.check(lib().upr_batch_create(ctx.handle, C.cast(arr, C.c_void_p), self.ng, k, eps[0],
-                                         eps[1], C.byref(self.handle), _stream(stream)))
+        ctx.check(lib().upr_batch_create(ctx.handle, C.cast(arr, C.c_void_p), nnz.ctypes.data,
+                                         self.ng, k, eps[0], eps[1], 1 if trusted else 0,
+                                         C.byref(self.handle), _stream(stream)))
         torch.cuda.synchronize()
         n, nnz = C.c_int64(), C.c_int64()
         self.off = np.zeros(self.ng + 1, np.int64)
