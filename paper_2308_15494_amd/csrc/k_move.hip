@@ -222,6 +222,147 @@ __global__ __launch_bounds__(kBlock) void k_best_move(
     if (threadIdx.x == 0 && cand_lds) cnt_add(counters, CNT_CAND, cand_lds);
 }
 
+// The same move choice with the row held in registers (k a multiple of 4, at
+// most 1024): G lanes per node, R int4 per lane (q = r * G + lane), U nodes
+// per lane group and step. The row loads, part[v] and the next node's loads
+// are in flight together, and omega(v, V_a) comes from the loaded row by a
+// shuffle instead of a dependent load.
+template <int G, int R, int U>
+__global__ __launch_bounds__(kBlock) void k_best_move_reg(
+    GraphView g, Blocks bk, const int32_t *__restrict__ part, const int32_t *__restrict__ conn,
+    const int64_t *__restrict__ W, const int64_t *__restrict__ cb,
+    const int64_t *__restrict__ pen1, int mode, const uint8_t *__restrict__ active,
+    int64_t *__restrict__ key, int64_t *__restrict__ pen, unsigned long long *counters)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int32_t k = bk.k;
+    const int32_t K = bk.total();
+    int64_t *sW = (int64_t *)lds_raw;
+    int64_t *sP = sW + K;
+    __shared__ unsigned long long cand_lds;
+    const bool use_lds = K <= 2048;
+    const bool unit = g.vwgt == nullptr;
+    if (threadIdx.x == 0) cand_lds = 0;
+    if (use_lds)
+        for (int j = threadIdx.x; j < K; j += kBlock) {
+            sW[j] = W[j];
+            sP[j] = pen1[j];
+        }
+    __syncthreads();
+    const int64_t *Wr = use_lds ? sW : W;
+    const int64_t *Pr = use_lds ? sP : pen1;
+
+    constexpr int GPB = kBlock / G;
+    const int lane = lane_id();
+    const int gl = lane & (G - 1);
+    const int gbase = lane & ~(G - 1);
+    const int nvec = k >> 2;
+    const int64_t stride = (int64_t)gridDim.x * GPB * U;
+    for (int64_t v0 = ((int64_t)blockIdx.x * GPB + threadIdx.x / G) * U; v0 < g.n; v0 += stride) {
+        int32_t A[U];
+        v4i32 x[U][R];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t v = v0 + u;
+            const bool valid = v < g.n;
+            A[u] = valid ? part[v] : -1;
+            if (valid && active && !active[v]) A[u] = -1;
+            const int32_t *row = conn + v * (int64_t)k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int q = r * G + gl;
+                if (valid && q < nvec) {
+                    x[u][r] = stream_load4(row + 4 * q);
+                } else {
+                    x[u][r].x = x[u][r].y = x[u][r].z = x[u][r].w = 0;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t v = v0 + u;
+            const int32_t Au = A[u];
+            const bool ok = (unsigned)Au < (unsigned)K;  // group-uniform
+            const int32_t a = ok ? bk.local(Au) : 0;
+            const int32_t base = ok ? bk.base(Au) : 0;
+            // omega(v, V_a) from the lane and register that hold column a
+            const int qa = a >> 2;
+            const int ra = qa / G;
+            v4i32 xr = x[u][0];
+#pragma unroll
+            for (int r = 1; r < R; ++r)
+                if (ra == r) xr = x[u][r];
+            const int comp = a & 3;
+            const int32_t mine = comp == 0 ? xr.x : comp == 1 ? xr.y : comp == 2 ? xr.z : xr.w;
+            const int32_t ca = __shfl(mine, gbase + (qa & (G - 1)));
+            int64_t best = 0, bestP = 0;
+            const int64_t cv = node_weight(g, ok ? v : 0);
+            if (ok) {
+                const int64_t lmax = bk.move_lmax_of(Au);
+                const int64_t *penq = bk.penq_of(Au);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int q = r * G + gl;
+                    if (q >= nvec) continue;
+                    const int32_t c4[4] = {x[u][r].x, x[u][r].y, x[u][r].z, x[u][r].w};
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int32_t cj = c4[t];
+                        const int j = q * 4 + t;
+                        if (cj <= ca || j == a) continue;
+                        const int64_t delta = (int64_t)cj - ca;
+                        int64_t P;
+                        if (unit) {
+                            P = Pr[base + j];
+                            if (P < 0) continue;
+                        } else {
+                            P = 0;
+                            const int64_t xx = Wr[base + j] + cv - lmax;
+                            if (xx > 0) {
+                                if (mode == 1 || mode == 3) continue;
+                                if (mode == 0) {
+                                    const int l = covering_slot(cb + (int64_t)(base + j) * kSlots, xx);
+                                    if (l >= kSlots) continue;
+                                    P = sat_mul_pen(penq[l], cv);
+                                }
+                            }
+                        }
+                        const int64_t sc = delta * 65536 - P;
+                        if (sc <= 0) continue;
+                        const int64_t packed = (sc << 16) | (int64_t)(0xFFFF - j);
+                        if (packed > best) {
+                            best = packed;
+                            bestP = P;
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int off = G / 2; off > 0; off >>= 1) {
+                const int64_t ob = __shfl_xor(best, off);
+                const int64_t op = __shfl_xor(bestP, off);
+                if (ob > best) {
+                    best = ob;
+                    bestP = op;
+                }
+            }
+            if (gl == 0 && v < g.n) {
+                if (best > 0) {
+                    const int64_t sc = best >> 16;
+                    const int32_t j = 0xFFFF - (int32_t)(best & 0xFFFF);
+                    key[v] = (sc << 16) | j;
+                    pen[v] = bestP;
+                    atomicAdd(&cand_lds, 1ull);
+                } else {
+                    key[v] = -1;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && cand_lds) cnt_add(counters, CNT_CAND, cand_lds);
+}
+
 hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t *part,
                             const int32_t *conn, const int64_t *W, const int64_t *cb,
                             const int64_t *pen1, int mode, const uint8_t *active, int64_t *key,
@@ -232,6 +373,23 @@ hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t 
     const size_t lds = bk.total() <= 2048 ? (size_t)bk.total() * 16 : 0;
     const bool vec = (k % 4) == 0;
     const int nvec = vec ? k / 4 : k;
+    if (vec && nvec <= 256) {
+#define UPR_BR(GG, RR, UU)                                                                          \
+    hipLaunchKernelGGL((k_best_move_reg<GG, RR, UU>),                                               \
+                       dim3(grid_cap((g.n + UU - 1) / UU, kBlock / GG, 8192)), dim3(kBlock), lds, s, \
+                       g, bk, part, conn, W, cb, pen1, mode, active, key, pen, counters)
+        if (nvec <= 1) UPR_BR(1, 1, 2);
+        else if (nvec <= 2) UPR_BR(2, 1, 2);
+        else if (nvec <= 4) UPR_BR(4, 1, 2);
+        else if (nvec <= 8) UPR_BR(8, 1, 2);
+        else if (nvec <= 16) UPR_BR(16, 1, 2);
+        else if (nvec <= 32) UPR_BR(32, 1, 2);
+        else if (nvec <= 64) UPR_BR(64, 1, 2);
+        else if (nvec <= 128) UPR_BR(64, 2, 1);
+        else UPR_BR(64, 4, 1);
+#undef UPR_BR
+        return hipGetLastError();
+    }
 #define UPR_BM(GG, VV)                                                                             \
     hipLaunchKernelGGL((k_best_move<GG, VV>), dim3(grid_cap(g.n, kBlock / GG, 8192)), dim3(kBlock), \
                        lds, s, g, bk, part, conn, W, cb, pen1, mode, active, key, pen, counters)
