@@ -122,6 +122,22 @@ const char *upr_last_error(const upr_ctx *ctx);
  * group, hubs by several workgroups). Created once per graph; enqueued on
  * `stream` and synchronised. The graph arrays must outlive the plan. */
 int upr_plan_create(upr_ctx *ctx, const upr_graph *graph, upr_plan **out, hipStream_t stream);
+
+/* Traversal thresholds of a plan (0 = default: the environment variables
+ * UPR_HUB_THRESHOLD / UPR_LOW_THRESHOLD / UPR_DIRTY_DIV if set, else 4096 / 32
+ * / 8). Nodes of degree above hub_threshold are hubs (split into edge chunks
+ * of whole workgroups), at most low_threshold are handled by 8-lane groups,
+ * the rest by a wave; the apply rebuilds table tiles instead of atomic deltas
+ * once the moving nodes' degrees sum above nnz / dirty_div. They change only
+ * the speed, never a result; paper_2308_15494_amd/tune.py picks them by
+ * timing trial rounds. */
+typedef struct {
+    int64_t hub_threshold;
+    int64_t low_threshold;
+    int64_t dirty_div;
+} upr_plan_opts;
+int upr_plan_create_opts(upr_ctx *ctx, const upr_graph *graph, const upr_plan_opts *opts,
+                         upr_plan **out, hipStream_t stream);
 void upr_plan_destroy(upr_plan *plan);
 /* Host-side facts of a plan (any output pointer may be NULL). */
 int upr_plan_info(const upr_plan *plan, int64_t *n, int64_t *nnz, int64_t *total_weight,
@@ -201,12 +217,13 @@ int upr_last_moves(upr_ctx *ctx, int64_t n, int32_t *target, int64_t *score, int
  * that every graph names only its own nodes (unless trusted, below).
  * Enqueued on `stream` and synchronised. ng * k <= UPR_MAX_BATCH_BLOCKS. */
 int upr_batch_create(upr_ctx *ctx, const upr_graph *graphs, const int64_t *nnz, int32_t ng,
-                     int32_t k, int32_t eps_num, int32_t eps_den, int32_t flags, upr_batch **out,
-                     hipStream_t stream);
+                     int32_t k, int32_t eps_num, int32_t eps_den, int32_t flags,
+                     const upr_plan_opts *opts, upr_batch **out, hipStream_t stream);
 /* upr_batch_create arguments: nnz, a host array [ng] of each graph's xadj[n]
  * (or NULL to read them from the device); flags: 0, or UPR_BATCH_TRUSTED when
  * every graph has passed upr_validate_graph or an earlier batch (a server
- * rebuilding batches of admitted graphs): the checks are skipped. */
+ * rebuilding batches of admitted graphs): the checks are skipped; opts: the
+ * union's plan thresholds (may be NULL). */
 #define UPR_BATCH_TRUSTED 1
 void upr_batch_destroy(upr_batch *batch);
 /* Union size, node offsets off[ng + 1] and L_max[ng] (any pointer may be NULL). */

@@ -623,17 +623,23 @@ int upr_validate_graph(upr_ctx *c, const upr_graph *graph, hipStream_t s)
 }
 
 static int plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipStream_t s,
-                       bool validate, int64_t known_nnz);
+                       bool validate, int64_t known_nnz, const upr_plan_opts *opts);
 
 int upr_plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipStream_t s)
 {
-    return plan_create(c, graph, out, s, true, -1);
+    return plan_create(c, graph, out, s, true, -1, nullptr);
+}
+
+int upr_plan_create_opts(upr_ctx *c, const upr_graph *graph, const upr_plan_opts *opts,
+                         upr_plan **out, hipStream_t s)
+{
+    return plan_create(c, graph, out, s, true, -1, opts);
 }
 
 // validate = false: the caller has checked the graph already (a batch of
 // graphs validated before); known_nnz >= 0: xadj[n], known on the host.
 static int plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipStream_t s,
-                       bool validate, int64_t known_nnz)
+                       bool validate, int64_t known_nnz, const upr_plan_opts *opts)
 {
     if (!c) return UPR_E_ARG;
     if (!out) return fail(c, UPR_E_ARG, "out is NULL");
@@ -669,8 +675,12 @@ static int plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipSt
     upr_plan *p = new upr_plan();
     p->ctx = c;
     p->g = g;
-    p->hub_t = env_int("UPR_HUB_THRESHOLD", kDefaultHubThreshold);
-    p->low_t = env_int("UPR_LOW_THRESHOLD", kDefaultLowThreshold);
+    // thresholds: the options, else the environment, else the defaults
+    p->hub_t = opts && opts->hub_threshold > 0 ? opts->hub_threshold
+                                               : env_int("UPR_HUB_THRESHOLD", kDefaultHubThreshold);
+    p->low_t = opts && opts->low_threshold > 0 ? opts->low_threshold
+                                               : env_int("UPR_LOW_THRESHOLD", kDefaultLowThreshold);
+    const int64_t dirty_div = opts && opts->dirty_div > 0 ? opts->dirty_div : env_int("UPR_DIRTY_DIV", 8);
     // a tile's edge count (nodes per tile x hub threshold) must fit int32
     p->hub_t = std::min<int64_t>(std::max<int64_t>(p->hub_t, 1), (int64_t)1 << 20);
     p->low_t = std::min<int64_t>(std::max<int64_t>(p->low_t, 0), p->hub_t);
@@ -686,7 +696,7 @@ static int plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipSt
             return bail(UPR_E_HIP, "reading xadj[n] failed");
         // integer-atomic deltas cost about as much per moved edge as a
         // rebuild costs per edge of the whole graph divided by this factor
-        p->dirty_threshold = p->nnz / std::max<int64_t>(env_int("UPR_DIRTY_DIV", 8), 1);
+        p->dirty_threshold = p->nnz / std::max<int64_t>(dirty_div, 1);
         if (dalloc(&p->wdeg, g.n) != hipSuccess || dalloc(&hub_list, g.n) != hipSuccess)
             return bail(UPR_E_NOMEM, "plan allocation failed");
         unsigned long long zero[8] = {0}, res[8];
@@ -1021,8 +1031,8 @@ void upr_batch_destroy(upr_batch *b)
 }
 
 int upr_batch_create(upr_ctx *c, const upr_graph *graphs, const int64_t *nnz_host, int32_t ng,
-                     int32_t k, int32_t eps_num, int32_t eps_den, int32_t flags, upr_batch **out,
-                     hipStream_t s)
+                     int32_t k, int32_t eps_num, int32_t eps_den, int32_t flags,
+                     const upr_plan_opts *opts, upr_batch **out, hipStream_t s)
 {
     if (!c) return UPR_E_ARG;
     if (!out) return fail(c, UPR_E_ARG, "out is NULL");
@@ -1111,7 +1121,7 @@ int upr_batch_create(upr_ctx *c, const upr_graph *graphs, const int64_t *nnz_hos
     if (got[1] != ~0ull) return bail(UPR_E_GRAPH, "a graph names a neighbour outside its own nodes");
     if (got[3] != ~0ull) return bail(UPR_E_GRAPH, "a graph has a non-positive edge weight");
     const upr_graph ug{b->n, b->xadj, b->adjncy, b->adjwgt, b->vwgt};
-    int rc = plan_create(c, &ug, &b->plan, s, !trusted, b->nnz);
+    int rc = plan_create(c, &ug, &b->plan, s, !trusted, b->nnz, opts);
     if (rc) {
         const std::string msg = c->err;
         upr_batch_destroy(b);

@@ -83,8 +83,10 @@ _SIGS = [
     ("upr_lmax", C.c_int64, [C.c_int64, C.c_int32, C.c_int32, C.c_int32]),
     ("upr_penalty_table", C.c_int, [C.c_int32, C.c_int32, C.c_void_p]),
     ("upr_batch_create", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
-                                   C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_void_p),
-                                   C.c_void_p]),
+                                   C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                   C.POINTER(C.c_void_p), C.c_void_p]),
+    ("upr_plan_create_opts", C.c_int, [C.c_void_p, C.POINTER(_Graph), C.c_void_p,
+                                       C.POINTER(C.c_void_p), C.c_void_p]),
     ("upr_batch_destroy", None, [C.c_void_p]),
     ("upr_batch_info", C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                  C.c_void_p, C.c_void_p]),
@@ -225,15 +227,30 @@ class DeviceGraph:
                         _ptr(self.adjwgt), _ptr(self.vwgt))
 
 
+class PlanOpts(C.Structure):
+    """upr_plan_opts: traversal thresholds (0 = default)."""
+    _fields_ = [("hub_threshold", C.c_int64), ("low_threshold", C.c_int64),
+                ("dirty_div", C.c_int64)]
+
+
+def plan_opts(hub_threshold=0, low_threshold=0, dirty_div=0) -> PlanOpts:
+    return PlanOpts(hub_threshold, low_threshold, dirty_div)
+
+
 class Plan:
     """upr_plan: a prepared graph (degrees, hub chunks). Keeps the graph alive."""
 
-    def __init__(self, ctx: Context, dg: DeviceGraph, stream=None):
+    def __init__(self, ctx: Context, dg: DeviceGraph, stream=None, opts: PlanOpts = None):
         self.ctx = ctx
         self.graph = dg
         self.handle = C.c_void_p()
-        ctx.check(lib().upr_plan_create(ctx.handle, C.byref(dg.c), C.byref(self.handle),
-                                        _stream(stream)))
+        self.opts = opts
+        if opts is None:
+            ctx.check(lib().upr_plan_create(ctx.handle, C.byref(dg.c), C.byref(self.handle),
+                                            _stream(stream)))
+        else:
+            ctx.check(lib().upr_plan_create_opts(ctx.handle, C.byref(dg.c), C.byref(opts),
+                                                 C.byref(self.handle), _stream(stream)))
 
     def info(self) -> dict:
         vals = [C.c_int64() for _ in range(5)]
@@ -321,12 +338,12 @@ def stats_dict(stats) -> dict:
 class Refiner:
     """Convenience holder: graph on device, plan, and (part, conn, W) state."""
 
-    def __init__(self, g, k, device=0, ctx=None):
+    def __init__(self, g, k, device=0, ctx=None, opts: PlanOpts = None):
         import torch
         self.ctx = ctx or Context(device)
         self.dev = torch.device("cuda", device)
         self.dg = DeviceGraph(g, self.dev)
-        self.plan = Plan(self.ctx, self.dg)
+        self.plan = Plan(self.ctx, self.dg, opts=opts)
         self.k = k
         self.conn = torch.zeros(max(self.dg.n * k, 1), dtype=torch.int32, device=self.dev)
         self.W = torch.zeros(k, dtype=torch.int64, device=self.dev)
@@ -354,8 +371,10 @@ class Batch:
     stats [ng, STATS_LEN]. The input DeviceGraphs may be dropped after
     construction."""
 
-    def __init__(self, ctx: Context, graphs, k, eps=(3, 100), stream=None, trusted=False):
-        """trusted: every graph was validated before (UPR_BATCH_TRUSTED)."""
+    def __init__(self, ctx: Context, graphs, k, eps=(3, 100), stream=None, trusted=False,
+                 opts: PlanOpts = None):
+        """trusted: every graph was validated before (UPR_BATCH_TRUSTED);
+        opts: the union's plan thresholds."""
         import torch
         self.ctx, self.k, self.eps = ctx, k, eps
         self.ng = len(graphs)
@@ -365,6 +384,7 @@ class Batch:
         self.handle = C.c_void_p()
         ctx.check(lib().upr_batch_create(ctx.handle, C.cast(arr, C.c_void_p), nnz.ctypes.data,
                                          self.ng, k, eps[0], eps[1], 1 if trusted else 0,
+                                         None if opts is None else C.byref(opts),
                                          C.byref(self.handle), _stream(stream)))
         torch.cuda.synchronize()
         n, nnz = C.c_int64(), C.c_int64()
