@@ -275,6 +275,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests of the serving leg (0 skips it)")
     ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the traversal thresholds before timing (default: the "
+                         "library's defaults, which the tuner did not beat by more than noise)")
     args = ap.parse_args()
     if args.ingest_pmc:
         ingest_pmc(*args.ingest_pmc)
@@ -312,7 +315,15 @@ def main():
 
     dev = torch.device("cuda", 0)
     ctx = upr.Context(0)
-    r = upr.Refiner(g, k, ctx=ctx)
+    opts, tune_rep = None, None
+    if args.tune:
+        # thresholds picked by timing trial rounds (they never change a result)
+        from paper_2308_15494_amd import tune
+        t0 = time.perf_counter()
+        opts, tune_rep = tune.tune_graph(ctx, g, k, part0, eps, rounds=3, repeats=2,
+                                         total_rounds=rounds)
+        log(f"tuned thresholds {tune_rep['chosen']} in {time.perf_counter() - t0:.1f}s")
+    r = upr.Refiner(g, k, ctx=ctx, opts=opts)
     plan_info = r.plan.info()
     stream = torch.cuda.current_stream()
 
@@ -376,7 +387,8 @@ def main():
         "config": {"workload": args.workload, "n": g.n, "m": g.m, "k": k,
                    "eps": f"{eps[0]}/{eps[1]}", "rounds": rounds,
                    "form": "resident" if args.resident else "rebuild",
-                   "hubs": plan_info["num_hubs"], "max_degree": plan_info["max_degree"]},
+                   "hubs": plan_info["num_hubs"], "max_degree": plan_info["max_degree"],
+                   "thresholds": tune_rep["chosen"] if tune_rep else "default"},
         "roofline": roofline,
         "phases_ms_per_round": {k_: round(v[0] / max(args.steps, 1), 4) for k_, v in phases.items()},
         "final_stats": final,
