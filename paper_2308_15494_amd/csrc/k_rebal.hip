@@ -146,6 +146,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
             const int64_t lmax = ok ? bk.lmax_of(A) : 0;
             int64_t best = -1, lw = INT64_MAX, cv = 1;
             int32_t lj = 0x7fffffff;
+            int32_t ca_mine = 0;  // omega(v, V_a), held by the lane that loads column a
             if (ok) {
                 cv = node_weight(g, v);
                 const int32_t *row = conn + v * (int64_t)k;
@@ -163,7 +164,10 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
 #pragma unroll
                     for (int t = 0; t < V; ++t) {
                         const int j = q * V + t;
-                        if (j == a) continue;
+                        if (j == a) {
+                            ca_mine = c4[t];
+                            continue;
+                        }
                         const int64_t wj = W0[base + j];
                         if (wj + cv > lmax) continue;
                         if (c4[t] > 0) {
@@ -188,6 +192,8 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
                     lj = oj;
                 }
             }
+            // column a sits in vector a / V, loaded by lane (a / V) mod G of the group
+            const int32_t ca = __shfl(ca_mine, (lane & ~(G - 1)) + ((a / V) & (G - 1)));
             bool push = false;
             int64_t hkey = 0;
             if (ok && gl == 0) {
@@ -201,9 +207,8 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
                 }
                 r.rtgt[v] = tgt >= 0 ? base + tgt : -1;
                 if (tgt >= 0) {
-                    const int64_t ca = conn[v * (int64_t)k + a];
                     // the plain-gain variant ranks by the gain alone (c(v) = 1)
-                    const int be = rebalance_bucket(ct - ca, plain ? 1 : cv);
+                    const int be = rebalance_bucket(ct - (int64_t)ca, plain ? 1 : cv);
                     r.rbeta[v] = (uint8_t)be;
                     hkey = (int64_t)(base + tgt) * kRbBuckets + be;
                     push = true;

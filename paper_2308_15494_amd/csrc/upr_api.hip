@@ -905,53 +905,47 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
             HIP_TRY(c, launch_best_move(p->g, bk, part, conn, W, c->bucket, c->pen1, q->mode,
                                         active, c->key, c->pen, c->counters, s));
         }
-        // one host decision: are there candidates at all (also reports bad input)
-        rc = sync_counters(c, s);
-        if (rc) return rc;
-        if (c->cnt[CNT_BAD_INPUT])
-            return fail(c, UPR_E_ARG, b ? "part holds a block outside its graph's range"
-                                        : "part holds values outside [0, k)");
-        const int64_t nc = (int64_t)c->cnt[CNT_CAND];
-        if (nc > 0) {
-            moved = true;
-            {
-                PhaseTimer t(c, 3, s);
-                int64_t *gp_out = q->seq_penalty ? c->gp : nullptr;
-                HIP_TRY(c, launch_filter(p->g, bk, optimistic, part, pv, c->key, c->pen, p->low_t,
-                                         p->hub_t, c->mvto, c->accflag, c->counters, gp_out, s));
-                HIP_TRY(c, launch_filter_hub(p->g, bk, optimistic, part, pv, c->key, c->pen, h,
-                                             c->mvto, c->accflag, c->counters, gp_out, s));
-                if (q->seq_penalty) {
-                    // eligible candidates in id order; their number sizes the sort
-                    HIP_TRY(c, launch_seq_select(n, c->key, c->gp, c->cand,
-                                                 c->counters + CNT_ELIG, c->seq_temp,
-                                                 c->seq_temp_size, s));
-                    rc = sync_counters(c, s);
-                    if (rc) return rc;
-                    const int64_t ne = (int64_t)c->cnt[CNT_ELIG];
-                    HIP_TRY(c, launch_seq_net(ne, c->cand, c->key, part, p->g.vwgt, c->avail, bk,
-                                              seq_score_bits(p->maxwdeg), c->ev_key, c->ev_key2,
-                                              c->ev_val, c->ev_val2, c->ev_prefix, c->netpre,
-                                              c->seq_temp, c->seq_temp_size, s));
-                    HIP_TRY(c, launch_filter_seq(p->g, bk, part, c->cand, ne, c->key, c->gp,
-                                                 c->netpre, W, c->bucket, q->mode, p->hub_t,
-                                                 c->mvto, c->accflag, c->counters, s));
-                }
-                if (b) HIP_TRY(c, launch_batch_move_stats(n, bk, part, c->key, c->accflag, gstat, s));
+        // no host decision here: with no candidates the filter and the apply
+        // find nothing to do; a bad part value is reported at the next
+        // synchronisation (every kernel range-checks it)
+        moved = true;
+        {
+            PhaseTimer t(c, 3, s);
+            int64_t *gp_out = q->seq_penalty ? c->gp : nullptr;
+            HIP_TRY(c, launch_filter(p->g, bk, optimistic, part, pv, c->key, c->pen, p->low_t,
+                                     p->hub_t, c->mvto, c->accflag, c->counters, gp_out, s));
+            HIP_TRY(c, launch_filter_hub(p->g, bk, optimistic, part, pv, c->key, c->pen, h,
+                                         c->mvto, c->accflag, c->counters, gp_out, s));
+            if (q->seq_penalty) {
+                // eligible candidates in id order; their number sizes the sort
+                HIP_TRY(c, launch_seq_select(n, c->key, c->gp, c->cand, c->counters + CNT_ELIG,
+                                             c->seq_temp, c->seq_temp_size, s));
+                rc = sync_counters(c, s);
+                if (rc) return rc;
+                if (c->cnt[CNT_BAD_INPUT])
+                    return fail(c, UPR_E_ARG, b ? "part holds a block outside its graph's range"
+                                                : "part holds values outside [0, k)");
+                const int64_t ne = (int64_t)c->cnt[CNT_ELIG];
+                HIP_TRY(c, launch_seq_net(ne, c->cand, c->key, part, p->g.vwgt, c->avail, bk,
+                                          seq_score_bits(p->maxwdeg), c->ev_key, c->ev_key2,
+                                          c->ev_val, c->ev_val2, c->ev_prefix, c->netpre,
+                                          c->seq_temp, c->seq_temp_size, s));
+                HIP_TRY(c, launch_filter_seq(p->g, bk, part, c->cand, ne, c->key, c->gp,
+                                             c->netpre, W, c->bucket, q->mode, p->hub_t, c->mvto,
+                                             c->accflag, c->counters, s));
             }
-            {
-                PhaseTimer t(c, 4, s);
-                HIP_TRY(c, launch_apply(p->g, bk, part, pv, conn, W, c->mvto, p->low_t, p->hub_t,
-                                        h, c->counters, p->dirty_threshold, c->dirty, s));
-            }
-            {
-                PhaseTimer t(c, 6, s);
-                HIP_TRY(c, launch_node_stats(p->g, bk, part, conn, p->wdeg, nullptr, nullptr, 0, 1,
-                                             c->counters, CNT_CUT2_MOVES, nullptr, gstat,
-                                             GS_CUT2_MOVES, s));
-            }
-        } else if (!b) {
-            HIP_TRY(c, launch_cnt_copy(c->counters, CNT_CUT2_MOVES, CNT_CUT2_BEFORE, s));
+            if (b) HIP_TRY(c, launch_batch_move_stats(n, bk, part, c->key, c->accflag, gstat, s));
+        }
+        {
+            PhaseTimer t(c, 4, s);
+            HIP_TRY(c, launch_apply(p->g, bk, part, pv, conn, W, c->mvto, p->low_t, p->hub_t, h,
+                                    c->counters, p->dirty_threshold, c->dirty, s));
+        }
+        {
+            PhaseTimer t(c, 6, s);
+            HIP_TRY(c, launch_node_stats(p->g, bk, part, conn, p->wdeg, nullptr, nullptr, 0, 1,
+                                         c->counters, CNT_CUT2_MOVES, nullptr, gstat,
+                                         GS_CUT2_MOVES, s));
         }
     }
     int64_t iters = 0, status = 0;
