@@ -51,7 +51,7 @@ class _Params(C.Structure):
 
 class _Debug(C.Structure):
     _fields_ = [("target", C.c_void_p), ("score", C.c_void_p), ("pen", C.c_void_p),
-                ("accept", C.c_void_p), ("pen_seq", C.c_void_p)]
+                ("accept", C.c_void_p), ("pen_seq", C.c_void_p), ("gp", C.c_void_p)]
 
 
 _lib = None
@@ -193,7 +193,7 @@ def penalty_buckets(g, k, part, conn, t=(7, 10)):
 
 def refine_round(g, p: _Params, part, conn=None, W=None, debug=False, active=None):
     """Run one round in place on (part, conn, W). Returns (stats, dbg) where dbg
-    is a dict of per-node arrays (target, score, pen, accept) or None. active:
+    is a dict of per-node arrays (target, score, pen, accept, pen_seq, gp) or None. active:
     optional uint8 mask of the nodes that may look for a move."""
     G = g if isinstance(g, Graph) else Graph(g)
     k = p.k
@@ -210,10 +210,10 @@ def refine_round(g, p: _Params, part, conn=None, W=None, debug=False, active=Non
     if debug:
         dbg = dict(target=np.zeros(G.n, np.int32), score=np.zeros(G.n, np.int64),
                    pen=np.zeros(G.n, np.int64), accept=np.zeros(G.n, np.uint8),
-                   pen_seq=np.zeros(G.n, np.int64))
+                   pen_seq=np.zeros(G.n, np.int64), gp=np.zeros(G.n, np.int64))
         dstruct = _Debug(dbg["target"].ctypes.data, dbg["score"].ctypes.data,
                          dbg["pen"].ctypes.data, dbg["accept"].ctypes.data,
-                         dbg["pen_seq"].ctypes.data)
+                         dbg["pen_seq"].ctypes.data, dbg["gp"].ctypes.data)
     if active is not None:
         _check(active, np.uint8, G.n, "active")
     rc = lib().orc_refine_round_active(C.byref(G.c), C.byref(p), part.ctypes.data,

@@ -95,6 +95,7 @@ typedef struct {
     int64_t *pen;     /* P(v, target) if candidate, else 0 */
     uint8_t *accept;  /* 1 if the move survived the conflict filter */
     int64_t *pen_seq; /* S3 penalty of a candidate (-1: forbidden), else 0 */
+    int64_t *gp;      /* S3 pessimistic gain of a candidate, else 0 */
 } orc_debug;
 
 static int64_t edge_w(const orc_graph *g, int64_t e) { return g->adjwgt ? g->adjwgt[e] : 1; }
@@ -518,6 +519,7 @@ int orc_refine_round_active(const orc_graph *g, const orc_params *p, int32_t *pa
      * before it. */
     uint8_t *accept = (uint8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
     int64_t *pen_seq = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    int64_t *gps = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
     int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(candidates > 0 ? candidates : 1));
     int64_t *net = (int64_t *)calloc((size_t)k, sizeof(int64_t));
     int64_t nc = 0;
@@ -545,6 +547,7 @@ int orc_refine_round_active(const orc_graph *g, const orc_params *p, int32_t *pa
             }
             gp += edge_w(g, e) * fu;
         }
+        gps[v] = gp;
         int64_t P = pen[v];
         int allowed = 1;
         const int eligible = gp > 0;
@@ -588,9 +591,10 @@ int orc_refine_round_active(const orc_graph *g, const orc_params *p, int32_t *pa
             if (dbg->pen) dbg->pen[v] = pen[v];
             if (dbg->accept) dbg->accept[v] = accept[v];
             if (dbg->pen_seq) dbg->pen_seq[v] = pen_seq[v];
+            if (dbg->gp) dbg->gp[v] = gps[v];
         }
     }
-    free(bucket); free(target); free(score); free(pen); free(accept); free(pen_seq);
+    free(bucket); free(target); free(score); free(pen); free(accept); free(pen_seq); free(gps);
     return 0;
 }
 

@@ -54,19 +54,6 @@ hipError_t launch_round_init(const Blocks &bk, int64_t *bucket, int64_t *W, cons
     return hipGetLastError();
 }
 
-// Least l with cb[l] >= x (cb nondecreasing), kSlots if none.
-__device__ __forceinline__ int covering_slot(const int64_t *cb, int64_t x)
-{
-    if (cb[kSlots - 1] < x) return kSlots;
-    int lo = 0, hi = kSlots - 1;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (cb[mid] >= x) hi = mid;
-        else lo = mid + 1;
-    }
-    return lo;
-}
-
 // Per block B: prefix sums over slots, cb[B][l] = sum_{i <= l} c(B_{i,B}), and
 // the penalty a node of weight 1 pays to enter B: 0 if W[B] + 1 <= L_max
 // (limited imbalance: the cap floor(alpha * L_max)); otherwise constrained and
@@ -464,100 +451,160 @@ __device__ __forceinline__ int64_t pessimistic_part(const GraphView &g, const Pa
     return acc;
 }
 
-// One class of a wave's compacted candidates: lane groups of G take the
-// set bits of mask in order; the node id / key of bit p sit in lane p.
-template <int G>
-__device__ __forceinline__ void filter_class(const GraphView &g, const Blocks &bk, int optimistic,
-                                             const int32_t *part,
-                                             const PartView &pv, const int64_t *key,
-                                             const int64_t *pen,
-                                             uint64_t mask, int64_t lane_v, int64_t lane_key,
-                                             int32_t *mvto, uint8_t *accflag,
-                                             unsigned long long *acc_lds,
-                                             unsigned long long *deg_lds, int64_t *gp_out)
-{
-    const int cnt = __popcll(mask);
-    const int lane = lane_id();
-    const int grp = lane / G;
-    const int gl = lane & (G - 1);
-    for (int p0 = 0; p0 < cnt; p0 += 64 / G) {
-        const int p = p0 + grp;
-        const bool ok = p < cnt;
-        const int src = ok ? nth_set_bit(mask, p) : 0;
-        const int64_t v = __shfl(lane_v, src);
-        const int64_t kv = __shfl(lane_key, src);
-        int64_t acc = 0;
-        int32_t b = 0, A = 0;
-        if (ok) {
-            A = part[v];
-            b = (int32_t)(kv & 0xFFFF);
-            acc = pessimistic_part(g, pv, key, v, bk.local(A), b, kv >> 16, g.xadj[v], g.xadj[v + 1],
-                                   gl, G, optimistic);
-        }
-        acc = group_sum<G>(acc);
-        bool take = false;
-        if (ok && gl == 0 && gp_out) {
-            gp_out[v] = acc;  // eligible ones are decided against the sequence-aware price
-            accflag[v] = 0;
-        } else if (ok && gl == 0) {
-            take = acc * 65536 - pen[v] > 0;
-            accflag[v] = take ? 1 : 0;
-            if (take) {
-                mvto[v] = bk.base(A) + b;
-                atomicAdd(deg_lds, (unsigned long long)(g.xadj[v + 1] - g.xadj[v]));
-            }
-        }
-        wave_count(take, acc_lds);
-    }
-}
+// Candidates of degree up to the hub threshold, one workgroup per tile of
+// kFilterTile consecutive nodes. The tile's candidate edges are spread over
+// all threads (edge -> node by a binary search over the tile's degree
+// prefix), kEdgeUnroll edges per thread and step so that their loads overlap;
+// each edge's term w * f is summed per node over the runs of equal nodes in
+// lane order, and the last lane of a run adds it to the node's LDS sum.
+constexpr int kFilterTile = 512;
 
 __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int optimistic,
                                                     const int32_t *__restrict__ part,
                                                     PartView pv, const int64_t *__restrict__ key,
-                                                    const int64_t *__restrict__ pen, int64_t low_t,
-                                                    int64_t hub_t, int32_t *mvto, uint8_t *accflag,
+                                                    const int64_t *__restrict__ pen, int64_t hub_t,
+                                                    int32_t *mvto, uint8_t *accflag,
                                                     unsigned long long *counters, int64_t *gp_out)
 {
+    __shared__ int32_t vstart[kFilterTile + 1];
+    __shared__ int64_t estart[kFilterTile];
+    __shared__ int64_t skey[kFilterTile];
+    __shared__ int32_t sa[kFilterTile];  // local source block; -1: not decided here
+    __shared__ unsigned long long sacc[kFilterTile];
+    __shared__ int32_t scan_lds[4];
     __shared__ unsigned long long acc_lds, deg_lds;
-    if (threadIdx.x == 0) {
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    if (tid == 0) {
         acc_lds = 0;
         deg_lds = 0;
     }
-    __syncthreads();
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < g.n;
-         base += stride) {
-        const int64_t v = base + lane_id();
-        int64_t kv = -1, deg = 0;
-        if (v < g.n) {
-            kv = key[v];
-            if (kv >= 0) deg = g.xadj[v + 1] - g.xadj[v];
+    const int64_t v0 = (int64_t)blockIdx.x * kFilterTile;
+    const int nt = (int)((g.n - v0) < kFilterTile ? (g.n - v0) : kFilterTile);
+
+    // candidates of the tile, their degrees and the degree prefix
+    int32_t run = 0;
+    for (int base = 0; base < nt; base += kBlock) {
+        const int i = base + tid;
+        int32_t vd = 0;
+        if (i < nt) {
+            const int64_t v = v0 + i;
+            const int64_t kv = key[v];
+            int32_t a = -1;
+            if (kv >= 0) {
+                const int64_t e0 = g.xadj[v], e1 = g.xadj[v + 1];
+                if (e1 - e0 <= hub_t) {
+                    a = bk.local(part[v]);
+                    vd = (int32_t)(e1 - e0);
+                    estart[i] = e0;
+                }
+            }
+            skey[i] = kv;
+            sa[i] = a;
+            sacc[i] = 0;
         }
-        const uint64_t mlow = __ballot(kv >= 0 && deg <= low_t);
-        const uint64_t mmid = __ballot(kv >= 0 && deg > low_t && deg <= hub_t);
-        if (mlow)
-            filter_class<kLowLanes>(g, bk, optimistic, part, pv, key, pen, mlow, v, kv, mvto,
-                                    accflag, &acc_lds, &deg_lds, gp_out);
-        if (mmid)
-            filter_class<64>(g, bk, optimistic, part, pv, key, pen, mmid, v, kv, mvto, accflag,
-                             &acc_lds, &deg_lds, gp_out);
+        int32_t total;
+        const int32_t inc = block_incl_scan(vd, scan_lds, &total);
+        if (i < nt) vstart[i] = run + inc - vd;
+        run += total;
+    }
+    if (tid == 0) vstart[nt] = run;
+    __syncthreads();
+
+    // S3 terms over all candidate edges of the tile; an earlier candidate
+    // neighbour u ((score, id) before v) counts in the worse of its current
+    // and its target block (optimistic variant: its target block)
+    const int32_t E = run;
+    for (int32_t q0 = tid & ~63; q0 < E; q0 += kBlock * kEdgeUnroll) {
+        int node[kEdgeUnroll];
+        int64_t e[kEdgeUnroll];
+#pragma unroll
+        for (int i = 0; i < kEdgeUnroll; ++i) {
+            const int32_t p = q0 + i * kBlock + lane;
+            node[i] = p < E ? upper_index(vstart, nt, p) : -1;
+            e[i] = node[i] >= 0 ? estart[node[i]] + (p - vstart[node[i]]) : 0;
+        }
+        int32_t u[kEdgeUnroll], w[kEdgeUnroll];
+#pragma unroll
+        for (int i = 0; i < kEdgeUnroll; ++i) {
+            u[i] = node[i] >= 0 ? stream_load(g.adjncy + e[i]) : 0;
+            w[i] = node[i] >= 0 ? stream_edge_weight(g, e[i]) : 0;
+        }
+        int32_t pu[kEdgeUnroll];
+        int64_t ku[kEdgeUnroll];
+#pragma unroll
+        for (int i = 0; i < kEdgeUnroll; ++i) {
+            pu[i] = node[i] >= 0 ? pget(pv, u[i]) : -1;
+            ku[i] = node[i] >= 0 ? key[u[i]] : -1;
+        }
+#pragma unroll
+        for (int i = 0; i < kEdgeUnroll; ++i) {
+            const int nd = node[i];
+            int64_t t = 0;
+            if (nd >= 0) {
+                const int64_t kv = skey[nd];
+                const int32_t a = sa[nd], b = (int32_t)(kv & 0xFFFF);
+                int f = move_sign(pu[i], a, b);
+                if (ku[i] >= 0) {
+                    const int64_t su = ku[i] >> 16, sv = kv >> 16;
+                    if (su > sv || (su == sv && (int64_t)u[i] < v0 + nd)) {
+                        const int ft = move_sign((int32_t)(ku[i] & 0xFFFF), a, b);
+                        f = (optimistic || ft < f) ? ft : f;
+                    }
+                }
+                t = (int64_t)w[i] * f;
+            }
+            // the lanes of one node are consecutive: sum each run
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int64_t ot = __shfl_up(t, off);
+                const int on = __shfl_up(nd, off);
+                if (lane >= off && on == nd) t += ot;
+            }
+            const int nx = __shfl_down(nd, 1);
+            if (nd >= 0 && (lane == 63 || nx != nd)) atomicAdd(&sacc[nd], (unsigned long long)t);
+        }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+
+    // decisions
+    for (int base = 0; base < nt; base += kBlock) {
+        const int i = base + tid;
+        bool take = false;
+        if (i < nt && sa[i] >= 0) {
+            const int64_t v = v0 + i;
+            const int64_t acc = (int64_t)sacc[i];
+            if (gp_out) {
+                gp_out[v] = acc;  // eligible ones are decided against the sequence-aware price
+                accflag[v] = 0;
+            } else {
+                take = acc * 65536 - pen[v] > 0;
+                accflag[v] = take ? 1 : 0;
+                if (take) {
+                    const int32_t A = part[v];
+                    mvto[v] = bk.base(A) + (int32_t)(skey[i] & 0xFFFF);
+                    atomicAdd(&deg_lds, (unsigned long long)(vstart[i + 1] - vstart[i]));
+                }
+            }
+        }
+        wave_count(take, &acc_lds);
+    }
+    __syncthreads();
+    if (tid == 0) {
         if (acc_lds) cnt_add(counters, CNT_ACC, acc_lds);
         if (deg_lds) cnt_add(counters, CNT_MOVED_DEG, deg_lds);
     }
 }
 
 hipError_t launch_filter(const GraphView &g, const Blocks &bk, int optimistic, const int32_t *part,
-                         const PartView &pv, const int64_t *key, const int64_t *pen, int64_t low_t,
-                         int64_t hub_t, int32_t *mvto, uint8_t *accflag,
-                         unsigned long long *counters, int64_t *gp_out, hipStream_t s)
+                         const PartView &pv, const int64_t *key, const int64_t *pen, int64_t hub_t,
+                         int32_t *mvto, uint8_t *accflag, unsigned long long *counters,
+                         int64_t *gp_out, hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_filter, dim3(grid_cap(g.n, kBlock, 8192)), dim3(kBlock), 0, s, g, bk,
-                       optimistic, part, pv, key, pen, low_t, hub_t, mvto, accflag, counters,
-                       gp_out);
+    const int64_t tiles = (g.n + kFilterTile - 1) / kFilterTile;
+    hipLaunchKernelGGL(k_filter, dim3((unsigned)tiles), dim3(kBlock), 0, s, g, bk, optimistic,
+                       part, pv, key, pen, hub_t, mvto, accflag, counters, gp_out);
     return hipGetLastError();
 }
 

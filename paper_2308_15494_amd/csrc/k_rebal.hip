@@ -99,10 +99,54 @@ hipError_t launch_rb_begin(const Blocks &bk, const int64_t *W, const RebalWs &r,
 constexpr int kHistLdsBytes = 49152;
 
 // Nodes of overloaded blocks: target and priority bucket. G lanes per node
-// scan its row (V ints per lane per step): best connected target that stays
-// balanced (max conn, ties to the smaller id) and the lightest such block
-// (min W, ties to the smaller id) as fallback.
-template <int G, int V>
+// scan its row (V ints per lane per vector): best connected target that
+// stays balanced (max conn, ties to the smaller id) and the lightest such
+// block (min W, ties to the smaller id) as fallback.
+
+// One vector of V columns starting at column j0 of a source row.
+template <int V>
+__device__ __forceinline__ void rb_scan_cols(const int32_t (&c)[V], int j0, int32_t a,
+                                             int32_t base, int64_t cv, int64_t lmax,
+                                             const int64_t *W0, int64_t &best, int64_t &lw,
+                                             int32_t &lj, int32_t &ca_mine)
+{
+#pragma unroll
+    for (int t = 0; t < V; ++t) {
+        const int j = j0 + t;
+        if (j == a) {
+            ca_mine = c[t];
+            continue;
+        }
+        const int64_t wj = W0[base + j];
+        if (wj + cv > lmax) continue;
+        if (c[t] > 0) {
+            const int64_t pk = ((int64_t)c[t] << 16) | (int64_t)(0xFFFF - j);
+            if (pk > best) best = pk;
+        }
+        if (wj < lw || (wj == lw && j < lj)) {
+            lw = wj;
+            lj = j;
+        }
+    }
+}
+
+template <int V>
+__device__ __forceinline__ void rb_load_vec(const int32_t *row, int q, int32_t (&c)[V])
+{
+    if constexpr (V == 4) {
+        const v4i32 x = stream_load4(row + 4 * q);
+        c[0] = x.x;
+        c[1] = x.y;
+        c[2] = x.z;
+        c[3] = x.w;
+    } else {
+        c[0] = stream_load(row + q);
+    }
+}
+
+// U source nodes per lane group at a time (their rows loaded together); with
+// U > 1 a row is one vector per lane (k / V <= G).
+template <int G, int V, int U>
 __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
                                                         const int32_t *__restrict__ part,
                                                         const int32_t *__restrict__ conn,
@@ -122,6 +166,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
     __syncthreads();
     const int64_t *W0 = w_lds ? sW : r.W0;
 
+    constexpr int GPW = 64 / G;  // lane groups per wave
     const int lane = lane_id();
     const int grp = lane / G;
     const int gl = lane & (G - 1);
@@ -135,89 +180,95 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
         const uint64_t mask =
             __ballot(lv < g.n && (unsigned)la < (unsigned)K && W0[la] > bk.src_lmax_of(la));
         const int cnt = __popcll(mask);
-        for (int p0 = 0; p0 < cnt; p0 += 64 / G) {
-            const int p = p0 + grp;
-            const bool ok = p < cnt;
-            const int src = ok ? nth_set_bit(mask, p) : 0;
-            const int64_t v = __shfl(lv, src);
-            const int32_t A = __shfl(la, src);
-            const int32_t a = ok ? bk.local(A) : 0;     // row index of the source
-            const int32_t base = ok ? bk.base(A) : 0;  // global id of local block 0
-            const int64_t lmax = ok ? bk.lmax_of(A) : 0;
-            int64_t best = -1, lw = INT64_MAX, cv = 1;
-            int32_t lj = 0x7fffffff;
-            int32_t ca_mine = 0;  // omega(v, V_a), held by the lane that loads column a
-            if (ok) {
-                cv = node_weight(g, v);
-                const int32_t *row = conn + v * (int64_t)k;
-                for (int q = gl; q < nvec; q += G) {
-                    int32_t c4[V];
-                    if constexpr (V == 4) {
-                        const int4 x = ((const int4 *)row)[q];
-                        c4[0] = x.x;
-                        c4[1] = x.y;
-                        c4[2] = x.z;
-                        c4[3] = x.w;
+        for (int p0 = 0; p0 < cnt; p0 += GPW * U) {
+            int64_t vu[U];
+            int32_t Au[U];
+            bool oku[U];
+            int32_t cu[U][V];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int p = p0 + u * GPW + grp;
+                oku[u] = p < cnt;
+                const int src = oku[u] ? nth_set_bit(mask, p) : 0;
+                vu[u] = __shfl(lv, src);
+                Au[u] = __shfl(la, src);
+            }
+            if constexpr (U > 1) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (oku[u] && gl < nvec) {
+                        rb_load_vec<V>(conn + vu[u] * (int64_t)k, gl, cu[u]);
                     } else {
-                        c4[0] = row[q];
-                    }
 #pragma unroll
-                    for (int t = 0; t < V; ++t) {
-                        const int j = q * V + t;
-                        if (j == a) {
-                            ca_mine = c4[t];
-                            continue;
-                        }
-                        const int64_t wj = W0[base + j];
-                        if (wj + cv > lmax) continue;
-                        if (c4[t] > 0) {
-                            const int64_t pk = ((int64_t)c4[t] << 16) | (int64_t)(0xFFFF - j);
-                            if (pk > best) best = pk;
-                        }
-                        if (wj < lw || (wj == lw && j < lj)) {
-                            lw = wj;
-                            lj = j;
-                        }
+                        for (int t = 0; t < V; ++t) cu[u][t] = 0;
                     }
                 }
             }
 #pragma unroll
-            for (int off = G / 2; off > 0; off >>= 1) {
-                const int64_t ob = __shfl_xor(best, off);
-                const int64_t ow = __shfl_xor(lw, off);
-                const int32_t oj = __shfl_xor(lj, off);
-                if (ob > best) best = ob;
-                if (ow < lw || (ow == lw && oj < lj)) {
-                    lw = ow;
-                    lj = oj;
+            for (int u = 0; u < U; ++u) {
+                const bool ok = oku[u];
+                const int64_t v = vu[u];
+                const int32_t A = Au[u];
+                const int32_t a = ok ? bk.local(A) : 0;     // row index of the source
+                const int32_t base = ok ? bk.base(A) : 0;  // global id of local block 0
+                const int64_t lmax = ok ? bk.lmax_of(A) : 0;
+                int64_t best = -1, lw = INT64_MAX, cv = 1;
+                int32_t lj = 0x7fffffff;
+                int32_t ca_mine = 0;  // omega(v, V_a), held by the lane that loads column a
+                if (ok) {
+                    cv = node_weight(g, v);
+                    if constexpr (U > 1) {
+                        if (gl < nvec)
+                            rb_scan_cols<V>(cu[u], gl * V, a, base, cv, lmax, W0, best, lw, lj,
+                                            ca_mine);
+                    } else {
+                        const int32_t *row = conn + v * (int64_t)k;
+                        for (int q = gl; q < nvec; q += G) {
+                            int32_t c[V];
+                            rb_load_vec<V>(row, q, c);
+                            rb_scan_cols<V>(c, q * V, a, base, cv, lmax, W0, best, lw, lj,
+                                            ca_mine);
+                        }
+                    }
                 }
-            }
-            // column a sits in vector a / V, loaded by lane (a / V) mod G of the group
-            const int32_t ca = __shfl(ca_mine, (lane & ~(G - 1)) + ((a / V) & (G - 1)));
-            bool push = false;
-            int64_t hkey = 0;
-            if (ok && gl == 0) {
-                int32_t tgt = -1;
-                int64_t ct = 0;
-                if (best >= 0) {
-                    tgt = 0xFFFF - (int32_t)(best & 0xFFFF);
-                    ct = best >> 16;
-                } else if (lj != 0x7fffffff) {
-                    tgt = lj;
+#pragma unroll
+                for (int off = G / 2; off > 0; off >>= 1) {
+                    const int64_t ob = __shfl_xor(best, off);
+                    const int64_t ow = __shfl_xor(lw, off);
+                    const int32_t oj = __shfl_xor(lj, off);
+                    if (ob > best) best = ob;
+                    if (ow < lw || (ow == lw && oj < lj)) {
+                        lw = ow;
+                        lj = oj;
+                    }
                 }
-                r.rtgt[v] = tgt >= 0 ? base + tgt : -1;
-                if (tgt >= 0) {
-                    // the plain-gain variant ranks by the gain alone (c(v) = 1)
-                    const int be = rebalance_bucket(ct - (int64_t)ca, plain ? 1 : cv);
-                    r.rbeta[v] = (uint8_t)be;
-                    hkey = (int64_t)(base + tgt) * kRbBuckets + be;
-                    push = true;
+                // column a sits in vector a / V, loaded by lane (a / V) mod G of the group
+                const int32_t ca = __shfl(ca_mine, (lane & ~(G - 1)) + ((a / V) & (G - 1)));
+                bool push = false;
+                int64_t hkey = 0;
+                if (ok && gl == 0) {
+                    int32_t tgt = -1;
+                    int64_t ct = 0;
+                    if (best >= 0) {
+                        tgt = 0xFFFF - (int32_t)(best & 0xFFFF);
+                        ct = best >> 16;
+                    } else if (lj != 0x7fffffff) {
+                        tgt = lj;
+                    }
+                    r.rtgt[v] = tgt >= 0 ? base + tgt : -1;
+                    if (tgt >= 0) {
+                        // the plain-gain variant ranks by the gain alone (c(v) = 1)
+                        const int be = rebalance_bucket(ct - (int64_t)ca, plain ? 1 : cv);
+                        r.rbeta[v] = (uint8_t)be;
+                        hkey = (int64_t)(base + tgt) * kRbBuckets + be;
+                        push = true;
+                    }
                 }
-            }
-            if (h_lds) {
-                if (push) atomicAdd(&sH[hkey], (uint32_t)cv);
-            } else {
-                wave_hist_add(r.hist_tgt, hkey, cv, push);
+                if (h_lds) {
+                    if (push) atomicAdd(&sH[hkey], (uint32_t)cv);
+                } else {
+                    wave_hist_add(r.hist_tgt, hkey, cv, push);
+                }
             }
         }
     }
@@ -525,24 +576,26 @@ hipError_t launch_rb_iteration(const GraphView &g, const Blocks &bk, const int32
                         (h_lds ? (size_t)K * kRbBuckets * 4 : 0);
     const bool vec = (k % 4) == 0;
     const int nvec = vec ? k / 4 : k;
-#define UPR_RP(GG, VV)                                                                          \
-    hipLaunchKernelGGL((k_rb_prepare<GG, VV>), dim3(lg), dim3(kBlock), plds, s, g, bk, part, conn, \
-                       r, hist32, plain)
+#define UPR_RP(GG, VV, UU)                                                                      \
+    hipLaunchKernelGGL((k_rb_prepare<GG, VV, UU>), dim3(lg), dim3(kBlock), plds, s, g, bk, part,   \
+                       conn, r, hist32, plain)
     if (vec) {
-        if (nvec <= 1) UPR_RP(1, 4);
-        else if (nvec <= 2) UPR_RP(2, 4);
-        else if (nvec <= 4) UPR_RP(4, 4);
-        else if (nvec <= 8) UPR_RP(8, 4);
-        else if (nvec <= 16) UPR_RP(16, 4);
-        else if (nvec <= 32) UPR_RP(32, 4);
-        else UPR_RP(64, 4);
+        if (nvec <= 1) UPR_RP(1, 4, 4);
+        else if (nvec <= 2) UPR_RP(2, 4, 4);
+        else if (nvec <= 4) UPR_RP(4, 4, 4);
+        else if (nvec <= 8) UPR_RP(8, 4, 4);
+        else if (nvec <= 16) UPR_RP(16, 4, 4);
+        else if (nvec <= 32) UPR_RP(32, 4, 4);
+        else if (nvec <= 64) UPR_RP(64, 4, 4);
+        else UPR_RP(64, 4, 1);
     } else {
-        if (nvec <= 2) UPR_RP(2, 1);
-        else if (nvec <= 4) UPR_RP(4, 1);
-        else if (nvec <= 8) UPR_RP(8, 1);
-        else if (nvec <= 16) UPR_RP(16, 1);
-        else if (nvec <= 32) UPR_RP(32, 1);
-        else UPR_RP(64, 1);
+        if (nvec <= 2) UPR_RP(2, 1, 4);
+        else if (nvec <= 4) UPR_RP(4, 1, 4);
+        else if (nvec <= 8) UPR_RP(8, 1, 4);
+        else if (nvec <= 16) UPR_RP(16, 1, 4);
+        else if (nvec <= 32) UPR_RP(32, 1, 4);
+        else if (nvec <= 64) UPR_RP(64, 1, 4);
+        else UPR_RP(64, 1, 1);
     }
 #undef UPR_RP
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -14,6 +14,14 @@
 // radix sort over the id-ordered input, so equal scores stay in id order; an
 // exclusive scan by block gives, at v's inflow event, the weight change of
 // v's target before v.
+//
+// Two implementations. The segment path (used whenever an event fits one
+// 64-bit key: order, id and the outflow flag) groups the events by block
+// with a counting sort and lets one workgroup per block sort its segment,
+// scan it and decide its inflow events: a candidate's decision involves
+// only its target block, so no list of eligible candidates, no host
+// synchronisation and no separate decision pass are needed. The general
+// path sorts (block, order) keys with a device-wide radix sort.
 #include "upr_common.h"
 
 #include <cstring>
@@ -171,6 +179,796 @@ hipError_t launch_seq_net(int64_t ne, const int32_t *cand, const int64_t *key, c
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_seq_scatter, dim3(grid_for(nev)), dim3(kBlock), 0, s, nev, ev_val2,
                        prefix, netpre);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- segment path --
+//
+// Events are grouped by block with a counting sort (per-block counts, their
+// offsets, placement). A block's segment of at most kRun events is sorted in
+// LDS by one workgroup. A longer segment is split into buckets of about
+// kBucketAvg events by splitters taken from a sorted sample of it (sample
+// sort: the keys are distinct, so ties in the order cannot unbalance the
+// buckets); its events are counted and scattered into the buckets by
+// workgroups over chunks of kChunk events, and every bucket is sorted by its
+// own workgroup. The scan of a bucket starts from the weight change of the
+// buckets before it in its block, summed while counting. A bucket that still
+// exceeds kRun is sorted by its workgroup in runs merged pairwise through
+// global memory (slow, but correct). Bucket boundaries depend on the
+// placement order, the sorted order and the decisions do not.
+
+namespace {
+
+constexpr int kSegBins = 1024;          // blocks up to which placement is aggregated per workgroup
+constexpr int kSegRows = 512;           // most workgroups of the counting and placement passes
+constexpr int kSortItems = 8;           // keys per thread of the workgroup sort
+constexpr int kWaveKeys = 64 * kSortItems;
+constexpr int kRun = kBlock * kSortItems;  // a segment or bucket sorted in LDS in one piece
+constexpr int kSplitThreads = 1024;     // threads of the splitter kernel
+constexpr int kSample = kSplitThreads * kSortItems;  // largest sample
+constexpr int kBucketAvg = 1024;        // average bucket of a split segment
+constexpr int kMaxBuckets = 2048;       // buckets of one segment at most
+constexpr int kOversample = 16;         // samples per bucket
+constexpr int kChunk = 2048;            // events per workgroup while bucketing
+constexpr int kSegMergeItems = 8;       // outputs per thread and step of a merge pass
+constexpr int kOffThreads = 1024;       // threads of the offsets kernels
+
+__host__ __device__ __forceinline__ int seg_buckets(int64_t m)
+{
+    if (m <= kRun) return 1;
+    const int64_t p = (m + kBucketAvg - 1) / kBucketAvg;
+    return p < kMaxBuckets ? (int)p : kMaxBuckets;
+}
+
+__host__ __device__ __forceinline__ int seg_chunks(int64_t m)
+{
+    return m <= kRun ? 0 : (int)((m + kChunk - 1) / kChunk);
+}
+
+// Grid bound of the bucketing passes: the sum over split blocks (fewer than
+// 2n / kRun of them) of m / kChunk + 1.
+int64_t seg_chunk_bound(int64_t n) { return 2 * n / kChunk + 2 * n / kRun + 2; }
+
+// ----------------------------------------------------- workgroup sort --
+//
+// Ascending sort of kSortItems keys per thread, blocked (thread t holds
+// positions t * kSortItems .. + kSortItems - 1). Each wave sorts its
+// kWaveKeys keys with a bitonic network (partners less than kSortItems
+// apart are in the same thread's registers, farther ones in the lane
+// stride / kSortItems away, reached by a shuffle), then the waves' sorted
+// runs are merged pairwise through LDS: each thread finds where its
+// kSortItems outputs start by a binary search over the diagonal (merge
+// path) and merges them sequentially.
+
+__device__ __forceinline__ void wave_bitonic(uint64_t (&k)[kSortItems])
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int size = 2; size <= kWaveKeys; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            if (stride >= kSortItems) {
+                // all partners first (independent shuffles in flight together)
+                const int lx = stride / kSortItems;
+                uint64_t o[kSortItems];
+#pragma unroll
+                for (int j = 0; j < kSortItems; ++j) o[j] = __shfl_xor(k[j], lx);
+                // stride and size are multiples of kSortItems here: the pair's
+                // position bits come from the lane alone
+                const int e = lane * kSortItems;
+                const bool keep_min = ((e & stride) == 0) == ((e & size) == 0);
+#pragma unroll
+                for (int j = 0; j < kSortItems; ++j)
+                    k[j] = ((k[j] < o[j]) == keep_min) ? k[j] : o[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < kSortItems; ++j) {
+                    if (j & stride) continue;
+                    const int j2 = j | stride;
+                    const bool asc = ((lane * kSortItems + j) & size) == 0;
+                    const uint64_t a = k[j], b = k[j2];
+                    const bool sw = (a > b) == asc;
+                    k[j] = sw ? b : a;
+                    k[j2] = sw ? a : b;
+                }
+            }
+        }
+    }
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void block_sort_keys(uint64_t (&k)[kSortItems], uint64_t *lds)
+{
+    wave_bitonic(k);
+    constexpr int N = BLOCK * kSortItems;
+    const int d0 = (int)threadIdx.x * kSortItems;
+#pragma unroll 1
+    for (int r = kWaveKeys; r < N; r <<= 1) {
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) lds[d0 + j] = k[j];
+        __syncthreads();
+        const int a0 = (d0 / (2 * r)) * (2 * r);
+        const uint64_t *A = lds + a0;
+        const uint64_t *Bv = lds + a0 + r;
+        const int diag = d0 - a0;
+        int lo = diag > r ? diag - r : 0;
+        int hi = diag < r ? diag : r;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (A[mid] <= Bv[diag - 1 - mid]) lo = mid + 1;
+            else hi = mid;
+        }
+        int ia = lo, ib = diag - lo;
+        uint64_t va = ia < r ? A[ia] : ~0ull;
+        uint64_t vb = ib < r ? Bv[ib] : ~0ull;
+#pragma unroll
+        for (int q = 0; q < kSortItems; ++q) {
+            if (va <= vb) {
+                k[q] = va;
+                ++ia;
+                va = ia < r ? A[ia] : ~0ull;
+            } else {
+                k[q] = vb;
+                ++ib;
+                vb = ib < r ? Bv[ib] : ~0ull;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------ counting sort --
+
+struct SegGeom {
+    int matrix;    // per-workgroup counts kept as a rows x K matrix
+    int64_t span;  // nodes per workgroup
+    int rows;      // workgroups
+};
+
+SegGeom seg_geom(int64_t n, int K)
+{
+    SegGeom g;
+    g.matrix = K <= kSegBins ? 1 : 0;
+    int64_t G = g.matrix ? std::min<int64_t>(kSegRows, kSegMatEntries / K) : kSegRows;
+    G = std::min<int64_t>(G, (n + kBlock - 1) / kBlock);
+    if (G < 1) G = 1;
+    g.span = (n + G - 1) / G;
+    g.rows = (int)((n + g.span - 1) / g.span);
+    return g;
+}
+
+constexpr int kNodeUnroll = 4;  // nodes per thread and step of the node passes
+
+// The eligible candidates among kNodeUnroll nodes v0 + u * kBlock (u <
+// kNodeUnroll, below hi): inflow block T and own block A (global ids), or
+// T = -1. The loads of the nodes are issued together.
+__device__ __forceinline__ void seg_event_blocks(const int64_t *key, const int64_t *gp,
+                                                 const int32_t *part, const Blocks &bk, int K,
+                                                 int64_t v0, int64_t hi, int64_t (&kv)[kNodeUnroll],
+                                                 int32_t (&A)[kNodeUnroll],
+                                                 int32_t (&T)[kNodeUnroll])
+{
+    int64_t g4[kNodeUnroll];
+#pragma unroll
+    for (int u = 0; u < kNodeUnroll; ++u) {
+        const int64_t v = v0 + (int64_t)u * kBlock;
+        kv[u] = v < hi ? key[v] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kNodeUnroll; ++u)
+        g4[u] = kv[u] >= 0 ? gp[v0 + (int64_t)u * kBlock] : 0;
+#pragma unroll
+    for (int u = 0; u < kNodeUnroll; ++u) {
+        T[u] = -1;
+        A[u] = -1;
+        if (kv[u] >= 0 && g4[u] > 0) {
+            const int32_t a = part[v0 + (int64_t)u * kBlock];
+            if ((unsigned)a < (unsigned)K) {
+                const int32_t t = bk.base(a) + (int32_t)(kv[u] & 0xFFFF);
+                if ((unsigned)t < (unsigned)K) {
+                    A[u] = a;
+                    T[u] = t;
+                }
+            }
+        }
+    }
+}
+
+// Events per block: in matrix form per workgroup (row blockIdx.x), else as
+// global counters.
+__global__ __launch_bounds__(kBlock) void k_seg_count(int64_t n, int64_t span,
+                                                      const int64_t *__restrict__ key,
+                                                      const int64_t *__restrict__ gp,
+                                                      const int32_t *__restrict__ part,
+                                                      const uint8_t *__restrict__ avail, Blocks bk,
+                                                      int matrix, uint32_t *mat,
+                                                      unsigned long long *cnt)
+{
+    __shared__ uint32_t h[kSegBins];
+    const int K = bk.total();
+    if (matrix)
+        for (int j = threadIdx.x; j < K; j += kBlock) h[j] = 0;
+    __syncthreads();
+    const int64_t lo = (int64_t)blockIdx.x * span;
+    const int64_t hi = lo + span < n ? lo + span : n;
+    for (int64_t v0 = lo + threadIdx.x; v0 < hi; v0 += (int64_t)kNodeUnroll * kBlock) {
+        int64_t kv[kNodeUnroll];
+        int32_t A[kNodeUnroll], T[kNodeUnroll];
+        seg_event_blocks(key, gp, part, bk, K, v0, hi, kv, A, T);
+#pragma unroll
+        for (int u = 0; u < kNodeUnroll; ++u) {
+            if (T[u] < 0) continue;
+            const bool out = avail[v0 + (int64_t)u * kBlock] == 0;
+            if (matrix) {
+                atomicAdd(&h[T[u]], 1u);
+                if (out) atomicAdd(&h[A[u]], 1u);
+            } else {
+                atomicAdd(&cnt[T[u]], 1ull);
+                if (out) atomicAdd(&cnt[A[u]], 1ull);
+            }
+        }
+    }
+    if (matrix) {
+        __syncthreads();
+        uint32_t *row = mat + (int64_t)blockIdx.x * K;
+        for (int j = threadIdx.x; j < K; j += kBlock) row[j] = h[j];
+    }
+}
+
+__device__ __forceinline__ int64_t excl_scan_1024(int64_t x, int64_t *lds /* >= 16 */,
+                                                  int64_t *total)
+{
+    const int64_t inc = wave_incl_scan(x);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane_id() == 63) lds[w] = inc;
+    __syncthreads();
+    int64_t base = 0, all = 0;
+    for (int i = 0; i < kOffThreads / 64; ++i) {
+        if (i < w) base += lds[i];
+        all += lds[i];
+    }
+    *total = all;
+    __syncthreads();
+    return base + inc - x;
+}
+
+// Segment starts seg_off[0..K] and the placement cursors (in matrix form
+// each entry (row, B) becomes the position of that workgroup's first event
+// in B's segment; otherwise cnt[B] becomes B's segment start). Then the
+// buckets: boff[B] is B's first bucket (boff[K] buckets in all), cpre[B] the
+// first bucketing chunk of a split block; a block that is not split is one
+// bucket at its segment, a split block's buckets get zeroed accumulators.
+__global__ __launch_bounds__(kOffThreads) void k_seg_offsets(int K, int rows, int matrix,
+                                                             SegWs ws)
+{
+    constexpr int kColBatch = 32;
+    __shared__ int64_t part_s[kOffThreads];
+    __shared__ int64_t segs[kSegBins];
+    __shared__ int64_t wtot[kOffThreads / 64];
+    const int t = threadIdx.x;
+    if (matrix) {
+        const int R = kOffThreads / K;  // row chunks per block (K <= kSegBins <= kOffThreads)
+        const int B = t % K, r = t / K;
+        const bool act = r < R;
+        const int rc = (rows + R - 1) / R;
+        const int r0 = act ? min(rows, r * rc) : 0;
+        const int r1 = act ? min(rows, r0 + rc) : 0;
+        int64_t sum = 0;
+        for (int i = r0; i < r1; i += kColBatch) {
+            uint32_t x[kColBatch];
+#pragma unroll
+            for (int u = 0; u < kColBatch; ++u)
+                x[u] = i + u < r1 ? ws.mat[(int64_t)(i + u) * K + B] : 0u;
+#pragma unroll
+            for (int u = 0; u < kColBatch; ++u) sum += x[u];
+        }
+        part_s[t] = sum;
+        __syncthreads();
+        int64_t coltot = 0;
+        if (t < K) {
+            for (int i = 0; i < R; ++i) {
+                const int64_t x = part_s[i * K + t];
+                part_s[i * K + t] = coltot;
+                coltot += x;
+            }
+        }
+        __syncthreads();
+        int64_t total;
+        const int64_t ex = excl_scan_1024(t < K ? coltot : 0, wtot, &total);
+        if (t < K) {
+            ws.seg_off[t] = ex;
+            segs[t] = ex;
+        }
+        if (t == 0) ws.seg_off[K] = total;
+        __syncthreads();
+        if (act) {
+            int64_t run = segs[B] + part_s[t];
+            for (int i = r0; i < r1; i += kColBatch) {
+                uint32_t x[kColBatch];
+#pragma unroll
+                for (int u = 0; u < kColBatch; ++u)
+                    x[u] = i + u < r1 ? ws.mat[(int64_t)(i + u) * K + B] : 0u;
+#pragma unroll
+                for (int u = 0; u < kColBatch; ++u) {
+                    if (i + u < r1) ws.mat[(int64_t)(i + u) * K + B] = (uint32_t)run;
+                    run += x[u];
+                }
+            }
+        }
+    } else {
+        int64_t carry = 0;
+        for (int b0 = 0; b0 < K; b0 += kOffThreads) {
+            const int B = b0 + t;
+            const int64_t x = B < K ? (int64_t)ws.cur[B] : 0;
+            int64_t total;
+            const int64_t ex = excl_scan_1024(x, wtot, &total);
+            if (B < K) {
+                ws.seg_off[B] = carry + ex;
+                ws.cur[B] = (unsigned long long)(carry + ex);
+            }
+            carry += total;
+        }
+        if (t == 0) ws.seg_off[K] = carry;
+    }
+    __syncthreads();
+    int64_t carry_p = 0, carry_q = 0;
+    for (int b0 = 0; b0 < K; b0 += kOffThreads) {
+        const int B = b0 + t;
+        const int64_t m = B < K ? ws.seg_off[B + 1] - ws.seg_off[B] : 0;
+        const int P = B < K ? seg_buckets(m) : 0;
+        const int Q = B < K ? seg_chunks(m) : 0;
+        int64_t tp, tq;
+        const int64_t ep = excl_scan_1024(P, wtot, &tp);
+        const int64_t eq = excl_scan_1024(Q, wtot, &tq);
+        if (B < K) {
+            const int32_t f = (int32_t)(carry_p + ep);
+            ws.boff[B] = f;
+            ws.cpre[B] = (int32_t)(carry_q + eq);
+            for (int i = 0; i < P; ++i) ws.bblk[f + i] = B;
+            if (P == 1) {
+                ws.bpos[f] = ws.seg_off[B];
+                ws.bsize[f] = m;
+                ws.bdel[f] = 0;
+            } else {
+                for (int i = 0; i < P; ++i) {
+                    ws.bcnt[f + i] = 0;
+                    ws.bdel[f + i] = 0;
+                }
+            }
+        }
+        carry_p += tp;
+        carry_q += tq;
+    }
+    if (t == 0) {
+        ws.boff[K] = (int32_t)carry_p;
+        ws.cpre[K] = (int32_t)carry_q;
+    }
+}
+
+// Each event's key, (order << (idb + 1)) | (v << 1) | outflow, at a free
+// position of its block's segment (the order within a segment is
+// irrelevant: the keys are distinct and are sorted next).
+__global__ __launch_bounds__(kBlock) void k_seg_place(int64_t n, int64_t span,
+                                                      const int64_t *__restrict__ key,
+                                                      const int64_t *__restrict__ gp,
+                                                      const int32_t *__restrict__ part,
+                                                      const uint8_t *__restrict__ avail, Blocks bk,
+                                                      int matrix, SegWs ws, int sb, int idb)
+{
+    __shared__ uint32_t lpos[kSegBins];
+    const int K = bk.total();
+    if (matrix) {
+        const uint32_t *row = ws.mat + (int64_t)blockIdx.x * K;
+        for (int j = threadIdx.x; j < K; j += kBlock) lpos[j] = row[j];
+    }
+    __syncthreads();
+    const uint64_t top = ((uint64_t)1 << sb) - 1;
+    const int64_t lo = (int64_t)blockIdx.x * span;
+    const int64_t hi = lo + span < n ? lo + span : n;
+    for (int64_t v0 = lo + threadIdx.x; v0 < hi; v0 += (int64_t)kNodeUnroll * kBlock) {
+        int64_t kv[kNodeUnroll];
+        int32_t A[kNodeUnroll], T[kNodeUnroll];
+        seg_event_blocks(key, gp, part, bk, K, v0, hi, kv, A, T);
+#pragma unroll
+        for (int u = 0; u < kNodeUnroll; ++u) {
+            if (T[u] < 0) continue;
+            const int64_t v = v0 + (int64_t)u * kBlock;
+            const uint64_t order = top - (uint64_t)(kv[u] >> 16);  // score desc
+            const uint64_t kin = (order << (idb + 1)) | ((uint64_t)v << 1);
+            const uint64_t pt =
+                matrix ? (uint64_t)atomicAdd(&lpos[T[u]], 1u) : atomicAdd(&ws.cur[T[u]], 1ull);
+            ws.ev[pt] = kin;
+            if (avail[v] == 0) {
+                const uint64_t pa = matrix ? (uint64_t)atomicAdd(&lpos[A[u]], 1u)
+                                           : atomicAdd(&ws.cur[A[u]], 1ull);
+                ws.ev[pa] = kin | 1ull;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------- buckets --
+
+// Splitters of a split block: S keys sampled at evenly spaced positions of
+// its segment (kOversample per bucket, at most kSample), sorted; splitter i
+// (1 <= i < P) is sample i * S / P.
+__global__ __launch_bounds__(kSplitThreads) void k_seg_split(SegWs ws)
+{
+    __shared__ uint64_t lds[kSample];
+    const int B = blockIdx.x;
+    const int f = ws.boff[B], P = ws.boff[B + 1] - f;
+    if (P <= 1) return;  // uniform over the workgroup
+    const int64_t s0 = ws.seg_off[B], m = ws.seg_off[B + 1] - s0;
+    int64_t S = (int64_t)P * kOversample;
+    if (S > kSample) S = kSample;
+    if (S > m) S = m;
+    uint64_t k[kSortItems];
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+        const int64_t idx = (int64_t)threadIdx.x * kSortItems + j;
+        k[j] = idx < S ? ws.ev[s0 + (idx * m) / S] : ~0ull;
+    }
+    block_sort_keys<kSplitThreads>(k, lds);
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) lds[threadIdx.x * kSortItems + j] = k[j];
+    __syncthreads();
+    for (int i = 1 + threadIdx.x; i < P; i += kSplitThreads)
+        ws.spl[f + i - 1] = lds[((int64_t)i * S) / P];
+}
+
+// Bucket of a key: the number of splitters not above it.
+__device__ __forceinline__ int bucket_of(const uint64_t *sp, int ns, uint64_t key)
+{
+    int lo = 0, hi = ns;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sp[mid] <= key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// One chunk of a split block's segment per workgroup: count its events per
+// bucket and sum their weight changes (PLACE false), or scatter them into
+// the buckets at the cursors (PLACE true).
+template <bool PLACE>
+__global__ __launch_bounds__(kBlock) void k_seg_bucket(GraphView g, int K, SegWs ws, int idb)
+{
+    constexpr int kPer = kChunk / kBlock;
+    __shared__ uint64_t ssp[kMaxBuckets];
+    __shared__ uint32_t hcnt[kMaxBuckets];
+    __shared__ int64_t hdel[PLACE ? 1 : kMaxBuckets];
+    const int j = blockIdx.x;
+    if (j >= ws.cpre[K]) return;  // uniform over the workgroup
+    const int B = upper_index(ws.cpre, K, j);
+    const int c = j - ws.cpre[B];
+    const int64_t s0 = ws.seg_off[B], m = ws.seg_off[B + 1] - s0;
+    const int f = ws.boff[B], P = ws.boff[B + 1] - f;
+    const int64_t lo = (int64_t)c * kChunk;
+    for (int i = threadIdx.x; i < P - 1; i += kBlock) ssp[i] = ws.spl[f + i];
+    for (int i = threadIdx.x; i < P; i += kBlock) {
+        hcnt[i] = 0;
+        if (!PLACE) hdel[i] = 0;
+    }
+    uint64_t key[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int64_t p = lo + threadIdx.x + (int64_t)u * kBlock;
+        key[u] = p < m ? ws.ev[s0 + p] : ~0ull;
+    }
+    __syncthreads();
+    const uint64_t idmask = ((uint64_t)1 << idb) - 1;
+    int bk[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        bk[u] = -1;
+        if (lo + threadIdx.x + (int64_t)u * kBlock < m) {
+            bk[u] = bucket_of(ssp, P - 1, key[u]);
+            if (!PLACE) {
+                atomicAdd(&hcnt[bk[u]], 1u);
+                const int64_t cv = node_weight(g, (int64_t)((key[u] >> 1) & idmask));
+                atomicAdd((unsigned long long *)&hdel[bk[u]],
+                          (unsigned long long)((key[u] & 1ull) ? -cv : cv));
+            } else {
+                atomicAdd(&hcnt[bk[u]], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    if (!PLACE) {
+        for (int i = threadIdx.x; i < P; i += kBlock)
+            if (hcnt[i]) {
+                atomicAdd(&ws.bcnt[f + i], (unsigned long long)hcnt[i]);
+                atomic_add_i64(&ws.bdel[f + i], hdel[i]);
+            }
+        return;
+    }
+    for (int i = threadIdx.x; i < P; i += kBlock)
+        if (hcnt[i]) hcnt[i] = (uint32_t)atomicAdd(&ws.bcnt[f + i], (unsigned long long)hcnt[i]);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kPer; ++u)
+        if (bk[u] >= 0) ws.tmp[atomicAdd(&hcnt[bk[u]], 1u)] = key[u];
+}
+
+// Buckets of split blocks: start (segment start plus the sizes of the
+// block's earlier buckets), size, carry (the weight change of the block's
+// earlier buckets), and the placement cursor.
+__global__ __launch_bounds__(kOffThreads) void k_seg_boffsets(int K, SegWs ws)
+{
+    __shared__ int64_t wtot[kOffThreads / 64];
+    const int NB = ws.boff[K];
+    const int t = threadIdx.x;
+    int64_t cc = 0, cd = 0;
+    for (int i0 = 0; i0 < NB; i0 += kOffThreads) {
+        const int i = i0 + t;
+        bool split = false;
+        if (i < NB) {
+            const int B = ws.bblk[i];
+            split = ws.boff[B + 1] - ws.boff[B] > 1;
+        }
+        const int64_t x = split ? (int64_t)ws.bcnt[i] : 0;
+        const int64_t y = split ? ws.bdel[i] : 0;
+        int64_t tx, ty;
+        const int64_t ex = excl_scan_1024(x, wtot, &tx);
+        const int64_t ey = excl_scan_1024(y, wtot, &ty);
+        if (i < NB) {
+            ws.scan_c[i] = cc + ex;
+            ws.scan_d[i] = cd + ey;
+        }
+        cc += tx;
+        cd += ty;
+    }
+    __syncthreads();
+    for (int i = t; i < NB; i += kOffThreads) {
+        const int B = ws.bblk[i];
+        const int f = ws.boff[B];
+        if (ws.boff[B + 1] - f <= 1) continue;
+        const int64_t pos = ws.seg_off[B] + ws.scan_c[i] - ws.scan_c[f];
+        ws.bsize[i] = (int64_t)ws.bcnt[i];
+        ws.bpos[i] = pos;
+        ws.bdel[i] = ws.scan_d[i] - ws.scan_d[f];
+        ws.bcnt[i] = (unsigned long long)pos;
+    }
+}
+
+// ----------------------------------------------------------- decide --
+
+// What the decision of an inflow event into block B needs.
+struct SegDecide {
+    GraphView g;
+    int32_t B;
+    int mode;
+    int64_t WB;           // W[B]
+    int64_t move_lmax;    // the fill limit of B's graph
+    const int64_t *cbB;   // B's slot prefix sums
+    const int64_t *penB;  // the penalty table of B's graph
+    uint64_t idmask;
+    const int64_t *gp;
+    int64_t hub_t;
+    int32_t *mvto;
+    uint8_t *accflag;
+};
+
+// The move of v into B, priced against W[B] plus the weight change of the
+// events before it (netpre).
+__device__ __forceinline__ void seg_decide_one(const SegDecide &d, int64_t v, int64_t cv,
+                                               int64_t netpre, unsigned long long *acc_lds,
+                                               unsigned long long *deg_lds)
+{
+    const int64_t gv = d.gp[v];
+    bool allowed = gv > 0;
+    int64_t P = 0;
+    const int64_t x = d.WB + netpre + cv - d.move_lmax;
+    if (allowed && x > 0) {
+        if (d.mode == 1 || d.mode == 3) allowed = false;
+        else if (d.mode == 0) {
+            const int l = covering_slot(d.cbB, x);
+            if (l >= kSlots) allowed = false;
+            else P = sat_mul_pen(d.penB[l], cv);
+        }
+    }
+    const bool take = allowed && gv * 65536 - P > 0;
+    d.accflag[v] = take ? 1 : 0;
+    if (take) {
+        d.mvto[v] = d.B;
+        atomicAdd(acc_lds, 1ull);
+        const int64_t deg = d.g.xadj[v + 1] - d.g.xadj[v];
+        if (deg <= d.hub_t) atomicAdd(deg_lds, (unsigned long long)deg);
+    }
+}
+
+// Scan and decide the kSortItems sorted keys of each thread (blocked: the
+// thread's first key is at position pos0 of the bucket); carry is the
+// weight change of the positions before this piece.
+__device__ __forceinline__ void seg_scan_decide(const uint64_t (&k)[kSortItems], int64_t pos0,
+                                                int64_t m, int64_t &carry, const SegDecide &d,
+                                                int64_t *scan_lds, unsigned long long *acc_lds,
+                                                unsigned long long *deg_lds)
+{
+    int64_t w[kSortItems];
+    int64_t ts = 0;
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+        w[j] = 0;
+        if (pos0 + j < m) {
+            const int64_t v = (int64_t)((k[j] >> 1) & d.idmask);
+            const int64_t c = node_weight(d.g, v);
+            w[j] = (k[j] & 1ull) ? -c : c;
+            ts += w[j];
+        }
+    }
+    int64_t total;
+    const int64_t inc = block_incl_scan(ts, scan_lds, &total);
+    int64_t run = carry + inc - ts;
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+        if (pos0 + j < m && !(k[j] & 1ull))
+            seg_decide_one(d, (int64_t)((k[j] >> 1) & d.idmask), w[j], run, acc_lds, deg_lds);
+        run += w[j];
+    }
+    carry += total;
+}
+
+// One workgroup per bucket: sort it, scan the weight changes from the
+// bucket's carry, decide the inflow events. A bucket beyond kRun is sorted
+// in runs of kRun and merged pairwise through the other buffer (merge path
+// over global memory, kSegMergeItems outputs per thread and step).
+__global__ __launch_bounds__(kBlock) void k_seg_decide(GraphView g, Blocks bk, SegWs ws, int idb,
+                                                       const int64_t *__restrict__ gp,
+                                                       const int64_t *__restrict__ W,
+                                                       const int64_t *__restrict__ cb, int mode,
+                                                       int64_t hub_t, int32_t *mvto,
+                                                       uint8_t *accflag,
+                                                       unsigned long long *counters)
+{
+    __shared__ uint64_t lds[kRun];
+    __shared__ int64_t scan_lds[4];
+    __shared__ unsigned long long acc_lds, deg_lds;
+    const int K = bk.total();
+    const int i = blockIdx.x;
+    if (i >= ws.boff[K]) return;  // uniform over the workgroup
+    const int32_t B = ws.bblk[i];
+    const bool split = ws.boff[B + 1] - ws.boff[B] > 1;
+    const int64_t m = ws.bsize[i];
+    if (m <= 0) return;
+    const int64_t s0 = ws.bpos[i];
+    int64_t carry = split ? ws.bdel[i] : 0;
+    if (threadIdx.x == 0) {
+        acc_lds = 0;
+        deg_lds = 0;
+    }
+    __syncthreads();
+    SegDecide d;
+    d.g = g;
+    d.B = B;
+    d.mode = mode;
+    d.WB = W[B];
+    d.move_lmax = bk.move_lmax_of(B);
+    d.cbB = cb + (int64_t)B * kSlots;
+    d.penB = bk.penq_of(B);
+    d.idmask = ((uint64_t)1 << idb) - 1;
+    d.gp = gp;
+    d.hub_t = hub_t;
+    d.mvto = mvto;
+    d.accflag = accflag;
+    uint64_t *src = (split ? ws.tmp : ws.ev) + s0;
+    uint64_t k[kSortItems];
+    if (m <= kRun) {
+        const int64_t pos0 = (int64_t)threadIdx.x * kSortItems;
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) k[j] = pos0 + j < m ? src[pos0 + j] : ~0ull;
+        block_sort_keys<kBlock>(k, lds);
+        seg_scan_decide(k, pos0, m, carry, d, scan_lds, &acc_lds, &deg_lds);
+    } else {
+        uint64_t *dst = (split ? ws.ev : ws.tmp) + s0;
+        // sorted runs
+        for (int64_t r0 = 0; r0 < m; r0 += kRun) {
+            const int64_t pos0 = r0 + (int64_t)threadIdx.x * kSortItems;
+#pragma unroll
+            for (int j = 0; j < kSortItems; ++j) k[j] = pos0 + j < m ? src[pos0 + j] : ~0ull;
+            block_sort_keys<kBlock>(k, lds);
+#pragma unroll
+            for (int j = 0; j < kSortItems; ++j)
+                if (pos0 + j < m) src[pos0 + j] = k[j];
+            __syncthreads();
+        }
+        // pairwise merges of runs of width w
+        for (int64_t w = kRun; w < m; w <<= 1) {
+            for (int64_t o0 = 0; o0 < m; o0 += (int64_t)kBlock * kSegMergeItems) {
+                const int64_t d0 = o0 + (int64_t)threadIdx.x * kSegMergeItems;
+                if (d0 >= m) continue;
+                const int64_t a0 = (d0 / (2 * w)) * (2 * w);
+                const int64_t a1 = a0 + w < m ? a0 + w : m;
+                const int64_t b1 = a1 + w < m ? a1 + w : m;
+                const int64_t la = a1 - a0, lb = b1 - a1, diag = d0 - a0;
+                int64_t lo = diag - lb > 0 ? diag - lb : 0;
+                int64_t hi = diag < la ? diag : la;
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (src[a0 + mid] <= src[a1 + diag - 1 - mid]) lo = mid + 1;
+                    else hi = mid;
+                }
+                int64_t ia = lo, ib = diag - lo;
+                for (int q = 0; q < kSegMergeItems && d0 + q < b1; ++q) {
+                    const bool ta = ia < la && (ib >= lb || src[a0 + ia] <= src[a1 + ib]);
+                    dst[d0 + q] = ta ? src[a0 + ia++] : src[a1 + ib++];
+                }
+            }
+            __syncthreads();
+            uint64_t *t = src;
+            src = dst;
+            dst = t;
+        }
+        // scan and decide in pieces of kRun
+        for (int64_t r0 = 0; r0 < m; r0 += kRun) {
+            const int64_t pos0 = r0 + (int64_t)threadIdx.x * kSortItems;
+#pragma unroll
+            for (int j = 0; j < kSortItems; ++j) k[j] = pos0 + j < m ? src[pos0 + j] : ~0ull;
+            seg_scan_decide(k, pos0, m, carry, d, scan_lds, &acc_lds, &deg_lds);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (acc_lds) cnt_add(counters, CNT_ACC, acc_lds);
+        if (deg_lds) cnt_add(counters, CNT_MOVED_DEG, deg_lds);
+    }
+}
+
+}  // namespace
+
+int seq_id_bits(int64_t n)
+{
+    return bit_width((uint64_t)(n > 1 ? n - 1 : 1));
+}
+
+// Keys stay below 2^63, so the all-ones padding of the sorts sorts last.
+bool seq_segments_fit(int sb, int64_t n)
+{
+    return sb + seq_id_bits(n) + 1 <= 63;
+}
+
+int64_t seq_bucket_bound(int64_t n, int K)
+{
+    return (int64_t)K + 2 * n / kBucketAvg + 2 * n / kRun + 2;
+}
+
+hipError_t launch_seq_segments(const GraphView &g, const Blocks &bk, const int64_t *key,
+                               const int64_t *gp, const int32_t *part, const uint8_t *avail,
+                               int sb, const SegWs &ws, const int64_t *W, const int64_t *cb,
+                               int mode, int64_t hub_t, int32_t *mvto, uint8_t *accflag,
+                               unsigned long long *counters, hipStream_t s)
+{
+    if (g.n <= 0) return hipSuccess;
+    const int K = bk.total();
+    const int idb = seq_id_bits(g.n);
+    const SegGeom geo = seg_geom(g.n, K);
+    hipError_t e;
+    if (!geo.matrix) {
+        e = launch_fill_i64((int64_t *)ws.cur, K, 0, s);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_seg_count, dim3(geo.rows), dim3(kBlock), 0, s, g.n, geo.span, key, gp,
+                       part, avail, bk, geo.matrix, ws.mat, ws.cur);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_seg_offsets, dim3(1), dim3(kOffThreads), 0, s, K, geo.rows, geo.matrix,
+                       ws);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_seg_place, dim3(geo.rows), dim3(kBlock), 0, s, g.n, geo.span, key, gp,
+                       part, avail, bk, geo.matrix, ws, sb, idb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_seg_split, dim3(K), dim3(kSplitThreads), 0, s, ws);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const unsigned chunks = (unsigned)seg_chunk_bound(g.n);
+    hipLaunchKernelGGL(k_seg_bucket<false>, dim3(chunks), dim3(kBlock), 0, s, g, K, ws, idb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_seg_boffsets, dim3(1), dim3(kOffThreads), 0, s, K, ws);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_seg_bucket<true>, dim3(chunks), dim3(kBlock), 0, s, g, K, ws, idb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_seg_decide, dim3((unsigned)seq_bucket_bound(g.n, K)), dim3(kBlock), 0, s,
+                       g, bk, ws, idb, gp, W, cb, mode, hub_t, mvto, accflag, counters);
     return hipGetLastError();
 }
 

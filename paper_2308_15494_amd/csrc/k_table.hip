@@ -199,18 +199,6 @@ static size_t gain_tile_lds(int32_t k, int T, bool p16)
     return rows + (size_t)(T + 1) * 4 + (size_t)T * 8 + 64;
 }
 
-// Largest i in [0, cnt) with a[i] <= p (a nondecreasing, a[0] <= p).
-__device__ __forceinline__ int upper_index(const int32_t *a, int cnt, int32_t p)
-{
-    int lo = 0, hi = cnt - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (a[mid] <= p) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
 // One workgroup per tile of T consecutive nodes: zero the T x k rows in
 // LDS, accumulate every non-hub edge of the tile (edge-parallel; the edge ->
 // node map is a binary search over the tile's degree prefix), write the rows

@@ -64,6 +64,15 @@ struct upr_ctx {
     uint32_t *ev_val = nullptr, *ev_val2 = nullptr;  // [2n]
     int64_t *ev_prefix = nullptr;                     // [2n]
     int64_t *netpre = nullptr;                        // [n]
+    uint32_t *seg_mat = nullptr;                      // [kSegMatEntries]
+    unsigned long long *seg_cur = nullptr;            // [K]
+    int64_t *seg_off = nullptr;                       // [K + 1]
+    int32_t *seg_boff = nullptr, *seg_cpre = nullptr; // [K + 1]
+    int32_t *seg_bblk = nullptr;                      // [NB] (NB = seq_bucket_bound)
+    int64_t *seg_bpos = nullptr, *seg_bsize = nullptr, *seg_bdel = nullptr;
+    int64_t *seg_scan_c = nullptr, *seg_scan_d = nullptr;
+    unsigned long long *seg_bcnt = nullptr;
+    uint64_t *seg_spl = nullptr;
     void *seq_temp = nullptr;
     size_t seq_temp_size = 0;
     int64_t *bucket = nullptr, *penq = nullptr;
@@ -175,6 +184,19 @@ void free_workspace(upr_ctx *c)
     dfree(c->ev_val2);
     dfree(c->ev_prefix);
     dfree(c->netpre);
+    dfree(c->seg_mat);
+    dfree(c->seg_cur);
+    dfree(c->seg_off);
+    dfree(c->seg_boff);
+    dfree(c->seg_cpre);
+    dfree(c->seg_bblk);
+    dfree(c->seg_bpos);
+    dfree(c->seg_bsize);
+    dfree(c->seg_bdel);
+    dfree(c->seg_scan_c);
+    dfree(c->seg_scan_d);
+    dfree(c->seg_bcnt);
+    dfree(c->seg_spl);
     if (c->seq_temp) (void)hipFree(c->seq_temp);
     c->seq_temp = nullptr;
     c->seq_temp_size = 0;
@@ -205,6 +227,7 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
     const int64_t K = std::max<int64_t>(std::max<int64_t>(k, c->cap_k), 2);
     HIP_TRY(c, hipDeviceSynchronize());
     free_workspace(c);
+    const int64_t NB = seq_bucket_bound(N, (int)K);
     bool ok = dalloc(&c->key, N) == hipSuccess && dalloc(&c->pen, N) == hipSuccess &&
               dalloc(&c->accflag, N) == hipSuccess && dalloc(&c->mvto, N) == hipSuccess &&
               dalloc(&c->dirty, N) == hipSuccess && dalloc(&c->gp, N) == hipSuccess &&
@@ -214,6 +237,14 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
               dalloc(&c->ev_key2, 2 * N) == hipSuccess && dalloc(&c->ev_val, 2 * N) == hipSuccess &&
               dalloc(&c->ev_val2, 2 * N) == hipSuccess && dalloc(&c->ev_prefix, 2 * N) == hipSuccess &&
               dalloc(&c->netpre, N) == hipSuccess &&
+              dalloc(&c->seg_mat, kSegMatEntries) == hipSuccess &&
+              dalloc(&c->seg_cur, K) == hipSuccess && dalloc(&c->seg_off, K + 1) == hipSuccess &&
+              dalloc(&c->seg_boff, K + 1) == hipSuccess && dalloc(&c->seg_cpre, K + 1) == hipSuccess &&
+              dalloc(&c->seg_bblk, NB) == hipSuccess && dalloc(&c->seg_bpos, NB) == hipSuccess &&
+              dalloc(&c->seg_bsize, NB) == hipSuccess && dalloc(&c->seg_bdel, NB) == hipSuccess &&
+              dalloc(&c->seg_scan_c, NB) == hipSuccess &&
+              dalloc(&c->seg_scan_d, NB) == hipSuccess && dalloc(&c->seg_bcnt, NB) == hipSuccess &&
+              dalloc(&c->seg_spl, NB) == hipSuccess &&
               dalloc(&c->bucket, K * kSlots) == hipSuccess && dalloc(&c->pen1, K) == hipSuccess &&
               dalloc(&c->rb.rtgt, N) == hipSuccess && dalloc(&c->rb.rbeta, N) == hipSuccess &&
               dalloc(&c->rb.W0, K) == hipSuccess &&
@@ -912,27 +943,38 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
         {
             PhaseTimer t(c, 3, s);
             int64_t *gp_out = q->seq_penalty ? c->gp : nullptr;
-            HIP_TRY(c, launch_filter(p->g, bk, optimistic, part, pv, c->key, c->pen, p->low_t,
-                                     p->hub_t, c->mvto, c->accflag, c->counters, gp_out, s));
+            HIP_TRY(c, launch_filter(p->g, bk, optimistic, part, pv, c->key, c->pen, p->hub_t,
+                                     c->mvto, c->accflag, c->counters, gp_out, s));
             HIP_TRY(c, launch_filter_hub(p->g, bk, optimistic, part, pv, c->key, c->pen, h,
                                          c->mvto, c->accflag, c->counters, gp_out, s));
             if (q->seq_penalty) {
-                // eligible candidates in id order; their number sizes the sort
-                HIP_TRY(c, launch_seq_select(n, c->key, c->gp, c->cand, c->counters + CNT_ELIG,
-                                             c->seq_temp, c->seq_temp_size, s));
-                rc = sync_counters(c, s);
-                if (rc) return rc;
-                if (c->cnt[CNT_BAD_INPUT])
-                    return fail(c, UPR_E_ARG, b ? "part holds a block outside its graph's range"
-                                                : "part holds values outside [0, k)");
-                const int64_t ne = (int64_t)c->cnt[CNT_ELIG];
-                HIP_TRY(c, launch_seq_net(ne, c->cand, c->key, part, p->g.vwgt, c->avail, bk,
-                                          seq_score_bits(p->maxwdeg), c->ev_key, c->ev_key2,
-                                          c->ev_val, c->ev_val2, c->ev_prefix, c->netpre,
-                                          c->seq_temp, c->seq_temp_size, s));
-                HIP_TRY(c, launch_filter_seq(p->g, bk, part, c->cand, ne, c->key, c->gp,
-                                             c->netpre, W, c->bucket, q->mode, p->hub_t, c->mvto,
-                                             c->accflag, c->counters, s));
+                const int sb = seq_score_bits(p->maxwdeg);
+                if (seq_segments_fit(sb, n)) {
+                    const SegWs ws{c->seg_mat,   c->seg_cur,    c->seg_off,    c->seg_boff,
+                                   c->seg_cpre,  c->seg_bblk,   c->seg_bpos,   c->seg_bsize,
+                                   c->seg_bdel,  c->seg_bcnt,   c->seg_scan_c, c->seg_scan_d,
+                                   c->seg_spl,   c->ev_key,     c->ev_key2};
+                    HIP_TRY(c, launch_seq_segments(p->g, bk, c->key, c->gp, part, c->avail, sb, ws,
+                                                   W, c->bucket, q->mode, p->hub_t, c->mvto,
+                                                   c->accflag, c->counters, s));
+                } else {
+                    // eligible candidates in id order; their number sizes the sort
+                    HIP_TRY(c, launch_seq_select(n, c->key, c->gp, c->cand, c->counters + CNT_ELIG,
+                                                 c->seq_temp, c->seq_temp_size, s));
+                    rc = sync_counters(c, s);
+                    if (rc) return rc;
+                    if (c->cnt[CNT_BAD_INPUT])
+                        return fail(c, UPR_E_ARG, b ? "part holds a block outside its graph's range"
+                                                    : "part holds values outside [0, k)");
+                    const int64_t ne = (int64_t)c->cnt[CNT_ELIG];
+                    HIP_TRY(c, launch_seq_net(ne, c->cand, c->key, part, p->g.vwgt, c->avail, bk, sb,
+                                              c->ev_key, c->ev_key2, c->ev_val, c->ev_val2,
+                                              c->ev_prefix, c->netpre, c->seq_temp,
+                                              c->seq_temp_size, s));
+                    HIP_TRY(c, launch_filter_seq(p->g, bk, part, c->cand, ne, c->key, c->gp,
+                                                 c->netpre, W, c->bucket, q->mode, p->hub_t,
+                                                 c->mvto, c->accflag, c->counters, s));
+                }
             }
             if (b) HIP_TRY(c, launch_batch_move_stats(n, bk, part, c->key, c->accflag, gstat, s));
         }

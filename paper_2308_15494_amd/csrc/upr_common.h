@@ -173,31 +173,38 @@ __device__ __forceinline__ int32_t stream_edge_weight(const GraphView &g, int64_
     return g.adjwgt ? stream_load(g.adjwgt + e) : 1;
 }
 
-// 3^l for l < 54 as a 128-bit value.
-__device__ __forceinline__ unsigned __int128 pow3_u128(int l)
+// 3^l for l < kSlots as 128-bit values (low and high words), built at
+// compile time.
+struct Pow3Table {
+    uint64_t lo[kSlots], hi[kSlots];
+};
+constexpr Pow3Table make_pow3_table()
 {
-    unsigned __int128 r = 1, b = 3;
-    while (l) {
-        if (l & 1) r *= b;
-        b *= b;
-        l >>= 1;
+    Pow3Table t{};
+    unsigned __int128 r = 1;
+    for (int l = 0; l < kSlots; ++l) {
+        t.lo[l] = (uint64_t)r;
+        t.hi[l] = (uint64_t)(r >> 64);
+        r *= 3;
     }
-    return r;
+    return t;
 }
+static __constant__ Pow3Table kPow3 = make_pow3_table();
 
-// Least l in [0, 54) with w * 2^l <= c * 3^l (l = ceil(log_1.5(w / c)) for
-// w > c, 0 for w <= c), 53 if none. Binary search: the predicate is monotone
-// in l because 3^l / 2^l grows.
+// Least l in [0, kSlots) with w * 2^l <= c * 3^l (l = ceil(log_1.5(w / c))
+// for w > c, 0 for w <= c), kSlots - 1 if none. Binary search: the predicate
+// is monotone in l because 3^l / 2^l grows. w < 2^63 and c < 2^31, so both
+// sides fit 128 bits (3^53 < 2^85).
 __device__ __forceinline__ int slot_of(int64_t w, int64_t c)
 {
     if (w <= c) return 0;
-    int lo = 1, hi = kSlots - 1;  // predicate false at 0, answer in [1, 53]
+    const unsigned __int128 W = (uint64_t)w, C = (uint64_t)c;
+    int lo = 1, hi = kSlots - 1;  // predicate false at 0, answer in [1, kSlots - 1]
     while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (((unsigned __int128)(uint64_t)w << mid) <= (unsigned __int128)(uint64_t)c * pow3_u128(mid))
-            hi = mid;
-        else
-            lo = mid + 1;
+        const int mid = (lo + hi) >> 1;
+        const unsigned __int128 p = ((unsigned __int128)kPow3.hi[mid] << 64) | kPow3.lo[mid];
+        if ((W << mid) <= C * p) hi = mid;
+        else lo = mid + 1;
     }
     return lo;
 }
@@ -277,6 +284,31 @@ __device__ __forceinline__ T block_incl_scan(T x, T *lds /* >= 4 */, T *total)
     *total = lds[0] + lds[1] + lds[2] + lds[3];
     __syncthreads();
     return base + inc;
+}
+
+// Least l with cb[l] >= x (cb nondecreasing), kSlots if none.
+__device__ __forceinline__ int covering_slot(const int64_t *cb, int64_t x)
+{
+    if (cb[kSlots - 1] < x) return kSlots;
+    int lo = 0, hi = kSlots - 1;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (cb[mid] >= x) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// Largest i in [0, cnt) with a[i] <= p (a nondecreasing, a[0] <= p).
+__device__ __forceinline__ int upper_index(const int32_t *a, int cnt, int32_t p)
+{
+    int lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (a[mid] <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
 }
 
 // Wave-aggregated append: lanes with pred reserve consecutive slots of a
@@ -435,7 +467,7 @@ hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t 
 // optimistic: an earlier candidate neighbour counts in its target block.
 hipError_t launch_filter(const GraphView &g, const Blocks &bk, int optimistic, const int32_t *part,
                          const PartView &pv,
-                         const int64_t *key, const int64_t *pen, int64_t low_t, int64_t hub_t,
+                         const int64_t *key, const int64_t *pen, int64_t hub_t,
                          int32_t *mvto, uint8_t *accflag, unsigned long long *counters,
                          int64_t *gp_out, hipStream_t s);
 hipError_t launch_filter_hub(const GraphView &g, const Blocks &bk, int optimistic,
@@ -462,6 +494,33 @@ hipError_t launch_seq_net(int64_t ne, const int32_t *cand, const int64_t *key, c
                           uint64_t *ev_key, uint64_t *ev_key2, uint32_t *ev_val,
                           uint32_t *ev_val2, int64_t *prefix, int64_t *netpre, void *temp,
                           size_t temp_bytes, hipStream_t s);
+// Segment path: events grouped by block, each block's segment (split into
+// buckets by sampled splitters when it is long) sorted, scanned and decided
+// by one workgroup per bucket (accflag, mvto, CNT_ACC, CNT_MOVED_DEG as
+// launch_filter_seq). Usable iff seq_segments_fit(sb, n): an event (order,
+// node id, outflow flag) fits 64 bits. NB = seq_bucket_bound(n, K).
+constexpr int kSegMatEntries = 1 << 18;  // per-workgroup block counts (uint32)
+struct SegWs {
+    uint32_t *mat;              // [kSegMatEntries]
+    unsigned long long *cur;    // [K] counts, then placement cursors
+    int64_t *seg_off;           // [K + 1] segment starts
+    int32_t *boff, *cpre;       // [K + 1] first bucket / first bucketing chunk of each block
+    int32_t *bblk;              // [NB] block of each bucket
+    int64_t *bpos, *bsize;      // [NB] bucket start and size
+    int64_t *bdel;              // [NB] weight-change sums, then carries
+    unsigned long long *bcnt;   // [NB] counts, then cursors
+    int64_t *scan_c, *scan_d;   // [NB] scratch of the bucket offsets
+    uint64_t *spl;              // [NB] splitters
+    uint64_t *ev, *tmp;         // [2n] event keys, bucket / merge buffer
+};
+int seq_id_bits(int64_t n);
+int64_t seq_bucket_bound(int64_t n, int K);
+bool seq_segments_fit(int sb, int64_t n);
+hipError_t launch_seq_segments(const GraphView &g, const Blocks &bk, const int64_t *key,
+                               const int64_t *gp, const int32_t *part, const uint8_t *avail,
+                               int sb, const SegWs &ws, const int64_t *W, const int64_t *cb,
+                               int mode, int64_t hub_t, int32_t *mvto, uint8_t *accflag,
+                               unsigned long long *counters, hipStream_t s);
 // Apply every move recorded in mvto (target block, -1 = none) and clear it.
 // If the moving nodes' degrees sum to at most dirty_threshold
 // (counters[CNT_MOVED_DEG]) the neighbours' rows get integer-atomic deltas;

@@ -1,0 +1,116 @@
+"""GPU parity of the sequence-aware filter's two implementations against the
+oracle. The segment path groups the events by block and sorts each block's
+segment in one workgroup: in LDS for segments up to 8192 events in four size
+classes, in sorted runs merged pairwise through global memory beyond that;
+the per-workgroup counts are a matrix for at most 1024 blocks and global
+counters above. The general path (device-wide radix sort) serves graphs whose
+event key does not fit 64 bits. Each case here is sized so that it reaches
+the path it names; the oracle's decisions give the segment sizes."""
+import numpy as np
+import pytest
+
+from paper_2308_15494_amd import graphgen as gg
+from tests.test_gpu_parity import Pair, ctx, say, upr  # noqa: F401  (fixtures)
+
+pytestmark = pytest.mark.gpu
+
+
+def segment_bounds(odbg, part0, k):
+    """Bounds of the largest segment: the most eligible candidates (positive
+    pessimistic gain) entering one block, and the most entering or leaving
+    one block (an outflow event is left out when its node is available for
+    rebalancing)."""
+    elig = (odbg["target"] >= 0) & (odbg["gp"] > 0)
+    inflow = np.bincount(odbg["target"][elig], minlength=k)
+    outflow = np.bincount(part0[elig], minlength=k)
+    return int(inflow.max()), int((inflow + outflow).max())
+
+
+@pytest.mark.parametrize("n,k,lo,hi", [
+    (6000, 64, 1, 256),          # one key per thread
+    (30000, 64, 257, 1024),      # 4 keys per thread
+    (60000, 16, 1025, 4096),     # 16 keys per thread
+    (60000, 4, 2049, 8192),      # 32 keys per thread
+    (250000, 2, 16385, None),    # runs of 8192 merged over at least two passes
+], ids=["s1", "s4", "s16", "s32", "merge"])
+def test_segment_size_classes(upr, ctx, n, k, lo, hi):
+    g = gg.chung_lu(n, 8.0, 2.3, seed=n + k)
+    part0 = gg.random_partition(g.n, k, 3)
+    pr = Pair(upr, ctx, g, k, part0)
+    for r, tau in enumerate([(1, 2), (3, 4)], start=1):
+        say(f"segments n={n} k={k} round {r}")
+        ost, odbg = pr.round(tau=tau)
+        pr.compare(ost, odbg, f"round {r}")
+        if r == 1:
+            smin, smax = segment_bounds(odbg, part0, k)
+            say(f"  largest segment in [{smin}, {smax}]")
+            assert smin >= lo and (hi is None or smax <= hi), (smin, smax)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_segment_merge_modes(upr, ctx, mode):
+    """The decisions of every mode from a long (merged) segment."""
+    g = gg.chung_lu(120000, 8.0, 2.3, seed=77)
+    k = 2
+    pr = Pair(upr, ctx, g, k, gg.random_partition(g.n, k, 5))
+    kw = dict(mode=mode, tau=(1, 2))
+    if mode == 3:
+        kw["alpha"] = (3, 2)
+    part0 = pr.opart.copy()
+    ost, odbg = pr.round(**kw)
+    pr.compare(ost, odbg, f"mode {mode}")
+    assert segment_bounds(odbg, part0, k)[0] > 8192
+
+
+def test_segment_counters_above_1024_blocks(upr, ctx):
+    """A batch of 24 graphs with k = 64 (1536 blocks): placement by global
+    counters; every graph's round equals its own oracle round."""
+    import torch
+    from oracle import oracle as O
+    k = 64
+    graphs = [gg.chung_lu(3000 + 100 * i, 8.0, 2.3, seed=200 + i) for i in range(24)]
+    parts = [gg.random_partition(g.n, k, 300 + i) for i, g in enumerate(graphs)]
+    b = upr.Batch(ctx, graphs, k)
+    b.set_partitions(parts)
+    p = upr.params(k, tau=(2, 3))
+    b.round(p)
+    torch.cuda.synchronize()
+    got = b.graph_stats()
+    loc = b.local_partitions()
+    for i, g in enumerate(graphs):
+        ref = parts[i].copy()
+        st, _ = O.refine_round(g, O.params(k, tau=(2, 3)), ref)
+        assert got[i] == O.stats_dict(st), i
+        assert np.array_equal(loc[i], ref), i
+    b.close()
+
+
+def heavy_hub_graph(n, seed):
+    """Ring plus random chords (weights 1..100) and a hub joined to 160
+    nodes by edges of weight 2^23: the hub's weighted degree needs 31 bits."""
+    rng = np.random.default_rng(seed)
+    ring_u = np.arange(n)
+    ring_v = (ring_u + 1) % n
+    cu = rng.integers(0, n, size=3 * n)
+    cv = rng.integers(0, n, size=3 * n)
+    hub_v = np.arange(1, 161)
+    u = np.concatenate([hub_v * 0, ring_u, cu])
+    v = np.concatenate([hub_v, ring_v, cv])
+    w = np.concatenate([np.full(160, 1 << 23), rng.integers(1, 101, size=n + 3 * n)])
+    xadj, adjncy, adjwgt = gg.csr_from_undirected(n, u, v, w)
+    return gg.Graph(n, xadj, adjncy, adjwgt, None, name=f"heavyhub_n{n}_s{seed}")
+
+
+def test_general_path_wide_keys(upr, ctx):
+    """n = 70000 (17 id bits) and a weighted degree of 31 bits (47 score
+    bits): an event key needs 65 bits, so the device-wide sort runs."""
+    g = heavy_hub_graph(70000, 9)
+    wdeg = np.add.reduceat(g.adjwgt.astype(np.int64), g.xadj[:-1])
+    assert int(wdeg.max()).bit_length() == 31
+    assert (g.n - 1).bit_length() + int(wdeg.max()).bit_length() + 16 + 1 > 64
+    k = 8
+    pr = Pair(upr, ctx, g, k, gg.random_partition(g.n, k, 4))
+    for r, tau in enumerate([(1, 2), (1, 1)], start=1):
+        say(f"wide keys round {r}")
+        ost, odbg = pr.round(tau=tau)
+        pr.compare(ost, odbg, f"round {r}")
