@@ -105,7 +105,8 @@ __global__ __launch_bounds__(kBlock) void k_best_move(
     GraphView g, Blocks bk, const int32_t *__restrict__ part, const int32_t *__restrict__ conn,
     const int64_t *__restrict__ W, const int64_t *__restrict__ cb,
     const int64_t *__restrict__ pen1, int mode, const uint8_t *__restrict__ active,
-    int64_t *__restrict__ key, int64_t *__restrict__ pen, unsigned long long *counters)
+    int64_t *__restrict__ key, int64_t *__restrict__ pen, unsigned long long *counters,
+    uint8_t *cflag)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int32_t k = bk.k;
@@ -199,6 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_best_move(
                 const int32_t j = 0xFFFF - (int32_t)(best & 0xFFFF);
                 key[v] = (sc << 16) | j;
                 pen[v] = bestP;
+                if (cflag) cflag[v] = (uint8_t)(bk.local(A) | kCandFlag);
                 atomicAdd(&cand_lds, 1ull);
             } else {
                 key[v] = -1;
@@ -219,7 +221,8 @@ __global__ __launch_bounds__(kBlock) void k_best_move_reg(
     GraphView g, Blocks bk, const int32_t *__restrict__ part, const int32_t *__restrict__ conn,
     const int64_t *__restrict__ W, const int64_t *__restrict__ cb,
     const int64_t *__restrict__ pen1, int mode, const uint8_t *__restrict__ active,
-    int64_t *__restrict__ key, int64_t *__restrict__ pen, unsigned long long *counters)
+    int64_t *__restrict__ key, int64_t *__restrict__ pen, unsigned long long *counters,
+    uint8_t *cflag)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int32_t k = bk.k;
@@ -339,6 +342,7 @@ __global__ __launch_bounds__(kBlock) void k_best_move_reg(
                     const int32_t j = 0xFFFF - (int32_t)(best & 0xFFFF);
                     key[v] = (sc << 16) | j;
                     pen[v] = bestP;
+                    if (cflag) cflag[v] = (uint8_t)(a | kCandFlag);
                     atomicAdd(&cand_lds, 1ull);
                 } else {
                     key[v] = -1;
@@ -353,7 +357,8 @@ __global__ __launch_bounds__(kBlock) void k_best_move_reg(
 hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t *part,
                             const int32_t *conn, const int64_t *W, const int64_t *cb,
                             const int64_t *pen1, int mode, const uint8_t *active, int64_t *key,
-                            int64_t *pen, unsigned long long *counters, hipStream_t s)
+                            int64_t *pen, unsigned long long *counters, uint8_t *cflag,
+                            hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
     const int32_t k = bk.k;
@@ -364,7 +369,7 @@ hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t 
 #define UPR_BR(GG, RR, UU)                                                                          \
     hipLaunchKernelGGL((k_best_move_reg<GG, RR, UU>),                                               \
                        dim3(grid_cap((g.n + UU - 1) / UU, kBlock / GG, 8192)), dim3(kBlock), lds, s, \
-                       g, bk, part, conn, W, cb, pen1, mode, active, key, pen, counters)
+                       g, bk, part, conn, W, cb, pen1, mode, active, key, pen, counters, cflag)
         if (nvec <= 1) UPR_BR(1, 1, 2);
         else if (nvec <= 2) UPR_BR(2, 1, 2);
         else if (nvec <= 4) UPR_BR(4, 1, 2);
@@ -379,7 +384,8 @@ hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t 
     }
 #define UPR_BM(GG, VV)                                                                             \
     hipLaunchKernelGGL((k_best_move<GG, VV>), dim3(grid_cap(g.n, kBlock / GG, 8192)), dim3(kBlock), \
-                       lds, s, g, bk, part, conn, W, cb, pen1, mode, active, key, pen, counters)
+                       lds, s, g, bk, part, conn, W, cb, pen1, mode, active, key, pen, counters, \
+                       cflag)
     if (vec) {
         if (nvec <= 1) UPR_BM(1, 4);
         else if (nvec <= 2) UPR_BM(2, 4);
@@ -532,10 +538,23 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int o
         }
         int32_t pu[kEdgeUnroll];
         int64_t ku[kEdgeUnroll];
+        if (pv.flagged) {
+            // a neighbour's key only if it is a candidate
+            int32_t raw[kEdgeUnroll];
 #pragma unroll
-        for (int i = 0; i < kEdgeUnroll; ++i) {
-            pu[i] = node[i] >= 0 ? pget(pv, u[i]) : -1;
-            ku[i] = node[i] >= 0 ? key[u[i]] : -1;
+            for (int i = 0; i < kEdgeUnroll; ++i)
+                raw[i] = node[i] >= 0 ? ((const uint8_t *)pv.p)[u[i]] : 0;
+#pragma unroll
+            for (int i = 0; i < kEdgeUnroll; ++i) {
+                pu[i] = node[i] >= 0 ? (raw[i] & (kCandFlag - 1)) : -1;
+                ku[i] = (raw[i] & kCandFlag) ? key[u[i]] : -1;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < kEdgeUnroll; ++i) {
+                pu[i] = node[i] >= 0 ? pget(pv, u[i]) : -1;
+                ku[i] = node[i] >= 0 ? key[u[i]] : -1;
+            }
         }
 #pragma unroll
         for (int i = 0; i < kEdgeUnroll; ++i) {

@@ -392,16 +392,32 @@ int hist32_ok(const upr_plan *p)
 // S5: the host loop over synchronous sub-iterations (one graph).
 int rebalance_loop(upr_ctx *c, const upr_plan *p, const Blocks &bk, int plain, int32_t *part,
                    const PartView &pv, int32_t *conn, int64_t *W, int64_t it_max,
-                   int64_t *iters_out, int64_t *status_out, hipStream_t s)
+                   int64_t *iters_out, int64_t *status_out, hipStream_t s, bool speculate)
 {
     const HubView h = p->hubs();
     int64_t iters = 0, status = 0;
     const int hist32 = hist32_ok(p);
     c->rb_dirty = true;
+    auto sub_iteration = [&]() -> int {
+        HIP_TRY(c, launch_rb_iteration(p->g, bk, part, conn, c->rb, c->mvto, hist32, plain,
+                                       p->hub_t, c->counters, nullptr, s));
+        HIP_TRY(c, launch_apply(p->g, bk, part, pv, conn, W, c->mvto, p->low_t, p->hub_t, h,
+                                c->counters, p->dirty_threshold, c->dirty, s));
+        HIP_TRY(c, launch_rb_begin(bk, W, c->rb, c->counters, nullptr, s));
+        return UPR_OK;
+    };
     HIP_TRY(c, launch_rb_begin(bk, W, c->rb, c->counters, nullptr, s));
-    int rc = sync_counters(c, s);
+    int rc;
+    if (speculate) {
+        // the first sub-iteration without waiting for the count of overloaded
+        // blocks: with none it finds no movable node and changes nothing
+        HIP_TRY(c, launch_cnt_copy(c->counters, CNT_OVER0, CNT_OVER, s));
+        if ((rc = sub_iteration())) return rc;
+    }
+    rc = sync_counters(c, s);
     if (rc) return rc;
     if (c->cnt[CNT_BAD_INPUT]) return fail(c, UPR_E_ARG, "part holds values outside [0, k)");
+    if (speculate && c->cnt[CNT_OVER0] != 0) iters = 1;
     for (;;) {
         if (c->cnt[CNT_OVER] == 0) break;
         if (iters > 0 && c->cnt[CNT_MOVED_NOW] == 0) {
@@ -413,11 +429,7 @@ int rebalance_loop(upr_ctx *c, const upr_plan *p, const Blocks &bk, int plain, i
             break;
         }
         ++iters;
-        HIP_TRY(c, launch_rb_iteration(p->g, bk, part, conn, c->rb, c->mvto, hist32, plain,
-                                       p->hub_t, c->counters, nullptr, s));
-        HIP_TRY(c, launch_apply(p->g, bk, part, pv, conn, W, c->mvto, p->low_t, p->hub_t, h,
-                                c->counters, p->dirty_threshold, c->dirty, s));
-        HIP_TRY(c, launch_rb_begin(bk, W, c->rb, c->counters, nullptr, s));
+        if ((rc = sub_iteration())) return rc;
         rc = sync_counters(c, s);
         if (rc) return rc;
     }
@@ -909,7 +921,7 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
                                  q->rebuild_table, s));
     if (b) HIP_TRY(c, launch_fill_i64(gstat, (int64_t)GS_COUNT * ng, 0, s));
     // compact partition copy for the neighbour gathers (kept in step by the apply)
-    const PartView pv{c->pc, k <= 256 ? 1 : 2};
+    const PartView pv{c->pc, k <= 256 ? 1 : 2, k <= 128 ? 1 : 0};
     HIP_TRY(c, launch_pack_part(n, bk, b ? b->goff_d : nullptr, part, c->pc, pv.bytes, c->counters, s));
     if (q->rebuild_table) {
         {
@@ -934,7 +946,8 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
             PhaseTimer t(c, 2, s);
             HIP_TRY(c, launch_cb_prefix(bk, c->bucket, W, q->mode, c->pen1, s));
             HIP_TRY(c, launch_best_move(p->g, bk, part, conn, W, c->bucket, c->pen1, q->mode,
-                                        active, c->key, c->pen, c->counters, s));
+                                        active, c->key, c->pen, c->counters,
+                                        pv.flagged ? (uint8_t *)c->pc : nullptr, s));
         }
         // no host decision here: with no candidates the filter and the apply
         // find nothing to do; a bad part value is reported at the next
@@ -998,7 +1011,9 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
         } else {
             const int64_t it_max =
                 q->max_rebalance_iters > 0 ? q->max_rebalance_iters : default_iters(p, k);
-            rc = rebalance_loop(c, p, bk, plain, part, pv, conn, W, it_max, &iters, &status, s);
+            // moves can overload a block except in constrained rounds
+            rc = rebalance_loop(c, p, bk, plain, part, pv, conn, W, it_max, &iters, &status, s,
+                                moves && q->mode != 1);
         }
         if (rc) return rc;
     }

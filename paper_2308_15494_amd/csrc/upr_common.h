@@ -31,6 +31,7 @@ enum Counter {
     CNT_TMP,           // scratch accumulator for standalone calls
     CNT_MOVED_DEG,     // sum of the degrees of the nodes marked to move
     CNT_ELIG,          // eligible candidates (pessimistic gain > 0), sequence-aware filter
+    CNT_OVER0,         // overloaded blocks when rebalancing starts
     CNT_COUNT = 32
 };
 
@@ -104,15 +105,23 @@ struct GraphView {
 
 // Read-only view of the partition for neighbour gathers: the caller's int32
 // array, or a compact copy with 1 (k <= 256) or 2 bytes per node that stays
-// resident in L2.
+// resident in L2. flagged (1 byte, k <= 128): bit 7 marks the move
+// candidates of the round (set by the best-move pass, cleared when the copy
+// is rebuilt), so the conflict filter reads a neighbour's key only when it is
+// a candidate.
 struct PartView {
     const void *p;
     int bytes;
+    int flagged = 0;
 };
+constexpr uint8_t kCandFlag = 0x80;
 
 __device__ __forceinline__ int32_t pget(const PartView &pv, int64_t u)
 {
-    if (pv.bytes == 1) return ((const uint8_t *)pv.p)[u];
+    if (pv.bytes == 1) {
+        const int32_t x = ((const uint8_t *)pv.p)[u];
+        return pv.flagged ? (x & (kCandFlag - 1)) : x;
+    }
     if (pv.bytes == 2) return ((const uint16_t *)pv.p)[u];
     return ((const int32_t *)pv.p)[u];
 }
@@ -462,7 +471,8 @@ hipError_t launch_cb_prefix(const Blocks &bk, int64_t *bucket, const int64_t *W,
 hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t *part,
                             const int32_t *conn, const int64_t *W, const int64_t *cb,
                             const int64_t *pen1, int mode, const uint8_t *active, int64_t *key,
-                            int64_t *pen, unsigned long long *counters, hipStream_t s);
+                            int64_t *pen, unsigned long long *counters, uint8_t *cflag,
+                            hipStream_t s);
 // With gp_out the pessimistic gains are stored (decided by launch_filter_seq).
 // optimistic: an earlier candidate neighbour counts in its target block.
 hipError_t launch_filter(const GraphView &g, const Blocks &bk, int optimistic, const int32_t *part,

@@ -233,6 +233,23 @@ def test_round_parity_small(upr, ctx, case, mode, seq):
                 pr.compare(ost, odbg, f"{name} mode {mode} seq {seq} seed {seed} {pname} round {r}")
 
 
+@pytest.mark.parametrize("k", [100, 126, 130, 200, 300, 1100])
+@pytest.mark.parametrize("seq", [1, 0])
+def test_round_parity_large_k(upr, ctx, k, seq):
+    """Rounds at k beyond the small cases: the candidate flag in the one-byte
+    partition copy (k <= 128, with both best-move kernels: k = 100 is a
+    multiple of 4, k = 126 is not), the one-byte copy without it (k = 130,
+    200), the two-byte copy (k = 300) and rows longer than a wave (k = 1100)."""
+    g = gg.chung_lu(6000, 10.0, 2.2, seed=k)
+    for pname, part0 in [("random", gg.random_partition(g.n, k, 1)),
+                         ("skewed", skewed_partition(g.n, k, 2, 0.3))]:
+        say(f"large k={k} seq={seq} start={pname} n={g.n}")
+        pr = Pair(upr, ctx, g, k, part0)
+        for r in range(1, 4):
+            ost, odbg = pr.round(tau=gg.tau_schedule(r, 3), seq_penalty=seq)
+            pr.compare(ost, odbg, f"k {k} seq {seq} {pname} round {r}")
+
+
 VARIANTS = [
     ("limited", dict(mode=3), True),
     ("optimistic", dict(variant=1), False),
