@@ -288,14 +288,16 @@ int64_t upr_lmax(int64_t total, int32_t k, int32_t eps_num, int32_t eps_den);
 int upr_penalty_table(int32_t tau_num, int32_t tau_den, int64_t *out);
 
 /* Per-phase device time of the calls on this context, accumulated in
- * milliseconds by HIP events while timing is enabled (enabling it records
- * events between phases on the call's stream). Phases: 0 gain table,
+ * milliseconds by HIP events while timing is enabled (each timed phase
+ * records two events on the call's stream). Phases: 0 gain table,
  * 1 penalty buckets, 2 best move, 3 filter, 4 apply, 5 rebalance, 6 cut,
  * 7 whole call. Phase 0 is the gain-table tile kernel alone, 1 the hub rows
  * and hub statistics (or, for a resident table, the penalty buckets).
+ * phase_mask: bit p times phase p (0 = off, UPR_TIMING_ALL = every phase).
  * counts[p] = number of intervals accumulated. */
 #define UPR_NUM_PHASES 8
-int upr_timing_enable(upr_ctx *ctx, int enable);
+#define UPR_TIMING_ALL 0xFF
+int upr_timing_enable(upr_ctx *ctx, int phase_mask);
 int upr_timing_read(upr_ctx *ctx, double *ms, int64_t *counts, int reset);
 
 #ifdef __cplusplus

@@ -88,36 +88,56 @@ hipError_t launch_batch_totals(const int64_t *goff, int32_t ng, const int32_t *v
     return hipGetLastError();
 }
 
-// Per-graph candidate and accepted counts after the filter.
-__global__ __launch_bounds__(kBlock) void k_batch_move_stats(int64_t n, Blocks bk,
+// Per-graph candidate and accepted counts after the filter. Each workgroup
+// takes a contiguous node range and sums per graph in LDS over the graphs
+// that own it (a range meets few graphs), then adds one value per graph.
+constexpr int kMoveStatsGraphs = 64;
+__global__ __launch_bounds__(kBlock) void k_batch_move_stats(int64_t n, int64_t span, Blocks bk,
+                                                              const int64_t *goff,
                                                               const int32_t *part,
                                                               const int64_t *key,
                                                               const uint8_t *accflag,
                                                               int64_t *gstat)
 {
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < n;
-         base += stride) {
-        const int64_t v = base + lane_id();
-        bool cand = false, acc = false;
-        int64_t gk = 0;
-        if (v < n) {
-            cand = key[v] >= 0;
-            acc = cand && accflag[v];
-            gk = (int64_t)bk.graph(part[v]) * GS_COUNT;
+    __shared__ unsigned long long lc[kMoveStatsGraphs], la[kMoveStatsGraphs];
+    __shared__ int32_t g0s;
+    const int64_t lo = (int64_t)blockIdx.x * span;
+    const int64_t hi = lo + span < n ? lo + span : n;
+    if (threadIdx.x == 0) g0s = graph_of_node(goff, bk.ng, lo);
+    for (int j = threadIdx.x; j < kMoveStatsGraphs; j += kBlock) {
+        lc[j] = 0;
+        la[j] = 0;
+    }
+    __syncthreads();
+    const int32_t g0 = g0s;
+    for (int64_t v = lo + threadIdx.x; v < hi; v += kBlock) {
+        if (key[v] < 0) continue;
+        const bool acc = accflag[v] != 0;
+        const int32_t gi = bk.graph(part[v]);
+        const uint32_t x = (uint32_t)(gi - g0);
+        if (x < (uint32_t)kMoveStatsGraphs) {
+            atomicAdd(&lc[x], 1ull);
+            if (acc) atomicAdd(&la[x], 1ull);
+        } else {
+            atomic_add_i64(&gstat[(int64_t)gi * GS_COUNT + GS_CAND], 1);
+            if (acc) atomic_add_i64(&gstat[(int64_t)gi * GS_COUNT + GS_ACC], 1);
         }
-        wave_hist_add(gstat, gk + GS_CAND, 1, cand);
-        wave_hist_add(gstat, gk + GS_ACC, 1, acc);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < kMoveStatsGraphs; j += kBlock) {
+        if (lc[j]) atomic_add_i64(&gstat[(int64_t)(g0 + j) * GS_COUNT + GS_CAND], (int64_t)lc[j]);
+        if (la[j]) atomic_add_i64(&gstat[(int64_t)(g0 + j) * GS_COUNT + GS_ACC], (int64_t)la[j]);
     }
 }
 
-hipError_t launch_batch_move_stats(int64_t n, const Blocks &bk, const int32_t *part,
-                                   const int64_t *key, const uint8_t *accflag, int64_t *gstat,
-                                   hipStream_t s)
+hipError_t launch_batch_move_stats(int64_t n, int64_t span, const Blocks &bk, const int64_t *goff,
+                                   const int32_t *part, const int64_t *key,
+                                   const uint8_t *accflag, int64_t *gstat, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_batch_move_stats, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, s, n,
-                       bk, part, key, accflag, gstat);
+    if (span < 1) span = stats_span(n, 0);
+    hipLaunchKernelGGL(k_batch_move_stats, dim3((unsigned)((n + span - 1) / span)), dim3(kBlock),
+                       0, s, n, span, bk, goff, part, key, accflag, gstat);
     return hipGetLastError();
 }
 

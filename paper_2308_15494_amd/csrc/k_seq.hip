@@ -185,7 +185,11 @@ hipError_t launch_seq_net(int64_t ne, const int32_t *cand, const int64_t *key, c
 // ------------------------------------------------------- segment path --
 //
 // Events are grouped by block with a counting sort (per-block counts, their
-// offsets, placement). A block's segment of at most kRun events is sorted in
+// offsets, placement). Each workgroup of the counting passes takes a
+// contiguous node range; in a batch its events fall into the blocks of the
+// few graphs that own those nodes, so it counts them in LDS over that window
+// of blocks and reserves its slots with one global atomic per block. A
+// block's segment of at most kRun events is sorted in
 // LDS by one workgroup. A longer segment is split into buckets of about
 // kBucketAvg events by splitters taken from a sorted sample of it (sample
 // sort: the keys are distinct, so ties in the order cannot unbalance the
@@ -199,7 +203,7 @@ hipError_t launch_seq_net(int64_t ne, const int32_t *cand, const int64_t *key, c
 
 namespace {
 
-constexpr int kSegBins = 1024;          // blocks up to which placement is aggregated per workgroup
+constexpr int kSegBins = 2048;          // block window up to which a workgroup aggregates in LDS
 constexpr int kSegRows = 512;           // most workgroups of the counting and placement passes
 constexpr int kSortItems = 8;           // keys per thread of the workgroup sort
 constexpr int kWaveKeys = 64 * kSortItems;
@@ -320,17 +324,14 @@ __device__ __forceinline__ void block_sort_keys(uint64_t (&k)[kSortItems], uint6
 // ------------------------------------------------------ counting sort --
 
 struct SegGeom {
-    int matrix;    // per-workgroup counts kept as a rows x K matrix
-    int64_t span;  // nodes per workgroup
+    int64_t span;  // nodes per workgroup (contiguous)
     int rows;      // workgroups
 };
 
-SegGeom seg_geom(int64_t n, int K)
+SegGeom seg_geom(int64_t n)
 {
     SegGeom g;
-    g.matrix = K <= kSegBins ? 1 : 0;
-    int64_t G = g.matrix ? std::min<int64_t>(kSegRows, kSegMatEntries / K) : kSegRows;
-    G = std::min<int64_t>(G, (n + kBlock - 1) / kBlock);
+    int64_t G = std::min<int64_t>(kSegRows, (n + kBlock - 1) / kBlock);
     if (G < 1) G = 1;
     g.span = (n + G - 1) / G;
     g.rows = (int)((n + g.span - 1) / g.span);
@@ -338,6 +339,24 @@ SegGeom seg_geom(int64_t n, int K)
 }
 
 constexpr int kNodeUnroll = 4;  // nodes per thread and step of the node passes
+
+// Counter copies per block for the counting sort: with few blocks every
+// workgroup would add to the same few addresses, so block B's count and
+// cursor are split over C copies (workgroup w uses copy w mod C), laid out
+// as the sub-ranges B * C + c of B's segment.
+__host__ __device__ __forceinline__ int seg_copies(int K)
+{
+    int c = 1;
+    while (c < 8 && (int64_t)K * c * 2 <= kSegCopyEntries) c <<= 1;
+    return c;
+}
+
+// Counter of copy c of block B; with copies, each counter has a cache line
+// of its own (atomics on one line are serialised).
+__host__ __device__ __forceinline__ int64_t seg_slot(int B, int c, int C)
+{
+    return ((int64_t)B * C + c) * (C > 1 ? kSegCopyPad : 1);
+}
 
 // The eligible candidates among kNodeUnroll nodes v0 + u * kBlock (u <
 // kNodeUnroll, below hi): inflow block T and own block A (global ids), or
@@ -374,23 +393,42 @@ __device__ __forceinline__ void seg_event_blocks(const int64_t *key, const int64
     }
 }
 
-// Events per block: in matrix form per workgroup (row blockIdx.x), else as
-// global counters.
+// Node range and block window of this workgroup; zeroes the LDS counts if
+// the window fits. Returns whether it does.
+__device__ __forceinline__ bool seg_window(int64_t n, int64_t span, const Blocks &bk,
+                                           const int64_t *goff, uint32_t *h, int32_t *win,
+                                           int64_t *lo, int64_t *hi, int32_t *B0, int32_t *nb)
+{
+    *lo = (int64_t)blockIdx.x * span;
+    *hi = *lo + span < n ? *lo + span : n;
+    if (threadIdx.x == 0) node_block_window(bk, goff, *lo, *hi, &win[0], &win[1]);
+    __syncthreads();
+    *B0 = win[0];
+    *nb = win[1];
+    const bool lds = *nb <= kSegBins;
+    if (lds)
+        for (int j = threadIdx.x; j < *nb; j += kBlock) h[j] = 0;
+    __syncthreads();
+    return lds;
+}
+
+// Events per block into cnt (zeroed before).
 __global__ __launch_bounds__(kBlock) void k_seg_count(int64_t n, int64_t span,
                                                       const int64_t *__restrict__ key,
                                                       const int64_t *__restrict__ gp,
                                                       const int32_t *__restrict__ part,
                                                       const uint8_t *__restrict__ avail, Blocks bk,
-                                                      int matrix, uint32_t *mat,
+                                                      const int64_t *__restrict__ goff,
                                                       unsigned long long *cnt)
 {
     __shared__ uint32_t h[kSegBins];
+    __shared__ int32_t win[2];
     const int K = bk.total();
-    if (matrix)
-        for (int j = threadIdx.x; j < K; j += kBlock) h[j] = 0;
-    __syncthreads();
-    const int64_t lo = (int64_t)blockIdx.x * span;
-    const int64_t hi = lo + span < n ? lo + span : n;
+    const int C = seg_copies(K);
+    const int copy = (int)blockIdx.x & (C - 1);
+    int64_t lo, hi;
+    int32_t B0, nb;
+    const bool lds = seg_window(n, span, bk, goff, h, win, &lo, &hi, &B0, &nb);
     for (int64_t v0 = lo + threadIdx.x; v0 < hi; v0 += (int64_t)kNodeUnroll * kBlock) {
         int64_t kv[kNodeUnroll];
         int32_t A[kNodeUnroll], T[kNodeUnroll];
@@ -399,20 +437,19 @@ __global__ __launch_bounds__(kBlock) void k_seg_count(int64_t n, int64_t span,
         for (int u = 0; u < kNodeUnroll; ++u) {
             if (T[u] < 0) continue;
             const bool out = avail[v0 + (int64_t)u * kBlock] == 0;
-            if (matrix) {
-                atomicAdd(&h[T[u]], 1u);
-                if (out) atomicAdd(&h[A[u]], 1u);
-            } else {
-                atomicAdd(&cnt[T[u]], 1ull);
-                if (out) atomicAdd(&cnt[A[u]], 1ull);
+            const uint32_t xt = (uint32_t)(T[u] - B0), xa = (uint32_t)(A[u] - B0);
+            if (lds && xt < (uint32_t)nb) atomicAdd(&h[xt], 1u);
+            else atomicAdd(&cnt[seg_slot(T[u], copy, C)], 1ull);
+            if (out) {
+                if (lds && xa < (uint32_t)nb) atomicAdd(&h[xa], 1u);
+                else atomicAdd(&cnt[seg_slot(A[u], copy, C)], 1ull);
             }
         }
     }
-    if (matrix) {
-        __syncthreads();
-        uint32_t *row = mat + (int64_t)blockIdx.x * K;
-        for (int j = threadIdx.x; j < K; j += kBlock) row[j] = h[j];
-    }
+    __syncthreads();
+    if (lds)
+        for (int j = threadIdx.x; j < nb; j += kBlock)
+            if (h[j]) atomicAdd(&cnt[seg_slot(B0 + j, copy, C)], (unsigned long long)h[j]);
 }
 
 __device__ __forceinline__ int64_t excl_scan_1024(int64_t x, int64_t *lds /* >= 16 */,
@@ -433,139 +470,119 @@ __device__ __forceinline__ int64_t excl_scan_1024(int64_t x, int64_t *lds /* >= 
     return base + inc - x;
 }
 
-// Segment starts seg_off[0..K] and the placement cursors (in matrix form
-// each entry (row, B) becomes the position of that workgroup's first event
-// in B's segment; otherwise cnt[B] becomes B's segment start). Then the
-// buckets: boff[B] is B's first bucket (boff[K] buckets in all), cpre[B] the
-// first bucketing chunk of a split block; a block that is not split is one
-// bucket at its segment, a split block's buckets get zeroed accumulators.
-__global__ __launch_bounds__(kOffThreads) void k_seg_offsets(int K, int rows, int matrix,
-                                                             SegWs ws)
+// Segment starts seg_off[0..K] (cur[B] becomes B's placement cursor). Then
+// the buckets: boff[B] is B's first bucket (boff[K] buckets in all), cpre[B]
+// the first bucketing chunk of a split block, slist the split blocks
+// (meta[0] of them); a block that is not split is one bucket at its
+// segment, a split block's buckets get zeroed accumulators.
+__global__ __launch_bounds__(kOffThreads) void k_seg_offsets(int K, SegWs ws)
 {
-    constexpr int kColBatch = 32;
-    __shared__ int64_t part_s[kOffThreads];
-    __shared__ int64_t segs[kSegBins];
     __shared__ int64_t wtot[kOffThreads / 64];
     const int t = threadIdx.x;
-    if (matrix) {
-        const int R = kOffThreads / K;  // row chunks per block (K <= kSegBins <= kOffThreads)
-        const int B = t % K, r = t / K;
-        const bool act = r < R;
-        const int rc = (rows + R - 1) / R;
-        const int r0 = act ? min(rows, r * rc) : 0;
-        const int r1 = act ? min(rows, r0 + rc) : 0;
-        int64_t sum = 0;
-        for (int i = r0; i < r1; i += kColBatch) {
-            uint32_t x[kColBatch];
-#pragma unroll
-            for (int u = 0; u < kColBatch; ++u)
-                x[u] = i + u < r1 ? ws.mat[(int64_t)(i + u) * K + B] : 0u;
-#pragma unroll
-            for (int u = 0; u < kColBatch; ++u) sum += x[u];
-        }
-        part_s[t] = sum;
-        __syncthreads();
-        int64_t coltot = 0;
-        if (t < K) {
-            for (int i = 0; i < R; ++i) {
-                const int64_t x = part_s[i * K + t];
-                part_s[i * K + t] = coltot;
-                coltot += x;
-            }
-        }
-        __syncthreads();
+    const int C = seg_copies(K);
+    const int KC = K * C;
+    int64_t carry = 0;
+    for (int b0 = 0; b0 < KC; b0 += kOffThreads) {
+        const int i = b0 + t;
+        const int64_t slot = seg_slot(i / C, i & (C - 1), C);
+        const int64_t x = i < KC ? (int64_t)ws.cur[slot] : 0;
         int64_t total;
-        const int64_t ex = excl_scan_1024(t < K ? coltot : 0, wtot, &total);
-        if (t < K) {
-            ws.seg_off[t] = ex;
-            segs[t] = ex;
+        const int64_t ex = excl_scan_1024(x, wtot, &total);
+        if (i < KC) {
+            if ((i & (C - 1)) == 0) ws.seg_off[i / C] = carry + ex;
+            ws.cur[slot] = (unsigned long long)(carry + ex);
         }
-        if (t == 0) ws.seg_off[K] = total;
-        __syncthreads();
-        if (act) {
-            int64_t run = segs[B] + part_s[t];
-            for (int i = r0; i < r1; i += kColBatch) {
-                uint32_t x[kColBatch];
-#pragma unroll
-                for (int u = 0; u < kColBatch; ++u)
-                    x[u] = i + u < r1 ? ws.mat[(int64_t)(i + u) * K + B] : 0u;
-#pragma unroll
-                for (int u = 0; u < kColBatch; ++u) {
-                    if (i + u < r1) ws.mat[(int64_t)(i + u) * K + B] = (uint32_t)run;
-                    run += x[u];
-                }
-            }
-        }
-    } else {
-        int64_t carry = 0;
-        for (int b0 = 0; b0 < K; b0 += kOffThreads) {
-            const int B = b0 + t;
-            const int64_t x = B < K ? (int64_t)ws.cur[B] : 0;
-            int64_t total;
-            const int64_t ex = excl_scan_1024(x, wtot, &total);
-            if (B < K) {
-                ws.seg_off[B] = carry + ex;
-                ws.cur[B] = (unsigned long long)(carry + ex);
-            }
-            carry += total;
-        }
-        if (t == 0) ws.seg_off[K] = carry;
+        carry += total;
     }
+    if (t == 0) ws.seg_off[K] = carry;
     __syncthreads();
-    int64_t carry_p = 0, carry_q = 0;
+    int64_t carry_p = 0, carry_q = 0, carry_s = 0;
     for (int b0 = 0; b0 < K; b0 += kOffThreads) {
         const int B = b0 + t;
         const int64_t m = B < K ? ws.seg_off[B + 1] - ws.seg_off[B] : 0;
         const int P = B < K ? seg_buckets(m) : 0;
         const int Q = B < K ? seg_chunks(m) : 0;
-        int64_t tp, tq;
+        int64_t tp, tq, ts;
         const int64_t ep = excl_scan_1024(P, wtot, &tp);
         const int64_t eq = excl_scan_1024(Q, wtot, &tq);
+        const int64_t es = excl_scan_1024(P > 1 ? 1 : 0, wtot, &ts);
         if (B < K) {
             const int32_t f = (int32_t)(carry_p + ep);
             ws.boff[B] = f;
             ws.cpre[B] = (int32_t)(carry_q + eq);
-            for (int i = 0; i < P; ++i) ws.bblk[f + i] = B;
             if (P == 1) {
+                ws.bblk[f] = B;
                 ws.bpos[f] = ws.seg_off[B];
                 ws.bsize[f] = m;
                 ws.bdel[f] = 0;
             } else {
-                for (int i = 0; i < P; ++i) {
-                    ws.bcnt[f + i] = 0;
-                    ws.bdel[f + i] = 0;
-                }
+                ws.slist[carry_s + es] = B;
             }
         }
         carry_p += tp;
         carry_q += tq;
+        carry_s += ts;
     }
     if (t == 0) {
         ws.boff[K] = (int32_t)carry_p;
         ws.cpre[K] = (int32_t)carry_q;
+        ws.meta[0] = (int32_t)carry_s;
+    }
+    __syncthreads();
+    // the buckets of split blocks, by all threads
+    for (int j = 0; j < (int)carry_s; ++j) {
+        const int B = ws.slist[j];
+        const int f = ws.boff[B], P = ws.boff[B + 1] - f;
+        for (int i = t; i < P; i += kOffThreads) {
+            ws.bblk[f + i] = B;
+            ws.bcnt[f + i] = 0;
+            ws.bdel[f + i] = 0;
+        }
     }
 }
 
 // Each event's key, (order << (idb + 1)) | (v << 1) | outflow, at a free
 // position of its block's segment (the order within a segment is
-// irrelevant: the keys are distinct and are sorted next).
+// irrelevant: the keys are distinct and are sorted next). The workgroup
+// counts its events per block of its window, reserves each block's slots
+// with one atomic, then hands them out in LDS.
 __global__ __launch_bounds__(kBlock) void k_seg_place(int64_t n, int64_t span,
                                                       const int64_t *__restrict__ key,
                                                       const int64_t *__restrict__ gp,
                                                       const int32_t *__restrict__ part,
                                                       const uint8_t *__restrict__ avail, Blocks bk,
-                                                      int matrix, SegWs ws, int sb, int idb)
+                                                      const int64_t *__restrict__ goff, SegWs ws,
+                                                      int sb, int idb)
 {
-    __shared__ uint32_t lpos[kSegBins];
+    __shared__ uint32_t h[kSegBins];
+    __shared__ int32_t win[2];
     const int K = bk.total();
-    if (matrix) {
-        const uint32_t *row = ws.mat + (int64_t)blockIdx.x * K;
-        for (int j = threadIdx.x; j < K; j += kBlock) lpos[j] = row[j];
+    const int C = seg_copies(K);
+    const int copy = (int)blockIdx.x & (C - 1);
+    int64_t lo, hi;
+    int32_t B0, nb;
+    const bool lds = seg_window(n, span, bk, goff, h, win, &lo, &hi, &B0, &nb);
+    if (lds) {
+        for (int64_t v0 = lo + threadIdx.x; v0 < hi; v0 += (int64_t)kNodeUnroll * kBlock) {
+            int64_t kv[kNodeUnroll];
+            int32_t A[kNodeUnroll], T[kNodeUnroll];
+            seg_event_blocks(key, gp, part, bk, K, v0, hi, kv, A, T);
+#pragma unroll
+            for (int u = 0; u < kNodeUnroll; ++u) {
+                if (T[u] < 0) continue;
+                const uint32_t xt = (uint32_t)(T[u] - B0), xa = (uint32_t)(A[u] - B0);
+                if (xt < (uint32_t)nb) atomicAdd(&h[xt], 1u);
+                if (avail[v0 + (int64_t)u * kBlock] == 0 && xa < (uint32_t)nb) atomicAdd(&h[xa], 1u);
+            }
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < nb; j += kBlock)
+            if (h[j])
+                h[j] = (uint32_t)atomicAdd(&ws.cur[seg_slot(B0 + j, copy, C)],
+                                           (unsigned long long)h[j]);
+        __syncthreads();
     }
-    __syncthreads();
     const uint64_t top = ((uint64_t)1 << sb) - 1;
-    const int64_t lo = (int64_t)blockIdx.x * span;
-    const int64_t hi = lo + span < n ? lo + span : n;
     for (int64_t v0 = lo + threadIdx.x; v0 < hi; v0 += (int64_t)kNodeUnroll * kBlock) {
         int64_t kv[kNodeUnroll];
         int32_t A[kNodeUnroll], T[kNodeUnroll];
@@ -576,12 +593,15 @@ __global__ __launch_bounds__(kBlock) void k_seg_place(int64_t n, int64_t span,
             const int64_t v = v0 + (int64_t)u * kBlock;
             const uint64_t order = top - (uint64_t)(kv[u] >> 16);  // score desc
             const uint64_t kin = (order << (idb + 1)) | ((uint64_t)v << 1);
-            const uint64_t pt =
-                matrix ? (uint64_t)atomicAdd(&lpos[T[u]], 1u) : atomicAdd(&ws.cur[T[u]], 1ull);
+            const uint32_t xt = (uint32_t)(T[u] - B0), xa = (uint32_t)(A[u] - B0);
+            const uint64_t pt = (lds && xt < (uint32_t)nb)
+                                    ? (uint64_t)atomicAdd(&h[xt], 1u)
+                                    : atomicAdd(&ws.cur[seg_slot(T[u], copy, C)], 1ull);
             ws.ev[pt] = kin;
             if (avail[v] == 0) {
-                const uint64_t pa = matrix ? (uint64_t)atomicAdd(&lpos[A[u]], 1u)
-                                           : atomicAdd(&ws.cur[A[u]], 1ull);
+                const uint64_t pa = (lds && xa < (uint32_t)nb)
+                                        ? (uint64_t)atomicAdd(&h[xa], 1u)
+                                        : atomicAdd(&ws.cur[seg_slot(A[u], copy, C)], 1ull);
                 ws.ev[pa] = kin | 1ull;
             }
         }
@@ -596,9 +616,9 @@ __global__ __launch_bounds__(kBlock) void k_seg_place(int64_t n, int64_t span,
 __global__ __launch_bounds__(kSplitThreads) void k_seg_split(SegWs ws)
 {
     __shared__ uint64_t lds[kSample];
-    const int B = blockIdx.x;
+    if ((int)blockIdx.x >= ws.meta[0]) return;  // uniform over the workgroup
+    const int B = ws.slist[blockIdx.x];
     const int f = ws.boff[B], P = ws.boff[B + 1] - f;
-    if (P <= 1) return;  // uniform over the workgroup
     const int64_t s0 = ws.seg_off[B], m = ws.seg_off[B + 1] - s0;
     int64_t S = (int64_t)P * kOversample;
     if (S > kSample) S = kSample;
@@ -934,31 +954,30 @@ int64_t seq_bucket_bound(int64_t n, int K)
     return (int64_t)K + 2 * n / kBucketAvg + 2 * n / kRun + 2;
 }
 
-hipError_t launch_seq_segments(const GraphView &g, const Blocks &bk, const int64_t *key,
-                               const int64_t *gp, const int32_t *part, const uint8_t *avail,
-                               int sb, const SegWs &ws, const int64_t *W, const int64_t *cb,
-                               int mode, int64_t hub_t, int32_t *mvto, uint8_t *accflag,
-                               unsigned long long *counters, hipStream_t s)
+hipError_t launch_seq_segments(const GraphView &g, const Blocks &bk, const int64_t *goff,
+                               const int64_t *key, const int64_t *gp, const int32_t *part,
+                               const uint8_t *avail, int sb, const SegWs &ws, const int64_t *W,
+                               const int64_t *cb, int mode, int64_t hub_t, int32_t *mvto,
+                               uint8_t *accflag, unsigned long long *counters, hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
     const int K = bk.total();
     const int idb = seq_id_bits(g.n);
-    const SegGeom geo = seg_geom(g.n, K);
-    hipError_t e;
-    if (!geo.matrix) {
-        e = launch_fill_i64((int64_t *)ws.cur, K, 0, s);
-        if (e != hipSuccess) return e;
-    }
+    const SegGeom geo = seg_geom(g.n);
+    const int C = seg_copies(K);
+    hipError_t e = launch_fill_i64((int64_t *)ws.cur, seg_slot(K, 0, C), 0, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_seg_count, dim3(geo.rows), dim3(kBlock), 0, s, g.n, geo.span, key, gp,
-                       part, avail, bk, geo.matrix, ws.mat, ws.cur);
+                       part, avail, bk, goff, ws.cur);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_seg_offsets, dim3(1), dim3(kOffThreads), 0, s, K, geo.rows, geo.matrix,
-                       ws);
+    hipLaunchKernelGGL(k_seg_offsets, dim3(1), dim3(kOffThreads), 0, s, K, ws);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_seg_place, dim3(geo.rows), dim3(kBlock), 0, s, g.n, geo.span, key, gp,
-                       part, avail, bk, geo.matrix, ws, sb, idb);
+                       part, avail, bk, goff, ws, sb, idb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_seg_split, dim3(K), dim3(kSplitThreads), 0, s, ws);
+    // split blocks hold more than kRun events each
+    const int64_t splits = std::min<int64_t>(K, 2 * g.n / kRun + 1);
+    hipLaunchKernelGGL(k_seg_split, dim3((unsigned)splits), dim3(kSplitThreads), 0, s, ws);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const unsigned chunks = (unsigned)seg_chunk_bound(g.n);
     hipLaunchKernelGGL(k_seg_bucket<false>, dim3(chunks), dim3(kBlock), 0, s, g, K, ws, idb);

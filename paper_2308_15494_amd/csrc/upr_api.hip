@@ -26,7 +26,7 @@ constexpr int64_t kDefaultLowThreshold = 32;
 constexpr int64_t kChunkEntries = int64_t(1) << 20;  // rebalancing id-chunk sums per side
 
 struct Timing {
-    bool on = false;
+    uint32_t mask = 0;  // phases timed (bit p = phase p)
     std::vector<hipEvent_t> pool;
     struct Pending {
         int phase;
@@ -64,8 +64,9 @@ struct upr_ctx {
     uint32_t *ev_val = nullptr, *ev_val2 = nullptr;  // [2n]
     int64_t *ev_prefix = nullptr;                     // [2n]
     int64_t *netpre = nullptr;                        // [n]
-    uint32_t *seg_mat = nullptr;                      // [kSegMatEntries]
     unsigned long long *seg_cur = nullptr;            // [K]
+    int32_t *seg_slist = nullptr;                     // [K]
+    int32_t *seg_meta = nullptr;                      // [4]
     int64_t *seg_off = nullptr;                       // [K + 1]
     int32_t *seg_boff = nullptr, *seg_cpre = nullptr; // [K + 1]
     int32_t *seg_bblk = nullptr;                      // [NB] (NB = seq_bucket_bound)
@@ -130,6 +131,10 @@ struct upr_batch {
     int64_t *gstat_d = nullptr, *host3_d = nullptr;
     // pinned mirrors (in the context's batch area, valid while the batch runs)
     int64_t *gstat_h = nullptr, *srcl_h = nullptr, *penq_h = nullptr, *host3_h = nullptr;
+    // statistics pass: nodes per workgroup (at most the smallest graph) and
+    // the most blocks the graphs of such a range own
+    int64_t stats_span = 0;
+    int32_t stats_window = 0;
 };
 
 namespace {
@@ -184,7 +189,8 @@ void free_workspace(upr_ctx *c)
     dfree(c->ev_val2);
     dfree(c->ev_prefix);
     dfree(c->netpre);
-    dfree(c->seg_mat);
+    dfree(c->seg_slist);
+    dfree(c->seg_meta);
     dfree(c->seg_cur);
     dfree(c->seg_off);
     dfree(c->seg_boff);
@@ -237,8 +243,8 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
               dalloc(&c->ev_key2, 2 * N) == hipSuccess && dalloc(&c->ev_val, 2 * N) == hipSuccess &&
               dalloc(&c->ev_val2, 2 * N) == hipSuccess && dalloc(&c->ev_prefix, 2 * N) == hipSuccess &&
               dalloc(&c->netpre, N) == hipSuccess &&
-              dalloc(&c->seg_mat, kSegMatEntries) == hipSuccess &&
-              dalloc(&c->seg_cur, K) == hipSuccess && dalloc(&c->seg_off, K + 1) == hipSuccess &&
+              dalloc(&c->seg_slist, K) == hipSuccess && dalloc(&c->seg_meta, 4) == hipSuccess &&
+              dalloc(&c->seg_cur, std::max<int64_t>(K, (int64_t)kSegCopyEntries * kSegCopyPad)) == hipSuccess && dalloc(&c->seg_off, K + 1) == hipSuccess &&
               dalloc(&c->seg_boff, K + 1) == hipSuccess && dalloc(&c->seg_cpre, K + 1) == hipSuccess &&
               dalloc(&c->seg_bblk, NB) == hipSuccess && dalloc(&c->seg_bpos, NB) == hipSuccess &&
               dalloc(&c->seg_bsize, NB) == hipSuccess && dalloc(&c->seg_bdel, NB) == hipSuccess &&
@@ -313,7 +319,7 @@ struct PhaseTimer {
     hipEvent_t a = nullptr;
     PhaseTimer(upr_ctx *c_, int p, hipStream_t s_) : c(c_), phase(p), s(s_)
     {
-        if (c->timing.on && (a = take_event(c))) (void)hipEventRecord(a, s);
+        if (((c->timing.mask >> phase) & 1u) && (a = take_event(c))) (void)hipEventRecord(a, s);
     }
     ~PhaseTimer()
     {
@@ -907,6 +913,12 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
     const int plain = (q->variant & UPR_VAR_PLAIN_PRIORITY) ? 1 : 0;
     const int32_t K = bk.total();
     int64_t *gstat = b ? b->gstat_d : nullptr;
+    StatsGeom sg;
+    if (b) {
+        sg.goff = b->goff_d;
+        sg.span = b->stats_span;
+        sg.window = b->stats_window;
+    }
     HIP_TRY(c, hipSetDevice(c->device));
     int rc = ensure_workspace(c, n, K);
     if (rc) return rc;
@@ -935,7 +947,7 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
     }
     {
         PhaseTimer t(c, 1, s);
-        HIP_TRY(c, launch_node_stats(p->g, bk, part, conn, p->wdeg, q->rebuild_table ? W : nullptr,
+        HIP_TRY(c, launch_node_stats(p->g, bk, sg, part, conn, p->wdeg, q->rebuild_table ? W : nullptr,
                                      moves ? c->bucket : nullptr, q->t_num, q->t_den, c->counters,
                                      CNT_CUT2_BEFORE, moves && q->seq_penalty ? c->avail : nullptr,
                                      gstat, GS_CUT2_BEFORE, s));
@@ -963,13 +975,14 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
             if (q->seq_penalty) {
                 const int sb = seq_score_bits(p->maxwdeg);
                 if (seq_segments_fit(sb, n)) {
-                    const SegWs ws{c->seg_mat,   c->seg_cur,    c->seg_off,    c->seg_boff,
-                                   c->seg_cpre,  c->seg_bblk,   c->seg_bpos,   c->seg_bsize,
-                                   c->seg_bdel,  c->seg_bcnt,   c->seg_scan_c, c->seg_scan_d,
-                                   c->seg_spl,   c->ev_key,     c->ev_key2};
-                    HIP_TRY(c, launch_seq_segments(p->g, bk, c->key, c->gp, part, c->avail, sb, ws,
-                                                   W, c->bucket, q->mode, p->hub_t, c->mvto,
-                                                   c->accflag, c->counters, s));
+                    const SegWs ws{c->seg_cur,    c->seg_off,    c->seg_boff,  c->seg_cpre,
+                                   c->seg_slist,  c->seg_meta,   c->seg_bblk,  c->seg_bpos,
+                                   c->seg_bsize,  c->seg_bdel,   c->seg_bcnt,  c->seg_scan_c,
+                                   c->seg_scan_d, c->seg_spl,    c->ev_key,    c->ev_key2};
+                    HIP_TRY(c, launch_seq_segments(p->g, bk, b ? b->goff_d : nullptr, c->key,
+                                                   c->gp, part, c->avail, sb, ws, W, c->bucket,
+                                                   q->mode, p->hub_t, c->mvto, c->accflag,
+                                                   c->counters, s));
                 } else {
                     // eligible candidates in id order; their number sizes the sort
                     HIP_TRY(c, launch_seq_select(n, c->key, c->gp, c->cand, c->counters + CNT_ELIG,
@@ -989,7 +1002,8 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
                                                  c->mvto, c->accflag, c->counters, s));
                 }
             }
-            if (b) HIP_TRY(c, launch_batch_move_stats(n, bk, part, c->key, c->accflag, gstat, s));
+            if (b) HIP_TRY(c, launch_batch_move_stats(n, b->stats_span, bk, b->goff_d, part, c->key, c->accflag,
+                                                       gstat, s));
         }
         {
             PhaseTimer t(c, 4, s);
@@ -998,7 +1012,7 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
         }
         {
             PhaseTimer t(c, 6, s);
-            HIP_TRY(c, launch_node_stats(p->g, bk, part, conn, p->wdeg, nullptr, nullptr, 0, 1,
+            HIP_TRY(c, launch_node_stats(p->g, bk, sg, part, conn, p->wdeg, nullptr, nullptr, 0, 1,
                                          c->counters, CNT_CUT2_MOVES, nullptr, gstat,
                                          GS_CUT2_MOVES, s));
         }
@@ -1019,7 +1033,7 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
     }
     {
         PhaseTimer t(c, 6, s);
-        HIP_TRY(c, launch_node_stats(p->g, bk, part, conn, p->wdeg, nullptr, nullptr, 0, 1,
+        HIP_TRY(c, launch_node_stats(p->g, bk, sg, part, conn, p->wdeg, nullptr, nullptr, 0, 1,
                                      c->counters, CNT_CUT2_AFTER, nullptr, gstat, GS_CUT2_AFTER, s));
     }
     if (b) {
@@ -1130,6 +1144,25 @@ int upr_batch_create(upr_ctx *c, const upr_graph *graphs, const int64_t *nnz_hos
     b->n = b->off[ng];
     b->nnz = eoff[ng];
     if (b->n >= ((int64_t)1 << 31) - 1) return bail(UPR_E_ARG, "the batch has 2^31 nodes or more");
+    {
+        // statistics pass: ranges no longer than the smallest graph meet at
+        // most two graphs
+        int64_t min_n = 0;
+        for (int32_t g = 0; g < ng; ++g) {
+            const int64_t gn = b->off[g + 1] - b->off[g];
+            if (gn > 0 && (min_n == 0 || gn < min_n)) min_n = gn;
+        }
+        b->stats_span = stats_span(b->n, min_n);
+        auto graph_of = [&](int64_t v) {
+            return (int32_t)(std::upper_bound(b->off.begin(), b->off.end(), v) - b->off.begin()) - 1;
+        };
+        int32_t most = 1;
+        for (int64_t lo = 0; lo < b->n; lo += b->stats_span) {
+            const int64_t hi = std::min(lo + b->stats_span, b->n);
+            most = std::max(most, graph_of(hi - 1) - graph_of(lo) + 1);
+        }
+        b->stats_window = most * k;
+    }
     // the union CSR
     if (dalloc(&b->xadj, b->n + 1) != hipSuccess || dalloc(&b->adjncy, b->nnz) != hipSuccess ||
         (any_ew && dalloc(&b->adjwgt, b->nnz) != hipSuccess) ||
@@ -1439,7 +1472,7 @@ int upr_last_moves(upr_ctx *c, int64_t n, int32_t *target, int64_t *score, int64
 int upr_timing_enable(upr_ctx *c, int enable)
 {
     if (!c) return UPR_E_ARG;
-    c->timing.on = enable != 0;
+    c->timing.mask = (uint32_t)enable & ((1u << UPR_NUM_PHASES) - 1u);
     return UPR_OK;
 }
 

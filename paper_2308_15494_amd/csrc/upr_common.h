@@ -308,6 +308,34 @@ __device__ __forceinline__ int covering_slot(const int64_t *cb, int64_t x)
     return lo;
 }
 
+// Graph of node v in a batch: the g with goff[g] <= v < goff[g + 1].
+__device__ __forceinline__ int32_t graph_of_node(const int64_t *goff, int32_t ng, int64_t v)
+{
+    int lo = 0, hi = ng - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (goff[mid] <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Blocks [B0, B0 + nb) of the graphs that own nodes [lo, hi) (a batch's
+// graphs own consecutive node ranges and consecutive block ranges).
+__device__ __forceinline__ void node_block_window(const Blocks &bk, const int64_t *goff,
+                                                  int64_t lo, int64_t hi, int32_t *B0, int32_t *nb)
+{
+    if (!goff || bk.ng == 1) {
+        *B0 = 0;
+        *nb = bk.total();
+        return;
+    }
+    const int32_t g0 = graph_of_node(goff, bk.ng, lo);
+    const int32_t g1 = graph_of_node(goff, bk.ng, hi - 1);
+    *B0 = g0 * bk.k;
+    *nb = (g1 - g0 + 1) * bk.k;
+}
+
 // Largest i in [0, cnt) with a[i] <= p (a nondecreasing, a[0] <= p).
 __device__ __forceinline__ int upper_index(const int32_t *a, int cnt, int32_t p)
 {
@@ -438,9 +466,19 @@ hipError_t launch_hub_bits(const HubView &h, uint32_t *bits, hipStream_t s);
 // nodes (bucket may be null), block weights W[part] += c (W may be null),
 // availability for rebalancing (avail may be null).
 // gstat (batch): the cut also goes to gstat[graph][gs_slot].
-hipError_t launch_node_stats(const GraphView &g, const Blocks &bk, const int32_t *part,
-                             const int32_t *conn, const int32_t *wdeg, int64_t *W,
-                             int64_t *bucket, int32_t t_num, int32_t t_den,
+// Geometry: each workgroup takes span consecutive nodes; window bounds the
+// blocks of the graphs owning such a range (a batch's goff; zeros: one
+// graph, default span).
+struct StatsGeom {
+    const int64_t *goff = nullptr;
+    int64_t span = 0;
+    int32_t window = 0;
+};
+// Node range of the statistics pass for n nodes, at most max_span (> 0).
+int64_t stats_span(int64_t n, int64_t max_span);
+hipError_t launch_node_stats(const GraphView &g, const Blocks &bk, const StatsGeom &sg,
+                             const int32_t *part, const int32_t *conn, const int32_t *wdeg,
+                             int64_t *W, int64_t *bucket, int32_t t_num, int32_t t_den,
                              unsigned long long *counters, int cut_slot, uint8_t *avail,
                              int64_t *gstat, int gs_slot, hipStream_t s);
 hipError_t launch_block_weights(const GraphView &g, int32_t k, const int32_t *part, int64_t *W,
@@ -509,12 +547,14 @@ hipError_t launch_seq_net(int64_t ne, const int32_t *cand, const int64_t *key, c
 // by one workgroup per bucket (accflag, mvto, CNT_ACC, CNT_MOVED_DEG as
 // launch_filter_seq). Usable iff seq_segments_fit(sb, n): an event (order,
 // node id, outflow flag) fits 64 bits. NB = seq_bucket_bound(n, K).
-constexpr int kSegMatEntries = 1 << 18;  // per-workgroup block counts (uint32)
+constexpr int kSegCopyEntries = 4096;  // counter copies of all blocks (when there are few)
+constexpr int kSegCopyPad = 16;        // counters per cache line
 struct SegWs {
-    uint32_t *mat;              // [kSegMatEntries]
-    unsigned long long *cur;    // [K] counts, then placement cursors
+    unsigned long long *cur;    // [max(K, kSegCopyEntries * kSegCopyPad)] counts, then cursors
     int64_t *seg_off;           // [K + 1] segment starts
     int32_t *boff, *cpre;       // [K + 1] first bucket / first bucketing chunk of each block
+    int32_t *slist;             // [K] blocks whose segment is split
+    int32_t *meta;              // [4] meta[0]: number of split blocks
     int32_t *bblk;              // [NB] block of each bucket
     int64_t *bpos, *bsize;      // [NB] bucket start and size
     int64_t *bdel;              // [NB] weight-change sums, then carries
@@ -526,9 +566,10 @@ struct SegWs {
 int seq_id_bits(int64_t n);
 int64_t seq_bucket_bound(int64_t n, int K);
 bool seq_segments_fit(int sb, int64_t n);
-hipError_t launch_seq_segments(const GraphView &g, const Blocks &bk, const int64_t *key,
-                               const int64_t *gp, const int32_t *part, const uint8_t *avail,
-                               int sb, const SegWs &ws, const int64_t *W, const int64_t *cb,
+// goff: a batch's node offsets (null for one graph).
+hipError_t launch_seq_segments(const GraphView &g, const Blocks &bk, const int64_t *goff,
+                               const int64_t *key, const int64_t *gp, const int32_t *part,
+                               const uint8_t *avail, int sb, const SegWs &ws, const int64_t *W, const int64_t *cb,
                                int mode, int64_t hub_t, int32_t *mvto, uint8_t *accflag,
                                unsigned long long *counters, hipStream_t s);
 // Apply every move recorded in mvto (target block, -1 = none) and clear it.
@@ -591,9 +632,9 @@ hipError_t launch_batch_copy(const GraphView &src, int64_t node_off, int64_t edg
 // out[2g] = total node weight of graph g, out[2g + 1] = its largest node weight.
 hipError_t launch_batch_totals(const int64_t *goff, int32_t ng, const int32_t *vwgt, int64_t *out,
                                hipStream_t s);
-hipError_t launch_batch_move_stats(int64_t n, const Blocks &bk, const int32_t *part,
-                                   const int64_t *key, const uint8_t *accflag, int64_t *gstat,
-                                   hipStream_t s);
+hipError_t launch_batch_move_stats(int64_t n, int64_t span, const Blocks &bk, const int64_t *goff,
+                                   const int32_t *part, const int64_t *key,
+                                   const uint8_t *accflag, int64_t *gstat, hipStream_t s);
 hipError_t launch_batch_stats_final(int32_t ng, const int64_t *gstat, const int64_t *lmax,
                                     const int64_t *host3, int moved, int64_t *stats, hipStream_t s);
 // driver: count of nonzero bytes; boundary nodes; nodes that did not move

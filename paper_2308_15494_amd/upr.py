@@ -199,8 +199,17 @@ class Context:
         except Exception:
             pass
 
-    def timing(self, enable: bool):
-        self.check(lib().upr_timing_enable(self.handle, int(enable)))
+    def timing(self, enable: bool, phases=None):
+        """Time every phase (enable, phases None), only the listed phases
+        (names or indices into PHASES), or nothing."""
+        mask = 0
+        if enable:
+            if phases is None:
+                mask = 0xFF
+            else:
+                for ph in phases:
+                    mask |= 1 << (PHASES.index(ph) if isinstance(ph, str) else int(ph))
+        self.check(lib().upr_timing_enable(self.handle, mask))
 
     def timing_read(self, reset=True) -> dict:
         ms = np.zeros(8, np.float64)
