@@ -27,7 +27,8 @@ static int grid_cap(int64_t items, int per_block, int cap)
 // Zero the counters, the penalty buckets and (rebuild form) the block
 // weights; for a single graph publish the round's Q16 penalty table and L_max.
 __global__ void k_round_init(Blocks bk, int64_t *bucket, int64_t *W, PenTable pq, int64_t lmax,
-                             int single, unsigned long long *counters, int zero_w)
+                             int single, unsigned long long *counters, int zero_w,
+                             unsigned long long *zero2, int64_t zero2_count)
 {
     const int64_t K = bk.total();
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -43,14 +44,16 @@ __global__ void k_round_init(Blocks bk, int64_t *bucket, int64_t *W, PenTable pq
         }
     }
     for (int64_t i = tid; i < kCntWords; i += stride) counters[i] = 0;
+    for (int64_t i = tid; i < zero2_count; i += stride) zero2[i] = 0;
 }
 
 hipError_t launch_round_init(const Blocks &bk, int64_t *bucket, int64_t *W, const PenTable &pq,
                              int64_t lmax, int single, unsigned long long *counters, int zero_w,
-                             hipStream_t s)
+                             unsigned long long *zero2, int64_t zero2_count, hipStream_t s)
 {
     hipLaunchKernelGGL(k_round_init, dim3(grid_cap((int64_t)bk.total() * kSlots, kBlock * 4, 1024)),
-                       dim3(kBlock), 0, s, bk, bucket, W, pq, lmax, single, counters, zero_w);
+                       dim3(kBlock), 0, s, bk, bucket, W, pq, lmax, single, counters, zero_w, zero2,
+                       zero2_count);
     return hipGetLastError();
 }
 
@@ -627,10 +630,17 @@ hipError_t launch_filter(const GraphView &g, const Blocks &bk, int optimistic, c
     return hipGetLastError();
 }
 
-// Hub candidates: each chunk adds its part of the pessimistic gain.
+// Hub candidates: each chunk adds its part of the pessimistic gain; the
+// chunk that finishes last (a per-hub ticket) decides the move (or, with
+// the sequence-aware price, stores the pessimistic gain) and resets the
+// accumulator and the ticket.
 __global__ __launch_bounds__(kBlock) void k_filter_hub(GraphView g, Blocks bk, int optimistic,
                                                         const int32_t *part, PartView pv,
-                                                        const int64_t *key, HubView h)
+                                                        const int64_t *key, const int64_t *pen,
+                                                        HubView h, int32_t *mvto,
+                                                        uint8_t *accflag,
+                                                        unsigned long long *counters,
+                                                        int64_t *gp_out)
 {
     __shared__ int64_t red[4];
     const HubChunk c = h.chunks[blockIdx.x];
@@ -641,42 +651,25 @@ __global__ __launch_bounds__(kBlock) void k_filter_hub(GraphView g, Blocks bk, i
     int64_t acc = pessimistic_part(g, pv, key, v, a, b, kv >> 16, c.e0, c.e1, threadIdx.x, kBlock,
                                    optimistic);
     acc = block_sum(acc, red);
-    if (threadIdx.x == 0 && acc) atomic_add_i64(&h.gacc[c.hub], acc);
-}
-
-// Hub candidates: decide (or, with the sequence-aware price, store the
-// pessimistic gain), mark the move, reset the accumulator.
-__global__ void k_filter_hub_final(Blocks bk, const int32_t *part, const int64_t *key,
-                                   const int64_t *pen, HubView h, int32_t *mvto, uint8_t *accflag,
-                                   unsigned long long *counters, int64_t *gp_out)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= h.nh) return;
-    const int64_t v = h.ids[i];
-    const int64_t kv = key[v];
-    const int64_t acc = h.gacc[i];
-    h.gacc[i] = 0;
-    if (kv < 0) return;
+    if (threadIdx.x != 0) return;
+    if (acc) atomic_add_i64(&h.gacc[c.hub], acc);
+    __threadfence();
+    if (atomicAdd(&h.ticket[c.hub], 1u) != (unsigned)(c.nchunk - 1)) return;
+    __threadfence();
+    const int64_t total = (int64_t)atomicExch((unsigned long long *)&h.gacc[c.hub], 0ull);
+    h.ticket[c.hub] = 0;
     if (gp_out) {
-        gp_out[v] = acc;
+        gp_out[v] = total;
         accflag[v] = 0;
         return;
     }
-    const bool ok = acc * 65536 - pen[v] > 0;
+    const bool ok = total * 65536 - pen[v] > 0;
     accflag[v] = ok ? 1 : 0;
     if (ok) {
-        mvto[v] = bk.base(part[v]) + (int32_t)(kv & 0xFFFF);
+        mvto[v] = bk.base(part[v]) + b;
         cnt_add(counters, CNT_ACC, 1ull);
+        cnt_add(counters, CNT_MOVED_DEG, (unsigned long long)(g.xadj[v + 1] - g.xadj[v]));
     }
-}
-
-__global__ void k_hub_moved_deg(GraphView g, const int32_t *mvto, HubView h,
-                                unsigned long long *counters)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= h.nh) return;
-    const int64_t v = h.ids[i];
-    if (mvto[v] >= 0) cnt_add(counters, CNT_MOVED_DEG, (unsigned long long)(g.xadj[v + 1] - g.xadj[v]));
 }
 
 hipError_t launch_filter_hub(const GraphView &g, const Blocks &bk, int optimistic,
@@ -686,11 +679,7 @@ hipError_t launch_filter_hub(const GraphView &g, const Blocks &bk, int optimisti
 {
     if (h.nh <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_filter_hub, dim3((unsigned)h.nchunks), dim3(kBlock), 0, s, g, bk,
-                       optimistic, part, pv, key, h);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_filter_hub_final, dim3((h.nh + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                       bk, part, key, pen, h, mvto, accflag, counters, gp_out);
+                       optimistic, part, pv, key, pen, h, mvto, accflag, counters, gp_out);
     return hipGetLastError();
 }
 
@@ -744,7 +733,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_seq(
             if (take) {
                 mvto[v] = b;
                 const int64_t deg = g.xadj[v + 1] - g.xadj[v];
-                if (deg <= hub_t) atomicAdd(&deg_lds, (unsigned long long)deg);
+                atomicAdd(&deg_lds, (unsigned long long)deg);
             }
         }
         wave_count(take, &acc_lds);
@@ -873,6 +862,16 @@ __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, Blocks bk, int32_
         const uint64_t mmid = __ballot(to >= 0 && deg > low_t && deg <= hub_t);
         if (mlow) apply_class<kLowLanes>(g, bk, part, pv, conn, wdst, mlow, v, to, mvto, h, dirty, T);
         if (mmid) apply_class<64>(g, bk, part, pv, conn, wdst, mmid, v, to, mvto, h, dirty, T);
+        if (to >= 0 && deg > hub_t) {
+            // a hub: its edges were applied by k_apply_hub (which read the old part)
+            const int32_t A = part[v];
+            const int64_t cv = node_weight(g, v);
+            part[v] = to;
+            pset((void *)pv.p, pv.bytes, v, bk.local(to));
+            mvto[v] = -1;
+            atomicAdd((unsigned long long *)&wdst[A], (unsigned long long)(-cv));
+            atomicAdd((unsigned long long *)&wdst[to], (unsigned long long)cv);
+        }
     }
     if (use_lds) {
         __syncthreads();
@@ -881,8 +880,10 @@ __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, Blocks bk, int32_
     }
 }
 
-// Hub moves: each chunk updates the rows of its neighbours (part of the hub
-// is still its source block here).
+// Hub moves, before k_apply: each chunk updates the rows of its neighbours
+// (part of the hub is still its source block here). The first chunk of every
+// hub also clears the hub's own row, which k_gain_hub rebuilds after the
+// apply.
 __global__ __launch_bounds__(kBlock) void k_apply_hub(GraphView g, Blocks bk, const int32_t *part,
                                                        int32_t *conn, const int32_t *mvto,
                                                        HubView h, const unsigned long long *counters,
@@ -891,13 +892,15 @@ __global__ __launch_bounds__(kBlock) void k_apply_hub(GraphView g, Blocks bk, co
 {
     const HubChunk c = h.chunks[blockIdx.x];
     const int64_t v = h.ids[c.hub];
+    const int32_t k = bk.k;
+    if (c.e0 == g.xadj[v])
+        for (int j = threadIdx.x; j < k; j += kBlock) conn[v * (int64_t)k + j] = 0;
     const int32_t B = mvto[v];
     if (B < 0) return;
     if ((int64_t)cnt_get(counters, CNT_MOVED_DEG) > dirty_threshold) {
         for (int64_t e = c.e0 + threadIdx.x; e < c.e1; e += kBlock) dirty[g.adjncy[e] / T] = 1;
         return;
     }
-    const int32_t k = bk.k;
     const int32_t a = bk.local(part[v]), b = bk.local(B);
     for (int64_t e = c.e0 + threadIdx.x; e < c.e1; e += kBlock) {
         const int64_t u = g.adjncy[e];
@@ -906,24 +909,6 @@ __global__ __launch_bounds__(kBlock) void k_apply_hub(GraphView g, Blocks bk, co
         atomicAdd(&conn[u * k + a], -w);
         atomicAdd(&conn[u * k + b], w);
     }
-}
-
-// Hub moves: part and block weights, then clear the mark.
-__global__ void k_apply_hub_final(GraphView g, Blocks bk, int32_t *part, PartView pv, int64_t *W,
-                                  int32_t *mvto, HubView h)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= h.nh) return;
-    const int64_t v = h.ids[i];
-    const int32_t b = mvto[v];
-    if (b < 0) return;
-    const int32_t a = part[v];
-    const int64_t cv = node_weight(g, v);
-    part[v] = b;
-    pset((void *)pv.p, pv.bytes, v, bk.local(b));
-    mvto[v] = -1;
-    atomic_add_i64(&W[a], -cv);
-    atomic_add_i64(&W[b], cv);
 }
 
 hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, const PartView &pv,
@@ -936,25 +921,17 @@ hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, con
     const int T = gain_tile_nodes(k);
     const size_t lds = bk.total() <= 2048 ? (size_t)bk.total() * 8 : 0;
     hipError_t e;
-    if (h.nh > 0) {  // hub degrees join the moved-degree sum first
-        hipLaunchKernelGGL(k_hub_moved_deg, dim3((h.nh + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                           g, mvto, h, (unsigned long long *)counters);
+    if (h.nh > 0) {
+        hipLaunchKernelGGL(k_apply_hub, dim3((unsigned)h.nchunks), dim3(kBlock), 0, s, g, bk, part,
+                           conn, mvto, h, counters, dirty_threshold, dirty, T);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_apply, dim3(grid_cap(g.n, kBlock, 4096)), dim3(kBlock), lds, s, g, bk,
                        part, pv, conn, W, mvto, low_t, hub_t, h, counters, dirty_threshold, dirty, T);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (h.nh > 0) {
-        hipLaunchKernelGGL(k_apply_hub, dim3((unsigned)h.nchunks), dim3(kBlock), 0, s, g, bk, part,
-                           conn, mvto, h, counters, dirty_threshold, dirty, T);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_apply_hub_final, dim3((h.nh + kBlock - 1) / kBlock), dim3(kBlock), 0,
-                           s, g, bk, part, pv, W, mvto, h);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    // rebuild the marked tiles (none are marked in the delta mode)
+    // rebuild the marked tiles (none are marked in the delta mode), then the hub rows
     if ((e = launch_gain_tile(g, k, pv, conn, hub_t, dirty, s)) != hipSuccess) return e;
-    return launch_rebuild_hub_rows(g, k, pv, conn, h, s);
+    return launch_gain_hub(g, k, pv, conn, h, s);
 }
 
 // ----------------------------------------------------------------- stats --

@@ -65,9 +65,9 @@ __device__ __forceinline__ bool rb_kept(const RbView &r, int64_t v, int32_t a, i
 // ------------------------------------------------------------------ begin --
 
 // Count source blocks and snapshot W (one workgroup). For a batch, also per
-// graph: gstat[g][GS_OVER].
+// graph: gstat[g][GS_OVER]. first: the count also goes to CNT_OVER0.
 __global__ void k_rb_begin(Blocks bk, const int64_t *W, int64_t *W0, unsigned long long *counters,
-                           int64_t *gstat)
+                           int64_t *gstat, int first)
 {
     __shared__ unsigned long long red[4];
     const int32_t K = bk.total();
@@ -84,13 +84,17 @@ __global__ void k_rb_begin(Blocks bk, const int64_t *W, int64_t *W0, unsigned lo
         if (gstat && o) atomic_add_i64(&gstat[(int64_t)bk.graph(j) * GS_COUNT + GS_OVER], 1);
     }
     over = block_sum(over, red);
-    if (threadIdx.x == 0) cnt_set(counters, CNT_OVER, over);
+    if (threadIdx.x == 0) {
+        cnt_set(counters, CNT_OVER, over);
+        if (first) cnt_set(counters, CNT_OVER0, over);
+    }
 }
 
 hipError_t launch_rb_begin(const Blocks &bk, const int64_t *W, const RebalWs &r,
-                           unsigned long long *counters, int64_t *gstat, hipStream_t s)
+                           unsigned long long *counters, int64_t *gstat, hipStream_t s, int first)
 {
-    hipLaunchKernelGGL(k_rb_begin, dim3(1), dim3(kBlock), 0, s, bk, W, r.W0, counters, gstat);
+    hipLaunchKernelGGL(k_rb_begin, dim3(1), dim3(kBlock), 0, s, bk, W, r.W0, counters, gstat,
+                       first);
     return hipGetLastError();
 }
 
@@ -540,7 +544,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_moves(GraphView g, Blocks bk, con
                     mvto[v] = j;
                     acc = true;
                     const int64_t deg = g.xadj[v + 1] - g.xadj[v];
-                    if (deg <= hub_t) atomicAdd(&mdeg, (unsigned long long)deg);  // hubs: apply
+                    atomicAdd(&mdeg, (unsigned long long)deg);
                 }
             }
         }

@@ -795,7 +795,7 @@ __device__ __forceinline__ void seg_decide_one(const SegDecide &d, int64_t v, in
         d.mvto[v] = d.B;
         atomicAdd(acc_lds, 1ull);
         const int64_t deg = d.g.xadj[v + 1] - d.g.xadj[v];
-        if (deg <= d.hub_t) atomicAdd(deg_lds, (unsigned long long)deg);
+        atomicAdd(deg_lds, (unsigned long long)deg);
     }
 }
 
@@ -949,6 +949,11 @@ bool seq_segments_fit(int sb, int64_t n)
     return sb + seq_id_bits(n) + 1 <= 63;
 }
 
+int64_t seq_counter_words(int K)
+{
+    return seg_slot(K, 0, seg_copies(K));
+}
+
 int64_t seq_bucket_bound(int64_t n, int K)
 {
     return (int64_t)K + 2 * n / kBucketAvg + 2 * n / kRun + 2;
@@ -964,9 +969,7 @@ hipError_t launch_seq_segments(const GraphView &g, const Blocks &bk, const int64
     const int K = bk.total();
     const int idb = seq_id_bits(g.n);
     const SegGeom geo = seg_geom(g.n);
-    const int C = seg_copies(K);
-    hipError_t e = launch_fill_i64((int64_t *)ws.cur, seg_slot(K, 0, C), 0, s);
-    if (e != hipSuccess) return e;
+    hipError_t e;
     hipLaunchKernelGGL(k_seg_count, dim3(geo.rows), dim3(kBlock), 0, s, g.n, geo.span, key, gp,
                        part, avail, bk, goff, ws.cur);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -215,12 +215,6 @@ __global__ __launch_bounds__(kBlock) void k_gain_hub(GraphView g, int32_t k, Par
         if (row[j]) atomicAdd(&dst[j], row[j]);
 }
 
-__global__ void k_zero_hub_rows(int32_t k, int32_t *conn, HubView h)
-{
-    int32_t *row = conn + (int64_t)h.ids[blockIdx.x] * k;
-    for (int j = threadIdx.x; j < k; j += kBlock) row[j] = 0;
-}
-
 __global__ void k_hub_bits(HubView h, uint32_t *bits)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -234,16 +228,6 @@ hipError_t launch_hub_bits(const HubView &h, uint32_t *bits, hipStream_t s)
     if (h.nh <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_hub_bits, dim3((h.nh + kBlock - 1) / kBlock), dim3(kBlock), 0, s, h, bits);
     return hipGetLastError();
-}
-
-hipError_t launch_rebuild_hub_rows(const GraphView &g, int32_t k, const PartView &part,
-                                   int32_t *conn, const HubView &h, hipStream_t s)
-{
-    if (h.nh <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero_hub_rows, dim3(h.nh), dim3(kBlock), 0, s, k, conn, h);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return launch_gain_hub(g, k, part, conn, h, s);
 }
 
 hipError_t launch_gain_hub(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,

@@ -102,13 +102,14 @@ struct upr_plan {
     HubChunk *chunks = nullptr;
     int64_t nchunks = 0;
     int64_t *gacc = nullptr;
+    unsigned int *hub_ticket = nullptr;
     uint32_t *hub_bits = nullptr;  // [ceil(n/32)]
     int64_t hub_t = kDefaultHubThreshold, low_t = kDefaultLowThreshold;
     int64_t dirty_threshold = 0;  // moved-degree sum above which tiles are rebuilt
 
     HubView hubs() const
     {
-        return HubView{nh, hub_ids, chunks, nchunks, gacc, hub_bits};
+        return HubView{nh, hub_ids, chunks, nchunks, gacc, hub_bits, hub_ticket};
     }
 };
 
@@ -412,12 +413,11 @@ int rebalance_loop(upr_ctx *c, const upr_plan *p, const Blocks &bk, int plain, i
         HIP_TRY(c, launch_rb_begin(bk, W, c->rb, c->counters, nullptr, s));
         return UPR_OK;
     };
-    HIP_TRY(c, launch_rb_begin(bk, W, c->rb, c->counters, nullptr, s));
+    HIP_TRY(c, launch_rb_begin(bk, W, c->rb, c->counters, nullptr, s, 1));
     int rc;
     if (speculate) {
         // the first sub-iteration without waiting for the count of overloaded
         // blocks: with none it finds no movable node and changes nothing
-        HIP_TRY(c, launch_cnt_copy(c->counters, CNT_OVER0, CNT_OVER, s));
         if ((rc = sub_iteration())) return rc;
     }
     rc = sync_counters(c, s);
@@ -770,7 +770,8 @@ static int plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipSt
             if (hipMemcpy(ids.data(), hub_list, sizeof(int32_t) * p->nh, hipMemcpyDeviceToHost) != hipSuccess)
                 return bail(UPR_E_HIP, "reading the hub list failed");
             std::sort(ids.begin(), ids.end());
-            if (dalloc(&p->hub_ids, p->nh) != hipSuccess || dalloc(&p->gacc, p->nh) != hipSuccess)
+            if (dalloc(&p->hub_ids, p->nh) != hipSuccess || dalloc(&p->gacc, p->nh) != hipSuccess ||
+                dalloc(&p->hub_ticket, p->nh) != hipSuccess)
                 return bail(UPR_E_NOMEM, "plan allocation failed");
             std::vector<int64_t> e01(2 * (size_t)p->nh);
             int64_t *d_e01 = nullptr;
@@ -782,9 +783,12 @@ static int plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipSt
             dfree(d_e01);
             if (!ok) return bail(UPR_E_HIP, "hub preparation failed");
             std::vector<HubChunk> chunks;
-            for (int32_t i = 0; i < p->nh; ++i)
+            for (int32_t i = 0; i < p->nh; ++i) {
+                const int32_t nc =
+                    (int32_t)((e01[2 * i + 1] - e01[2 * i] + kHubChunkEdges - 1) / kHubChunkEdges);
                 for (int64_t e = e01[2 * i]; e < e01[2 * i + 1]; e += kHubChunkEdges)
-                    chunks.push_back(HubChunk{i, 0, e, std::min(e + kHubChunkEdges, e01[2 * i + 1])});
+                    chunks.push_back(HubChunk{i, nc, e, std::min(e + kHubChunkEdges, e01[2 * i + 1])});
+            }
             p->nchunks = (int64_t)chunks.size();
             const int64_t words = (g.n + 31) / 32;
             if (dalloc(&p->chunks, p->nchunks) != hipSuccess || dalloc(&p->hub_bits, words) != hipSuccess)
@@ -793,6 +797,7 @@ static int plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipSt
                 return bail(UPR_E_HIP, "hub bitmap clear failed");
             ok = hipMemcpy(p->chunks, chunks.data(), sizeof(HubChunk) * chunks.size(), hipMemcpyHostToDevice) == hipSuccess &&
                  launch_fill_i64(p->gacc, p->nh, 0, s) == hipSuccess &&
+                 launch_fill_i32((int32_t *)p->hub_ticket, p->nh, 0, s) == hipSuccess &&
                  launch_hub_bits(p->hubs(), p->hub_bits, s) == hipSuccess &&
                  hipStreamSynchronize(s) == hipSuccess;
             if (!ok) return bail(UPR_E_HIP, "hub preparation failed");
@@ -812,6 +817,7 @@ void upr_plan_destroy(upr_plan *p)
     dfree(p->hub_ids);
     dfree(p->chunks);
     dfree(p->gacc);
+    dfree(p->hub_ticket);
     dfree(p->hub_bits);
     delete p;
 }
@@ -929,8 +935,11 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
 
     PenTable pq;
     if (!b) host_penq(q->tau_num, q->tau_den, pq.q);
+    // the segment path's counters start at zero
+    const bool seg = moves && q->seq_penalty && seq_segments_fit(seq_score_bits(p->maxwdeg), n);
     HIP_TRY(c, launch_round_init(bk, c->bucket, W, pq, lmax, b ? 0 : 1, c->counters,
-                                 q->rebuild_table, s));
+                                 q->rebuild_table, seg ? c->seg_cur : nullptr,
+                                 seg ? seq_counter_words(K) : 0, s));
     if (b) HIP_TRY(c, launch_fill_i64(gstat, (int64_t)GS_COUNT * ng, 0, s));
     // compact partition copy for the neighbour gathers (kept in step by the apply)
     const PartView pv{c->pc, k <= 256 ? 1 : 2, k <= 128 ? 1 : 0};

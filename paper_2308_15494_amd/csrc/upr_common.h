@@ -133,8 +133,8 @@ __device__ __forceinline__ void pset(void *pc, int bytes, int64_t v, int32_t b)
 }
 
 struct HubChunk {
-    int32_t hub;  // index into the sorted hub id list
-    int32_t pad;
+    int32_t hub;     // index into the sorted hub id list
+    int32_t nchunk;  // chunks of this hub
     int64_t e0, e1;
 };
 
@@ -146,6 +146,7 @@ struct HubView {
     int64_t nchunks;
     int64_t *gacc;        // [nh] filter gain accumulator
     const uint32_t *bits; // [ceil(n/32)] bit v set iff v is a hub
+    unsigned int *ticket; // [nh] chunks of the filter done (the last one decides)
 };
 
 __device__ __forceinline__ bool is_hub(const HubView &h, int64_t u)
@@ -451,9 +452,6 @@ hipError_t launch_gain_tile(const GraphView &g, int32_t k, const PartView &part,
                             int64_t hub_t, uint8_t *dirty, hipStream_t s);
 hipError_t launch_gain_hub(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,
                            const HubView &h, hipStream_t s);
-// Zero the hub rows and accumulate them again from the hubs' edge chunks.
-hipError_t launch_rebuild_hub_rows(const GraphView &g, int32_t k, const PartView &part,
-                                   int32_t *conn, const HubView &h, hipStream_t s);
 // Compact copy of part (bytes = 1 or 2).
 // Compact copy of the local blocks (bytes = 1 or 2). Checks every value: a
 // global block id below bk.total() and, for a batch (goff = node offsets of
@@ -494,12 +492,12 @@ hipError_t launch_check_part(int64_t n, int32_t k, const int32_t *part,
                              unsigned long long *counters, hipStream_t s);
 
 // moves (S0, S2-S4)
-// Zero the counters, the buckets ([K][kSlots]) and, if zero_w, W ([K]).
-// With single (one graph) also publish its penalty table and L_max into
-// bk.penq / bk.lmax / bk.src_lmax (writable workspace).
+// Zero the counters, the buckets ([K][kSlots]), zero2 ([zero2_count]) and,
+// if zero_w, W ([K]). With single (one graph) also publish its penalty table
+// and L_max into bk.penq / bk.lmax / bk.src_lmax (writable workspace).
 hipError_t launch_round_init(const Blocks &bk, int64_t *bucket, int64_t *W, const PenTable &pq,
                              int64_t lmax, int single, unsigned long long *counters, int zero_w,
-                             hipStream_t s);
+                             unsigned long long *zero2, int64_t zero2_count, hipStream_t s);
 // Prefix sums of the buckets; pen1[B] = penalty of a unit-weight node moving
 // into B (0 if it fits, -1 if forbidden).
 hipError_t launch_cb_prefix(const Blocks &bk, int64_t *bucket, const int64_t *W, int mode,
@@ -565,6 +563,9 @@ struct SegWs {
 };
 int seq_id_bits(int64_t n);
 int64_t seq_bucket_bound(int64_t n, int K);
+// Entries of ws.cur the segment path uses for K blocks; they must be zero
+// when it starts (the round's init clears them).
+int64_t seq_counter_words(int K);
 bool seq_segments_fit(int sb, int64_t n);
 // goff: a batch's node offsets (null for one graph).
 hipError_t launch_seq_segments(const GraphView &g, const Blocks &bk, const int64_t *goff,
@@ -612,7 +613,8 @@ struct RebalWs {
 // Snapshot W and count the source blocks (weight above src_lmax): in total
 // (counters[CNT_OVER]) and, for a batch, per graph (gstat[g][GS_OVER]).
 hipError_t launch_rb_begin(const Blocks &bk, const int64_t *W, const RebalWs &r,
-                           unsigned long long *counters, int64_t *gstat, hipStream_t s);
+                           unsigned long long *counters, int64_t *gstat, hipStream_t s,
+                           int first = 0);
 // One sub-iteration up to the move marks: targets and buckets, source and
 // target selection; accepted nodes get mvto[v] = target. hist32: the
 // per-workgroup histograms may use 32-bit LDS counters (no overflow).
