@@ -138,6 +138,8 @@ typedef struct {
 } upr_plan_opts;
 int upr_plan_create_opts(upr_ctx *ctx, const upr_graph *graph, const upr_plan_opts *opts,
                          upr_plan **out, hipStream_t stream);
+/* Frees the plan's device memory. A plan may be destroyed after its context
+ * (it is usable only while the context lives). */
 void upr_plan_destroy(upr_plan *plan);
 /* Host-side facts of a plan (any output pointer may be NULL). */
 int upr_plan_info(const upr_plan *plan, int64_t *n, int64_t *nnz, int64_t *total_weight,
@@ -225,6 +227,7 @@ int upr_batch_create(upr_ctx *ctx, const upr_graph *graphs, const int64_t *nnz, 
  * rebuilding batches of admitted graphs): the checks are skipped; opts: the
  * union's plan thresholds (may be NULL). */
 #define UPR_BATCH_TRUSTED 1
+/* Frees the batch; like a plan, it may be destroyed after its context. */
 void upr_batch_destroy(upr_batch *batch);
 /* Union size, node offsets off[ng + 1] and L_max[ng] (any pointer may be NULL). */
 int upr_batch_info(const upr_batch *batch, int64_t *n_total, int64_t *nnz_total, int64_t *node_off,

@@ -189,17 +189,18 @@ hipError_t launch_seq_net(int64_t ne, const int32_t *cand, const int64_t *key, c
 // contiguous node range; in a batch its events fall into the blocks of the
 // few graphs that own those nodes, so it counts them in LDS over that window
 // of blocks and reserves its slots with one global atomic per block. A
-// block's segment of at most kRun events is sorted in
-// LDS by one workgroup. A longer segment is split into buckets of about
-// kBucketAvg events by splitters taken from a sorted sample of it (sample
-// sort: the keys are distinct, so ties in the order cannot unbalance the
-// buckets); its events are counted and scattered into the buckets by
-// workgroups over chunks of kChunk events, and every bucket is sorted by its
-// own workgroup. The scan of a bucket starts from the weight change of the
-// buckets before it in its block, summed while counting. A bucket that still
-// exceeds kRun is sorted by its workgroup in runs merged pairwise through
-// global memory (slow, but correct). Bucket boundaries depend on the
-// placement order, the sorted order and the decisions do not.
+// block's segment of at most kRun events is sorted in LDS by one workgroup.
+// A longer segment is split into buckets of about SegWs::bucket_avg events
+// (at least kBucketAvg) by splitters taken from a sorted sample of it
+// (sample sort: the keys are distinct, so ties in the order cannot
+// unbalance the buckets); its events are counted and scattered into the
+// buckets by workgroups over chunks of kChunk events, and every bucket is
+// sorted by its own workgroup. The scan of a bucket starts from the weight
+// change of the buckets before it in its block, summed while counting. A
+// bucket of up to 2 kRun events (a sampling outlier) is sorted in two
+// halves merged in LDS; a larger one in runs merged pairwise through global
+// memory (slow, but correct). Bucket boundaries depend on the placement
+// order, the sorted order and the decisions do not.
 
 namespace {
 
@@ -208,19 +209,19 @@ constexpr int kSegRows = 512;           // most workgroups of the counting and p
 constexpr int kSortItems = 8;           // keys per thread of the workgroup sort
 constexpr int kWaveKeys = 64 * kSortItems;
 constexpr int kRun = kBlock * kSortItems;  // a segment or bucket sorted in LDS in one piece
-constexpr int kSplitThreads = 1024;     // threads of the splitter kernel
+constexpr int kSplitThreads = 512;      // threads of the splitter kernel
 constexpr int kSample = kSplitThreads * kSortItems;  // largest sample
-constexpr int kBucketAvg = 1024;        // average bucket of a split segment
+constexpr int kBucketAvg = 768;         // average bucket of a split segment
 constexpr int kMaxBuckets = 2048;       // buckets of one segment at most
-constexpr int kOversample = 16;         // samples per bucket
+constexpr int kOversample = 8;          // samples per bucket
 constexpr int kChunk = 2048;            // events per workgroup while bucketing
 constexpr int kSegMergeItems = 8;       // outputs per thread and step of a merge pass
 constexpr int kOffThreads = 1024;       // threads of the offsets kernels
 
-__host__ __device__ __forceinline__ int seg_buckets(int64_t m)
+__host__ __device__ __forceinline__ int seg_buckets(int64_t m, int avg)
 {
     if (m <= kRun) return 1;
-    const int64_t p = (m + kBucketAvg - 1) / kBucketAvg;
+    const int64_t p = (m + avg - 1) / avg;
     return p < kMaxBuckets ? (int)p : kMaxBuckets;
 }
 
@@ -470,17 +471,48 @@ __device__ __forceinline__ int64_t excl_scan_1024(int64_t x, int64_t *lds /* >= 
     return base + inc - x;
 }
 
+// Three exclusive scans at once (one set of barriers).
+__device__ __forceinline__ void excl_scan3_1024(const int64_t (&x)[3], int64_t (&ex)[3],
+                                                int64_t (&total)[3], int64_t *lds /* >= 48 */)
+{
+    int64_t inc[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) inc[q] = wave_incl_scan(x[q]);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane_id() == 63)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) lds[q * 16 + w] = inc[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        int64_t base = 0, all = 0;
+        for (int i = 0; i < kOffThreads / 64; ++i) {
+            if (i < w) base += lds[q * 16 + i];
+            all += lds[q * 16 + i];
+        }
+        ex[q] = base + inc[q] - x[q];
+        total[q] = all;
+    }
+    __syncthreads();
+}
+
 // Segment starts seg_off[0..K] (cur[B] becomes B's placement cursor). Then
 // the buckets: boff[B] is B's first bucket (boff[K] buckets in all), cpre[B]
 // the first bucketing chunk of a split block, slist the split blocks
 // (meta[0] of them); a block that is not split is one bucket at its
-// segment, a split block's buckets get zeroed accumulators.
+// segment, a split block's buckets get zeroed accumulators. Up to kOffLds
+// blocks, the offsets are also kept in LDS for the second pass.
+constexpr int kOffLds = 2048;
 __global__ __launch_bounds__(kOffThreads) void k_seg_offsets(int K, SegWs ws)
 {
-    __shared__ int64_t wtot[kOffThreads / 64];
+    __shared__ int64_t wtot[48];
+    __shared__ int64_t s_off[kOffLds + 1];
+    __shared__ int32_t s_boff[kOffLds + 1];
     const int t = threadIdx.x;
     const int C = seg_copies(K);
     const int KC = K * C;
+    const bool lds = K <= kOffLds;
     int64_t carry = 0;
     for (int b0 = 0; b0 < KC; b0 += kOffThreads) {
         const int i = b0 + t;
@@ -489,50 +521,58 @@ __global__ __launch_bounds__(kOffThreads) void k_seg_offsets(int K, SegWs ws)
         int64_t total;
         const int64_t ex = excl_scan_1024(x, wtot, &total);
         if (i < KC) {
-            if ((i & (C - 1)) == 0) ws.seg_off[i / C] = carry + ex;
+            if ((i & (C - 1)) == 0) {
+                ws.seg_off[i / C] = carry + ex;
+                if (lds) s_off[i / C] = carry + ex;
+            }
             ws.cur[slot] = (unsigned long long)(carry + ex);
         }
         carry += total;
     }
-    if (t == 0) ws.seg_off[K] = carry;
+    if (t == 0) {
+        ws.seg_off[K] = carry;
+        if (lds) s_off[K] = carry;
+    }
     __syncthreads();
+    const int64_t *off = lds ? s_off : ws.seg_off;
     int64_t carry_p = 0, carry_q = 0, carry_s = 0;
     for (int b0 = 0; b0 < K; b0 += kOffThreads) {
         const int B = b0 + t;
-        const int64_t m = B < K ? ws.seg_off[B + 1] - ws.seg_off[B] : 0;
-        const int P = B < K ? seg_buckets(m) : 0;
-        const int Q = B < K ? seg_chunks(m) : 0;
-        int64_t tp, tq, ts;
-        const int64_t ep = excl_scan_1024(P, wtot, &tp);
-        const int64_t eq = excl_scan_1024(Q, wtot, &tq);
-        const int64_t es = excl_scan_1024(P > 1 ? 1 : 0, wtot, &ts);
+        const int64_t m = B < K ? off[B + 1] - off[B] : 0;
+        const int P = B < K ? seg_buckets(m, ws.bucket_avg) : 0;
+        const int64_t x[3] = {P, B < K ? seg_chunks(m) : 0, P > 1 ? 1 : 0};
+        int64_t ex[3], tot[3];
+        excl_scan3_1024(x, ex, tot, wtot);
         if (B < K) {
-            const int32_t f = (int32_t)(carry_p + ep);
+            const int32_t f = (int32_t)(carry_p + ex[0]);
             ws.boff[B] = f;
-            ws.cpre[B] = (int32_t)(carry_q + eq);
+            if (lds) s_boff[B] = f;
+            ws.cpre[B] = (int32_t)(carry_q + ex[1]);
             if (P == 1) {
                 ws.bblk[f] = B;
-                ws.bpos[f] = ws.seg_off[B];
+                ws.bpos[f] = off[B];
                 ws.bsize[f] = m;
                 ws.bdel[f] = 0;
             } else {
-                ws.slist[carry_s + es] = B;
+                ws.slist[carry_s + ex[2]] = B;
             }
         }
-        carry_p += tp;
-        carry_q += tq;
-        carry_s += ts;
+        carry_p += tot[0];
+        carry_q += tot[1];
+        carry_s += tot[2];
     }
     if (t == 0) {
         ws.boff[K] = (int32_t)carry_p;
+        if (lds) s_boff[K] = (int32_t)carry_p;
         ws.cpre[K] = (int32_t)carry_q;
         ws.meta[0] = (int32_t)carry_s;
     }
     __syncthreads();
     // the buckets of split blocks, by all threads
+    const int32_t *bo = lds ? s_boff : ws.boff;
     for (int j = 0; j < (int)carry_s; ++j) {
         const int B = ws.slist[j];
-        const int f = ws.boff[B], P = ws.boff[B + 1] - f;
+        const int f = bo[B], P = bo[B + 1] - f;
         for (int i = t; i < P; i += kOffThreads) {
             ws.bblk[f + i] = B;
             ws.bcnt[f + i] = 0;
@@ -774,10 +814,10 @@ struct SegDecide {
 // The move of v into B, priced against W[B] plus the weight change of the
 // events before it (netpre).
 __device__ __forceinline__ void seg_decide_one(const SegDecide &d, int64_t v, int64_t cv,
-                                               int64_t netpre, unsigned long long *acc_lds,
+                                               int64_t gv, int64_t netpre,
+                                               unsigned long long *acc_lds,
                                                unsigned long long *deg_lds)
 {
-    const int64_t gv = d.gp[v];
     bool allowed = gv > 0;
     int64_t P = 0;
     const int64_t x = d.WB + netpre + cv - d.move_lmax;
@@ -799,18 +839,19 @@ __device__ __forceinline__ void seg_decide_one(const SegDecide &d, int64_t v, in
     }
 }
 
-// Scan and decide the kSortItems sorted keys of each thread (blocked: the
+// Scan and decide the IPT sorted keys of each thread (blocked: the
 // thread's first key is at position pos0 of the bucket); carry is the
 // weight change of the positions before this piece.
-__device__ __forceinline__ void seg_scan_decide(const uint64_t (&k)[kSortItems], int64_t pos0,
+template <int IPT>
+__device__ __forceinline__ void seg_scan_decide(const uint64_t (&k)[IPT], int64_t pos0,
                                                 int64_t m, int64_t &carry, const SegDecide &d,
                                                 int64_t *scan_lds, unsigned long long *acc_lds,
                                                 unsigned long long *deg_lds)
 {
-    int64_t w[kSortItems];
+    int64_t w[IPT];
     int64_t ts = 0;
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
+    for (int j = 0; j < IPT; ++j) {
         w[j] = 0;
         if (pos0 + j < m) {
             const int64_t v = (int64_t)((k[j] >> 1) & d.idmask);
@@ -819,22 +860,31 @@ __device__ __forceinline__ void seg_scan_decide(const uint64_t (&k)[kSortItems],
             ts += w[j];
         }
     }
+    // the inflow events' pessimistic gains, loaded together
+    int64_t gv[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j)
+        gv[j] = (pos0 + j < m && !(k[j] & 1ull)) ? d.gp[(int64_t)((k[j] >> 1) & d.idmask)] : 0;
     int64_t total;
     const int64_t inc = block_incl_scan(ts, scan_lds, &total);
     int64_t run = carry + inc - ts;
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
+    for (int j = 0; j < IPT; ++j) {
         if (pos0 + j < m && !(k[j] & 1ull))
-            seg_decide_one(d, (int64_t)((k[j] >> 1) & d.idmask), w[j], run, acc_lds, deg_lds);
+            seg_decide_one(d, (int64_t)((k[j] >> 1) & d.idmask), w[j], gv[j], run, acc_lds,
+                           deg_lds);
         run += w[j];
     }
     carry += total;
 }
 
 // One workgroup per bucket: sort it, scan the weight changes from the
-// bucket's carry, decide the inflow events. A bucket beyond kRun is sorted
-// in runs of kRun and merged pairwise through the other buffer (merge path
-// over global memory, kSegMergeItems outputs per thread and step).
+// bucket's carry, decide the inflow events. Up to 2 kRun keys the two
+// halves are sorted in turn into LDS and merged there (merge path, the
+// merged order in two pieces of kSortItems outputs per thread); a larger
+// bucket is sorted in runs of kRun and merged pairwise through the other
+// buffer (merge path over global memory, kSegMergeItems outputs per thread
+// and step).
 __global__ __launch_bounds__(kBlock) void k_seg_decide(GraphView g, Blocks bk, SegWs ws, int idb,
                                                        const int64_t *__restrict__ gp,
                                                        const int64_t *__restrict__ W,
@@ -843,8 +893,9 @@ __global__ __launch_bounds__(kBlock) void k_seg_decide(GraphView g, Blocks bk, S
                                                        uint8_t *accflag,
                                                        unsigned long long *counters)
 {
-    __shared__ uint64_t lds[kRun];
+    __shared__ uint64_t lds[2 * kRun];
     __shared__ int64_t scan_lds[4];
+    __shared__ int64_t s_cb[kSlots], s_pen[kSlots];
     __shared__ unsigned long long acc_lds, deg_lds;
     const int K = bk.total();
     const int i = blockIdx.x;
@@ -859,6 +910,11 @@ __global__ __launch_bounds__(kBlock) void k_seg_decide(GraphView g, Blocks bk, S
         acc_lds = 0;
         deg_lds = 0;
     }
+    // the block's slot prefix sums and penalty table (the price search reads them per event)
+    if (threadIdx.x < kSlots) {
+        s_cb[threadIdx.x] = cb[(int64_t)B * kSlots + threadIdx.x];
+        s_pen[threadIdx.x] = bk.penq_of(B)[threadIdx.x];
+    }
     __syncthreads();
     SegDecide d;
     d.g = g;
@@ -866,8 +922,8 @@ __global__ __launch_bounds__(kBlock) void k_seg_decide(GraphView g, Blocks bk, S
     d.mode = mode;
     d.WB = W[B];
     d.move_lmax = bk.move_lmax_of(B);
-    d.cbB = cb + (int64_t)B * kSlots;
-    d.penB = bk.penq_of(B);
+    d.cbB = s_cb;
+    d.penB = s_pen;
     d.idmask = ((uint64_t)1 << idb) - 1;
     d.gp = gp;
     d.hub_t = hub_t;
@@ -880,7 +936,48 @@ __global__ __launch_bounds__(kBlock) void k_seg_decide(GraphView g, Blocks bk, S
 #pragma unroll
         for (int j = 0; j < kSortItems; ++j) k[j] = pos0 + j < m ? src[pos0 + j] : ~0ull;
         block_sort_keys<kBlock>(k, lds);
-        seg_scan_decide(k, pos0, m, carry, d, scan_lds, &acc_lds, &deg_lds);
+        seg_scan_decide<kSortItems>(k, pos0, m, carry, d, scan_lds, &acc_lds, &deg_lds);
+    } else if (m <= 2 * kRun) {
+        // each half sorted with the upper half of the buffer as scratch, then
+        // stored; the second half's sort leaves the first half untouched
+        for (int hf = 0; hf < 2; ++hf) {
+            const int64_t pos0 = (int64_t)hf * kRun + (int64_t)threadIdx.x * kSortItems;
+#pragma unroll
+            for (int j = 0; j < kSortItems; ++j) k[j] = pos0 + j < m ? src[pos0 + j] : ~0ull;
+            block_sort_keys<kBlock>(k, lds + kRun);
+#pragma unroll
+            for (int j = 0; j < kSortItems; ++j) lds[pos0 + j] = k[j];
+            __syncthreads();
+        }
+        // the merged order in two pieces: outputs [0, kRun), then [kRun, 2 kRun),
+        // kSortItems consecutive ones per thread (blocked) in each
+        const uint64_t *A = lds, *Bv = lds + kRun;
+        for (int hf = 0; hf < 2; ++hf) {
+            const int diag = hf * kRun + (int)threadIdx.x * kSortItems;
+            int lo = diag > kRun ? diag - kRun : 0;
+            int hi = diag < kRun ? diag : kRun;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (A[mid] <= Bv[diag - 1 - mid]) lo = mid + 1;
+                else hi = mid;
+            }
+            int ia = lo, ib = diag - lo;
+            uint64_t va = ia < kRun ? A[ia] : ~0ull;
+            uint64_t vb = ib < kRun ? Bv[ib] : ~0ull;
+#pragma unroll
+            for (int q = 0; q < kSortItems; ++q) {
+                if (va <= vb) {
+                    k[q] = va;
+                    ++ia;
+                    va = ia < kRun ? A[ia] : ~0ull;
+                } else {
+                    k[q] = vb;
+                    ++ib;
+                    vb = ib < kRun ? Bv[ib] : ~0ull;
+                }
+            }
+            seg_scan_decide<kSortItems>(k, diag, m, carry, d, scan_lds, &acc_lds, &deg_lds);
+        }
     } else {
         uint64_t *dst = (split ? ws.ev : ws.tmp) + s0;
         // sorted runs
@@ -926,7 +1023,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_decide(GraphView g, Blocks bk, S
             const int64_t pos0 = r0 + (int64_t)threadIdx.x * kSortItems;
 #pragma unroll
             for (int j = 0; j < kSortItems; ++j) k[j] = pos0 + j < m ? src[pos0 + j] : ~0ull;
-            seg_scan_decide(k, pos0, m, carry, d, scan_lds, &acc_lds, &deg_lds);
+            seg_scan_decide<kSortItems>(k, pos0, m, carry, d, scan_lds, &acc_lds, &deg_lds);
         }
     }
     __syncthreads();
@@ -953,6 +1050,8 @@ int64_t seq_counter_words(int K)
 {
     return seg_slot(K, 0, seg_copies(K));
 }
+
+int seq_bucket_avg_min() { return kBucketAvg; }
 
 int64_t seq_bucket_bound(int64_t n, int K)
 {

@@ -48,6 +48,10 @@ int64_t env_int(const char *name, int64_t dflt)
 
 struct upr_ctx {
     int device = 0;
+    // target bucket size of the sequence-aware price's split segments
+    // (UPR_SEQ_BUCKET_AVG, read at creation; never below the default, which
+    // sizes the bucket tables)
+    int32_t seq_bucket_avg = 0;
     std::string err;
     // workspace
     int64_t cap_n = 0, cap_k = 0;
@@ -94,6 +98,7 @@ struct upr_ctx {
 
 struct upr_plan {
     upr_ctx *ctx = nullptr;
+    int device = 0;  // the context's device (a plan may outlive its context)
     GraphView g{};
     int64_t nnz = 0, total = 0, maxdeg = 0, maxwdeg = 0, maxvw = 0;
     int32_t *wdeg = nullptr;
@@ -117,6 +122,7 @@ struct upr_plan {
 // its plan, and the per-graph constants and statistics.
 struct upr_batch {
     upr_ctx *ctx = nullptr;
+    int device = 0;  // the context's device (a batch may outlive its context)
     upr_plan *plan = nullptr;  // plan of the union graph
     int32_t ng = 0, k = 0, eps_num = 0, eps_den = 0;
     int64_t n = 0, nnz = 0, max_n = 0;
@@ -587,6 +593,9 @@ int upr_create(upr_ctx **out, int device)
     }
     upr_ctx *c = new upr_ctx();
     c->device = device;
+    c->seq_bucket_avg = (int32_t)std::min<int64_t>(
+        std::max<int64_t>(env_int("UPR_SEQ_BUCKET_AVG", seq_bucket_avg_min()), seq_bucket_avg_min()),
+        1 << 20);
     if (hipSetDevice(device) != hipSuccess ||
         hipMalloc((void **)&c->counters, sizeof(unsigned long long) * kCntWords) != hipSuccess ||
         hipMalloc((void **)&c->flags, sizeof(unsigned long long) * 8) != hipSuccess ||
@@ -723,6 +732,7 @@ static int plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipSt
 
     upr_plan *p = new upr_plan();
     p->ctx = c;
+    p->device = c->device;
     p->g = g;
     // thresholds: the options, else the environment, else the defaults
     p->hub_t = opts && opts->hub_threshold > 0 ? opts->hub_threshold
@@ -811,7 +821,7 @@ static int plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipSt
 void upr_plan_destroy(upr_plan *p)
 {
     if (!p) return;
-    if (p->ctx) (void)hipSetDevice(p->ctx->device);
+    (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
     dfree(p->wdeg);
     dfree(p->hub_ids);
@@ -987,7 +997,8 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
                     const SegWs ws{c->seg_cur,    c->seg_off,    c->seg_boff,  c->seg_cpre,
                                    c->seg_slist,  c->seg_meta,   c->seg_bblk,  c->seg_bpos,
                                    c->seg_bsize,  c->seg_bdel,   c->seg_bcnt,  c->seg_scan_c,
-                                   c->seg_scan_d, c->seg_spl,    c->ev_key,    c->ev_key2};
+                                   c->seg_scan_d, c->seg_spl,    c->ev_key,    c->ev_key2,
+                                   c->seq_bucket_avg};
                     HIP_TRY(c, launch_seq_segments(p->g, bk, b ? b->goff_d : nullptr, c->key,
                                                    c->gp, part, c->avail, sb, ws, W, c->bucket,
                                                    q->mode, p->hub_t, c->mvto, c->accflag,
@@ -1088,7 +1099,7 @@ int upr_rebalance(upr_ctx *c, const upr_plan *p, const upr_params *q, int32_t *p
 void upr_batch_destroy(upr_batch *b)
 {
     if (!b) return;
-    if (b->ctx) (void)hipSetDevice(b->ctx->device);
+    (void)hipSetDevice(b->device);
     (void)hipDeviceSynchronize();
     if (b->plan) upr_plan_destroy(b->plan);
     dfree(b->xadj);
@@ -1122,6 +1133,7 @@ int upr_batch_create(upr_ctx *c, const upr_graph *graphs, const int64_t *nnz_hos
     HIP_TRY(c, hipSetDevice(c->device));
     upr_batch *b = new upr_batch();
     b->ctx = c;
+    b->device = c->device;
     b->ng = ng;
     b->k = k;
     b->eps_num = eps_num;

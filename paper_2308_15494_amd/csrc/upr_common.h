@@ -560,9 +560,11 @@ struct SegWs {
     int64_t *scan_c, *scan_d;   // [NB] scratch of the bucket offsets
     uint64_t *spl;              // [NB] splitters
     uint64_t *ev, *tmp;         // [2n] event keys, bucket / merge buffer
+    int32_t bucket_avg;         // target bucket size of a split segment (>= seq_bucket_avg_min())
 };
 int seq_id_bits(int64_t n);
 int64_t seq_bucket_bound(int64_t n, int K);
+int seq_bucket_avg_min();
 // Entries of ws.cur the segment path uses for K blocks; they must be zero
 // when it starts (the round's init clears them).
 int64_t seq_counter_words(int K);

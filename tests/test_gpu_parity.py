@@ -532,3 +532,19 @@ def test_driver_parity(upr, ctx, case):
         assert np.array_equal(part.cpu().numpy(), opart)
         assert np.array_equal(conn.cpu().numpy().reshape(g.n, k), O.gain_table(g, k, opart))
         assert np.array_equal(W.cpu().numpy(), O.block_weights(g, k, opart))
+
+
+def test_plan_and_batch_outlive_context(upr, ctx):
+    """A plan and a batch destroyed after their context leave no error
+    behind: the next call on another context succeeds."""
+    g = gg.chung_lu(2000, 8.0, 2.3, seed=31)
+    c2 = upr.Context(0)
+    dg = upr.DeviceGraph(g)
+    plan = upr.Plan(c2, dg)
+    b = upr.Batch(c2, [g, gg.rgg2d(800, seed=32)], 4)
+    c2.close()
+    plan.close()
+    b.close()
+    pr = Pair(upr, ctx, g, 4, gg.random_partition(g.n, 4, 1))
+    ost, odbg = pr.round(tau=(1, 2))
+    pr.compare(ost, odbg, "after a closed context")

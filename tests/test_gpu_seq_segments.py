@@ -114,3 +114,28 @@ def test_general_path_wide_keys(upr, ctx):
         say(f"wide keys round {r}")
         ost, odbg = pr.round(tau=tau)
         pr.compare(ost, odbg, f"round {r}")
+
+
+@pytest.mark.parametrize("avg", [3000, 9000], ids=["lds_halves", "global_merge"])
+def test_segment_large_buckets(upr, monkeypatch, avg):
+    """Buckets of a split segment larger than one LDS sort: about 3000 events
+    (two halves sorted and merged in LDS) and about 9000 (runs merged
+    through global memory). The bucket size is raised for a fresh context."""
+    monkeypatch.setenv("UPR_SEQ_BUCKET_AVG", str(avg))
+    c = upr.Context(0)
+    try:
+        g = gg.chung_lu(250000, 8.0, 2.3, seed=252)
+        k = 2
+        part0 = gg.random_partition(g.n, k, 3)
+        pr = Pair(upr, c, g, k, part0)
+        for r, (mode, tau) in enumerate([(0, (1, 2)), (2, (1, 1)), (0, (3, 4))], start=1):
+            say(f"large buckets avg={avg} round {r} mode {mode}")
+            p0 = pr.opart.copy()
+            ost, odbg = pr.round(tau=tau, mode=mode)
+            pr.compare(ost, odbg, f"avg {avg} round {r}")
+            if r == 1:
+                # the segment is split, into buckets of about avg events
+                assert segment_bounds(odbg, p0, k)[0] > avg
+        pr.plan.close()
+    finally:
+        c.close()
