@@ -117,20 +117,20 @@ void upr_destroy(upr_ctx *ctx);
 const char *upr_last_error(const upr_ctx *ctx);
 
 /* Plan: the per-graph preparation of Section 2's input -- weighted degrees
- * omega(I(v)), total node weight c(V), and the degree classes that decide how
- * each node's adjacency is traversed (low- and mid-degree nodes by a lane
- * group, hubs by several workgroups). Created once per graph; enqueued on
+ * omega(I(v)), total node weight c(V), and the hubs: nodes whose adjacency
+ * is traversed by several workgroups instead of inside their node tile.
+ * Created once per graph; enqueued on
  * `stream` and synchronised. The graph arrays must outlive the plan. */
 int upr_plan_create(upr_ctx *ctx, const upr_graph *graph, upr_plan **out, hipStream_t stream);
 
 /* Traversal thresholds of a plan (0 = default: the environment variables
- * UPR_HUB_THRESHOLD / UPR_LOW_THRESHOLD / UPR_DIRTY_DIV if set, else 4096 / 32
- * / 8). Nodes of degree above hub_threshold are hubs (split into edge chunks
- * of whole workgroups), at most low_threshold are handled by 8-lane groups,
- * the rest by a wave; the apply rebuilds table tiles instead of atomic deltas
- * once the moving nodes' degrees sum above nnz / dirty_div. They change only
- * the speed, never a result; paper_2308_15494_amd/tune.py picks them by
- * timing trial rounds. */
+ * UPR_HUB_THRESHOLD / UPR_DIRTY_DIV if set, else 4096 / 8). Nodes of degree
+ * above hub_threshold are hubs (split into edge chunks of whole workgroups);
+ * the apply rebuilds table tiles instead of atomic deltas once the moving
+ * nodes' degrees sum above nnz / dirty_div. low_threshold is ignored (the
+ * apply no longer splits nodes by degree; the field keeps the layout). They
+ * change only the speed, never a result; paper_2308_15494_amd/tune.py picks
+ * them by timing trial rounds. */
 typedef struct {
     int64_t hub_threshold;
     int64_t low_threshold;

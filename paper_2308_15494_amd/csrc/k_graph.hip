@@ -360,7 +360,8 @@ hipError_t launch_node_stats(const GraphView &g, const Blocks &bk, const StatsGe
 
 __global__ void k_store_half(const unsigned long long *counters, int slot, int64_t *out)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = (int64_t)(cnt_get(counters, slot) / 2);
+    const unsigned long long v = wave_cnt_get(counters, slot);
+    if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = (int64_t)(v / 2);
 }
 
 hipError_t launch_store_half(const unsigned long long *counters, int slot, int64_t *out,

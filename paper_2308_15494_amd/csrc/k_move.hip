@@ -12,7 +12,6 @@
 
 namespace upr {
 
-constexpr int kLowLanes = 8;
 
 static int grid_cap(int64_t items, int per_block, int cap)
 {
@@ -62,23 +61,28 @@ hipError_t launch_round_init(const Blocks &bk, int64_t *bucket, int64_t *W, cons
 // (limited imbalance: the cap floor(alpha * L_max)); otherwise constrained and
 // limited imbalance: -1 (forbidden); penalty-free: 0; penalised: penq[l] for
 // the least covering slot l, -1 if none.
-__global__ void k_cb_prefix(Blocks bk, int64_t *bucket, const int64_t *W, int mode, int64_t *pen1)
+// One wave per block j: lane l holds slot l, a wave scan turns the slot
+// weights into cumulative ones, and the least slot that covers the excess is
+// the lowest lane of a ballot.
+__global__ __launch_bounds__(kBlock) void k_cb_prefix(Blocks bk, int64_t *bucket, const int64_t *W,
+                                                       int mode, int64_t *pen1)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= bk.total()) return;
-    int64_t *b = bucket + (int64_t)j * kSlots;
-    int64_t run = 0;
-    for (int l = 0; l < kSlots; ++l) {
-        run += b[l];
-        b[l] = run;
-    }
-    const int64_t x = W[j] + 1 - bk.move_lmax_of(j);
+    static_assert(kSlots <= 64, "one slot per lane");
+    const int64_t j = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    if (j >= bk.total()) return;  // whole waves
+    const int l = lane_id();
+    int64_t *b = bucket + j * kSlots;
+    const int64_t run = wave_incl_scan(l < kSlots ? b[l] : (int64_t)0);
+    if (l < kSlots) b[l] = run;
+    const int64_t x = W[j] + 1 - bk.move_lmax_of((int32_t)j);
+    const uint64_t cov = __ballot(l < kSlots && run >= x);
+    if (l != 0) return;
     int64_t p = 0;
     if (x > 0) {
         if (mode == 1 || mode == 3) p = -1;
         else if (mode == 0) {
-            const int l = covering_slot(b, x);
-            p = l >= kSlots ? -1 : bk.penq_of(j)[l];
+            const int ls = cov ? __ffsll((unsigned long long)cov) - 1 : kSlots;
+            p = ls >= kSlots ? -1 : bk.penq_of((int32_t)j)[ls];
         }
     }
     pen1[j] = p;
@@ -87,8 +91,8 @@ __global__ void k_cb_prefix(Blocks bk, int64_t *bucket, const int64_t *W, int mo
 hipError_t launch_cb_prefix(const Blocks &bk, int64_t *bucket, const int64_t *W, int mode,
                             int64_t *pen1, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cb_prefix, dim3((bk.total() + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                       bk, bucket, W, mode, pen1);
+    hipLaunchKernelGGL(k_cb_prefix, dim3((unsigned)(((int64_t)bk.total() * 64 + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, bk, bucket, W, mode, pen1);
     return hipGetLastError();
 }
 
@@ -765,112 +769,126 @@ hipError_t launch_filter_seq(const GraphView &g, const Blocks &bk, const int32_t
 // conn[u][a] -= omega(v, u), conn[u][b] += omega(v, u). Integer atomics
 // commute, so the result does not depend on the order of the moves. a and b
 // are global block ids (W); the rows use their local ids.
-template <int G>
-__device__ __forceinline__ void apply_class(const GraphView &g, const Blocks &bk, int32_t *part,
-                                            const PartView &pv, int32_t *conn, int64_t *wdst,
-                                            uint64_t mask,
-                                            int64_t lane_v, int32_t lane_to, int32_t *mvto,
-                                            const HubView &h, uint8_t *dirty, int T)
-{
-    const int cnt = __popcll(mask);
-    const int lane = lane_id();
-    const int grp = lane / G;
-    const int gl = lane & (G - 1);
-    for (int p0 = 0; p0 < cnt; p0 += 64 / G) {
-        const int p = p0 + grp;
-        const bool ok = p < cnt;
-        const int src = ok ? nth_set_bit(mask, p) : 0;
-        const int64_t v = __shfl(lane_v, src);
-        const int32_t b = __shfl(lane_to, src);
-        if (!ok) continue;
-        int32_t A = 0;
-        if (gl == 0) A = part[v];
-        A = __shfl(A, lane & ~(G - 1));
-        const int32_t k = bk.k;
-        const int32_t a = bk.local(A), lb = bk.local(b);  // row indices
-        const int64_t e1 = g.xadj[v + 1];
-        // kEdgeUnroll neighbours per lane are loaded before they are used
-        for (int64_t e = g.xadj[v] + gl; e < e1; e += (int64_t)kEdgeUnroll * G) {
-            int32_t u[kEdgeUnroll];
-#pragma unroll
-            for (int i = 0; i < kEdgeUnroll; ++i) {
-                const int64_t ei = e + (int64_t)i * G;
-                u[i] = ei < e1 ? g.adjncy[ei] : -1;
-            }
-            if (dirty) {
-#pragma unroll
-                for (int i = 0; i < kEdgeUnroll; ++i)
-                    if (u[i] >= 0) dirty[u[i] / T] = 1;
-            } else {
-                int32_t w[kEdgeUnroll];
-                bool hub[kEdgeUnroll];
-#pragma unroll
-                for (int i = 0; i < kEdgeUnroll; ++i) {
-                    const int64_t ei = e + (int64_t)i * G;
-                    w[i] = u[i] >= 0 ? edge_weight(g, ei) : 0;
-                    hub[i] = u[i] >= 0 && is_hub(h, u[i]);  // hub rows are rebuilt afterwards
-                }
-#pragma unroll
-                for (int i = 0; i < kEdgeUnroll; ++i) {
-                    if (u[i] < 0 || hub[i]) continue;
-                    atomicAdd(&conn[(int64_t)u[i] * k + a], -w[i]);
-                    atomicAdd(&conn[(int64_t)u[i] * k + lb], w[i]);
-                }
-            }
-        }
-        if (gl == 0) {
-            const int64_t cv = node_weight(g, v);
-            part[v] = b;
-            pset((void *)pv.p, pv.bytes, v, lb);
-            mvto[v] = -1;
-            atomicAdd((unsigned long long *)&wdst[A], (unsigned long long)(-cv));
-            atomicAdd((unsigned long long *)&wdst[b], (unsigned long long)cv);
-        }
-    }
-}
+//
+// One workgroup per tile of kApplyTile consecutive nodes. Each mover of the
+// tile is bookkept by its own thread (part, compact copy, mvto, block
+// weights summed in LDS); then the movers' edges are spread over all threads
+// of the workgroup (edge -> node by a binary search over the tile's degree
+// prefix), so a mover of high degree is split over many lanes instead of
+// holding up one wave. Delta mode: the two atomics per edge; rebuild mode
+// (moving degrees above dirty_threshold): the neighbours' tiles are marked.
+// Hubs: bookkeeping only, their edges were applied by k_apply_hub (which
+// read the old part).
+constexpr int kApplyTile = 1024;
 
 __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, Blocks bk, int32_t *part,
                                                    PartView pv, int32_t *conn, int64_t *W,
-                                                   int32_t *mvto,
-                                                   int64_t low_t, int64_t hub_t, HubView h,
+                                                   int32_t *mvto, int64_t hub_t,
                                                    const unsigned long long *counters,
                                                    int64_t dirty_threshold, uint8_t *dirty_flags,
                                                    int T)
 {
-    uint8_t *dirty =
-        (int64_t)cnt_get(counters, CNT_MOVED_DEG) > dirty_threshold ? dirty_flags : (uint8_t *)nullptr;
+    __shared__ int32_t vstart[kApplyTile + 1];
+    __shared__ int64_t estart[kApplyTile];
+    __shared__ uint32_t sab[kApplyTile];  // local source | local target << 16
+    __shared__ int32_t scan_lds[4];
     extern __shared__ __align__(16) unsigned char lds_raw[];
+    uint8_t *dirty = (int64_t)wave_cnt_get(counters, CNT_MOVED_DEG) > dirty_threshold
+                         ? dirty_flags
+                         : (uint8_t *)nullptr;
     int64_t *wloc = (int64_t *)lds_raw;
     const int32_t K = bk.total();
     const bool use_lds = K <= 2048;
-    if (use_lds) {
+    if (use_lds)
         for (int j = threadIdx.x; j < K; j += kBlock) wloc[j] = 0;
-        __syncthreads();
-    }
+    __syncthreads();
     int64_t *wdst = use_lds ? wloc : W;
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < g.n;
-         base += stride) {
-        const int64_t v = base + lane_id();
-        int32_t to = -1;
-        int64_t deg = 0;
-        if (v < g.n) {
-            to = mvto[v];
-            if (to >= 0) deg = g.xadj[v + 1] - g.xadj[v];
+    const int64_t v0 = (int64_t)blockIdx.x * kApplyTile;
+    const int nt = (int)((g.n - v0) < kApplyTile ? (g.n - v0) : kApplyTile);
+
+    // bookkeeping per mover, the movers' degrees (hubs: none) and their
+    // prefix: thread t takes the tile's nodes 4t .. 4t + 3 (one 16-byte load
+    // of mvto), one scan over the threads' sums
+    static_assert(kApplyTile == 4 * kBlock, "four nodes per thread");
+    const int i0 = 4 * threadIdx.x;
+    int32_t to4[4] = {-1, -1, -1, -1};
+    if (i0 + 3 < nt) {
+        const int4 t4 = *(const int4 *)(mvto + v0 + i0);
+        to4[0] = t4.x;
+        to4[1] = t4.y;
+        to4[2] = t4.z;
+        to4[3] = t4.w;
+    } else {
+        for (int j = 0; j < 4; ++j)
+            if (i0 + j < nt) to4[j] = mvto[v0 + i0 + j];
+    }
+    int32_t vd4[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int32_t to = to4[j];
+        if (to < 0) continue;
+        const int i = i0 + j;
+        const int64_t v = v0 + i;
+        const int64_t e0 = g.xadj[v], e1 = g.xadj[v + 1];
+        const int32_t A = part[v];
+        const uint32_t lb = (uint32_t)bk.local(to);
+        if (e1 - e0 <= hub_t) {
+            vd4[j] = (int32_t)(e1 - e0);
+            estart[i] = e0;
+            sab[i] = (uint32_t)bk.local(A) | (lb << 16);
         }
-        const uint64_t mlow = __ballot(to >= 0 && deg <= low_t);
-        const uint64_t mmid = __ballot(to >= 0 && deg > low_t && deg <= hub_t);
-        if (mlow) apply_class<kLowLanes>(g, bk, part, pv, conn, wdst, mlow, v, to, mvto, h, dirty, T);
-        if (mmid) apply_class<64>(g, bk, part, pv, conn, wdst, mmid, v, to, mvto, h, dirty, T);
-        if (to >= 0 && deg > hub_t) {
-            // a hub: its edges were applied by k_apply_hub (which read the old part)
-            const int32_t A = part[v];
-            const int64_t cv = node_weight(g, v);
-            part[v] = to;
-            pset((void *)pv.p, pv.bytes, v, bk.local(to));
-            mvto[v] = -1;
-            atomicAdd((unsigned long long *)&wdst[A], (unsigned long long)(-cv));
-            atomicAdd((unsigned long long *)&wdst[to], (unsigned long long)cv);
+        const int64_t cv = node_weight(g, v);
+        part[v] = to;
+        pset((void *)pv.p, pv.bytes, v, (int32_t)lb);
+        mvto[v] = -1;
+        atomicAdd((unsigned long long *)&wdst[A], (unsigned long long)(-cv));
+        atomicAdd((unsigned long long *)&wdst[to], (unsigned long long)cv);
+    }
+    int32_t run;
+    {
+        const int32_t sum = vd4[0] + vd4[1] + vd4[2] + vd4[3];
+        const int32_t inc = block_incl_scan(sum, scan_lds, &run);
+        int32_t x = inc - sum;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (i0 + j < nt) vstart[i0 + j] = x;
+            x += vd4[j];
+        }
+    }
+    if (threadIdx.x == 0) vstart[nt] = run;
+    __syncthreads();
+
+    // the movers' edges, kEdgeUnroll per thread and step so that their loads overlap
+    const int32_t E = run;
+    const int32_t k = bk.k;
+    for (int32_t p0 = threadIdx.x; p0 < E; p0 += kBlock * kEdgeUnroll) {
+        int node[kEdgeUnroll];
+        int64_t e[kEdgeUnroll];
+        int32_t u[kEdgeUnroll];
+#pragma unroll
+        for (int i = 0; i < kEdgeUnroll; ++i) {
+            const int32_t p = p0 + i * kBlock;
+            node[i] = p < E ? upper_index(vstart, nt, p) : -1;
+            e[i] = node[i] >= 0 ? estart[node[i]] + (p - vstart[node[i]]) : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < kEdgeUnroll; ++i) u[i] = node[i] >= 0 ? g.adjncy[e[i]] : -1;
+        if (dirty) {
+#pragma unroll
+            for (int i = 0; i < kEdgeUnroll; ++i)
+                if (u[i] >= 0) mark_dirty(dirty, u[i] / T);
+        } else {
+            int32_t w[kEdgeUnroll];
+#pragma unroll
+            for (int i = 0; i < kEdgeUnroll; ++i) w[i] = node[i] >= 0 ? edge_weight(g, e[i]) : 0;
+#pragma unroll
+            for (int i = 0; i < kEdgeUnroll; ++i) {
+                if (u[i] < 0) continue;
+                const uint32_t ab = sab[node[i]];
+                int32_t *row = conn + (int64_t)u[i] * k;
+                atomicAdd(&row[ab & 0xFFFF], -w[i]);
+                atomicAdd(&row[ab >> 16], w[i]);
+            }
         }
     }
     if (use_lds) {
@@ -881,9 +899,10 @@ __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, Blocks bk, int32_
 }
 
 // Hub moves, before k_apply: each chunk updates the rows of its neighbours
-// (part of the hub is still its source block here). The first chunk of every
-// hub also clears the hub's own row, which k_gain_hub rebuilds after the
-// apply.
+// (part of the hub is still its source block here). When the apply rebuilds
+// the table, the first chunk of every hub also clears the hub's own row,
+// which k_gain_hub rebuilds after the apply; in the delta mode hub rows get
+// their deltas like every other row.
 __global__ __launch_bounds__(kBlock) void k_apply_hub(GraphView g, Blocks bk, const int32_t *part,
                                                        int32_t *conn, const int32_t *mvto,
                                                        HubView h, const unsigned long long *counters,
@@ -893,18 +912,18 @@ __global__ __launch_bounds__(kBlock) void k_apply_hub(GraphView g, Blocks bk, co
     const HubChunk c = h.chunks[blockIdx.x];
     const int64_t v = h.ids[c.hub];
     const int32_t k = bk.k;
-    if (c.e0 == g.xadj[v])
+    const bool rebuild = (int64_t)wave_cnt_get(counters, CNT_MOVED_DEG) > dirty_threshold;
+    if (rebuild && c.e0 == g.xadj[v])
         for (int j = threadIdx.x; j < k; j += kBlock) conn[v * (int64_t)k + j] = 0;
     const int32_t B = mvto[v];
     if (B < 0) return;
-    if ((int64_t)cnt_get(counters, CNT_MOVED_DEG) > dirty_threshold) {
-        for (int64_t e = c.e0 + threadIdx.x; e < c.e1; e += kBlock) dirty[g.adjncy[e] / T] = 1;
+    if (rebuild) {
+        for (int64_t e = c.e0 + threadIdx.x; e < c.e1; e += kBlock) mark_dirty(dirty, g.adjncy[e] / T);
         return;
     }
     const int32_t a = bk.local(part[v]), b = bk.local(B);
     for (int64_t e = c.e0 + threadIdx.x; e < c.e1; e += kBlock) {
         const int64_t u = g.adjncy[e];
-        if (is_hub(h, u)) continue;
         const int32_t w = edge_weight(g, e);
         atomicAdd(&conn[u * k + a], -w);
         atomicAdd(&conn[u * k + b], w);
@@ -912,7 +931,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_hub(GraphView g, Blocks bk, co
 }
 
 hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, const PartView &pv,
-                        int32_t *conn, int64_t *W, int32_t *mvto, int64_t low_t, int64_t hub_t,
+                        int32_t *conn, int64_t *W, int32_t *mvto, int64_t hub_t,
                         const HubView &h, const unsigned long long *counters,
                         int64_t dirty_threshold, uint8_t *dirty, hipStream_t s)
 {
@@ -926,12 +945,13 @@ hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, con
                            conn, mvto, h, counters, dirty_threshold, dirty, T);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_apply, dim3(grid_cap(g.n, kBlock, 4096)), dim3(kBlock), lds, s, g, bk,
-                       part, pv, conn, W, mvto, low_t, hub_t, h, counters, dirty_threshold, dirty, T);
+    const int64_t tiles = (g.n + kApplyTile - 1) / kApplyTile;
+    hipLaunchKernelGGL(k_apply, dim3((unsigned)tiles), dim3(kBlock), lds, s, g, bk, part, pv, conn,
+                       W, mvto, hub_t, counters, dirty_threshold, dirty, T);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // rebuild the marked tiles (none are marked in the delta mode), then the hub rows
+    // rebuild the marked tiles and the hub rows (nothing in the delta mode)
     if ((e = launch_gain_tile(g, k, pv, conn, hub_t, dirty, s)) != hipSuccess) return e;
-    return launch_gain_hub(g, k, pv, conn, h, s);
+    return launch_gain_hub(g, k, pv, conn, h, s, counters, dirty_threshold);
 }
 
 // ----------------------------------------------------------------- stats --
@@ -939,14 +959,21 @@ hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, con
 __global__ void k_stats_final(int64_t *stats, const unsigned long long *c, int64_t lmax,
                               int64_t iters, int64_t status)
 {
+    // one wave: every lane reads its copy of each counter
+    const int64_t cb = (int64_t)wave_cnt_get(c, CNT_CUT2_BEFORE) / 2;
+    const int64_t cm = (int64_t)wave_cnt_get(c, CNT_CUT2_MOVES) / 2;
+    const int64_t ca = (int64_t)wave_cnt_get(c, CNT_CUT2_AFTER) / 2;
+    const int64_t nc = (int64_t)wave_cnt_get(c, CNT_CAND);
+    const int64_t na = (int64_t)wave_cnt_get(c, CNT_ACC);
+    const int64_t nr = (int64_t)wave_cnt_get(c, CNT_REBAL_MOVES);
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     stats[0] = lmax;
-    stats[1] = (int64_t)cnt_get(c, CNT_CUT2_BEFORE) / 2;
-    stats[2] = (int64_t)cnt_get(c, CNT_CUT2_MOVES) / 2;
-    stats[3] = (int64_t)cnt_get(c, CNT_CUT2_AFTER) / 2;
-    stats[4] = (int64_t)cnt_get(c, CNT_CAND);
-    stats[5] = (int64_t)cnt_get(c, CNT_ACC);
-    stats[6] = (int64_t)cnt_get(c, CNT_REBAL_MOVES);
+    stats[1] = cb;
+    stats[2] = cm;
+    stats[3] = ca;
+    stats[4] = nc;
+    stats[5] = na;
+    stats[6] = nr;
     stats[7] = iters;
     stats[8] = status;
     for (int i = 9; i < 12; ++i) stats[i] = 0;
@@ -955,7 +982,7 @@ __global__ void k_stats_final(int64_t *stats, const unsigned long long *c, int64
 // dst = src (summed over the copies) for a spread counter.
 __global__ void k_cnt_copy(unsigned long long *c, int dst, int src)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) cnt_set(c, dst, cnt_get(c, src));
+    wave_cnt_set(c, dst, wave_cnt_get(c, src));
 }
 
 hipError_t launch_cnt_copy(unsigned long long *counters, int dst, int src, hipStream_t s)

@@ -66,8 +66,10 @@ __device__ __forceinline__ bool rb_kept(const RbView &r, int64_t v, int32_t a, i
 
 // Count source blocks and snapshot W (one workgroup). For a batch, also per
 // graph: gstat[g][GS_OVER]. first: the count also goes to CNT_OVER0.
-__global__ void k_rb_begin(Blocks bk, const int64_t *W, int64_t *W0, unsigned long long *counters,
-                           int64_t *gstat, int first)
+__global__ __launch_bounds__(kBlock) void k_rb_begin(Blocks bk, const int64_t *W, int64_t *W0,
+                                                      unsigned long long *counters, int64_t *gstat,
+                                                      int first, unsigned long long *pub,
+                                                      unsigned long long seq)
 {
     __shared__ unsigned long long red[4];
     const int32_t K = bk.total();
@@ -84,17 +86,37 @@ __global__ void k_rb_begin(Blocks bk, const int64_t *W, int64_t *W0, unsigned lo
         if (gstat && o) atomic_add_i64(&gstat[(int64_t)bk.graph(j) * GS_COUNT + GS_OVER], 1);
     }
     over = block_sum(over, red);
-    if (threadIdx.x == 0) {
-        cnt_set(counters, CNT_OVER, over);
-        if (first) cnt_set(counters, CNT_OVER0, over);
+    if (threadIdx.x < 64) {
+        wave_cnt_set(counters, CNT_OVER, over);
+        if (first) wave_cnt_set(counters, CNT_OVER0, over);
     }
+    if (!pub) return;
+    // publish every counter's sum: wave w sums slots 8w .. 8w + 7 (the ones
+    // set above take the value computed here)
+    static_assert(CNT_COUNT == 32 && kBlock == 256, "four waves of eight slots");
+    const int w = threadIdx.x >> 6;
+    unsigned long long v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = wave_cnt_get(counters, w * 8 + i);
+    if (lane_id() < 8) {
+        const int slot = w * 8 + lane_id();
+        unsigned long long x = v[0];
+#pragma unroll
+        for (int i = 1; i < 8; ++i) x = lane_id() == i ? v[i] : x;
+        if (slot == CNT_OVER || (first && slot == CNT_OVER0)) x = over;
+        pub[1 + slot] = x;
+    }
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(&pub[0], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 hipError_t launch_rb_begin(const Blocks &bk, const int64_t *W, const RebalWs &r,
-                           unsigned long long *counters, int64_t *gstat, hipStream_t s, int first)
+                           unsigned long long *counters, int64_t *gstat, hipStream_t s, int first,
+                           unsigned long long *pub, unsigned long long seq)
 {
     hipLaunchKernelGGL(k_rb_begin, dim3(1), dim3(kBlock), 0, s, bk, W, r.W0, counters, gstat,
-                       first);
+                       first, pub, seq);
     return hipGetLastError();
 }
 

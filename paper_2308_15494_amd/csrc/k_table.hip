@@ -195,12 +195,17 @@ hipError_t launch_gain_tile(const GraphView &g, int32_t k, const PartView &part,
 // --------------------------------------------------------------- hub rows --
 
 // One workgroup per chunk of a hub's edges: accumulate into an LDS row, then
-// add the non-zero entries into the hub's row of conn (zeroed by the tile).
+// add the non-zero entries into the hub's row of conn (zeroed by the tile,
+// or by the hub apply). counters != null: only if the apply before rebuilt
+// the table.
 __global__ __launch_bounds__(kBlock) void k_gain_hub(GraphView g, int32_t k, PartView part,
-                                                      int32_t *conn, HubView h)
+                                                      int32_t *conn, HubView h,
+                                                      const unsigned long long *counters,
+                                                      int64_t dirty_threshold)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     int32_t *row = (int32_t *)lds_raw;
+    if (counters && (int64_t)wave_cnt_get(counters, CNT_MOVED_DEG) <= dirty_threshold) return;
     const HubChunk c = h.chunks[blockIdx.x];
     const int64_t v = h.ids[c.hub];
     for (int j = threadIdx.x; j < k; j += kBlock) row[j] = 0;
@@ -231,11 +236,12 @@ hipError_t launch_hub_bits(const HubView &h, uint32_t *bits, hipStream_t s)
 }
 
 hipError_t launch_gain_hub(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,
-                           const HubView &h, hipStream_t s)
+                           const HubView &h, hipStream_t s, const unsigned long long *counters,
+                           int64_t dirty_threshold)
 {
     if (h.nchunks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_gain_hub, dim3((unsigned)h.nchunks), dim3(kBlock), (size_t)k * 4, s, g, k,
-                       part, conn, h);
+                       part, conn, h, counters, dirty_threshold);
     return hipGetLastError();
 }
 

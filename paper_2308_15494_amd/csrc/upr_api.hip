@@ -22,7 +22,6 @@ namespace {
 
 constexpr int64_t kHubChunkEdges = 4096;
 constexpr int64_t kDefaultHubThreshold = 4096;
-constexpr int64_t kDefaultLowThreshold = 32;
 constexpr int64_t kChunkEntries = int64_t(1) << 20;  // rebalancing id-chunk sums per side
 
 struct Timing {
@@ -88,6 +87,11 @@ struct upr_ctx {
     RebalWs rb{};
     unsigned long long *pinned = nullptr;  // host mirror of the counters' copies
     unsigned long long cnt[CNT_COUNT] = {0};  // their sums, after sync_counters
+    // host-coherent [1 + CNT_COUNT]: a sequence number, then the counter sums
+    // published by the rebalancer's begin kernel (null: not available)
+    unsigned long long *pub = nullptr;
+    unsigned long long *pub_d = nullptr;  // its device address
+    unsigned long long pub_seq = 0;
     // pinned host area of the batches run on this context (grown on demand;
     // pinned allocations are slow, and batches are rebuilt often by a server)
     int64_t *bpinned = nullptr;
@@ -109,7 +113,7 @@ struct upr_plan {
     int64_t *gacc = nullptr;
     unsigned int *hub_ticket = nullptr;
     uint32_t *hub_bits = nullptr;  // [ceil(n/32)]
-    int64_t hub_t = kDefaultHubThreshold, low_t = kDefaultLowThreshold;
+    int64_t hub_t = kDefaultHubThreshold;
     int64_t dirty_threshold = 0;  // moved-degree sum above which tiles are rebuilt
 
     HubView hubs() const
@@ -387,6 +391,32 @@ int sync_counters(upr_ctx *c, hipStream_t s)
     return UPR_OK;
 }
 
+// Wait for the counter sums that the last k_rb_begin published with
+// sequence number seq. The host spins on pub[0] (a sleeping stream wait
+// wakes up tens of microseconds late); every 1024 polls it asks whether the
+// stream has drained, which ends the wait with an error if the stream failed
+// or finished without publishing.
+static int wait_published(upr_ctx *c, hipStream_t s, unsigned long long seq)
+{
+    for (uint64_t i = 1;; ++i) {
+        if (__atomic_load_n(&c->pub[0], __ATOMIC_ACQUIRE) == seq) break;
+        if ((i & 1023) == 0) {
+            const hipError_t q = hipStreamQuery(s);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(c, UPR_E_HIP, "HIP error %d (%s) while waiting for the counters", (int)q,
+                            hipGetErrorString(q));
+            }
+            if (__atomic_load_n(&c->pub[0], __ATOMIC_ACQUIRE) == seq) break;
+            return fail(c, UPR_E_HIP, "the stream finished without publishing the counters");
+        }
+        __builtin_ia32_pause();
+    }
+    for (int j = 0; j < CNT_COUNT; ++j) c->cnt[j] = __atomic_load_n(&c->pub[1 + j], __ATOMIC_RELAXED);
+    return UPR_OK;
+}
+
 int64_t default_iters(const upr_plan *p, int32_t k)
 {
     return p->g.vwgt ? 4 * (int64_t)k : (int64_t)k + 1;
@@ -411,22 +441,31 @@ int rebalance_loop(upr_ctx *c, const upr_plan *p, const Blocks &bk, int plain, i
     int64_t iters = 0, status = 0;
     const int hist32 = hist32_ok(p);
     c->rb_dirty = true;
+    // every k_rb_begin publishes the counters (when the context can); the
+    // host waits for the last one's
+    auto begin = [&](int first) -> int {
+        HIP_TRY(c, launch_rb_begin(bk, W, c->rb, c->counters, nullptr, s, first, c->pub_d,
+                                   ++c->pub_seq));
+        return UPR_OK;
+    };
+    auto sync = [&]() -> int {
+        return c->pub ? wait_published(c, s, c->pub_seq) : sync_counters(c, s);
+    };
     auto sub_iteration = [&]() -> int {
         HIP_TRY(c, launch_rb_iteration(p->g, bk, part, conn, c->rb, c->mvto, hist32, plain,
                                        p->hub_t, c->counters, nullptr, s));
-        HIP_TRY(c, launch_apply(p->g, bk, part, pv, conn, W, c->mvto, p->low_t, p->hub_t, h,
+        HIP_TRY(c, launch_apply(p->g, bk, part, pv, conn, W, c->mvto, p->hub_t, h,
                                 c->counters, p->dirty_threshold, c->dirty, s));
-        HIP_TRY(c, launch_rb_begin(bk, W, c->rb, c->counters, nullptr, s));
-        return UPR_OK;
+        return begin(0);
     };
-    HIP_TRY(c, launch_rb_begin(bk, W, c->rb, c->counters, nullptr, s, 1));
     int rc;
+    if ((rc = begin(1))) return rc;
     if (speculate) {
         // the first sub-iteration without waiting for the count of overloaded
         // blocks: with none it finds no movable node and changes nothing
         if ((rc = sub_iteration())) return rc;
     }
-    rc = sync_counters(c, s);
+    rc = sync();
     if (rc) return rc;
     if (c->cnt[CNT_BAD_INPUT]) return fail(c, UPR_E_ARG, "part holds values outside [0, k)");
     if (speculate && c->cnt[CNT_OVER0] != 0) iters = 1;
@@ -442,7 +481,7 @@ int rebalance_loop(upr_ctx *c, const upr_plan *p, const Blocks &bk, int plain, i
         }
         ++iters;
         if ((rc = sub_iteration())) return rc;
-        rc = sync_counters(c, s);
+        rc = sync();
         if (rc) return rc;
     }
     c->rb_dirty = false;
@@ -532,7 +571,7 @@ int rebalance_loop_batch(upr_ctx *c, const upr_plan *p, upr_batch *b, const Bloc
         HIP_TRY(c, hipMemcpyAsync(b->srcl_d, b->srcl_h, sizeof(int64_t) * ng, hipMemcpyHostToDevice, s));
         HIP_TRY(c, launch_rb_iteration(p->g, bk, part, conn, c->rb, c->mvto, hist32, plain,
                                        p->hub_t, c->counters, b->gstat_d, s));
-        HIP_TRY(c, launch_apply(p->g, bk, part, pv, conn, W, c->mvto, p->low_t, p->hub_t, h,
+        HIP_TRY(c, launch_apply(p->g, bk, part, pv, conn, W, c->mvto, p->hub_t, h,
                                 c->counters, p->dirty_threshold, c->dirty, s));
         HIP_TRY(c, launch_rb_begin(bk, W, c->rb, c->counters, b->gstat_d, s));
         rc = sync_batch(c, b, s);
@@ -608,6 +647,17 @@ int upr_create(upr_ctx **out, int device)
         return UPR_E_NOMEM;
     }
     (void)hipMemset(c->counters, 0, sizeof(unsigned long long) * kCntWords);
+    // the published counters: without host-coherent memory the rebalancing
+    // loop copies the counters and waits for the stream instead
+    if (hipHostMalloc((void **)&c->pub, sizeof(unsigned long long) * (1 + CNT_COUNT),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&c->pub_d, c->pub, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        if (c->pub) (void)hipHostFree(c->pub);
+        c->pub = c->pub_d = nullptr;
+    } else {
+        for (int i = 0; i <= CNT_COUNT; ++i) c->pub[i] = 0;
+    }
     *out = c;
     return UPR_OK;
 }
@@ -624,6 +674,7 @@ void upr_destroy(upr_ctx *c)
     dfree(c->lmax1);
     dfree(c->srcl1);
     if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->pub) (void)hipHostFree(c->pub);
     if (c->bpinned) (void)hipHostFree(c->bpinned);
     for (auto &p : c->timing.pending) {
         (void)hipEventDestroy(p.a);
@@ -737,12 +788,9 @@ static int plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipSt
     // thresholds: the options, else the environment, else the defaults
     p->hub_t = opts && opts->hub_threshold > 0 ? opts->hub_threshold
                                                : env_int("UPR_HUB_THRESHOLD", kDefaultHubThreshold);
-    p->low_t = opts && opts->low_threshold > 0 ? opts->low_threshold
-                                               : env_int("UPR_LOW_THRESHOLD", kDefaultLowThreshold);
     const int64_t dirty_div = opts && opts->dirty_div > 0 ? opts->dirty_div : env_int("UPR_DIRTY_DIV", 8);
     // a tile's edge count (nodes per tile x hub threshold) must fit int32
     p->hub_t = std::min<int64_t>(std::max<int64_t>(p->hub_t, 1), (int64_t)1 << 20);
-    p->low_t = std::min<int64_t>(std::max<int64_t>(p->low_t, 0), p->hub_t);
     int32_t *hub_list = nullptr;
     auto bail = [&](int code, const char *msg) {
         dfree(hub_list);
@@ -1027,7 +1075,7 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
         }
         {
             PhaseTimer t(c, 4, s);
-            HIP_TRY(c, launch_apply(p->g, bk, part, pv, conn, W, c->mvto, p->low_t, p->hub_t, h,
+            HIP_TRY(c, launch_apply(p->g, bk, part, pv, conn, W, c->mvto, p->hub_t, h,
                                     c->counters, p->dirty_threshold, c->dirty, s));
         }
         {

@@ -155,6 +155,15 @@ __device__ __forceinline__ bool is_hub(const HubView &h, int64_t u)
 }
 
 // ---------------------------------------------------------------- device --
+// Marks tile t of the gain table for a rebuild. The flag is read first and
+// written only while it is clear: once a tile is marked, the moves of its
+// other neighbours only read the cached byte instead of queueing stores on
+// the few cache lines that hold every tile's flag.
+__device__ __forceinline__ void mark_dirty(uint8_t *dirty, int64_t t)
+{
+    if (dirty[t] == 0) dirty[t] = 1;
+}
+
 
 __device__ __forceinline__ int64_t node_weight(const GraphView &g, int64_t v)
 {
@@ -415,10 +424,24 @@ __device__ __forceinline__ unsigned long long cnt_get(const unsigned long long *
     for (int i = 0; i < kCntCopies; ++i) s += c[i * CNT_COUNT + slot];
     return s;
 }
+// The same sum read by a whole wave (every lane active): lane i loads copy i,
+// so the copies arrive in one round trip; every lane gets the sum.
+__device__ __forceinline__ unsigned long long wave_cnt_get(const unsigned long long *c, int slot)
+{
+    static_assert(kCntCopies == 64, "one copy per lane");
+    return wave_sum(c[lane_id() * CNT_COUNT + slot]);
+}
 // One thread sets a counter: copy 0 holds the value, the others 0.
 __device__ __forceinline__ void cnt_set(unsigned long long *c, int slot, unsigned long long v)
 {
     for (int i = 0; i < kCntCopies; ++i) c[i * CNT_COUNT + slot] = i == 0 ? v : 0ull;
+}
+
+// The same by a whole wave: lane i writes copy i.
+__device__ __forceinline__ void wave_cnt_set(unsigned long long *c, int slot, unsigned long long v)
+{
+    const int i = lane_id();
+    c[i * CNT_COUNT + slot] = i == 0 ? v : 0ull;
 }
 
 // Add the number of lanes with pred to an LDS counter (lane 0 of the wave).
@@ -450,8 +473,14 @@ int gain_tile_nodes(int32_t k);
 // cleared).
 hipError_t launch_gain_tile(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,
                             int64_t hub_t, uint8_t *dirty, hipStream_t s);
+// Hub rows, accumulated into rows that are zero. After an apply (counters
+// != null) only when that apply rebuilt the table (the moving nodes' degrees
+// above dirty_threshold); in the delta mode the rows are already up to date
+// and every workgroup returns at once.
 hipError_t launch_gain_hub(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,
-                           const HubView &h, hipStream_t s);
+                           const HubView &h, hipStream_t s,
+                           const unsigned long long *counters = nullptr,
+                           int64_t dirty_threshold = 0);
 // Compact copy of part (bytes = 1 or 2).
 // Compact copy of the local blocks (bytes = 1 or 2). Checks every value: a
 // global block id below bk.total() and, for a batch (goff = node offsets of
@@ -579,10 +608,10 @@ hipError_t launch_seq_segments(const GraphView &g, const Blocks &bk, const int64
 // If the moving nodes' degrees sum to at most dirty_threshold
 // (counters[CNT_MOVED_DEG]) the neighbours' rows get integer-atomic deltas;
 // otherwise their gain-table tiles are marked and rebuilt from the new
-// partition. Hub rows are always rebuilt.
+// partition, and the hub rows are rebuilt.
 // pv: the compact partition copy to keep in step (pv.p writable, or bytes 4).
 hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, const PartView &pv,
-                        int32_t *conn, int64_t *W, int32_t *mvto, int64_t low_t, int64_t hub_t,
+                        int32_t *conn, int64_t *W, int32_t *mvto, int64_t hub_t,
                         const HubView &h, const unsigned long long *counters,
                         int64_t dirty_threshold, uint8_t *dirty, hipStream_t s);
 hipError_t launch_stats_final(int64_t *stats, const unsigned long long *counters, int64_t lmax,
@@ -614,9 +643,13 @@ struct RebalWs {
 
 // Snapshot W and count the source blocks (weight above src_lmax): in total
 // (counters[CNT_OVER]) and, for a batch, per graph (gstat[g][GS_OVER]).
+// pub (host-coherent memory, may be null): the sums of all CNT_COUNT counters
+// go to pub[1 + slot], then pub[0] = seq with a system-scope release, so the
+// host can read them without waiting for the stream.
 hipError_t launch_rb_begin(const Blocks &bk, const int64_t *W, const RebalWs &r,
                            unsigned long long *counters, int64_t *gstat, hipStream_t s,
-                           int first = 0);
+                           int first = 0, unsigned long long *pub = nullptr,
+                           unsigned long long seq = 0);
 // One sub-iteration up to the move marks: targets and buckets, source and
 // target selection; accepted nodes get mvto[v] = target. hist32: the
 // per-workgroup histograms may use 32-bit LDS counters (no overflow).

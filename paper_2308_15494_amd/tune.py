@@ -3,8 +3,7 @@ batch.
 
 The thresholds decide how work is spread over lanes and workgroups (hub
 threshold: degree above which a node's edges are split into whole-workgroup
-chunks; low threshold: degree up to which 8-lane groups handle a node; dirty
-divisor: when the apply rebuilds table tiles instead of sending atomic
+chunks; dirty divisor: when the apply rebuilds table tiles instead of sending atomic
 deltas). None of them changes a result, so the tuner may pick any of them:
 it times a few rounds of the real workload per candidate, coordinate by
 coordinate, and keeps the fastest. It also checks that every candidate gives
@@ -20,7 +19,6 @@ from . import graphgen as gg
 from . import upr
 
 HUB = (1024, 2048, 4096, 8192, 16384)
-LOW = (8, 16, 32, 64, 128)
 DIRTY = (2, 4, 8, 16, 32)
 
 
@@ -96,17 +94,15 @@ def tune_batch(ctx, graphs, k, parts, eps=(3, 100), rounds=3, repeats=2, total_r
 
 
 def _coordinate_search(runner_for, rounds, repeats):
-    cur = dict(hub_threshold=4096, low_threshold=32, dirty_div=8)
+    cur = dict(hub_threshold=4096, dirty_div=8)
     report = []
     ref = None
     best_t = None
-    for name, values in (("hub_threshold", HUB), ("low_threshold", LOW), ("dirty_div", DIRTY)):
+    for name, values in (("hub_threshold", HUB), ("dirty_div", DIRTY)):
         best_v = cur[name]
         for v in values:
             trial = dict(cur)
             trial[name] = v
-            if trial["low_threshold"] > trial["hub_threshold"]:
-                continue
             t, res = _time_rounds(runner_for(upr.plan_opts(**trial)), rounds, repeats)
             if ref is None:
                 ref = res

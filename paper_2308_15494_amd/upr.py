@@ -237,13 +237,14 @@ class DeviceGraph:
 
 
 class PlanOpts(C.Structure):
-    """upr_plan_opts: traversal thresholds (0 = default)."""
+    """upr_plan_opts: traversal thresholds (0 = default; low_threshold is
+    ignored by the library)."""
     _fields_ = [("hub_threshold", C.c_int64), ("low_threshold", C.c_int64),
                 ("dirty_div", C.c_int64)]
 
 
-def plan_opts(hub_threshold=0, low_threshold=0, dirty_div=0) -> PlanOpts:
-    return PlanOpts(hub_threshold, low_threshold, dirty_div)
+def plan_opts(hub_threshold=0, dirty_div=0) -> PlanOpts:
+    return PlanOpts(hub_threshold, 0, dirty_div)
 
 
 class Plan:

@@ -189,7 +189,6 @@ def test_hub_paths(upr, ctx, monkeypatch):
     real rows (and chunks span several workgroups)."""
     import torch
     monkeypatch.setenv("UPR_HUB_THRESHOLD", "40")
-    monkeypatch.setenv("UPR_LOW_THRESHOLD", "6")
     for seed in range(3):
         g = gg.with_weights(gg.chung_lu(6000, 12.0, 2.05, seed=seed, d_max=5000), seed, wmax=7,
                             vmax=3 if seed == 2 else 0)
