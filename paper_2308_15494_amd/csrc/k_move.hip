@@ -377,14 +377,17 @@ hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t 
     hipLaunchKernelGGL((k_best_move_reg<GG, RR, UU>),                                               \
                        dim3(grid_cap((g.n + UU - 1) / UU, kBlock / GG, 8192)), dim3(kBlock), lds, s, \
                        g, bk, part, conn, W, cb, pen1, mode, active, key, pen, counters, cflag)
+        // each lane holds up to four int4 of the row: fewer lanes per node
+        // mean fewer shuffle rounds per scored entry (at k = 64, 4 lanes per
+        // node took 80 us where 16 lanes took 102)
         if (nvec <= 1) UPR_BR(1, 1, 2);
-        else if (nvec <= 2) UPR_BR(2, 1, 2);
-        else if (nvec <= 4) UPR_BR(4, 1, 2);
-        else if (nvec <= 8) UPR_BR(8, 1, 2);
-        else if (nvec <= 16) UPR_BR(16, 1, 2);
-        else if (nvec <= 32) UPR_BR(32, 1, 2);
-        else if (nvec <= 64) UPR_BR(64, 1, 2);
-        else if (nvec <= 128) UPR_BR(64, 2, 1);
+        else if (nvec <= 2) UPR_BR(1, 2, 2);
+        else if (nvec <= 4) UPR_BR(1, 4, 1);
+        else if (nvec <= 8) UPR_BR(2, 4, 1);
+        else if (nvec <= 16) UPR_BR(4, 4, 1);
+        else if (nvec <= 32) UPR_BR(8, 4, 1);
+        else if (nvec <= 64) UPR_BR(16, 4, 1);
+        else if (nvec <= 128) UPR_BR(32, 4, 1);
         else UPR_BR(64, 4, 1);
 #undef UPR_BR
         return hipGetLastError();

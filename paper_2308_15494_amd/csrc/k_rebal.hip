@@ -171,8 +171,9 @@ __device__ __forceinline__ void rb_load_vec(const int32_t *row, int q, int32_t (
 }
 
 // U source nodes per lane group at a time (their rows loaded together); with
-// U > 1 a row is one vector per lane (k / V <= G).
-template <int G, int V, int U>
+// U > 1 or R > 1 a lane holds R vectors of the row, vector q = gl + r * G
+// (k / V <= G * R). Fewer lanes per node mean fewer shuffle rounds per entry.
+template <int G, int V, int U, int R>
 __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
                                                         const int32_t *__restrict__ part,
                                                         const int32_t *__restrict__ conn,
@@ -210,7 +211,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
             int64_t vu[U];
             int32_t Au[U];
             bool oku[U];
-            int32_t cu[U][V];
+            int32_t cu[U][R][V];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int p = p0 + u * GPW + grp;
@@ -219,14 +220,18 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
                 vu[u] = __shfl(lv, src);
                 Au[u] = __shfl(la, src);
             }
-            if constexpr (U > 1) {
+            if constexpr (U > 1 || R > 1) {
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    if (oku[u] && gl < nvec) {
-                        rb_load_vec<V>(conn + vu[u] * (int64_t)k, gl, cu[u]);
-                    } else {
 #pragma unroll
-                        for (int t = 0; t < V; ++t) cu[u][t] = 0;
+                    for (int r = 0; r < R; ++r) {
+                        const int q = gl + r * G;
+                        if (oku[u] && q < nvec) {
+                            rb_load_vec<V>(conn + vu[u] * (int64_t)k, q, cu[u][r]);
+                        } else {
+#pragma unroll
+                            for (int t = 0; t < V; ++t) cu[u][r][t] = 0;
+                        }
                     }
                 }
             }
@@ -243,10 +248,14 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
                 int32_t ca_mine = 0;  // omega(v, V_a), held by the lane that loads column a
                 if (ok) {
                     cv = node_weight(g, v);
-                    if constexpr (U > 1) {
-                        if (gl < nvec)
-                            rb_scan_cols<V>(cu[u], gl * V, a, base, cv, lmax, W0, best, lw, lj,
-                                            ca_mine);
+                    if constexpr (U > 1 || R > 1) {
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const int q = gl + r * G;
+                            if (q < nvec)
+                                rb_scan_cols<V>(cu[u][r], q * V, a, base, cv, lmax, W0, best, lw,
+                                                lj, ca_mine);
+                        }
                     } else {
                         const int32_t *row = conn + v * (int64_t)k;
                         for (int q = gl; q < nvec; q += G) {
@@ -602,26 +611,27 @@ hipError_t launch_rb_iteration(const GraphView &g, const Blocks &bk, const int32
                         (h_lds ? (size_t)K * kRbBuckets * 4 : 0);
     const bool vec = (k % 4) == 0;
     const int nvec = vec ? k / 4 : k;
-#define UPR_RP(GG, VV, UU)                                                                      \
-    hipLaunchKernelGGL((k_rb_prepare<GG, VV, UU>), dim3(lg), dim3(kBlock), plds, s, g, bk, part,   \
-                       conn, r, hist32, plain)
+#define UPR_RP(GG, VV, UU, RR)                                                                  \
+    hipLaunchKernelGGL((k_rb_prepare<GG, VV, UU, RR>), dim3(lg), dim3(kBlock), plds, s, g, bk,     \
+                       part, conn, r, hist32, plain)
     if (vec) {
-        if (nvec <= 1) UPR_RP(1, 4, 4);
-        else if (nvec <= 2) UPR_RP(2, 4, 4);
-        else if (nvec <= 4) UPR_RP(4, 4, 4);
-        else if (nvec <= 8) UPR_RP(8, 4, 4);
-        else if (nvec <= 16) UPR_RP(16, 4, 4);
-        else if (nvec <= 32) UPR_RP(32, 4, 4);
-        else if (nvec <= 64) UPR_RP(64, 4, 4);
-        else UPR_RP(64, 4, 1);
+        // up to four int4 of the row per lane
+        if (nvec <= 1) UPR_RP(1, 4, 4, 1);
+        else if (nvec <= 2) UPR_RP(1, 4, 2, 2);
+        else if (nvec <= 4) UPR_RP(1, 4, 1, 4);
+        else if (nvec <= 8) UPR_RP(2, 4, 1, 4);
+        else if (nvec <= 16) UPR_RP(4, 4, 1, 4);
+        else if (nvec <= 32) UPR_RP(8, 4, 1, 4);
+        else if (nvec <= 64) UPR_RP(16, 4, 1, 4);
+        else UPR_RP(64, 4, 1, 1);
     } else {
-        if (nvec <= 2) UPR_RP(2, 1, 4);
-        else if (nvec <= 4) UPR_RP(4, 1, 4);
-        else if (nvec <= 8) UPR_RP(8, 1, 4);
-        else if (nvec <= 16) UPR_RP(16, 1, 4);
-        else if (nvec <= 32) UPR_RP(32, 1, 4);
-        else if (nvec <= 64) UPR_RP(64, 1, 4);
-        else UPR_RP(64, 1, 1);
+        if (nvec <= 2) UPR_RP(2, 1, 4, 1);
+        else if (nvec <= 4) UPR_RP(4, 1, 4, 1);
+        else if (nvec <= 8) UPR_RP(8, 1, 4, 1);
+        else if (nvec <= 16) UPR_RP(16, 1, 4, 1);
+        else if (nvec <= 32) UPR_RP(32, 1, 4, 1);
+        else if (nvec <= 64) UPR_RP(64, 1, 4, 1);
+        else UPR_RP(64, 1, 1, 1);
     }
 #undef UPR_RP
     if ((e = hipGetLastError()) != hipSuccess) return e;
