@@ -471,8 +471,9 @@ __device__ __forceinline__ int64_t pessimistic_part(const GraphView &g, const Pa
 // kFilterTile consecutive nodes. The tile's candidate edges are spread over
 // all threads (edge -> node by a binary search over the tile's degree
 // prefix), kEdgeUnroll edges per thread and step so that their loads overlap;
-// each edge's term w * f is summed per node over the runs of equal nodes in
-// lane order, and the last lane of a run adds it to the node's LDS sum.
+// each edge adds its term w * f to the node's 32-bit LDS sum (a node's sum is
+// bounded by its weighted degree, below 2^31). One LDS atomic per edge was
+// faster than a segmented wave scan over the runs of equal nodes.
 constexpr int kFilterTile = 512;
 
 __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int optimistic,
@@ -486,7 +487,7 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int o
     __shared__ int64_t estart[kFilterTile];
     __shared__ int64_t skey[kFilterTile];
     __shared__ int32_t sa[kFilterTile];  // local source block; -1: not decided here
-    __shared__ unsigned long long sacc[kFilterTile];
+    __shared__ int32_t sacc[kFilterTile];  // |sum| <= weighted degree < 2^31
     __shared__ int32_t scan_lds[4];
     __shared__ unsigned long long acc_lds, deg_lds;
     const int tid = threadIdx.x;
@@ -569,7 +570,7 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int o
 #pragma unroll
         for (int i = 0; i < kEdgeUnroll; ++i) {
             const int nd = node[i];
-            int64_t t = 0;
+            int32_t t = 0;
             if (nd >= 0) {
                 const int64_t kv = skey[nd];
                 const int32_t a = sa[nd], b = (int32_t)(kv & 0xFFFF);
@@ -581,17 +582,9 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int o
                         f = (optimistic || ft < f) ? ft : f;
                     }
                 }
-                t = (int64_t)w[i] * f;
+                t = w[i] * f;
             }
-            // the lanes of one node are consecutive: sum each run
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const int64_t ot = __shfl_up(t, off);
-                const int on = __shfl_up(nd, off);
-                if (lane >= off && on == nd) t += ot;
-            }
-            const int nx = __shfl_down(nd, 1);
-            if (nd >= 0 && (lane == 63 || nx != nd)) atomicAdd(&sacc[nd], (unsigned long long)t);
+            if (t != 0) atomicAdd(&sacc[nd], t);
         }
     }
     __syncthreads();
@@ -602,7 +595,7 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int o
         bool take = false;
         if (i < nt && sa[i] >= 0) {
             const int64_t v = v0 + i;
-            const int64_t acc = (int64_t)sacc[i];
+            const int64_t acc = sacc[i];
             if (gp_out) {
                 gp_out[v] = acc;  // eligible ones are decided against the sequence-aware price
                 accflag[v] = 0;
