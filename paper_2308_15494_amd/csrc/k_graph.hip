@@ -268,44 +268,67 @@ __global__ __launch_bounds__(kBlock) void k_node_stats(GraphView g, Blocks bk,
     __syncthreads();
 
     unsigned long long s = 0;
-    // loop bound uniform per wave (wave_hist_add needs whole waves)
-    for (int64_t vb = lo + (threadIdx.x & ~63); vb < hi; vb += kBlock) {
-        const int64_t v = vb + lane_id();
-        bool ok = v < hi;
-        int32_t a = 0;
-        int64_t cv = 1, inner = 0, wd = 0;
-        if (ok) {
-            a = part[v];
-            if ((unsigned)a >= (unsigned)K) {
-                atomicAdd(&bad, 1ull);
-                ok = false;
-            } else {
-                inner = conn[v * (int64_t)k + bk.local(a)];
-                wd = wdeg[v];
-                cv = node_weight(g, v);
-                s += (unsigned long long)(wd - inner);
+    // kStatsUnroll nodes per thread and step: their part entries, then their
+    // table entries and degrees are loaded together (from clamped indices,
+    // without a branch). Loop bound uniform per wave (wave_hist_add needs
+    // whole waves).
+    constexpr int kStatsUnroll = 8;
+    for (int64_t vb = lo + (threadIdx.x & ~63); vb < hi; vb += (int64_t)kBlock * kStatsUnroll) {
+        int32_t au[kStatsUnroll];
+        int32_t inu[kStatsUnroll], wdu[kStatsUnroll];
+#pragma unroll
+        for (int i = 0; i < kStatsUnroll; ++i) {
+            const int64_t v = vb + (int64_t)i * kBlock + lane_id();
+            au[i] = part[v < hi ? v : hi - 1];
+        }
+#pragma unroll
+        for (int i = 0; i < kStatsUnroll; ++i) {
+            const int64_t v = vb + (int64_t)i * kBlock + lane_id();
+            const int64_t vc = v < hi ? v : hi - 1;
+            const int32_t a = (unsigned)au[i] < (unsigned)K ? au[i] : 0;
+            inu[i] = conn[vc * (int64_t)k + bk.local(a)];
+            wdu[i] = wdeg[vc];
+        }
+#pragma unroll
+        for (int i = 0; i < kStatsUnroll; ++i) {
+            const int64_t v = vb + (int64_t)i * kBlock + lane_id();
+            bool ok = v < hi;
+            int32_t a = 0;
+            int64_t cv = 1, inner = 0, wd = 0;
+            if (ok) {
+                a = au[i];
+                if ((unsigned)a >= (unsigned)K) {
+                    atomicAdd(&bad, 1ull);
+                    ok = false;
+                } else {
+                    inner = inu[i];
+                    wd = wdu[i];
+                    cv = node_weight(g, v);
+                    s += (unsigned long long)(wd - inner);
+                }
             }
-        }
-        const uint32_t x = (uint32_t)(a - B0);
-        const bool inw = ok && x < (uint32_t)nb;
-        if (gstat) {
-            if (s_lds && inw) atomicAdd((unsigned long long *)&gsl[bk.graph(a) - g0],
-                                        (unsigned long long)(wd - inner));
-            wave_hist_add(gstat, (int64_t)bk.graph(a) * GS_COUNT + gs_slot, wd - inner,
-                          ok && !(s_lds && inw));
-        }
-        if (W) {
-            if (w_lds && inw) atomicAdd((unsigned long long *)&lw[x], (unsigned long long)cv);
-            if (!w_lds) wave_hist_add(W, a, cv, ok);
-            else wave_hist_add(W, a, cv, ok && !inw);
-        }
-        if (bucket) {
-            const bool avail = ok && (int64_t)t_den * inner >= (int64_t)t_num * wd;
-            if (avail_out && v < hi) avail_out[v] = avail ? 1 : 0;
-            const int l = avail ? slot_of(inner, cv) : 0;
-            if (b_lds && avail && inw)
-                atomicAdd((unsigned long long *)&lb[(int64_t)x * kSlots + l], (unsigned long long)cv);
-            wave_hist_add(bucket, (int64_t)a * kSlots + l, cv, avail && !(b_lds && inw));
+            const uint32_t x = (uint32_t)(a - B0);
+            const bool inw = ok && x < (uint32_t)nb;
+            if (gstat) {
+                if (s_lds && inw) atomicAdd((unsigned long long *)&gsl[bk.graph(a) - g0],
+                                            (unsigned long long)(wd - inner));
+                wave_hist_add(gstat, (int64_t)bk.graph(a) * GS_COUNT + gs_slot, wd - inner,
+                              ok && !(s_lds && inw));
+            }
+            if (W) {
+                if (w_lds && inw) atomicAdd((unsigned long long *)&lw[x], (unsigned long long)cv);
+                if (!w_lds) wave_hist_add(W, a, cv, ok);
+                else wave_hist_add(W, a, cv, ok && !inw);
+            }
+            if (bucket) {
+                const bool avail = ok && (int64_t)t_den * inner >= (int64_t)t_num * wd;
+                if (avail_out && v < hi) avail_out[v] = avail ? 1 : 0;
+                const int l = avail ? slot_of(inner, cv) : 0;
+                if (b_lds && avail && inw)
+                    atomicAdd((unsigned long long *)&lb[(int64_t)x * kSlots + l],
+                              (unsigned long long)cv);
+                wave_hist_add(bucket, (int64_t)a * kSlots + l, cv, avail && !(b_lds && inw));
+            }
         }
     }
     s = block_sum(s, red);

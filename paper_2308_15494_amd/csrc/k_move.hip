@@ -476,6 +476,7 @@ __device__ __forceinline__ int64_t pessimistic_part(const GraphView &g, const Pa
 // faster than a segmented wave scan over the runs of equal nodes.
 constexpr int kFilterTile = 512;
 
+template <int PB>
 __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int optimistic,
                                                     const int32_t *__restrict__ part,
                                                     PartView pv, const int64_t *__restrict__ key,
@@ -491,7 +492,6 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int o
     __shared__ int32_t scan_lds[4];
     __shared__ unsigned long long acc_lds, deg_lds;
     const int tid = threadIdx.x;
-    const int lane = lane_id();
     if (tid == 0) {
         acc_lds = 0;
         deg_lds = 0;
@@ -530,60 +530,59 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int o
 
     // S3 terms over all candidate edges of the tile; an earlier candidate
     // neighbour u ((score, id) before v) counts in the worse of its current
-    // and its target block (optimistic variant: its target block)
+    // and its target block (optimistic variant: its target block). Every
+    // load is issued unconditionally (a slot past the last edge rereads that
+    // edge and adds nothing; a neighbour that is no candidate rereads the
+    // node's own key), so the loads of all slots are in flight together.
     const int32_t E = run;
-    for (int32_t q0 = tid & ~63; q0 < E; q0 += kBlock * kEdgeUnroll) {
+    const int32_t pmask = part_mask(pv);
+    for (int32_t q0 = tid; q0 < E; q0 += kBlock * kEdgeUnroll) {
+        bool ok[kEdgeUnroll];
         int node[kEdgeUnroll];
         int64_t e[kEdgeUnroll];
 #pragma unroll
         for (int i = 0; i < kEdgeUnroll; ++i) {
-            const int32_t p = q0 + i * kBlock + lane;
-            node[i] = p < E ? upper_index(vstart, nt, p) : -1;
-            e[i] = node[i] >= 0 ? estart[node[i]] + (p - vstart[node[i]]) : 0;
+            const int32_t p = q0 + i * kBlock;
+            ok[i] = p < E;
+            const int32_t pc = ok[i] ? p : E - 1;
+            node[i] = upper_index(vstart, nt, pc);
+            e[i] = estart[node[i]] + (pc - vstart[node[i]]);
         }
         int32_t u[kEdgeUnroll], w[kEdgeUnroll];
 #pragma unroll
         for (int i = 0; i < kEdgeUnroll; ++i) {
-            u[i] = node[i] >= 0 ? stream_load(g.adjncy + e[i]) : 0;
-            w[i] = node[i] >= 0 ? stream_edge_weight(g, e[i]) : 0;
+            u[i] = stream_load(g.adjncy + e[i]);
+            w[i] = stream_edge_weight(g, e[i]);
         }
-        int32_t pu[kEdgeUnroll];
-        int64_t ku[kEdgeUnroll];
-        if (pv.flagged) {
-            // a neighbour's key only if it is a candidate
-            int32_t raw[kEdgeUnroll];
+        int32_t raw[kEdgeUnroll];
 #pragma unroll
-            for (int i = 0; i < kEdgeUnroll; ++i)
-                raw[i] = node[i] >= 0 ? ((const uint8_t *)pv.p)[u[i]] : 0;
+        for (int i = 0; i < kEdgeUnroll; ++i) raw[i] = pget_w<PB>(pv.p, u[i], -1);
+        // a neighbour's key only if it is a candidate (flag bit of the
+        // compact copy; without flags every neighbour's key)
+        int64_t kraw[kEdgeUnroll];
+        bool cand[kEdgeUnroll];
 #pragma unroll
-            for (int i = 0; i < kEdgeUnroll; ++i) {
-                pu[i] = node[i] >= 0 ? (raw[i] & (kCandFlag - 1)) : -1;
-                ku[i] = (raw[i] & kCandFlag) ? key[u[i]] : -1;
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < kEdgeUnroll; ++i) {
-                pu[i] = node[i] >= 0 ? pget(pv, u[i]) : -1;
-                ku[i] = node[i] >= 0 ? key[u[i]] : -1;
-            }
+        for (int i = 0; i < kEdgeUnroll; ++i) {
+            cand[i] = !pv.flagged || (raw[i] & kCandFlag);
+            kraw[i] = key[cand[i] ? (int64_t)u[i] : v0 + node[i]];
         }
 #pragma unroll
         for (int i = 0; i < kEdgeUnroll; ++i) {
+            if (!ok[i]) continue;
             const int nd = node[i];
-            int32_t t = 0;
-            if (nd >= 0) {
-                const int64_t kv = skey[nd];
-                const int32_t a = sa[nd], b = (int32_t)(kv & 0xFFFF);
-                int f = move_sign(pu[i], a, b);
-                if (ku[i] >= 0) {
-                    const int64_t su = ku[i] >> 16, sv = kv >> 16;
-                    if (su > sv || (su == sv && (int64_t)u[i] < v0 + nd)) {
-                        const int ft = move_sign((int32_t)(ku[i] & 0xFFFF), a, b);
-                        f = (optimistic || ft < f) ? ft : f;
-                    }
+            const int32_t pu = raw[i] & pmask;
+            const int64_t ku = cand[i] ? kraw[i] : -1;
+            const int64_t kv = skey[nd];
+            const int32_t a = sa[nd], b = (int32_t)(kv & 0xFFFF);
+            int f = move_sign(pu, a, b);
+            if (ku >= 0) {
+                const int64_t su = ku >> 16, sv = kv >> 16;
+                if (su > sv || (su == sv && (int64_t)u[i] < v0 + nd)) {
+                    const int ft = move_sign((int32_t)(ku & 0xFFFF), a, b);
+                    f = (optimistic || ft < f) ? ft : f;
                 }
-                t = w[i] * f;
             }
+            const int32_t t = w[i] * f;
             if (t != 0) atomicAdd(&sacc[nd], t);
         }
     }
@@ -625,8 +624,13 @@ hipError_t launch_filter(const GraphView &g, const Blocks &bk, int optimistic, c
 {
     if (g.n <= 0) return hipSuccess;
     const int64_t tiles = (g.n + kFilterTile - 1) / kFilterTile;
-    hipLaunchKernelGGL(k_filter, dim3((unsigned)tiles), dim3(kBlock), 0, s, g, bk, optimistic,
-                       part, pv, key, pen, hub_t, mvto, accflag, counters, gp_out);
+#define UPR_FI(BB)                                                                                 \
+    hipLaunchKernelGGL(k_filter<BB>, dim3((unsigned)tiles), dim3(kBlock), 0, s, g, bk, optimistic,   \
+                       part, pv, key, pen, hub_t, mvto, accflag, counters, gp_out)
+    if (pv.bytes == 1) UPR_FI(1);
+    else if (pv.bytes == 2) UPR_FI(2);
+    else UPR_FI(4);
+#undef UPR_FI
     return hipGetLastError();
 }
 
@@ -858,28 +862,33 @@ __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, Blocks bk, int32_
     const int32_t E = run;
     const int32_t k = bk.k;
     for (int32_t p0 = threadIdx.x; p0 < E; p0 += kBlock * kEdgeUnroll) {
+        // loads from clamped indices without a branch, so that they are in
+        // flight together (a slot past the last edge rereads it, unused)
+        bool ok[kEdgeUnroll];
         int node[kEdgeUnroll];
         int64_t e[kEdgeUnroll];
         int32_t u[kEdgeUnroll];
 #pragma unroll
         for (int i = 0; i < kEdgeUnroll; ++i) {
             const int32_t p = p0 + i * kBlock;
-            node[i] = p < E ? upper_index(vstart, nt, p) : -1;
-            e[i] = node[i] >= 0 ? estart[node[i]] + (p - vstart[node[i]]) : 0;
+            ok[i] = p < E;
+            const int32_t pc = ok[i] ? p : E - 1;
+            node[i] = upper_index(vstart, nt, pc);
+            e[i] = estart[node[i]] + (pc - vstart[node[i]]);
         }
 #pragma unroll
-        for (int i = 0; i < kEdgeUnroll; ++i) u[i] = node[i] >= 0 ? g.adjncy[e[i]] : -1;
+        for (int i = 0; i < kEdgeUnroll; ++i) u[i] = g.adjncy[e[i]];
         if (dirty) {
 #pragma unroll
             for (int i = 0; i < kEdgeUnroll; ++i)
-                if (u[i] >= 0) mark_dirty(dirty, u[i] / T);
+                if (ok[i]) mark_dirty(dirty, u[i] / T);
         } else {
             int32_t w[kEdgeUnroll];
 #pragma unroll
-            for (int i = 0; i < kEdgeUnroll; ++i) w[i] = node[i] >= 0 ? edge_weight(g, e[i]) : 0;
+            for (int i = 0; i < kEdgeUnroll; ++i) w[i] = edge_weight(g, e[i]);
 #pragma unroll
             for (int i = 0; i < kEdgeUnroll; ++i) {
-                if (u[i] < 0) continue;
+                if (!ok[i]) continue;
                 const uint32_t ab = sab[node[i]];
                 int32_t *row = conn + (int64_t)u[i] * k;
                 atomicAdd(&row[ab & 0xFFFF], -w[i]);

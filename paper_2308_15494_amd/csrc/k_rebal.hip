@@ -221,17 +221,15 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
                 Au[u] = __shfl(la, src);
             }
             if constexpr (U > 1 || R > 1) {
+                // unconditional loads (an unused slot holds lane 0's node, a
+                // valid one; q >= nvec rereads the last vector, unused), so
+                // that all rows are in flight together
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         const int q = gl + r * G;
-                        if (oku[u] && q < nvec) {
-                            rb_load_vec<V>(conn + vu[u] * (int64_t)k, q, cu[u][r]);
-                        } else {
-#pragma unroll
-                            for (int t = 0; t < V; ++t) cu[u][r][t] = 0;
-                        }
+                        rb_load_vec<V>(conn + vu[u] * (int64_t)k, q < nvec ? q : nvec - 1, cu[u][r]);
                     }
                 }
             }

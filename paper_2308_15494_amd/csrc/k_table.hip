@@ -44,7 +44,8 @@ static size_t gain_tile_lds(int32_t k, int T, bool p16)
 // i / 2 if i is even, the high half otherwise). A sum never carries into the
 // neighbouring half, the tile takes half the LDS and twice as many
 // workgroups stay resident per CU to hide the gathers' latency.
-template <bool WEIGHTED, bool P16>
+// PB: bytes per entry of the partition view (1, 2 or 4).
+template <bool WEIGHTED, bool P16, int PB>
 __device__ __forceinline__ void gain_tile_body(const GraphView &g, int32_t k, int T,
                                                const PartView &part,
                                                int32_t *__restrict__ conn, int64_t hub_t)
@@ -61,6 +62,7 @@ __device__ __forceinline__ void gain_tile_body(const GraphView &g, int32_t k, in
     const int tid = threadIdx.x;
     const int64_t kk = k;
     const int entries = nt * k;
+    const int32_t pmask = part_mask(part);
 
     {
         int4 *t4 = (int4 *)tile;
@@ -89,30 +91,35 @@ __device__ __forceinline__ void gain_tile_body(const GraphView &g, int32_t k, in
     if (tid == 0) vstart[nt] = run;
     __syncthreads();
 
-    // kUnroll independent edges per thread and step, so that their loads
-    // (adjncy, then the part gathers) are in flight together
-    constexpr int kUnroll = 4;
+    // kUnroll independent edges per thread and step. Every load is issued
+    // unconditionally (a slot past the tile's last edge reads that last edge
+    // again and adds nothing), so the adjacency loads and then the part
+    // gathers of all slots are in flight together.
+    constexpr int kUnroll = 8;
     const int32_t E = run;
     for (int32_t p0 = tid; p0 < E; p0 += kBlock * kUnroll) {
+        bool ok[kUnroll];
         int node[kUnroll];
         int64_t e[kUnroll];
         int32_t u[kUnroll], w[kUnroll], pu[kUnroll];
 #pragma unroll
         for (int i = 0; i < kUnroll; ++i) {
             const int32_t p = p0 + i * kBlock;
-            node[i] = p < E ? upper_index(vstart, nt, p) : -1;
-            e[i] = node[i] >= 0 ? gstart[node[i]] + (p - vstart[node[i]]) : 0;
+            ok[i] = p < E;
+            const int32_t pc = ok[i] ? p : E - 1;
+            node[i] = upper_index(vstart, nt, pc);
+            e[i] = gstart[node[i]] + (pc - vstart[node[i]]);
         }
 #pragma unroll
         for (int i = 0; i < kUnroll; ++i) {
-            u[i] = node[i] >= 0 ? g.adjncy[e[i]] : 0;
-            w[i] = (WEIGHTED && node[i] >= 0) ? g.adjwgt[e[i]] : 1;
+            u[i] = g.adjncy[e[i]];
+            w[i] = WEIGHTED ? g.adjwgt[e[i]] : 1;
         }
 #pragma unroll
-        for (int i = 0; i < kUnroll; ++i) pu[i] = node[i] >= 0 ? pget(part, u[i]) : -1;
+        for (int i = 0; i < kUnroll; ++i) pu[i] = pget_w<PB>(part.p, u[i], pmask);
 #pragma unroll
         for (int i = 0; i < kUnroll; ++i)
-            if ((unsigned)pu[i] < (unsigned)k) {
+            if (ok[i] && (unsigned)pu[i] < (unsigned)k) {
                 const int idx = node[i] * k + pu[i];
                 if (P16) atomicAdd(&tile[idx >> 1], w[i] << ((idx & 1) << 4));
                 else atomicAdd(&tile[idx], w[i]);
@@ -147,13 +154,13 @@ __device__ __forceinline__ void gain_tile_body(const GraphView &g, int32_t k, in
         for (int64_t i = done + tid; i < total_ints; i += kBlock) dst[i] = tile[i];
     }
 }
-template <bool WEIGHTED, bool P16>
+template <bool WEIGHTED, bool P16, int PB>
 __global__ __launch_bounds__(kBlock) void k_gain_tile(GraphView g, int32_t k, int T, PartView part,
                                                        int32_t *__restrict__ conn, int64_t hub_t)
 {
-    gain_tile_body<WEIGHTED, P16>(g, k, T, part, conn, hub_t);
+    gain_tile_body<WEIGHTED, P16, PB>(g, k, T, part, conn, hub_t);
 }
-template <bool WEIGHTED, bool P16>
+template <bool WEIGHTED, bool P16, int PB>
 __global__ __launch_bounds__(kBlock) void k_gain_refresh(GraphView g, int32_t k, int T,
                                                           PartView part,
                                                           int32_t *__restrict__ conn,
@@ -162,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_gain_refresh(GraphView g, int32_t k,
     if (!dirty[blockIdx.x]) return;
     __syncthreads();
     if (threadIdx.x == 0) dirty[blockIdx.x] = 0;
-    gain_tile_body<WEIGHTED, P16>(g, k, T, part, conn, hub_t);
+    gain_tile_body<WEIGHTED, P16, PB>(g, k, T, part, conn, hub_t);
 }
 
 hipError_t launch_gain_tile(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,
@@ -172,22 +179,29 @@ hipError_t launch_gain_tile(const GraphView &g, int32_t k, const PartView &part,
     const int T = gain_tile_nodes(k);
     const int64_t tiles = (g.n + T - 1) / T;
     const size_t lds = gain_tile_lds(k, T, g.tile16 != 0);
-#define UPR_TILE(KERN, WW, PP, ...)                                                                 \
-    hipLaunchKernelGGL((KERN<WW, PP>), dim3((unsigned)tiles), dim3(kBlock), lds, s, g, k, T, part, \
-                       conn, hub_t __VA_ARGS__)
+#define UPR_TILE(KERN, WW, PP, BB, ...)                                                             \
+    hipLaunchKernelGGL((KERN<WW, PP, BB>), dim3((unsigned)tiles), dim3(kBlock), lds, s, g, k, T,    \
+                       part, conn, hub_t __VA_ARGS__)
+#define UPR_TILE_B(KERN, WW, PP, ...)                                                               \
+    do {                                                                                            \
+        if (part.bytes == 1) UPR_TILE(KERN, WW, PP, 1, __VA_ARGS__);                                \
+        else if (part.bytes == 2) UPR_TILE(KERN, WW, PP, 2, __VA_ARGS__);                           \
+        else UPR_TILE(KERN, WW, PP, 4, __VA_ARGS__);                                                \
+    } while (0)
 #define UPR_TILE_ALL(KERN, ...)                                                                     \
     do {                                                                                            \
         if (g.adjwgt) {                                                                             \
-            if (g.tile16) UPR_TILE(KERN, true, true, __VA_ARGS__);                                  \
-            else UPR_TILE(KERN, true, false, __VA_ARGS__);                                          \
+            if (g.tile16) UPR_TILE_B(KERN, true, true, __VA_ARGS__);                                \
+            else UPR_TILE_B(KERN, true, false, __VA_ARGS__);                                        \
         } else {                                                                                    \
-            if (g.tile16) UPR_TILE(KERN, false, true, __VA_ARGS__);                                 \
-            else UPR_TILE(KERN, false, false, __VA_ARGS__);                                         \
+            if (g.tile16) UPR_TILE_B(KERN, false, true, __VA_ARGS__);                               \
+            else UPR_TILE_B(KERN, false, false, __VA_ARGS__);                                       \
         }                                                                                           \
     } while (0)
     if (dirty) UPR_TILE_ALL(k_gain_refresh, , dirty);
     else UPR_TILE_ALL(k_gain_tile, );
 #undef UPR_TILE_ALL
+#undef UPR_TILE_B
 #undef UPR_TILE
     return hipGetLastError();
 }

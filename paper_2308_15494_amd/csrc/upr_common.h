@@ -126,6 +126,22 @@ __device__ __forceinline__ int32_t pget(const PartView &pv, int64_t u)
     return ((const int32_t *)pv.p)[u];
 }
 
+// The same with the width fixed at compile time: a plain load, no branch (a
+// load inside a branch is waited for before the branch joins, which
+// serialises loads that are meant to be in flight together). mask: 0x7F for
+// a flagged copy, else all ones.
+template <int PB>
+__device__ __forceinline__ int32_t pget_w(const void *p, int64_t u, int32_t mask)
+{
+    if constexpr (PB == 1) return ((const uint8_t *)p)[u] & mask;
+    else if constexpr (PB == 2) return ((const uint16_t *)p)[u];
+    else return ((const int32_t *)p)[u];
+}
+__device__ __forceinline__ int32_t part_mask(const PartView &pv)
+{
+    return pv.flagged ? (int32_t)(kCandFlag - 1) : -1;
+}
+
 __device__ __forceinline__ void pset(void *pc, int bytes, int64_t v, int32_t b)
 {
     if (bytes == 1) ((uint8_t *)pc)[v] = (uint8_t)b;
