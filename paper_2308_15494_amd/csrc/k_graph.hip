@@ -4,6 +4,10 @@
 // cut edges, and the compact partition copy.
 #include "upr_common.h"
 
+#include <cstring>
+
+#include <rocprim/rocprim.hpp>
+
 namespace upr {
 
 // ------------------------------------------------------------------ fill --
@@ -482,6 +486,96 @@ hipError_t launch_check_part(int64_t n, int32_t k, const int32_t *part,
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_check_part, dim3(grid_for(n, kBlock * 8, 2048)), dim3(kBlock), 0, s, n, k,
                        part, counters);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- relabelling --
+
+// The table build gathers the block of every neighbour; R-MAT-like graphs
+// send most edges to few high-degree nodes. With neighbour ids renumbered by
+// descending degree (ties by id), those nodes' entries of the compact
+// partition copy share a few cache lines that stay in L1. Rows stay in place:
+// only the neighbour ids in the table build's copy of the adjacency change.
+__global__ void k_degree_keys(GraphView g, uint32_t *keys, int32_t *ids)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += stride) {
+        const int64_t d = g.xadj[v + 1] - g.xadj[v];
+        keys[v] = 0xFFFFFFFFu - (uint32_t)(d < 0xFFFFFFFFll ? d : 0xFFFFFFFFll);
+        ids[v] = (int32_t)v;
+    }
+}
+__global__ void k_inverse(int64_t n, const int32_t *order, int32_t *perm)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        perm[order[i]] = (int32_t)i;
+}
+__global__ void k_relabel_adj(int64_t nnz, const int32_t *adjncy, const int32_t *perm, int32_t *adj_r)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride)
+        adj_r[e] = perm[adjncy[e]];
+}
+
+hipError_t launch_degree_relabel(const GraphView &g, int64_t nnz, int32_t *order, int32_t *perm,
+                                 int32_t *adj_r, hipStream_t s)
+{
+    if (g.n <= 0) return hipSuccess;
+    uint32_t *keys = nullptr, *keys2 = nullptr;
+    int32_t *ids = nullptr;
+    void *temp = nullptr;
+    size_t bytes = 0;
+    hipError_t e = hipMalloc((void **)&keys, sizeof(uint32_t) * g.n);
+    if (e == hipSuccess) e = hipMalloc((void **)&keys2, sizeof(uint32_t) * g.n);
+    if (e == hipSuccess) e = hipMalloc((void **)&ids, sizeof(int32_t) * g.n);
+    if (e == hipSuccess)
+        e = rocprim::radix_sort_pairs(nullptr, bytes, keys, keys2, ids, order, (size_t)g.n, 0, 32, s);
+    if (e == hipSuccess) e = hipMalloc(&temp, bytes > 0 ? bytes : 1);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_degree_keys, dim3(grid_for(g.n, kBlock * 4)), dim3(kBlock), 0, s, g, keys,
+                           ids);
+        e = hipGetLastError();
+    }
+    // a stable sort: equal degrees keep ascending ids
+    if (e == hipSuccess)
+        e = rocprim::radix_sort_pairs(temp, bytes, keys, keys2, ids, order, (size_t)g.n, 0, 32, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_inverse, dim3(grid_for(g.n, kBlock * 4)), dim3(kBlock), 0, s, g.n, order,
+                           perm);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && nnz > 0) {
+        hipLaunchKernelGGL(k_relabel_adj, dim3(grid_for(nnz, kBlock * 4)), dim3(kBlock), 0, s, nnz,
+                           g.adjncy, perm, adj_r);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(keys);
+    (void)hipFree(keys2);
+    (void)hipFree(ids);
+    (void)hipFree(temp);
+    return e;
+}
+
+// The compact partition copy in label order: pc2[i] = pc[order[i]].
+__global__ void k_pack_relabel(int64_t n, const int32_t *order, const void *pc, void *pc2,
+                               int bytes)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int64_t v = order[i];
+        if (bytes == 1) ((uint8_t *)pc2)[i] = ((const uint8_t *)pc)[v];
+        else ((uint16_t *)pc2)[i] = ((const uint16_t *)pc)[v];
+    }
+}
+
+hipError_t launch_pack_relabel(int64_t n, const int32_t *order, const void *pc, void *pc2,
+                               int bytes, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_relabel, dim3(grid_for(n, kBlock * 4, 4096)), dim3(kBlock), 0, s, n,
+                       order, pc, pc2, bytes);
     return hipGetLastError();
 }
 

@@ -786,7 +786,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, Blocks bk, int32_
                                                    int32_t *mvto, int64_t hub_t,
                                                    const unsigned long long *counters,
                                                    int64_t dirty_threshold, uint8_t *dirty_flags,
-                                                   int T)
+                                                   int T, void *pc2, const int32_t *perm)
 {
     __shared__ int32_t vstart[kApplyTile + 1];
     __shared__ int64_t estart[kApplyTile];
@@ -840,6 +840,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, Blocks bk, int32_
         const int64_t cv = node_weight(g, v);
         part[v] = to;
         pset((void *)pv.p, pv.bytes, v, (int32_t)lb);
+        if (pc2) pset(pc2, pv.bytes, perm[v], (int32_t)lb);
         mvto[v] = -1;
         atomicAdd((unsigned long long *)&wdst[A], (unsigned long long)(-cv));
         atomicAdd((unsigned long long *)&wdst[to], (unsigned long long)cv);
@@ -938,7 +939,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_hub(GraphView g, Blocks bk, co
 hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, const PartView &pv,
                         int32_t *conn, int64_t *W, int32_t *mvto, int64_t hub_t,
                         const HubView &h, const unsigned long long *counters,
-                        int64_t dirty_threshold, uint8_t *dirty, hipStream_t s)
+                        int64_t dirty_threshold, uint8_t *dirty, const GraphView &tg,
+                        const PartView &tpv, void *pc2, const int32_t *perm, hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
     const int32_t k = bk.k;
@@ -952,11 +954,11 @@ hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, con
     }
     const int64_t tiles = (g.n + kApplyTile - 1) / kApplyTile;
     hipLaunchKernelGGL(k_apply, dim3((unsigned)tiles), dim3(kBlock), lds, s, g, bk, part, pv, conn,
-                       W, mvto, hub_t, counters, dirty_threshold, dirty, T);
+                       W, mvto, hub_t, counters, dirty_threshold, dirty, T, pc2, perm);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // rebuild the marked tiles and the hub rows (nothing in the delta mode)
-    if ((e = launch_gain_tile(g, k, pv, conn, hub_t, dirty, s)) != hipSuccess) return e;
-    return launch_gain_hub(g, k, pv, conn, h, s, counters, dirty_threshold);
+    if ((e = launch_gain_tile(tg, k, tpv, conn, hub_t, dirty, s)) != hipSuccess) return e;
+    return launch_gain_hub(tg, k, tpv, conn, h, s, counters, dirty_threshold);
 }
 
 // ----------------------------------------------------------------- stats --

@@ -22,6 +22,7 @@ namespace {
 
 constexpr int64_t kHubChunkEdges = 4096;
 constexpr int64_t kDefaultHubThreshold = 4096;
+constexpr int64_t kRelabelMinNodes = 65536;  // relabel the table build's adjacency from here on
 constexpr int64_t kChunkEntries = int64_t(1) << 20;  // rebalancing id-chunk sums per side
 
 struct Timing {
@@ -59,6 +60,7 @@ struct upr_ctx {
     int32_t *mvto = nullptr;     // [n] pending move target, -1 = none
     uint8_t *dirty = nullptr;    // [n] gain-table tiles to rebuild
     uint16_t *pc = nullptr;      // [n] compact copy of part for neighbour gathers
+    uint16_t *pc2 = nullptr;     // [n] the same in the plan's label order (table build)
     // sequence-aware penalty
     int64_t *gp = nullptr;       // [n] pessimistic gains of candidates
     uint8_t *avail = nullptr;    // [n] available for rebalancing
@@ -115,10 +117,22 @@ struct upr_plan {
     uint32_t *hub_bits = nullptr;  // [ceil(n/32)]
     int64_t hub_t = kDefaultHubThreshold;
     int64_t dirty_threshold = 0;  // moved-degree sum above which tiles are rebuilt
+    // neighbour ids renumbered by descending degree for the table build (null:
+    // not built, the table build reads the graph as given)
+    int32_t *adj_r = nullptr;  // [nnz] perm[adjncy[e]]
+    int32_t *perm = nullptr;   // [n] label of node v
+    int32_t *order = nullptr;  // [n] node of label i
 
     HubView hubs() const
     {
         return HubView{nh, hub_ids, chunks, nchunks, gacc, hub_bits, hub_ticket};
+    }
+    // the graph as the table build reads it
+    GraphView table_graph() const
+    {
+        GraphView t = g;
+        if (adj_r) t.adjncy = adj_r;
+        return t;
     }
 };
 
@@ -191,6 +205,7 @@ void free_workspace(upr_ctx *c)
     dfree(c->mvto);
     dfree(c->dirty);
     dfree(c->pc);
+    dfree(c->pc2);
     dfree(c->gp);
     dfree(c->avail);
     dfree(c->cand);
@@ -248,7 +263,7 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
     bool ok = dalloc(&c->key, N) == hipSuccess && dalloc(&c->pen, N) == hipSuccess &&
               dalloc(&c->accflag, N) == hipSuccess && dalloc(&c->mvto, N) == hipSuccess &&
               dalloc(&c->dirty, N) == hipSuccess && dalloc(&c->gp, N) == hipSuccess &&
-              dalloc(&c->pc, N) == hipSuccess &&
+              dalloc(&c->pc, N) == hipSuccess && dalloc(&c->pc2, N) == hipSuccess &&
               dalloc(&c->avail, N) == hipSuccess && dalloc(&c->cand, N) == hipSuccess &&
               dalloc(&c->ev_key, 2 * N) == hipSuccess &&
               dalloc(&c->ev_key2, 2 * N) == hipSuccess && dalloc(&c->ev_val, 2 * N) == hipSuccess &&
@@ -432,6 +447,23 @@ int hist32_ok(const upr_plan *p)
            ((unsigned __int128)1 << 32);
 }
 
+// The table build's view of the partition: the label-order copy when the
+// plan has relabelled its adjacency, else pv itself.
+static PartView table_part(const upr_ctx *c, const upr_plan *p, const PartView &pv)
+{
+    return p->order ? PartView{c->pc2, pv.bytes, 0} : pv;
+}
+
+// S4 for the moves marked in mvto; rebuilt tiles and hub rows are built from
+// the table build's views.
+static hipError_t apply_moves(upr_ctx *c, const upr_plan *p, const Blocks &bk, int32_t *part,
+                              const PartView &pv, int32_t *conn, int64_t *W, hipStream_t s)
+{
+    return launch_apply(p->g, bk, part, pv, conn, W, c->mvto, p->hub_t, p->hubs(), c->counters,
+                        p->dirty_threshold, c->dirty, p->table_graph(), table_part(c, p, pv),
+                        p->order ? (void *)c->pc2 : nullptr, p->perm, s);
+}
+
 // S5: the host loop over synchronous sub-iterations (one graph).
 int rebalance_loop(upr_ctx *c, const upr_plan *p, const Blocks &bk, int plain, int32_t *part,
                    const PartView &pv, int32_t *conn, int64_t *W, int64_t it_max,
@@ -454,8 +486,7 @@ int rebalance_loop(upr_ctx *c, const upr_plan *p, const Blocks &bk, int plain, i
     auto sub_iteration = [&]() -> int {
         HIP_TRY(c, launch_rb_iteration(p->g, bk, part, conn, c->rb, c->mvto, hist32, plain,
                                        p->hub_t, c->counters, nullptr, s));
-        HIP_TRY(c, launch_apply(p->g, bk, part, pv, conn, W, c->mvto, p->hub_t, h,
-                                c->counters, p->dirty_threshold, c->dirty, s));
+        HIP_TRY(c, apply_moves(c, p, bk, part, pv, conn, W, s));
         return begin(0);
     };
     int rc;
@@ -571,8 +602,7 @@ int rebalance_loop_batch(upr_ctx *c, const upr_plan *p, upr_batch *b, const Bloc
         HIP_TRY(c, hipMemcpyAsync(b->srcl_d, b->srcl_h, sizeof(int64_t) * ng, hipMemcpyHostToDevice, s));
         HIP_TRY(c, launch_rb_iteration(p->g, bk, part, conn, c->rb, c->mvto, hist32, plain,
                                        p->hub_t, c->counters, b->gstat_d, s));
-        HIP_TRY(c, launch_apply(p->g, bk, part, pv, conn, W, c->mvto, p->hub_t, h,
-                                c->counters, p->dirty_threshold, c->dirty, s));
+        HIP_TRY(c, apply_moves(c, p, bk, part, pv, conn, W, s));
         HIP_TRY(c, launch_rb_begin(bk, W, c->rb, c->counters, b->gstat_d, s));
         rc = sync_batch(c, b, s);
         if (rc) return rc;
@@ -861,6 +891,24 @@ static int plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipSt
             if (!ok) return bail(UPR_E_HIP, "hub preparation failed");
         }
         dfree(hub_list);
+        // relabelled adjacency for the table build: UPR_RELABEL=0 never, 2
+        // always, else (default) for graphs whose compact partition copy
+        // outgrows an L1 (kRelabelMinNodes). Skipped, not an error, if its
+        // memory cannot be had.
+        const int64_t relabel = env_int("UPR_RELABEL", 1);
+        if (p->nnz > 0 && (relabel == 2 || (relabel == 1 && g.n >= kRelabelMinNodes))) {
+            if (dalloc(&p->adj_r, p->nnz) == hipSuccess && dalloc(&p->perm, g.n) == hipSuccess &&
+                dalloc(&p->order, g.n) == hipSuccess) {
+                if (launch_degree_relabel(g, p->nnz, p->order, p->perm, p->adj_r, s) != hipSuccess)
+                    return bail(UPR_E_HIP, "relabelling the adjacency failed");
+            } else {
+                (void)hipGetLastError();
+                dfree(p->adj_r);
+                dfree(p->perm);
+                dfree(p->order);
+                p->adj_r = p->perm = p->order = nullptr;
+            }
+        }
     }
     *out = p;
     return UPR_OK;
@@ -877,6 +925,9 @@ void upr_plan_destroy(upr_plan *p)
     dfree(p->gacc);
     dfree(p->hub_ticket);
     dfree(p->hub_bits);
+    dfree(p->adj_r);
+    dfree(p->perm);
+    dfree(p->order);
     delete p;
 }
 
@@ -1002,14 +1053,18 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
     // compact partition copy for the neighbour gathers (kept in step by the apply)
     const PartView pv{c->pc, k <= 256 ? 1 : 2, k <= 128 ? 1 : 0};
     HIP_TRY(c, launch_pack_part(n, bk, b ? b->goff_d : nullptr, part, c->pc, pv.bytes, c->counters, s));
+    // the same in the plan's label order for the table build
+    if (p->order) HIP_TRY(c, launch_pack_relabel(n, p->order, c->pc, c->pc2, pv.bytes, s));
+    const PartView tpv = table_part(c, p, pv);
     if (q->rebuild_table) {
+        const GraphView tg = p->table_graph();
         {
             PhaseTimer t(c, 0, s);
-            HIP_TRY(c, launch_gain_tile(p->g, k, pv, conn, p->hub_t, nullptr, s));
+            HIP_TRY(c, launch_gain_tile(tg, k, tpv, conn, p->hub_t, nullptr, s));
         }
         if (p->nh > 0) {
             PhaseTimer t(c, 1, s);
-            HIP_TRY(c, launch_gain_hub(p->g, k, pv, conn, h, s));
+            HIP_TRY(c, launch_gain_hub(tg, k, tpv, conn, h, s));
         }
     }
     {
@@ -1075,8 +1130,7 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
         }
         {
             PhaseTimer t(c, 4, s);
-            HIP_TRY(c, launch_apply(p->g, bk, part, pv, conn, W, c->mvto, p->hub_t, h,
-                                    c->counters, p->dirty_threshold, c->dirty, s));
+            HIP_TRY(c, apply_moves(c, p, bk, part, pv, conn, W, s));
         }
         {
             PhaseTimer t(c, 6, s);

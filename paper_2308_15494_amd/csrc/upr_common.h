@@ -505,6 +505,14 @@ hipError_t launch_gain_hub(const GraphView &g, int32_t k, const PartView &part, 
 hipError_t launch_pack_part(int64_t n, const Blocks &bk, const int64_t *goff, const int32_t *part,
                             void *pc, int bytes, unsigned long long *counters, hipStream_t s);
 hipError_t launch_hub_bits(const HubView &h, uint32_t *bits, hipStream_t s);
+// Neighbour ids renumbered by descending degree (ties by id) for the table
+// build: order[i] = node of label i, perm[v] = label of v, adj_r[e] =
+// perm[adjncy[e]]. Allocates and frees its own sort space; synchronises s.
+hipError_t launch_degree_relabel(const GraphView &g, int64_t nnz, int32_t *order, int32_t *perm,
+                                 int32_t *adj_r, hipStream_t s);
+// pc2[i] = pc[order[i]] (the compact copy in label order; bytes 1 or 2).
+hipError_t launch_pack_relabel(int64_t n, const int32_t *order, const void *pc, void *pc2,
+                               int bytes, hipStream_t s);
 // Per node: 2*cut into counters[cut_slot], penalty buckets of the available
 // nodes (bucket may be null), block weights W[part] += c (W may be null),
 // availability for rebalancing (avail may be null).
@@ -626,10 +634,14 @@ hipError_t launch_seq_segments(const GraphView &g, const Blocks &bk, const int64
 // otherwise their gain-table tiles are marked and rebuilt from the new
 // partition, and the hub rows are rebuilt.
 // pv: the compact partition copy to keep in step (pv.p writable, or bytes 4).
+// tg / tpv: the graph and partition views the table build reads (the
+// relabelled ones when the plan has them); pc2 / perm (may be null): the
+// compact copy in label order, kept in step with pv.
 hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, const PartView &pv,
                         int32_t *conn, int64_t *W, int32_t *mvto, int64_t hub_t,
                         const HubView &h, const unsigned long long *counters,
-                        int64_t dirty_threshold, uint8_t *dirty, hipStream_t s);
+                        int64_t dirty_threshold, uint8_t *dirty, const GraphView &tg,
+                        const PartView &tpv, void *pc2, const int32_t *perm, hipStream_t s);
 hipError_t launch_stats_final(int64_t *stats, const unsigned long long *counters, int64_t lmax,
                               int64_t iters, int64_t status, hipStream_t s);
 hipError_t launch_export_moves(int64_t n, const int64_t *key, const int64_t *pen,

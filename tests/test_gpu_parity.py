@@ -499,6 +499,28 @@ def test_apply_modes(upr, ctx, monkeypatch, div):
             pr.compare(ost, odbg, f"{name} round {r}")
 
 
+@pytest.mark.parametrize("div", ["1", "100000000"], ids=["delta", "rebuild"])
+@pytest.mark.parametrize("relabel", ["2", "0"], ids=["relabelled", "as_given"])
+def test_table_relabelling(upr, ctx, monkeypatch, relabel, div):
+    """The table build reads a copy of the adjacency whose neighbour ids are
+    renumbered by descending degree, with the partition copy in that order
+    (forced here below the default size limit, and switched off): tables,
+    partitions and statistics equal the oracle's in both apply modes, with
+    hubs, and with the one- and two-byte partition copies (k = 300)."""
+    monkeypatch.setenv("UPR_RELABEL", relabel)
+    monkeypatch.setenv("UPR_DIRTY_DIV", div)
+    monkeypatch.setenv("UPR_HUB_THRESHOLD", "64")
+    for name, g, k in [("rmat", gg.rmat(12, 16, seed=41), 32),
+                       ("cl_w", gg.with_weights(gg.chung_lu(4000, 8.0, 2.1, seed=6), 6, 6, 3), 8),
+                       ("cl_k300", gg.chung_lu(3000, 12.0, 2.2, seed=7), 300),
+                       ("grid", gg.grid2d(40, 50), 16)]:
+        say(f"relabel={relabel} div={div} case={name}")
+        pr = Pair(upr, ctx, g, k, skewed_partition(g.n, k, 4, 0.35))
+        for r in range(1, 5):
+            ost, odbg = pr.round(tau=gg.tau_schedule(r, 4))
+            pr.compare(ost, odbg, f"{name} round {r}")
+
+
 # ------------------------------------------------------------ driver --
 
 @pytest.mark.parametrize("case", [("cl", 8), ("rgg", 16), ("rmat", 8), ("cl_w", 4)])
