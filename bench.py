@@ -59,8 +59,9 @@ COPY_BYTES = 1 << 30  # calibration copy: reads and writes this many bytes
 
 
 def pmc_run(args):
-    """Workload for the counter runs: a few gain-table builds of the benchmark
-    graph, then a plain device copy of COPY_BYTES (the calibration kernel)."""
+    """Workload for the counter runs: the first rounds of the benchmark (the
+    table build in the same configuration as in the timed rounds), then a
+    plain device copy of COPY_BYTES (the calibration kernel)."""
     import torch
     from paper_2308_15494_amd import graphgen as gg
     from paper_2308_15494_amd import upr
@@ -68,8 +69,8 @@ def pmc_run(args):
     ctx = upr.Context(0)
     r = upr.Refiner(g, k, ctx=ctx)
     r.set_partition(gg.random_partition(g.n, k, seed))
-    for _ in range(5):
-        upr.gain_table(ctx, r.plan, k, r.part, r.conn)
+    for i in range(1, 6):
+        r.round(upr.params(k, eps, tau=gg.tau_schedule(i, rounds)))
     src = torch.ones(COPY_BYTES // 4, dtype=torch.int32, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):

@@ -762,7 +762,8 @@ int upr_validate_graph(upr_ctx *c, const upr_graph *graph, hipStream_t s)
 }
 
 static int plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipStream_t s,
-                       bool validate, int64_t known_nnz, const upr_plan_opts *opts);
+                       bool validate, int64_t known_nnz, const upr_plan_opts *opts,
+                       bool batch = false);
 
 int upr_plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipStream_t s)
 {
@@ -776,9 +777,10 @@ int upr_plan_create_opts(upr_ctx *c, const upr_graph *graph, const upr_plan_opts
 }
 
 // validate = false: the caller has checked the graph already (a batch of
-// graphs validated before); known_nnz >= 0: xadj[n], known on the host.
+// graphs validated before); known_nnz >= 0: xadj[n], known on the host;
+// batch: the union graph of a batch (not relabelled by default).
 static int plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipStream_t s,
-                       bool validate, int64_t known_nnz, const upr_plan_opts *opts)
+                       bool validate, int64_t known_nnz, const upr_plan_opts *opts, bool batch)
 {
     if (!c) return UPR_E_ARG;
     if (!out) return fail(c, UPR_E_ARG, "out is NULL");
@@ -892,11 +894,13 @@ static int plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipSt
         }
         dfree(hub_list);
         // relabelled adjacency for the table build: UPR_RELABEL=0 never, 2
-        // always, else (default) for graphs whose compact partition copy
-        // outgrows an L1 (kRelabelMinNodes). Skipped, not an error, if its
-        // memory cannot be had.
+        // always, else (default) for single graphs whose compact partition
+        // copy outgrows an L1 (kRelabelMinNodes). Not for a batch by default:
+        // a server rebuilds batches often and the sort costs more there than
+        // it saves. Skipped, not an error, if its memory cannot be had.
         const int64_t relabel = env_int("UPR_RELABEL", 1);
-        if (p->nnz > 0 && (relabel == 2 || (relabel == 1 && g.n >= kRelabelMinNodes))) {
+        if (p->nnz > 0 &&
+            (relabel == 2 || (relabel == 1 && !batch && g.n >= kRelabelMinNodes))) {
             if (dalloc(&p->adj_r, p->nnz) == hipSuccess && dalloc(&p->perm, g.n) == hipSuccess &&
                 dalloc(&p->order, g.n) == hipSuccess) {
                 if (launch_degree_relabel(g, p->nnz, p->order, p->perm, p->adj_r, s) != hipSuccess)
@@ -1328,7 +1332,7 @@ int upr_batch_create(upr_ctx *c, const upr_graph *graphs, const int64_t *nnz_hos
     if (got[1] != ~0ull) return bail(UPR_E_GRAPH, "a graph names a neighbour outside its own nodes");
     if (got[3] != ~0ull) return bail(UPR_E_GRAPH, "a graph has a non-positive edge weight");
     const upr_graph ug{b->n, b->xadj, b->adjncy, b->adjwgt, b->vwgt};
-    int rc = plan_create(c, &ug, &b->plan, s, !trusted, b->nnz, opts);
+    int rc = plan_create(c, &ug, &b->plan, s, !trusted, b->nnz, opts, true);
     if (rc) {
         const std::string msg = c->err;
         upr_batch_destroy(b);
