@@ -444,14 +444,22 @@ hipError_t launch_cut_edges(const GraphView &g, const int32_t *part, unsigned lo
     return hipGetLastError();
 }
 
+// pc2 (may be null): the same values in label order, pc2[i] = local block of
+// order[i] (a gather of part; a bad value there is counted through its own
+// node v).
 __global__ void k_pack_part(int64_t n, Blocks bk, const int64_t *goff, const int32_t *part,
-                            void *pc, int bytes, unsigned long long *counters)
+                            void *pc, int bytes, unsigned long long *counters,
+                            const int32_t *order, void *pc2)
 {
     const int32_t K = bk.total();
     bool bad = false;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
         const int32_t B = part[v];
+        if (pc2) {
+            const int32_t B2 = part[order[v]];
+            pset(pc2, bytes, v, (unsigned)B2 < (unsigned)K ? bk.local(B2) : 0);
+        }
         if ((unsigned)B >= (unsigned)K) {
             bad = true;
             continue;
@@ -463,11 +471,12 @@ __global__ void k_pack_part(int64_t n, Blocks bk, const int64_t *goff, const int
 }
 
 hipError_t launch_pack_part(int64_t n, const Blocks &bk, const int64_t *goff, const int32_t *part,
-                            void *pc, int bytes, unsigned long long *counters, hipStream_t s)
+                            void *pc, int bytes, unsigned long long *counters, hipStream_t s,
+                            const int32_t *order, void *pc2)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pack_part, dim3(grid_for(n, kBlock * 4, 4096)), dim3(kBlock), 0, s, n, bk,
-                       goff, part, pc, bytes, counters);
+                       goff, part, pc, bytes, counters, order, pc2);
     return hipGetLastError();
 }
 
@@ -556,27 +565,6 @@ hipError_t launch_degree_relabel(const GraphView &g, int64_t nnz, int32_t *order
     (void)hipFree(ids);
     (void)hipFree(temp);
     return e;
-}
-
-// The compact partition copy in label order: pc2[i] = pc[order[i]].
-__global__ void k_pack_relabel(int64_t n, const int32_t *order, const void *pc, void *pc2,
-                               int bytes)
-{
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const int64_t v = order[i];
-        if (bytes == 1) ((uint8_t *)pc2)[i] = ((const uint8_t *)pc)[v];
-        else ((uint16_t *)pc2)[i] = ((const uint16_t *)pc)[v];
-    }
-}
-
-hipError_t launch_pack_relabel(int64_t n, const int32_t *order, const void *pc, void *pc2,
-                               int bytes, hipStream_t s)
-{
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pack_relabel, dim3(grid_for(n, kBlock * 4, 4096)), dim3(kBlock), 0, s, n,
-                       order, pc, pc2, bytes);
-    return hipGetLastError();
 }
 
 }  // namespace upr

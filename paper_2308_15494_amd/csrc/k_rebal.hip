@@ -385,25 +385,66 @@ __device__ __forceinline__ bool rb_member(const RebalWs &r, const Blocks &bk, in
     return (unsigned)a < (unsigned)bk.total() && r.W0[a] > bk.src_lmax_of(a) && r.rtgt[v] >= 0;
 }
 
+// One wave's kRbRuns runs of 64 node ids (run i: base + 64 i + lane) for the
+// rebalancer's node scans. Every load of all runs is issued before any is
+// used (from clamped indices, without a branch): a node's loads depend on
+// each other (part, then its block's weights), and taken one node at a time
+// they were a chain of round trips.
+constexpr int kRbRuns = 4;
+struct RbRuns {
+    int64_t v[kRbRuns];
+    int32_t a[kRbRuns], j[kRbRuns];
+    int be[kRbRuns];
+    bool mem[kRbRuns];  // movable node of an overloaded block (rb_member)
+    int64_t cv[kRbRuns];
+};
+__device__ __forceinline__ void rb_load_runs(const GraphView &g, const Blocks &bk,
+                                             const int32_t *part, const RebalWs &r, int64_t base,
+                                             RbRuns &x)
+{
+    const int32_t K = bk.total();
+    const int lane = lane_id();
+    int64_t vc[kRbRuns];
+#pragma unroll
+    for (int i = 0; i < kRbRuns; ++i) {
+        x.v[i] = base + 64 * i + lane;
+        vc[i] = x.v[i] < g.n ? x.v[i] : g.n - 1;
+        x.a[i] = part[vc[i]];
+        x.j[i] = r.rtgt[vc[i]];
+        x.be[i] = r.rbeta[vc[i]];
+        x.cv[i] = node_weight(g, vc[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < kRbRuns; ++i) {
+        const bool ok = x.v[i] < g.n && (unsigned)x.a[i] < (unsigned)K;
+        const int32_t a = ok ? x.a[i] : 0;
+        x.mem[i] = ok && r.W0[a] > bk.src_lmax_of(a) && x.j[i] >= 0;
+    }
+}
+
 // Nodes in the cutoff bucket add their weight to the chunk of their id
 // (target side: every offer; source side: accepted offers).
 __global__ __launch_bounds__(kBlock) void k_rb_chunks(GraphView g, Blocks bk, const int32_t *part,
                                                        RebalWs r, RbView rv, int target_side)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.n; v += stride) {
-        const int32_t a = part[v];
-        if (!rb_member(r, bk, v, a)) continue;
-        const int be = r.rbeta[v];
-        const int32_t j = r.rtgt[v];
-        // chunks count node ids from the start of the node's graph
-        const int64_t c = (v - (r.goff ? r.goff[bk.graph(a)] : 0)) >> r.chunk_shift;
-        if (target_side) {
-            if (be == r.cbeta_tgt[j])
-                atomic_add_i64(&r.chunk_tgt[(int64_t)j * r.nchunks + c], node_weight(g, v));
-        } else {
-            if (be == r.cbeta_src[a] && rb_accepted(rv, v, j))
-                atomic_add_i64(&r.chunk_src[(int64_t)a * r.nchunks + c], node_weight(g, v));
+    const int64_t stride = (int64_t)gridDim.x * kBlock * kRbRuns;
+    for (int64_t base = ((int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63)) * kRbRuns; base < g.n;
+         base += stride) {
+        RbRuns x;
+        rb_load_runs(g, bk, part, r, base, x);
+#pragma unroll
+        for (int i = 0; i < kRbRuns; ++i) {
+            if (!x.mem[i]) continue;
+            const int32_t a = x.a[i], j = x.j[i];
+            // chunks count node ids from the start of the node's graph
+            const int64_t c = (x.v[i] - (r.goff ? r.goff[bk.graph(a)] : 0)) >> r.chunk_shift;
+            if (target_side) {
+                if (x.be[i] == r.cbeta_tgt[j])
+                    atomic_add_i64(&r.chunk_tgt[(int64_t)j * r.nchunks + c], x.cv[i]);
+            } else {
+                if (x.be[i] == r.cbeta_src[a] && rb_accepted(rv, x.v[i], j))
+                    atomic_add_i64(&r.chunk_src[(int64_t)a * r.nchunks + c], x.cv[i]);
+            }
         }
     }
 }
@@ -420,24 +461,20 @@ __global__ __launch_bounds__(kBlock) void k_rb_src_hist(GraphView g, Blocks bk, 
         for (int j = threadIdx.x; j < K * kRbBuckets; j += kBlock) sH[j] = 0;
         __syncthreads();
     }
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < g.n;
+    const int64_t stride = (int64_t)gridDim.x * kBlock * kRbRuns;
+    for (int64_t base = ((int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63)) * kRbRuns; base < g.n;
          base += stride) {
-        const int64_t v = base + lane_id();
-        bool sel = false;
-        int64_t hkey = 0, cv = 0;
-        if (v < g.n) {
-            const int32_t a = part[v];
-            if (rb_member(r, bk, v, a) && rb_accepted(rv, v, r.rtgt[v])) {
-                sel = true;
-                hkey = (int64_t)a * kRbBuckets + r.rbeta[v];
-                cv = node_weight(g, v);
+        RbRuns x;
+        rb_load_runs(g, bk, part, r, base, x);
+#pragma unroll
+        for (int i = 0; i < kRbRuns; ++i) {
+            const bool sel = x.mem[i] && rb_accepted(rv, x.v[i], x.j[i]);
+            const int64_t hkey = sel ? (int64_t)x.a[i] * kRbBuckets + x.be[i] : 0;
+            if (h_lds) {
+                if (sel) atomicAdd(&sH[hkey], (uint32_t)x.cv[i]);
+            } else {
+                wave_hist_add(r.hist_src, hkey, sel ? x.cv[i] : 0, sel);
             }
-        }
-        if (h_lds) {
-            if (sel) atomicAdd(&sH[hkey], (uint32_t)cv);
-        } else {
-            wave_hist_add(r.hist_src, hkey, cv, sel);
         }
     }
     if (h_lds) {
@@ -559,26 +596,24 @@ __global__ __launch_bounds__(kBlock) void k_rb_moves(GraphView g, Blocks bk, con
         mdeg = 0;
     }
     __syncthreads();
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < g.n;
+    const int64_t stride = (int64_t)gridDim.x * kBlock * kRbRuns;
+    for (int64_t base = ((int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63)) * kRbRuns; base < g.n;
          base += stride) {
-        const int64_t v = base + lane_id();
-        bool acc = false;
-        int32_t a = 0;
-        if (v < g.n) {
-            a = part[v];
-            if (rb_member(r, bk, v, a)) {
-                const int32_t j = r.rtgt[v];
-                if (rb_kept(rv, v, a, j)) {
-                    mvto[v] = j;
-                    acc = true;
-                    const int64_t deg = g.xadj[v + 1] - g.xadj[v];
-                    atomicAdd(&mdeg, (unsigned long long)deg);
-                }
+        RbRuns x;
+        rb_load_runs(g, bk, part, r, base, x);
+#pragma unroll
+        for (int i = 0; i < kRbRuns; ++i) {
+            const bool acc = x.mem[i] && rb_kept(rv, x.v[i], x.a[i], x.j[i]);
+            if (acc) {
+                const int64_t v = x.v[i];
+                mvto[v] = x.j[i];
+                atomicAdd(&mdeg, (unsigned long long)(g.xadj[v + 1] - g.xadj[v]));
             }
+            wave_count(acc, &moved);
+            if (gstat)
+                wave_hist_add(gstat, (int64_t)bk.graph(acc ? x.a[i] : 0) * GS_COUNT + GS_MOVED_NOW, 1,
+                              acc);
         }
-        wave_count(acc, &moved);
-        if (gstat) wave_hist_add(gstat, (int64_t)bk.graph(a) * GS_COUNT + GS_MOVED_NOW, 1, acc);
     }
     __syncthreads();
     if (threadIdx.x == 0 && moved) {

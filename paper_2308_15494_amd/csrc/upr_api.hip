@@ -1056,9 +1056,9 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
     if (b) HIP_TRY(c, launch_fill_i64(gstat, (int64_t)GS_COUNT * ng, 0, s));
     // compact partition copy for the neighbour gathers (kept in step by the apply)
     const PartView pv{c->pc, k <= 256 ? 1 : 2, k <= 128 ? 1 : 0};
-    HIP_TRY(c, launch_pack_part(n, bk, b ? b->goff_d : nullptr, part, c->pc, pv.bytes, c->counters, s));
-    // the same in the plan's label order for the table build
-    if (p->order) HIP_TRY(c, launch_pack_relabel(n, p->order, c->pc, c->pc2, pv.bytes, s));
+    // and the same in the plan's label order for the table build
+    HIP_TRY(c, launch_pack_part(n, bk, b ? b->goff_d : nullptr, part, c->pc, pv.bytes, c->counters, s,
+                                p->order, p->order ? c->pc2 : nullptr));
     const PartView tpv = table_part(c, p, pv);
     if (q->rebuild_table) {
         const GraphView tg = p->table_graph();

@@ -497,22 +497,21 @@ hipError_t launch_gain_hub(const GraphView &g, int32_t k, const PartView &part, 
                            const HubView &h, hipStream_t s,
                            const unsigned long long *counters = nullptr,
                            int64_t dirty_threshold = 0);
-// Compact copy of part (bytes = 1 or 2).
 // Compact copy of the local blocks (bytes = 1 or 2). Checks every value: a
 // global block id below bk.total() and, for a batch (goff = node offsets of
 // the graphs, ng + 1 entries), a block of the node's own graph; violations
-// count in counters[CNT_BAD_INPUT].
+// count in counters[CNT_BAD_INPUT]. With order / pc2: also the copy in the
+// plan's label order, pc2[i] = local block of node order[i].
 hipError_t launch_pack_part(int64_t n, const Blocks &bk, const int64_t *goff, const int32_t *part,
-                            void *pc, int bytes, unsigned long long *counters, hipStream_t s);
+                            void *pc, int bytes, unsigned long long *counters, hipStream_t s,
+                            const int32_t *order = nullptr, void *pc2 = nullptr);
 hipError_t launch_hub_bits(const HubView &h, uint32_t *bits, hipStream_t s);
 // Neighbour ids renumbered by descending degree (ties by id) for the table
 // build: order[i] = node of label i, perm[v] = label of v, adj_r[e] =
 // perm[adjncy[e]]. Allocates and frees its own sort space; synchronises s.
 hipError_t launch_degree_relabel(const GraphView &g, int64_t nnz, int32_t *order, int32_t *perm,
                                  int32_t *adj_r, hipStream_t s);
-// pc2[i] = pc[order[i]] (the compact copy in label order; bytes 1 or 2).
-hipError_t launch_pack_relabel(int64_t n, const int32_t *order, const void *pc, void *pc2,
-                               int bytes, hipStream_t s);
+
 // Per node: 2*cut into counters[cut_slot], penalty buckets of the available
 // nodes (bucket may be null), block weights W[part] += c (W may be null),
 // availability for rebalancing (avail may be null).
