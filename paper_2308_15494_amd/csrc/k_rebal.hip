@@ -123,6 +123,8 @@ hipError_t launch_rb_begin(const Blocks &bk, const int64_t *W, const RebalWs &r,
 // ---------------------------------------------------------------- prepare --
 
 constexpr int kHistLdsBytes = 49152;
+// 64-node runs per wave and step of the node scans (their loads in flight together)
+constexpr int kRbRuns = 4;
 
 // Nodes of overloaded blocks: target and priority bucket. G lanes per node
 // scan its row (V ints per lane per vector): best connected target that
@@ -198,109 +200,125 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
     const int grp = lane / G;
     const int gl = lane & (G - 1);
     const int nvec = k / V;
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t base = (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63); base < g.n;
-         base += stride) {
-        const int64_t lv = base + lane;
-        int32_t la = -1;
-        if (lv < g.n) la = part[lv];
-        const uint64_t mask =
-            __ballot(lv < g.n && (unsigned)la < (unsigned)K && W0[la] > bk.src_lmax_of(la));
-        const int cnt = __popcll(mask);
-        for (int p0 = 0; p0 < cnt; p0 += GPW * U) {
-            int64_t vu[U];
-            int32_t Au[U];
-            bool oku[U];
-            int32_t cu[U][R][V];
+    // kRbRuns runs of 64 node ids per wave and step: their part entries and
+    // block weights are loaded before any run is worked on
+    const int64_t stride = (int64_t)gridDim.x * kBlock * kRbRuns;
+    for (int64_t base0 = ((int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63)) * kRbRuns; base0 < g.n;
+         base0 += stride) {
+        int32_t lar[kRbRuns];
+        uint64_t maskr[kRbRuns];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int p = p0 + u * GPW + grp;
-                oku[u] = p < cnt;
-                const int src = oku[u] ? nth_set_bit(mask, p) : 0;
-                vu[u] = __shfl(lv, src);
-                Au[u] = __shfl(la, src);
-            }
-            if constexpr (U > 1 || R > 1) {
-                // unconditional loads (an unused slot holds lane 0's node, a
-                // valid one; q >= nvec rereads the last vector, unused), so
-                // that all rows are in flight together
+        for (int i = 0; i < kRbRuns; ++i) {
+            const int64_t lv = base0 + 64 * i + lane;
+            lar[i] = part[lv < g.n ? lv : g.n - 1];
+        }
+#pragma unroll
+        for (int i = 0; i < kRbRuns; ++i) {
+            const int64_t lv = base0 + 64 * i + lane;
+            const bool ok = lv < g.n && (unsigned)lar[i] < (unsigned)K;
+            const int32_t a = ok ? lar[i] : 0;
+            maskr[i] = __ballot(ok && W0[a] > bk.src_lmax_of(a));
+        }
+        for (int run = 0; run < kRbRuns; ++run) {
+            const int64_t lv = base0 + 64 * run + lane;
+            const int32_t la = lar[run];
+            const uint64_t mask = maskr[run];
+            const int cnt = __popcll(mask);
+            for (int p0 = 0; p0 < cnt; p0 += GPW * U) {
+                int64_t vu[U];
+                int32_t Au[U];
+                bool oku[U];
+                int32_t cu[U][R][V];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const int q = gl + r * G;
-                        rb_load_vec<V>(conn + vu[u] * (int64_t)k, q < nvec ? q : nvec - 1, cu[u][r]);
-                    }
+                    const int p = p0 + u * GPW + grp;
+                    oku[u] = p < cnt;
+                    const int src = oku[u] ? nth_set_bit(mask, p) : 0;
+                    vu[u] = __shfl(lv, src);
+                    Au[u] = __shfl(la, src);
                 }
-            }
+                if constexpr (U > 1 || R > 1) {
+                    // unconditional loads (an unused slot holds lane 0's node, a
+                    // valid one; q >= nvec rereads the last vector, unused), so
+                    // that all rows are in flight together
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const bool ok = oku[u];
-                const int64_t v = vu[u];
-                const int32_t A = Au[u];
-                const int32_t a = ok ? bk.local(A) : 0;     // row index of the source
-                const int32_t base = ok ? bk.base(A) : 0;  // global id of local block 0
-                const int64_t lmax = ok ? bk.lmax_of(A) : 0;
-                int64_t best = -1, lw = INT64_MAX, cv = 1;
-                int32_t lj = 0x7fffffff;
-                int32_t ca_mine = 0;  // omega(v, V_a), held by the lane that loads column a
-                if (ok) {
-                    cv = node_weight(g, v);
-                    if constexpr (U > 1 || R > 1) {
+                    for (int u = 0; u < U; ++u) {
 #pragma unroll
                         for (int r = 0; r < R; ++r) {
                             const int q = gl + r * G;
-                            if (q < nvec)
-                                rb_scan_cols<V>(cu[u][r], q * V, a, base, cv, lmax, W0, best, lw,
-                                                lj, ca_mine);
-                        }
-                    } else {
-                        const int32_t *row = conn + v * (int64_t)k;
-                        for (int q = gl; q < nvec; q += G) {
-                            int32_t c[V];
-                            rb_load_vec<V>(row, q, c);
-                            rb_scan_cols<V>(c, q * V, a, base, cv, lmax, W0, best, lw, lj,
-                                            ca_mine);
+                            rb_load_vec<V>(conn + vu[u] * (int64_t)k, q < nvec ? q : nvec - 1, cu[u][r]);
                         }
                     }
                 }
 #pragma unroll
-                for (int off = G / 2; off > 0; off >>= 1) {
-                    const int64_t ob = __shfl_xor(best, off);
-                    const int64_t ow = __shfl_xor(lw, off);
-                    const int32_t oj = __shfl_xor(lj, off);
-                    if (ob > best) best = ob;
-                    if (ow < lw || (ow == lw && oj < lj)) {
-                        lw = ow;
-                        lj = oj;
+                for (int u = 0; u < U; ++u) {
+                    const bool ok = oku[u];
+                    const int64_t v = vu[u];
+                    const int32_t A = Au[u];
+                    const int32_t a = ok ? bk.local(A) : 0;     // row index of the source
+                    const int32_t base = ok ? bk.base(A) : 0;  // global id of local block 0
+                    const int64_t lmax = ok ? bk.lmax_of(A) : 0;
+                    int64_t best = -1, lw = INT64_MAX, cv = 1;
+                    int32_t lj = 0x7fffffff;
+                    int32_t ca_mine = 0;  // omega(v, V_a), held by the lane that loads column a
+                    if (ok) {
+                        cv = node_weight(g, v);
+                        if constexpr (U > 1 || R > 1) {
+#pragma unroll
+                            for (int r = 0; r < R; ++r) {
+                                const int q = gl + r * G;
+                                if (q < nvec)
+                                    rb_scan_cols<V>(cu[u][r], q * V, a, base, cv, lmax, W0, best, lw,
+                                                    lj, ca_mine);
+                            }
+                        } else {
+                            const int32_t *row = conn + v * (int64_t)k;
+                            for (int q = gl; q < nvec; q += G) {
+                                int32_t c[V];
+                                rb_load_vec<V>(row, q, c);
+                                rb_scan_cols<V>(c, q * V, a, base, cv, lmax, W0, best, lw, lj,
+                                                ca_mine);
+                            }
+                        }
                     }
-                }
-                // column a sits in vector a / V, loaded by lane (a / V) mod G of the group
-                const int32_t ca = __shfl(ca_mine, (lane & ~(G - 1)) + ((a / V) & (G - 1)));
-                bool push = false;
-                int64_t hkey = 0;
-                if (ok && gl == 0) {
-                    int32_t tgt = -1;
-                    int64_t ct = 0;
-                    if (best >= 0) {
-                        tgt = 0xFFFF - (int32_t)(best & 0xFFFF);
-                        ct = best >> 16;
-                    } else if (lj != 0x7fffffff) {
-                        tgt = lj;
+#pragma unroll
+                    for (int off = G / 2; off > 0; off >>= 1) {
+                        const int64_t ob = __shfl_xor(best, off);
+                        const int64_t ow = __shfl_xor(lw, off);
+                        const int32_t oj = __shfl_xor(lj, off);
+                        if (ob > best) best = ob;
+                        if (ow < lw || (ow == lw && oj < lj)) {
+                            lw = ow;
+                            lj = oj;
+                        }
                     }
-                    r.rtgt[v] = tgt >= 0 ? base + tgt : -1;
-                    if (tgt >= 0) {
-                        // the plain-gain variant ranks by the gain alone (c(v) = 1)
-                        const int be = rebalance_bucket(ct - (int64_t)ca, plain ? 1 : cv);
-                        r.rbeta[v] = (uint8_t)be;
-                        hkey = (int64_t)(base + tgt) * kRbBuckets + be;
-                        push = true;
+                    // column a sits in vector a / V, loaded by lane (a / V) mod G of the group
+                    const int32_t ca = __shfl(ca_mine, (lane & ~(G - 1)) + ((a / V) & (G - 1)));
+                    bool push = false;
+                    int64_t hkey = 0;
+                    if (ok && gl == 0) {
+                        int32_t tgt = -1;
+                        int64_t ct = 0;
+                        if (best >= 0) {
+                            tgt = 0xFFFF - (int32_t)(best & 0xFFFF);
+                            ct = best >> 16;
+                        } else if (lj != 0x7fffffff) {
+                            tgt = lj;
+                        }
+                        r.rtgt[v] = tgt >= 0 ? base + tgt : -1;
+                        if (tgt >= 0) {
+                            // the plain-gain variant ranks by the gain alone (c(v) = 1)
+                            const int be = rebalance_bucket(ct - (int64_t)ca, plain ? 1 : cv);
+                            r.rbeta[v] = (uint8_t)be;
+                            hkey = (int64_t)(base + tgt) * kRbBuckets + be;
+                            push = true;
+                        }
                     }
-                }
-                if (h_lds) {
-                    if (push) atomicAdd(&sH[hkey], (uint32_t)cv);
-                } else {
-                    wave_hist_add(r.hist_tgt, hkey, cv, push);
+                    if (h_lds) {
+                        if (push) atomicAdd(&sH[hkey], (uint32_t)cv);
+                    } else {
+                        wave_hist_add(r.hist_tgt, hkey, cv, push);
+                    }
                 }
             }
         }
@@ -390,7 +408,6 @@ __device__ __forceinline__ bool rb_member(const RebalWs &r, const Blocks &bk, in
 // used (from clamped indices, without a branch): a node's loads depend on
 // each other (part, then its block's weights), and taken one node at a time
 // they were a chain of round trips.
-constexpr int kRbRuns = 4;
 struct RbRuns {
     int64_t v[kRbRuns];
     int32_t a[kRbRuns], j[kRbRuns];
@@ -486,6 +503,8 @@ __global__ __launch_bounds__(kBlock) void k_rb_src_hist(GraphView g, Blocks bk, 
 
 // ------------------------------------------------------------- id bounds --
 
+constexpr int kThetaRun = 16;  // chunks per thread: nchunks <= 4096 = kThetaRun * kBlock
+
 // One workgroup per block. Within the cutoff bucket, find the id bound:
 //   source: theta = (first id at which the cumulative weight reaches need) + 1
 //   target: theta = first id at which the cumulative weight exceeds room
@@ -515,17 +534,28 @@ __global__ __launch_bounds__(kBlock) void k_rb_theta(GraphView g, Blocks bk, con
         found_lds[0] = -1;
         found_lds[1] = 0;
     }
+    // a run of at most kThetaRun chunks per thread (nchunks <= 4096), held in
+    // registers: all its loads are issued together
     const int64_t per = (r.nchunks + kBlock - 1) / kBlock;
     const int64_t c_lo = threadIdx.x * per;
-    const int64_t c_hi = (c_lo + per) < r.nchunks ? (c_lo + per) : r.nchunks;
+    int64_t xs[kThetaRun];
     int64_t run_sum = 0;
-    for (int64_t c = c_lo; c < c_hi; ++c) run_sum += row[c];
+#pragma unroll
+    for (int i = 0; i < kThetaRun; ++i) {
+        const int64_t c = c_lo + i;
+        const bool in = i < per && c < r.nchunks;
+        const int64_t x = row[in ? c : 0];
+        xs[i] = in ? x : 0;
+        run_sum += xs[i];
+    }
     int64_t total;
     const int64_t incl = block_incl_scan(run_sum, scan_lds, &total);
     int64_t cum = incl - run_sum;
-    for (int64_t c = c_lo; c < c_hi; ++c) {
-        const int64_t x = row[c];
+#pragma unroll
+    for (int i = 0; i < kThetaRun; ++i) {
+        const int64_t x = xs[i];
         if (x) {
+            const int64_t c = c_lo + i;
             row[c] = 0;
             const int64_t nxt = cum + x;
             const bool reach = target_side ? (nxt > limit) : (nxt >= limit);
