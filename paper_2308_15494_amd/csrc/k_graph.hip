@@ -240,7 +240,9 @@ __global__ __launch_bounds__(kBlock) void k_node_stats(GraphView g, Blocks bk,
                                                         int32_t t_num, int32_t t_den,
                                                         unsigned long long *counters, int cut_slot,
                                                         uint8_t *avail_out, int64_t *gstat,
-                                                        int gs_slot)
+                                                        int gs_slot,
+                                                        const int32_t *__restrict__ inner,
+                                                        const uint32_t *__restrict__ hub_bits)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ unsigned long long red[4];
@@ -290,8 +292,10 @@ __global__ __launch_bounds__(kBlock) void k_node_stats(GraphView g, Blocks bk,
             const int64_t v = vb + (int64_t)i * kBlock + lane_id();
             const int64_t vc = v < hi ? v : hi - 1;
             const int32_t a = (unsigned)au[i] < (unsigned)K ? au[i] : 0;
-            inu[i] = conn[vc * (int64_t)k + bk.local(a)];
+            inu[i] = inner ? inner[vc] : conn[vc * (int64_t)k + bk.local(a)];
             wdu[i] = wdeg[vc];
+            if (inner && hub_bits && ((hub_bits[vc >> 5] >> (vc & 31)) & 1u))
+                inu[i] = conn[vc * (int64_t)k + bk.local(a)];  // a hub (rare)
         }
 #pragma unroll
         for (int i = 0; i < kStatsUnroll; ++i) {
@@ -370,7 +374,8 @@ hipError_t launch_node_stats(const GraphView &g, const Blocks &bk, const StatsGe
                              const int32_t *part, const int32_t *conn, const int32_t *wdeg,
                              int64_t *W, int64_t *bucket, int32_t t_num, int32_t t_den,
                              unsigned long long *counters, int cut_slot, uint8_t *avail,
-                             int64_t *gstat, int gs_slot, hipStream_t s)
+                             int64_t *gstat, int gs_slot, hipStream_t s, const int32_t *inner,
+                             const uint32_t *hub_bits)
 {
     if (g.n <= 0) return hipSuccess;
     const int64_t span = sg.span > 0 ? sg.span : stats_span(g.n, 0);
@@ -381,7 +386,7 @@ hipError_t launch_node_stats(const GraphView &g, const Blocks &bk, const StatsGe
     const int64_t rows = (g.n + span - 1) / span;
     hipLaunchKernelGGL(k_node_stats, dim3((unsigned)rows), dim3(kBlock), lds, s, g, bk, sg.goff,
                        span, W ? cap_w : 0, bucket ? cap_b : 0, part, conn, wdeg, W, bucket, t_num,
-                       t_den, counters, cut_slot, avail, gstat, gs_slot);
+                       t_den, counters, cut_slot, avail, gstat, gs_slot, inner, hub_bits);
     return hipGetLastError();
 }
 

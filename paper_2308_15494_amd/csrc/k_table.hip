@@ -30,7 +30,7 @@ static size_t gain_tile_lds(int32_t k, int T, bool p16)
 {
     size_t rows = (size_t)T * k * (p16 ? 2 : 4);
     if (rows < 4) rows = 4;
-    return rows + (size_t)(T + 1) * 4 + (size_t)T * 8 + 64;
+    return rows + (size_t)(T + 1) * 4 + (size_t)T * 8 + (size_t)T * 2 + 64;
 }
 
 // One workgroup per tile of T consecutive nodes: zero the T x k rows in
@@ -45,16 +45,21 @@ static size_t gain_tile_lds(int32_t k, int T, bool p16)
 // neighbouring half, the tile takes half the LDS and twice as many
 // workgroups stay resident per CU to hide the gathers' latency.
 // PB: bytes per entry of the partition view (1, 2 or 4).
+// inner (may be null): each non-hub node's own entry conn[v][own block] is
+// also written to inner[v] (own: the partition in node order), so that the
+// statistics pass need not gather it from the row.
 template <bool WEIGHTED, bool P16, int PB>
 __device__ __forceinline__ void gain_tile_body(const GraphView &g, int32_t k, int T,
                                                const PartView &part,
-                                               int32_t *__restrict__ conn, int64_t hub_t)
+                                               int32_t *__restrict__ conn, int64_t hub_t,
+                                               int32_t *__restrict__ inner, const PartView &own)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     int32_t *tile = (int32_t *)lds_raw;
     const size_t rows_bytes = ((size_t)T * k * (P16 ? 2 : 4) + 15) & ~(size_t)15;
     int32_t *vstart = (int32_t *)(lds_raw + rows_bytes);
     int64_t *gstart = (int64_t *)(lds_raw + rows_bytes + (((size_t)(T + 1) * 4 + 15) & ~(size_t)15));
+    int16_t *sown = (int16_t *)(gstart + T);  // own block of each node (with inner)
     __shared__ int32_t scan_lds[4];
 
     const int64_t v0 = (int64_t)blockIdx.x * T;
@@ -73,15 +78,18 @@ __device__ __forceinline__ void gain_tile_body(const GraphView &g, int32_t k, in
     }
 
     // virtual degrees (hubs contribute none) and their exclusive prefix,
-    // in chunks of kBlock nodes
+    // in chunks of kBlock nodes; with inner, each node's own block goes to
+    // LDS and a hub is marked by gstart = -1 (its edges are never visited)
     int32_t run = 0;
     for (int base = 0; base < nt; base += kBlock) {
         const int i = base + tid;
         int32_t vd = 0;
         if (i < nt) {
             const int64_t a = g.xadj[v0 + i], b = g.xadj[v0 + i + 1];
-            gstart[i] = a;
-            vd = (b - a) > hub_t ? 0 : (int32_t)(b - a);
+            const bool hub = (b - a) > hub_t;
+            gstart[i] = hub && inner ? -1 : a;
+            vd = hub ? 0 : (int32_t)(b - a);
+            if (inner) sown[i] = (int16_t)(pget(own, v0 + i) & part_mask(own));
         }
         int32_t total;
         const int32_t inc = block_incl_scan(vd, scan_lds, &total);
@@ -153,12 +161,21 @@ __device__ __forceinline__ void gain_tile_body(const GraphView &g, int32_t k, in
     } else {
         for (int64_t i = done + tid; i < total_ints; i += kBlock) dst[i] = tile[i];
     }
+    if (inner) {
+        for (int i = tid; i < nt; i += kBlock) {
+            const int32_t j = sown[i];
+            if (gstart[i] < 0 || (unsigned)j >= (unsigned)k) continue;  // a hub: its row comes later
+            const int idx = i * k + j;
+            inner[v0 + i] = P16 ? (int32_t)((const uint16_t *)tile)[idx] : tile[idx];
+        }
+    }
 }
 template <bool WEIGHTED, bool P16, int PB>
 __global__ __launch_bounds__(kBlock) void k_gain_tile(GraphView g, int32_t k, int T, PartView part,
-                                                       int32_t *__restrict__ conn, int64_t hub_t)
+                                                       int32_t *__restrict__ conn, int64_t hub_t,
+                                                       int32_t *__restrict__ inner, PartView own)
 {
-    gain_tile_body<WEIGHTED, P16, PB>(g, k, T, part, conn, hub_t);
+    gain_tile_body<WEIGHTED, P16, PB>(g, k, T, part, conn, hub_t, inner, own);
 }
 template <bool WEIGHTED, bool P16, int PB>
 __global__ __launch_bounds__(kBlock) void k_gain_refresh(GraphView g, int32_t k, int T,
@@ -169,11 +186,12 @@ __global__ __launch_bounds__(kBlock) void k_gain_refresh(GraphView g, int32_t k,
     if (!dirty[blockIdx.x]) return;
     __syncthreads();
     if (threadIdx.x == 0) dirty[blockIdx.x] = 0;
-    gain_tile_body<WEIGHTED, P16, PB>(g, k, T, part, conn, hub_t);
+    gain_tile_body<WEIGHTED, P16, PB>(g, k, T, part, conn, hub_t, nullptr, part);
 }
 
 hipError_t launch_gain_tile(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,
-                            int64_t hub_t, uint8_t *dirty, hipStream_t s)
+                            int64_t hub_t, uint8_t *dirty, hipStream_t s, int32_t *inner,
+                            const PartView &own)
 {
     if (g.n <= 0) return hipSuccess;
     const int T = gain_tile_nodes(k);
@@ -199,7 +217,7 @@ hipError_t launch_gain_tile(const GraphView &g, int32_t k, const PartView &part,
         }                                                                                           \
     } while (0)
     if (dirty) UPR_TILE_ALL(k_gain_refresh, , dirty);
-    else UPR_TILE_ALL(k_gain_tile, );
+    else UPR_TILE_ALL(k_gain_tile, , inner, own);
 #undef UPR_TILE_ALL
 #undef UPR_TILE_B
 #undef UPR_TILE

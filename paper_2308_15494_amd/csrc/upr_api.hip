@@ -61,6 +61,7 @@ struct upr_ctx {
     uint8_t *dirty = nullptr;    // [n] gain-table tiles to rebuild
     uint16_t *pc = nullptr;      // [n] compact copy of part for neighbour gathers
     uint16_t *pc2 = nullptr;     // [n] the same in the plan's label order (table build)
+    int32_t *inner = nullptr;    // [n] conn[v][part[v]] of non-hub nodes, from the table build
     // sequence-aware penalty
     int64_t *gp = nullptr;       // [n] pessimistic gains of candidates
     uint8_t *avail = nullptr;    // [n] available for rebalancing
@@ -206,6 +207,7 @@ void free_workspace(upr_ctx *c)
     dfree(c->dirty);
     dfree(c->pc);
     dfree(c->pc2);
+    dfree(c->inner);
     dfree(c->gp);
     dfree(c->avail);
     dfree(c->cand);
@@ -264,6 +266,7 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
               dalloc(&c->accflag, N) == hipSuccess && dalloc(&c->mvto, N) == hipSuccess &&
               dalloc(&c->dirty, N) == hipSuccess && dalloc(&c->gp, N) == hipSuccess &&
               dalloc(&c->pc, N) == hipSuccess && dalloc(&c->pc2, N) == hipSuccess &&
+              dalloc(&c->inner, N) == hipSuccess &&
               dalloc(&c->avail, N) == hipSuccess && dalloc(&c->cand, N) == hipSuccess &&
               dalloc(&c->ev_key, 2 * N) == hipSuccess &&
               dalloc(&c->ev_key2, 2 * N) == hipSuccess && dalloc(&c->ev_val, 2 * N) == hipSuccess &&
@@ -1064,7 +1067,7 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
         const GraphView tg = p->table_graph();
         {
             PhaseTimer t(c, 0, s);
-            HIP_TRY(c, launch_gain_tile(tg, k, tpv, conn, p->hub_t, nullptr, s));
+            HIP_TRY(c, launch_gain_tile(tg, k, tpv, conn, p->hub_t, nullptr, s, c->inner, pv));
         }
         if (p->nh > 0) {
             PhaseTimer t(c, 1, s);
@@ -1073,10 +1076,12 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
     }
     {
         PhaseTimer t(c, 1, s);
+        // the rebuilt table's own entries come from the tile build
         HIP_TRY(c, launch_node_stats(p->g, bk, sg, part, conn, p->wdeg, q->rebuild_table ? W : nullptr,
                                      moves ? c->bucket : nullptr, q->t_num, q->t_den, c->counters,
                                      CNT_CUT2_BEFORE, moves && q->seq_penalty ? c->avail : nullptr,
-                                     gstat, GS_CUT2_BEFORE, s));
+                                     gstat, GS_CUT2_BEFORE, s, q->rebuild_table ? c->inner : nullptr,
+                                     p->nh > 0 ? p->hub_bits : nullptr));
     }
     bool moved = false;
     if (moves) {

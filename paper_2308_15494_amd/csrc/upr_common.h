@@ -487,8 +487,11 @@ hipError_t launch_hub_ranges(const int64_t *xadj, const int32_t *ids, int32_t nh
 int gain_tile_nodes(int32_t k);
 // With dirty != null only tiles whose flag is set are rebuilt (flags are
 // cleared).
+// inner / own (full build only): each non-hub node's conn[v][own block] also
+// goes to inner[v]; own is the partition in node order.
 hipError_t launch_gain_tile(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,
-                            int64_t hub_t, uint8_t *dirty, hipStream_t s);
+                            int64_t hub_t, uint8_t *dirty, hipStream_t s,
+                            int32_t *inner = nullptr, const PartView &own = PartView{});
 // Hub rows, accumulated into rows that are zero. After an apply (counters
 // != null) only when that apply rebuilt the table (the moving nodes' degrees
 // above dirty_threshold); in the delta mode the rows are already up to date
@@ -524,13 +527,16 @@ struct StatsGeom {
     int64_t span = 0;
     int32_t window = 0;
 };
+// inner (may be null): conn[v][part[v]] of the non-hub nodes, written by the
+// table build; hub_bits marks the hubs, whose entry is gathered from the row.
 // Node range of the statistics pass for n nodes, at most max_span (> 0).
 int64_t stats_span(int64_t n, int64_t max_span);
 hipError_t launch_node_stats(const GraphView &g, const Blocks &bk, const StatsGeom &sg,
                              const int32_t *part, const int32_t *conn, const int32_t *wdeg,
                              int64_t *W, int64_t *bucket, int32_t t_num, int32_t t_den,
                              unsigned long long *counters, int cut_slot, uint8_t *avail,
-                             int64_t *gstat, int gs_slot, hipStream_t s);
+                             int64_t *gstat, int gs_slot, hipStream_t s,
+                             const int32_t *inner = nullptr, const uint32_t *hub_bits = nullptr);
 hipError_t launch_block_weights(const GraphView &g, int32_t k, const int32_t *part, int64_t *W,
                                 unsigned long long *counters, hipStream_t s);
 // 2 * cut from the adjacency into the spread counter `slot`; out = that / 2.
