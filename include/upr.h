@@ -127,7 +127,8 @@ int upr_plan_create(upr_ctx *ctx, const upr_graph *graph, upr_plan **out, hipStr
  * UPR_HUB_THRESHOLD / UPR_DIRTY_DIV if set, else 4096 / 8). Nodes of degree
  * above hub_threshold are hubs (split into edge chunks of whole workgroups);
  * the apply rebuilds table tiles instead of atomic deltas once the moving
- * nodes' degrees sum above nnz / dirty_div. low_threshold is ignored (the
+ * nodes' degrees sum above nnz / dirty_div (from twice that on, or above
+ * nnz / UPR_REBUILD_ALL_DIV when set, every tile without marking any). low_threshold is ignored (the
  * apply no longer splits nodes by degree; the field keeps the layout). They
  * change only the speed, never a result; paper_2308_15494_amd/tune.py picks
  * them by timing trial rounds. */

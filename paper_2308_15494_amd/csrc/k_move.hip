@@ -786,16 +786,18 @@ __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, Blocks bk, int32_
                                                    int32_t *mvto, int64_t hub_t,
                                                    const unsigned long long *counters,
                                                    int64_t dirty_threshold, uint8_t *dirty_flags,
-                                                   int T, void *pc2, const int32_t *perm)
+                                                   int T, void *pc2, const int32_t *perm,
+                                                   int64_t all_threshold)
 {
     __shared__ int32_t vstart[kApplyTile + 1];
     __shared__ int64_t estart[kApplyTile];
     __shared__ uint32_t sab[kApplyTile];  // local source | local target << 16
     __shared__ int32_t scan_lds[4];
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    uint8_t *dirty = (int64_t)wave_cnt_get(counters, CNT_MOVED_DEG) > dirty_threshold
-                         ? dirty_flags
-                         : (uint8_t *)nullptr;
+    const int64_t moved_deg = (int64_t)wave_cnt_get(counters, CNT_MOVED_DEG);
+    uint8_t *dirty = moved_deg > dirty_threshold ? dirty_flags : (uint8_t *)nullptr;
+    // above all_threshold every tile is rebuilt: no edge walk at all
+    const bool all = moved_deg > all_threshold;
     int64_t *wloc = (int64_t *)lds_raw;
     const int32_t K = bk.total();
     const bool use_lds = K <= 2048;
@@ -860,7 +862,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, Blocks bk, int32_
     __syncthreads();
 
     // the movers' edges, kEdgeUnroll per thread and step so that their loads overlap
-    const int32_t E = run;
+    const int32_t E = all ? 0 : run;
     const int32_t k = bk.k;
     for (int32_t p0 = threadIdx.x; p0 < E; p0 += kBlock * kEdgeUnroll) {
         // loads from clamped indices without a branch, so that they are in
@@ -913,18 +915,21 @@ __global__ __launch_bounds__(kBlock) void k_apply_hub(GraphView g, Blocks bk, co
                                                        int32_t *conn, const int32_t *mvto,
                                                        HubView h, const unsigned long long *counters,
                                                        int64_t dirty_threshold, uint8_t *dirty,
-                                                       int T)
+                                                       int T, int64_t all_threshold)
 {
     const HubChunk c = h.chunks[blockIdx.x];
     const int64_t v = h.ids[c.hub];
     const int32_t k = bk.k;
-    const bool rebuild = (int64_t)wave_cnt_get(counters, CNT_MOVED_DEG) > dirty_threshold;
+    const int64_t moved_deg = (int64_t)wave_cnt_get(counters, CNT_MOVED_DEG);
+    const bool rebuild = moved_deg > dirty_threshold;
     if (rebuild && c.e0 == g.xadj[v])
         for (int j = threadIdx.x; j < k; j += kBlock) conn[v * (int64_t)k + j] = 0;
     const int32_t B = mvto[v];
     if (B < 0) return;
     if (rebuild) {
-        for (int64_t e = c.e0 + threadIdx.x; e < c.e1; e += kBlock) mark_dirty(dirty, g.adjncy[e] / T);
+        if (moved_deg <= all_threshold)  // else every tile is rebuilt
+            for (int64_t e = c.e0 + threadIdx.x; e < c.e1; e += kBlock)
+                mark_dirty(dirty, g.adjncy[e] / T);
         return;
     }
     const int32_t a = bk.local(part[v]), b = bk.local(B);
@@ -940,7 +945,8 @@ hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, con
                         int32_t *conn, int64_t *W, int32_t *mvto, int64_t hub_t,
                         const HubView &h, const unsigned long long *counters,
                         int64_t dirty_threshold, uint8_t *dirty, const GraphView &tg,
-                        const PartView &tpv, void *pc2, const int32_t *perm, hipStream_t s)
+                        const PartView &tpv, void *pc2, const int32_t *perm,
+                        int64_t all_threshold, hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
     const int32_t k = bk.k;
@@ -949,15 +955,18 @@ hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, con
     hipError_t e;
     if (h.nh > 0) {
         hipLaunchKernelGGL(k_apply_hub, dim3((unsigned)h.nchunks), dim3(kBlock), 0, s, g, bk, part,
-                           conn, mvto, h, counters, dirty_threshold, dirty, T);
+                           conn, mvto, h, counters, dirty_threshold, dirty, T, all_threshold);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     const int64_t tiles = (g.n + kApplyTile - 1) / kApplyTile;
     hipLaunchKernelGGL(k_apply, dim3((unsigned)tiles), dim3(kBlock), lds, s, g, bk, part, pv, conn,
-                       W, mvto, hub_t, counters, dirty_threshold, dirty, T, pc2, perm);
+                       W, mvto, hub_t, counters, dirty_threshold, dirty, T, pc2, perm,
+                       all_threshold);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // rebuild the marked tiles and the hub rows (nothing in the delta mode)
-    if ((e = launch_gain_tile(tg, k, tpv, conn, hub_t, dirty, s)) != hipSuccess) return e;
+    if ((e = launch_gain_tile(tg, k, tpv, conn, hub_t, dirty, s, nullptr, PartView{}, counters,
+                              all_threshold)) != hipSuccess)
+        return e;
     return launch_gain_hub(tg, k, tpv, conn, h, s, counters, dirty_threshold);
 }
 

@@ -178,12 +178,18 @@ __global__ __launch_bounds__(kBlock) void k_gain_tile(GraphView g, int32_t k, in
     gain_tile_body<WEIGHTED, P16, PB>(g, k, T, part, conn, hub_t, inner, own);
 }
 template <bool WEIGHTED, bool P16, int PB>
+// Rebuilds the marked tiles, or every tile when the moving nodes' degrees
+// (counters[CNT_MOVED_DEG]) sum above all_threshold (the apply then marks
+// nothing: nearly every tile would be marked).
 __global__ __launch_bounds__(kBlock) void k_gain_refresh(GraphView g, int32_t k, int T,
                                                           PartView part,
                                                           int32_t *__restrict__ conn,
-                                                          int64_t hub_t, uint8_t *dirty)
+                                                          int64_t hub_t, uint8_t *dirty,
+                                                          const unsigned long long *counters,
+                                                          int64_t all_threshold)
 {
-    if (!dirty[blockIdx.x]) return;
+    const bool all = counters && (int64_t)wave_cnt_get(counters, CNT_MOVED_DEG) > all_threshold;
+    if (!all && !dirty[blockIdx.x]) return;  // uniform over the workgroup
     __syncthreads();
     if (threadIdx.x == 0) dirty[blockIdx.x] = 0;
     gain_tile_body<WEIGHTED, P16, PB>(g, k, T, part, conn, hub_t, nullptr, part);
@@ -191,7 +197,8 @@ __global__ __launch_bounds__(kBlock) void k_gain_refresh(GraphView g, int32_t k,
 
 hipError_t launch_gain_tile(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,
                             int64_t hub_t, uint8_t *dirty, hipStream_t s, int32_t *inner,
-                            const PartView &own)
+                            const PartView &own, const unsigned long long *counters,
+                            int64_t all_threshold)
 {
     if (g.n <= 0) return hipSuccess;
     const int T = gain_tile_nodes(k);
@@ -216,7 +223,7 @@ hipError_t launch_gain_tile(const GraphView &g, int32_t k, const PartView &part,
             else UPR_TILE_B(KERN, false, false, __VA_ARGS__);                                       \
         }                                                                                           \
     } while (0)
-    if (dirty) UPR_TILE_ALL(k_gain_refresh, , dirty);
+    if (dirty) UPR_TILE_ALL(k_gain_refresh, , dirty, counters, all_threshold);
     else UPR_TILE_ALL(k_gain_tile, , inner, own);
 #undef UPR_TILE_ALL
 #undef UPR_TILE_B

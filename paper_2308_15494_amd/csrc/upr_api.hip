@@ -118,6 +118,7 @@ struct upr_plan {
     uint32_t *hub_bits = nullptr;  // [ceil(n/32)]
     int64_t hub_t = kDefaultHubThreshold;
     int64_t dirty_threshold = 0;  // moved-degree sum above which tiles are rebuilt
+    int64_t all_threshold = 0;    // ... above which every tile is (nothing is marked)
     // neighbour ids renumbered by descending degree for the table build (null:
     // not built, the table build reads the graph as given)
     int32_t *adj_r = nullptr;  // [nnz] perm[adjncy[e]]
@@ -464,7 +465,7 @@ static hipError_t apply_moves(upr_ctx *c, const upr_plan *p, const Blocks &bk, i
 {
     return launch_apply(p->g, bk, part, pv, conn, W, c->mvto, p->hub_t, p->hubs(), c->counters,
                         p->dirty_threshold, c->dirty, p->table_graph(), table_part(c, p, pv),
-                        p->order ? (void *)c->pc2 : nullptr, p->perm, s);
+                        p->order ? (void *)c->pc2 : nullptr, p->perm, p->all_threshold, s);
 }
 
 // S5: the host loop over synchronous sub-iterations (one graph).
@@ -839,6 +840,10 @@ static int plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipSt
         // integer-atomic deltas cost about as much per moved edge as a
         // rebuild costs per edge of the whole graph divided by this factor
         p->dirty_threshold = p->nnz / std::max<int64_t>(dirty_div, 1);
+        // from twice that on, marking tiles is not worth its edge walk
+        // (UPR_REBUILD_ALL_DIV: from nnz / div on)
+        const int64_t all_div = env_int("UPR_REBUILD_ALL_DIV", 0);
+        p->all_threshold = all_div > 0 ? p->nnz / all_div : 2 * p->dirty_threshold;
         if (dalloc(&p->wdeg, g.n) != hipSuccess || dalloc(&hub_list, g.n) != hipSuccess)
             return bail(UPR_E_NOMEM, "plan allocation failed");
         unsigned long long zero[8] = {0}, res[8];

@@ -489,9 +489,13 @@ int gain_tile_nodes(int32_t k);
 // cleared).
 // inner / own (full build only): each non-hub node's conn[v][own block] also
 // goes to inner[v]; own is the partition in node order.
+// With dirty: counters / all_threshold make every tile rebuild once the
+// moving nodes' degrees sum above all_threshold.
 hipError_t launch_gain_tile(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,
                             int64_t hub_t, uint8_t *dirty, hipStream_t s,
-                            int32_t *inner = nullptr, const PartView &own = PartView{});
+                            int32_t *inner = nullptr, const PartView &own = PartView{},
+                            const unsigned long long *counters = nullptr,
+                            int64_t all_threshold = 0);
 // Hub rows, accumulated into rows that are zero. After an apply (counters
 // != null) only when that apply rebuilt the table (the moving nodes' degrees
 // above dirty_threshold); in the delta mode the rows are already up to date
@@ -637,7 +641,8 @@ hipError_t launch_seq_segments(const GraphView &g, const Blocks &bk, const int64
 // If the moving nodes' degrees sum to at most dirty_threshold
 // (counters[CNT_MOVED_DEG]) the neighbours' rows get integer-atomic deltas;
 // otherwise their gain-table tiles are marked and rebuilt from the new
-// partition, and the hub rows are rebuilt.
+// partition, and the hub rows are rebuilt; above all_threshold no tile is
+// marked and every tile is rebuilt.
 // pv: the compact partition copy to keep in step (pv.p writable, or bytes 4).
 // tg / tpv: the graph and partition views the table build reads (the
 // relabelled ones when the plan has them); pc2 / perm (may be null): the
@@ -646,7 +651,8 @@ hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, con
                         int32_t *conn, int64_t *W, int32_t *mvto, int64_t hub_t,
                         const HubView &h, const unsigned long long *counters,
                         int64_t dirty_threshold, uint8_t *dirty, const GraphView &tg,
-                        const PartView &tpv, void *pc2, const int32_t *perm, hipStream_t s);
+                        const PartView &tpv, void *pc2, const int32_t *perm,
+                        int64_t all_threshold, hipStream_t s);
 hipError_t launch_stats_final(int64_t *stats, const unsigned long long *counters, int64_t lmax,
                               int64_t iters, int64_t status, hipStream_t s);
 hipError_t launch_export_moves(int64_t n, const int64_t *key, const int64_t *pen,

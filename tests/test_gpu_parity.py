@@ -483,11 +483,14 @@ def test_rmat20_full_rounds(upr, ctx):
         pr.compare(ost, odbg, f"rmat20 round {r}")
 
 
-@pytest.mark.parametrize("div", ["1", "100000000"], ids=["delta", "rebuild"])
-def test_apply_modes(upr, ctx, monkeypatch, div):
-    """Both ways of updating the table after moves (integer-atomic deltas, or
-    marking and rebuilding tiles) give the oracle's table."""
+@pytest.mark.parametrize("div,all_div", [("1", "0"), ("100000000", "1"), ("100000000", "0")],
+                         ids=["delta", "rebuild_marked", "rebuild_all"])
+def test_apply_modes(upr, ctx, monkeypatch, div, all_div):
+    """The ways of updating the table after moves (integer-atomic deltas,
+    marking and rebuilding the tiles of the movers' neighbours, or rebuilding
+    every tile) give the oracle's table."""
     monkeypatch.setenv("UPR_DIRTY_DIV", div)
+    monkeypatch.setenv("UPR_REBUILD_ALL_DIV", all_div)
     monkeypatch.setenv("UPR_HUB_THRESHOLD", "64")
     for name, g, k in [("rmat", gg.rmat(12, 16, seed=31), 32),
                        ("cl_w", gg.with_weights(gg.chung_lu(4000, 8.0, 2.1, seed=5), 5, 6, 3), 8),
