@@ -124,7 +124,7 @@ const char *upr_last_error(const upr_ctx *ctx);
 int upr_plan_create(upr_ctx *ctx, const upr_graph *graph, upr_plan **out, hipStream_t stream);
 
 /* Traversal thresholds of a plan (0 = default: the environment variables
- * UPR_HUB_THRESHOLD / UPR_DIRTY_DIV if set, else 4096 / 8). Nodes of degree
+ * UPR_HUB_THRESHOLD / UPR_DIRTY_DIV if set, else 4096 / 16). Nodes of degree
  * above hub_threshold are hubs (split into edge chunks of whole workgroups);
  * the apply rebuilds table tiles instead of atomic deltas once the moving
  * nodes' degrees sum above nnz / dirty_div (from twice that on, or above

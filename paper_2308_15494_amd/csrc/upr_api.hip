@@ -824,7 +824,7 @@ static int plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipSt
     // thresholds: the options, else the environment, else the defaults
     p->hub_t = opts && opts->hub_threshold > 0 ? opts->hub_threshold
                                                : env_int("UPR_HUB_THRESHOLD", kDefaultHubThreshold);
-    const int64_t dirty_div = opts && opts->dirty_div > 0 ? opts->dirty_div : env_int("UPR_DIRTY_DIV", 8);
+    const int64_t dirty_div = opts && opts->dirty_div > 0 ? opts->dirty_div : env_int("UPR_DIRTY_DIV", 16);
     // a tile's edge count (nodes per tile x hub threshold) must fit int32
     p->hub_t = std::min<int64_t>(std::max<int64_t>(p->hub_t, 1), (int64_t)1 << 20);
     int32_t *hub_list = nullptr;

@@ -94,7 +94,7 @@ def tune_batch(ctx, graphs, k, parts, eps=(3, 100), rounds=3, repeats=2, total_r
 
 
 def _coordinate_search(runner_for, rounds, repeats):
-    cur = dict(hub_threshold=4096, dirty_div=8)
+    cur = dict(hub_threshold=4096, dirty_div=16)
     report = []
     ref = None
     best_t = None
