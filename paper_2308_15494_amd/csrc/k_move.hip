@@ -470,11 +470,12 @@ __device__ __forceinline__ int64_t pessimistic_part(const GraphView &g, const Pa
 // Candidates of degree up to the hub threshold, one workgroup per tile of
 // kFilterTile consecutive nodes. The tile's candidate edges are spread over
 // all threads (edge -> node by a binary search over the tile's degree
-// prefix), kEdgeUnroll edges per thread and step so that their loads overlap;
+// prefix), kFilterUnroll edges per thread and step so that their loads overlap;
 // each edge adds its term w * f to the node's 32-bit LDS sum (a node's sum is
 // bounded by its weighted degree, below 2^31). One LDS atomic per edge was
 // faster than a segmented wave scan over the runs of equal nodes.
 constexpr int kFilterTile = 512;
+constexpr int kFilterUnroll = 8;  // edges per thread and step (8 measured best of 2, 4, 8)
 
 template <int PB>
 __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int optimistic,
@@ -536,38 +537,38 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int o
     // node's own key), so the loads of all slots are in flight together.
     const int32_t E = run;
     const int32_t pmask = part_mask(pv);
-    for (int32_t q0 = tid; q0 < E; q0 += kBlock * kEdgeUnroll) {
-        bool ok[kEdgeUnroll];
-        int node[kEdgeUnroll];
-        int64_t e[kEdgeUnroll];
+    for (int32_t q0 = tid; q0 < E; q0 += kBlock * kFilterUnroll) {
+        bool ok[kFilterUnroll];
+        int node[kFilterUnroll];
+        int64_t e[kFilterUnroll];
 #pragma unroll
-        for (int i = 0; i < kEdgeUnroll; ++i) {
+        for (int i = 0; i < kFilterUnroll; ++i) {
             const int32_t p = q0 + i * kBlock;
             ok[i] = p < E;
             const int32_t pc = ok[i] ? p : E - 1;
             node[i] = upper_index(vstart, nt, pc);
             e[i] = estart[node[i]] + (pc - vstart[node[i]]);
         }
-        int32_t u[kEdgeUnroll], w[kEdgeUnroll];
+        int32_t u[kFilterUnroll], w[kFilterUnroll];
 #pragma unroll
-        for (int i = 0; i < kEdgeUnroll; ++i) {
+        for (int i = 0; i < kFilterUnroll; ++i) {
             u[i] = stream_load(g.adjncy + e[i]);
             w[i] = stream_edge_weight(g, e[i]);
         }
-        int32_t raw[kEdgeUnroll];
+        int32_t raw[kFilterUnroll];
 #pragma unroll
-        for (int i = 0; i < kEdgeUnroll; ++i) raw[i] = pget_w<PB>(pv.p, u[i], -1);
+        for (int i = 0; i < kFilterUnroll; ++i) raw[i] = pget_w<PB>(pv.p, u[i], -1);
         // a neighbour's key only if it is a candidate (flag bit of the
         // compact copy; without flags every neighbour's key)
-        int64_t kraw[kEdgeUnroll];
-        bool cand[kEdgeUnroll];
+        int64_t kraw[kFilterUnroll];
+        bool cand[kFilterUnroll];
 #pragma unroll
-        for (int i = 0; i < kEdgeUnroll; ++i) {
+        for (int i = 0; i < kFilterUnroll; ++i) {
             cand[i] = !pv.flagged || (raw[i] & kCandFlag);
             kraw[i] = key[cand[i] ? (int64_t)u[i] : v0 + node[i]];
         }
 #pragma unroll
-        for (int i = 0; i < kEdgeUnroll; ++i) {
+        for (int i = 0; i < kFilterUnroll; ++i) {
             if (!ok[i]) continue;
             const int nd = node[i];
             const int32_t pu = raw[i] & pmask;
