@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_best_move(
     const int64_t *__restrict__ W, const int64_t *__restrict__ cb,
     const int64_t *__restrict__ pen1, int mode, const uint8_t *__restrict__ active,
     int64_t *__restrict__ key, int64_t *__restrict__ pen, unsigned long long *counters,
-    uint8_t *cflag)
+    uint8_t *cflag, uint8_t *cflag2, int64_t *key2, const int32_t *perm)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int32_t k = bk.k;
@@ -208,6 +208,11 @@ __global__ __launch_bounds__(kBlock) void k_best_move(
                 key[v] = (sc << 16) | j;
                 pen[v] = bestP;
                 if (cflag) cflag[v] = (uint8_t)(bk.local(A) | kCandFlag);
+                if (cflag2) {  // the same in the plan's label order
+                    const int32_t lv = perm[v];
+                    cflag2[lv] = (uint8_t)(bk.local(A) | kCandFlag);
+                    key2[lv] = (sc << 16) | j;
+                }
                 atomicAdd(&cand_lds, 1ull);
             } else {
                 key[v] = -1;
@@ -229,7 +234,7 @@ __global__ __launch_bounds__(kBlock) void k_best_move_reg(
     const int64_t *__restrict__ W, const int64_t *__restrict__ cb,
     const int64_t *__restrict__ pen1, int mode, const uint8_t *__restrict__ active,
     int64_t *__restrict__ key, int64_t *__restrict__ pen, unsigned long long *counters,
-    uint8_t *cflag)
+    uint8_t *cflag, uint8_t *cflag2, int64_t *key2, const int32_t *perm)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int32_t k = bk.k;
@@ -350,6 +355,11 @@ __global__ __launch_bounds__(kBlock) void k_best_move_reg(
                     key[v] = (sc << 16) | j;
                     pen[v] = bestP;
                     if (cflag) cflag[v] = (uint8_t)(a | kCandFlag);
+                    if (cflag2) {  // the same in the plan's label order
+                        const int32_t lv = perm[v];
+                        cflag2[lv] = (uint8_t)(a | kCandFlag);
+                        key2[lv] = (sc << 16) | j;
+                    }
                     atomicAdd(&cand_lds, 1ull);
                 } else {
                     key[v] = -1;
@@ -365,7 +375,7 @@ hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t 
                             const int32_t *conn, const int64_t *W, const int64_t *cb,
                             const int64_t *pen1, int mode, const uint8_t *active, int64_t *key,
                             int64_t *pen, unsigned long long *counters, uint8_t *cflag,
-                            hipStream_t s)
+                            hipStream_t s, uint8_t *cflag2, int64_t *key2, const int32_t *perm)
 {
     if (g.n <= 0) return hipSuccess;
     const int32_t k = bk.k;
@@ -376,7 +386,8 @@ hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t 
 #define UPR_BR(GG, RR, UU)                                                                          \
     hipLaunchKernelGGL((k_best_move_reg<GG, RR, UU>),                                               \
                        dim3(grid_cap((g.n + UU - 1) / UU, kBlock / GG, 8192)), dim3(kBlock), lds, s, \
-                       g, bk, part, conn, W, cb, pen1, mode, active, key, pen, counters, cflag)
+                       g, bk, part, conn, W, cb, pen1, mode, active, key, pen, counters, cflag,  \
+                       cflag2, key2, perm)
         // each lane holds up to four int4 of the row: fewer lanes per node
         // mean fewer shuffle rounds per scored entry (at k = 64, 4 lanes per
         // node took 80 us where 16 lanes took 102)
@@ -395,7 +406,7 @@ hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t 
 #define UPR_BM(GG, VV)                                                                             \
     hipLaunchKernelGGL((k_best_move<GG, VV>), dim3(grid_cap(g.n, kBlock / GG, 8192)), dim3(kBlock), \
                        lds, s, g, bk, part, conn, W, cb, pen1, mode, active, key, pen, counters, \
-                       cflag)
+                       cflag, cflag2, key2, perm)
     if (vec) {
         if (nvec <= 1) UPR_BM(1, 4);
         else if (nvec <= 2) UPR_BM(2, 4);
@@ -477,13 +488,18 @@ __device__ __forceinline__ int64_t pessimistic_part(const GraphView &g, const Pa
 constexpr int kFilterTile = 512;
 constexpr int kFilterUnroll = 8;  // edges per thread and step (8 measured best of 2, 4, 8)
 
-template <int PB>
+// RL: a neighbour's block and key are read by its label (adj_r[e]) from the
+// copies in the plan's degree order (pv2 with candidate flags, key2), where
+// the high-degree nodes share cache lines; its id (ties) still from adjncy.
+template <int PB, bool RL>
 __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int optimistic,
                                                     const int32_t *__restrict__ part,
                                                     PartView pv, const int64_t *__restrict__ key,
                                                     const int64_t *__restrict__ pen, int64_t hub_t,
                                                     int32_t *mvto, uint8_t *accflag,
-                                                    unsigned long long *counters, int64_t *gp_out)
+                                                    unsigned long long *counters, int64_t *gp_out,
+                                                    const int32_t *__restrict__ adj_r, PartView pv2,
+                                                    const int64_t *__restrict__ key2)
 {
     __shared__ int32_t vstart[kFilterTile + 1];
     __shared__ int64_t estart[kFilterTile];
@@ -533,8 +549,8 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int o
     // neighbour u ((score, id) before v) counts in the worse of its current
     // and its target block (optimistic variant: its target block). Every
     // load is issued unconditionally (a slot past the last edge rereads that
-    // edge and adds nothing; a neighbour that is no candidate rereads the
-    // node's own key), so the loads of all slots are in flight together.
+    // edge and adds nothing), so the loads of all slots are in flight
+    // together.
     const int32_t E = run;
     const int32_t pmask = part_mask(pv);
     for (int32_t q0 = tid; q0 < E; q0 += kBlock * kFilterUnroll) {
@@ -549,15 +565,17 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int o
             node[i] = upper_index(vstart, nt, pc);
             e[i] = estart[node[i]] + (pc - vstart[node[i]]);
         }
-        int32_t u[kFilterUnroll], w[kFilterUnroll];
+        int32_t u[kFilterUnroll], w[kFilterUnroll], ur[kFilterUnroll];
 #pragma unroll
         for (int i = 0; i < kFilterUnroll; ++i) {
             u[i] = stream_load(g.adjncy + e[i]);
             w[i] = stream_edge_weight(g, e[i]);
+            if constexpr (RL) ur[i] = stream_load(adj_r + e[i]);
         }
         int32_t raw[kFilterUnroll];
 #pragma unroll
-        for (int i = 0; i < kFilterUnroll; ++i) raw[i] = pget_w<PB>(pv.p, u[i], -1);
+        for (int i = 0; i < kFilterUnroll; ++i)
+            raw[i] = RL ? pget_w<PB>(pv2.p, ur[i], -1) : pget_w<PB>(pv.p, u[i], -1);
         // a neighbour's key only if it is a candidate (flag bit of the
         // compact copy; without flags every neighbour's key)
         int64_t kraw[kFilterUnroll];
@@ -565,7 +583,10 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int o
 #pragma unroll
         for (int i = 0; i < kFilterUnroll; ++i) {
             cand[i] = !pv.flagged || (raw[i] & kCandFlag);
-            kraw[i] = key[cand[i] ? (int64_t)u[i] : v0 + node[i]];
+            // (a neighbour that is no candidate takes the node's own key from
+            // LDS: unused, and no load in a branch)
+            if constexpr (RL) kraw[i] = cand[i] ? key2[ur[i]] : skey[node[i]];
+            else kraw[i] = cand[i] ? key[u[i]] : skey[node[i]];
         }
 #pragma unroll
         for (int i = 0; i < kFilterUnroll; ++i) {
@@ -621,16 +642,19 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int o
 hipError_t launch_filter(const GraphView &g, const Blocks &bk, int optimistic, const int32_t *part,
                          const PartView &pv, const int64_t *key, const int64_t *pen, int64_t hub_t,
                          int32_t *mvto, uint8_t *accflag, unsigned long long *counters,
-                         int64_t *gp_out, hipStream_t s)
+                         int64_t *gp_out, hipStream_t s, const int32_t *adj_r, const PartView &pv2,
+                         const int64_t *key2)
 {
     if (g.n <= 0) return hipSuccess;
     const int64_t tiles = (g.n + kFilterTile - 1) / kFilterTile;
-#define UPR_FI(BB)                                                                                 \
-    hipLaunchKernelGGL(k_filter<BB>, dim3((unsigned)tiles), dim3(kBlock), 0, s, g, bk, optimistic,   \
-                       part, pv, key, pen, hub_t, mvto, accflag, counters, gp_out)
-    if (pv.bytes == 1) UPR_FI(1);
-    else if (pv.bytes == 2) UPR_FI(2);
-    else UPR_FI(4);
+#define UPR_FI(BB, RR)                                                                             \
+    hipLaunchKernelGGL((k_filter<BB, RR>), dim3((unsigned)tiles), dim3(kBlock), 0, s, g, bk,         \
+                       optimistic, part, pv, key, pen, hub_t, mvto, accflag, counters, gp_out,     \
+                       adj_r, pv2, key2)
+    if (adj_r && pv2.p && key2 && pv.bytes == 1 && pv.flagged) UPR_FI(1, true);
+    else if (pv.bytes == 1) UPR_FI(1, false);
+    else if (pv.bytes == 2) UPR_FI(2, false);
+    else UPR_FI(4, false);
 #undef UPR_FI
     return hipGetLastError();
 }

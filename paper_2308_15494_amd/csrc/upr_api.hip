@@ -56,6 +56,7 @@ struct upr_ctx {
     // workspace
     int64_t cap_n = 0, cap_k = 0;
     int64_t *key = nullptr, *pen = nullptr;
+    int64_t *key2 = nullptr;  // [n] the candidates' keys in the plan's label order
     uint8_t *accflag = nullptr;
     int32_t *mvto = nullptr;     // [n] pending move target, -1 = none
     uint8_t *dirty = nullptr;    // [n] gain-table tiles to rebuild
@@ -202,6 +203,7 @@ void dfree(T *&p)
 void free_workspace(upr_ctx *c)
 {
     dfree(c->key);
+    dfree(c->key2);
     dfree(c->pen);
     dfree(c->accflag);
     dfree(c->mvto);
@@ -264,6 +266,7 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
     free_workspace(c);
     const int64_t NB = seq_bucket_bound(N, (int)K);
     bool ok = dalloc(&c->key, N) == hipSuccess && dalloc(&c->pen, N) == hipSuccess &&
+              dalloc(&c->key2, N) == hipSuccess &&
               dalloc(&c->accflag, N) == hipSuccess && dalloc(&c->mvto, N) == hipSuccess &&
               dalloc(&c->dirty, N) == hipSuccess && dalloc(&c->gp, N) == hipSuccess &&
               dalloc(&c->pc, N) == hipSuccess && dalloc(&c->pc2, N) == hipSuccess &&
@@ -455,7 +458,7 @@ int hist32_ok(const upr_plan *p)
 // plan has relabelled its adjacency, else pv itself.
 static PartView table_part(const upr_ctx *c, const upr_plan *p, const PartView &pv)
 {
-    return p->order ? PartView{c->pc2, pv.bytes, 0} : pv;
+    return p->order ? PartView{c->pc2, pv.bytes, pv.flagged} : pv;
 }
 
 // S4 for the moves marked in mvto; rebuilt tiles and hub rows are built from
@@ -1093,9 +1096,13 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
         {
             PhaseTimer t(c, 2, s);
             HIP_TRY(c, launch_cb_prefix(bk, c->bucket, W, q->mode, c->pen1, s));
+            // with the degree order, the flags and keys also in label order
+            const bool rl = pv.flagged && pv.bytes == 1 && p->order;
             HIP_TRY(c, launch_best_move(p->g, bk, part, conn, W, c->bucket, c->pen1, q->mode,
                                         active, c->key, c->pen, c->counters,
-                                        pv.flagged ? (uint8_t *)c->pc : nullptr, s));
+                                        pv.flagged ? (uint8_t *)c->pc : nullptr, s,
+                                        rl ? (uint8_t *)c->pc2 : nullptr, rl ? c->key2 : nullptr,
+                                        p->perm));
         }
         // no host decision here: with no candidates the filter and the apply
         // find nothing to do; a bad part value is reported at the next
@@ -1104,8 +1111,11 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
         {
             PhaseTimer t(c, 3, s);
             int64_t *gp_out = q->seq_penalty ? c->gp : nullptr;
+            const bool rl = pv.flagged && pv.bytes == 1 && p->order;
             HIP_TRY(c, launch_filter(p->g, bk, optimistic, part, pv, c->key, c->pen, p->hub_t,
-                                     c->mvto, c->accflag, c->counters, gp_out, s));
+                                     c->mvto, c->accflag, c->counters, gp_out, s,
+                                     rl ? p->adj_r : nullptr, rl ? tpv : PartView{},
+                                     rl ? c->key2 : nullptr));
             HIP_TRY(c, launch_filter_hub(p->g, bk, optimistic, part, pv, c->key, c->pen, h,
                                          c->mvto, c->accflag, c->counters, gp_out, s));
             if (q->seq_penalty) {

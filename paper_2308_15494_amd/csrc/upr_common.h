@@ -565,19 +565,25 @@ hipError_t launch_round_init(const Blocks &bk, int64_t *bucket, int64_t *W, cons
 hipError_t launch_cb_prefix(const Blocks &bk, int64_t *bucket, const int64_t *W, int mode,
                             int64_t *pen1, hipStream_t s);
 // active (may be null: every node): only nodes with active[v] != 0 look for
-// a move.
+// a move. cflag (may be null): the compact partition copy whose bit 7 marks
+// the candidates; cflag2 / key2 / perm (may be null): the flagged copy and
+// the candidates' keys in the plan's label order.
 hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t *part,
                             const int32_t *conn, const int64_t *W, const int64_t *cb,
                             const int64_t *pen1, int mode, const uint8_t *active, int64_t *key,
                             int64_t *pen, unsigned long long *counters, uint8_t *cflag,
-                            hipStream_t s);
+                            hipStream_t s, uint8_t *cflag2 = nullptr, int64_t *key2 = nullptr,
+                            const int32_t *perm = nullptr);
 // With gp_out the pessimistic gains are stored (decided by launch_filter_seq).
+// adj_r / pv2 / key2 (may be null; one-byte flagged pv only): neighbours'
+// blocks and keys read by label from the copies in the plan's degree order.
 // optimistic: an earlier candidate neighbour counts in its target block.
 hipError_t launch_filter(const GraphView &g, const Blocks &bk, int optimistic, const int32_t *part,
                          const PartView &pv,
                          const int64_t *key, const int64_t *pen, int64_t hub_t,
                          int32_t *mvto, uint8_t *accflag, unsigned long long *counters,
-                         int64_t *gp_out, hipStream_t s);
+                         int64_t *gp_out, hipStream_t s, const int32_t *adj_r = nullptr,
+                         const PartView &pv2 = PartView{}, const int64_t *key2 = nullptr);
 hipError_t launch_filter_hub(const GraphView &g, const Blocks &bk, int optimistic,
                              const int32_t *part, const PartView &pv,
                              const int64_t *key, const int64_t *pen, const HubView &h,
