@@ -1,13 +1,13 @@
 // Move phase of one round: penalty prefix sums, penalised best move,
 // conflict filter and scatter-apply.
 //
-// Every per-node kernel scans node ids in wave-sized runs of 64 (coalesced
-// reads of the per-node arrays). Nodes that need work are compacted inside
-// the wave (ballot, then each lane group picks the n-th set bit) and handled
-// by lane groups sized to their degree class: 8 lanes for low-degree nodes,
-// the whole wave for mid-degree nodes; hubs are split into edge chunks
-// processed by whole workgroups. Counters are summed per workgroup in LDS and
-// added to global memory once per workgroup.
+// Best move gives each node a lane group that holds its table row in
+// registers. The filter and the apply take tiles of consecutive nodes and
+// spread the tile's edges (of candidates, of movers) over all threads of the
+// workgroup; hubs are split into edge chunks processed by whole workgroups.
+// Loads meant to be in flight together are issued without branches.
+// Counters are summed per workgroup in LDS and added to global memory once
+// per workgroup.
 #include "upr_common.h"
 
 namespace upr {

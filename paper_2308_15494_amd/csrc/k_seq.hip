@@ -363,26 +363,34 @@ __host__ __device__ __forceinline__ int64_t seg_slot(int B, int c, int C)
 // kNodeUnroll, below hi): inflow block T and own block A (global ids), or
 // T = -1. The loads of the nodes are issued together.
 __device__ __forceinline__ void seg_event_blocks(const int64_t *key, const int64_t *gp,
-                                                 const int32_t *part, const Blocks &bk, int K,
-                                                 int64_t v0, int64_t hi, int64_t (&kv)[kNodeUnroll],
+                                                 const int32_t *part, const uint8_t *avail,
+                                                 const Blocks &bk, int K, int64_t v0, int64_t hi,
+                                                 int64_t (&kv)[kNodeUnroll],
                                                  int32_t (&A)[kNodeUnroll],
-                                                 int32_t (&T)[kNodeUnroll])
+                                                 int32_t (&T)[kNodeUnroll],
+                                                 bool (&out)[kNodeUnroll])
 {
+    // every load from a clamped index and without a branch (gp and part of a
+    // node that is no candidate are read and unused), so that all are in
+    // flight together
     int64_t g4[kNodeUnroll];
+    int32_t a4[kNodeUnroll];
 #pragma unroll
     for (int u = 0; u < kNodeUnroll; ++u) {
         const int64_t v = v0 + (int64_t)u * kBlock;
-        kv[u] = v < hi ? key[v] : -1;
+        const int64_t vc = v < hi ? v : hi - 1;
+        kv[u] = key[vc];
+        g4[u] = gp[vc];
+        a4[u] = part[vc];
+        out[u] = avail[vc] == 0;  // an outflow event too (source not in V_r)
+        if (v >= hi) kv[u] = -1;
     }
-#pragma unroll
-    for (int u = 0; u < kNodeUnroll; ++u)
-        g4[u] = kv[u] >= 0 ? gp[v0 + (int64_t)u * kBlock] : 0;
 #pragma unroll
     for (int u = 0; u < kNodeUnroll; ++u) {
         T[u] = -1;
         A[u] = -1;
         if (kv[u] >= 0 && g4[u] > 0) {
-            const int32_t a = part[v0 + (int64_t)u * kBlock];
+            const int32_t a = a4[u];
             if ((unsigned)a < (unsigned)K) {
                 const int32_t t = bk.base(a) + (int32_t)(kv[u] & 0xFFFF);
                 if ((unsigned)t < (unsigned)K) {
@@ -433,15 +441,15 @@ __global__ __launch_bounds__(kBlock) void k_seg_count(int64_t n, int64_t span,
     for (int64_t v0 = lo + threadIdx.x; v0 < hi; v0 += (int64_t)kNodeUnroll * kBlock) {
         int64_t kv[kNodeUnroll];
         int32_t A[kNodeUnroll], T[kNodeUnroll];
-        seg_event_blocks(key, gp, part, bk, K, v0, hi, kv, A, T);
+        bool out[kNodeUnroll];
+        seg_event_blocks(key, gp, part, avail, bk, K, v0, hi, kv, A, T, out);
 #pragma unroll
         for (int u = 0; u < kNodeUnroll; ++u) {
             if (T[u] < 0) continue;
-            const bool out = avail[v0 + (int64_t)u * kBlock] == 0;
             const uint32_t xt = (uint32_t)(T[u] - B0), xa = (uint32_t)(A[u] - B0);
             if (lds && xt < (uint32_t)nb) atomicAdd(&h[xt], 1u);
             else atomicAdd(&cnt[seg_slot(T[u], copy, C)], 1ull);
-            if (out) {
+            if (out[u]) {
                 if (lds && xa < (uint32_t)nb) atomicAdd(&h[xa], 1u);
                 else atomicAdd(&cnt[seg_slot(A[u], copy, C)], 1ull);
             }
@@ -606,13 +614,14 @@ __global__ __launch_bounds__(kBlock) void k_seg_place(int64_t n, int64_t span,
         for (int64_t v0 = lo + threadIdx.x; v0 < hi; v0 += (int64_t)kNodeUnroll * kBlock) {
             int64_t kv[kNodeUnroll];
             int32_t A[kNodeUnroll], T[kNodeUnroll];
-            seg_event_blocks(key, gp, part, bk, K, v0, hi, kv, A, T);
+            bool out[kNodeUnroll];
+            seg_event_blocks(key, gp, part, avail, bk, K, v0, hi, kv, A, T, out);
 #pragma unroll
             for (int u = 0; u < kNodeUnroll; ++u) {
                 if (T[u] < 0) continue;
                 const uint32_t xt = (uint32_t)(T[u] - B0), xa = (uint32_t)(A[u] - B0);
                 if (xt < (uint32_t)nb) atomicAdd(&h[xt], 1u);
-                if (avail[v0 + (int64_t)u * kBlock] == 0 && xa < (uint32_t)nb) atomicAdd(&h[xa], 1u);
+                if (out[u] && xa < (uint32_t)nb) atomicAdd(&h[xa], 1u);
             }
         }
         __syncthreads();
@@ -626,7 +635,8 @@ __global__ __launch_bounds__(kBlock) void k_seg_place(int64_t n, int64_t span,
     for (int64_t v0 = lo + threadIdx.x; v0 < hi; v0 += (int64_t)kNodeUnroll * kBlock) {
         int64_t kv[kNodeUnroll];
         int32_t A[kNodeUnroll], T[kNodeUnroll];
-        seg_event_blocks(key, gp, part, bk, K, v0, hi, kv, A, T);
+        bool out[kNodeUnroll];
+        seg_event_blocks(key, gp, part, avail, bk, K, v0, hi, kv, A, T, out);
 #pragma unroll
         for (int u = 0; u < kNodeUnroll; ++u) {
             if (T[u] < 0) continue;
@@ -638,7 +648,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_place(int64_t n, int64_t span,
                                     ? (uint64_t)atomicAdd(&h[xt], 1u)
                                     : atomicAdd(&ws.cur[seg_slot(T[u], copy, C)], 1ull);
             ws.ev[pt] = kin;
-            if (avail[v] == 0) {
+            if (out[u]) {
                 const uint64_t pa = (lds && xa < (uint32_t)nb)
                                         ? (uint64_t)atomicAdd(&h[xa], 1u)
                                         : atomicAdd(&ws.cur[seg_slot(A[u], copy, C)], 1ull);

@@ -14,17 +14,12 @@ constexpr int64_t kPenCap = int64_t(1) << 62;
 
 // Device counters (unsigned long long slots of ws.counters).
 enum Counter {
-    CNT_CL_LOW = 0,    // low-degree candidate list length
-    CNT_CL_MID,        // mid-degree candidate list length
-    CNT_MV_LOW,        // low-degree move list length
-    CNT_MV_MID,        // mid-degree move list length
-    CNT_CAND,          // candidates (all classes)
+    CNT_CAND = 0,      // candidates
     CNT_ACC,           // accepted moves
     CNT_CUT2_BEFORE,   // 2 * cut before
     CNT_CUT2_MOVES,    // 2 * cut after the filtered moves
     CNT_CUT2_AFTER,    // 2 * cut after rebalancing
     CNT_REBAL_MOVES,   // moves made by rebalancing
-    CNT_OLIST,         // nodes of overloaded blocks with a valid target
     CNT_MOVED_NOW,     // moves of the current rebalancing sub-iteration
     CNT_OVER,          // number of overloaded blocks
     CNT_BAD_INPUT,     // nonzero: a part value was out of range
