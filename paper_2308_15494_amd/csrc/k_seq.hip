@@ -725,7 +725,8 @@ __global__ __launch_bounds__(kBlock) void k_seg_bucket(GraphView g, int K, SegWs
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int64_t p = lo + threadIdx.x + (int64_t)u * kBlock;
-        key[u] = p < m ? ws.ev[s0 + p] : ~0ull;
+        const uint64_t x = ws.ev[s0 + (p < m ? p : m - 1)];  // clamped: no load in a branch
+        key[u] = p < m ? x : ~0ull;
     }
     __syncthreads();
     const uint64_t idmask = ((uint64_t)1 << idb) - 1;
@@ -858,23 +859,34 @@ __device__ __forceinline__ void seg_scan_decide(const uint64_t (&k)[IPT], int64_
                                                 int64_t *scan_lds, unsigned long long *acc_lds,
                                                 unsigned long long *deg_lds)
 {
-    int64_t w[IPT];
+    // the events' node weights and the inflow events' pessimistic gains,
+    // loaded together (node 0 stands in for the slots past the bucket's end,
+    // whose keys hold no node id)
+    int64_t w[IPT], gv[IPT], cw[IPT];
+    int64_t vs[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; ++j) vs[j] = pos0 + j < m ? (int64_t)((k[j] >> 1) & d.idmask) : 0;
+    if (d.g.vwgt) {  // uniform: the two forms keep their loads together
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            gv[j] = d.gp[vs[j]];
+            cw[j] = d.g.vwgt[vs[j]];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            gv[j] = d.gp[vs[j]];
+            cw[j] = 1;
+        }
+    }
     int64_t ts = 0;
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
-        w[j] = 0;
-        if (pos0 + j < m) {
-            const int64_t v = (int64_t)((k[j] >> 1) & d.idmask);
-            const int64_t c = node_weight(d.g, v);
-            w[j] = (k[j] & 1ull) ? -c : c;
-            ts += w[j];
-        }
+        const bool ok = pos0 + j < m;
+        w[j] = ok ? ((k[j] & 1ull) ? -cw[j] : cw[j]) : 0;
+        gv[j] = (ok && !(k[j] & 1ull)) ? gv[j] : 0;
+        ts += w[j];
     }
-    // the inflow events' pessimistic gains, loaded together
-    int64_t gv[IPT];
-#pragma unroll
-    for (int j = 0; j < IPT; ++j)
-        gv[j] = (pos0 + j < m && !(k[j] & 1ull)) ? d.gp[(int64_t)((k[j] >> 1) & d.idmask)] : 0;
     int64_t total;
     const int64_t inc = block_incl_scan(ts, scan_lds, &total);
     int64_t run = carry + inc - ts;
@@ -895,6 +907,19 @@ __device__ __forceinline__ void seg_scan_decide(const uint64_t (&k)[IPT], int64_
 // bucket is sorted in runs of kRun and merged pairwise through the other
 // buffer (merge path over global memory, kSegMergeItems outputs per thread
 // and step).
+// k[j] = src[pos0 + j] below m, else the largest key (m >= 1): loads from
+// clamped indices without a branch, so that all are in flight together.
+__device__ __forceinline__ void seg_load_keys(uint64_t (&k)[kSortItems], const uint64_t *src,
+                                              int64_t pos0, int64_t m)
+{
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+        const int64_t p = pos0 + j;
+        const uint64_t x = src[p < m ? p : m - 1];
+        k[j] = p < m ? x : ~0ull;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_seg_decide(GraphView g, Blocks bk, SegWs ws, int idb,
                                                        const int64_t *__restrict__ gp,
                                                        const int64_t *__restrict__ W,
@@ -943,8 +968,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_decide(GraphView g, Blocks bk, S
     uint64_t k[kSortItems];
     if (m <= kRun) {
         const int64_t pos0 = (int64_t)threadIdx.x * kSortItems;
-#pragma unroll
-        for (int j = 0; j < kSortItems; ++j) k[j] = pos0 + j < m ? src[pos0 + j] : ~0ull;
+        seg_load_keys(k, src, pos0, m);
         block_sort_keys<kBlock>(k, lds);
         seg_scan_decide<kSortItems>(k, pos0, m, carry, d, scan_lds, &acc_lds, &deg_lds);
     } else if (m <= 2 * kRun) {
@@ -952,8 +976,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_decide(GraphView g, Blocks bk, S
         // stored; the second half's sort leaves the first half untouched
         for (int hf = 0; hf < 2; ++hf) {
             const int64_t pos0 = (int64_t)hf * kRun + (int64_t)threadIdx.x * kSortItems;
-#pragma unroll
-            for (int j = 0; j < kSortItems; ++j) k[j] = pos0 + j < m ? src[pos0 + j] : ~0ull;
+            seg_load_keys(k, src, pos0, m);
             block_sort_keys<kBlock>(k, lds + kRun);
 #pragma unroll
             for (int j = 0; j < kSortItems; ++j) lds[pos0 + j] = k[j];
@@ -993,8 +1016,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_decide(GraphView g, Blocks bk, S
         // sorted runs
         for (int64_t r0 = 0; r0 < m; r0 += kRun) {
             const int64_t pos0 = r0 + (int64_t)threadIdx.x * kSortItems;
-#pragma unroll
-            for (int j = 0; j < kSortItems; ++j) k[j] = pos0 + j < m ? src[pos0 + j] : ~0ull;
+            seg_load_keys(k, src, pos0, m);
             block_sort_keys<kBlock>(k, lds);
 #pragma unroll
             for (int j = 0; j < kSortItems; ++j)
@@ -1031,8 +1053,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_decide(GraphView g, Blocks bk, S
         // scan and decide in pieces of kRun
         for (int64_t r0 = 0; r0 < m; r0 += kRun) {
             const int64_t pos0 = r0 + (int64_t)threadIdx.x * kSortItems;
-#pragma unroll
-            for (int j = 0; j < kSortItems; ++j) k[j] = pos0 + j < m ? src[pos0 + j] : ~0ull;
+            seg_load_keys(k, src, pos0, m);
             seg_scan_decide<kSortItems>(k, pos0, m, carry, d, scan_lds, &acc_lds, &deg_lds);
         }
     }
