@@ -27,7 +27,8 @@ static int grid_cap(int64_t items, int per_block, int cap)
 // weights; for a single graph publish the round's Q16 penalty table and L_max.
 __global__ void k_round_init(Blocks bk, int64_t *bucket, int64_t *W, PenTable pq, int64_t lmax,
                              int single, unsigned long long *counters, int zero_w,
-                             unsigned long long *zero2, int64_t zero2_count)
+                             unsigned long long *zero2, int64_t zero2_count, HubView h,
+                             int32_t *hub_conn, int32_t k)
 {
     const int64_t K = bk.total();
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -44,15 +45,20 @@ __global__ void k_round_init(Blocks bk, int64_t *bucket, int64_t *W, PenTable pq
     }
     for (int64_t i = tid; i < kCntWords; i += stride) counters[i] = 0;
     for (int64_t i = tid; i < zero2_count; i += stride) zero2[i] = 0;
+    if (hub_conn)
+        for (int64_t i = tid; i < (int64_t)h.nh * k; i += stride)
+            hub_conn[(int64_t)h.ids[i / k] * k + i % k] = 0;
 }
 
 hipError_t launch_round_init(const Blocks &bk, int64_t *bucket, int64_t *W, const PenTable &pq,
                              int64_t lmax, int single, unsigned long long *counters, int zero_w,
-                             unsigned long long *zero2, int64_t zero2_count, hipStream_t s)
+                             unsigned long long *zero2, int64_t zero2_count, hipStream_t s,
+                             const HubView &h, int32_t *hub_conn, int32_t k)
 {
+    if (hub_conn && (h.nh <= 0 || k <= 0)) hub_conn = nullptr;
     hipLaunchKernelGGL(k_round_init, dim3(grid_cap((int64_t)bk.total() * kSlots, kBlock * 4, 1024)),
                        dim3(kBlock), 0, s, bk, bucket, W, pq, lmax, single, counters, zero_w, zero2,
-                       zero2_count);
+                       zero2_count, h, hub_conn, k);
     return hipGetLastError();
 }
 
@@ -934,7 +940,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, Blocks bk, int32_
 // Hub moves, before k_apply: each chunk updates the rows of its neighbours
 // (part of the hub is still its source block here). When the apply rebuilds
 // the table, the first chunk of every hub also clears the hub's own row,
-// which k_gain_hub rebuilds after the apply; in the delta mode hub rows get
+// which the refresh after the apply rebuilds; in the delta mode hub rows get
 // their deltas like every other row.
 __global__ __launch_bounds__(kBlock) void k_apply_hub(GraphView g, Blocks bk, const int32_t *part,
                                                        int32_t *conn, const int32_t *mvto,
@@ -989,10 +995,8 @@ hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, con
                        all_threshold);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // rebuild the marked tiles and the hub rows (nothing in the delta mode)
-    if ((e = launch_gain_tile(tg, k, tpv, conn, hub_t, dirty, s, nullptr, PartView{}, counters,
-                              all_threshold)) != hipSuccess)
-        return e;
-    return launch_gain_hub(tg, k, tpv, conn, h, s, counters, dirty_threshold);
+    return launch_gain_refresh(tg, k, tpv, conn, hub_t, h, dirty, counters, dirty_threshold,
+                               all_threshold, s);
 }
 
 // ----------------------------------------------------------------- stats --

@@ -36,8 +36,8 @@ static size_t gain_tile_lds(int32_t k, int T, bool p16)
 // One workgroup per tile of T consecutive nodes: zero the T x k rows in
 // LDS, accumulate every non-hub edge of the tile (edge-parallel; the edge ->
 // node map is a binary search over the tile's degree prefix), write the rows
-// back as one contiguous span. Hub rows are written as zeros here and filled
-// by k_gain_hub.
+// back as one contiguous span. Hub rows are left alone: their chunks, in the
+// same launch, write them.
 //
 // P16: when every tiled row sum fits 16 bits (non-hub weighted degrees below
 // 2^16), two counters share an LDS word (entry i in the low half of word
@@ -52,7 +52,8 @@ template <bool WEIGHTED, bool P16, int PB>
 __device__ __forceinline__ void gain_tile_body(const GraphView &g, int32_t k, int T,
                                                const PartView &part,
                                                int32_t *__restrict__ conn, int64_t hub_t,
-                                               int32_t *__restrict__ inner, const PartView &own)
+                                               int32_t *__restrict__ inner, const PartView &own,
+                                               int64_t tile_id)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     int32_t *tile = (int32_t *)lds_raw;
@@ -61,8 +62,9 @@ __device__ __forceinline__ void gain_tile_body(const GraphView &g, int32_t k, in
     int64_t *gstart = (int64_t *)(lds_raw + rows_bytes + (((size_t)(T + 1) * 4 + 15) & ~(size_t)15));
     int16_t *sown = (int16_t *)(gstart + T);  // own block of each node (with inner)
     __shared__ int32_t scan_lds[4];
+    __shared__ int32_t any_hub;
 
-    const int64_t v0 = (int64_t)blockIdx.x * T;
+    const int64_t v0 = tile_id * T;
     const int nt = (int)((g.n - v0) < T ? (g.n - v0) : T);
     const int tid = threadIdx.x;
     const int64_t kk = k;
@@ -78,8 +80,9 @@ __device__ __forceinline__ void gain_tile_body(const GraphView &g, int32_t k, in
     }
 
     // virtual degrees (hubs contribute none) and their exclusive prefix,
-    // in chunks of kBlock nodes; with inner, each node's own block goes to
-    // LDS and a hub is marked by gstart = -1 (its edges are never visited)
+    // in chunks of kBlock nodes; a hub is marked by gstart = -1 (its edges
+    // are never visited) and with inner, each node's own block goes to LDS
+    if (tid == 0) any_hub = 0;  // ordered before the flag writes by the scan's barriers
     int32_t run = 0;
     for (int base = 0; base < nt; base += kBlock) {
         const int i = base + tid;
@@ -87,13 +90,16 @@ __device__ __forceinline__ void gain_tile_body(const GraphView &g, int32_t k, in
         if (i < nt) {
             const int64_t a = g.xadj[v0 + i], b = g.xadj[v0 + i + 1];
             const bool hub = (b - a) > hub_t;
-            gstart[i] = hub && inner ? -1 : a;
+            gstart[i] = hub ? -1 : a;
             vd = hub ? 0 : (int32_t)(b - a);
             if (inner) sown[i] = (int16_t)(pget(own, v0 + i) & part_mask(own));
         }
         int32_t total;
         const int32_t inc = block_incl_scan(vd, scan_lds, &total);
-        if (i < nt) vstart[i] = run + inc - vd;
+        if (i < nt) {
+            vstart[i] = run + inc - vd;
+            if (gstart[i] < 0) any_hub = 1;
+        }
         run += total;
     }
     if (tid == 0) vstart[nt] = run;
@@ -135,11 +141,16 @@ __device__ __forceinline__ void gain_tile_body(const GraphView &g, int32_t k, in
     }
     __syncthreads();
 
-    // coalesced write-back of the contiguous rows [v0, v0 + nt)
+    // coalesced write-back of the contiguous rows [v0, v0 + nt); a tile
+    // that holds a hub skips the hub's row
     int32_t *dst = conn + v0 * kk;
     const int64_t total_ints = entries;
     int64_t done = 0;
-    if (((uintptr_t)dst & 15) == 0) {
+    if (any_hub) {
+        for (int i = tid; i < entries; i += kBlock)
+            if (gstart[i / k] >= 0) dst[i] = P16 ? (int32_t)((const uint16_t *)tile)[i] : tile[i];
+        done = total_ints;
+    } else if (((uintptr_t)dst & 15) == 0) {
         const int64_t n4 = total_ints >> 2;
         int4 *d4 = (int4 *)dst;
         if (P16) {
@@ -170,48 +181,108 @@ __device__ __forceinline__ void gain_tile_body(const GraphView &g, int32_t k, in
         }
     }
 }
+// A chunk of a hub's edges: accumulate the chunk's counts in an LDS row,
+// then add its non-zero entries into the hub's row of conn (which is zero
+// before the first chunk adds: no chunk waits for another).
+template <bool WEIGHTED, int PB>
+__device__ __forceinline__ void gain_hub_chunk(const GraphView &g, int32_t k, const PartView &part,
+                                               int32_t *__restrict__ conn, const HubView &h,
+                                               int64_t ci)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    int32_t *row = (int32_t *)lds_raw;
+    const int tid = threadIdx.x;
+    const HubChunk c = h.chunks[ci];
+    const int64_t v = h.ids[c.hub];
+    const int32_t pmask = part_mask(part);
+    for (int j = tid; j < k; j += kBlock) row[j] = 0;
+    __syncthreads();
+    // as in the tile: every load issued unconditionally (a slot past the
+    // chunk's end reads its last edge again and adds nothing)
+    constexpr int kUnroll = 8;
+    for (int64_t p0 = c.e0 + tid; p0 < c.e1; p0 += (int64_t)kBlock * kUnroll) {
+        bool ok[kUnroll];
+        int64_t e[kUnroll];
+        int32_t u[kUnroll], w[kUnroll], pu[kUnroll];
+#pragma unroll
+        for (int i = 0; i < kUnroll; ++i) {
+            const int64_t q = p0 + i * kBlock;
+            ok[i] = q < c.e1;
+            e[i] = ok[i] ? q : c.e1 - 1;
+        }
+#pragma unroll
+        for (int i = 0; i < kUnroll; ++i) {
+            u[i] = g.adjncy[e[i]];
+            w[i] = WEIGHTED ? g.adjwgt[e[i]] : 1;
+        }
+#pragma unroll
+        for (int i = 0; i < kUnroll; ++i) pu[i] = pget_w<PB>(part.p, u[i], pmask);
+#pragma unroll
+        for (int i = 0; i < kUnroll; ++i)
+            if (ok[i] && (unsigned)pu[i] < (unsigned)k) atomicAdd(&row[pu[i]], w[i]);
+    }
+    __syncthreads();
+    int32_t *dst = conn + v * (int64_t)k;
+    for (int j = tid; j < k; j += kBlock)
+        if (row[j]) atomicAdd(&dst[j], row[j]);
+}
+
+// The hubs' chunks take the first h.nchunks workgroups (they start first:
+// a chunk's edges are many more than a tile's), the tiles the rest.
 template <bool WEIGHTED, bool P16, int PB>
 __global__ __launch_bounds__(kBlock) void k_gain_tile(GraphView g, int32_t k, int T, PartView part,
                                                        int32_t *__restrict__ conn, int64_t hub_t,
-                                                       int32_t *__restrict__ inner, PartView own)
+                                                       HubView h, int32_t *__restrict__ inner,
+                                                       PartView own)
 {
-    gain_tile_body<WEIGHTED, P16, PB>(g, k, T, part, conn, hub_t, inner, own);
+    if ((int64_t)blockIdx.x < h.nchunks) {
+        gain_hub_chunk<WEIGHTED, PB>(g, k, part, conn, h, blockIdx.x);
+        return;
+    }
+    gain_tile_body<WEIGHTED, P16, PB>(g, k, T, part, conn, hub_t, inner, own,
+                                      (int64_t)blockIdx.x - h.nchunks);
 }
-template <bool WEIGHTED, bool P16, int PB>
 // Rebuilds the marked tiles, or every tile when the moving nodes' degrees
 // (counters[CNT_MOVED_DEG]) sum above all_threshold (the apply then marks
-// nothing: nearly every tile would be marked).
+// nothing: nearly every tile would be marked), and the hub rows when they
+// sum above dirty_threshold.
+template <bool WEIGHTED, bool P16, int PB>
 __global__ __launch_bounds__(kBlock) void k_gain_refresh(GraphView g, int32_t k, int T,
                                                           PartView part,
                                                           int32_t *__restrict__ conn,
-                                                          int64_t hub_t, uint8_t *dirty,
+                                                          int64_t hub_t, HubView h, uint8_t *dirty,
                                                           const unsigned long long *counters,
+                                                          int64_t dirty_threshold,
                                                           int64_t all_threshold)
 {
-    const bool all = counters && (int64_t)wave_cnt_get(counters, CNT_MOVED_DEG) > all_threshold;
-    if (!all && !dirty[blockIdx.x]) return;  // uniform over the workgroup
+    const int64_t moved_deg = (int64_t)wave_cnt_get(counters, CNT_MOVED_DEG);
+    if ((int64_t)blockIdx.x < h.nchunks) {
+        if (moved_deg > dirty_threshold) gain_hub_chunk<WEIGHTED, PB>(g, k, part, conn, h, blockIdx.x);
+        return;
+    }
+    const int64_t t = (int64_t)blockIdx.x - h.nchunks;
+    if (moved_deg <= all_threshold && !dirty[t]) return;  // uniform over the workgroup
     __syncthreads();
-    if (threadIdx.x == 0) dirty[blockIdx.x] = 0;
-    gain_tile_body<WEIGHTED, P16, PB>(g, k, T, part, conn, hub_t, nullptr, part);
+    if (threadIdx.x == 0) dirty[t] = 0;
+    gain_tile_body<WEIGHTED, P16, PB>(g, k, T, part, conn, hub_t, nullptr, part, t);
 }
 
-hipError_t launch_gain_tile(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,
-                            int64_t hub_t, uint8_t *dirty, hipStream_t s, int32_t *inner,
-                            const PartView &own, const unsigned long long *counters,
-                            int64_t all_threshold)
+namespace {
+size_t table_lds(int32_t k, int T, bool p16)
 {
-    if (g.n <= 0) return hipSuccess;
-    const int T = gain_tile_nodes(k);
-    const int64_t tiles = (g.n + T - 1) / T;
-    const size_t lds = gain_tile_lds(k, T, g.tile16 != 0);
-#define UPR_TILE(KERN, WW, PP, BB, ...)                                                             \
-    hipLaunchKernelGGL((KERN<WW, PP, BB>), dim3((unsigned)tiles), dim3(kBlock), lds, s, g, k, T,    \
-                       part, conn, hub_t __VA_ARGS__)
+    return std::max(gain_tile_lds(k, T, p16), (size_t)k * 4);
+}
+bool hubs_ready(const HubView &h)
+{
+    return h.nchunks <= 0 || (h.chunks && h.ids);
+}
+}  // namespace
+
 #define UPR_TILE_B(KERN, WW, PP, ...)                                                               \
     do {                                                                                            \
-        if (part.bytes == 1) UPR_TILE(KERN, WW, PP, 1, __VA_ARGS__);                                \
-        else if (part.bytes == 2) UPR_TILE(KERN, WW, PP, 2, __VA_ARGS__);                           \
-        else UPR_TILE(KERN, WW, PP, 4, __VA_ARGS__);                                                \
+        if (part.bytes == 1) hipLaunchKernelGGL((KERN<WW, PP, 1>), __VA_ARGS__);                    \
+        else if (part.bytes == 2) hipLaunchKernelGGL((KERN<WW, PP, 2>), __VA_ARGS__);               \
+        else hipLaunchKernelGGL((KERN<WW, PP, 4>), __VA_ARGS__);                                    \
     } while (0)
 #define UPR_TILE_ALL(KERN, ...)                                                                     \
     do {                                                                                            \
@@ -223,40 +294,54 @@ hipError_t launch_gain_tile(const GraphView &g, int32_t k, const PartView &part,
             else UPR_TILE_B(KERN, false, false, __VA_ARGS__);                                       \
         }                                                                                           \
     } while (0)
-    if (dirty) UPR_TILE_ALL(k_gain_refresh, , dirty, counters, all_threshold);
-    else UPR_TILE_ALL(k_gain_tile, , inner, own);
-#undef UPR_TILE_ALL
-#undef UPR_TILE_B
-#undef UPR_TILE
+
+hipError_t launch_gain_table(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,
+                             int64_t hub_t, const HubView &h, hipStream_t s, int32_t *inner,
+                             const PartView &own)
+{
+    if (g.n <= 0) return hipSuccess;
+    if (!hubs_ready(h)) return hipErrorInvalidValue;
+    const int T = gain_tile_nodes(k);
+    const int64_t grid = (g.n + T - 1) / T + std::max<int64_t>(h.nchunks, 0);
+    const size_t lds = table_lds(k, T, g.tile16 != 0);
+    UPR_TILE_ALL(k_gain_tile, dim3((unsigned)grid), dim3(kBlock), lds, s, g, k, T, part, conn,
+                 hub_t, h, inner, own);
     return hipGetLastError();
 }
 
+hipError_t launch_gain_refresh(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,
+                               int64_t hub_t, const HubView &h, uint8_t *dirty,
+                               const unsigned long long *counters, int64_t dirty_threshold,
+                               int64_t all_threshold, hipStream_t s)
+{
+    if (g.n <= 0) return hipSuccess;
+    if (!hubs_ready(h) || !dirty || !counters) return hipErrorInvalidValue;
+    const int T = gain_tile_nodes(k);
+    const int64_t grid = (g.n + T - 1) / T + std::max<int64_t>(h.nchunks, 0);
+    const size_t lds = table_lds(k, T, g.tile16 != 0);
+    UPR_TILE_ALL(k_gain_refresh, dim3((unsigned)grid), dim3(kBlock), lds, s, g, k, T, part, conn,
+                 hub_t, h, dirty, counters, dirty_threshold, all_threshold);
+    return hipGetLastError();
+}
+#undef UPR_TILE_ALL
+#undef UPR_TILE_B
+
 // --------------------------------------------------------------- hub rows --
 
-// One workgroup per chunk of a hub's edges: accumulate into an LDS row, then
-// add the non-zero entries into the hub's row of conn (zeroed by the tile,
-// or by the hub apply). counters != null: only if the apply before rebuilt
-// the table.
-__global__ __launch_bounds__(kBlock) void k_gain_hub(GraphView g, int32_t k, PartView part,
-                                                      int32_t *conn, HubView h,
-                                                      const unsigned long long *counters,
-                                                      int64_t dirty_threshold)
+__global__ void k_zero_hub_rows(HubView h, int32_t *conn, int32_t k)
 {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    int32_t *row = (int32_t *)lds_raw;
-    if (counters && (int64_t)wave_cnt_get(counters, CNT_MOVED_DEG) <= dirty_threshold) return;
-    const HubChunk c = h.chunks[blockIdx.x];
-    const int64_t v = h.ids[c.hub];
-    for (int j = threadIdx.x; j < k; j += kBlock) row[j] = 0;
-    __syncthreads();
-    for (int64_t e = c.e0 + threadIdx.x; e < c.e1; e += kBlock) {
-        const int32_t pu = pget(part, g.adjncy[e]);
-        if ((unsigned)pu < (unsigned)k) atomicAdd(&row[pu], edge_weight(g, e));
-    }
-    __syncthreads();
-    int32_t *dst = conn + v * (int64_t)k;
-    for (int j = threadIdx.x; j < k; j += kBlock)
-        if (row[j]) atomicAdd(&dst[j], row[j]);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)h.nh * k) return;
+    conn[(int64_t)h.ids[i / k] * k + i % k] = 0;
+}
+
+hipError_t launch_zero_hub_rows(const HubView &h, int32_t *conn, int32_t k, hipStream_t s)
+{
+    const int64_t total = (int64_t)h.nh * k;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_hub_rows, dim3((unsigned)((total + kBlock - 1) / kBlock)), dim3(kBlock),
+                       0, s, h, conn, k);
+    return hipGetLastError();
 }
 
 __global__ void k_hub_bits(HubView h, uint32_t *bits)
@@ -274,14 +359,5 @@ hipError_t launch_hub_bits(const HubView &h, uint32_t *bits, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_gain_hub(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,
-                           const HubView &h, hipStream_t s, const unsigned long long *counters,
-                           int64_t dirty_threshold)
-{
-    if (h.nchunks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gain_hub, dim3((unsigned)h.nchunks), dim3(kBlock), (size_t)k * 4, s, g, k,
-                       part, conn, h, counters, dirty_threshold);
-    return hipGetLastError();
-}
 
 }  // namespace upr

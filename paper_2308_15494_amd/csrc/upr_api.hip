@@ -973,8 +973,8 @@ int upr_gain_table(upr_ctx *c, const upr_plan *p, int32_t k, const int32_t *part
     if (c->cnt[CNT_BAD_INPUT]) return fail(c, UPR_E_ARG, "part holds values outside [0, k)");
     PhaseTimer t(c, 0, s);
     const PartView pv{part, 4};
-    HIP_TRY(c, launch_gain_tile(p->g, k, pv, conn, p->hub_t, nullptr, s));
-    HIP_TRY(c, launch_gain_hub(p->g, k, pv, conn, p->hubs(), s));
+    HIP_TRY(c, launch_zero_hub_rows(p->hubs(), conn, k, s));
+    HIP_TRY(c, launch_gain_table(p->g, k, pv, conn, p->hub_t, p->hubs(), s));
     return UPR_OK;
 }
 
@@ -1063,7 +1063,8 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
     const bool seg = moves && q->seq_penalty && seq_segments_fit(seq_score_bits(p->maxwdeg), n);
     HIP_TRY(c, launch_round_init(bk, c->bucket, W, pq, lmax, b ? 0 : 1, c->counters,
                                  q->rebuild_table, seg ? c->seg_cur : nullptr,
-                                 seg ? seq_counter_words(K) : 0, s));
+                                 seg ? seq_counter_words(K) : 0, s, h,
+                                 q->rebuild_table ? conn : nullptr, k));
     if (b) HIP_TRY(c, launch_fill_i64(gstat, (int64_t)GS_COUNT * ng, 0, s));
     // compact partition copy for the neighbour gathers (kept in step by the apply)
     const PartView pv{c->pc, k <= 256 ? 1 : 2, k <= 128 ? 1 : 0};
@@ -1075,11 +1076,8 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
         const GraphView tg = p->table_graph();
         {
             PhaseTimer t(c, 0, s);
-            HIP_TRY(c, launch_gain_tile(tg, k, tpv, conn, p->hub_t, nullptr, s, c->inner, pv));
-        }
-        if (p->nh > 0) {
-            PhaseTimer t(c, 1, s);
-            HIP_TRY(c, launch_gain_hub(tg, k, tpv, conn, h, s));
+            // the hub rows were cleared by the round's init
+            HIP_TRY(c, launch_gain_table(tg, k, tpv, conn, p->hub_t, h, s, c->inner, pv));
         }
     }
     {
@@ -1598,8 +1596,8 @@ int upr_refine(upr_ctx *c, const upr_plan *p, const upr_driver *d, int32_t *part
     }
     if (d->fm_rounds == 0 && n > 0) {
         // the table and block weights of the final partition
-        HIP_TRY(c, launch_gain_tile(p->g, d->k, PartView{part, 4}, conn, p->hub_t, nullptr, s));
-        HIP_TRY(c, launch_gain_hub(p->g, d->k, PartView{part, 4}, conn, p->hubs(), s));
+        HIP_TRY(c, launch_zero_hub_rows(p->hubs(), conn, d->k, s));
+        HIP_TRY(c, launch_gain_table(p->g, d->k, PartView{part, 4}, conn, p->hub_t, p->hubs(), s));
         HIP_TRY(c, launch_fill_i64(W, d->k, 0, s));
         HIP_TRY(c, launch_block_weights(p->g, d->k, part, W, c->counters, s));
     }

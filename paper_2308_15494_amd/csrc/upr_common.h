@@ -480,25 +480,25 @@ hipError_t launch_hub_ranges(const int64_t *xadj, const int32_t *ids, int32_t nh
 
 // table (S1)
 int gain_tile_nodes(int32_t k);
-// With dirty != null only tiles whose flag is set are rebuilt (flags are
-// cleared).
-// inner / own (full build only): each non-hub node's conn[v][own block] also
-// goes to inner[v]; own is the partition in node order.
-// With dirty: counters / all_threshold make every tile rebuild once the
-// moving nodes' degrees sum above all_threshold.
-hipError_t launch_gain_tile(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,
-                            int64_t hub_t, uint8_t *dirty, hipStream_t s,
-                            int32_t *inner = nullptr, const PartView &own = PartView{},
-                            const unsigned long long *counters = nullptr,
-                            int64_t all_threshold = 0);
-// Hub rows, accumulated into rows that are zero. After an apply (counters
-// != null) only when that apply rebuilt the table (the moving nodes' degrees
-// above dirty_threshold); in the delta mode the rows are already up to date
-// and every workgroup returns at once.
-hipError_t launch_gain_hub(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,
-                           const HubView &h, hipStream_t s,
-                           const unsigned long long *counters = nullptr,
-                           int64_t dirty_threshold = 0);
+// The full table: one workgroup per tile of non-hub rows and, in the same
+// launch, one per chunk of a hub's edges, which adds the chunk's counts into
+// the hub's row: the hub rows must be zero (launch_zero_hub_rows).
+// inner / own: each non-hub node's conn[v][own block] also goes to inner[v];
+// own is the partition in node order.
+hipError_t launch_gain_table(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,
+                             int64_t hub_t, const HubView &h, hipStream_t s,
+                             int32_t *inner = nullptr, const PartView &own = PartView{});
+// After an apply: the tiles whose dirty flag is set (flags are cleared), or
+// every tile once the moving nodes' degrees (counters[CNT_MOVED_DEG]) sum
+// above all_threshold, and the hub rows (cleared by the hub apply) once they
+// sum above dirty_threshold. In the delta mode every workgroup returns at
+// once.
+hipError_t launch_gain_refresh(const GraphView &g, int32_t k, const PartView &part, int32_t *conn,
+                               int64_t hub_t, const HubView &h, uint8_t *dirty,
+                               const unsigned long long *counters, int64_t dirty_threshold,
+                               int64_t all_threshold, hipStream_t s);
+// Clears the hubs' rows of conn.
+hipError_t launch_zero_hub_rows(const HubView &h, int32_t *conn, int32_t k, hipStream_t s);
 // Compact copy of the local blocks (bytes = 1 or 2). Checks every value: a
 // global block id below bk.total() and, for a batch (goff = node offsets of
 // the graphs, ng + 1 entries), a block of the node's own graph; violations
@@ -552,9 +552,12 @@ hipError_t launch_check_part(int64_t n, int32_t k, const int32_t *part,
 // Zero the counters, the buckets ([K][kSlots]), zero2 ([zero2_count]) and,
 // if zero_w, W ([K]). With single (one graph) also publish its penalty table
 // and L_max into bk.penq / bk.lmax / bk.src_lmax (writable workspace).
+// With hub_conn: also clears the hubs' rows of the table (k entries each).
 hipError_t launch_round_init(const Blocks &bk, int64_t *bucket, int64_t *W, const PenTable &pq,
                              int64_t lmax, int single, unsigned long long *counters, int zero_w,
-                             unsigned long long *zero2, int64_t zero2_count, hipStream_t s);
+                             unsigned long long *zero2, int64_t zero2_count, hipStream_t s,
+                             const HubView &h = HubView{}, int32_t *hub_conn = nullptr,
+                             int32_t k = 0);
 // Prefix sums of the buckets; pen1[B] = penalty of a unit-weight node moving
 // into B (0 if it fits, -1 if forbidden).
 hipError_t launch_cb_prefix(const Blocks &bk, int64_t *bucket, const int64_t *W, int mode,
