@@ -142,7 +142,9 @@ __device__ __forceinline__ void gain_tile_body(const GraphView &g, int32_t k, in
     __syncthreads();
 
     // coalesced write-back of the contiguous rows [v0, v0 + nt); a tile
-    // that holds a hub skips the hub's row
+    // that holds a hub skips the hub's row. The stores are non-temporal: the
+    // table streams through the L2 without evicting the partition copy that
+    // the other tiles gather from.
     int32_t *dst = conn + v0 * kk;
     const int64_t total_ints = entries;
     int64_t done = 0;
@@ -157,12 +159,16 @@ __device__ __forceinline__ void gain_tile_body(const GraphView &g, int32_t k, in
             const uint2 *s2 = (const uint2 *)tile;
             for (int64_t i = tid; i < n4; i += kBlock) {
                 const uint2 x = s2[i];
-                d4[i] = make_int4((int)(x.x & 0xFFFF), (int)(x.x >> 16), (int)(x.y & 0xFFFF),
-                                  (int)(x.y >> 16));
+                v4i32 y;
+                y.x = (int)(x.x & 0xFFFF);
+                y.y = (int)(x.x >> 16);
+                y.z = (int)(x.y & 0xFFFF);
+                y.w = (int)(x.y >> 16);
+                __builtin_nontemporal_store(y, (v4i32 *)d4 + i);
             }
         } else {
-            const int4 *s4 = (const int4 *)tile;
-            for (int64_t i = tid; i < n4; i += kBlock) d4[i] = s4[i];
+            const v4i32 *s4 = (const v4i32 *)tile;
+            for (int64_t i = tid; i < n4; i += kBlock) __builtin_nontemporal_store(s4[i], (v4i32 *)d4 + i);
         }
         done = n4 << 2;
     }
