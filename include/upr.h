@@ -295,8 +295,8 @@ int upr_penalty_table(int32_t tau_num, int32_t tau_den, int64_t *out);
  * milliseconds by HIP events while timing is enabled (each timed phase
  * records two events on the call's stream). Phases: 0 gain table,
  * 1 penalty buckets, 2 best move, 3 filter, 4 apply, 5 rebalance, 6 cut,
- * 7 whole call. Phase 0 is the gain-table tile kernel alone, 1 the hub rows
- * and hub statistics (or, for a resident table, the penalty buckets).
+ * 7 whole call. Phase 0 is the gain-table kernel (its tiles and the hubs'
+ * edge chunks), 1 the node statistics and penalty buckets.
  * phase_mask: bit p times phase p (0 = off, UPR_TIMING_ALL = every phase).
  * counts[p] = number of intervals accumulated. */
 #define UPR_NUM_PHASES 8

@@ -21,7 +21,7 @@ ERRORS = {-1: "UPR_E_ARG", -2: "UPR_E_GRAPH", -3: "UPR_E_INFEASIBLE", -4: "UPR_E
 STATS_LEN = 12
 STAT_NAMES = ["l_max", "cut_before", "cut_after_moves", "cut_after", "candidates",
               "accepted", "rebalance_moves", "rebalance_iters", "status"]
-PHASES = ["gain_tile", "gain_hub", "best_move", "filter", "apply", "rebalance", "cut", "call"]
+PHASES = ["gain_tile", "stats", "best_move", "filter", "apply", "rebalance", "cut", "call"]
 MODES = {"penalised": 0, "constrained": 1, "free": 2, "limited": 3}
 
 
