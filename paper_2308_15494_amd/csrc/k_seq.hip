@@ -577,10 +577,28 @@ __global__ __launch_bounds__(kOffThreads) void k_seg_offsets(int K, SegWs ws)
     }
     __syncthreads();
     // the buckets of split blocks, by all threads
-    const int32_t *bo = lds ? s_boff : ws.boff;
+    if (lds) {
+        // one bucket per thread and step: its block is the last B with
+        // boff[B] <= f (every block has at least one bucket)
+        const int nbk = s_boff[K];
+        for (int f = t; f < nbk; f += kOffThreads) {
+            int lo = 0, hi = K - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_boff[mid] <= f) lo = mid;
+                else hi = mid - 1;
+            }
+            if (s_boff[lo + 1] - s_boff[lo] > 1) {
+                ws.bblk[f] = lo;
+                ws.bcnt[f] = 0;
+                ws.bdel[f] = 0;
+            }
+        }
+        return;
+    }
     for (int j = 0; j < (int)carry_s; ++j) {
         const int B = ws.slist[j];
-        const int f = bo[B], P = bo[B + 1] - f;
+        const int f = ws.boff[B], P = ws.boff[B + 1] - f;
         for (int i = t; i < P; i += kOffThreads) {
             ws.bblk[f + i] = B;
             ws.bcnt[f + i] = 0;
