@@ -281,14 +281,18 @@ __device__ __forceinline__ void wave_bitonic(uint64_t (&k)[kSortItems])
     }
 }
 
+// live (uniform over the workgroup): only the first live positions hold
+// keys that matter, the rest hold ~0; merging stops once one sorted run
+// covers them.
 template <int BLOCK>
-__device__ __forceinline__ void block_sort_keys(uint64_t (&k)[kSortItems], uint64_t *lds)
+__device__ __forceinline__ void block_sort_keys(uint64_t (&k)[kSortItems], uint64_t *lds,
+                                                int64_t live = (int64_t)BLOCK * kSortItems)
 {
     wave_bitonic(k);
     constexpr int N = BLOCK * kSortItems;
     const int d0 = (int)threadIdx.x * kSortItems;
 #pragma unroll 1
-    for (int r = kWaveKeys; r < N; r <<= 1) {
+    for (int r = kWaveKeys; r < N && r < live; r <<= 1) {
 #pragma unroll
         for (int j = 0; j < kSortItems; ++j) lds[d0 + j] = k[j];
         __syncthreads();
@@ -695,9 +699,11 @@ __global__ __launch_bounds__(kSplitThreads) void k_seg_split(SegWs ws)
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
         const int64_t idx = (int64_t)threadIdx.x * kSortItems + j;
-        k[j] = idx < S ? ws.ev[s0 + (idx * m) / S] : ~0ull;
+        const uint64_t x = ws.ev[s0 + ((idx < S ? idx : S - 1) * m) / S];  // clamped: no load in a branch
+        k[j] = idx < S ? x : ~0ull;
     }
-    block_sort_keys<kSplitThreads>(k, lds);
+    // the S samples fill the first positions: the runs past them stay ~0
+    block_sort_keys<kSplitThreads>(k, lds, S);
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) lds[threadIdx.x * kSortItems + j] = k[j];
     __syncthreads();
@@ -987,7 +993,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_decide(GraphView g, Blocks bk, S
     if (m <= kRun) {
         const int64_t pos0 = (int64_t)threadIdx.x * kSortItems;
         seg_load_keys(k, src, pos0, m);
-        block_sort_keys<kBlock>(k, lds);
+        block_sort_keys<kBlock>(k, lds, m);
         seg_scan_decide<kSortItems>(k, pos0, m, carry, d, scan_lds, &acc_lds, &deg_lds);
     } else if (m <= 2 * kRun) {
         // each half sorted with the upper half of the buffer as scratch, then
@@ -995,7 +1001,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_decide(GraphView g, Blocks bk, S
         for (int hf = 0; hf < 2; ++hf) {
             const int64_t pos0 = (int64_t)hf * kRun + (int64_t)threadIdx.x * kSortItems;
             seg_load_keys(k, src, pos0, m);
-            block_sort_keys<kBlock>(k, lds + kRun);
+            block_sort_keys<kBlock>(k, lds + kRun, hf == 0 ? (int64_t)kRun : m - kRun);
 #pragma unroll
             for (int j = 0; j < kSortItems; ++j) lds[pos0 + j] = k[j];
             __syncthreads();
@@ -1035,7 +1041,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_decide(GraphView g, Blocks bk, S
         for (int64_t r0 = 0; r0 < m; r0 += kRun) {
             const int64_t pos0 = r0 + (int64_t)threadIdx.x * kSortItems;
             seg_load_keys(k, src, pos0, m);
-            block_sort_keys<kBlock>(k, lds);
+            block_sort_keys<kBlock>(k, lds, m - r0 < kRun ? m - r0 : (int64_t)kRun);
 #pragma unroll
             for (int j = 0; j < kSortItems; ++j)
                 if (pos0 + j < m) src[pos0 + j] = k[j];
