@@ -184,9 +184,33 @@ def test_gain_table_counter_width(upr, ctx, total):
             pr.compare(ost, odbg, f"total {total} k {k} round {r}")
 
 
+def test_gain_table_hub_rows(upr, ctx, monkeypatch):
+    """The standalone table build with hubs of several edge chunks, twice into
+    the same buffer: the hub rows are cleared before the chunks add into them,
+    so the second partition's table holds no counts of the first."""
+    import torch
+    monkeypatch.setenv("UPR_HUB_THRESHOLD", "40")
+    for seed, k in ((1, 64), (2, 5)):
+        g = gg.rmat(16, 16, seed=seed)  # largest degrees near 10^4: hubs of up to 3 chunks
+        if seed == 2:
+            g = gg.with_weights(g, seed, wmax=7)
+        say(f"hub table case seed={seed} n={g.n} max_deg={g.meta['max_degree']} k={k}")
+        dg = upr.DeviceGraph(g)
+        plan = upr.Plan(ctx, dg)
+        assert plan.info()["num_hubs"] > 0
+        assert g.meta["max_degree"] > 4096  # a hub of more than one chunk
+        conn = None
+        for rep in range(2):
+            part = gg.random_partition(g.n, k, 10 * seed + rep)
+            conn = upr.gain_table(ctx, plan, k, to_dev(part), conn)
+            torch.cuda.synchronize()
+            assert np.array_equal(conn.cpu().numpy().reshape(g.n, k), O.gain_table(g, k, part)), rep
+
+
 def test_hub_paths(upr, ctx, monkeypatch):
-    """Force a low hub threshold so the multi-workgroup hub kernels carry
-    real rows (and chunks span several workgroups)."""
+    """Force a low hub threshold so the hub kernels (one workgroup per edge
+    chunk) carry real rows through whole rounds; these hubs fit one chunk
+    each, the table test above has hubs of several."""
     import torch
     monkeypatch.setenv("UPR_HUB_THRESHOLD", "40")
     for seed in range(3):
