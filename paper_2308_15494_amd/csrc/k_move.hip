@@ -491,7 +491,7 @@ __device__ __forceinline__ int64_t pessimistic_part(const GraphView &g, const Pa
 // each edge adds its term w * f to the node's 32-bit LDS sum (a node's sum is
 // bounded by its weighted degree, below 2^31). One LDS atomic per edge was
 // faster than a segmented wave scan over the runs of equal nodes.
-constexpr int kFilterTile = 512;
+constexpr int kFilterTile = 256;
 constexpr int kFilterUnroll = 8;  // edges per thread and step (8 measured best of 2, 4, 8)
 
 // RL: a neighbour's block and key are read by its label (adj_r[e]) from the
