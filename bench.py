@@ -1,12 +1,18 @@
 """Benchmark: edges/s of one refinement round on one MI355X.
 
-A step is one full round (gain table, penalised best move, conflict filter,
-apply, rebalance, cut) of the R-MAT scale-20 graph (2^20 nodes, 16 draws per
-node, a,b,c,d = .57,.19,.19,.05, ~15.7M undirected edges after dropping
-self-loops and duplicates) at k = 64, eps = 3/100, starting from a seeded
-random balanced partition; round r uses tau_r = (18 + r) / 38 (20 rounds).
-The table is rebuilt inside every round (the rebuild form). Inputs are
-resident in HBM before the timed region.
+A step is one full round (gain table, penalised best move, conflict filter
+with the sequence-aware price, apply, rebalance, cut) of the R-MAT scale-20
+graph (2^20 nodes, 16 draws per node, a,b,c,d = .57,.19,.19,.05, ~15.7M
+undirected edges after dropping self-loops and duplicates) at k = 64,
+eps = 3/100, starting from a seeded random balanced partition; round r uses
+tau_r = (18 + r) / 38 (20 rounds). The table is rebuilt inside every round
+(the rebuild form). Inputs are resident in HBM before the timed region.
+
+The same line also carries: the rooflines of the gain-table, best-move,
+filter and apply kernels; the other single-graph workloads (the 2048 x 2048
+grid at k = 64 and the 8M-node weighted Chung-Lu graph at k = 256), each
+with edges/s, its kernel rooflines and an oracle round for parity; the
+batched-vs-plain and serving legs; and the oracle timed on host cores.
 
 Prints one JSON line. Diagnostics go to stderr.
 """
@@ -130,27 +136,180 @@ def ingest_pmc(fetch_csv, write_csv):
     print(json.dumps(rec))
 
 
-def cpu_baseline(g, k, eps, rounds, part0, seconds):
+def cpu_baseline(g, k, eps, rounds, part0, seconds, max_rounds=None):
     """The oracle, single-threaded on a host core, on the first rounds of the
-    same workload until about `seconds` of work; returns (baseline, stats list)."""
+    same workload until about `seconds` of work (at most max_rounds); returns
+    (baseline, [(stats, part, W)] per round)."""
     from oracle import oracle as O
     from paper_2308_15494_amd import graphgen as gg
     G = O.Graph(g)
     part = part0.copy()
     conn = np.zeros(g.n * k, np.int32)
     W = np.zeros(k, np.int64)
-    stats = []
+    out = []
     t0 = time.perf_counter()
     r = 0
-    while r < rounds:
+    cap = rounds if max_rounds is None else min(rounds, max_rounds)
+    while r < cap:
         r += 1
         st, _ = O.refine_round(G, O.params(k, eps, tau=gg.tau_schedule(r, rounds)), part, conn, W)
-        stats.append(st.copy())
+        out.append((st.copy(), part.copy(), W.copy()))
+        log(f"  oracle round {r}: {time.perf_counter() - t0:.1f}s")
         if time.perf_counter() - t0 > seconds:
             break
     dt = time.perf_counter() - t0
+    del conn
     return {"value": g.m * r / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {r} of {rounds} rounds of the same workload, one thread"}, stats
+            "sample": f"first {r} of {rounds} rounds of the same workload, one thread"}, out
+
+
+def host_info():
+    """CPU model and the cores this process may run on (the oracle uses one)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu_model": model, "nproc": avail, "cpu_count": os.cpu_count()}
+
+
+def roofline_entry(kernel, bytes_total, seconds_total, launches, note):
+    """One kernel's HBM roofline from its algorithmic bytes and event-timed
+    launch durations summed over `launches` launches."""
+    if not launches or seconds_total <= 0:
+        return {"bound": "hbm", "kernel": kernel, "achieved": None, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": None, "traffic": None, "launches": launches,
+                "algorithmic_bytes_per_launch": None, "avg_launch_us": None, "bytes": note}
+    ach = bytes_total / seconds_total / 1e9
+    return {"bound": "hbm", "kernel": kernel, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None, "launches": launches,
+            "algorithmic_bytes_per_launch": bytes_total / launches,
+            "avg_launch_us": 1e6 * seconds_total / launches, "bytes": note}
+
+
+def single_graph(ctx, g, k, eps, rounds, part0, steps, warmup, resident, hub_t=4096,
+                 dirty_div=16, phase_rounds=None, opts=None):
+    """Times `steps` rounds of one graph (edges/s; only the gain-table kernel
+    is bracketed by events inside the timed region), then repeats them from
+    the same start, untimed, with every phase timed and read after each
+    round, to get the per-round statistics, partitions and block weights
+    (for the parity check) and the per-kernel rooflines."""
+    import torch
+    from paper_2308_15494_amd import graphgen as gg
+    from paper_2308_15494_amd import upr
+    r = upr.Refiner(g, k, ctx=ctx, opts=opts)
+    info = r.plan.info()
+
+    def run_rounds(count, per_round=None):
+        for i in range(1, count + 1):
+            p = upr.params(k, eps, tau=gg.tau_schedule(i, rounds),
+                           rebuild_table=0 if (resident and i > 1) else 1)
+            r.round(p)
+            if per_round is not None:
+                per_round(i)
+
+    def restart():
+        r.set_partition(part0)
+        r.conn.zero_()
+        r.W.zero_()
+        torch.cuda.synchronize()
+
+    restart()
+    run_rounds(warmup)
+    torch.cuda.synchronize()
+    restart()
+    ctx.timing_read(reset=True)
+    ctx.timing(True, phases=["gain_tile"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    run_rounds(steps)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ctx.timing(False)
+    tile_ms, tile_cnt = ctx.timing_read(reset=True)["gain_tile"]
+    total_s = t2 - t1
+    final = upr.stats_dict(r.stats)
+
+    # the repeat: per-round phases, statistics, partitions and move counts
+    deg = np.diff(g.xadj).astype(np.int64)
+    nonhub = deg <= hub_t
+    weighted = g.adjwgt is not None
+    rec = []
+    nrep = steps if phase_rounds is None else min(steps, phase_rounds)
+
+    def per_round(i):
+        ph = ctx.timing_read(reset=True)
+        mv = upr.last_moves(ctx, g.n)
+        tgt = mv["target"].cpu().numpy()
+        acc = mv["accept"].cpu().numpy().astype(bool)
+        cand = tgt >= 0
+        rec.append({"phases": {k_: v[0] for k_, v in ph.items()},
+                    "counts": {k_: v[1] for k_, v in ph.items()},
+                    "stats": r.stats.cpu().numpy().copy(),
+                    "part": r.part.cpu().numpy().copy(), "W": r.W.cpu().numpy().copy(),
+                    "cand_edges": int(deg[cand & nonhub].sum()),
+                    "acc_edges": int(deg[acc].sum()), "acc_nodes": int(acc.sum())})
+
+    restart()
+    ctx.timing_read(reset=True)
+    ctx.timing(True)
+    run_rounds(nrep, per_round)
+    torch.cuda.synchronize()
+    ctx.timing(False)
+    if nrep == steps and upr.stats_dict(rec[-1]["stats"]) != final:
+        raise RuntimeError("the repeated rounds gave different statistics")
+
+    n, nnz = g.n, g.nnz
+    ew = 8 if weighted else 4
+    # per-kernel rooflines over the repeated rounds (algorithmic bytes per launch)
+    bm_bytes = sum(4 * n * k + 16 * n for _ in rec)
+    bm_s = sum(x["phases"]["best_move_kernel"] for x in rec) / 1e3
+    fl_bytes = sum(ew * x["cand_edges"] + 17 * n for x in rec)
+    fl_s = sum(x["phases"]["filter_kernel"] for x in rec) / 1e3
+    dirty_threshold = nnz // dirty_div
+    delta = [x for x in rec if x["acc_edges"] <= dirty_threshold and x["acc_edges"] > 0]
+    ap_bytes = sum((ew + 16) * x["acc_edges"] for x in delta)
+    ap_s = sum(x["phases"]["apply"] for x in delta) / 1e3
+    avg_tile_s = tile_ms / 1e3 / max(tile_cnt, 1)
+    algo = gain_tile_bytes(n, nnz, k, weighted)
+    rooflines = {
+        "k_gain_tile": {**roofline_entry("k_gain_tile", algo * tile_cnt, tile_ms / 1e3, tile_cnt,
+                                         "8(n+1) + 4nnz [+4nnz weights] + 4n + 4nk"),
+                        "note": "timed region"},
+        "k_best_move": roofline_entry("k_best_move", bm_bytes, bm_s, len(rec), "4nk + 16n"),
+        "k_filter": roofline_entry("k_filter", fl_bytes, fl_s, len(rec),
+                                   "4 (+4 weights) per candidate edge + 17n"),
+        "k_apply": roofline_entry("k_apply (delta rounds)", ap_bytes, ap_s, len(delta),
+                                  "(4 [+4 weights] + 16) per moved edge; rounds whose moved "
+                                  "edges stay under the tile-rebuild threshold"),
+    }
+    phases = {k_: round(sum(x["phases"][k_] for x in rec) / max(len(rec), 1), 4)
+              for k_ in rec[0]["phases"]} if rec else {}
+    return {"value": g.m * steps / total_s, "ms_per_step": 1e3 * total_s / steps,
+            "final": final, "info": info, "rooflines": rooflines, "phases": phases,
+            "avg_tile_s": avg_tile_s, "tile_cnt": tile_cnt, "algo": algo, "rec": rec,
+            "refiner": r}
+
+
+def parity(rec, orc):
+    """GPU rounds against the oracle's: statistics, partition and block
+    weights after every round both ran."""
+    nchk = min(len(rec), len(orc))
+    ok = True
+    for i in range(nchk):
+        st, part, W = orc[i]
+        ok &= bool(np.array_equal(rec[i]["stats"][:9], st[:9]))
+        ok &= bool(np.array_equal(rec[i]["part"], part))
+        ok &= bool(np.array_equal(rec[i]["W"], W))
+    return nchk, ok
 
 
 def batched_vs_plain(ctx, spec, eps=(3, 100), rounds=10):
@@ -258,6 +417,38 @@ def serving(ctx, spec, eps=(3, 100), rounds=10, load=0.7, budget_gb=200.0, check
             "server_time_s": tim}
 
 
+def extra_workload(ctx, name, steps, warmup, cpu_seconds, oracle_rounds, no_cpu):
+    """One more single-graph workload: edges/s over its rounds, its kernel
+    rooflines, and the oracle's first rounds for the baseline and parity
+    (statistics, partition and block weights)."""
+    from paper_2308_15494_amd import graphgen as gg
+    t0 = time.perf_counter()
+    g, k, eps, rounds, seed = gg.workload(name)
+    part0 = gg.random_partition(g.n, k, seed)
+    log(f"workload {name}: n={g.n} m={g.m} k={k} max_deg={g.meta['max_degree']} "
+        f"gen {time.perf_counter() - t0:.1f}s")
+    res = single_graph(ctx, g, k, eps, rounds, part0, steps, warmup, False,
+                       phase_rounds=max(oracle_rounds, 3))
+    res.pop("refiner").plan.close()
+    out = {"value": res["value"], "unit": "edges/s", "ms_per_step": res["ms_per_step"],
+           "steps": steps, "config": {"n": g.n, "m": g.m, "k": k, "eps": f"{eps[0]}/{eps[1]}",
+                                      "rounds": rounds, "weighted": g.adjwgt is not None,
+                                      "max_degree": res["info"]["max_degree"],
+                                      "hubs": res["info"]["num_hubs"], "form": "rebuild"},
+           "roofline": res["rooflines"]["k_gain_tile"], "rooflines": res["rooflines"],
+           "phases_ms_per_round": res["phases"], "final_stats": res["final"]}
+    log(f"{name}: {out['value']:.3e} edges/s, {out['ms_per_step']:.3f} ms per round")
+    if not no_cpu:
+        base, orc = cpu_baseline(g, k, eps, rounds, part0, cpu_seconds, max_rounds=oracle_rounds)
+        nchk, ok = parity(res["rec"], orc)
+        out["cpu_baseline"] = base
+        out["parity_rounds_checked"] = nchk
+        out["parity_ok"] = ok
+        log(f"{name}: oracle {base['value']:.3e} edges/s; parity over {nchk} rounds "
+            f"(stats, partition, block weights): {ok}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,6 +466,10 @@ def main():
                     help="graphs of the batched-vs-plain leg (0 skips it)")
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests of the serving leg (0 skips it)")
+    ap.add_argument("--extra", default="grid2048,chunglu8m",
+                    help="comma-separated further single-graph workloads ('' skips them)")
+    ap.add_argument("--extra-oracle-rounds", type=int, default=1,
+                    help="oracle rounds per further workload (baseline and parity)")
     ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--tune", action="store_true",
                     help="autotune the traversal thresholds before timing (default: the "
@@ -314,7 +509,6 @@ def main():
     log(f"workload {args.workload}: n={g.n} m={g.m} k={k} max_deg={g.meta['max_degree']} "
         f"gen {time.perf_counter() - t0:.1f}s")
 
-    dev = torch.device("cuda", 0)
     ctx = upr.Context(0)
     opts, tune_rep = None, None
     if args.tune:
@@ -324,77 +518,22 @@ def main():
         opts, tune_rep = tune.tune_graph(ctx, g, k, part0, eps, rounds=3, repeats=2,
                                          total_rounds=rounds)
         log(f"tuned thresholds {tune_rep['chosen']} in {time.perf_counter() - t0:.1f}s")
-    r = upr.Refiner(g, k, ctx=ctx, opts=opts)
-    plan_info = r.plan.info()
-    stream = torch.cuda.current_stream()
-
-    def run_rounds(count, record=None):
-        for i in range(1, count + 1):
-            p = upr.params(k, eps, tau=gg.tau_schedule(i, rounds),
-                           rebuild_table=0 if (args.resident and i > 1) else 1)
-            r.round(p)
-            if record is not None:
-                record.append(r.stats.clone())
-
-    # warmup from the initial partition, then reset
-    r.set_partition(part0)
-    run_rounds(args.warmup)
-    torch.cuda.synchronize()
-
-    def restart():
-        r.set_partition(part0)
-        r.conn.zero_()
-        r.W.zero_()
-        torch.cuda.synchronize()
-
-    # timed: only the gain-table kernel is bracketed by events (its launch
-    # duration for the roofline)
-    restart()
-    ctx.timing_read(reset=True)
-    ctx.timing(True, phases=["gain_tile"])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    run_rounds(args.steps)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    ctx.timing(False)
-    tile_ms, tile_cnt = ctx.timing_read(reset=True)["gain_tile"]
-    total_s = t2 - t1
-    ms_per_step = 1e3 * total_s / args.steps
-    value = g.m * args.steps / total_s
-    final = upr.stats_dict(r.stats)
-
-    # the same rounds again from the same start, untimed: per-round statistics
-    # (checked against the oracle below) and the per-phase breakdown
-    restart()
-    recorded = []
-    ctx.timing(True)
-    run_rounds(args.steps, recorded)
-    torch.cuda.synchronize()
-    ctx.timing(False)
-    phases = ctx.timing_read(reset=True)
-    if upr.stats_dict(recorded[-1]) != final:
-        raise RuntimeError("the repeated rounds gave different statistics")
-
-    # dominant kernel: the gain-table tile kernel (phase 0)
-    avg_tile_s = tile_ms / 1e3 / max(tile_cnt, 1)
-    nnz_tile = g.nnz  # hubs are few; see the design doc for the exact per-launch accounting
-    algo = gain_tile_bytes(g.n, nnz_tile, k, g.adjwgt is not None)
-    achieved = algo / avg_tile_s / 1e9 if tile_cnt else None
-    roofline = {"bound": "hbm", "kernel": "k_gain_tile", "achieved": achieved,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                "traffic": stored_traffic(), "algorithmic_bytes": algo,
-                "avg_launch_us": avg_tile_s * 1e6}
+    res = single_graph(ctx, g, k, eps, rounds, part0, args.steps, args.warmup, args.resident,
+                       opts=opts)
+    res.pop("refiner").plan.close()
+    plan_info = res["info"]
+    head = dict(res["rooflines"]["k_gain_tile"])
+    head["traffic"] = stored_traffic()
+    head["algorithmic_bytes"] = res["algo"]
 
     out = {
         "metric": "edges/s per refine round (gain+move+rebalance), batched vs plain; p99 latency",
-        "value": value,
+        "value": res["value"],
         "unit": "edges/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -403,12 +542,25 @@ def main():
         "config": {"workload": args.workload, "n": g.n, "m": g.m, "k": k,
                    "eps": f"{eps[0]}/{eps[1]}", "rounds": rounds,
                    "form": "resident" if args.resident else "rebuild",
+                   "round": "sequence-aware filter price (seq_penalty=1), mode 0, tau_r = (18+r)/38",
                    "hubs": plan_info["num_hubs"], "max_degree": plan_info["max_degree"],
                    "thresholds": tune_rep["chosen"] if tune_rep else "default"},
-        "roofline": roofline,
-        "phases_ms_per_round": {k_: round(v[0] / max(args.steps, 1), 4) for k_, v in phases.items()},
-        "final_stats": final,
+        "roofline": head,
+        "rooflines": res["rooflines"],
+        "phases_ms_per_round": res["phases"],
+        "final_stats": res["final"],
+        "host": host_info(),
     }
+
+    if not args.no_cpu:
+        base, orc = cpu_baseline(g, k, eps, rounds, part0, args.cpu_seconds)
+        out["cpu_baseline"] = base
+        nchk, ok = parity(res["rec"], orc)
+        out["parity_rounds_checked"] = nchk
+        out["parity_ok"] = ok
+        log(f"cpu oracle {base['value']:.3e} edges/s; parity over {nchk} rounds "
+            f"(stats, partition, block weights): {ok}")
+    del res
 
     if bspec:
         out["batched"] = batched_vs_plain(ctx, bspec)
@@ -417,14 +569,13 @@ def main():
         out["serving"] = serving(ctx, sspec)
         log(f"serving: {out['serving']}")
 
-    if not args.no_cpu:
-        base, ostats = cpu_baseline(g, k, eps, rounds, part0, args.cpu_seconds)
-        out["cpu_baseline"] = base
-        nchk = min(len(ostats), len(recorded))
-        ok = all(np.array_equal(recorded[i].cpu().numpy()[:9], ostats[i][:9]) for i in range(nchk))
-        out["parity_rounds_checked"] = nchk
-        out["parity_ok"] = bool(ok)
-        log(f"cpu oracle {base['value']:.3e} edges/s; parity over {nchk} rounds: {ok}")
+    extra = [w for w in args.extra.split(",") if w]
+    if extra:
+        out["workloads"] = {}
+        for name in extra:
+            out["workloads"][name] = extra_workload(ctx, name, args.steps, 2, args.cpu_seconds,
+                                                    args.extra_oracle_rounds, args.no_cpu)
+            torch.cuda.empty_cache()
 
     print(json.dumps(out), flush=True)
 

@@ -128,7 +128,8 @@ int upr_plan_create(upr_ctx *ctx, const upr_graph *graph, upr_plan **out, hipStr
  * above hub_threshold are hubs (split into edge chunks of whole workgroups);
  * the apply rebuilds table tiles instead of atomic deltas once the moving
  * nodes' degrees sum above nnz / dirty_div (from twice that on, or above
- * nnz / UPR_REBUILD_ALL_DIV when set, every tile without marking any). low_threshold is ignored (the
+ * nnz / UPR_REBUILD_ALL_DIV when set but never below the marking threshold, every tile
+ * without marking any). low_threshold is ignored (the
  * apply no longer splits nodes by degree; the field keeps the layout). They
  * change only the speed, never a result; paper_2308_15494_amd/tune.py picks
  * them by timing trial rounds. */
@@ -295,12 +296,17 @@ int upr_penalty_table(int32_t tau_num, int32_t tau_den, int64_t *out);
  * milliseconds by HIP events while timing is enabled (each timed phase
  * records two events on the call's stream). Phases: 0 gain table,
  * 1 penalty buckets, 2 best move, 3 filter, 4 apply, 5 rebalance, 6 cut,
- * 7 whole call. Phase 0 is the gain-table kernel (its tiles and the hubs'
- * edge chunks), 1 the node statistics and penalty buckets.
+ * 7 whole call, 8 the best-move kernel alone, 9 the filter's edge-tile
+ * kernel alone. Phase 0 is the gain-table kernel (its tiles and the hubs'
+ * edge chunks), 1 the node statistics and penalty buckets, 2 the bucket
+ * prefix sums and the best-move kernel, 3 the whole conflict filter (edge
+ * tiles, hub chunks, sequence-aware price), 4 the apply of the filtered
+ * moves (table deltas or tile rebuilds included).
  * phase_mask: bit p times phase p (0 = off, UPR_TIMING_ALL = every phase).
- * counts[p] = number of intervals accumulated. */
-#define UPR_NUM_PHASES 8
-#define UPR_TIMING_ALL 0xFF
+ * ms and counts: arrays of UPR_NUM_PHASES; counts[p] = number of intervals
+ * accumulated. */
+#define UPR_NUM_PHASES 10
+#define UPR_TIMING_ALL 0x3FF
 int upr_timing_enable(upr_ctx *ctx, int phase_mask);
 int upr_timing_read(upr_ctx *ctx, double *ms, int64_t *counts, int reset);
 

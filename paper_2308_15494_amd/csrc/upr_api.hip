@@ -847,6 +847,10 @@ static int plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipSt
         // (UPR_REBUILD_ALL_DIV: from nnz / div on)
         const int64_t all_div = env_int("UPR_REBUILD_ALL_DIV", 0);
         p->all_threshold = all_div > 0 ? p->nnz / all_div : 2 * p->dirty_threshold;
+        // never below the marking threshold: between the two, the apply would
+        // skip the movers' edge walk (every tile is rebuilt) while the hub
+        // rows, rebuilt only above the marking threshold, still wait for deltas
+        p->all_threshold = std::max(p->all_threshold, p->dirty_threshold);
         if (dalloc(&p->wdeg, g.n) != hipSuccess || dalloc(&hub_list, g.n) != hipSuccess)
             return bail(UPR_E_NOMEM, "plan allocation failed");
         unsigned long long zero[8] = {0}, res[8];
@@ -1096,6 +1100,7 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
             HIP_TRY(c, launch_cb_prefix(bk, c->bucket, W, q->mode, c->pen1, s));
             // with the degree order, the flags and keys also in label order
             const bool rl = pv.flagged && pv.bytes == 1 && p->order;
+            PhaseTimer tk(c, 8, s);
             HIP_TRY(c, launch_best_move(p->g, bk, part, conn, W, c->bucket, c->pen1, q->mode,
                                         active, c->key, c->pen, c->counters,
                                         pv.flagged ? (uint8_t *)c->pc : nullptr, s,
@@ -1110,10 +1115,13 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
             PhaseTimer t(c, 3, s);
             int64_t *gp_out = q->seq_penalty ? c->gp : nullptr;
             const bool rl = pv.flagged && pv.bytes == 1 && p->order;
-            HIP_TRY(c, launch_filter(p->g, bk, optimistic, part, pv, c->key, c->pen, p->hub_t,
-                                     c->mvto, c->accflag, c->counters, gp_out, s,
-                                     rl ? p->adj_r : nullptr, rl ? tpv : PartView{},
-                                     rl ? c->key2 : nullptr));
+            {
+                PhaseTimer tk(c, 9, s);
+                HIP_TRY(c, launch_filter(p->g, bk, optimistic, part, pv, c->key, c->pen, p->hub_t,
+                                         c->mvto, c->accflag, c->counters, gp_out, s,
+                                         rl ? p->adj_r : nullptr, rl ? tpv : PartView{},
+                                         rl ? c->key2 : nullptr));
+            }
             HIP_TRY(c, launch_filter_hub(p->g, bk, optimistic, part, pv, c->key, c->pen, h,
                                          c->mvto, c->accflag, c->counters, gp_out, s));
             if (q->seq_penalty) {

@@ -28,6 +28,8 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -64,12 +66,62 @@ class Graph:
         return int(self.n if self.vwgt is None else int(self.vwgt.astype(np.int64).sum()))
 
 
+def _workers() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _threaded(fn, arr, out_dtype, chunk=1 << 22):
+    """fn applied to consecutive chunks of arr on a thread pool (numpy's
+    searching and sorting routines release the GIL), concatenated."""
+    if arr.size <= chunk or _workers() == 1:
+        return fn(arr).astype(out_dtype, copy=False)
+    out = np.empty(arr.size, dtype=out_dtype)
+
+    def run(i):
+        out[i:i + chunk] = fn(arr[i:i + chunk])
+
+    with ThreadPoolExecutor(_workers()) as ex:
+        list(ex.map(run, range(0, arr.size, chunk)))
+    return out
+
+
+def _argsort(key: np.ndarray) -> np.ndarray:
+    """An ordering of key by value (equal keys in any order). Large inputs
+    are split by value into buckets at sampled splitters, and the buckets
+    are sorted on a thread pool."""
+    if key.size < (1 << 23) or _workers() == 1:
+        return np.argsort(key, kind="stable")
+    nb = 4 * _workers()
+    sample = np.sort(key[:: max(key.size // 65536, 1)])
+    spl = sample[np.linspace(0, sample.size - 1, nb + 1)[1:-1].astype(np.int64)]
+    bucket = _threaded(lambda x: np.searchsorted(spl, x, side="right"), key, np.int16)
+    counts = np.bincount(bucket, minlength=nb)
+    by_bucket = np.argsort(bucket, kind="stable")
+    del bucket
+    starts = np.concatenate([[0], np.cumsum(counts)])
+    out = np.empty(key.size, dtype=np.int64)
+
+    def run(b):
+        idx = by_bucket[starts[b]:starts[b + 1]]
+        out[starts[b]:starts[b + 1]] = idx[np.argsort(key[idx], kind="stable")]
+
+    with ThreadPoolExecutor(_workers()) as ex:
+        list(ex.map(run, range(nb)))
+    return out
+
+
+def searchsorted_right(cdf: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """np.searchsorted(cdf, x, side="right"), on a thread pool for large x."""
+    return _threaded(lambda c: np.searchsorted(cdf, c, side="right"), x, np.int64)
+
+
 def csr_from_undirected(n: int, u: np.ndarray, v: np.ndarray,
                         w: np.ndarray | None = None) -> tuple:
     """Symmetric CSR from undirected pairs.
 
     Self-loops are dropped; duplicate pairs (in either orientation) are merged,
-    keeping the weight of the first occurrence. Rows come out sorted.
+    keeping the weight of the first occurrence. Rows come out sorted: row x
+    lists its smaller neighbours, then its larger ones, each ascending.
     """
     u = np.asarray(u, dtype=np.int64)
     v = np.asarray(v, dtype=np.int64)
@@ -77,26 +129,57 @@ def csr_from_undirected(n: int, u: np.ndarray, v: np.ndarray,
     u, v = u[keep], v[keep]
     if w is not None:
         w = np.asarray(w)[keep]
-    lo = np.minimum(u, v)
-    hi = np.maximum(u, v)
-    key = lo * n + hi
-    key, first = np.unique(key, return_index=True)
+    key = np.minimum(u, v) * n + np.maximum(u, v)
+    del u, v, keep
+    if w is None:
+        key = np.unique(key)
+    else:
+        # sorted distinct keys, each with the weight of its first draw
+        order = _argsort(key)
+        ks = key[order]
+        first = np.ones(ks.size, dtype=bool)
+        first[1:] = ks[1:] != ks[:-1]
+        starts = np.flatnonzero(first)
+        key = ks[starts]
+        del ks, first
+        if starts.size:
+            w = w[np.minimum.reduceat(order, starts)].astype(np.int32)
+        else:
+            w = w[:0].astype(np.int32)
+        del order, starts
     lo = key // n
-    hi = key % n
-    if w is not None:
-        w = w[first].astype(np.int32)
-    src = np.concatenate([lo, hi])
-    dst = np.concatenate([hi, lo])
-    order = np.argsort(src * n + dst, kind="stable")
-    src = src[order]
-    dst = dst[order]
-    counts = np.bincount(src, minlength=n) if n > 0 else np.zeros(0, np.int64)
+    hi = key - lo * n
+    del key
+    below = np.bincount(hi, minlength=n) if n > 0 else np.zeros(0, np.int64)
+    above = np.bincount(lo, minlength=n) if n > 0 else np.zeros(0, np.int64)
     xadj = np.zeros(n + 1, dtype=np.int64)
-    np.cumsum(counts, out=xadj[1:])
-    adjncy = dst.astype(np.int32)
-    adjwgt = None
+    np.cumsum(below + above, out=xadj[1:])
+    nnz = int(xadj[-1])
+    adjncy = np.empty(nnz, dtype=np.int32)
+    adjwgt = None if w is None else np.empty(nnz, dtype=np.int32)
+    m = lo.size
+    rank = np.arange(m, dtype=np.int64)
+    # larger neighbours: the pairs are sorted by (lo, hi) already
+    first_above = np.cumsum(above) - above
+    pos = xadj[lo] + below[lo] + (rank - first_above[lo])
+    adjncy[pos] = hi
     if w is not None:
-        adjwgt = np.concatenate([w, w])[order].astype(np.int32)
+        adjwgt[pos] = w
+    # smaller neighbours: the pairs sorted by (hi, lo)
+    if w is None:
+        kb = np.sort(hi * n + lo)
+        row = kb // n
+        col = kb - row * n
+        wb = None
+    else:
+        ob = _argsort(hi * n + lo)
+        row, col, wb = hi[ob], lo[ob], w[ob]
+        del ob
+    first_below = np.cumsum(below) - below
+    pos = xadj[row] + (rank - first_below[row])
+    adjncy[pos] = col
+    if wb is not None:
+        adjwgt[pos] = wb
     return xadj, adjncy, adjwgt
 
 
@@ -117,9 +200,20 @@ def _chung_lu_weights(n: int, avg_deg: float, beta: float, d_max: float) -> np.n
     """
     i = np.arange(n, dtype=np.float64)
     gamma = 1.0 / (beta - 1.0)
+    buf = np.empty(n, dtype=np.float64)
+
+    def fill(i0: float, lo: int, hi: int):
+        buf[lo:hi] = d_max * (i0 / (i[lo:hi] + i0)) ** gamma
 
     def mean_for(i0: float) -> float:
-        return float((d_max * (i0 / (i + i0)) ** gamma).mean())
+        # the elementwise values on a thread pool, the mean over the whole array
+        if n < (1 << 20) or _workers() == 1:
+            fill(i0, 0, n)
+        else:
+            step = (n + _workers() - 1) // _workers()
+            with ThreadPoolExecutor(_workers()) as ex:
+                list(ex.map(lambda lo: fill(i0, lo, min(lo + step, n)), range(0, n, step)))
+        return float(buf.mean())
 
     lo, hi = 1e-9, float(n) * 1e6
     for _ in range(200):
@@ -147,8 +241,8 @@ def chung_lu(n: int, avg_deg: float, beta: float, seed: int, d_max: float | None
     cdf = np.cumsum(w)
     cdf /= cdf[-1]
     pairs = int(n * avg_deg // 2)
-    a = np.searchsorted(cdf, rng.random(pairs), side="right")
-    b = np.searchsorted(cdf, rng.random(pairs), side="right")
+    a = searchsorted_right(cdf, rng.random(pairs))
+    b = searchsorted_right(cdf, rng.random(pairs))
     np.minimum(a, n - 1, out=a)
     np.minimum(b, n - 1, out=b)
     ew = rng.integers(1, wmax + 1, size=pairs, dtype=np.int32) if wmax > 0 else None
@@ -347,8 +441,16 @@ def generate_parallel(fn, count: int, workers: int, **kw):
     chunks = [(i, min(i + (count + workers - 1) // workers, count))
               for i in range(0, count, (count + workers - 1) // workers)]
     ctx = mp.get_context("fork")
-    with ctx.Pool(len(chunks)) as pool:
+    pool = ctx.Pool(len(chunks))
+    try:
         parts = pool.starmap(_gen_range, [(fn.__name__, a, b, seed0, kw) for a, b in chunks])
+    except BaseException:
+        pool.terminate()
+        pool.join()
+        raise
+    # the workers exit on their own (no terminate, no signal)
+    pool.close()
+    pool.join()
     return [x for part in parts for x in part]
 
 

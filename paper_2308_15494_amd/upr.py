@@ -21,7 +21,8 @@ ERRORS = {-1: "UPR_E_ARG", -2: "UPR_E_GRAPH", -3: "UPR_E_INFEASIBLE", -4: "UPR_E
 STATS_LEN = 12
 STAT_NAMES = ["l_max", "cut_before", "cut_after_moves", "cut_after", "candidates",
               "accepted", "rebalance_moves", "rebalance_iters", "status"]
-PHASES = ["gain_tile", "stats", "best_move", "filter", "apply", "rebalance", "cut", "call"]
+PHASES = ["gain_tile", "stats", "best_move", "filter", "apply", "rebalance", "cut", "call",
+          "best_move_kernel", "filter_kernel"]
 MODES = {"penalised": 0, "constrained": 1, "free": 2, "limited": 3}
 
 
@@ -205,15 +206,15 @@ class Context:
         mask = 0
         if enable:
             if phases is None:
-                mask = 0xFF
+                mask = (1 << len(PHASES)) - 1
             else:
                 for ph in phases:
                     mask |= 1 << (PHASES.index(ph) if isinstance(ph, str) else int(ph))
         self.check(lib().upr_timing_enable(self.handle, mask))
 
     def timing_read(self, reset=True) -> dict:
-        ms = np.zeros(8, np.float64)
-        cnt = np.zeros(8, np.int64)
+        ms = np.zeros(len(PHASES), np.float64)
+        cnt = np.zeros(len(PHASES), np.int64)
         self.check(lib().upr_timing_read(self.handle, ms.ctypes.data, cnt.ctypes.data, int(reset)))
         return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(PHASES)}
 

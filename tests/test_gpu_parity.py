@@ -493,26 +493,19 @@ def test_errors(upr, ctx):
     pr.compare(ost, odbg, "after errors")
 
 
-# ------------------------------------------------------------ full size --
+# ------------------------------------------------------------ apply modes --
+# (the full-size workloads are compared in test_gpu_fullsize.py)
 
-def test_rmat20_full_rounds(upr, ctx):
-    """R-MAT scale 20, k = 64: the benchmarked workload, bit-exact after every
-    round (first 6 of its 20 rounds; each oracle round is ~1 s on one core)."""
-    g, k, eps, rounds, seed = gg.workload("rmat20")
-    say(f"rmat20 n={g.n} m={g.m}")
-    pr = Pair(upr, ctx, g, k, gg.random_partition(g.n, k, seed))
-    for r in range(1, 7):
-        say(f"rmat20 round {r}")
-        ost, odbg = pr.round(eps=eps, tau=gg.tau_schedule(r, rounds))
-        pr.compare(ost, odbg, f"rmat20 round {r}")
-
-
-@pytest.mark.parametrize("div,all_div", [("1", "0"), ("100000000", "1"), ("100000000", "0")],
-                         ids=["delta", "rebuild_marked", "rebuild_all"])
+@pytest.mark.parametrize("div,all_div", [("1", "0"), ("100000000", "1"), ("100000000", "0"),
+                                         ("1", "100000000"), ("16", "32")],
+                         ids=["delta", "rebuild_marked", "rebuild_all", "all_below_marking",
+                              "all_div_above_dirty_div"])
 def test_apply_modes(upr, ctx, monkeypatch, div, all_div):
     """The ways of updating the table after moves (integer-atomic deltas,
     marking and rebuilding the tiles of the movers' neighbours, or rebuilding
-    every tile) give the oracle's table."""
+    every tile) give the oracle's table. The last two cases ask for a
+    whole-table threshold below the marking one (it is raised to the marking
+    threshold, so hub rows get their deltas whenever tiles are not marked)."""
     monkeypatch.setenv("UPR_DIRTY_DIV", div)
     monkeypatch.setenv("UPR_REBUILD_ALL_DIV", all_div)
     monkeypatch.setenv("UPR_HUB_THRESHOLD", "64")

@@ -26,6 +26,19 @@ def segment_bounds(odbg, part0, k):
     return int(inflow.max()), int((inflow + outflow).max())
 
 
+def exact_segment_sizes(g, k, part0, odbg):
+    """Events of each block's segment: the eligible candidates entering it,
+    plus those leaving it that are not available for rebalancing (the
+    availability from the oracle's penalty buckets of the round-start
+    partition)."""
+    from oracle import oracle as O
+    _, avail = O.penalty_buckets(g, k, part0, O.gain_table(g, k, part0))
+    elig = (odbg["target"] >= 0) & (odbg["gp"] > 0)
+    inflow = np.bincount(odbg["target"][elig], minlength=k)
+    outflow = np.bincount(part0[elig & (avail == 0)], minlength=k)
+    return inflow + outflow
+
+
 @pytest.mark.parametrize("n,k,lo,hi", [
     (6000, 64, 1, 256),          # one key per thread
     (30000, 64, 257, 1024),      # 4 keys per thread
@@ -134,8 +147,12 @@ def test_segment_large_buckets(upr, monkeypatch, avg):
             ost, odbg = pr.round(tau=tau, mode=mode)
             pr.compare(ost, odbg, f"avg {avg} round {r}")
             if r == 1:
-                # the segment is split, into buckets of about avg events
-                assert segment_bounds(odbg, p0, k)[0] > avg
+                # the segment is split, into buckets of about avg events: the
+                # largest bucket is at least the average, which is above one
+                # LDS sort (2048 keys) for 3000 and above two (4096) for 9000
+                m = exact_segment_sizes(g, k, p0, odbg).max()
+                nb = 1 if m <= 2048 else -(-m // avg)
+                assert m / nb > {3000: 2048, 9000: 4096}[avg], (m, nb)
         pr.plan.close()
     finally:
         c.close()
