@@ -172,6 +172,23 @@ int upr_block_weights(upr_ctx *ctx, const upr_plan *plan, int32_t k, const int32
 int upr_edge_cut(upr_ctx *ctx, const upr_plan *plan, const int32_t *part, int64_t *cut,
                  hipStream_t stream);
 
+/* Edge cut without device allocation. For callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops and
+ * harnesses that forbid hipMalloc. Same result as upr_edge_cut (the
+ * Section 2 objective), taken from the graph directly, so no plan is needed:
+ * graph: device arrays as in upr_graph (vwgt is not read); part: device
+ * int32 [n], any values (only equality is tested); cut: device int64 [1],
+ * out. The context is used for its device and its error message only.
+ * Scratch: a static device array of 2^18 partial sums per device (2 MiB),
+ * one per tile of 1024 nodes, held until the process ends; hence
+ * n <= UPR_NOALLOC_MAX_NODES, and a larger n gives UPR_E_ARG with nothing
+ * enqueued. Calls no allocating routine; every call on a device shares that
+ * device's array, so calls that overlap on one device (other streams or
+ * threads) race and must be serialised by the caller. */
+#define UPR_NOALLOC_MAX_NODES ((int64_t)1 << 28)
+int upr_edge_cut_noalloc(upr_ctx *ctx, const upr_graph *graph, const int32_t *part, int64_t *cut,
+                         hipStream_t stream);
+
 /* One refinement round, in place on (part, conn, block_w):
  *   S1 gain table and block weights (if params->rebuild_table), cut;
  *   penalty buckets of the rebalance-available nodes (Section 5.3);

@@ -48,11 +48,14 @@ int64_t env_int(const char *name, int64_t dflt)
 
 struct upr_ctx {
     int device = 0;
+    // device address of the no-allocation scratch array on this device (null:
+    // not available, upr_edge_cut_noalloc then fails)
+    void *noalloc = nullptr;
     // target bucket size of the sequence-aware price's split segments
     // (UPR_SEQ_BUCKET_AVG, read at creation; never below the default, which
     // sizes the bucket tables)
     int32_t seq_bucket_avg = 0;
-    std::string err;
+    char err[512] = {0};  // last error (fixed storage: reporting an error allocates nothing)
     // workspace
     int64_t cap_n = 0, cap_k = 0;
     int64_t *key = nullptr, *pen = nullptr;
@@ -174,7 +177,7 @@ int fail(upr_ctx *c, int code, const char *fmt, ...)
     va_start(ap, fmt);
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
-    if (c) c->err = buf;
+    if (c) snprintf(c->err, sizeof c->err, "%s", buf);
     return code;
 }
 
@@ -684,6 +687,12 @@ int upr_create(upr_ctx **out, int device)
         return UPR_E_NOMEM;
     }
     (void)hipMemset(c->counters, 0, sizeof(unsigned long long) * kCntWords);
+    // the no-allocation scratch of this device (its address is taken once per
+    // device; without it only upr_edge_cut_noalloc is unavailable)
+    if (noalloc_init(device, &c->noalloc) != hipSuccess) {
+        (void)hipGetLastError();
+        c->noalloc = nullptr;
+    }
     // the published counters: without host-coherent memory the rebalancing
     // loop copies the counters and waits for the stream instead
     if (hipHostMalloc((void **)&c->pub, sizeof(unsigned long long) * (1 + CNT_COUNT),
@@ -724,7 +733,7 @@ void upr_destroy(upr_ctx *c)
 const char *upr_last_error(const upr_ctx *c)
 {
     if (!c) return "null context";
-    return c->err.c_str();
+    return c->err;
 }
 
 int upr_validate_graph(upr_ctx *c, const upr_graph *graph, hipStream_t s)
@@ -1010,6 +1019,22 @@ int upr_edge_cut(upr_ctx *c, const upr_plan *p, const int32_t *part, int64_t *cu
     HIP_TRY(c, hipMemsetAsync(c->counters, 0, sizeof(unsigned long long) * kCntWords, s));
     HIP_TRY(c, launch_cut_edges(p->g, part, c->counters, CNT_TMP, s));
     HIP_TRY(c, launch_store_half(c->counters, CNT_TMP, cut, s));
+    return UPR_OK;
+}
+
+int upr_edge_cut_noalloc(upr_ctx *c, const upr_graph *graph, const int32_t *part, int64_t *cut,
+                         hipStream_t s)
+{
+    if (!c) return UPR_E_ARG;
+    if (!graph || !cut) return fail(c, UPR_E_ARG, "graph/cut NULL");
+    if (graph->n < 0 || graph->n > UPR_NOALLOC_MAX_NODES)
+        return fail(c, UPR_E_ARG, "n=%lld outside [0, %lld], the no-allocation scratch limit",
+                    (long long)graph->n, (long long)UPR_NOALLOC_MAX_NODES);
+    if (graph->n > 0 && (!graph->xadj || !part)) return fail(c, UPR_E_ARG, "xadj/part NULL");
+    if (!c->noalloc) return fail(c, UPR_E_HIP, "the no-allocation scratch of device %d is unavailable", c->device);
+    HIP_TRY(c, hipSetDevice(c->device));
+    const GraphView g{graph->n, graph->xadj, graph->adjncy, graph->adjwgt, graph->vwgt};
+    HIP_TRY(c, launch_cut_noalloc(g, part, cut, c->noalloc, s));
     return UPR_OK;
 }
 
@@ -1360,7 +1385,7 @@ int upr_batch_create(upr_ctx *c, const upr_graph *graphs, const int64_t *nnz_hos
     const upr_graph ug{b->n, b->xadj, b->adjncy, b->adjwgt, b->vwgt};
     int rc = plan_create(c, &ug, &b->plan, s, !trusted, b->nnz, opts, true);
     if (rc) {
-        const std::string msg = c->err;
+        const std::string msg(c->err);
         upr_batch_destroy(b);
         return fail(c, rc, "batch plan: %s", msg.c_str());
     }

@@ -705,6 +705,13 @@ hipError_t launch_rb_iteration(const GraphView &g, const Blocks &bk, const int32
                                int64_t *gstat, hipStream_t s);
 int rb_scan_grid(int64_t n);
 
+// no-allocation edge cut (noalloc.hip): the device address of the scratch
+// array on `device` (which the caller made current), taken once per device;
+// then the two-pass cut with that address.
+hipError_t noalloc_init(int device, void **ptr);
+hipError_t launch_cut_noalloc(const GraphView &g, const int32_t *part, int64_t *cut,
+                              void *scratch_ptr, hipStream_t s);
+
 // batches (k_batch.hip)
 hipError_t launch_batch_copy(const GraphView &src, int64_t node_off, int64_t edge_off,
                              int64_t nnz, int64_t *xadj, int32_t *adjncy, int32_t *adjwgt,

@@ -75,6 +75,8 @@ _SIGS = [
     ("upr_block_weights", C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                     C.c_void_p]),
     ("upr_edge_cut", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("upr_edge_cut_noalloc", C.c_int, [C.c_void_p, C.POINTER(_Graph), C.c_void_p, C.c_void_p,
+                                       C.c_void_p]),
     ("upr_refine_round", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(Params), C.c_void_p,
                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("upr_rebalance", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(Params), C.c_void_p,
@@ -308,6 +310,17 @@ def edge_cut(ctx, plan, part, out=None, stream=None):
     if out is None:
         out = torch.empty(1, dtype=torch.int64, device=part.device)
     ctx.check(lib().upr_edge_cut(ctx.handle, plan.handle, _ptr(part), _ptr(out), _stream(stream)))
+    return out
+
+
+NOALLOC_MAX_NODES = 1 << 28
+
+
+def edge_cut_noalloc(ctx, dg, part, out, stream=None):
+    """upr_edge_cut_noalloc: the cut of part on DeviceGraph dg into the
+    caller's device int64 tensor out (nothing is allocated)."""
+    ctx.check(lib().upr_edge_cut_noalloc(ctx.handle, C.byref(dg.c), _ptr(part), _ptr(out),
+                                         _stream(stream)))
     return out
 
 
