@@ -7,7 +7,9 @@ host numpy arrays; the oracle works in place like the round it models.
 Statistics slots (int64[12]):
     0 l_max, 1 cut_before, 2 cut_after_moves, 3 cut_after, 4 candidates,
     5 accepted, 6 rebalance_moves, 7 rebalance_iters, 8 status (0 balanced,
-    1 rebalancing stuck or out of iterations), 9-11 unused.
+    1 rebalancing stuck or out of iterations), 9 prefix_steps and
+    10 reverted (best-prefix rounds: filtered moves kept, -1 if no boundary
+    was balanced; nodes returned to their round-start block), 11 unused.
 """
 from __future__ import annotations
 
@@ -23,7 +25,8 @@ LIB = os.path.join(HERE, "liborc.so")
 SLOTS = 54
 STATS = 12
 STAT_NAMES = ["l_max", "cut_before", "cut_after_moves", "cut_after", "candidates",
-              "accepted", "rebalance_moves", "rebalance_iters", "status"]
+              "accepted", "rebalance_moves", "rebalance_iters", "status", "prefix_steps",
+              "reverted"]
 
 
 def build(force: bool = True) -> str:
@@ -51,7 +54,9 @@ class _Params(C.Structure):
 
 class _Debug(C.Structure):
     _fields_ = [("target", C.c_void_p), ("score", C.c_void_p), ("pen", C.c_void_p),
-                ("accept", C.c_void_p), ("pen_seq", C.c_void_p), ("gp", C.c_void_p)]
+                ("accept", C.c_void_p), ("pen_seq", C.c_void_p), ("gp", C.c_void_p),
+                ("seq", C.c_void_p), ("bgain", C.c_void_p), ("bbal", C.c_void_p),
+                ("pref", C.c_void_p)]
 
 
 _lib = None
@@ -122,6 +127,7 @@ class Graph:
 
 OPTIMISTIC = 1        # variant bit: optimistic conflict filter
 PLAIN_PRIORITY = 2    # variant bit: rebalancing priority by the plain gain
+BEST_PREFIX = 4       # variant bit: interleaved move sequence and best prefix
 
 
 def params(k, eps=(3, 100), t=(7, 10), tau=(1, 1), mode=0, rebuild_table=1,
@@ -210,10 +216,11 @@ def refine_round(g, p: _Params, part, conn=None, W=None, debug=False, active=Non
     if debug:
         dbg = dict(target=np.zeros(G.n, np.int32), score=np.zeros(G.n, np.int64),
                    pen=np.zeros(G.n, np.int64), accept=np.zeros(G.n, np.uint8),
-                   pen_seq=np.zeros(G.n, np.int64), gp=np.zeros(G.n, np.int64))
-        dstruct = _Debug(dbg["target"].ctypes.data, dbg["score"].ctypes.data,
-                         dbg["pen"].ctypes.data, dbg["accept"].ctypes.data,
-                         dbg["pen_seq"].ctypes.data, dbg["gp"].ctypes.data)
+                   pen_seq=np.zeros(G.n, np.int64), gp=np.zeros(G.n, np.int64),
+                   seq=np.zeros(4 * max(G.n, 1), np.int64),
+                   bgain=np.zeros(G.n + 1, np.int64), bbal=np.zeros(G.n + 1, np.uint8),
+                   pref=np.full(4, -2, np.int64))
+        dstruct = _Debug(*[dbg[f].ctypes.data for f, _ in _Debug._fields_])
     if active is not None:
         _check(active, np.uint8, G.n, "active")
     rc = lib().orc_refine_round_active(C.byref(G.c), C.byref(p), part.ctypes.data,
@@ -222,6 +229,12 @@ def refine_round(g, p: _Params, part, conn=None, W=None, debug=False, active=Non
                                        None if active is None else active.ctypes.data)
     if rc != 0:
         raise ValueError(f"oracle refine_round rejected its arguments (rc={rc})")
+    if dbg is not None and dbg["pref"][0] >= 0:
+        # best-prefix round: trim the sequence and boundary arrays to size
+        ln, nm = int(dbg["pref"][0]), int(dbg["pref"][1])
+        dbg["seq"] = dbg["seq"][: 4 * ln].reshape(ln, 4)
+        dbg["bgain"] = dbg["bgain"][: nm + 1]
+        dbg["bbal"] = dbg["bbal"][: nm + 1]
     return stats, dbg
 
 

@@ -81,11 +81,16 @@ typedef struct {
 
 #define ORC_VAR_OPTIMISTIC 1
 #define ORC_VAR_PLAIN_PRIORITY 2
+#define ORC_VAR_BEST_PREFIX 4     /* interleaved move sequence and best prefix (Section 5.4) */
 
 /* Statistics, same order as the int64 slots the tests read. */
 enum {
     ST_LMAX = 0, ST_CUT_BEFORE, ST_CUT_AFTER_MOVES, ST_CUT_AFTER, ST_CANDIDATES,
-    ST_ACCEPTED, ST_REBAL_MOVES, ST_REBAL_ITERS, ST_STATUS, ST_COUNT = 12
+    ST_ACCEPTED, ST_REBAL_MOVES, ST_REBAL_ITERS, ST_STATUS,
+    ST_PREFIX_STEPS,  /* best-prefix rounds: moves of the filtered sequence kept (-1: no
+                         balanced boundary, nothing reverted) */
+    ST_REVERTED,      /* best-prefix rounds: nodes returned to their round-start block */
+    ST_COUNT = 12
 };
 
 /* Optional per-node outputs of the move phase (any pointer may be NULL). */
@@ -96,6 +101,11 @@ typedef struct {
     uint8_t *accept;  /* 1 if the move survived the conflict filter */
     int64_t *pen_seq; /* S3 penalty of a candidate (-1: forbidden), else 0 */
     int64_t *gp;      /* S3 pessimistic gain of a candidate, else 0 */
+    /* best-prefix rounds (any may be NULL): */
+    int64_t *seq;     /* [4 n] the interleaved sequence: (node, from, to, step) per move */
+    int64_t *bgain;   /* [n + 1] exact cumulative gain at each step boundary */
+    uint8_t *bbal;    /* [n + 1] 1 iff the partition at that boundary is balanced */
+    int64_t *pref;    /* [4] moves in the sequence, steps, best boundary, moves kept */
 } orc_debug;
 
 static int64_t edge_w(const orc_graph *g, int64_t e) { return g->adjwgt ? g->adjwgt[e] : 1; }
@@ -254,7 +264,8 @@ static int rb_cmp(const void *x, const void *y)
  * All of 1-4 read the sub-iteration's starting W and conn.
  */
 static int rebalance_iterate(const orc_graph *g, const orc_params *p, int64_t lmax, int32_t *part,
-                             int32_t *conn, int64_t *W, int64_t *moves_out, int64_t *iters_out)
+                             int32_t *conn, int64_t *W, int64_t *moves_out, int64_t *iters_out,
+                             int64_t *rec_iter, int32_t *rec_beta)
 {
     const int32_t k = p->k;
     const int64_t n = g->n;
@@ -344,9 +355,11 @@ static int rebalance_iterate(const orc_graph *g, const orc_params *p, int64_t lm
                 if (got < need) { sel[items[i].id] = 2; got += items[i].c; }
         }
 
-        /* step 5 */
+        /* step 5 (rec_iter / rec_beta, if given: the sub-iteration and the
+         * priority bucket of each move, the order in which it was made) */
         for (int64_t v = 0; v < n; ++v)
             if (sel[v] == 2) {
+                if (rec_iter) { rec_iter[v] = iters; rec_beta[v] = beta[v]; }
                 apply_move(g, k, part, conn, W, v, tgt[v]);
                 ++moved_now;
             }
@@ -427,6 +440,159 @@ static int cand_cmp(const void *x, const void *y)
     return u < v ? -1 : (u > v);
 }
 
+/* ------------------------------------------------------------ prefix -- */
+
+/* A rebalancing move in its list R_i: grouped by the block it left, in the
+ * order the rebalancer made it (sub-iteration, then priority bucket, then
+ * id: the order in which a source keeps its nodes). */
+typedef struct { int32_t from; int64_t iter; int32_t beta; int64_t id; } rmove;
+
+static int rmove_cmp(const void *x, const void *y)
+{
+    const rmove *a = (const rmove *)x, *b = (const rmove *)y;
+    if (a->from != b->from) return a->from < b->from ? -1 : 1;
+    if (a->iter != b->iter) return a->iter < b->iter ? -1 : 1;
+    if (a->beta != b->beta) return a->beta < b->beta ? -1 : 1;
+    return a->id < b->id ? -1 : (a->id > b->id);
+}
+
+static int all_balanced(const int64_t *W, int32_t k, int64_t lmax)
+{
+    for (int32_t j = 0; j < k; ++j)
+        if (W[j] > lmax) return 0;
+    return 1;
+}
+
+/* Interleaved move sequence and best prefix (Section 5.4, the last two steps
+ * of Algorithm 1), after S4 and S5 have run.
+ *
+ * part0 / W0: the round-start partition and block weights; part: after S5.
+ * order[0..nc): the candidates in the filter's order; accept: its decisions.
+ * rec_iter / rec_beta: sub-iteration (0: none) and bucket of S5's moves.
+ *
+ *  1. A node moved by both the filtered moves (a -> b) and the rebalancer
+ *     (b -> c) is combined into one move a -> c in the place of the first
+ *     (the footnote of Section 5.4); if c = a it is dropped. M is the
+ *     filtered moves in the filter's order, so combined; R_i the other
+ *     rebalancing moves out of block i, in the order they were made.
+ *  2. Interleave: starting from W0, append the moves of M one by one; when a
+ *     move m into block b leaves b overloaded, append the minimal prefix of
+ *     the unused moves of R_b that brings b back to L_max (all of them if
+ *     they do not suffice). A step is m with the moves it pulled in; the
+ *     boundaries after each step are the candidate prefixes.
+ *  3. Recompute each move's gain exactly at its position: a neighbour sits
+ *     in its new block if its move comes earlier in the sequence, else in
+ *     its round-start block.
+ *  4. Keep the prefix ending at the balanced boundary with the highest
+ *     cumulative gain (the earliest on ties); every other move of the round
+ *     is undone. With no balanced boundary nothing is undone.
+ * Returns the boundary kept (-1: none) and fills stats and dbg. */
+static int64_t best_prefix(const orc_graph *g, int32_t k, int64_t lmax, const int32_t *part0,
+                           const int64_t *W0, int32_t *part, int32_t *conn, int64_t *W,
+                           const int64_t *order, int64_t nc, const uint8_t *accept,
+                           const int64_t *rec_iter, const int32_t *rec_beta, int64_t *stats,
+                           const orc_debug *dbg)
+{
+    const int64_t n = g->n;
+    const size_t N = (size_t)(n > 0 ? n : 1);
+    /* 1. M (filter order, combined moves) and the lists R_i */
+    int64_t *mlist = (int64_t *)malloc(sizeof(int64_t) * N);
+    int64_t nm = 0;
+    for (int64_t i = 0; i < nc; ++i) {
+        const int64_t v = order[i];
+        if (accept[v] && part[v] != part0[v]) mlist[nm++] = v;
+    }
+    rmove *rl = (rmove *)malloc(sizeof(rmove) * N);
+    int64_t nr = 0;
+    for (int64_t v = 0; v < n; ++v)
+        if (rec_iter[v] > 0 && !accept[v]) {
+            rl[nr].from = part0[v]; rl[nr].iter = rec_iter[v];
+            rl[nr].beta = rec_beta[v]; rl[nr].id = v; ++nr;
+        }
+    qsort(rl, (size_t)nr, sizeof(rmove), rmove_cmp);
+    int64_t *rstart = (int64_t *)calloc((size_t)k + 1, sizeof(int64_t));
+    for (int64_t i = 0; i < nr; ++i) rstart[rl[i].from + 1]++;
+    for (int32_t j = 0; j < k; ++j) rstart[j + 1] += rstart[j];
+    int64_t *used = (int64_t *)calloc((size_t)k, sizeof(int64_t));
+
+    /* 2. interleave */
+    int64_t *Wc = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
+    memcpy(Wc, W0, sizeof(int64_t) * (size_t)k);
+    int64_t *seq_node = (int64_t *)malloc(sizeof(int64_t) * N);
+    int64_t *seq_step = (int64_t *)malloc(sizeof(int64_t) * N);
+    int32_t *seq_to = (int32_t *)malloc(sizeof(int32_t) * N);
+    uint8_t *bal = (uint8_t *)malloc((size_t)nm + 1);
+    int64_t len = 0;
+    bal[0] = (uint8_t)all_balanced(Wc, k, lmax);
+    for (int64_t j = 0; j < nm; ++j) {
+        const int64_t v = mlist[j];
+        const int32_t b = part[v];
+        Wc[part0[v]] -= node_c(g, v);
+        Wc[b] += node_c(g, v);
+        seq_node[len] = v; seq_step[len] = j; seq_to[len] = b; ++len;
+        while (Wc[b] > lmax && rstart[b] + used[b] < rstart[b + 1]) {
+            const int64_t r = rl[rstart[b] + used[b]].id;
+            ++used[b];
+            Wc[b] -= node_c(g, r);
+            Wc[part[r]] += node_c(g, r);
+            seq_node[len] = r; seq_step[len] = j; seq_to[len] = part[r]; ++len;
+        }
+        bal[j + 1] = (uint8_t)all_balanced(Wc, k, lmax);
+    }
+
+    /* 3. exact gains in sequence order */
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * N);
+    for (int64_t v = 0; v < n; ++v) pos[v] = -1;
+    for (int64_t i = 0; i < len; ++i) pos[seq_node[i]] = i;
+    int64_t *bgain = (int64_t *)calloc((size_t)nm + 1, sizeof(int64_t));
+    for (int64_t i = 0; i < len; ++i) {
+        const int64_t u = seq_node[i];
+        const int32_t a = part0[u], b = part[u];
+        int64_t gain = 0;
+        for (int64_t e = g->xadj[u]; e < g->xadj[u + 1]; ++e) {
+            const int64_t x = g->adjncy[e];
+            const int32_t bx = (pos[x] >= 0 && pos[x] < i) ? part[x] : part0[x];
+            gain += edge_w(g, e) * ((bx == b) - (bx == a));
+        }
+        bgain[seq_step[i] + 1] += gain;
+    }
+    for (int64_t j = 0; j < nm; ++j) bgain[j + 1] += bgain[j];
+
+    /* 4. best balanced boundary, earliest on ties */
+    int64_t best = -1;
+    for (int64_t j = 0; j <= nm; ++j)
+        if (bal[j] && (best < 0 || bgain[j] > bgain[best])) best = j;
+    int64_t kept = 0, reverted = 0;
+    if (best >= 0) {
+        for (int64_t v = 0; v < n; ++v) {
+            if (part[v] == part0[v]) continue;
+            if (pos[v] >= 0 && seq_step[pos[v]] < best) { ++kept; continue; }
+            apply_move(g, k, part, conn, W, v, part0[v]);
+            ++reverted;
+        }
+    }
+    stats[ST_PREFIX_STEPS] = best;
+    stats[ST_REVERTED] = reverted;
+    if (dbg) {
+        if (dbg->seq)
+            for (int64_t i = 0; i < len; ++i) {
+                const int64_t u = seq_node[i];
+                dbg->seq[4 * i] = u;
+                dbg->seq[4 * i + 1] = part0[u];
+                dbg->seq[4 * i + 2] = seq_to[i];
+                dbg->seq[4 * i + 3] = seq_step[i];
+            }
+        if (dbg->bgain) memcpy(dbg->bgain, bgain, sizeof(int64_t) * ((size_t)nm + 1));
+        if (dbg->bbal) memcpy(dbg->bbal, bal, (size_t)nm + 1);
+        if (dbg->pref) {
+            dbg->pref[0] = len; dbg->pref[1] = nm; dbg->pref[2] = best; dbg->pref[3] = kept;
+        }
+    }
+    free(mlist); free(rl); free(rstart); free(used); free(Wc); free(seq_node); free(seq_step);
+    free(seq_to); free(bal); free(pos); free(bgain);
+    return best;
+}
+
 /* ------------------------------------------------------------- rounds -- */
 
 static int check_params(const orc_graph *g, const orc_params *p, const int32_t *part)
@@ -436,7 +602,7 @@ static int check_params(const orc_graph *g, const orc_params *p, const int32_t *
     if (p->tau_num < 0 || p->tau_den <= 0 || p->tau_num > p->tau_den) return -1;
     if (p->mode < 0 || p->mode > 3) return -1;
     if (p->mode == 3 && (p->alpha_den <= 0 || p->alpha_num < p->alpha_den)) return -1;
-    if (p->variant & ~(ORC_VAR_OPTIMISTIC | ORC_VAR_PLAIN_PRIORITY)) return -1;
+    if (p->variant & ~(ORC_VAR_OPTIMISTIC | ORC_VAR_PLAIN_PRIORITY | ORC_VAR_BEST_PREFIX)) return -1;
     for (int64_t v = 0; v < g->n; ++v)
         if (part[v] < 0 || part[v] >= p->k) return -1;
     return 0;
@@ -565,10 +731,23 @@ int orc_refine_round_active(const orc_graph *g, const orc_params *p, int32_t *pa
         }
         if (eligible && allowed && gp * 65536 - P > 0) { accept[v] = 1; ++accepted; }
     }
-    free(order);
     free(net);
     free(avail);
     stats[ST_ACCEPTED] = accepted;
+
+    /* the round-start state, for the best prefix */
+    const int prefix = (p->variant & ORC_VAR_BEST_PREFIX) != 0;
+    int32_t *part0 = NULL;
+    int64_t *W0 = NULL, *rec_iter = NULL;
+    int32_t *rec_beta = NULL;
+    if (prefix) {
+        part0 = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+        W0 = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
+        rec_iter = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+        rec_beta = (int32_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
+        memcpy(part0, part, sizeof(int32_t) * (size_t)n);
+        memcpy(W0, W, sizeof(int64_t) * (size_t)k);
+    }
 
     /* S4: apply (commutative updates; the order does not matter). */
     for (int64_t v = 0; v < n; ++v)
@@ -577,9 +756,18 @@ int orc_refine_round_active(const orc_graph *g, const orc_params *p, int32_t *pa
 
     /* S5 */
     int64_t moves = 0, iters = 0;
-    stats[ST_STATUS] = rebalance_iterate(g, p, lmax, part, conn, W, &moves, &iters);
+    stats[ST_STATUS] = rebalance_iterate(g, p, lmax, part, conn, W, &moves, &iters, rec_iter,
+                                         rec_beta);
     stats[ST_REBAL_MOVES] = moves;
     stats[ST_REBAL_ITERS] = iters;
+
+    /* interleaved move sequence and best prefix */
+    if (prefix) {
+        if (best_prefix(g, k, lmax, part0, W0, part, conn, W, order, nc, accept, rec_iter,
+                        rec_beta, stats, dbg) >= 0)
+            stats[ST_STATUS] = 0;
+        free(part0); free(W0); free(rec_iter); free(rec_beta);
+    }
 
     /* S6 */
     stats[ST_CUT_AFTER] = orc_cut_table(g, k, part, conn);
@@ -595,6 +783,7 @@ int orc_refine_round_active(const orc_graph *g, const orc_params *p, int32_t *pa
         }
     }
     free(bucket); free(target); free(score); free(pen); free(accept); free(pen_seq); free(gps);
+    free(order);
     return 0;
 }
 
@@ -613,7 +802,7 @@ int orc_rebalance(const orc_graph *g, const orc_params *p, int32_t *part, int32_
     prepare(g, p, part, conn, W, stats, &lmax);
     stats[ST_CUT_AFTER_MOVES] = stats[ST_CUT_BEFORE];
     int64_t moves = 0, iters = 0;
-    stats[ST_STATUS] = rebalance_iterate(g, p, lmax, part, conn, W, &moves, &iters);
+    stats[ST_STATUS] = rebalance_iterate(g, p, lmax, part, conn, W, &moves, &iters, NULL, NULL);
     stats[ST_REBAL_MOVES] = moves;
     stats[ST_REBAL_ITERS] = iters;
     stats[ST_CUT_AFTER] = orc_cut_table(g, p->k, part, conn);

@@ -20,7 +20,8 @@ ERRORS = {-1: "UPR_E_ARG", -2: "UPR_E_GRAPH", -3: "UPR_E_INFEASIBLE", -4: "UPR_E
           -5: "UPR_E_HIP"}
 STATS_LEN = 12
 STAT_NAMES = ["l_max", "cut_before", "cut_after_moves", "cut_after", "candidates",
-              "accepted", "rebalance_moves", "rebalance_iters", "status"]
+              "accepted", "rebalance_moves", "rebalance_iters", "status", "prefix_steps",
+              "reverted"]
 PHASES = ["gain_tile", "stats", "best_move", "filter", "apply", "rebalance", "cut", "call",
           "best_move_kernel", "filter_kernel"]
 MODES = {"penalised": 0, "constrained": 1, "free": 2, "limited": 3}

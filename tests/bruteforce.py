@@ -332,3 +332,83 @@ def filter_decisions(g, k, part, t, tau, eps, mode=0, seq=True, alpha=(1, 1), op
         acc = P is not None and gp > 0 and gp * 65536 - P > 0
         out[v] = (acc, P)
     return out
+
+
+def rebalance_all(g, k, part, L, plain=False):
+    """Sub-iterations with the rules of rebalance_one_iteration until no block
+    is overloaded, nothing moved, or the iteration cap (k + 1 for unit node
+    weights, 4k otherwise). Returns the partition and the moves in the order
+    they were made: (node, from, to) per sub-iteration, each source's nodes
+    in (priority bucket, id) order, grouped by source block."""
+    part = list(part)
+    cap = k + 1 if g.vwgt is None else 4 * k
+    moves = []
+    for it in range(1, cap + 1):
+        W = [block_weight(g, part, j) for j in range(k)]
+        if all(w <= L for w in W):
+            break
+        new = rebalance_one_iteration(g, k, part, L, plain)
+        moved = [v for v in range(g.n) if new[v] != part[v]]
+        if not moved:
+            break
+        # the order of the rebalancer: per source, by (bucket, id), with the
+        # bucket of the move from the sub-iteration's starting partition
+        def bucket(v):
+            gain = move_gain(g, part, v, new[v])
+            return rebalance_bucket(gain, 1 if plain else node_w(g, v))
+        moved.sort(key=lambda v: (part[v], bucket(v), v))
+        moves += [(v, part[v], new[v]) for v in moved]
+        part = new
+    return part, moves
+
+
+def interleaved_best_prefix(g, k, part0, filtered, L, plain=False):
+    """Section 5.4 from its rules, on lists: `filtered` are the filtered moves
+    (node, target) in the filter's order, applied together to part0; the
+    rebalancer then runs; a node moved by both is one move from its start to
+    its end (dropped if it ends where it started); each filtered move is
+    followed by the fewest unused rebalancing moves out of its target block
+    (in the rebalancer's order) that leave that block at most L; exact gains
+    are cut differences. Returns (final partition, best boundary or -1,
+    cumulative gains per boundary, balanced flags per boundary)."""
+    after = list(part0)
+    for v, t in filtered:
+        after[v] = t
+    final, rmoves = rebalance_all(g, k, after, L, plain)
+    fset = {v for v, _ in filtered}
+    seq_m = [(v, part0[v], final[v]) for v, _ in filtered if final[v] != part0[v]]
+    rlists = {}
+    for v, a, b in rmoves:
+        if v not in fset:
+            rlists.setdefault(a, []).append((v, a, b))
+    used = {j: 0 for j in range(k)}
+    cur = list(part0)
+
+    def balanced(p):
+        return all(block_weight(g, p, j) <= L for j in range(k))
+
+    cut0 = cut(g, part0)
+    gains, bal, steps = [0], [balanced(cur)], []
+    for v, a, b in seq_m:
+        step = [(v, a, b)]
+        cur[v] = b
+        lst = rlists.get(b, [])
+        while block_weight(g, cur, b) > L and used[b] < len(lst):
+            r = lst[used[b]]
+            used[b] += 1
+            cur[r[0]] = r[2]
+            step.append(r)
+        steps.append(step)
+        gains.append(cut0 - cut(g, cur))
+        bal.append(balanced(cur))
+    best = -1
+    for j in range(len(gains)):
+        if bal[j] and (best < 0 or gains[j] > gains[best]):
+            best = j
+    if best < 0:
+        return final, best, gains, bal
+    out = list(part0)
+    for step in steps[:best]:
+        for v, a, b in step:
+            out[v] = b
+    return out, best, gains, bal

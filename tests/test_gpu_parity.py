@@ -436,7 +436,8 @@ def test_empty_graph(upr, ctx):
     torch.cuda.synchronize()
     assert upr.stats_dict(st) == {"l_max": 0, "cut_before": 0, "cut_after_moves": 0,
                                   "cut_after": 0, "candidates": 0, "accepted": 0,
-                                  "rebalance_moves": 0, "rebalance_iters": 0, "status": 0}
+                                  "rebalance_moves": 0, "rebalance_iters": 0, "status": 0,
+                                  "prefix_steps": 0, "reverted": 0}
 
 
 def test_errors(upr, ctx):

@@ -154,4 +154,4 @@ def test_variant_params_checked(orc):
     with pytest.raises(Exception):
         orc.refine_round(g, orc.params(2, mode=3, alpha=(9, 10)), part)
     with pytest.raises(Exception):
-        orc.refine_round(g, orc.params(2, variant=4), part)
+        orc.refine_round(g, orc.params(2, variant=8), part)
