@@ -88,11 +88,27 @@ typedef struct {
                                       candidate neighbour in its target block (moved) instead
                                       of the worse of its two blocks;
                                     UPR_VAR_PLAIN_PRIORITY: rebalancing ranks nodes by the
-                                      gain alone, without the node weight (Section 8.2) */
+                                      gain alone, without the node weight (Section 8.2);
+                                    UPR_VAR_BEST_PREFIX: after the rebalancing, the filtered
+                                      and the rebalancing moves form one interleaved sequence
+                                      with exact gains, and the round keeps its best balanced
+                                      prefix (Section 5.4; single-graph rounds only) */
 } upr_params;
 
 #define UPR_VAR_OPTIMISTIC 1
 #define UPR_VAR_PLAIN_PRIORITY 2
+/* The interleaved sequence (Section 5.4 and the end of Algorithm 1): a node
+ * moved by the filter (a -> b) and by the rebalancer (b -> c) makes one move
+ * a -> c (none if c = a), placed as its filtered move; the filtered moves in
+ * the filter's order, each followed, when it leaves its target b
+ * overloaded, by the fewest unused rebalancing moves out of b (in the order
+ * they were made: sub-iteration, priority bucket, id) that bring b back to
+ * L_max. Gains are recomputed exactly in sequence order; of the boundaries
+ * after each filtered move (and its rebalancing moves) that leave every
+ * block within L_max, the one with the highest cumulative gain is kept
+ * (the earliest on ties) and every other move of the round is undone. With
+ * no balanced boundary the round's result stands. */
+#define UPR_VAR_BEST_PREFIX 4
 
 /* Round statistics, written to a device int64 array of UPR_STATS_LEN slots. */
 enum {
@@ -105,6 +121,9 @@ enum {
     UPR_ST_REBAL_MOVES,       /* moves made by rebalancing */
     UPR_ST_REBAL_ITERS,       /* rebalancing sub-iterations */
     UPR_ST_STATUS,            /* 0 balanced; 1 rebalancing stuck or out of iterations */
+    UPR_ST_PREFIX_STEPS,      /* best-prefix rounds: filtered moves kept, -1 if no boundary
+                                 was balanced (nothing undone); 0 otherwise */
+    UPR_ST_REVERTED,          /* best-prefix rounds: nodes returned to their round-start block */
     UPR_STATS_LEN = 12
 };
 

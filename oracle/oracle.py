@@ -56,7 +56,7 @@ class _Debug(C.Structure):
     _fields_ = [("target", C.c_void_p), ("score", C.c_void_p), ("pen", C.c_void_p),
                 ("accept", C.c_void_p), ("pen_seq", C.c_void_p), ("gp", C.c_void_p),
                 ("seq", C.c_void_p), ("bgain", C.c_void_p), ("bbal", C.c_void_p),
-                ("pref", C.c_void_p)]
+                ("pref", C.c_void_p), ("rrec", C.c_void_p)]
 
 
 _lib = None
@@ -219,7 +219,7 @@ def refine_round(g, p: _Params, part, conn=None, W=None, debug=False, active=Non
                    pen_seq=np.zeros(G.n, np.int64), gp=np.zeros(G.n, np.int64),
                    seq=np.zeros(4 * max(G.n, 1), np.int64),
                    bgain=np.zeros(G.n + 1, np.int64), bbal=np.zeros(G.n + 1, np.uint8),
-                   pref=np.full(4, -2, np.int64))
+                   pref=np.full(4, -2, np.int64), rrec=np.zeros(max(G.n, 1), np.int64))
         dstruct = _Debug(*[dbg[f].ctypes.data for f, _ in _Debug._fields_])
     if active is not None:
         _check(active, np.uint8, G.n, "active")

@@ -106,6 +106,7 @@ typedef struct {
     int64_t *bgain;   /* [n + 1] exact cumulative gain at each step boundary */
     uint8_t *bbal;    /* [n + 1] 1 iff the partition at that boundary is balanced */
     int64_t *pref;    /* [4] moves in the sequence, steps, best boundary, moves kept */
+    int64_t *rrec;    /* [n] rebalancing moves: sub-iteration << 8 | bucket, else 0 */
 } orc_debug;
 
 static int64_t edge_w(const orc_graph *g, int64_t e) { return g->adjwgt ? g->adjwgt[e] : 1; }
@@ -587,6 +588,9 @@ static int64_t best_prefix(const orc_graph *g, int32_t k, int64_t lmax, const in
         if (dbg->pref) {
             dbg->pref[0] = len; dbg->pref[1] = nm; dbg->pref[2] = best; dbg->pref[3] = kept;
         }
+        if (dbg->rrec)
+            for (int64_t v = 0; v < n; ++v)
+                dbg->rrec[v] = rec_iter[v] > 0 ? (rec_iter[v] << 8) | rec_beta[v] : 0;
     }
     free(mlist); free(rl); free(rstart); free(used); free(Wc); free(seq_node); free(seq_step);
     free(seq_to); free(bal); free(pos); free(bgain);

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libupr.so")
 SOURCES = ["k_table.hip", "k_graph.hip", "k_move.hip", "k_rebal.hip", "k_seq.hip", "k_batch.hip",
-           "noalloc.hip", "upr_api.hip"]
+           "k_prefix.hip", "noalloc.hip", "upr_api.hip"]
 ARCH = os.environ.get("UPR_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # no packed fp32 instructions anywhere in device code

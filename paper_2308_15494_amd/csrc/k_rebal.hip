@@ -614,11 +614,13 @@ __global__ __launch_bounds__(kBlock) void k_rb_theta(GraphView g, Blocks bk, con
 
 // ------------------------------------------------------------------ moves --
 
-// Accepted nodes get mvto[v] = target; counts per workgroup.
+// Accepted nodes get mvto[v] = target; counts per workgroup. rbrec (may be
+// null): each moved node's sub-iteration and priority bucket, iter << 8 |
+// bucket (the order in which the move was made).
 __global__ __launch_bounds__(kBlock) void k_rb_moves(GraphView g, Blocks bk, const int32_t *part,
                                                       RebalWs r, RbView rv, int32_t *mvto,
                                                       int64_t hub_t, unsigned long long *counters,
-                                                      int64_t *gstat)
+                                                      int64_t *gstat, int32_t *rbrec, int32_t iter)
 {
     __shared__ unsigned long long moved, mdeg;
     if (threadIdx.x == 0) {
@@ -637,6 +639,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_moves(GraphView g, Blocks bk, con
             if (acc) {
                 const int64_t v = x.v[i];
                 mvto[v] = x.j[i];
+                if (rbrec) rbrec[v] = (iter << 8) | (int32_t)r.rbeta[v];
                 atomicAdd(&mdeg, (unsigned long long)(g.xadj[v + 1] - g.xadj[v]));
             }
             wave_count(acc, &moved);
@@ -662,7 +665,7 @@ int rb_scan_grid(int64_t n) { return grid_cap(n, kBlock, 1024); }
 hipError_t launch_rb_iteration(const GraphView &g, const Blocks &bk, const int32_t *part,
                                const int32_t *conn, const RebalWs &r, int32_t *mvto, int hist32,
                                int plain, int64_t hub_t, unsigned long long *counters,
-                               int64_t *gstat, hipStream_t s)
+                               int64_t *gstat, hipStream_t s, int32_t *rbrec, int32_t iter)
 {
     hipError_t e;
     const RbView rv{r.rtgt, r.rbeta, r.W0, r.cbeta_src, r.theta_src, r.cbeta_tgt, r.theta_tgt};
@@ -717,7 +720,7 @@ hipError_t launch_rb_iteration(const GraphView &g, const Blocks &bk, const int32
     hipLaunchKernelGGL(k_rb_theta, dim3(K), dim3(kBlock), 0, s, g, bk, part, r, rv, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rb_moves, dim3(lg), dim3(kBlock), 0, s, g, bk, part, r, rv, mvto, hub_t,
-                       counters, gstat);
+                       counters, gstat, rbrec, iter);
     return hipGetLastError();
 }
 

@@ -105,6 +105,10 @@ struct upr_ctx {
     int64_t bpinned_cap = 0;  // int64 entries
     bool rb_dirty = false;
     Timing timing;
+    // interleaved best prefix (allocated on first use)
+    BpWs bp{};
+    int64_t bp_cap_n = 0;
+    int32_t bp_cap_k = 0;
 };
 
 struct upr_plan {
@@ -324,6 +328,75 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
     return UPR_OK;
 }
 
+void free_bp(upr_ctx *c)
+{
+    BpWs &w = c->bp;
+    for (void **p : {(void **)&w.part0, (void **)&w.rbrec, (void **)&w.W0, (void **)&w.fm,
+                     (void **)&w.fr, (void **)&w.ids, (void **)&w.ids2, (void **)&w.mlist,
+                     (void **)&w.rlist, (void **)&w.rfrom, (void **)&w.rto, (void **)&w.tau,
+                     (void **)&w.stepof, (void **)&w.rc, (void **)&w.rwi, (void **)&w.rin_inc,
+                     (void **)&w.rin_key, (void **)&w.k0, (void **)&w.k1, (void **)&w.evs,
+                     (void **)&w.d0, (void **)&w.d1, (void **)&w.acc, (void **)&w.need,
+                     (void **)&w.tcum, (void **)&w.pos, (void **)&w.ecnt, (void **)&w.eoff,
+                     (void **)&w.roff, (void **)&w.rinoff, (void **)&w.cstep, (void **)&w.rbefore,
+                     (void **)&w.over_incl, (void **)&w.stepgain, (void **)&w.gain_incl,
+                     (void **)&w.best_g, (void **)&w.best_j, (void **)&w.cnt, (void **)&w.changed,
+                     (void **)&w.scal, &w.temp}) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
+    w.rcnt = nullptr;
+    w.temp_bytes = 0;
+    c->bp_cap_n = 0;
+    c->bp_cap_k = 0;
+}
+
+// The best-prefix workspace for n nodes and K blocks.
+int ensure_bp(upr_ctx *c, int64_t n, int32_t K)
+{
+    if (n <= c->bp_cap_n && K <= c->bp_cap_k) return UPR_OK;
+    const int64_t N = std::max<int64_t>(std::max(n, c->bp_cap_n), 1);
+    const int32_t KK = std::max<int32_t>(std::max(K, c->bp_cap_k), 2);
+    HIP_TRY(c, hipDeviceSynchronize());
+    free_bp(c);
+    BpWs &w = c->bp;
+    bool ok = dalloc(&w.part0, N) == hipSuccess && dalloc(&w.rbrec, N) == hipSuccess &&
+              dalloc(&w.W0, KK) == hipSuccess && dalloc(&w.fm, N) == hipSuccess &&
+              dalloc(&w.fr, N) == hipSuccess && dalloc(&w.ids, N) == hipSuccess &&
+              dalloc(&w.ids2, N) == hipSuccess && dalloc(&w.mlist, N) == hipSuccess &&
+              dalloc(&w.rlist, N) == hipSuccess && dalloc(&w.rfrom, N) == hipSuccess &&
+              dalloc(&w.rto, N) == hipSuccess && dalloc(&w.tau, N) == hipSuccess &&
+              dalloc(&w.stepof, N) == hipSuccess && dalloc(&w.rc, N) == hipSuccess &&
+              dalloc(&w.rwi, N) == hipSuccess && dalloc(&w.rin_inc, N) == hipSuccess &&
+              dalloc(&w.rin_key, N) == hipSuccess && dalloc(&w.k0, 3 * N) == hipSuccess &&
+              dalloc(&w.k1, 3 * N) == hipSuccess && dalloc(&w.evs, 2 * N) == hipSuccess &&
+              dalloc(&w.d0, 3 * N) == hipSuccess && dalloc(&w.d1, 3 * N) == hipSuccess &&
+              dalloc(&w.acc, 3 * N) == hipSuccess && dalloc(&w.need, 2 * N) == hipSuccess &&
+              dalloc(&w.tcum, 2 * N) == hipSuccess && dalloc(&w.pos, N) == hipSuccess &&
+              dalloc(&w.ecnt, 2 * ((int64_t)KK + 1)) == hipSuccess &&
+              dalloc(&w.eoff, (int64_t)KK + 1) == hipSuccess &&
+              dalloc(&w.roff, (int64_t)KK + 1) == hipSuccess &&
+              dalloc(&w.rinoff, (int64_t)KK + 1) == hipSuccess &&
+              dalloc(&w.cstep, N + 1) == hipSuccess && dalloc(&w.rbefore, N + 1) == hipSuccess &&
+              dalloc(&w.over_incl, N + 1) == hipSuccess && dalloc(&w.stepgain, N + 1) == hipSuccess &&
+              dalloc(&w.gain_incl, N + 1) == hipSuccess && dalloc(&w.best_g, 1024) == hipSuccess &&
+              dalloc(&w.best_j, 1024) == hipSuccess && dalloc(&w.cnt, 2) == hipSuccess &&
+              dalloc(&w.changed, 1) == hipSuccess && dalloc(&w.scal, 4) == hipSuccess;
+    if (ok) {
+        w.temp_bytes = bp_temp_bytes(N);
+        ok = hipMalloc(&w.temp, w.temp_bytes) == hipSuccess;
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        free_bp(c);
+        return fail(c, UPR_E_NOMEM, "best-prefix workspace allocation failed for n=%lld", (long long)N);
+    }
+    w.rcnt = w.ecnt + KK + 1;
+    c->bp_cap_n = N;
+    c->bp_cap_k = KK;
+    return UPR_OK;
+}
+
 // Chunking of node ids for the rebalancer's in-bucket id bounds: n = the
 // largest graph's node count, k = number of blocks.
 void set_chunking(RebalWs &r, int64_t n, int32_t k)
@@ -381,7 +454,7 @@ int check_params(upr_ctx *c, const upr_plan *p, const upr_params *q)
     if (q->mode < 0 || q->mode > 3) return fail(c, UPR_E_ARG, "mode=%d not in {0,1,2,3}", q->mode);
     if (q->mode == 3 && (q->alpha_den <= 0 || q->alpha_num < q->alpha_den))
         return fail(c, UPR_E_ARG, "alpha must be a rational >= 1");
-    if (q->variant & ~(UPR_VAR_OPTIMISTIC | UPR_VAR_PLAIN_PRIORITY))
+    if (q->variant & ~(UPR_VAR_OPTIMISTIC | UPR_VAR_PLAIN_PRIORITY | UPR_VAR_BEST_PREFIX))
         return fail(c, UPR_E_ARG, "unknown variant bits 0x%x", q->variant);
     if (q->max_rebalance_iters < 0) return fail(c, UPR_E_ARG, "max_rebalance_iters < 0");
     if (q->seq_penalty != 0 && q->seq_penalty != 1) return fail(c, UPR_E_ARG, "seq_penalty not 0/1");
@@ -477,8 +550,10 @@ static hipError_t apply_moves(upr_ctx *c, const upr_plan *p, const Blocks &bk, i
 // S5: the host loop over synchronous sub-iterations (one graph).
 int rebalance_loop(upr_ctx *c, const upr_plan *p, const Blocks &bk, int plain, int32_t *part,
                    const PartView &pv, int32_t *conn, int64_t *W, int64_t it_max,
-                   int64_t *iters_out, int64_t *status_out, hipStream_t s, bool speculate)
+                   int64_t *iters_out, int64_t *status_out, hipStream_t s, bool speculate,
+                   int32_t *rbrec = nullptr)
 {
+    int32_t launched = 0;  // sub-iterations launched (numbers the records in rbrec)
     const HubView h = p->hubs();
     int64_t iters = 0, status = 0;
     const int hist32 = hist32_ok(p);
@@ -495,7 +570,7 @@ int rebalance_loop(upr_ctx *c, const upr_plan *p, const Blocks &bk, int plain, i
     };
     auto sub_iteration = [&]() -> int {
         HIP_TRY(c, launch_rb_iteration(p->g, bk, part, conn, c->rb, c->mvto, hist32, plain,
-                                       p->hub_t, c->counters, nullptr, s));
+                                       p->hub_t, c->counters, nullptr, s, rbrec, ++launched));
         HIP_TRY(c, apply_moves(c, p, bk, part, pv, conn, W, s));
         return begin(0);
     };
@@ -714,6 +789,7 @@ void upr_destroy(upr_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     free_workspace(c);
+    free_bp(c);
     dfree(c->counters);
     dfree(c->flags);
     dfree(c->penq);
@@ -1070,6 +1146,8 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
     }
     const int optimistic = (q->variant & UPR_VAR_OPTIMISTIC) ? 1 : 0;
     const int plain = (q->variant & UPR_VAR_PLAIN_PRIORITY) ? 1 : 0;
+    // the interleaved best prefix: single graphs, rounds with moves
+    const bool prefix = moves && !b && (q->variant & UPR_VAR_BEST_PREFIX) && n > 0;
     const int32_t K = bk.total();
     int64_t *gstat = b ? b->gstat_d : nullptr;
     StatsGeom sg;
@@ -1081,6 +1159,7 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
     HIP_TRY(c, hipSetDevice(c->device));
     int rc = ensure_workspace(c, n, K);
     if (rc) return rc;
+    if (prefix && (rc = ensure_bp(c, n, K))) return rc;
     set_chunking(c->rb, b ? b->max_n : n, K);
     c->rb.goff = b ? b->goff_d : nullptr;
     const HubView h = p->hubs();
@@ -1118,6 +1197,7 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
                                      gstat, GS_CUT2_BEFORE, s, q->rebuild_table ? c->inner : nullptr,
                                      p->nh > 0 ? p->hub_bits : nullptr));
     }
+    if (prefix) HIP_TRY(c, launch_bp_record_start(n, K, part, W, c->bp, s));
     bool moved = false;
     if (moves) {
         {
@@ -1204,9 +1284,21 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
                 q->max_rebalance_iters > 0 ? q->max_rebalance_iters : default_iters(p, k);
             // moves can overload a block except in constrained rounds
             rc = rebalance_loop(c, p, bk, plain, part, pv, conn, W, it_max, &iters, &status, s,
-                                moves && q->mode != 1);
+                                moves && q->mode != 1, prefix ? c->bp.rbrec : nullptr);
         }
         if (rc) return rc;
+    }
+    if (prefix) {
+        PhaseTimer t(c, 5, s);
+        const BpApply ap{bk, p->hub_t, h, p->dirty_threshold, c->dirty, p->table_graph(), tpv,
+                         p->order ? (void *)c->pc2 : nullptr, p->perm, p->all_threshold};
+        int its = 0;
+        const hipError_t e = run_best_prefix(p->g, K, lmax, part, pv, conn, W, c->accflag, c->key,
+                                             c->mvto, c->counters, c->bp, ap, stats, &its, s);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, UPR_E_HIP, "best prefix failed: %s", hipGetErrorString(e));
+        }
     }
     {
         PhaseTimer t(c, 6, s);
@@ -1224,6 +1316,7 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
         HIP_TRY(c, launch_cnt_copy(c->counters, CNT_CUT2_MOVES, CNT_CUT2_BEFORE, s));
     }
     HIP_TRY(c, launch_stats_final(stats, c->counters, lmax, iters, status, s));
+    if (prefix) HIP_TRY(c, launch_bp_stats(c->bp, stats, s));
     return UPR_OK;
 }
 
@@ -1443,6 +1536,8 @@ static int batch_common(upr_ctx *c, upr_batch *b, const upr_params *q, const int
         return fail(c, UPR_E_ARG, "part/conn/block_w/stats NULL");
     if ((tau_num == nullptr) != (tau_den == nullptr))
         return fail(c, UPR_E_ARG, "give both tau arrays or neither");
+    if (q->variant & UPR_VAR_BEST_PREFIX)
+        return fail(c, UPR_E_ARG, "the best-prefix variant is for single-graph rounds");
     HIP_TRY(c, hipSetDevice(c->device));
     // the host mirrors live in the context's pinned area, shared by its
     // batches: the previous call's last copy out of it must have completed

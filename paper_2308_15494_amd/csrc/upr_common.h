@@ -699,11 +699,65 @@ hipError_t launch_rb_begin(const Blocks &bk, const int64_t *W, const RebalWs &r,
 // gstat (batch): moves per graph in gstat[g][GS_MOVED_NOW] (reset first) and
 // gstat[g][GS_REBAL_MOVES].
 // plain: rebalancing priority by the gain alone (node weight left out).
+// rbrec (may be null): moved nodes get (iter << 8) | priority bucket.
 hipError_t launch_rb_iteration(const GraphView &g, const Blocks &bk, const int32_t *part,
                                const int32_t *conn, const RebalWs &r, int32_t *mvto, int hist32,
                                int plain, int64_t hub_t, unsigned long long *counters,
-                               int64_t *gstat, hipStream_t s);
+                               int64_t *gstat, hipStream_t s, int32_t *rbrec = nullptr,
+                               int32_t iter = 0);
 int rb_scan_grid(int64_t n);
+
+// interleaved move sequence and best prefix (k_prefix.hip). Workspace for
+// n nodes and K blocks (one graph).
+struct BpWs {
+    int32_t *part0, *rbrec;                      // [n] round-start partition; S5 move records
+    int64_t *W0;                                 // [K] round-start block weights
+    uint8_t *fm, *fr;                            // [n] in the filtered list / the rebalancing list
+    int32_t *ids, *ids2, *mlist, *rlist;         // [n] selections and their sorted orders
+    int32_t *rfrom, *rto, *tau, *stepof;         // [n]
+    int64_t *rc, *rwi, *rin_inc;                 // [n]
+    uint64_t *rin_key;                           // [n]
+    uint64_t *k0, *k1, *evs;                     // [3n] sort keys, [2n] sorted events
+    int64_t *d0, *d1, *acc;                      // [3n]
+    int32_t *need, *tcum;                        // [2n]
+    int64_t *pos;                                // [n]
+    int32_t *ecnt, *rcnt, *eoff, *roff, *rinoff; // [K + 1] each (rcnt inside ecnt's allocation)
+    int32_t *cstep, *rbefore, *over_incl;        // [n + 1]
+    int64_t *stepgain, *gain_incl;               // [n + 1]
+    int64_t *best_g;                             // [1024]
+    int32_t *best_j;                             // [1024]
+    int32_t *cnt;                                // [2]
+    unsigned long long *changed;                 // [1]
+    int64_t *scal;                               // [4]: best boundary, nodes undone
+    void *temp;
+    size_t temp_bytes;
+};
+// What the undo needs to call the apply.
+struct BpApply {
+    Blocks bk;
+    int64_t hub_t;
+    HubView h;
+    int64_t dirty_threshold;
+    uint8_t *dirty;
+    GraphView tg;
+    PartView tpv;
+    void *pc2;
+    const int32_t *perm;
+    int64_t all_threshold;
+};
+size_t bp_temp_bytes(int64_t n);
+// Before the moves: copies part and W, clears the rebalancing records.
+hipError_t launch_bp_record_start(int64_t n, int32_t K, const int32_t *part, const int64_t *W,
+                                  const BpWs &ws, hipStream_t s);
+// After S5: builds the sequence, keeps the best balanced prefix and undoes
+// the rest (synchronises s a few times). iterations: fixed-point rounds.
+hipError_t run_best_prefix(const GraphView &g, int32_t K, int64_t lmax, int32_t *part,
+                           const PartView &pv, int32_t *conn, int64_t *W, const uint8_t *accflag,
+                           const int64_t *key, int32_t *mvto, unsigned long long *counters,
+                           const BpWs &ws, const BpApply &apply, int64_t *stats, int *iterations,
+                           hipStream_t s);
+// Statistics slots 8 (status 0 when a balanced boundary was kept), 9 and 10.
+hipError_t launch_bp_stats(const BpWs &ws, int64_t *stats, hipStream_t s);
 
 // no-allocation edge cut (noalloc.hip): the device address of the scratch
 // array on `device` (which the caller made current), taken once per device;

@@ -50,6 +50,7 @@ class Params(C.Structure):
 
 VAR_OPTIMISTIC = 1
 VAR_PLAIN_PRIORITY = 2
+VAR_BEST_PREFIX = 4
 
 
 def params(k, eps=(3, 100), t=(7, 10), tau=(1, 1), mode=0, rebuild_table=1,
