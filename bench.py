@@ -136,7 +136,7 @@ def ingest_pmc(fetch_csv, write_csv):
     print(json.dumps(rec))
 
 
-def cpu_baseline(g, k, eps, rounds, part0, seconds, max_rounds=None):
+def cpu_baseline(g, k, eps, rounds, part0, seconds, max_rounds=None, variant=0):
     """The oracle, single-threaded on a host core, on the first rounds of the
     same workload until about `seconds` of work (at most max_rounds); returns
     (baseline, [(stats, part, W)] per round)."""
@@ -152,7 +152,8 @@ def cpu_baseline(g, k, eps, rounds, part0, seconds, max_rounds=None):
     cap = rounds if max_rounds is None else min(rounds, max_rounds)
     while r < cap:
         r += 1
-        st, _ = O.refine_round(G, O.params(k, eps, tau=gg.tau_schedule(r, rounds)), part, conn, W)
+        st, _ = O.refine_round(G, O.params(k, eps, tau=gg.tau_schedule(r, rounds), variant=variant),
+                               part, conn, W)
         out.append((st.copy(), part.copy(), W.copy()))
         log(f"  oracle round {r}: {time.perf_counter() - t0:.1f}s")
         if time.perf_counter() - t0 > seconds:
@@ -196,7 +197,7 @@ def roofline_entry(kernel, bytes_total, seconds_total, launches, note):
 
 
 def single_graph(ctx, g, k, eps, rounds, part0, steps, warmup, resident, hub_t=4096,
-                 dirty_div=16, phase_rounds=None, opts=None):
+                 dirty_div=16, phase_rounds=None, opts=None, variant=0):
     """Times `steps` rounds of one graph (edges/s; only the gain-table kernel
     is bracketed by events inside the timed region), then repeats them from
     the same start, untimed, with every phase timed and read after each
@@ -211,7 +212,7 @@ def single_graph(ctx, g, k, eps, rounds, part0, steps, warmup, resident, hub_t=4
     def run_rounds(count, per_round=None):
         for i in range(1, count + 1):
             p = upr.params(k, eps, tau=gg.tau_schedule(i, rounds),
-                           rebuild_table=0 if (resident and i > 1) else 1)
+                           rebuild_table=0 if (resident and i > 1) else 1, variant=variant)
             r.round(p)
             if per_round is not None:
                 per_round(i)
@@ -449,6 +450,31 @@ def extra_workload(ctx, name, steps, warmup, cpu_seconds, oracle_rounds, no_cpu)
     return out
 
 
+def best_prefix_leg(ctx, g, k, eps, rounds, part0, steps, cpu_seconds, oracle_rounds, no_cpu):
+    """The same workload with the interleaved best prefix (Section 5.4) after
+    every round's rebalancing: edges/s, the cost over the plain round, the
+    prefix kept, and parity with the oracle's first rounds."""
+    from paper_2308_15494_amd import upr
+    res = single_graph(ctx, g, k, eps, rounds, part0, steps, 2, False, phase_rounds=steps,
+                       variant=upr.VAR_BEST_PREFIX)
+    res.pop("refiner").plan.close()
+    kept = [int(x["stats"][9]) for x in res["rec"]]
+    undone = [int(x["stats"][10]) for x in res["rec"]]
+    out = {"value": res["value"], "unit": "edges/s", "ms_per_step": res["ms_per_step"],
+           "steps": steps, "variant": "best prefix (variant bit 4)",
+           "prefix_steps_per_round": kept, "undone_per_round": undone,
+           "final_stats": res["final"], "rebalance_ms_per_round": res["phases"].get("rebalance")}
+    if not no_cpu:
+        _, orc = cpu_baseline(g, k, eps, rounds, part0, cpu_seconds, max_rounds=oracle_rounds,
+                              variant=upr.VAR_BEST_PREFIX)
+        nchk, ok = parity(res["rec"], orc)
+        out["parity_rounds_checked"] = nchk
+        out["parity_ok"] = ok
+    log(f"best prefix: {out['value']:.3e} edges/s, {out['ms_per_step']:.3f} ms per round, "
+        f"parity {out.get('parity_ok')} over {out.get('parity_rounds_checked')} rounds")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -470,6 +496,8 @@ def main():
                     help="comma-separated further single-graph workloads ('' skips them)")
     ap.add_argument("--extra-oracle-rounds", type=int, default=1,
                     help="oracle rounds per further workload (baseline and parity)")
+    ap.add_argument("--prefix-oracle-rounds", type=int, default=4,
+                    help="oracle rounds checked for the best-prefix leg (0 skips the leg)")
     ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--tune", action="store_true",
                     help="autotune the traversal thresholds before timing (default: the "
@@ -561,6 +589,9 @@ def main():
         log(f"cpu oracle {base['value']:.3e} edges/s; parity over {nchk} rounds "
             f"(stats, partition, block weights): {ok}")
     del res
+    if args.prefix_oracle_rounds > 0:
+        out["best_prefix"] = best_prefix_leg(ctx, g, k, eps, rounds, part0, args.steps,
+                                             args.cpu_seconds, args.prefix_oracle_rounds, args.no_cpu)
 
     if bspec:
         out["batched"] = batched_vs_plain(ctx, bspec)

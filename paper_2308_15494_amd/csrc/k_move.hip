@@ -10,6 +10,8 @@
 // per workgroup.
 #include "upr_common.h"
 
+#include <cstdlib>
+
 namespace upr {
 
 
@@ -119,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void k_best_move(
     const int64_t *__restrict__ W, const int64_t *__restrict__ cb,
     const int64_t *__restrict__ pen1, int mode, const uint8_t *__restrict__ active,
     int64_t *__restrict__ key, int64_t *__restrict__ pen, unsigned long long *counters,
-    uint8_t *cflag, uint8_t *cflag2, int64_t *key2, const int32_t *perm)
+    uint8_t *cflag, uint8_t *cflag2, int64_t *key2, const int32_t *perm, int32_t adj_deg)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int32_t k = bk.k;
@@ -145,6 +147,8 @@ __global__ __launch_bounds__(kBlock) void k_best_move(
     const int64_t stride = (int64_t)gridDim.x * GPB;
     const int64_t first = (int64_t)blockIdx.x * GPB + threadIdx.x / G;
     for (int64_t v = first; v < g.n; v += stride) {
+        // nodes of degree <= adj_deg are decided by the adjacency form
+        if (adj_deg > 0 && g.xadj[v + 1] - g.xadj[v] <= adj_deg) continue;  // group-uniform
         int64_t best = 0, bestP = 0;
         const int32_t A = part[v];
         const int64_t cv = node_weight(g, v);
@@ -240,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_best_move_reg(
     const int64_t *__restrict__ W, const int64_t *__restrict__ cb,
     const int64_t *__restrict__ pen1, int mode, const uint8_t *__restrict__ active,
     int64_t *__restrict__ key, int64_t *__restrict__ pen, unsigned long long *counters,
-    uint8_t *cflag, uint8_t *cflag2, int64_t *key2, const int32_t *perm)
+    uint8_t *cflag, uint8_t *cflag2, int64_t *key2, const int32_t *perm, int32_t adj_deg)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int32_t k = bk.k;
@@ -268,11 +272,14 @@ __global__ __launch_bounds__(kBlock) void k_best_move_reg(
     const int64_t stride = (int64_t)gridDim.x * GPB * U;
     for (int64_t v0 = ((int64_t)blockIdx.x * GPB + threadIdx.x / G) * U; v0 < g.n; v0 += stride) {
         int32_t A[U];
+        bool skip[U];
         v4i32 x[U][R];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t v = v0 + u;
-            const bool valid = v < g.n;
+            // nodes of degree <= adj_deg are decided by the adjacency form
+            skip[u] = v < g.n && adj_deg > 0 && g.xadj[v + 1] - g.xadj[v] <= adj_deg;
+            const bool valid = v < g.n && !skip[u];
             A[u] = valid ? part[v] : -1;
             if (valid && active && !active[v]) A[u] = -1;
             const int32_t *row = conn + v * (int64_t)k;
@@ -354,7 +361,7 @@ __global__ __launch_bounds__(kBlock) void k_best_move_reg(
                     bestP = op;
                 }
             }
-            if (gl == 0 && v < g.n) {
+            if (gl == 0 && v < g.n && !skip[u]) {
                 if (best > 0) {
                     const int64_t sc = best >> 16;
                     const int32_t j = 0xFFFF - (int32_t)(best & 0xFFFF);
@@ -377,15 +384,207 @@ __global__ __launch_bounds__(kBlock) void k_best_move_reg(
     if (threadIdx.x == 0 && cand_lds) cnt_add(counters, CNT_CAND, cand_lds);
 }
 
+// The same move choice from the adjacency instead of the table row (the
+// row scan costs 4k bytes per node, this one xadj and about 5 bytes per
+// edge): one thread per node of degree <= maxd (at most D), which sums its neighbours'
+// edge weights per block in a register list (their blocks from the compact
+// partition copy) and scores every listed block against the sum for its
+// own block. Nodes of higher degree are left to the row kernel.
+template <int D, int PB>
+__global__ __launch_bounds__(kBlock) void k_best_move_adj(
+    GraphView g, Blocks bk, const int32_t *__restrict__ part, PartView pv,
+    const int64_t *__restrict__ W, const int64_t *__restrict__ cb,
+    const int64_t *__restrict__ pen1, int mode, const uint8_t *__restrict__ active,
+    int64_t *__restrict__ key, int64_t *__restrict__ pen, unsigned long long *counters,
+    uint8_t *cflag, uint8_t *cflag2, int64_t *key2, const int32_t *perm, int32_t maxd)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int32_t K = bk.total();
+    int64_t *sW = (int64_t *)lds_raw;
+    int64_t *sP = sW + K;
+    __shared__ unsigned long long cand_lds;
+    const bool use_lds = K <= 2048;
+    const bool unit = g.vwgt == nullptr;
+    if (threadIdx.x == 0) cand_lds = 0;
+    if (use_lds)
+        for (int j = threadIdx.x; j < K; j += kBlock) {
+            sW[j] = W[j];
+            sP[j] = pen1[j];
+        }
+    __syncthreads();
+    const int64_t *Wr = use_lds ? sW : W;
+    const int64_t *Pr = use_lds ? sP : pen1;
+    const int32_t pmask = part_mask(pv);
+    unsigned long long cands = 0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < g.n; v += stride) {
+        const int64_t e0 = g.xadj[v];
+        const int32_t d = (int32_t)(g.xadj[v + 1] - e0);
+        if (d > maxd) continue;  // maxd <= D; the row kernel takes the rest
+        const int32_t A = part[v];
+        bool ok = (unsigned)A < (unsigned)K && d > 0 && (!active || active[v]);
+        const int32_t a = ok ? bk.local(A) : 0;
+        // the neighbours' blocks and edge weights, loaded together (a slot
+        // past the row rereads its last edge and is ignored)
+        int32_t nb[D], nw[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const int64_t e = e0 + (i < d ? i : (d > 0 ? d - 1 : 0));
+            const int32_t u = ok ? g.adjncy[e] : 0;
+            nw[i] = ok ? edge_weight(g, e) : 0;
+            nb[i] = u;
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) nb[i] = pget_w<PB>(pv.p, nb[i], pmask);
+        // per-block sums: list of distinct blocks other than a
+        int32_t lb[D], ls[D];
+        int32_t cnt = 0, ca = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            lb[i] = -1;
+            ls[i] = 0;
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            if (i >= d) break;
+            const int32_t j = nb[i];
+            if (j == a) {
+                ca += nw[i];
+                continue;
+            }
+            bool found = false;
+#pragma unroll
+            for (int t = 0; t < D; ++t)
+                if (lb[t] == j) {
+                    ls[t] += nw[i];
+                    found = true;
+                }
+#pragma unroll
+            for (int t = 0; t < D; ++t)
+                if (!found && t == cnt) {
+                    lb[t] = j;
+                    ls[t] = nw[i];
+                }
+            cnt += found ? 0 : 1;
+        }
+        int64_t best = 0, bestP = 0;
+        if (ok) {
+            const int32_t base = bk.base(A);
+            const int64_t cv = node_weight(g, v);
+            const int64_t lmax = bk.move_lmax_of(A);
+            const int64_t *penq = bk.penq_of(A);
+#pragma unroll
+            for (int t = 0; t < D; ++t) {
+                const int32_t cj = ls[t];
+                const int32_t j = lb[t];
+                if (j < 0 || j >= bk.k || cj <= ca) continue;
+                const int64_t delta = (int64_t)cj - ca;
+                int64_t P;
+                if (unit) {
+                    P = Pr[base + j];
+                    if (P < 0) continue;
+                } else {
+                    P = 0;
+                    const int64_t xx = Wr[base + j] + cv - lmax;
+                    if (xx > 0) {
+                        if (mode == 1 || mode == 3) continue;
+                        if (mode == 0) {
+                            const int l = covering_slot(cb + (int64_t)(base + j) * kSlots, xx);
+                            if (l >= kSlots) continue;
+                            P = sat_mul_pen(penq[l], cv);
+                        }
+                    }
+                }
+                const int64_t sc = delta * 65536 - P;
+                if (sc <= 0) continue;
+                const int64_t packed = (sc << 16) | (int64_t)(0xFFFF - j);
+                if (packed > best) {
+                    best = packed;
+                    bestP = P;
+                }
+            }
+        }
+        if (best > 0) {
+            const int64_t sc = best >> 16;
+            const int32_t j = 0xFFFF - (int32_t)(best & 0xFFFF);
+            key[v] = (sc << 16) | j;
+            pen[v] = bestP;
+            if (cflag) cflag[v] = (uint8_t)(a | kCandFlag);
+            if (cflag2) {
+                const int32_t lv = perm[v];
+                cflag2[lv] = (uint8_t)(a | kCandFlag);
+                key2[lv] = (sc << 16) | j;
+            }
+            ++cands;
+        } else {
+            key[v] = -1;
+        }
+    }
+    cands = wave_sum(cands);
+    if (lane_id() == 0 && cands) atomicAdd(&cand_lds, cands);
+    __syncthreads();
+    if (threadIdx.x == 0 && cand_lds) cnt_add(counters, CNT_CAND, cand_lds);
+}
+
+// Largest degree the adjacency form takes for k blocks. The row is 4k bytes
+// streamed; the adjacency costs xadj, 4 bytes per edge streamed and one
+// random gather per edge, which costs about as much as 32 streamed bytes
+// (at k = 64 the adjacency form for nodes of degree up to 16 made R-MAT's
+// best move twice as slow, the 4-neighbour grid's 30% faster). Its register
+// list holds at most kAdjMaxDeg blocks. Splitting the nodes between the two
+// forms costs a second pass over xadj and a launch, which pays only for long
+// rows: the adjacency form is used when it takes every node (max_deg within
+// the bound) or when rows are at least 1 KB (k >= 256; at k = 64 the split
+// made R-MAT's best move 50% slower). 0: the row form for every node
+// (UPR_ADJ_DEG overrides: 0 disables, else the bound, capped).
+constexpr int kAdjMaxDeg = 16;
+int32_t best_move_adj_deg(int32_t k, int pv_bytes, int64_t max_deg)
+{
+    if (pv_bytes > 2) return 0;
+    const char *env = getenv("UPR_ADJ_DEG");
+    if (env && *env) {
+        const long x = strtol(env, nullptr, 10);
+        return (int32_t)(x < 0 ? 0 : (x > kAdjMaxDeg ? kAdjMaxDeg : x));
+    }
+    int32_t d = (4 * k - 16) / 36;
+    if (d > kAdjMaxDeg) d = kAdjMaxDeg;
+    if (d < 4) return 0;
+    return (max_deg <= d || k >= 256) ? d : 0;
+}
+
 hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t *part,
                             const int32_t *conn, const int64_t *W, const int64_t *cb,
                             const int64_t *pen1, int mode, const uint8_t *active, int64_t *key,
                             int64_t *pen, unsigned long long *counters, uint8_t *cflag,
-                            hipStream_t s, uint8_t *cflag2, int64_t *key2, const int32_t *perm)
+                            hipStream_t s, uint8_t *cflag2, int64_t *key2, const int32_t *perm,
+                            const PartView &pv, int32_t adj_deg, int64_t max_deg)
 {
     if (g.n <= 0) return hipSuccess;
     const int32_t k = bk.k;
     const size_t lds = bk.total() <= 2048 ? (size_t)bk.total() * 16 : 0;
+    if (adj_deg > 0) {
+        if (adj_deg > kAdjMaxDeg || pv.bytes > 2) return hipErrorInvalidValue;
+        // the register list no longer than the graph's largest degree
+        const int32_t dl = max_deg < adj_deg ? (int32_t)max_deg : adj_deg;
+#define UPR_BA(DD, PP)                                                                             \
+    hipLaunchKernelGGL((k_best_move_adj<DD, PP>), dim3(grid_cap(g.n, kBlock, 8192)), dim3(kBlock),  \
+                       lds, s, g, bk, part, pv, W, cb, pen1, mode, active, key, pen, counters,     \
+                       cflag, cflag2, key2, perm, adj_deg)
+        if (dl <= 4) {
+            if (pv.bytes == 1) UPR_BA(4, 1);
+            else UPR_BA(4, 2);
+        } else if (dl <= 8) {
+            if (pv.bytes == 1) UPR_BA(8, 1);
+            else UPR_BA(8, 2);
+        } else {
+            if (pv.bytes == 1) UPR_BA(16, 1);
+            else UPR_BA(16, 2);
+        }
+#undef UPR_BA
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (max_deg <= adj_deg) return hipSuccess;  // no node is left for the row
+    }
     const bool vec = (k % 4) == 0;
     const int nvec = vec ? k / 4 : k;
     if (vec && nvec <= 256) {
@@ -393,7 +592,7 @@ hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t 
     hipLaunchKernelGGL((k_best_move_reg<GG, RR, UU>),                                               \
                        dim3(grid_cap((g.n + UU - 1) / UU, kBlock / GG, 8192)), dim3(kBlock), lds, s, \
                        g, bk, part, conn, W, cb, pen1, mode, active, key, pen, counters, cflag,  \
-                       cflag2, key2, perm)
+                       cflag2, key2, perm, adj_deg)
         // each lane holds up to four int4 of the row: fewer lanes per node
         // mean fewer shuffle rounds per scored entry (at k = 64, 4 lanes per
         // node took 80 us where 16 lanes took 102)
@@ -412,7 +611,7 @@ hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t 
 #define UPR_BM(GG, VV)                                                                             \
     hipLaunchKernelGGL((k_best_move<GG, VV>), dim3(grid_cap(g.n, kBlock / GG, 8192)), dim3(kBlock), \
                        lds, s, g, bk, part, conn, W, cb, pen1, mode, active, key, pen, counters, \
-                       cflag, cflag2, key2, perm)
+                       cflag, cflag2, key2, perm, adj_deg)
     if (vec) {
         if (nvec <= 1) UPR_BM(1, 4);
         else if (nvec <= 2) UPR_BM(2, 4);

@@ -1210,7 +1210,7 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
                                         active, c->key, c->pen, c->counters,
                                         pv.flagged ? (uint8_t *)c->pc : nullptr, s,
                                         rl ? (uint8_t *)c->pc2 : nullptr, rl ? c->key2 : nullptr,
-                                        p->perm));
+                                        p->perm, pv, best_move_adj_deg(k, pv.bytes, p->maxdeg), p->maxdeg));
         }
         // no host decision here: with no candidates the filter and the apply
         // find nothing to do; a bad part value is reported at the next

@@ -566,12 +566,19 @@ hipError_t launch_cb_prefix(const Blocks &bk, int64_t *bucket, const int64_t *W,
 // a move. cflag (may be null): the compact partition copy whose bit 7 marks
 // the candidates; cflag2 / key2 / perm (may be null): the flagged copy and
 // the candidates' keys in the plan's label order.
+// pv / adj_deg: nodes of degree <= adj_deg (0: none) are decided from their
+// adjacency with the neighbours' blocks from the compact copy pv (1 or 2
+// bytes), the others from their table row; best_move_adj_deg(k, bytes,
+// max_deg) is the default bound. max_deg: the graph's largest degree (with max_deg <=
+// adj_deg the row kernel is not launched).
+int32_t best_move_adj_deg(int32_t k, int pv_bytes, int64_t max_deg);
 hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t *part,
                             const int32_t *conn, const int64_t *W, const int64_t *cb,
                             const int64_t *pen1, int mode, const uint8_t *active, int64_t *key,
                             int64_t *pen, unsigned long long *counters, uint8_t *cflag,
                             hipStream_t s, uint8_t *cflag2 = nullptr, int64_t *key2 = nullptr,
-                            const int32_t *perm = nullptr);
+                            const int32_t *perm = nullptr, const PartView &pv = PartView{},
+                            int32_t adj_deg = 0, int64_t max_deg = 0);
 // With gp_out the pessimistic gains are stored (decided by launch_filter_seq).
 // adj_r / pv2 / key2 (may be null; one-byte flagged pv only): neighbours'
 // blocks and keys read by label from the copies in the plan's degree order.
