@@ -313,14 +313,55 @@ def parity(rec, orc):
     return nchk, ok
 
 
-def batched_vs_plain(ctx, spec, eps=(3, 100), rounds=10):
+def _oracle_job(args):
+    g, k, seed, eps, rounds = args
+    from oracle import oracle as O
+    from paper_2308_15494_amd import graphgen as gg
+    G = O.Graph(g)
+    part = gg.random_partition(g.n, k, seed)
+    conn = np.zeros(max(g.n * k, 1), np.int32)
+    W = np.zeros(k, np.int64)
+    for r in range(1, rounds + 1):
+        O.refine_round(G, O.params(k, eps, tau=gg.tau_schedule(r, rounds)), part, conn, W)
+    return g.m
+
+
+def oracle_pool(spec, workers, what, eps=(3, 100), rounds=10):
+    """The oracle on the host's cores: one single-threaded oracle process per
+    core, one graph (all its rounds) per task; graphs/s over the sample.
+    Forked before anything touches the GPU."""
+    import multiprocessing as mp
+    if not spec:
+        return None
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    pool = ctx.Pool(workers)
+    try:
+        edges = pool.map(_oracle_job, [(g, k, s, eps, rounds) for g, k, s in spec], chunksize=1)
+    except BaseException:
+        pool.terminate()
+        pool.join()
+        raise
+    pool.close()
+    pool.join()
+    dt = time.perf_counter() - t0
+    return {"value": len(spec) / dt, "unit": "graphs/s", "cores": workers, "kind": "oracle",
+            "sample": f"{what}: {len(spec)} graphs ({sum(edges)} edges), {rounds} rounds each, "
+                      f"one process per core"}
+
+
+def batched_vs_plain(ctx, spec, eps=(3, 100), rounds=10, tune_batches=True):
     """The many-graphs workload refined twice: plain (one graph after the
     other, upr_refine_round per graph and round) and batched (one batch per k,
-    upr_batch_refine_round per round). Plans and batches are built and warmed
-    up before the timed regions; both start from the same partitions and
-    must end with identical partitions and statistics."""
+    upr_batch_refine_round per round). Each batch's traversal thresholds are
+    picked by the autotuner first (timed trial rounds; the plain graphs keep
+    the defaults: 512 tunings would cost more than they save). Plans and
+    batches are built and warmed up before the timed regions; both start
+    from the same partitions and must end with identical partitions and
+    statistics."""
     import torch
     from paper_2308_15494_amd import graphgen as gg
+    from paper_2308_15494_amd import tune
     from paper_2308_15494_amd import upr
     refs = []
     for g, k, seed in spec:
@@ -329,7 +370,19 @@ def batched_vs_plain(ctx, spec, eps=(3, 100), rounds=10):
     groups = {}
     for i, (g, k, seed) in enumerate(spec):
         groups.setdefault(k, []).append(i)
-    batches = {k: upr.Batch(ctx, [refs[i].dg for i in idx], k, eps) for k, idx in groups.items()}
+    chosen, tune_s = {}, 0.0
+    opts = {}
+    if tune_batches:
+        t0 = time.perf_counter()
+        for k, idx in groups.items():
+            o, rep_ = tune.tune_batch(ctx, [spec[i][0] for i in idx], k,
+                                      [gg.random_partition(spec[i][0].n, k, spec[i][2]) for i in idx],
+                                      eps, rounds=3, repeats=1, total_rounds=rounds)
+            opts[k] = o
+            chosen[k] = rep_["chosen"]
+        tune_s = time.perf_counter() - t0
+    batches = {k: upr.Batch(ctx, [refs[i].dg for i in idx], k, eps, opts=opts.get(k))
+               for k, idx in groups.items()}
 
     def reset_plain():
         for r, (g, k, seed) in zip(refs, spec):
@@ -377,7 +430,9 @@ def batched_vs_plain(ctx, spec, eps=(3, 100), rounds=10):
             "nodes": int(sum(g.n for g, _, _ in spec)), "edges": int(sum(g.m for g, _, _ in spec)),
             "plain_graphs_per_s": ng / out["plain"], "batched_graphs_per_s": ng / out["batched"],
             "plain_s": out["plain"], "batched_s": out["batched"],
-            "speedup": out["plain"] / out["batched"], "identical_results": same}
+            "speedup": out["plain"] / out["batched"], "identical_results": same,
+            "thresholds": {str(k): v for k, v in chosen.items()} if chosen else "default",
+            "tune_s": tune_s}
 
 
 def serving(ctx, spec, eps=(3, 100), rounds=10, load=0.7, budget_gb=200.0, check=4, seed=7):
@@ -490,8 +545,12 @@ def main():
                     help="write the gain-table traffic record from two rocprofv3 --pmc CSVs")
     ap.add_argument("--batch-graphs", type=int, default=512,
                     help="graphs of the batched-vs-plain leg (0 skips it)")
-    ap.add_argument("--serve-requests", type=int, default=200,
-                    help="requests of the serving leg (0 skips it)")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests of the serving leg (0 skips it; the full stream is 2000)")
+    ap.add_argument("--serve-mmax", type=float, default=1e7,
+                    help="largest edge count of a serving request (log-uniform from 1e4)")
+    ap.add_argument("--pool-sample", type=int, default=64,
+                    help="graphs of each many-graphs workload that the host-core oracle pool refines")
     ap.add_argument("--extra", default="grid2048,chunglu8m",
                     help="comma-separated further single-graph workloads ('' skips them)")
     ap.add_argument("--extra-oracle-rounds", type=int, default=1,
@@ -522,11 +581,21 @@ def main():
     t0 = time.perf_counter()
     bspec = gg.generate_parallel(gg.batch_set, args.batch_graphs, args.gen_workers, seed0=1000) \
         if args.batch_graphs > 0 else []
-    sspec = gg.generate_parallel(gg.serve_set, args.serve_requests, args.gen_workers, seed0=100_000) \
-        if args.serve_requests > 0 else []
+    sspec = gg.generate_parallel(gg.serve_set, args.serve_requests, args.gen_workers, seed0=100_000,
+                                 m_max=args.serve_mmax) if args.serve_requests > 0 else []
     if bspec or sspec:
         log(f"generated {len(bspec)} batch graphs and {len(sspec)} requests in "
             f"{time.perf_counter() - t0:.1f}s")
+    # the oracle on the host's cores for the many-graphs workloads (forked
+    # before the GPU is touched), on a bounded sample of each
+    pools = {}
+    if not args.no_cpu and args.pool_sample > 0:
+        workers = host_info()["nproc"] or 1
+        t0 = time.perf_counter()
+        pools["batched"] = oracle_pool(bspec[: args.pool_sample], workers, "the many-graphs workload")
+        pools["serving"] = oracle_pool(sspec[: max(args.pool_sample // 2, 1)], workers,
+                                       "the serving requests")
+        log(f"host-core oracle pools {pools} in {time.perf_counter() - t0:.1f}s")
 
     import torch
     from paper_2308_15494_amd import upr
@@ -595,9 +664,14 @@ def main():
 
     if bspec:
         out["batched"] = batched_vs_plain(ctx, bspec)
+        if pools.get("batched"):
+            out["batched"]["cpu_baseline"] = pools["batched"]
         log(f"batched: {out['batched']}")
     if sspec:
         out["serving"] = serving(ctx, sspec)
+        out["serving"]["m_range"] = [1e4, args.serve_mmax]
+        if pools.get("serving"):
+            out["serving"]["cpu_baseline"] = pools["serving"]
         log(f"serving: {out['serving']}")
 
     extra = [w for w in args.extra.split(",") if w]

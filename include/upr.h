@@ -283,6 +283,19 @@ int upr_batch_info(const upr_batch *batch, int64_t *n_total, int64_t *nnz_total,
 int upr_batch_refine_round(upr_ctx *ctx, upr_batch *batch, const upr_params *params,
                            const int32_t *tau_num, const int32_t *tau_den, int32_t *part,
                            int32_t *conn, int64_t *block_w, int64_t *stats, hipStream_t stream);
+/* Carry graphs' round state between batches on the device, for a server
+ * that rebuilds its batch when membership changes: for every graph g of
+ * dst with src_index[g] >= 0 (host int32 [dst's ng]), graph src_index[g] of
+ * src -- the same graph, same node count and k -- has its partition copied
+ * (block ids renumbered from its old to its new global range), its table
+ * rows and its block weights. Graphs with src_index[g] < 0 are not touched.
+ * src_part / src_conn / src_block_w and the dst arrays: the device state
+ * arrays of the two batches, laid out as for upr_batch_refine_round.
+ * Enqueued on `stream`; the arrays of src must stay valid until it has run. */
+int upr_batch_carry(upr_ctx *ctx, const upr_batch *src, const int32_t *src_part,
+                    const int32_t *src_conn, const int64_t *src_block_w, const upr_batch *dst,
+                    const int32_t *src_index, int32_t *dst_part, int32_t *dst_conn,
+                    int64_t *dst_block_w, hipStream_t stream);
 /* Rebalancing alone of every graph of the batch (as upr_rebalance). */
 int upr_batch_rebalance(upr_ctx *ctx, upr_batch *batch, const upr_params *params, int32_t *part,
                         int32_t *conn, int64_t *block_w, int64_t *stats, hipStream_t stream);

@@ -52,6 +52,44 @@ hipError_t launch_batch_copy(const GraphView &src, int64_t node_off, int64_t edg
     return hipGetLastError();
 }
 
+// Carry graphs' round state from one batch into another: record r =
+// (source node offset, destination node offset, nodes, source graph,
+// destination graph); workgroups (x, r) copy strided parts of graph r's
+// partition (block ids moved from the source graph's range to the
+// destination's), its table rows and its block weights.
+__global__ void k_batch_carry(const int64_t *rec, int32_t k, const int32_t *src_part,
+                              const int32_t *src_conn, const int64_t *src_W, int32_t *dst_part,
+                              int32_t *dst_conn, int64_t *dst_W)
+{
+    const int64_t *r = rec + 5 * (int64_t)blockIdx.y;
+    const int64_t so = r[0], d0 = r[1], n = r[2];
+    const int32_t shift = (int32_t)((r[4] - r[3]) * k);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t v = t; v < n; v += stride) dst_part[d0 + v] = src_part[so + v] + shift;
+    const int64_t cells = n * k;
+    const int32_t *sc = src_conn + so * k;
+    int32_t *dc = dst_conn + d0 * k;
+    for (int64_t i = t; i < cells; i += stride) dc[i] = sc[i];
+    for (int64_t j = t; j < k; j += stride) dst_W[r[4] * k + j] = src_W[r[3] * k + j];
+}
+
+hipError_t launch_batch_carry(const int64_t *rec, int32_t nrec, int64_t max_cells, int32_t k,
+                              const int32_t *src_part, const int32_t *src_conn,
+                              const int64_t *src_W, int32_t *dst_part, int32_t *dst_conn,
+                              int64_t *dst_W, hipStream_t s)
+{
+    const int gx = grid_for(max_cells, kBlock * 4, 256);
+    for (int32_t r0 = 0; r0 < nrec; r0 += 65535) {  // grid y is at most 65535
+        const int32_t nr = nrec - r0 < 65535 ? nrec - r0 : 65535;
+        hipLaunchKernelGGL(k_batch_carry, dim3(gx, nr), dim3(kBlock), 0, s, rec + 5 * (int64_t)r0, k,
+                           src_part, src_conn, src_W, dst_part, dst_conn, dst_W);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // Per graph (one workgroup each): total node weight and the largest one.
 __global__ void k_batch_totals(const int64_t *goff, const int32_t *vwgt, int64_t *out)
 {

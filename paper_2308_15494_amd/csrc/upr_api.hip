@@ -105,6 +105,9 @@ struct upr_ctx {
     int64_t bpinned_cap = 0;  // int64 entries
     bool rb_dirty = false;
     Timing timing;
+    // carry records of upr_batch_carry (device, grown on demand)
+    int64_t *carry = nullptr;
+    int64_t carry_cap = 0;
     // interleaved best prefix (allocated on first use)
     BpWs bp{};
     int64_t bp_cap_n = 0;
@@ -790,6 +793,7 @@ void upr_destroy(upr_ctx *c)
     (void)hipDeviceSynchronize();
     free_workspace(c);
     free_bp(c);
+    dfree(c->carry);
     dfree(c->counters);
     dfree(c->flags);
     dfree(c->penq);
@@ -1563,6 +1567,52 @@ static int batch_common(upr_ctx *c, upr_batch *b, const upr_params *q, const int
                                   hipMemcpyHostToDevice, s));
     }
     return round_core(c, b->plan, b, q, part, conn, W, stats, s, moves);
+}
+
+int upr_batch_carry(upr_ctx *c, const upr_batch *src, const int32_t *src_part,
+                    const int32_t *src_conn, const int64_t *src_W, const upr_batch *dst,
+                    const int32_t *src_index, int32_t *dst_part, int32_t *dst_conn, int64_t *dst_W,
+                    hipStream_t s)
+{
+    if (!c) return UPR_E_ARG;
+    if (!src || !dst || !src_index) return fail(c, UPR_E_ARG, "batch or index NULL");
+    if (src->ctx != c || dst->ctx != c) return fail(c, UPR_E_ARG, "batch belongs to another context");
+    if (src->k != dst->k) return fail(c, UPR_E_ARG, "k differs (%d and %d)", src->k, dst->k);
+    std::vector<int64_t> rec;
+    int64_t max_cells = 0;
+    for (int32_t g = 0; g < dst->ng; ++g) {
+        const int32_t o = src_index[g];
+        if (o < 0) continue;
+        if (o >= src->ng) return fail(c, UPR_E_ARG, "graph %d: source index %d out of range", g, o);
+        const int64_t n = dst->off[g + 1] - dst->off[g];
+        if (src->off[o + 1] - src->off[o] != n)
+            return fail(c, UPR_E_ARG, "graph %d: %lld nodes, source graph %d has %lld", g, (long long)n,
+                        o, (long long)(src->off[o + 1] - src->off[o]));
+        rec.insert(rec.end(), {src->off[o], dst->off[g], n, (int64_t)o, (int64_t)g});
+        max_cells = std::max<int64_t>(max_cells, std::max<int64_t>(n * src->k, src->k));
+    }
+    const int32_t nrec = (int32_t)(rec.size() / 5);
+    if (nrec == 0) return UPR_OK;
+    if ((!src_part || !src_conn || !src_W || !dst_part || !dst_conn || !dst_W))
+        return fail(c, UPR_E_ARG, "state array NULL");
+    HIP_TRY(c, hipSetDevice(c->device));
+    if ((int64_t)rec.size() > c->carry_cap) {
+        HIP_TRY(c, hipStreamSynchronize(s));
+        dfree(c->carry);
+        c->carry_cap = 0;
+        const int64_t cap = std::max<int64_t>((int64_t)rec.size(), 5 * 1024);
+        if (dalloc(&c->carry, cap) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, UPR_E_NOMEM, "carry records allocation failed");
+        }
+        c->carry_cap = cap;
+    }
+    // the records go through pageable memory: the copy completes before the
+    // call returns, so the host vector may go
+    HIP_TRY(c, hipMemcpyAsync(c->carry, rec.data(), sizeof(int64_t) * rec.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, launch_batch_carry(c->carry, nrec, max_cells, src->k, src_part, src_conn, src_W, dst_part,
+                                  dst_conn, dst_W, s));
+    return UPR_OK;
 }
 
 int upr_batch_refine_round(upr_ctx *c, upr_batch *b, const upr_params *q, const int32_t *tau_num,

@@ -777,6 +777,13 @@ hipError_t launch_cut_noalloc(const GraphView &g, const int32_t *part, int64_t *
 hipError_t launch_batch_copy(const GraphView &src, int64_t node_off, int64_t edge_off,
                              int64_t nnz, int64_t *xadj, int32_t *adjncy, int32_t *adjwgt,
                              int32_t *vwgt, int last, hipStream_t s);
+// rec: device int64 [nrec][5] = (source node offset, destination node
+// offset, nodes, source graph, destination graph); max_cells: the largest
+// nodes * k among them.
+hipError_t launch_batch_carry(const int64_t *rec, int32_t nrec, int64_t max_cells, int32_t k,
+                              const int32_t *src_part, const int32_t *src_conn,
+                              const int64_t *src_W, int32_t *dst_part, int32_t *dst_conn,
+                              int64_t *dst_W, hipStream_t s);
 // out[2g] = total node weight of graph g, out[2g + 1] = its largest node weight.
 hipError_t launch_batch_totals(const int64_t *goff, int32_t ng, const int32_t *vwgt, int64_t *out,
                                hipStream_t s);

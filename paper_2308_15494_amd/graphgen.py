@@ -410,7 +410,7 @@ def batch_set(count: int = 512, seed0: int = 1000, n_min: int = 1000, n_max: int
     return out
 
 
-def serve_set(count: int = 200, seed0: int = 100_000, m_min: float = 1e4, m_max: float = 1e6):
+def serve_set(count: int = 2000, seed0: int = 100_000, m_min: float = 1e4, m_max: float = 1e7):
     """The serving workload: `count` requests (seeds seed0 + j), edge counts
     log-uniform in [m_min, m_max]; Chung-Lu with n = m/8 (mean degree 16,
     exponent uniform in [2.1, 2.8]) or R-MAT with scale ceil(log2(m/16)) and

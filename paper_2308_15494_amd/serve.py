@@ -10,9 +10,11 @@ each batch runs one round of all its requests, finished requests leave, and
 requests that have arrived are admitted as long as their footprint fits the
 budget; a running batch takes newcomers at most every `admit_every` steps,
 since each change of membership rebuilds it. When a batch's membership
-changes it is rebuilt from the surviving
-requests' partitions, and that step recomputes the tables (a table is a
-function of the partition, so the result is the same as keeping it).
+changes, a new union is built and the surviving requests' partitions, gain
+tables and block weights are carried into it on the device
+(upr_batch_carry), so their state stays resident; only when newcomers join
+does the next step rebuild the tables (a table is a function of the
+partition, so the result is the same either way).
 
 Because no kernel lets two graphs of a batch interact, each request's result
 is exactly what it gets when refined alone.
@@ -89,23 +91,29 @@ class _Group:
         self.since_rebuild = 0
 
     def rebuild(self):
-        """New union of the current jobs, carrying their partitions."""
-        import torch
-        old = self.batch
-        if old is not None:
-            torch.cuda.synchronize()
-            parts = old.local_partitions()
-            for j, p in zip(self.members, parts):
-                j.part = p
-            old.close()
+        """New union of the current jobs. Jobs that were in the old union
+        keep their partition, table rows and block weights, carried on the
+        device; returns True if newcomers joined (their tables must be
+        built, so the next step rebuilds every table)."""
+        old, old_members = self.batch, self.members
         self.batch = None
         self.members = list(self.jobs)
+        where = {id(j): i for i, j in enumerate(old_members)} if old is not None else {}
+        src = [where.get(id(j), -1) for j in self.members]
         if self.members:
             # admitted graphs were validated on admission
             self.batch = upr.Batch(self.ctx, [j.dg for j in self.members], self.k, self.eps,
                                    trusted=True)
-            self.batch.set_partitions([j.part for j in self.members])
+            # newcomers start from their own partition; carried slices are
+            # overwritten on the device
+            self.batch.set_partitions([j.part if s < 0 else np.zeros(j.req.graph.n, np.int32)
+                                       for j, s in zip(self.members, src)])
+            if old is not None and any(s >= 0 for s in src):
+                self.batch.carry_from(old, src)
+        if old is not None:
+            old.close()  # waits for the carry
         self.dirty = False
+        return any(s < 0 for s in src)
 
     def step(self):
         """One round of every member; returns the members that finished."""
@@ -183,8 +191,8 @@ class Server:
                     grp.dirty = True
                 if grp.dirty:
                     t1 = clock()
-                    grp.rebuild()
-                    grp.fresh = True
+                    # resident state carried over unless newcomers joined
+                    grp.fresh = grp.rebuild()
                     grp.since_rebuild = 0
                     self._tick("rebuild_s", clock() - t1)
                     self._tick("rebuilds", 1)

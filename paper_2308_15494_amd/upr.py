@@ -98,6 +98,9 @@ _SIGS = [
     ("upr_batch_refine_round", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(Params), C.c_void_p,
                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                          C.c_void_p, C.c_void_p]),
+    ("upr_batch_carry", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p]),
     ("upr_batch_rebalance", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(Params), C.c_void_p,
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("upr_refine", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -460,6 +463,17 @@ class Batch:
                                                  _ptr(self.part), _ptr(self.conn), _ptr(self.W),
                                                  _ptr(self.stats), _stream(stream)))
         return self.stats
+
+    def carry_from(self, src: "Batch", src_index, stream=None):
+        """upr_batch_carry: graphs of this batch with src_index[g] >= 0 take
+        the partition, table rows and block weights of graph src_index[g] of
+        src (device to device)."""
+        idx = np.ascontiguousarray(src_index, np.int32)
+        if self.part is None:
+            raise ValueError("set_partitions first (the carried graphs' slices are overwritten)")
+        self.ctx.check(lib().upr_batch_carry(
+            self.ctx.handle, src.handle, _ptr(src.part), _ptr(src.conn), _ptr(src.W), self.handle,
+            idx.ctypes.data, _ptr(self.part), _ptr(self.conn), _ptr(self.W), _stream(stream)))
 
     def close(self):
         if self.handle:

@@ -197,3 +197,72 @@ def test_batch_errors(upr, ctx):
     # too many blocks
     with pytest.raises(upr.UprError):
         upr.Batch(ctx, [graphs[0]] * 9, 8192)
+
+
+def test_batch_carry_state(upr, ctx):
+    """upr_batch_carry: graphs carried from one batch into a rebuilt one keep
+    their partition (block ids renumbered to the new range), table rows and
+    block weights, device to device; a resident round of the new batch then
+    equals each graph's oracle round from the same state."""
+    import torch
+    k = 8
+    graphs = [gg.chung_lu(3000, 8.0, 2.2, seed=81), gg.grid2d(31, 29),
+              gg.with_weights(gg.chung_lu(2000, 10.0, 2.1, seed=82), 83, wmax=9),
+              gg.rmat(10, 12, seed=84)]
+    parts = [gg.random_partition(g.n, k, 90 + i) for i, g in enumerate(graphs)]
+    a = upr.Batch(ctx, graphs, k)
+    a.set_partitions(parts)
+    for r in range(1, 3):
+        a.round(upr.params(k, tau=gg.tau_schedule(r, 4)))
+    torch.cuda.synchronize()
+    a_parts = a.local_partitions()
+    a_conn = a.conn.cpu().numpy()
+    a_W = a.W.cpu().numpy().reshape(len(graphs), k)
+    # the new union: graph 3, a newcomer, graph 0, graph 2 (graph 1 left)
+    newcomer = gg.rgg2d(1200, seed=85)
+    order = [3, None, 0, 2]
+    b = upr.Batch(ctx, [graphs[i] if i is not None else newcomer for i in order], k)
+    start = gg.random_partition(newcomer.n, k, 99)
+    b.set_partitions([start if i is None else np.zeros(graphs[i].n, np.int32) for i in order])
+    b.carry_from(a, [i if i is not None else -1 for i in order])
+    torch.cuda.synchronize()
+    got = b.local_partitions()
+    b_conn = b.conn.cpu().numpy()
+    b_W = b.W.cpu().numpy().reshape(len(order), k)
+    for g, i in enumerate(order):
+        n = graphs[i].n if i is not None else newcomer.n
+        rows = b_conn[b.off[g] * k:(b.off[g] + n) * k]
+        if i is None:
+            assert np.array_equal(got[g], start)
+            assert not rows.any() and not b_W[g].any()  # untouched
+            continue
+        assert np.array_equal(got[g], a_parts[i]), g
+        assert np.array_equal(rows, a_conn[a.off[i] * k:(a.off[i] + n) * k]), g
+        assert np.array_equal(b_W[g], a_W[i]), g
+        assert np.array_equal(b.part.cpu().numpy()[b.off[g]:b.off[g + 1]] // k, np.full(n, g))
+    a.close()
+    b.close()
+    # resident round after a carry without newcomers
+    c = upr.Batch(ctx, [graphs[2], graphs[0]], k)
+    c.set_partitions([np.zeros(graphs[2].n, np.int32), np.zeros(graphs[0].n, np.int32)])
+    a = upr.Batch(ctx, graphs, k)
+    a.set_partitions(parts)
+    a.round(upr.params(k, tau=gg.tau_schedule(1, 4)))
+    c.carry_from(a, [2, 0])
+    c.round(upr.params(k, tau=gg.tau_schedule(2, 4), rebuild_table=0))
+    torch.cuda.synchronize()
+    st = c.graph_stats()
+    loc = c.local_partitions()
+    for g, i in enumerate([2, 0]):
+        ref = parts[i].copy()
+        conn = np.zeros(graphs[i].n * k, np.int32)
+        W = np.zeros(k, np.int64)
+        O.refine_round(graphs[i], O.params(k, tau=gg.tau_schedule(1, 4)), ref, conn, W)
+        ost, _ = O.refine_round(graphs[i], O.params(k, tau=gg.tau_schedule(2, 4), rebuild_table=0),
+                                ref, conn, W)
+        assert st[g] == O.stats_dict(ost), g
+        assert np.array_equal(loc[g], ref), g
+        n = graphs[i].n
+        assert np.array_equal(c.conn.cpu().numpy()[c.off[g] * k:(c.off[g] + n) * k], conn), g
+    a.close()
+    c.close()
