@@ -576,8 +576,25 @@ def main():
         return
 
     # the many-graphs inputs are generated first, in forked workers, before
-    # anything touches the GPU
+    # anything touches the GPU; the host-core oracle pools run before that,
+    # on the first graphs of each workload (the same seeds), so that their
+    # forked processes do not inherit the whole generated sets
     from paper_2308_15494_amd import graphgen as gg
+    pools = {}
+    if not args.no_cpu and args.pool_sample > 0:
+        workers = host_info()["nproc"] or 1
+        t0 = time.perf_counter()
+        nb = min(args.pool_sample, args.batch_graphs)
+        ns = min(max(args.pool_sample // 2, 1), args.serve_requests)
+        if nb > 0:
+            pools["batched"] = oracle_pool(
+                gg.generate_parallel(gg.batch_set, nb, args.gen_workers, seed0=1000), workers,
+                "the many-graphs workload")
+        if ns > 0:
+            pools["serving"] = oracle_pool(
+                gg.generate_parallel(gg.serve_set, ns, args.gen_workers, seed0=100_000,
+                                     m_max=args.serve_mmax), workers, "the serving requests")
+        log(f"host-core oracle pools {pools} in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
     bspec = gg.generate_parallel(gg.batch_set, args.batch_graphs, args.gen_workers, seed0=1000) \
         if args.batch_graphs > 0 else []
@@ -586,16 +603,6 @@ def main():
     if bspec or sspec:
         log(f"generated {len(bspec)} batch graphs and {len(sspec)} requests in "
             f"{time.perf_counter() - t0:.1f}s")
-    # the oracle on the host's cores for the many-graphs workloads (forked
-    # before the GPU is touched), on a bounded sample of each
-    pools = {}
-    if not args.no_cpu and args.pool_sample > 0:
-        workers = host_info()["nproc"] or 1
-        t0 = time.perf_counter()
-        pools["batched"] = oracle_pool(bspec[: args.pool_sample], workers, "the many-graphs workload")
-        pools["serving"] = oracle_pool(sspec[: max(args.pool_sample // 2, 1)], workers,
-                                       "the serving requests")
-        log(f"host-core oracle pools {pools} in {time.perf_counter() - t0:.1f}s")
 
     import torch
     from paper_2308_15494_amd import upr

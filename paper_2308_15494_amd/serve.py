@@ -161,12 +161,14 @@ class Server:
                 need = req.footprint()
                 if active and used + need > self.budget:
                     break  # wait for memory to free up (arrival order is kept)
+                key = (req.k, tuple(req.eps))
+                grp = groups.get(key)
+                if grp is not None and (len(grp.jobs) + len(grp.waiting) + 1) * req.k > upr.MAX_BATCH_BLOCKS:
+                    break  # the batch has as many graphs as its block ids allow
                 t1 = clock()
                 dg = upr.DeviceGraph(req.graph, torch.device("cuda", self.ctx.device))
                 upr.validate_graph(self.ctx, dg)
                 self._tick("admit_s", clock() - t1)
-                key = (req.k, tuple(req.eps))
-                grp = groups.get(key)
                 if grp is None:
                     grp = groups[key] = _Group(self.ctx, req.k, req.eps)
                 grp.waiting.append(_Job(req, dg, clock() - t0))

@@ -19,6 +19,7 @@ UPR_OK = 0
 ERRORS = {-1: "UPR_E_ARG", -2: "UPR_E_GRAPH", -3: "UPR_E_INFEASIBLE", -4: "UPR_E_NOMEM",
           -5: "UPR_E_HIP"}
 STATS_LEN = 12
+MAX_BATCH_BLOCKS = 65536  # UPR_MAX_BATCH_BLOCKS: graphs times k of one batch
 STAT_NAMES = ["l_max", "cut_before", "cut_after_moves", "cut_after", "candidates",
               "accepted", "rebalance_moves", "rebalance_iters", "status", "prefix_steps",
               "reverted"]
