@@ -31,8 +31,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gain_tile_rmat20.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2308_15494_amd", "csrc", "k_table.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_rmat20.json")
+CSRC = os.path.join(ROOT, "paper_2308_15494_amd", "csrc")
+# kernels with an HBM traffic record: (roofline key, name needle, source file)
+TRAFFIC_KERNELS = [("k_gain_tile", "k_gain_tile<", "k_table.hip"),
+                   ("k_best_move", "k_best_move_reg<", "k_move.hip"),
+                   ("k_filter", "k_filter<", "k_move.hip")]
 
 
 def log(*a):
@@ -45,28 +49,31 @@ def gain_tile_bytes(n, nnz, k, weighted):
     return 8 * (n + 1) + 4 * nnz * (2 if weighted else 1) + 4 * n + 4 * n * k
 
 
-def kernel_sha():
-    with open(KERNEL_SRC, "rb") as f:
+def source_sha(name):
+    with open(os.path.join(CSRC, name), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def stored_traffic():
+def stored_traffic(key):
+    """HBM bytes per launch of a kernel from the traffic record, or None if
+    there is none or the kernel's source changed since it was taken."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha") != kernel_sha():
+    rec = t.get(key)
+    if not rec or rec.get("source_sha") != source_sha(rec.get("source", "")):
         return None
-    return t.get("bytes_per_launch")
+    return rec.get("bytes_per_launch")
 
 
 COPY_BYTES = 1 << 30  # calibration copy: reads and writes this many bytes
 
 
 def pmc_run(args):
-    """Workload for the counter runs: the first rounds of the benchmark (the
-    table build in the same configuration as in the timed rounds), then a
+    """Workload for the counter runs: the benchmark's rounds from its initial
+    partition (the kernels in the configuration of the timed rounds), then a
     plain device copy of COPY_BYTES (the calibration kernel)."""
     import torch
     from paper_2308_15494_amd import graphgen as gg
@@ -75,7 +82,7 @@ def pmc_run(args):
     ctx = upr.Context(0)
     r = upr.Refiner(g, k, ctx=ctx)
     r.set_partition(gg.random_partition(g.n, k, seed))
-    for i in range(1, 6):
+    for i in range(1, rounds + 1):
         r.round(upr.params(k, eps, tau=gg.tau_schedule(i, rounds)))
     src = torch.ones(COPY_BYTES // 4, dtype=torch.int32, device="cuda")
     dst = torch.empty_like(src)
@@ -103,9 +110,10 @@ def _pmc_dispatches(path, counter):
 
 
 def ingest_pmc(fetch_csv, write_csv):
-    """Write the traffic record of k_gain_tile from the two counter runs. The
-    calibration is the largest dispatch of the device copy kernel, which reads
-    and writes COPY_BYTES."""
+    """Write the traffic records of the table, best-move and filter kernels
+    from the two counter runs (averages over their launches in the run). The
+    calibration is the largest dispatch of the device copy kernel, which
+    reads and writes COPY_BYTES."""
     fetch = _pmc_dispatches(fetch_csv, "FETCH_SIZE")
     write = _pmc_dispatches(write_csv, "WRITE_SIZE")
 
@@ -116,24 +124,25 @@ def ingest_pmc(fetch_csv, write_csv):
                 return keys[0]
         raise SystemExit(f"no kernel matching {needles} in counters")
 
-    tile = kernel(fetch, ["k_gain_tile"])
     copy = kernel(fetch, ["copyBuffer", "elementwise_kernel"])
-    tile_f = sum(fetch[tile]) / len(fetch[tile])
-    tile_w = sum(write[tile]) / len(write[tile])
     copy_f = max(fetch[copy])
     copy_w = max(write[kernel(write, [copy])])
     f_scale = COPY_BYTES / copy_f   # bytes per counter unit (reads)
     w_scale = COPY_BYTES / copy_w   # bytes per counter unit (writes)
-    rec = {"kernel": tile, "kernel_sha": kernel_sha(), "copy_kernel": copy,
-           "copy_bytes_each_way": COPY_BYTES, "fetch_counter": tile_f, "write_counter": tile_w,
-           "copy_fetch_counter": copy_f, "copy_write_counter": copy_w,
-           "fetch_scale": f_scale, "write_scale": w_scale,
-           "bytes_per_launch": tile_f * f_scale + tile_w * w_scale,
-           "fetch_bytes": tile_f * f_scale, "write_bytes": tile_w * w_scale}
+    out = {"copy_kernel": copy, "copy_bytes_each_way": COPY_BYTES, "copy_fetch_counter": copy_f,
+           "copy_write_counter": copy_w, "fetch_scale": f_scale, "write_scale": w_scale}
+    for key, needle, src in TRAFFIC_KERNELS:
+        name = kernel(fetch, [needle])
+        kf = sum(fetch[name]) / len(fetch[name])
+        kw = sum(write[name]) / len(write[name])
+        out[key] = {"kernel": name, "source": src, "source_sha": source_sha(src),
+                    "launches": len(fetch[name]), "fetch_counter": kf, "write_counter": kw,
+                    "bytes_per_launch": kf * f_scale + kw * w_scale,
+                    "fetch_bytes": kf * f_scale, "write_bytes": kw * w_scale}
     os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
     with open(TRAFFIC_FILE, "w") as f:
-        json.dump(rec, f, indent=1)
-    print(json.dumps(rec))
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
 
 
 def cpu_baseline(g, k, eps, rounds, part0, seconds, max_rounds=None, variant=0):
@@ -627,7 +636,11 @@ def main():
     res.pop("refiner").plan.close()
     plan_info = res["info"]
     head = dict(res["rooflines"]["k_gain_tile"])
-    head["traffic"] = stored_traffic()
+    if args.workload == "rmat20" and not args.resident:
+        # HBM bytes per launch from the counter runs of this workload
+        for key, _, _ in TRAFFIC_KERNELS:
+            res["rooflines"][key]["traffic"] = stored_traffic(key)
+        head["traffic"] = res["rooflines"]["k_gain_tile"]["traffic"]
     head["algorithmic_bytes"] = res["algo"]
 
     out = {

@@ -704,7 +704,8 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int o
                                                     int32_t *mvto, uint8_t *accflag,
                                                     unsigned long long *counters, int64_t *gp_out,
                                                     const int32_t *__restrict__ adj_r, PartView pv2,
-                                                    const int64_t *__restrict__ key2)
+                                                    const int64_t *__restrict__ key2,
+                                                    const int32_t *__restrict__ order)
 {
     __shared__ int32_t vstart[kFilterTile + 1];
     __shared__ int64_t estart[kFilterTile];
@@ -770,12 +771,14 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int o
             node[i] = upper_index(vstart, nt, pc);
             e[i] = estart[node[i]] + (pc - vstart[node[i]]);
         }
+        // with the label copy the neighbour's id is needed only to break a
+        // tie of scores; it is then taken from the label's node (order)
         int32_t u[kFilterUnroll], w[kFilterUnroll], ur[kFilterUnroll];
 #pragma unroll
         for (int i = 0; i < kFilterUnroll; ++i) {
-            u[i] = stream_load(g.adjncy + e[i]);
-            w[i] = stream_edge_weight(g, e[i]);
             if constexpr (RL) ur[i] = stream_load(adj_r + e[i]);
+            else u[i] = stream_load(g.adjncy + e[i]);
+            w[i] = stream_edge_weight(g, e[i]);
         }
         int32_t raw[kFilterUnroll];
 #pragma unroll
@@ -804,7 +807,12 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int o
             int f = move_sign(pu, a, b);
             if (ku >= 0) {
                 const int64_t su = ku >> 16, sv = kv >> 16;
-                if (su > sv || (su == sv && (int64_t)u[i] < v0 + nd)) {
+                bool earlier = su > sv;
+                if (su == sv) {
+                    const int64_t uid = RL ? (int64_t)order[ur[i]] : (int64_t)u[i];
+                    earlier = uid < v0 + nd;
+                }
+                if (earlier) {
                     const int ft = move_sign((int32_t)(ku & 0xFFFF), a, b);
                     f = (optimistic || ft < f) ? ft : f;
                 }
@@ -848,15 +856,15 @@ hipError_t launch_filter(const GraphView &g, const Blocks &bk, int optimistic, c
                          const PartView &pv, const int64_t *key, const int64_t *pen, int64_t hub_t,
                          int32_t *mvto, uint8_t *accflag, unsigned long long *counters,
                          int64_t *gp_out, hipStream_t s, const int32_t *adj_r, const PartView &pv2,
-                         const int64_t *key2)
+                         const int64_t *key2, const int32_t *order)
 {
     if (g.n <= 0) return hipSuccess;
     const int64_t tiles = (g.n + kFilterTile - 1) / kFilterTile;
 #define UPR_FI(BB, RR)                                                                             \
     hipLaunchKernelGGL((k_filter<BB, RR>), dim3((unsigned)tiles), dim3(kBlock), 0, s, g, bk,         \
                        optimistic, part, pv, key, pen, hub_t, mvto, accflag, counters, gp_out,     \
-                       adj_r, pv2, key2)
-    if (adj_r && pv2.p && key2 && pv.bytes == 1 && pv.flagged) UPR_FI(1, true);
+                       adj_r, pv2, key2, order)
+    if (adj_r && pv2.p && key2 && order && pv.bytes == 1 && pv.flagged) UPR_FI(1, true);
     else if (pv.bytes == 1) UPR_FI(1, false);
     else if (pv.bytes == 2) UPR_FI(2, false);
     else UPR_FI(4, false);

@@ -1229,7 +1229,7 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
                 HIP_TRY(c, launch_filter(p->g, bk, optimistic, part, pv, c->key, c->pen, p->hub_t,
                                          c->mvto, c->accflag, c->counters, gp_out, s,
                                          rl ? p->adj_r : nullptr, rl ? tpv : PartView{},
-                                         rl ? c->key2 : nullptr));
+                                         rl ? c->key2 : nullptr, rl ? p->order : nullptr));
             }
             HIP_TRY(c, launch_filter_hub(p->g, bk, optimistic, part, pv, c->key, c->pen, h,
                                          c->mvto, c->accflag, c->counters, gp_out, s));

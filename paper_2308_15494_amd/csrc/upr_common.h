@@ -580,15 +580,17 @@ hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t 
                             const int32_t *perm = nullptr, const PartView &pv = PartView{},
                             int32_t adj_deg = 0, int64_t max_deg = 0);
 // With gp_out the pessimistic gains are stored (decided by launch_filter_seq).
-// adj_r / pv2 / key2 (may be null; one-byte flagged pv only): neighbours'
-// blocks and keys read by label from the copies in the plan's degree order.
+// adj_r / pv2 / key2 / order (may be null; one-byte flagged pv only):
+// neighbours' blocks and keys read by label from the copies in the plan's
+// degree order, and a neighbour's id (for a tie of scores) from order.
 // optimistic: an earlier candidate neighbour counts in its target block.
 hipError_t launch_filter(const GraphView &g, const Blocks &bk, int optimistic, const int32_t *part,
                          const PartView &pv,
                          const int64_t *key, const int64_t *pen, int64_t hub_t,
                          int32_t *mvto, uint8_t *accflag, unsigned long long *counters,
                          int64_t *gp_out, hipStream_t s, const int32_t *adj_r = nullptr,
-                         const PartView &pv2 = PartView{}, const int64_t *key2 = nullptr);
+                         const PartView &pv2 = PartView{}, const int64_t *key2 = nullptr,
+                         const int32_t *order = nullptr);
 hipError_t launch_filter_hub(const GraphView &g, const Blocks &bk, int optimistic,
                              const int32_t *part, const PartView &pv,
                              const int64_t *key, const int64_t *pen, const HubView &h,
