@@ -280,7 +280,14 @@ def single_graph(ctx, g, k, eps, rounds, part0, steps, warmup, resident, hub_t=4
     n, nnz = g.n, g.nnz
     ew = 8 if weighted else 4
     # per-kernel rooflines over the repeated rounds (algorithmic bytes per launch)
-    bm_bytes = sum(4 * n * k + 16 * n for _ in rec)
+    # best move: a row node reads its row and part and writes key and penalty
+    # (4k + 20); an adjacency node reads xadj, part, its edges and their
+    # neighbours' one- or two-byte blocks, and writes the same (28 + (ew + pb) d)
+    adj = upr.best_move_adjacency_degree(k, info["max_degree"])
+    pb = 1 if k <= 256 else 2
+    small = deg <= adj if adj > 0 else np.zeros(n, bool)
+    bm_once = int((4 * k + 20) * (n - small.sum()) + 28 * small.sum() + (ew + pb) * deg[small].sum())
+    bm_bytes = bm_once * len(rec)
     bm_s = sum(x["phases"]["best_move_kernel"] for x in rec) / 1e3
     fl_bytes = sum(ew * x["cand_edges"] + 17 * n for x in rec)
     fl_s = sum(x["phases"]["filter_kernel"] for x in rec) / 1e3
@@ -294,7 +301,9 @@ def single_graph(ctx, g, k, eps, rounds, part0, steps, warmup, resident, hub_t=4
         "k_gain_tile": {**roofline_entry("k_gain_tile", algo * tile_cnt, tile_ms / 1e3, tile_cnt,
                                          "8(n+1) + 4nnz [+4nnz weights] + 4n + 4nk"),
                         "note": "timed region"},
-        "k_best_move": roofline_entry("k_best_move", bm_bytes, bm_s, len(rec), "4nk + 16n"),
+        "k_best_move": roofline_entry("k_best_move", bm_bytes, bm_s, len(rec),
+                                      f"row nodes 4k + 20, adjacency nodes (degree <= {adj}) "
+                                      f"28 + {ew + pb} per edge"),
         "k_filter": roofline_entry("k_filter", fl_bytes, fl_s, len(rec),
                                    "4 (+4 weights) per candidate edge + 17n"),
         "k_apply": roofline_entry("k_apply (delta rounds)", ap_bytes, ap_s, len(delta),

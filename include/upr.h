@@ -338,6 +338,11 @@ int upr_refine(upr_ctx *ctx, const upr_plan *plan, const upr_driver *driver, int
 /* Host-side helpers (no device work). */
 /* L_max = floor((1 + eps) * ceil(total / k)) with eps = eps_num / eps_den. */
 int64_t upr_lmax(int64_t total, int32_t k, int32_t eps_num, int32_t eps_den);
+/* Best move decides a node of degree <= this bound from its adjacency, every
+ * other node from its table row (the same result either way), for a graph
+ * with k blocks and the given largest degree; 0: every node from its row.
+ * The environment variable UPR_ADJ_DEG overrides the bound (at most 16). */
+int32_t upr_best_move_adjacency_degree(int32_t k, int64_t max_degree);
 /* Q16 penalty factors floor(tau * (3/2)^l * 2^16), l = 0..53, into out[54]. */
 int upr_penalty_table(int32_t tau_num, int32_t tau_den, int64_t *out);
 

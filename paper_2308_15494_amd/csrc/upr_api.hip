@@ -732,6 +732,12 @@ int64_t upr_lmax(int64_t total, int32_t k, int32_t eps_num, int32_t eps_den)
     return (int64_t)(x / (uint64_t)eps_den);
 }
 
+int32_t upr_best_move_adjacency_degree(int32_t k, int64_t max_degree)
+{
+    if (k < 2 || k > UPR_MAX_K) return 0;
+    return best_move_adj_deg(k, k <= 256 ? 1 : 2, max_degree);
+}
+
 int upr_penalty_table(int32_t tau_num, int32_t tau_den, int64_t *out)
 {
     if (!out || tau_den <= 0 || tau_num < 0 || tau_num > tau_den) return UPR_E_ARG;

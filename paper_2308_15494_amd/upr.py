@@ -88,6 +88,7 @@ _SIGS = [
                                  C.c_void_p, C.c_void_p]),
     ("upr_lmax", C.c_int64, [C.c_int64, C.c_int32, C.c_int32, C.c_int32]),
     ("upr_penalty_table", C.c_int, [C.c_int32, C.c_int32, C.c_void_p]),
+    ("upr_best_move_adjacency_degree", C.c_int32, [C.c_int32, C.c_int64]),
     ("upr_batch_create", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                    C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                    C.POINTER(C.c_void_p), C.c_void_p]),
@@ -162,6 +163,10 @@ def refine(ctx, plan, d: Driver, part, conn, W, stream=None):
 
 def lmax(total, k, eps=(3, 100)) -> int:
     return int(lib().upr_lmax(total, k, eps[0], eps[1]))
+
+
+def best_move_adjacency_degree(k, max_degree) -> int:
+    return int(lib().upr_best_move_adjacency_degree(k, max_degree))
 
 
 def penalty_table(tau) -> np.ndarray:
