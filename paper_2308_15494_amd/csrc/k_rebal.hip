@@ -175,6 +175,10 @@ __device__ __forceinline__ void rb_load_vec(const int32_t *row, int q, int32_t (
 // U source nodes per lane group at a time (their rows loaded together); with
 // U > 1 or R > 1 a lane holds R vectors of the row, vector q = gl + r * G
 // (k / V <= G * R). Fewer lanes per node mean fewer shuffle rounds per entry.
+// A wave lists the sources among its kRbRuns runs of 64 nodes first and
+// takes them GPW * U at a time, so that the rows of all its sources are
+// loaded in as few round trips as possible (a source block holds a few
+// percent of the nodes: run by run, each run cost a round trip of its own).
 template <int G, int V, int U, int R>
 __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
                                                         const int32_t *__restrict__ part,
@@ -219,11 +223,15 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
             const int32_t a = ok ? lar[i] : 0;
             maskr[i] = __ballot(ok && W0[a] > bk.src_lmax_of(a));
         }
-        for (int run = 0; run < kRbRuns; ++run) {
-            const int64_t lv = base0 + 64 * run + lane;
-            const int32_t la = lar[run];
-            const uint64_t mask = maskr[run];
-            const int cnt = __popcll(mask);
+        int cntr[kRbRuns];
+        int cnt = 0;
+#pragma unroll
+        for (int i = 0; i < kRbRuns; ++i) {
+            cntr[i] = __popcll(maskr[i]);
+            cnt += cntr[i];
+        }
+        {
+            // source p of the wave's list: the q-th set bit of the run that holds it
             for (int p0 = 0; p0 < cnt; p0 += GPW * U) {
                 int64_t vu[U];
                 int32_t Au[U];
@@ -233,9 +241,18 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
                 for (int u = 0; u < U; ++u) {
                     const int p = p0 + u * GPW + grp;
                     oku[u] = p < cnt;
-                    const int src = oku[u] ? nth_set_bit(mask, p) : 0;
-                    vu[u] = __shfl(lv, src);
-                    Au[u] = __shfl(la, src);
+                    int q = oku[u] ? p : 0, run = 0;
+                    uint64_t mask = maskr[0];
+#pragma unroll
+                    for (int i = 0; i + 1 < kRbRuns; ++i)
+                        if (run == i && q >= cntr[i]) {
+                            q -= cntr[i];
+                            run = i + 1;
+                            mask = maskr[i + 1];
+                        }
+                    // an unused slot takes the wave's first source (cnt > 0)
+                    vu[u] = base0 + 64 * run + (oku[u] ? nth_set_bit(mask, q) : nth_set_bit(mask, 0));
+                    Au[u] = part[vu[u]];
                 }
                 if constexpr (U > 1 || R > 1) {
                     // unconditional loads (an unused slot holds lane 0's node, a
@@ -685,8 +702,8 @@ hipError_t launch_rb_iteration(const GraphView &g, const Blocks &bk, const int32
         if (nvec <= 1) UPR_RP(1, 4, 4, 1);
         else if (nvec <= 2) UPR_RP(1, 4, 2, 2);
         else if (nvec <= 4) UPR_RP(1, 4, 1, 4);
-        else if (nvec <= 8) UPR_RP(2, 4, 1, 4);
-        else if (nvec <= 16) UPR_RP(4, 4, 1, 4);
+        else if (nvec <= 8) UPR_RP(2, 4, 2, 4);
+        else if (nvec <= 16) UPR_RP(4, 4, 2, 4);
         else if (nvec <= 32) UPR_RP(8, 4, 1, 4);
         else if (nvec <= 64) UPR_RP(16, 4, 1, 4);
         else UPR_RP(64, 4, 1, 1);
