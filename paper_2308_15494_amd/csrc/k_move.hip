@@ -254,11 +254,16 @@ __global__ __launch_bounds__(kBlock) void k_best_move_reg(
     __shared__ unsigned long long cand_lds;
     const bool use_lds = K <= 2048;
     const bool unit = g.vwgt == nullptr;
+    // unit node weights with the table in LDS: a forbidden target (P < 0)
+    // gets a penalty above any gain (a gain is below 2^31, its score below
+    // 2^47), so that one signed comparison decides every entry
+    const bool lean = unit && use_lds;
     if (threadIdx.x == 0) cand_lds = 0;
     if (use_lds)
         for (int j = threadIdx.x; j < K; j += kBlock) {
             sW[j] = W[j];
-            sP[j] = pen1[j];
+            const int64_t P = pen1[j];
+            sP[j] = (lean && P < 0) ? kPenCap : P;
         }
     __syncthreads();
     const int64_t *Wr = use_lds ? sW : W;
@@ -312,7 +317,34 @@ __global__ __launch_bounds__(kBlock) void k_best_move_reg(
             const int32_t ca = __shfl(mine, gbase + (qa & (G - 1)));
             int64_t best = 0, bestP = 0;
             const int64_t cv = node_weight(g, ok ? v : 0);
-            if (ok) {
+            if (ok && lean) {
+                // score (c_j - c_a) 2^16 - P_j for every column: the own
+                // block (0 - P) and columns with c_j <= c_a never score above
+                // zero, so no test of their own is needed; columns come in
+                // increasing order, a strict comparison keeps the smallest j
+                // of a tie
+                int64_t bsc = 0;
+                int32_t bj = 0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int q = r * G + gl;
+                    if (q >= nvec) continue;
+                    const int32_t c4[4] = {x[u][r].x, x[u][r].y, x[u][r].z, x[u][r].w};
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int j = q * 4 + t;
+                        const int64_t sc = ((int64_t)(c4[t] - ca) << 16) - Pr[base + j];
+                        if (sc > bsc) {
+                            bsc = sc;
+                            bj = j;
+                        }
+                    }
+                }
+                if (bsc > 0) {
+                    best = (bsc << 16) | (int64_t)(0xFFFF - bj);
+                    bestP = Pr[base + bj];
+                }
+            } else if (ok) {
                 const int64_t lmax = bk.move_lmax_of(Au);
                 const int64_t *penq = bk.penq_of(Au);
 #pragma unroll
