@@ -333,7 +333,8 @@ __global__ __launch_bounds__(kBlock) void k_best_move_reg(
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
                         const int j = q * 4 + t;
-                        const int64_t sc = ((int64_t)(c4[t] - ca) << 16) - Pr[base + j];
+                        // (sP itself, not the generic Pr: LDS loads instead of flat ones)
+                        const int64_t sc = ((int64_t)(c4[t] - ca) << 16) - sP[base + j];
                         if (sc > bsc) {
                             bsc = sc;
                             bj = j;
@@ -342,7 +343,7 @@ __global__ __launch_bounds__(kBlock) void k_best_move_reg(
                 }
                 if (bsc > 0) {
                     best = (bsc << 16) | (int64_t)(0xFFFF - bj);
-                    bestP = Pr[base + bj];
+                    bestP = sP[base + bj];
                 }
             } else if (ok) {
                 const int64_t lmax = bk.move_lmax_of(Au);

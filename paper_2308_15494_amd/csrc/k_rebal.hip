@@ -197,8 +197,10 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
     if (h_lds)
         for (int j = threadIdx.x; j < K * kRbBuckets; j += kBlock) sH[j] = 0;
     __syncthreads();
-    const int64_t *W0 = w_lds ? sW : r.W0;
-
+    // the node scan, instantiated once per source of the block weights (the
+    // LDS copy or global memory), so that the weights are read with LDS
+    // loads rather than generic ones
+    auto scan_nodes = [&](const int64_t *W0) {
     constexpr int GPW = 64 / G;  // lane groups per wave
     const int lane = lane_id();
     const int grp = lane / G;
@@ -340,6 +342,9 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
             }
         }
     }
+    };
+    if (w_lds) scan_nodes(sW);
+    else scan_nodes(r.W0);
     if (h_lds) {
         __syncthreads();
         for (int j = threadIdx.x; j < K * kRbBuckets; j += kBlock)
