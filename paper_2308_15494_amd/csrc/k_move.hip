@@ -115,7 +115,7 @@ hipError_t launch_cb_prefix(const Blocks &bk, int64_t *bucket, const int64_t *W,
 // best score (ties to the smaller j) is reduced as (score << 16 | 0xFFFF - j).
 // key[v] = score << 16 | j for candidates (score > 0), -1 otherwise. j is the
 // local block (row index); W, cb and pen1 are read at the global id base + j.
-template <int G, int V>
+template <int G, int V, bool LW>
 __global__ __launch_bounds__(kBlock) void k_best_move(
     GraphView g, Blocks bk, const int32_t *__restrict__ part, const int32_t *__restrict__ conn,
     const int64_t *__restrict__ W, const int64_t *__restrict__ cb,
@@ -129,7 +129,9 @@ __global__ __launch_bounds__(kBlock) void k_best_move(
     int64_t *sW = (int64_t *)lds_raw;
     int64_t *sP = sW + K;
     __shared__ unsigned long long cand_lds;
-    const bool use_lds = K <= 2048;
+    // LW (K <= 2048): block weights and penalties from their LDS copies; a
+    // compile-time choice, so that no load goes through a generic pointer
+    constexpr bool use_lds = LW;
     const bool unit = g.vwgt == nullptr;
     if (threadIdx.x == 0) cand_lds = 0;
     if (use_lds)
@@ -138,8 +140,9 @@ __global__ __launch_bounds__(kBlock) void k_best_move(
             sP[j] = pen1[j];
         }
     __syncthreads();
-    const int64_t *Wr = use_lds ? sW : W;
-    const int64_t *Pr = use_lds ? sP : pen1;
+    // values, not a pointer that may point to either: LDS or global loads, not generic ones
+    auto Wr = [&](int64_t i) { return use_lds ? sW[i] : W[i]; };
+    auto Pr = [&](int64_t i) { return use_lds ? sP[i] : pen1[i]; };
 
     constexpr int GPB = kBlock / G;
     const int gl = threadIdx.x & (G - 1);
@@ -178,11 +181,11 @@ __global__ __launch_bounds__(kBlock) void k_best_move(
                     const int64_t delta = (int64_t)cj - ca;
                     int64_t P;
                     if (unit) {
-                        P = Pr[base + j];
+                        P = Pr(base + j);
                         if (P < 0) continue;
                     } else {
                         P = 0;
-                        const int64_t x = Wr[base + j] + cv - lmax;
+                        const int64_t x = Wr(base + j) + cv - lmax;
                         if (x > 0) {
                             if (mode == 1 || mode == 3) continue;
                             if (mode == 0) {
@@ -238,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void k_best_move(
 // per lane group and step. The row loads, part[v] and the next node's loads
 // are in flight together, and omega(v, V_a) comes from the loaded row by a
 // shuffle instead of a dependent load.
-template <int G, int R, int U>
+template <int G, int R, int U, bool LW>
 __global__ __launch_bounds__(kBlock) void k_best_move_reg(
     GraphView g, Blocks bk, const int32_t *__restrict__ part, const int32_t *__restrict__ conn,
     const int64_t *__restrict__ W, const int64_t *__restrict__ cb,
@@ -252,7 +255,9 @@ __global__ __launch_bounds__(kBlock) void k_best_move_reg(
     int64_t *sW = (int64_t *)lds_raw;
     int64_t *sP = sW + K;
     __shared__ unsigned long long cand_lds;
-    const bool use_lds = K <= 2048;
+    // LW (K <= 2048): block weights and penalties from their LDS copies; a
+    // compile-time choice, so that no load goes through a generic pointer
+    constexpr bool use_lds = LW;
     const bool unit = g.vwgt == nullptr;
     // unit node weights with the table in LDS: a forbidden target (P < 0)
     // gets a penalty above any gain (a gain is below 2^31, its score below
@@ -266,8 +271,9 @@ __global__ __launch_bounds__(kBlock) void k_best_move_reg(
             sP[j] = (lean && P < 0) ? kPenCap : P;
         }
     __syncthreads();
-    const int64_t *Wr = use_lds ? sW : W;
-    const int64_t *Pr = use_lds ? sP : pen1;
+    // values, not a pointer that may point to either: LDS or global loads, not generic ones
+    auto Wr = [&](int64_t i) { return use_lds ? sW[i] : W[i]; };
+    auto Pr = [&](int64_t i) { return use_lds ? sP[i] : pen1[i]; };
 
     constexpr int GPB = kBlock / G;
     const int lane = lane_id();
@@ -361,11 +367,11 @@ __global__ __launch_bounds__(kBlock) void k_best_move_reg(
                         const int64_t delta = (int64_t)cj - ca;
                         int64_t P;
                         if (unit) {
-                            P = Pr[base + j];
+                            P = Pr(base + j);
                             if (P < 0) continue;
                         } else {
                             P = 0;
-                            const int64_t xx = Wr[base + j] + cv - lmax;
+                            const int64_t xx = Wr(base + j) + cv - lmax;
                             if (xx > 0) {
                                 if (mode == 1 || mode == 3) continue;
                                 if (mode == 0) {
@@ -423,7 +429,7 @@ __global__ __launch_bounds__(kBlock) void k_best_move_reg(
 // edge weights per block in a register list (their blocks from the compact
 // partition copy) and scores every listed block against the sum for its
 // own block. Nodes of higher degree are left to the row kernel.
-template <int D, int PB>
+template <int D, int PB, bool LW>
 __global__ __launch_bounds__(kBlock) void k_best_move_adj(
     GraphView g, Blocks bk, const int32_t *__restrict__ part, PartView pv,
     const int64_t *__restrict__ W, const int64_t *__restrict__ cb,
@@ -436,7 +442,9 @@ __global__ __launch_bounds__(kBlock) void k_best_move_adj(
     int64_t *sW = (int64_t *)lds_raw;
     int64_t *sP = sW + K;
     __shared__ unsigned long long cand_lds;
-    const bool use_lds = K <= 2048;
+    // LW (K <= 2048): block weights and penalties from their LDS copies; a
+    // compile-time choice, so that no load goes through a generic pointer
+    constexpr bool use_lds = LW;
     const bool unit = g.vwgt == nullptr;
     if (threadIdx.x == 0) cand_lds = 0;
     if (use_lds)
@@ -445,8 +453,9 @@ __global__ __launch_bounds__(kBlock) void k_best_move_adj(
             sP[j] = pen1[j];
         }
     __syncthreads();
-    const int64_t *Wr = use_lds ? sW : W;
-    const int64_t *Pr = use_lds ? sP : pen1;
+    // values, not a pointer that may point to either: LDS or global loads, not generic ones
+    auto Wr = [&](int64_t i) { return use_lds ? sW[i] : W[i]; };
+    auto Pr = [&](int64_t i) { return use_lds ? sP[i] : pen1[i]; };
     const int32_t pmask = part_mask(pv);
     unsigned long long cands = 0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
@@ -514,11 +523,11 @@ __global__ __launch_bounds__(kBlock) void k_best_move_adj(
                 const int64_t delta = (int64_t)cj - ca;
                 int64_t P;
                 if (unit) {
-                    P = Pr[base + j];
+                    P = Pr(base + j);
                     if (P < 0) continue;
                 } else {
                     P = 0;
-                    const int64_t xx = Wr[base + j] + cv - lmax;
+                    const int64_t xx = Wr(base + j) + cv - lmax;
                     if (xx > 0) {
                         if (mode == 1 || mode == 3) continue;
                         if (mode == 0) {
@@ -594,15 +603,23 @@ hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t 
 {
     if (g.n <= 0) return hipSuccess;
     const int32_t k = bk.k;
-    const size_t lds = bk.total() <= 2048 ? (size_t)bk.total() * 16 : 0;
+    const bool lw = bk.total() <= 2048;
+    const size_t lds = lw ? (size_t)bk.total() * 16 : 0;
     if (adj_deg > 0) {
         if (adj_deg > kAdjMaxDeg || pv.bytes > 2) return hipErrorInvalidValue;
         // the register list no longer than the graph's largest degree
         const int32_t dl = max_deg < adj_deg ? (int32_t)max_deg : adj_deg;
 #define UPR_BA(DD, PP)                                                                             \
-    hipLaunchKernelGGL((k_best_move_adj<DD, PP>), dim3(grid_cap(g.n, kBlock, 8192)), dim3(kBlock),  \
-                       lds, s, g, bk, part, pv, W, cb, pen1, mode, active, key, pen, counters,     \
-                       cflag, cflag2, key2, perm, adj_deg)
+    do {                                                                                           \
+        if (lw)                                                                                    \
+            hipLaunchKernelGGL((k_best_move_adj<DD, PP, true>), dim3(grid_cap(g.n, kBlock, 8192)), \
+                               dim3(kBlock), lds, s, g, bk, part, pv, W, cb, pen1, mode, active,   \
+                               key, pen, counters, cflag, cflag2, key2, perm, adj_deg);            \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_best_move_adj<DD, PP, false>), dim3(grid_cap(g.n, kBlock, 8192)),\
+                               dim3(kBlock), lds, s, g, bk, part, pv, W, cb, pen1, mode, active,   \
+                               key, pen, counters, cflag, cflag2, key2, perm, adj_deg);            \
+    } while (0)
         if (dl <= 4) {
             if (pv.bytes == 1) UPR_BA(4, 1);
             else UPR_BA(4, 2);
@@ -622,10 +639,18 @@ hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t 
     const int nvec = vec ? k / 4 : k;
     if (vec && nvec <= 256) {
 #define UPR_BR(GG, RR, UU)                                                                          \
-    hipLaunchKernelGGL((k_best_move_reg<GG, RR, UU>),                                               \
-                       dim3(grid_cap((g.n + UU - 1) / UU, kBlock / GG, 8192)), dim3(kBlock), lds, s, \
-                       g, bk, part, conn, W, cb, pen1, mode, active, key, pen, counters, cflag,  \
-                       cflag2, key2, perm, adj_deg)
+    do {                                                                                            \
+        if (lw)                                                                                     \
+            hipLaunchKernelGGL((k_best_move_reg<GG, RR, UU, true>),                                 \
+                               dim3(grid_cap((g.n + UU - 1) / UU, kBlock / GG, 8192)), dim3(kBlock), \
+                               lds, s, g, bk, part, conn, W, cb, pen1, mode, active, key, pen,      \
+                               counters, cflag, cflag2, key2, perm, adj_deg);                       \
+        else                                                                                        \
+            hipLaunchKernelGGL((k_best_move_reg<GG, RR, UU, false>),                                \
+                               dim3(grid_cap((g.n + UU - 1) / UU, kBlock / GG, 8192)), dim3(kBlock), \
+                               lds, s, g, bk, part, conn, W, cb, pen1, mode, active, key, pen,      \
+                               counters, cflag, cflag2, key2, perm, adj_deg);                       \
+    } while (0)
         // each lane holds up to four int4 of the row: fewer lanes per node
         // mean fewer shuffle rounds per scored entry (at k = 64, 4 lanes per
         // node took 80 us where 16 lanes took 102)
@@ -642,9 +667,16 @@ hipError_t launch_best_move(const GraphView &g, const Blocks &bk, const int32_t 
         return hipGetLastError();
     }
 #define UPR_BM(GG, VV)                                                                             \
-    hipLaunchKernelGGL((k_best_move<GG, VV>), dim3(grid_cap(g.n, kBlock / GG, 8192)), dim3(kBlock), \
-                       lds, s, g, bk, part, conn, W, cb, pen1, mode, active, key, pen, counters, \
-                       cflag, cflag2, key2, perm, adj_deg)
+    do {                                                                                           \
+        if (lw)                                                                                    \
+            hipLaunchKernelGGL((k_best_move<GG, VV, true>), dim3(grid_cap(g.n, kBlock / GG, 8192)),  \
+                               dim3(kBlock), lds, s, g, bk, part, conn, W, cb, pen1, mode, active,  \
+                               key, pen, counters, cflag, cflag2, key2, perm, adj_deg);             \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_best_move<GG, VV, false>), dim3(grid_cap(g.n, kBlock / GG, 8192)), \
+                               dim3(kBlock), lds, s, g, bk, part, conn, W, cb, pen1, mode, active,  \
+                               key, pen, counters, cflag, cflag2, key2, perm, adj_deg);             \
+    } while (0)
     if (vec) {
         if (nvec <= 1) UPR_BM(1, 4);
         else if (nvec <= 2) UPR_BM(2, 4);
@@ -824,10 +856,11 @@ __global__ __launch_bounds__(kBlock) void k_filter(GraphView g, Blocks bk, int o
 #pragma unroll
         for (int i = 0; i < kFilterUnroll; ++i) {
             cand[i] = !pv.flagged || (raw[i] & kCandFlag);
-            // (a neighbour that is no candidate takes the node's own key from
-            // LDS: unused, and no load in a branch)
-            if constexpr (RL) kraw[i] = cand[i] ? key2[ur[i]] : skey[node[i]];
-            else kraw[i] = cand[i] ? key[u[i]] : skey[node[i]];
+            // (a neighbour that is no candidate reads entry 0, one cached
+            // line, unused: no load in a branch, and a global load rather than
+            // a generic one that could also reach LDS)
+            if constexpr (RL) kraw[i] = key2[cand[i] ? ur[i] : 0];
+            else kraw[i] = key[cand[i] ? u[i] : 0];
         }
 #pragma unroll
         for (int i = 0; i < kFilterUnroll; ++i) {
@@ -1052,6 +1085,7 @@ hipError_t launch_filter_seq(const GraphView &g, const Blocks &bk, const int32_t
 // read the old part).
 constexpr int kApplyTile = 1024;
 
+template <bool LW>
 __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, Blocks bk, int32_t *part,
                                                    PartView pv, int32_t *conn, int64_t *W,
                                                    int32_t *mvto, int64_t hub_t,
@@ -1071,11 +1105,13 @@ __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, Blocks bk, int32_
     const bool all = moved_deg > all_threshold;
     int64_t *wloc = (int64_t *)lds_raw;
     const int32_t K = bk.total();
-    const bool use_lds = K <= 2048;
+    // LW (K <= 2048): block weights summed in LDS, a compile-time choice so
+    // that the atomics are LDS ones rather than generic ones
+    constexpr bool use_lds = LW;
     if (use_lds)
         for (int j = threadIdx.x; j < K; j += kBlock) wloc[j] = 0;
     __syncthreads();
-    int64_t *wdst = use_lds ? wloc : W;
+
     const int64_t v0 = (int64_t)blockIdx.x * kApplyTile;
     const int nt = (int)((g.n - v0) < kApplyTile ? (g.n - v0) : kApplyTile);
 
@@ -1115,8 +1151,13 @@ __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, Blocks bk, int32_
         pset((void *)pv.p, pv.bytes, v, (int32_t)lb);
         if (pc2) pset(pc2, pv.bytes, perm[v], (int32_t)lb);
         mvto[v] = -1;
-        atomicAdd((unsigned long long *)&wdst[A], (unsigned long long)(-cv));
-        atomicAdd((unsigned long long *)&wdst[to], (unsigned long long)cv);
+        if (use_lds) {  // (LDS atomics, not generic ones)
+            atomicAdd((unsigned long long *)&wloc[A], (unsigned long long)(-cv));
+            atomicAdd((unsigned long long *)&wloc[to], (unsigned long long)cv);
+        } else {
+            atomicAdd((unsigned long long *)&W[A], (unsigned long long)(-cv));
+            atomicAdd((unsigned long long *)&W[to], (unsigned long long)cv);
+        }
     }
     int32_t run;
     {
@@ -1230,9 +1271,14 @@ hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, con
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     const int64_t tiles = (g.n + kApplyTile - 1) / kApplyTile;
-    hipLaunchKernelGGL(k_apply, dim3((unsigned)tiles), dim3(kBlock), lds, s, g, bk, part, pv, conn,
-                       W, mvto, hub_t, counters, dirty_threshold, dirty, T, pc2, perm,
-                       all_threshold);
+    if (bk.total() <= 2048)
+        hipLaunchKernelGGL(k_apply<true>, dim3((unsigned)tiles), dim3(kBlock), lds, s, g, bk, part,
+                           pv, conn, W, mvto, hub_t, counters, dirty_threshold, dirty, T, pc2, perm,
+                           all_threshold);
+    else
+        hipLaunchKernelGGL(k_apply<false>, dim3((unsigned)tiles), dim3(kBlock), lds, s, g, bk, part,
+                           pv, conn, W, mvto, hub_t, counters, dirty_threshold, dirty, T, pc2, perm,
+                           all_threshold);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // rebuild the marked tiles and the hub rows (nothing in the delta mode)
     return launch_gain_refresh(tg, k, tpv, conn, hub_t, h, dirty, counters, dirty_threshold,
