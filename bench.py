@@ -575,6 +575,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat20")
     ap.add_argument("--resident", action="store_true", help="time the resident-table form")
+    ap.add_argument("--no-resident-leg", action="store_true",
+                    help="skip the resident form reported beside the rebuild-form headline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--pmc-run", action="store_true",
@@ -698,7 +700,7 @@ def main():
         "host": host_info(),
     }
 
-    if not args.resident:
+    if not args.resident and not args.no_resident_leg:
         out["resident"] = resident_leg(ctx, g, k, eps, rounds, part0, args.steps, args.warmup,
                                        res["rec"])
     if not args.no_cpu:
