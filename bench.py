@@ -209,8 +209,9 @@ def roofline_entry(kernel, bytes_total, seconds_total, launches, note):
 
 def single_graph(ctx, g, k, eps, rounds, part0, steps, warmup, resident, hub_t=4096,
                  dirty_div=16, phase_rounds=None, opts=None, variant=0):
-    """Times `steps` rounds of one graph (edges/s; only the gain-table kernel
-    is bracketed by events inside the timed region), then repeats them from
+    """Times `steps` rounds of one graph, run by one upr_refine_rounds call
+    (edges/s; only the gain-table kernel is bracketed by events inside the
+    timed region), then repeats them one call per round from
     the same start, untimed, with every phase timed and read after each
     round, to get the per-round statistics, partitions and block weights
     (for the parity check) and the per-kernel rooflines."""
@@ -220,11 +221,13 @@ def single_graph(ctx, g, k, eps, rounds, part0, steps, warmup, resident, hub_t=4
     r = upr.Refiner(g, k, ctx=ctx, opts=opts)
     info = r.plan.info()
 
+    def round_params(i):
+        return upr.params(k, eps, tau=gg.tau_schedule(i, rounds),
+                          rebuild_table=0 if (resident and i > 1) else 1, variant=variant)
+
     def run_rounds(count, per_round=None):
         for i in range(1, count + 1):
-            p = upr.params(k, eps, tau=gg.tau_schedule(i, rounds),
-                           rebuild_table=0 if (resident and i > 1) else 1, variant=variant)
-            r.round(p)
+            r.round(round_params(i))
             if per_round is not None:
                 per_round(i)
 
@@ -234,21 +237,25 @@ def single_graph(ctx, g, k, eps, rounds, part0, steps, warmup, resident, hub_t=4
         r.W.zero_()
         torch.cuda.synchronize()
 
+    # the timed rounds: the schedule's parameters are inputs, built beforehand,
+    # and the rounds run in one call (upr_refine_rounds)
+    sched = [round_params(i) for i in range(1, steps + 1)]
     restart()
-    run_rounds(warmup)
+    if warmup > 0:
+        r.rounds([round_params(i) for i in range(1, warmup + 1)])
     torch.cuda.synchronize()
     restart()
     ctx.timing_read(reset=True)
     ctx.timing(True, phases=["gain_tile"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    run_rounds(steps)
+    st_all = r.rounds(sched)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     ctx.timing(False)
     tile_ms, tile_cnt = ctx.timing_read(reset=True)["gain_tile"]
     total_s = t2 - t1
-    final = upr.stats_dict(r.stats)
+    final = upr.stats_dict(st_all[steps - 1] if steps > 0 else r.stats)
 
     # the repeat: per-round phases, statistics, partitions and move counts
     deg = np.diff(g.xadj).astype(np.int64)

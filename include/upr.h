@@ -231,6 +231,18 @@ int upr_edge_cut_noalloc(upr_ctx *ctx, const upr_graph *graph, const int32_t *pa
 int upr_refine_round(upr_ctx *ctx, const upr_plan *plan, const upr_params *params, int32_t *part,
                      int32_t *conn, int64_t *block_w, int64_t *stats, hipStream_t stream);
 
+/* A schedule of rounds (Section 5.5: one round after another, each with its
+ * own penalty factor tau and form): round r = 0 .. rounds - 1 with
+ * params[r] (host array), in place on (part, conn, block_w), exactly as
+ * `rounds` calls of upr_refine_round but without returning to the caller
+ * between them. stats: device int64 [rounds * UPR_STATS_LEN], round r's at
+ * r * UPR_STATS_LEN. Stops at the first round that fails and returns its
+ * error (the rounds before it stand, later entries of stats are not
+ * written). rounds = 0 does nothing. */
+int upr_refine_rounds(upr_ctx *ctx, const upr_plan *plan, const upr_params *params, int32_t rounds,
+                      int32_t *part, int32_t *conn, int64_t *block_w, int64_t *stats,
+                      hipStream_t stream);
+
 /* Rebalancing alone (Section 7.1): S1 if params->rebuild_table, then S5 and
  * S6. Same arrays as upr_refine_round; mode and tau are ignored. */
 int upr_rebalance(upr_ctx *ctx, const upr_plan *plan, const upr_params *params, int32_t *part,

@@ -1348,6 +1348,20 @@ int upr_refine_round(upr_ctx *c, const upr_plan *p, const upr_params *q, int32_t
     return round_common(c, p, q, part, conn, W, stats, s, true);
 }
 
+int upr_refine_rounds(upr_ctx *c, const upr_plan *p, const upr_params *q, int32_t rounds,
+                      int32_t *part, int32_t *conn, int64_t *W, int64_t *stats, hipStream_t s)
+{
+    if (!c) return UPR_E_ARG;
+    if (rounds < 0) return fail(c, UPR_E_ARG, "rounds=%d is negative", rounds);
+    if (rounds > 0 && (!q || !stats)) return fail(c, UPR_E_ARG, "params/stats NULL");
+    for (int32_t r = 0; r < rounds; ++r) {
+        const int rc = round_common(c, p, q + r, part, conn, W, stats + (int64_t)r * UPR_STATS_LEN,
+                                    s, true);
+        if (rc) return rc;
+    }
+    return UPR_OK;
+}
+
 int upr_rebalance(upr_ctx *c, const upr_plan *p, const upr_params *q, int32_t *part, int32_t *conn,
                   int64_t *W, int64_t *stats, hipStream_t s)
 {

@@ -82,6 +82,8 @@ _SIGS = [
                                        C.c_void_p]),
     ("upr_refine_round", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(Params), C.c_void_p,
                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("upr_refine_rounds", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("upr_rebalance", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(Params), C.c_void_p,
                                 C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("upr_last_moves", C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -345,6 +347,20 @@ def refine_round(ctx, plan, p: Params, part, conn, W, stats=None, stream=None):
     return stats
 
 
+def refine_rounds(ctx, plan, ps, part, conn, W, stats=None, stream=None):
+    """Rounds with the Params of the sequence ps, one after another, in one
+    call (upr_refine_rounds); returns the device stats tensor [len(ps),
+    STATS_LEN]."""
+    import torch
+    arr = (Params * len(ps))(*ps)
+    if stats is None:
+        stats = torch.empty((max(len(ps), 1), STATS_LEN), dtype=torch.int64, device=part.device)
+    ctx.check(lib().upr_refine_rounds(ctx.handle, plan.handle, C.cast(arr, C.c_void_p), len(ps),
+                                      _ptr(part), _ptr(conn), _ptr(W), _ptr(stats),
+                                      _stream(stream)))
+    return stats
+
+
 def rebalance(ctx, plan, p: Params, part, conn, W, stats=None, stream=None):
     import torch
     if stats is None:
@@ -392,6 +408,10 @@ class Refiner:
     def round(self, p: Params):
         refine_round(self.ctx, self.plan, p, self.part, self.conn, self.W, self.stats)
         return self.stats
+
+    def rounds(self, ps, stats=None):
+        """The rounds of ps in one call; returns their stats [len(ps), STATS_LEN]."""
+        return refine_rounds(self.ctx, self.plan, ps, self.part, self.conn, self.W, stats)
 
     def rebalance(self, p: Params):
         rebalance(self.ctx, self.plan, p, self.part, self.conn, self.W, self.stats)
