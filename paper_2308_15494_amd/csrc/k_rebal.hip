@@ -201,147 +201,147 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
     // LDS copy or global memory), so that the weights are read with LDS
     // loads rather than generic ones
     auto scan_nodes = [&](const int64_t *W0) {
-    constexpr int GPW = 64 / G;  // lane groups per wave
-    const int lane = lane_id();
-    const int grp = lane / G;
-    const int gl = lane & (G - 1);
-    const int nvec = k / V;
-    // kRbRuns runs of 64 node ids per wave and step: their part entries and
-    // block weights are loaded before any run is worked on
-    const int64_t stride = (int64_t)gridDim.x * kBlock * kRbRuns;
-    for (int64_t base0 = ((int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63)) * kRbRuns; base0 < g.n;
-         base0 += stride) {
-        int32_t lar[kRbRuns];
-        uint64_t maskr[kRbRuns];
-#pragma unroll
-        for (int i = 0; i < kRbRuns; ++i) {
-            const int64_t lv = base0 + 64 * i + lane;
-            lar[i] = part[lv < g.n ? lv : g.n - 1];
-        }
-#pragma unroll
-        for (int i = 0; i < kRbRuns; ++i) {
-            const int64_t lv = base0 + 64 * i + lane;
-            const bool ok = lv < g.n && (unsigned)lar[i] < (unsigned)K;
-            const int32_t a = ok ? lar[i] : 0;
-            maskr[i] = __ballot(ok && W0[a] > bk.src_lmax_of(a));
-        }
-        int cntr[kRbRuns];
-        int cnt = 0;
-#pragma unroll
-        for (int i = 0; i < kRbRuns; ++i) {
-            cntr[i] = __popcll(maskr[i]);
-            cnt += cntr[i];
-        }
-        {
+        constexpr int GPW = 64 / G;  // lane groups per wave
+        const int lane = lane_id();
+        const int grp = lane / G;
+        const int gl = lane & (G - 1);
+        const int nvec = k / V;
+        // kRbRuns runs of 64 node ids per wave and step: their part entries and
+        // block weights are loaded before any run is worked on
+        const int64_t stride = (int64_t)gridDim.x * kBlock * kRbRuns;
+        for (int64_t base0 = ((int64_t)blockIdx.x * kBlock + (threadIdx.x & ~63)) * kRbRuns; base0 < g.n;
+             base0 += stride) {
+            int32_t lar[kRbRuns];
+            uint64_t maskr[kRbRuns];
+    #pragma unroll
+            for (int i = 0; i < kRbRuns; ++i) {
+                const int64_t lv = base0 + 64 * i + lane;
+                lar[i] = part[lv < g.n ? lv : g.n - 1];
+            }
+    #pragma unroll
+            for (int i = 0; i < kRbRuns; ++i) {
+                const int64_t lv = base0 + 64 * i + lane;
+                const bool ok = lv < g.n && (unsigned)lar[i] < (unsigned)K;
+                const int32_t a = ok ? lar[i] : 0;
+                maskr[i] = __ballot(ok && W0[a] > bk.src_lmax_of(a));
+            }
+            int cntr[kRbRuns];
+            int cnt = 0;
+    #pragma unroll
+            for (int i = 0; i < kRbRuns; ++i) {
+                cntr[i] = __popcll(maskr[i]);
+                cnt += cntr[i];
+            }
             // source p of the wave's list: the q-th set bit of the run that holds it
-            for (int p0 = 0; p0 < cnt; p0 += GPW * U) {
-                int64_t vu[U];
-                int32_t Au[U];
-                bool oku[U];
-                int32_t cu[U][R][V];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int p = p0 + u * GPW + grp;
-                    oku[u] = p < cnt;
-                    int q = oku[u] ? p : 0, run = 0;
-                    uint64_t mask = maskr[0];
-#pragma unroll
-                    for (int i = 0; i + 1 < kRbRuns; ++i)
-                        if (run == i && q >= cntr[i]) {
-                            q -= cntr[i];
-                            run = i + 1;
-                            mask = maskr[i + 1];
-                        }
-                    // an unused slot takes the wave's first source (cnt > 0)
-                    vu[u] = base0 + 64 * run + (oku[u] ? nth_set_bit(mask, q) : nth_set_bit(mask, 0));
-                    Au[u] = part[vu[u]];
-                }
-                if constexpr (U > 1 || R > 1) {
-                    // unconditional loads (an unused slot holds lane 0's node, a
-                    // valid one; q >= nvec rereads the last vector, unused), so
-                    // that all rows are in flight together
-#pragma unroll
+            {
+                for (int p0 = 0; p0 < cnt; p0 += GPW * U) {
+                    int64_t vu[U];
+                    int32_t Au[U];
+                    bool oku[U];
+                    int32_t cu[U][R][V];
+    #pragma unroll
                     for (int u = 0; u < U; ++u) {
-#pragma unroll
-                        for (int r = 0; r < R; ++r) {
-                            const int q = gl + r * G;
-                            rb_load_vec<V>(conn + vu[u] * (int64_t)k, q < nvec ? q : nvec - 1, cu[u][r]);
-                        }
+                        const int p = p0 + u * GPW + grp;
+                        oku[u] = p < cnt;
+                        int q = oku[u] ? p : 0, run = 0;
+                        uint64_t mask = maskr[0];
+    #pragma unroll
+                        for (int i = 0; i + 1 < kRbRuns; ++i)
+                            if (run == i && q >= cntr[i]) {
+                                q -= cntr[i];
+                                run = i + 1;
+                                mask = maskr[i + 1];
+                            }
+                        // an unused slot takes the wave's first source (cnt > 0)
+                        vu[u] = base0 + 64 * run + (oku[u] ? nth_set_bit(mask, q) : nth_set_bit(mask, 0));
+                        Au[u] = part[vu[u]];
                     }
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const bool ok = oku[u];
-                    const int64_t v = vu[u];
-                    const int32_t A = Au[u];
-                    const int32_t a = ok ? bk.local(A) : 0;     // row index of the source
-                    const int32_t base = ok ? bk.base(A) : 0;  // global id of local block 0
-                    const int64_t lmax = ok ? bk.lmax_of(A) : 0;
-                    int64_t best = -1, lw = INT64_MAX, cv = 1;
-                    int32_t lj = 0x7fffffff;
-                    int32_t ca_mine = 0;  // omega(v, V_a), held by the lane that loads column a
-                    if (ok) {
-                        cv = node_weight(g, v);
-                        if constexpr (U > 1 || R > 1) {
-#pragma unroll
+                    if constexpr (U > 1 || R > 1) {
+                        // unconditional loads (an unused slot holds the wave's first
+                        // source; q >= nvec rereads the last vector, unused), so
+                        // that all rows are in flight together
+    #pragma unroll
+                        for (int u = 0; u < U; ++u) {
+    #pragma unroll
                             for (int r = 0; r < R; ++r) {
                                 const int q = gl + r * G;
-                                if (q < nvec)
-                                    rb_scan_cols<V>(cu[u][r], q * V, a, base, cv, lmax, W0, best, lw,
-                                                    lj, ca_mine);
+                                rb_load_vec<V>(conn + vu[u] * (int64_t)k, q < nvec ? q : nvec - 1, cu[u][r]);
                             }
+                        }
+                    }
+    #pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const bool ok = oku[u];
+                        const int64_t v = vu[u];
+                        const int32_t A = Au[u];
+                        const int32_t a = ok ? bk.local(A) : 0;     // row index of the source
+                        const int32_t base = ok ? bk.base(A) : 0;  // global id of local block 0
+                        const int64_t lmax = ok ? bk.lmax_of(A) : 0;
+                        int64_t best = -1, lw = INT64_MAX, cv = 1;
+                        int32_t lj = 0x7fffffff;
+                        int32_t ca_mine = 0;  // omega(v, V_a), held by the lane that loads column a
+                        if (ok) {
+                            cv = node_weight(g, v);
+                            if constexpr (U > 1 || R > 1) {
+    #pragma unroll
+                                for (int r = 0; r < R; ++r) {
+                                    const int q = gl + r * G;
+                                    if (q < nvec)
+                                        rb_scan_cols<V>(cu[u][r], q * V, a, base, cv, lmax, W0, best, lw,
+                                                        lj, ca_mine);
+                                }
+                            } else {
+                                const int32_t *row = conn + v * (int64_t)k;
+                                for (int q = gl; q < nvec; q += G) {
+                                    int32_t c[V];
+                                    rb_load_vec<V>(row, q, c);
+                                    rb_scan_cols<V>(c, q * V, a, base, cv, lmax, W0, best, lw, lj,
+                                                    ca_mine);
+                                }
+                            }
+                        }
+    #pragma unroll
+                        for (int off = G / 2; off > 0; off >>= 1) {
+                            const int64_t ob = __shfl_xor(best, off);
+                            const int64_t ow = __shfl_xor(lw, off);
+                            const int32_t oj = __shfl_xor(lj, off);
+                            if (ob > best) best = ob;
+                            if (ow < lw || (ow == lw && oj < lj)) {
+                                lw = ow;
+                                lj = oj;
+                            }
+                        }
+                        // column a sits in vector a / V, loaded by lane (a / V) mod G of the group
+                        const int32_t ca = __shfl(ca_mine, (lane & ~(G - 1)) + ((a / V) & (G - 1)));
+                        bool push = false;
+                        int64_t hkey = 0;
+                        if (ok && gl == 0) {
+                            int32_t tgt = -1;
+                            int64_t ct = 0;
+                            if (best >= 0) {
+                                tgt = 0xFFFF - (int32_t)(best & 0xFFFF);
+                                ct = best >> 16;
+                            } else if (lj != 0x7fffffff) {
+                                tgt = lj;
+                            }
+                            r.rtgt[v] = tgt >= 0 ? base + tgt : -1;
+                            if (tgt >= 0) {
+                                // the plain-gain variant ranks by the gain alone (c(v) = 1)
+                                const int be = rebalance_bucket(ct - (int64_t)ca, plain ? 1 : cv);
+                                r.rbeta[v] = (uint8_t)be;
+                                hkey = (int64_t)(base + tgt) * kRbBuckets + be;
+                                push = true;
+                            }
+                        }
+                        if (h_lds) {
+                            if (push) atomicAdd(&sH[hkey], (uint32_t)cv);
                         } else {
-                            const int32_t *row = conn + v * (int64_t)k;
-                            for (int q = gl; q < nvec; q += G) {
-                                int32_t c[V];
-                                rb_load_vec<V>(row, q, c);
-                                rb_scan_cols<V>(c, q * V, a, base, cv, lmax, W0, best, lw, lj,
-                                                ca_mine);
-                            }
+                            wave_hist_add(r.hist_tgt, hkey, cv, push);
                         }
-                    }
-#pragma unroll
-                    for (int off = G / 2; off > 0; off >>= 1) {
-                        const int64_t ob = __shfl_xor(best, off);
-                        const int64_t ow = __shfl_xor(lw, off);
-                        const int32_t oj = __shfl_xor(lj, off);
-                        if (ob > best) best = ob;
-                        if (ow < lw || (ow == lw && oj < lj)) {
-                            lw = ow;
-                            lj = oj;
-                        }
-                    }
-                    // column a sits in vector a / V, loaded by lane (a / V) mod G of the group
-                    const int32_t ca = __shfl(ca_mine, (lane & ~(G - 1)) + ((a / V) & (G - 1)));
-                    bool push = false;
-                    int64_t hkey = 0;
-                    if (ok && gl == 0) {
-                        int32_t tgt = -1;
-                        int64_t ct = 0;
-                        if (best >= 0) {
-                            tgt = 0xFFFF - (int32_t)(best & 0xFFFF);
-                            ct = best >> 16;
-                        } else if (lj != 0x7fffffff) {
-                            tgt = lj;
-                        }
-                        r.rtgt[v] = tgt >= 0 ? base + tgt : -1;
-                        if (tgt >= 0) {
-                            // the plain-gain variant ranks by the gain alone (c(v) = 1)
-                            const int be = rebalance_bucket(ct - (int64_t)ca, plain ? 1 : cv);
-                            r.rbeta[v] = (uint8_t)be;
-                            hkey = (int64_t)(base + tgt) * kRbBuckets + be;
-                            push = true;
-                        }
-                    }
-                    if (h_lds) {
-                        if (push) atomicAdd(&sH[hkey], (uint32_t)cv);
-                    } else {
-                        wave_hist_add(r.hist_tgt, hkey, cv, push);
                     }
                 }
             }
         }
-    }
     };
     if (w_lds) scan_nodes(sW);
     else scan_nodes(r.W0);
