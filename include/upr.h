@@ -358,6 +358,23 @@ int32_t upr_best_move_adjacency_degree(int32_t k, int64_t max_degree);
 /* Q16 penalty factors floor(tau * (3/2)^l * 2^16), l = 0..53, into out[54]. */
 int upr_penalty_table(int32_t tau_num, int32_t tau_den, int64_t *out);
 
+/* Captured move phases, for callers that run many rounds of one
+ * configuration: with enable != 0, a round's kernels from the partition
+ * copies to the cut after the filtered moves (S1 to S4) are captured into a
+ * HIP graph on the context's own stream the first time a configuration is
+ * seen, and replayed from it afterwards; the round's first kernel (which
+ * holds the round's penalty factors) and the rebalancing stay eager. A
+ * configuration is the plan, k, eps, t, mode, rebuild_table, seq_penalty,
+ * variant, alpha and the part / conn / block_w arrays (a graph replays the
+ * kernel arguments it was captured with). Used for single graphs without
+ * the best prefix, without an activity mask (the driver's label-propagation
+ * rounds), with the segment path of the sequence-aware price and with phase
+ * timing off; every other round runs eagerly. Results are identical either
+ * way. At most 16 graphs are kept per context; they are freed when the
+ * workspace grows, when capture is disabled (which synchronises the device)
+ * and by upr_destroy. */
+int upr_capture_enable(upr_ctx *ctx, int enable);
+
 /* Per-phase device time of the calls on this context, accumulated in
  * milliseconds by HIP events while timing is enabled (each timed phase
  * records two events on the call's stream). Phases: 0 gain table,

@@ -1262,7 +1262,7 @@ hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, con
 {
     if (g.n <= 0) return hipSuccess;
     const int32_t k = bk.k;
-    const int T = gain_tile_nodes(k);
+    const int T = gain_tile_nodes(k, g.n);
     const size_t lds = bk.total() <= 2048 ? (size_t)bk.total() * 8 : 0;
     hipError_t e;
     if (h.nh > 0) {

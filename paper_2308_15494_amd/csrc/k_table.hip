@@ -18,11 +18,19 @@ namespace upr {
 constexpr int kTileInts = 8192;  // LDS ints of one tile's rows (32 KiB)
 constexpr int kTileMaxNodes = 1024;
 
-int gain_tile_nodes(int32_t k)
+// Nodes per tile: as many rows as kTileInts LDS ints hold (at most
+// kTileMaxNodes), halved (down to kTileMinNodes) while the graph would get
+// fewer than kTileMinTiles tiles, so that a small graph still spreads over
+// the CUs.
+constexpr int kTileMinNodes = 16;
+constexpr int64_t kTileMinTiles = 2048;
+
+int gain_tile_nodes(int32_t k, int64_t n)
 {
     int t = kTileInts / k;
     if (t > kTileMaxNodes) t = kTileMaxNodes;
     if (t < 1) t = 1;
+    while (t > kTileMinNodes && (n + t - 1) / t < kTileMinTiles) t /= 2;
     return t;
 }
 
@@ -307,7 +315,7 @@ hipError_t launch_gain_table(const GraphView &g, int32_t k, const PartView &part
 {
     if (g.n <= 0) return hipSuccess;
     if (!hubs_ready(h)) return hipErrorInvalidValue;
-    const int T = gain_tile_nodes(k);
+    const int T = gain_tile_nodes(k, g.n);
     const int64_t grid = (g.n + T - 1) / T + std::max<int64_t>(h.nchunks, 0);
     const size_t lds = table_lds(k, T, g.tile16 != 0);
     UPR_TILE_ALL(k_gain_tile, dim3((unsigned)grid), dim3(kBlock), lds, s, g, k, T, part, conn,
@@ -322,7 +330,7 @@ hipError_t launch_gain_refresh(const GraphView &g, int32_t k, const PartView &pa
 {
     if (g.n <= 0) return hipSuccess;
     if (!hubs_ready(h) || !dirty || !counters) return hipErrorInvalidValue;
-    const int T = gain_tile_nodes(k);
+    const int T = gain_tile_nodes(k, g.n);
     const int64_t grid = (g.n + T - 1) / T + std::max<int64_t>(h.nchunks, 0);
     const size_t lds = table_lds(k, T, g.tile16 != 0);
     UPR_TILE_ALL(k_gain_refresh, dim3((unsigned)grid), dim3(kBlock), lds, s, g, k, T, part, conn,

@@ -9,6 +9,7 @@
 #include "upr_common.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -24,6 +25,9 @@ constexpr int64_t kHubChunkEdges = 4096;
 constexpr int64_t kDefaultHubThreshold = 4096;
 constexpr int64_t kRelabelMinNodes = 65536;  // relabel the table build's adjacency from here on
 constexpr int64_t kChunkEntries = int64_t(1) << 20;  // rebalancing id-chunk sums per side
+
+constexpr int kCaptureKey = 16;       // words of a captured span's key
+constexpr size_t kCaptureMax = 16;    // captured spans kept per context
 
 struct Timing {
     uint32_t mask = 0;  // phases timed (bit p = phase p)
@@ -105,6 +109,16 @@ struct upr_ctx {
     int64_t bpinned_cap = 0;  // int64 entries
     bool rb_dirty = false;
     Timing timing;
+    // captured move phases (upr_capture_enable): a non-blocking stream of the
+    // context's own (default priority) to capture on, and the graphs by key
+    bool capture = false;
+    hipStream_t cap_stream = nullptr;
+    struct Captured {
+        uint64_t key[kCaptureKey];
+        hipGraphExec_t exec;
+    };
+    std::vector<Captured> captured;
+    uint64_t ws_gen = 0;  // bumped whenever the workspace is reallocated
     // carry records of upr_batch_carry (device, grown on demand)
     int64_t *carry = nullptr;
     int64_t carry_cap = 0;
@@ -116,6 +130,7 @@ struct upr_ctx {
 
 struct upr_plan {
     upr_ctx *ctx = nullptr;
+    uint64_t serial = 0;  // unique per plan created in this process (keys of captured spans)
     int device = 0;  // the context's device (a plan may outlive its context)
     GraphView g{};
     int64_t nnz = 0, total = 0, maxdeg = 0, maxwdeg = 0, maxvw = 0;
@@ -210,6 +225,13 @@ void dfree(T *&p)
     p = nullptr;
 }
 
+// The captured spans of a context (their kernels hold workspace addresses).
+void drop_captured(upr_ctx *c)
+{
+    for (auto &g : c->captured) (void)hipGraphExecDestroy(g.exec);
+    c->captured.clear();
+}
+
 void free_workspace(upr_ctx *c)
 {
     dfree(c->key);
@@ -274,6 +296,8 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
     const int64_t K = std::max<int64_t>(std::max<int64_t>(k, c->cap_k), 2);
     HIP_TRY(c, hipDeviceSynchronize());
     free_workspace(c);
+    drop_captured(c);  // their kernels hold the old workspace's addresses
+    ++c->ws_gen;
     const int64_t NB = seq_bucket_bound(N, (int)K);
     bool ok = dalloc(&c->key, N) == hipSuccess && dalloc(&c->pen, N) == hipSuccess &&
               dalloc(&c->key2, N) == hipSuccess &&
@@ -813,6 +837,8 @@ void upr_destroy(upr_ctx *c)
         (void)hipEventDestroy(p.b);
     }
     for (auto e : c->timing.pool) (void)hipEventDestroy(e);
+    drop_captured(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
 }
 
@@ -916,6 +942,8 @@ static int plan_create(upr_ctx *c, const upr_graph *graph, upr_plan **out, hipSt
     }
 
     upr_plan *p = new upr_plan();
+    static std::atomic<uint64_t> plan_serial{0};
+    p->serial = ++plan_serial;
     p->ctx = c;
     p->device = c->device;
     p->g = g;
@@ -1124,6 +1152,47 @@ int upr_edge_cut_noalloc(upr_ctx *c, const upr_graph *graph, const int32_t *part
     return UPR_OK;
 }
 
+// Enqueue `span` on s as a HIP graph: replayed when a graph with this key was
+// captured before, else captured on the context's own stream (nothing runs
+// while capturing), instantiated, kept (at most kCaptureMax, the oldest
+// dropped) and launched.
+static int run_captured(upr_ctx *c, const uint64_t (&key)[kCaptureKey],
+                        const std::function<int(hipStream_t)> &span, hipStream_t s)
+{
+    for (auto &g : c->captured)
+        if (std::equal(key, key + kCaptureKey, g.key)) {
+            HIP_TRY(c, hipGraphLaunch(g.exec, s));
+            return UPR_OK;
+        }
+    HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int rc = span(c->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+    if (rc || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return rc ? rc : fail(c, UPR_E_HIP, "capturing the move phases failed: %s",
+                              hipGetErrorString(e));
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, UPR_E_HIP, "instantiating the move phases failed: %s", hipGetErrorString(ei));
+    }
+    if (c->captured.size() >= kCaptureMax) {
+        (void)hipGraphExecDestroy(c->captured.front().exec);
+        c->captured.erase(c->captured.begin());
+    }
+    upr_ctx::Captured g;
+    std::copy(key, key + kCaptureKey, g.key);
+    g.exec = exec;
+    c->captured.push_back(g);
+    HIP_TRY(c, hipGraphLaunch(exec, s));
+    return UPR_OK;
+}
+
 // One round (moves = true) or a standalone rebalancing (moves = false) of a
 // single graph (b == null) or of every graph of a batch.
 static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_params *q,
@@ -1183,13 +1252,17 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
                                  q->rebuild_table, seg ? c->seg_cur : nullptr,
                                  seg ? seq_counter_words(K) : 0, s, h,
                                  q->rebuild_table ? conn : nullptr, k));
-    if (b) HIP_TRY(c, launch_fill_i64(gstat, (int64_t)GS_COUNT * ng, 0, s));
     // compact partition copy for the neighbour gathers (kept in step by the apply)
     const PartView pv{c->pc, k <= 256 ? 1 : 2, k <= 128 ? 1 : 0};
     // and the same in the plan's label order for the table build
+    const PartView tpv = table_part(c, p, pv);
+    bool moved = false;
+    // everything from here to the rebalancing: enqueued on s, or captured
+    // once per configuration and replayed (upr_capture_enable)
+    const std::function<int(hipStream_t)> span = [&](hipStream_t s) -> int {
+    if (b) HIP_TRY(c, launch_fill_i64(gstat, (int64_t)GS_COUNT * ng, 0, s));
     HIP_TRY(c, launch_pack_part(n, bk, b ? b->goff_d : nullptr, part, c->pc, pv.bytes, c->counters, s,
                                 p->order, p->order ? c->pc2 : nullptr));
-    const PartView tpv = table_part(c, p, pv);
     if (q->rebuild_table) {
         const GraphView tg = p->table_graph();
         {
@@ -1208,7 +1281,6 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
                                      p->nh > 0 ? p->hub_bits : nullptr));
     }
     if (prefix) HIP_TRY(c, launch_bp_record_start(n, K, part, W, c->bp, s));
-    bool moved = false;
     if (moves) {
         {
             PhaseTimer t(c, 2, s);
@@ -1255,8 +1327,8 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
                     // eligible candidates in id order; their number sizes the sort
                     HIP_TRY(c, launch_seq_select(n, c->key, c->gp, c->cand, c->counters + CNT_ELIG,
                                                  c->seq_temp, c->seq_temp_size, s));
-                    rc = sync_counters(c, s);
-                    if (rc) return rc;
+                    const int rs = sync_counters(c, s);
+                    if (rs) return rs;
                     if (c->cnt[CNT_BAD_INPUT])
                         return fail(c, UPR_E_ARG, b ? "part holds a block outside its graph's range"
                                                     : "part holds values outside [0, k)");
@@ -1284,6 +1356,27 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
                                          GS_CUT2_MOVES, s));
         }
     }
+    return UPR_OK;
+    };
+    // captured: one graph, no driver activity mask, no best prefix, no phase
+    // timing, and no host synchronisation inside the span (the segment path
+    // of the sequence-aware price)
+    const bool cap = c->capture && c->cap_stream && !b && !active && !prefix && moves &&
+                     c->timing.mask == 0 && (!q->seq_penalty || seg);
+    if (cap) {
+        const uint64_t key[kCaptureKey] = {
+            p->serial, c->ws_gen, (uint64_t)k, (uint64_t)(uint32_t)q->eps_num,
+            (uint64_t)(uint32_t)q->eps_den, (uint64_t)(uint32_t)q->t_num, (uint64_t)(uint32_t)q->t_den,
+            (uint64_t)(uint32_t)q->mode, (uint64_t)(uint32_t)q->rebuild_table,
+            (uint64_t)(uint32_t)q->seq_penalty, (uint64_t)(uint32_t)q->variant,
+            q->mode == 3 ? ((uint64_t)(uint32_t)q->alpha_num << 32 | (uint32_t)q->alpha_den) : 0,
+            (uint64_t)(uintptr_t)part, (uint64_t)(uintptr_t)conn, (uint64_t)(uintptr_t)W, 0};
+        rc = run_captured(c, key, span, s);
+        moved = true;
+    } else {
+        rc = span(s);
+    }
+    if (rc) return rc;
     int64_t iters = 0, status = 0;
     {
         PhaseTimer t(c, 5, s);
@@ -1809,6 +1902,22 @@ int upr_last_moves(upr_ctx *c, int64_t n, int32_t *target, int64_t *score, int64
     if (n < 0 || n > c->cap_n) return fail(c, UPR_E_ARG, "n=%lld exceeds the last round's size", (long long)n);
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, launch_export_moves(n, c->key, c->pen, c->accflag, target, score, pen, accept, s));
+    return UPR_OK;
+}
+
+int upr_capture_enable(upr_ctx *c, int enable)
+{
+    if (!c) return UPR_E_ARG;
+    if (enable && !c->cap_stream) {
+        HIP_TRY(c, hipSetDevice(c->device));
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    }
+    if (!enable) {
+        HIP_TRY(c, hipSetDevice(c->device));
+        HIP_TRY(c, hipDeviceSynchronize());
+        drop_captured(c);
+    }
+    c->capture = enable != 0;
     return UPR_OK;
 }
 

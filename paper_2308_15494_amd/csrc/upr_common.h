@@ -479,7 +479,7 @@ hipError_t launch_hub_ranges(const int64_t *xadj, const int32_t *ids, int32_t nh
                              hipStream_t s);
 
 // table (S1)
-int gain_tile_nodes(int32_t k);
+int gain_tile_nodes(int32_t k, int64_t n);
 // The full table: one workgroup per tile of non-hub rows and, in the same
 // launch, one per chunk of a hub's edges, which adds the chunk's counts into
 // the hub's row: the hub rows must be zero (launch_zero_hub_rows).

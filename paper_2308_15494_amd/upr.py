@@ -110,6 +110,7 @@ _SIGS = [
     ("upr_refine", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                              C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32),
                              C.c_void_p]),
+    ("upr_capture_enable", C.c_int, [C.c_void_p, C.c_int]),
     ("upr_timing_enable", C.c_int, [C.c_void_p, C.c_int]),
     ("upr_timing_read", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
 ]
@@ -214,6 +215,11 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def capture(self, enable: bool):
+        """Replay the move phases of repeated round configurations from HIP
+        graphs (upr_capture_enable)."""
+        self.check(lib().upr_capture_enable(self.handle, 1 if enable else 0))
 
     def timing(self, enable: bool, phases=None):
         """Time every phase (enable, phases None), only the listed phases
