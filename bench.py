@@ -380,7 +380,8 @@ def oracle_pool(spec, workers, what, eps=(3, 100), rounds=10):
 def batched_vs_plain(ctx, spec, eps=(3, 100), rounds=10, tune_batches=True):
     """The many-graphs workload refined twice: plain (one graph after the
     other, upr_refine_round per graph and round) and batched (one batch per k,
-    upr_batch_refine_round per round). Each batch's traversal thresholds are
+    upr_batch_refine_round per round), then batched once more with the move
+    phases replayed from captured HIP graphs (upr_capture_enable). Each batch's traversal thresholds are
     picked by the autotuner first (timed trial rounds; the plain graphs keep
     the defaults: 512 tunings would cost more than they save). Plans and
     batches are built and warmed up before the timed regions; both start
@@ -442,14 +443,30 @@ def batched_vs_plain(ctx, spec, eps=(3, 100), rounds=10, tune_batches=True):
         torch.cuda.synchronize()
         out[name] = time.perf_counter() - t0
     # identical results, graph by graph
-    same = True
-    for k, idx in groups.items():
-        b = batches[k]
-        parts = b.local_partitions()
-        st = b.stats.cpu().numpy().reshape(b.ng, upr.STATS_LEN)
-        for j, i in enumerate(idx):
-            same &= bool(np.array_equal(parts[j], refs[i].part.cpu().numpy()))
-            same &= bool(np.array_equal(st[j], refs[i].stats.cpu().numpy()))
+    def same_as_plain():
+        same = True
+        for k, idx in groups.items():
+            b = batches[k]
+            parts = b.local_partitions()
+            st = b.stats.cpu().numpy().reshape(b.ng, upr.STATS_LEN)
+            for j, i in enumerate(idx):
+                same &= bool(np.array_equal(parts[j], refs[i].part.cpu().numpy()))
+                same &= bool(np.array_equal(st[j], refs[i].stats.cpu().numpy()))
+        return same
+
+    same = same_as_plain()
+    # the batched rounds again with their move phases replayed from HIP graphs
+    # (one per batch, captured in the warm-up pass)
+    ctx.capture(True)
+    reset_batched()
+    run_batched()
+    reset_batched()
+    t0 = time.perf_counter()
+    run_batched()
+    torch.cuda.synchronize()
+    out["captured"] = time.perf_counter() - t0
+    same_captured = same_as_plain()
+    ctx.capture(False)
     for b in batches.values():
         b.close()
     ng = len(spec)
@@ -458,6 +475,7 @@ def batched_vs_plain(ctx, spec, eps=(3, 100), rounds=10, tune_batches=True):
             "plain_graphs_per_s": ng / out["plain"], "batched_graphs_per_s": ng / out["batched"],
             "plain_s": out["plain"], "batched_s": out["batched"],
             "speedup": out["plain"] / out["batched"], "identical_results": same,
+            "captured_graphs_per_s": ng / out["captured"], "captured_identical_results": same_captured,
             "thresholds": {str(k): v for k, v in chosen.items()} if chosen else "default",
             "tune_s": tune_s}
 

@@ -366,10 +366,11 @@ int upr_penalty_table(int32_t tau_num, int32_t tau_den, int64_t *out);
  * holds the round's penalty factors) and the rebalancing stay eager. A
  * configuration is the plan, k, eps, t, mode, rebuild_table, seq_penalty,
  * variant, alpha and the part / conn / block_w arrays (a graph replays the
- * kernel arguments it was captured with). Used for single graphs without
- * the best prefix, without an activity mask (the driver's label-propagation
- * rounds), with the segment path of the sequence-aware price and with phase
- * timing off; every other round runs eagerly. Results are identical either
+ * kernel arguments it was captured with; a batch is keyed by its own plan,
+ * its per-graph penalty factors stay eager). Used for single graphs and
+ * batches, without the best prefix, without an activity mask (the driver's
+ * label-propagation rounds), with the segment path of the sequence-aware
+ * price and with phase timing off; every other round runs eagerly. Results are identical either
  * way. At most 16 graphs are kept per context; they are freed when the
  * workspace grows, when capture is disabled (which synchronises the device)
  * and by upr_destroy. */

@@ -1358,10 +1358,10 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
     }
     return UPR_OK;
     };
-    // captured: one graph, no driver activity mask, no best prefix, no phase
-    // timing, and no host synchronisation inside the span (the segment path
-    // of the sequence-aware price)
-    const bool cap = c->capture && c->cap_stream && !b && !active && !prefix && moves &&
+    // captured: a graph or a batch (its own plan), no driver activity mask,
+    // no best prefix, no phase timing, and no host synchronisation inside the
+    // span (the segment path of the sequence-aware price)
+    const bool cap = c->capture && c->cap_stream && !active && !prefix && moves &&
                      c->timing.mask == 0 && (!q->seq_penalty || seg);
     if (cap) {
         const uint64_t key[kCaptureKey] = {

@@ -104,3 +104,33 @@ def test_capture_keys_and_eviction(upr, ctx2):
     _compare(a, b, "after new arrays")
     a.plan.close()
     b.plan.close()
+
+
+def test_captured_batch_rounds_equal_eager(upr, ctx2):
+    """A batch (its own plan, per-graph penalty factors uploaded eagerly every
+    round): captured and eager rounds agree on every graph after every round."""
+    eager, cap = ctx2
+    graphs = [gg.chung_lu(3000 + 500 * i, 8.0, 2.3, seed=20 + i) if i % 2 == 0 else
+              gg.rgg2d(2500 + 400 * i, seed=30 + i) for i in range(6)]
+    k = 8
+    parts = [skewed_partition(g.n, k, i, 0.3) for i, g in enumerate(graphs)]
+    ba, bb = upr.Batch(eager, graphs, k), upr.Batch(cap, graphs, k)
+    ba.set_partitions(parts)
+    bb.set_partitions(parts)
+    R = 6
+    for r in range(1, R + 1):
+        taus = [gg.tau_schedule(min(r + g, R), R) for g in range(len(graphs))]
+        p = upr.params(k, tau=(1, 1))
+        sa = ba.round(p, taus=taus).cpu().numpy()
+        sb = bb.round(p, taus=taus).cpu().numpy()
+        assert np.array_equal(sa, sb), f"round {r}: stats"
+        for name in ("part", "W", "conn"):
+            assert np.array_equal(getattr(ba, name).cpu().numpy(), getattr(bb, name).cpu().numpy()), \
+                f"round {r}: {name}"
+        # eager work on the capturing context between replays
+        g0 = upr.DeviceGraph(graphs[0])
+        pl = upr.Plan(cap, g0)
+        upr.gain_table(cap, pl, k, to_dev(parts[0].astype(np.int32)))
+        pl.close()
+    ba.close()
+    bb.close()
