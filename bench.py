@@ -483,7 +483,8 @@ def batched_vs_plain(ctx, spec, eps=(3, 100), rounds=10, tune_batches=True):
 def serving(ctx, spec, eps=(3, 100), rounds=10, load=0.7, budget_gb=200.0, check=4, seed=7):
     """Poisson stream of refinement requests through the continuous-batching
     server. The capacity is measured first with every request arriving at
-    time 0; the stream then arrives at `load` times that rate. Reports
+    time 0, then again on the context with its move phases captured in HIP
+    graphs; the stream then arrives at `load` times the eager rate. Reports
     latency percentiles (completion minus arrival) and throughput; a few
     requests are also refined alone and must give the same result."""
     from paper_2308_15494_amd import serve
@@ -495,6 +496,21 @@ def serving(ctx, spec, eps=(3, 100), rounds=10, load=0.7, budget_gb=200.0, check
     t0 = time.perf_counter()
     srv.run(reqs0)
     cap = len(reqs0) / (time.perf_counter() - t0)
+    # the same capacity run on a context that replays its move phases from
+    # captured HIP graphs (a batch whose membership changed is a new plan,
+    # captured on its first round)
+    ctx.capture(True)
+    try:
+        srv.run(reqs0[: min(8, len(reqs0))])
+        t0 = time.perf_counter()
+        res_c = srv.run(reqs0)
+        cap_c = len(reqs0) / (time.perf_counter() - t0)
+    finally:
+        ctx.capture(False)
+    same_c = True
+    for r in res_c[:check]:
+        part, stats = serve.refine_alone(ctx, reqs0[r.rid])
+        same_c &= bool(np.array_equal(part, r.part)) and stats == r.stats
     rate = load * cap
     arr = serve.poisson_arrivals(len(spec), rate, seed)
     reqs = [serve.Request(j, g, k, eps, rounds=rounds, arrival=float(arr[j]), part_seed=s)
@@ -510,6 +526,7 @@ def serving(ctx, spec, eps=(3, 100), rounds=10, load=0.7, budget_gb=200.0, check
         part, stats = serve.refine_alone(ctx, reqs[r.rid])
         same &= bool(np.array_equal(part, r.part)) and stats == r.stats
     return {"requests": len(spec), "rounds": rounds, "capacity_graphs_per_s": cap,
+            "captured_capacity_graphs_per_s": cap_c, "captured_same_as_alone": same_c,
             "arrival_rate_per_s": rate, "graphs_per_s": len(res) / span,
             "p50_latency_ms": 1e3 * float(np.percentile(lat, 50)),
             "p99_latency_ms": 1e3 * float(np.percentile(lat, 99)),

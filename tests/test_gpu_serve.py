@@ -1,6 +1,7 @@
 """Serving with continuous batching: every request's result (final partition
 and per-round statistics) is the same in the mix as alone, and the same as
-the oracle's."""
+the oracle's, also when the server's context replays its move phases from
+captured HIP graphs."""
 import sys
 
 import numpy as np
@@ -29,6 +30,16 @@ def env():
     ctx.close()
 
 
+@pytest.fixture(scope="module")
+def cap_ctx(env):
+    upr = env[0]
+    c = upr.Context(0)
+    c.capture(True)
+    yield c
+    c.capture(False)
+    c.close()
+
+
 def make_requests(serve, count, seed, rate):
     rng = np.random.default_rng(seed)
     arr = serve.poisson_arrivals(count, rate, seed)
@@ -45,12 +56,15 @@ def make_requests(serve, count, seed, rate):
     return reqs
 
 
+@pytest.mark.parametrize("captured", [False, True])
 @pytest.mark.parametrize("budget_mb", [1, 4096])
-def test_serve_results_same_alone_and_in_mix(env, budget_mb):
+def test_serve_results_same_alone_and_in_mix(env, cap_ctx, budget_mb, captured):
     upr, serve, ctx = env
     reqs = make_requests(serve, 14, 5, rate=400.0)
-    say(f"serve budget={budget_mb}MB sizes={[r.graph.n for r in reqs]} k={[r.k for r in reqs]}")
-    srv = serve.Server(ctx, budget_mb << 20)
+    say(f"serve budget={budget_mb}MB captured={captured} sizes={[r.graph.n for r in reqs]} "
+        f"k={[r.k for r in reqs]}")
+    # requests refined alone run on the eager context
+    srv = serve.Server(cap_ctx if captured else ctx, budget_mb << 20)
     res = srv.run(reqs)
     assert [r.rid for r in res] == list(range(len(reqs)))
     for req, r in zip(reqs, res):
