@@ -11,7 +11,8 @@ tau_r = (18 + r) / 38 (20 rounds). The table is rebuilt inside every round
 The same line also carries: the rooflines of the gain-table, best-move,
 filter and apply kernels; the resident form of the same rounds (table built
 in the first round, then kept by the applies' deltas; identical results
-required); the other single-graph workloads (the 2048 x 2048
+required); the same rounds with their move phases replayed from a captured
+HIP graph (identical results required); the other single-graph workloads (the 2048 x 2048
 grid at k = 64 and the 8M-node weighted Chung-Lu graph at k = 256), each
 with edges/s, its kernel rooflines and an oracle round for parity; the
 batched-vs-plain and serving legs; and the oracle timed on host cores.
@@ -585,6 +586,51 @@ def resident_leg(ctx, g, k, eps, rounds, part0, steps, warmup, head_rec):
     return out
 
 
+def captured_leg(ctx, g, k, eps, rounds, part0, steps, warmup, head_rec, opts=None):
+    """The headline rounds again with their move phases replayed from a HIP
+    graph captured in the warm-up (upr_capture_enable; the whole schedule
+    shares one configuration, the penalty factors are uploaded eagerly),
+    timed the same way; every round's statistics and the final partition and
+    block weights must equal the eager rounds'."""
+    import torch
+    from paper_2308_15494_amd import graphgen as gg
+    from paper_2308_15494_amd import upr
+    r = upr.Refiner(g, k, ctx=ctx, opts=opts)
+
+    def ps(i):
+        return upr.params(k, eps, tau=gg.tau_schedule(i, rounds))
+
+    def restart():
+        r.set_partition(part0)
+        r.conn.zero_()
+        r.W.zero_()
+        torch.cuda.synchronize()
+
+    sched = [ps(i) for i in range(1, steps + 1)]
+    ctx.capture(True)
+    try:
+        restart()
+        r.rounds([ps(i) for i in range(1, max(warmup, 1) + 1)])
+        restart()
+        t1 = time.perf_counter()
+        st = r.rounds(sched)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+    finally:
+        ctx.capture(False)
+    st = st.cpu().numpy()
+    same = len(head_rec) == steps and all(
+        np.array_equal(st[i], head_rec[i]["stats"]) for i in range(steps)) and \
+        np.array_equal(r.part.cpu().numpy(), head_rec[-1]["part"]) and \
+        np.array_equal(r.W.cpu().numpy(), head_rec[-1]["W"])
+    r.plan.close()
+    out = {"value": g.m * steps / (t2 - t1), "unit": "edges/s", "ms_per_step": 1e3 * (t2 - t1) / steps,
+           "steps": steps, "same_as_eager": bool(same)}
+    log(f"captured move phases: {out['value']:.3e} edges/s, {out['ms_per_step']:.3f} ms per round, "
+        f"same as eager: {same}")
+    return out
+
+
 def best_prefix_leg(ctx, g, k, eps, rounds, part0, steps, cpu_seconds, oracle_rounds, no_cpu):
     """The same workload with the interleaved best prefix (Section 5.4) after
     every round's rebalancing: edges/s, the cost over the plain round, the
@@ -745,6 +791,9 @@ def main():
     if not args.resident and not args.no_resident_leg:
         out["resident"] = resident_leg(ctx, g, k, eps, rounds, part0, args.steps, args.warmup,
                                        res["rec"])
+    if not args.resident:
+        out["captured"] = captured_leg(ctx, g, k, eps, rounds, part0, args.steps, args.warmup,
+                                       res["rec"], opts=opts)
     if not args.no_cpu:
         base, orc = cpu_baseline(g, k, eps, rounds, part0, args.cpu_seconds)
         out["cpu_baseline"] = base
