@@ -242,8 +242,17 @@ __global__ __launch_bounds__(kBlock) void k_node_stats(GraphView g, Blocks bk,
                                                         uint8_t *avail_out, int64_t *gstat,
                                                         int gs_slot,
                                                         const int32_t *__restrict__ inner,
-                                                        const uint32_t *__restrict__ hub_bits)
+                                                        const uint32_t *__restrict__ hub_bits,
+                                                        int cut_cond)
 {
+    if (cut_cond && wave_cnt_get(counters, CNT_CUT_STALE) == 0) {
+        // every apply since the first pass summed its change of the cut
+        if (blockIdx.x == 0 && threadIdx.x < 64)
+            wave_cnt_set(counters, cut_slot,
+                         wave_cnt_get(counters, CNT_CUT2_BEFORE) +
+                             wave_cnt_get(counters, CNT_CUT2_DELTA));
+        return;
+    }
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ unsigned long long red[4];
     __shared__ unsigned long long bad;
@@ -375,7 +384,7 @@ hipError_t launch_node_stats(const GraphView &g, const Blocks &bk, const StatsGe
                              int64_t *W, int64_t *bucket, int32_t t_num, int32_t t_den,
                              unsigned long long *counters, int cut_slot, uint8_t *avail,
                              int64_t *gstat, int gs_slot, hipStream_t s, const int32_t *inner,
-                             const uint32_t *hub_bits)
+                             const uint32_t *hub_bits, bool cut_cond)
 {
     if (g.n <= 0) return hipSuccess;
     const int64_t span = sg.span > 0 ? sg.span : stats_span(g.n, 0);
@@ -386,7 +395,8 @@ hipError_t launch_node_stats(const GraphView &g, const Blocks &bk, const StatsGe
     const int64_t rows = (g.n + span - 1) / span;
     hipLaunchKernelGGL(k_node_stats, dim3((unsigned)rows), dim3(kBlock), lds, s, g, bk, sg.goff,
                        span, W ? cap_w : 0, bucket ? cap_b : 0, part, conn, wdeg, W, bucket, t_num,
-                       t_den, counters, cut_slot, avail, gstat, gs_slot, inner, hub_bits);
+                       t_den, counters, cut_slot, avail, gstat, gs_slot, inner, hub_bits,
+                       cut_cond && !W && !bucket && !gstat ? 1 : 0);
     return hipGetLastError();
 }
 

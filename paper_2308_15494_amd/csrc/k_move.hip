@@ -1081,7 +1081,7 @@ hipError_t launch_filter_seq(const GraphView &g, const Blocks &bk, const int32_t
 // prefix), so a mover of high degree is split over many lanes instead of
 // holding up one wave. Delta mode: the two atomics per edge; rebuild mode
 // (moving degrees above dirty_threshold): the neighbours' tiles are marked.
-// Hubs: bookkeeping only, their edges were applied by k_apply_hub (which
+// Hubs: bookkeeping only, their edges were applied by k_apply_pre (which
 // read the old part).
 constexpr int kApplyTile = 1024;
 
@@ -1218,59 +1218,195 @@ __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, Blocks bk, int32_
     }
 }
 
-// Hub moves, before k_apply: each chunk updates the rows of its neighbours
-// (part of the hub is still its source block here). When the apply rebuilds
-// the table, the first chunk of every hub also clears the hub's own row,
-// which the refresh after the apply rebuilds; in the delta mode hub rows get
-// their deltas like every other row.
-__global__ __launch_bounds__(kBlock) void k_apply_hub(GraphView g, Blocks bk, const int32_t *part,
-                                                       int32_t *conn, const int32_t *mvto,
-                                                       HubView h, const unsigned long long *counters,
-                                                       int64_t dirty_threshold, uint8_t *dirty,
-                                                       int T, int64_t all_threshold)
+// The term of the directed entry (v, u) in the change of 2 * cut when v
+// moves a -> b and u sits in pu with target tu (-1: u stays); see
+// k_apply_pre.
+__device__ __forceinline__ int64_t cut_term(int32_t a, int32_t b, int32_t pu, int32_t tu,
+                                            int32_t w)
 {
-    const HubChunk c = h.chunks[blockIdx.x];
-    const int64_t v = h.ids[c.hub];
+    const int32_t pn = tu >= 0 ? tu : pu;
+    const int x = (b != pn ? 1 : 0) - (a != pu ? 1 : 0);
+    return (int64_t)w * x * (tu >= 0 ? 1 : 2);
+}
+
+// Before k_apply, in one launch: the hub movers' edges, one workgroup per hub
+// chunk (part of a hub is still its source block here), and with CUT the
+// change of 2 * cut the moves make, summed into counters[CNT_CUT2_DELTA]
+// (two's complement) by the hub chunks for the hub movers and by tiles of
+// kApplyTile nodes (the workgroups after the chunks) for the others. Nothing
+// here changes part or mvto, which k_apply updates afterwards.
+//
+// Hub rows: when the apply rebuilds the table, the first chunk of every hub
+// clears the hub's own row, which the refresh after the apply rebuilds; in
+// the delta mode hub rows get their deltas like every other row.
+//
+// The cut (Section 2) is a sum over the directed entries of the symmetric
+// adjacency, each edge twice; an entry's term w [p(v) != p(u)] changes only
+// if v or u moves. The entries out of a mover v are summed here; an entry
+// into v from a neighbour u that stays has the same term as (v, u), so such
+// an entry counts twice, and one between two movers is met from both ends.
+// With the moving degrees above cut_max (the apply rebuilds tiles, or the
+// walk would cost more than a recount) nothing is summed and
+// counters[CNT_CUT_STALE] is raised, so that the cut is recounted.
+template <bool CUT>
+__global__ __launch_bounds__(kBlock) void k_apply_pre(GraphView g, Blocks bk,
+                                                       const int32_t *__restrict__ part,
+                                                       int32_t *conn,
+                                                       const int32_t *__restrict__ mvto,
+                                                       HubView h, unsigned long long *counters,
+                                                       int64_t dirty_threshold, uint8_t *dirty,
+                                                       int T, int64_t all_threshold, int64_t hub_t,
+                                                       int64_t cut_max)
+{
+    __shared__ int32_t vstart[CUT ? kApplyTile + 1 : 1];
+    __shared__ int64_t estart[CUT ? kApplyTile : 1];
+    __shared__ int32_t sa[CUT ? kApplyTile : 1], sb[CUT ? kApplyTile : 1];
+    __shared__ int32_t scan_lds[4];
+    __shared__ int64_t red[4];
     const int32_t k = bk.k;
     const int64_t moved_deg = (int64_t)wave_cnt_get(counters, CNT_MOVED_DEG);
-    const bool rebuild = moved_deg > dirty_threshold;
-    if (rebuild && c.e0 == g.xadj[v])
-        for (int j = threadIdx.x; j < k; j += kBlock) conn[v * (int64_t)k + j] = 0;
-    const int32_t B = mvto[v];
-    if (B < 0) return;
-    if (rebuild) {
-        if (moved_deg <= all_threshold)  // else every tile is rebuilt
-            for (int64_t e = c.e0 + threadIdx.x; e < c.e1; e += kBlock)
-                mark_dirty(dirty, g.adjncy[e] / T);
-        return;
+    const bool cut = CUT && moved_deg <= cut_max;
+    if (CUT && !cut && blockIdx.x == 0 && threadIdx.x == 0) cnt_add(counters, CNT_CUT_STALE, 1ull);
+    const int64_t nhc = h.nh > 0 ? h.nchunks : 0;
+    int64_t acc = 0;
+    if ((int64_t)blockIdx.x < nhc) {
+        const HubChunk c = h.chunks[blockIdx.x];
+        const int64_t v = h.ids[c.hub];
+        const bool rebuild = moved_deg > dirty_threshold;
+        if (rebuild && c.e0 == g.xadj[v])
+            for (int j = threadIdx.x; j < k; j += kBlock) conn[v * (int64_t)k + j] = 0;
+        const int32_t B = mvto[v];
+        if (B < 0) return;  // uniform over the workgroup
+        if (rebuild) {
+            if (moved_deg <= all_threshold)  // else every tile is rebuilt
+                for (int64_t e = c.e0 + threadIdx.x; e < c.e1; e += kBlock)
+                    mark_dirty(dirty, g.adjncy[e] / T);
+            return;
+        }
+        const int32_t A = part[v];
+        const int32_t a = bk.local(A), b = bk.local(B);
+        // kHubUnroll edges per thread and step, their loads in flight together
+        // (a slot past the chunk rereads its last edge, unused)
+        constexpr int kHubUnroll = 8;
+        for (int64_t e0 = c.e0 + threadIdx.x; e0 < c.e1; e0 += (int64_t)kBlock * kHubUnroll) {
+            bool ok[kHubUnroll];
+            int32_t u[kHubUnroll], w[kHubUnroll], pu[kHubUnroll], tu[kHubUnroll];
+#pragma unroll
+            for (int i = 0; i < kHubUnroll; ++i) {
+                const int64_t e = e0 + (int64_t)i * kBlock;
+                ok[i] = e < c.e1;
+                const int64_t ec = ok[i] ? e : c.e1 - 1;
+                u[i] = g.adjncy[ec];
+                w[i] = edge_weight(g, ec);
+            }
+            if (cut) {
+#pragma unroll
+                for (int i = 0; i < kHubUnroll; ++i) {
+                    pu[i] = part[u[i]];
+                    tu[i] = mvto[u[i]];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < kHubUnroll; ++i) {
+                if (!ok[i]) continue;
+                int32_t *row = conn + (int64_t)u[i] * k;
+                atomicAdd(&row[a], -w[i]);
+                atomicAdd(&row[b], w[i]);
+                if (cut) acc += cut_term(A, B, pu[i], tu[i], w[i]);
+            }
+        }
+    } else {
+        if (!cut) return;  // uniform over the grid
+        const int64_t v0 = ((int64_t)blockIdx.x - nhc) * kApplyTile;
+        const int nt = (int)((g.n - v0) < kApplyTile ? (g.n - v0) : kApplyTile);
+        const int i0 = 4 * threadIdx.x;
+        int32_t vd4[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int i = i0 + j;
+            if (i >= nt) continue;
+            const int64_t v = v0 + i;
+            const int32_t to = mvto[v];
+            if (to < 0) continue;
+            const int64_t e0 = g.xadj[v], e1 = g.xadj[v + 1];
+            if (e1 - e0 > hub_t) continue;  // a hub: its chunks
+            vd4[j] = (int32_t)(e1 - e0);
+            estart[i] = e0;
+            sa[i] = part[v];
+            sb[i] = to;
+        }
+        int32_t run;
+        {
+            const int32_t sum = vd4[0] + vd4[1] + vd4[2] + vd4[3];
+            const int32_t inc = block_incl_scan(sum, scan_lds, &run);
+            int32_t x = inc - sum;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (i0 + j < nt) vstart[i0 + j] = x;
+                x += vd4[j];
+            }
+        }
+        if (threadIdx.x == 0) vstart[nt] = run;
+        __syncthreads();
+        const int32_t E = run;
+        for (int32_t p0 = threadIdx.x; p0 < E; p0 += kBlock * kEdgeUnroll) {
+            // loads from clamped indices without a branch, in flight together
+            bool ok[kEdgeUnroll];
+            int node[kEdgeUnroll];
+            int32_t u[kEdgeUnroll], w[kEdgeUnroll], pu[kEdgeUnroll], tu[kEdgeUnroll];
+#pragma unroll
+            for (int i = 0; i < kEdgeUnroll; ++i) {
+                const int32_t p = p0 + i * kBlock;
+                ok[i] = p < E;
+                const int32_t pc = ok[i] ? p : E - 1;
+                node[i] = upper_index(vstart, nt, pc);
+                const int64_t e = estart[node[i]] + (pc - vstart[node[i]]);
+                u[i] = g.adjncy[e];
+                w[i] = edge_weight(g, e);
+            }
+#pragma unroll
+            for (int i = 0; i < kEdgeUnroll; ++i) {
+                pu[i] = part[u[i]];
+                tu[i] = mvto[u[i]];
+            }
+#pragma unroll
+            for (int i = 0; i < kEdgeUnroll; ++i)
+                if (ok[i]) acc += cut_term(sa[node[i]], sb[node[i]], pu[i], tu[i], w[i]);
+        }
     }
-    const int32_t a = bk.local(part[v]), b = bk.local(B);
-    for (int64_t e = c.e0 + threadIdx.x; e < c.e1; e += kBlock) {
-        const int64_t u = g.adjncy[e];
-        const int32_t w = edge_weight(g, e);
-        atomicAdd(&conn[u * k + a], -w);
-        atomicAdd(&conn[u * k + b], w);
+    if (CUT) {
+        acc = block_sum(acc, red);
+        if (threadIdx.x == 0 && acc != 0) cnt_add(counters, CNT_CUT2_DELTA, (unsigned long long)acc);
     }
 }
 
 hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, const PartView &pv,
                         int32_t *conn, int64_t *W, int32_t *mvto, int64_t hub_t,
-                        const HubView &h, const unsigned long long *counters,
+                        const HubView &h, unsigned long long *counters,
                         int64_t dirty_threshold, uint8_t *dirty, const GraphView &tg,
                         const PartView &tpv, void *pc2, const int32_t *perm,
-                        int64_t all_threshold, hipStream_t s)
+                        int64_t all_threshold, hipStream_t s, bool cut_delta)
 {
     if (g.n <= 0) return hipSuccess;
     const int32_t k = bk.k;
     const int T = gain_tile_nodes(k, g.n);
     const size_t lds = bk.total() <= 2048 ? (size_t)bk.total() * 8 : 0;
-    hipError_t e;
-    if (h.nh > 0) {
-        hipLaunchKernelGGL(k_apply_hub, dim3((unsigned)h.nchunks), dim3(kBlock), 0, s, g, bk, part,
-                           conn, mvto, h, counters, dirty_threshold, dirty, T, all_threshold);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
     const int64_t tiles = (g.n + kApplyTile - 1) / kApplyTile;
+    hipError_t e;
+    // the hub movers and, for one graph, the change of the cut (a walk over
+    // more moving degrees than n / 8, three loads per edge and two of them
+    // gathers, costs more than the recount's one table line per node)
+    const int64_t nhc = h.nh > 0 ? h.nchunks : 0;
+    const int64_t cut_max = std::min<int64_t>(dirty_threshold, g.n / 8);
+    if (cut_delta)
+        hipLaunchKernelGGL(k_apply_pre<true>, dim3((unsigned)(nhc + tiles)), dim3(kBlock), 0, s, g,
+                           bk, part, conn, mvto, h, counters, dirty_threshold, dirty, T,
+                           all_threshold, hub_t, cut_max);
+    else if (nhc > 0)
+        hipLaunchKernelGGL(k_apply_pre<false>, dim3((unsigned)nhc), dim3(kBlock), 0, s, g, bk, part,
+                           conn, mvto, h, counters, dirty_threshold, dirty, T, all_threshold, hub_t,
+                           cut_max);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     if (bk.total() <= 2048)
         hipLaunchKernelGGL(k_apply<true>, dim3((unsigned)tiles), dim3(kBlock), lds, s, g, bk, part,
                            pv, conn, W, mvto, hub_t, counters, dirty_threshold, dirty, T, pc2, perm,

@@ -565,20 +565,23 @@ static PartView table_part(const upr_ctx *c, const upr_plan *p, const PartView &
 }
 
 // S4 for the moves marked in mvto; rebuilt tiles and hub rows are built from
-// the table build's views.
+// the table build's views. cut_delta: the apply also sums its change of the
+// cut (one graph), which spares the statistics pass after it.
 static hipError_t apply_moves(upr_ctx *c, const upr_plan *p, const Blocks &bk, int32_t *part,
-                              const PartView &pv, int32_t *conn, int64_t *W, hipStream_t s)
+                              const PartView &pv, int32_t *conn, int64_t *W, hipStream_t s,
+                              bool cut_delta)
 {
     return launch_apply(p->g, bk, part, pv, conn, W, c->mvto, p->hub_t, p->hubs(), c->counters,
                         p->dirty_threshold, c->dirty, p->table_graph(), table_part(c, p, pv),
-                        p->order ? (void *)c->pc2 : nullptr, p->perm, p->all_threshold, s);
+                        p->order ? (void *)c->pc2 : nullptr, p->perm, p->all_threshold, s,
+                        cut_delta);
 }
 
 // S5: the host loop over synchronous sub-iterations (one graph).
 int rebalance_loop(upr_ctx *c, const upr_plan *p, const Blocks &bk, int plain, int32_t *part,
                    const PartView &pv, int32_t *conn, int64_t *W, int64_t it_max,
                    int64_t *iters_out, int64_t *status_out, hipStream_t s, bool speculate,
-                   int32_t *rbrec = nullptr)
+                   int32_t *rbrec, bool cut_delta)
 {
     int32_t launched = 0;  // sub-iterations launched (numbers the records in rbrec)
     const HubView h = p->hubs();
@@ -598,7 +601,7 @@ int rebalance_loop(upr_ctx *c, const upr_plan *p, const Blocks &bk, int plain, i
     auto sub_iteration = [&]() -> int {
         HIP_TRY(c, launch_rb_iteration(p->g, bk, part, conn, c->rb, c->mvto, hist32, plain,
                                        p->hub_t, c->counters, nullptr, s, rbrec, ++launched));
-        HIP_TRY(c, apply_moves(c, p, bk, part, pv, conn, W, s));
+        HIP_TRY(c, apply_moves(c, p, bk, part, pv, conn, W, s, cut_delta));
         return begin(0);
     };
     int rc;
@@ -714,7 +717,7 @@ int rebalance_loop_batch(upr_ctx *c, const upr_plan *p, upr_batch *b, const Bloc
         HIP_TRY(c, hipMemcpyAsync(b->srcl_d, b->srcl_h, sizeof(int64_t) * ng, hipMemcpyHostToDevice, s));
         HIP_TRY(c, launch_rb_iteration(p->g, bk, part, conn, c->rb, c->mvto, hist32, plain,
                                        p->hub_t, c->counters, b->gstat_d, s));
-        HIP_TRY(c, apply_moves(c, p, bk, part, pv, conn, W, s));
+        HIP_TRY(c, apply_moves(c, p, bk, part, pv, conn, W, s, false));
         HIP_TRY(c, launch_rb_begin(bk, W, c->rb, c->counters, b->gstat_d, s));
         rc = sync_batch(c, b, s);
         if (rc) return rc;
@@ -1227,6 +1230,10 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
     const int plain = (q->variant & UPR_VAR_PLAIN_PRIORITY) ? 1 : 0;
     // the interleaved best prefix: single graphs, rounds with moves
     const bool prefix = moves && !b && (q->variant & UPR_VAR_BEST_PREFIX) && n > 0;
+    // one graph without the best prefix: the applies sum their change of the
+    // cut, and the cut statistics after them are a sum unless an apply
+    // rebuilt tiles
+    const bool cut_delta = !b && !prefix;
     const int32_t K = bk.total();
     int64_t *gstat = b ? b->gstat_d : nullptr;
     StatsGeom sg;
@@ -1347,13 +1354,13 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
         }
         {
             PhaseTimer t(c, 4, s);
-            HIP_TRY(c, apply_moves(c, p, bk, part, pv, conn, W, s));
+            HIP_TRY(c, apply_moves(c, p, bk, part, pv, conn, W, s, cut_delta));
         }
         {
             PhaseTimer t(c, 6, s);
             HIP_TRY(c, launch_node_stats(p->g, bk, sg, part, conn, p->wdeg, nullptr, nullptr, 0, 1,
                                          c->counters, CNT_CUT2_MOVES, nullptr, gstat,
-                                         GS_CUT2_MOVES, s));
+                                         GS_CUT2_MOVES, s, nullptr, nullptr, cut_delta));
         }
     }
     return UPR_OK;
@@ -1387,7 +1394,7 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
                 q->max_rebalance_iters > 0 ? q->max_rebalance_iters : default_iters(p, k);
             // moves can overload a block except in constrained rounds
             rc = rebalance_loop(c, p, bk, plain, part, pv, conn, W, it_max, &iters, &status, s,
-                                moves && q->mode != 1, prefix ? c->bp.rbrec : nullptr);
+                                moves && q->mode != 1, prefix ? c->bp.rbrec : nullptr, cut_delta);
         }
         if (rc) return rc;
     }
@@ -1406,7 +1413,8 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
     {
         PhaseTimer t(c, 6, s);
         HIP_TRY(c, launch_node_stats(p->g, bk, sg, part, conn, p->wdeg, nullptr, nullptr, 0, 1,
-                                     c->counters, CNT_CUT2_AFTER, nullptr, gstat, GS_CUT2_AFTER, s));
+                                     c->counters, CNT_CUT2_AFTER, nullptr, gstat, GS_CUT2_AFTER, s,
+                                     nullptr, nullptr, cut_delta));
     }
     if (b) {
         HIP_TRY(c, hipMemcpyAsync(b->host3_d, b->host3_h, sizeof(int64_t) * 3 * ng,

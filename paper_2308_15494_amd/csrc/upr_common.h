@@ -27,6 +27,8 @@ enum Counter {
     CNT_MOVED_DEG,     // sum of the degrees of the nodes marked to move
     CNT_ELIG,          // eligible candidates (pessimistic gain > 0), sequence-aware filter
     CNT_OVER0,         // overloaded blocks when rebalancing starts
+    CNT_CUT2_DELTA,    // change of 2 * cut by the round's applies so far (two's complement)
+    CNT_CUT_STALE,     // nonzero: an apply rebuilt tiles, so CNT_CUT2_DELTA is incomplete
     CNT_COUNT = 32
 };
 
@@ -528,6 +530,9 @@ struct StatsGeom {
 };
 // inner (may be null): conn[v][part[v]] of the non-hub nodes, written by the
 // table build; hub_bits marks the hubs, whose entry is gathered from the row.
+// cut_cond (one graph, cut statistics only): unless counters[CNT_CUT_STALE]
+// is set, the pass stores CNT_CUT2_BEFORE + CNT_CUT2_DELTA into cut_slot
+// and reads nothing else.
 // Node range of the statistics pass for n nodes, at most max_span (> 0).
 int64_t stats_span(int64_t n, int64_t max_span);
 hipError_t launch_node_stats(const GraphView &g, const Blocks &bk, const StatsGeom &sg,
@@ -535,7 +540,8 @@ hipError_t launch_node_stats(const GraphView &g, const Blocks &bk, const StatsGe
                              int64_t *W, int64_t *bucket, int32_t t_num, int32_t t_den,
                              unsigned long long *counters, int cut_slot, uint8_t *avail,
                              int64_t *gstat, int gs_slot, hipStream_t s,
-                             const int32_t *inner = nullptr, const uint32_t *hub_bits = nullptr);
+                             const int32_t *inner = nullptr, const uint32_t *hub_bits = nullptr,
+                             bool cut_cond = false);
 hipError_t launch_block_weights(const GraphView &g, int32_t k, const int32_t *part, int64_t *W,
                                 unsigned long long *counters, hipStream_t s);
 // 2 * cut from the adjacency into the spread counter `slot`; out = that / 2.
@@ -660,12 +666,15 @@ hipError_t launch_seq_segments(const GraphView &g, const Blocks &bk, const int64
 // tg / tpv: the graph and partition views the table build reads (the
 // relabelled ones when the plan has them); pc2 / perm (may be null): the
 // compact copy in label order, kept in step with pv.
+// cut_delta (one graph): before the apply changes anything, the change of
+// 2 * cut the moves make is added to counters[CNT_CUT2_DELTA] in the delta
+// mode; when tiles are rebuilt instead, counters[CNT_CUT_STALE] is raised.
 hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, const PartView &pv,
                         int32_t *conn, int64_t *W, int32_t *mvto, int64_t hub_t,
-                        const HubView &h, const unsigned long long *counters,
+                        const HubView &h, unsigned long long *counters,
                         int64_t dirty_threshold, uint8_t *dirty, const GraphView &tg,
                         const PartView &tpv, void *pc2, const int32_t *perm,
-                        int64_t all_threshold, hipStream_t s);
+                        int64_t all_threshold, hipStream_t s, bool cut_delta = false);
 hipError_t launch_stats_final(int64_t *stats, const unsigned long long *counters, int64_t lmax,
                               int64_t iters, int64_t status, hipStream_t s);
 hipError_t launch_export_moves(int64_t n, const int64_t *key, const int64_t *pen,

@@ -543,6 +543,52 @@ def test_table_relabelling(upr, ctx, monkeypatch, relabel, div):
             pr.compare(ost, odbg, f"{name} round {r}")
 
 
+def hub_star_on_grid(rows, cols, leaves):
+    """A rows x cols grid plus one hub joined to `leaves` leaves (ids after
+    the grid: the hub, then its leaves)."""
+    n0 = rows * cols
+    ids = np.arange(n0, dtype=np.int64).reshape(rows, cols)
+    u = np.r_[ids[:, :-1].ravel(), ids[:-1, :].ravel(), np.full(leaves, n0)]
+    v = np.r_[ids[:, 1:].ravel(), ids[1:, :].ravel(), n0 + 1 + np.arange(leaves)]
+    n = n0 + 1 + leaves
+    xadj, adjncy, _ = gg.csr_from_undirected(n, u, v)
+    return gg._finish(gg.Graph(n, xadj, adjncy, None, None, name="hub_star_grid"))
+
+
+def test_cut_from_apply_deltas(upr, ctx, monkeypatch):
+    """The cut after the moves and after rebalancing is summed from the
+    movers' edges while the moving degrees stay small, else recounted. A hub
+    (above a forced threshold of 64) whose 300 leaves sit in the other block
+    is the only node with a positive pessimistic gain: its move is summed by
+    the hub-chunk walk; later rounds and a skewed start move ordinary nodes
+    (the tile walk) and, in the first rounds, enough to be recounted. Every
+    statistic equals the oracle's."""
+    monkeypatch.setenv("UPR_HUB_THRESHOLD", "64")
+    monkeypatch.setenv("UPR_DIRTY_DIV", "1")
+    g = hub_star_on_grid(60, 70, 300)
+    n0 = 60 * 70
+    part = np.zeros(g.n, np.int32)
+    part[2300:n0] = 1
+    part[n0 + 1:] = 1  # the leaves; the hub stays in block 0
+    pr = Pair(upr, ctx, g, 2, part)
+    assert pr.plan.info()["num_hubs"] == 1
+    ost, odbg = pr.round(tau=(1, 2))
+    pr.compare(ost, odbg, "hub round")
+    assert int(ost[5]) == 1 and odbg["accept"][n0] == 1  # the hub alone moved
+    for r in range(2, 4):
+        ost, odbg = pr.round(tau=(1, 1))
+        pr.compare(ost, odbg, f"round {r}")
+    # ordinary movers, many at first
+    for name, g2, k in [("cl", gg.chung_lu(6000, 8.0, 2.3, seed=3), 8),
+                        ("rmat_w", gg.with_weights(gg.rmat(12, 16, seed=4), 4, wmax=5), 16)]:
+        pr = Pair(upr, ctx, g2, k, skewed_partition(g2.n, k, 5, 0.4))
+        for r in range(1, 7):
+            ost, odbg = pr.round(tau=gg.tau_schedule(r, 6))
+            pr.compare(ost, odbg, f"{name} round {r}")
+        ost = pr.rebalance()
+        pr.compare(ost, None, f"{name} standalone rebalance")
+
+
 # ------------------------------------------------------------ driver --
 
 @pytest.mark.parametrize("case", [("cl", 8), ("rgg", 16), ("rmat", 8), ("cl_w", 4)])
