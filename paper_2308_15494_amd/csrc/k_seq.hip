@@ -465,7 +465,25 @@ __global__ __launch_bounds__(kBlock) void k_seg_count(int64_t n, int64_t span,
             if (h[j]) atomicAdd(&cnt[seg_slot(B0 + j, copy, C)], (unsigned long long)h[j]);
 }
 
-__device__ __forceinline__ int64_t excl_scan_1024(int64_t x, int64_t *lds /* >= 16 */,
+// Exclusive scans over the 1024 threads: each wave scans its values, wave 0
+// scans the 16 wave totals and publishes every wave's base and the total
+// (kScanSlots entries of lds per scan), so that a thread holds one base
+// rather than all 16 totals (with 1024 threads a thread has at most 128
+// registers).
+constexpr int kScanSlots = kOffThreads / 64 + 1;
+
+__device__ __forceinline__ void scan_wave_totals(int64_t *lds)
+{
+    if ((threadIdx.x >> 6) == 0) {
+        const int l = lane_id();
+        const int64_t t = l < kScanSlots - 1 ? lds[l] : 0;
+        const int64_t it = wave_incl_scan(t);
+        if (l < kScanSlots - 1) lds[l] = it - t;
+        if (l == kScanSlots - 2) lds[kScanSlots - 1] = it;
+    }
+}
+
+__device__ __forceinline__ int64_t excl_scan_1024(int64_t x, int64_t *lds /* >= kScanSlots */,
                                                   int64_t *total)
 {
     const int64_t inc = wave_incl_scan(x);
@@ -473,19 +491,18 @@ __device__ __forceinline__ int64_t excl_scan_1024(int64_t x, int64_t *lds /* >= 
     __syncthreads();
     if (lane_id() == 63) lds[w] = inc;
     __syncthreads();
-    int64_t base = 0, all = 0;
-    for (int i = 0; i < kOffThreads / 64; ++i) {
-        if (i < w) base += lds[i];
-        all += lds[i];
-    }
-    *total = all;
+    scan_wave_totals(lds);
+    __syncthreads();
+    const int64_t base = lds[w];
+    *total = lds[kScanSlots - 1];
     __syncthreads();
     return base + inc - x;
 }
 
 // Three exclusive scans at once (one set of barriers).
 __device__ __forceinline__ void excl_scan3_1024(const int64_t (&x)[3], int64_t (&ex)[3],
-                                                int64_t (&total)[3], int64_t *lds /* >= 48 */)
+                                                int64_t (&total)[3],
+                                                int64_t *lds /* >= 3 * kScanSlots */)
 {
     int64_t inc[3];
 #pragma unroll
@@ -494,17 +511,15 @@ __device__ __forceinline__ void excl_scan3_1024(const int64_t (&x)[3], int64_t (
     __syncthreads();
     if (lane_id() == 63)
 #pragma unroll
-        for (int q = 0; q < 3; ++q) lds[q * 16 + w] = inc[q];
+        for (int q = 0; q < 3; ++q) lds[q * kScanSlots + w] = inc[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 3; ++q) scan_wave_totals(lds + q * kScanSlots);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        int64_t base = 0, all = 0;
-        for (int i = 0; i < kOffThreads / 64; ++i) {
-            if (i < w) base += lds[q * 16 + i];
-            all += lds[q * 16 + i];
-        }
-        ex[q] = base + inc[q] - x[q];
-        total[q] = all;
+        ex[q] = lds[q * kScanSlots + w] + inc[q] - x[q];
+        total[q] = lds[q * kScanSlots + kScanSlots - 1];
     }
     __syncthreads();
 }
@@ -518,7 +533,7 @@ __device__ __forceinline__ void excl_scan3_1024(const int64_t (&x)[3], int64_t (
 constexpr int kOffLds = 2048;
 __global__ __launch_bounds__(kOffThreads) void k_seg_offsets(int K, SegWs ws)
 {
-    __shared__ int64_t wtot[48];
+    __shared__ int64_t wtot[3 * kScanSlots];
     __shared__ int64_t s_off[kOffLds + 1];
     __shared__ int32_t s_boff[kOffLds + 1];
     const int t = threadIdx.x;
@@ -792,7 +807,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_bucket(GraphView g, int K, SegWs
 // earlier buckets), and the placement cursor.
 __global__ __launch_bounds__(kOffThreads) void k_seg_boffsets(int K, SegWs ws)
 {
-    __shared__ int64_t wtot[kOffThreads / 64];
+    __shared__ int64_t wtot[kScanSlots];
     const int NB = ws.boff[K];
     const int t = threadIdx.x;
     int64_t cc = 0, cd = 0;
