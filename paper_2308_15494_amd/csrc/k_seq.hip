@@ -862,11 +862,9 @@ struct SegDecide {
 };
 
 // The move of v into B, priced against W[B] plus the weight change of the
-// events before it (netpre).
-__device__ __forceinline__ void seg_decide_one(const SegDecide &d, int64_t v, int64_t cv,
-                                               int64_t gv, int64_t netpre,
-                                               unsigned long long *acc_lds,
-                                               unsigned long long *deg_lds)
+// events before it (netpre); returns whether it is taken.
+__device__ __forceinline__ bool seg_decide_one(const SegDecide &d, int64_t v, int64_t cv,
+                                               int64_t gv, int64_t netpre)
 {
     bool allowed = gv > 0;
     int64_t P = 0;
@@ -881,12 +879,8 @@ __device__ __forceinline__ void seg_decide_one(const SegDecide &d, int64_t v, in
     }
     const bool take = allowed && gv * 65536 - P > 0;
     d.accflag[v] = take ? 1 : 0;
-    if (take) {
-        d.mvto[v] = d.B;
-        atomicAdd(acc_lds, 1ull);
-        const int64_t deg = d.g.xadj[v + 1] - d.g.xadj[v];
-        atomicAdd(deg_lds, (unsigned long long)deg);
-    }
+    if (take) d.mvto[v] = d.B;
+    return take;
 }
 
 // Scan and decide the IPT sorted keys of each thread (blocked: the
@@ -898,10 +892,11 @@ __device__ __forceinline__ void seg_scan_decide(const uint64_t (&k)[IPT], int64_
                                                 int64_t *scan_lds, unsigned long long *acc_lds,
                                                 unsigned long long *deg_lds)
 {
-    // the events' node weights and the inflow events' pessimistic gains,
-    // loaded together (node 0 stands in for the slots past the bucket's end,
-    // whose keys hold no node id)
-    int64_t w[IPT], gv[IPT], cw[IPT];
+    // the events' node weights, the inflow events' pessimistic gains and
+    // degrees (for the moved-degree count), loaded together (node 0 stands in
+    // for the slots past the bucket's end, whose keys hold no node id), so
+    // that the decisions below wait on no load
+    int64_t w[IPT], gv[IPT], cw[IPT], dg[IPT];
     int64_t vs[IPT];
 #pragma unroll
     for (int j = 0; j < IPT; ++j) vs[j] = pos0 + j < m ? (int64_t)((k[j] >> 1) & d.idmask) : 0;
@@ -910,12 +905,14 @@ __device__ __forceinline__ void seg_scan_decide(const uint64_t (&k)[IPT], int64_
         for (int j = 0; j < IPT; ++j) {
             gv[j] = d.gp[vs[j]];
             cw[j] = d.g.vwgt[vs[j]];
+            dg[j] = d.g.xadj[vs[j] + 1] - d.g.xadj[vs[j]];
         }
     } else {
 #pragma unroll
         for (int j = 0; j < IPT; ++j) {
             gv[j] = d.gp[vs[j]];
             cw[j] = 1;
+            dg[j] = d.g.xadj[vs[j] + 1] - d.g.xadj[vs[j]];
         }
     }
     int64_t ts = 0;
@@ -929,12 +926,22 @@ __device__ __forceinline__ void seg_scan_decide(const uint64_t (&k)[IPT], int64_
     int64_t total;
     const int64_t inc = block_incl_scan(ts, scan_lds, &total);
     int64_t run = carry + inc - ts;
+    unsigned long long nacc = 0, ndeg = 0;
 #pragma unroll
     for (int j = 0; j < IPT; ++j) {
-        if (pos0 + j < m && !(k[j] & 1ull))
-            seg_decide_one(d, (int64_t)((k[j] >> 1) & d.idmask), w[j], gv[j], run, acc_lds,
-                           deg_lds);
+        if (pos0 + j < m && !(k[j] & 1ull) &&
+            seg_decide_one(d, (int64_t)((k[j] >> 1) & d.idmask), w[j], gv[j], run)) {
+            ++nacc;
+            ndeg += (unsigned long long)dg[j];
+        }
         run += w[j];
+    }
+    // one LDS atomic per wave for each count
+    nacc = wave_sum(nacc);
+    ndeg = wave_sum(ndeg);
+    if (lane_id() == 0 && nacc) {
+        atomicAdd(acc_lds, nacc);
+        atomicAdd(deg_lds, ndeg);
     }
     carry += total;
 }

@@ -250,11 +250,13 @@ __device__ __forceinline__ int rebalance_bucket(int64_t gain, int64_t c)
     return kSlots + 1 + slot_of(-gain, c);
 }
 
+// min(q * c, kPenCap) for q, c >= 0 (a Q16 penalty factor and a node
+// weight), from the exact 128-bit product: no 64-bit division.
 __device__ __forceinline__ int64_t sat_mul_pen(int64_t q, int64_t c)
 {
-    if (q != 0 && c > kPenCap / q) return kPenCap;
-    int64_t p = q * c;
-    return p > kPenCap ? kPenCap : p;
+    const uint64_t lo = (uint64_t)q * (uint64_t)c;
+    const uint64_t hi = __umul64hi((uint64_t)q, (uint64_t)c);
+    return (hi != 0 || lo > (uint64_t)kPenCap) ? kPenCap : (int64_t)lo;
 }
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
