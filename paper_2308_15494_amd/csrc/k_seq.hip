@@ -206,10 +206,11 @@ namespace {
 
 constexpr int kSegBins = 2048;          // block window up to which a workgroup aggregates in LDS
 constexpr int kSegRows = 512;           // most workgroups of the counting and placement passes
-constexpr int kSortItems = 8;           // keys per thread of the workgroup sort
+constexpr int kSortItems = 4;           // keys per thread of the workgroup sorts
 constexpr int kWaveKeys = 64 * kSortItems;
-constexpr int kRun = kBlock * kSortItems;  // a segment or bucket sorted in LDS in one piece
-constexpr int kSplitThreads = 512;      // threads of the splitter kernel
+constexpr int kDecideThreads = 512;     // threads of the decide kernel (one bucket each)
+constexpr int kRun = kDecideThreads * kSortItems;  // a segment or bucket sorted in LDS in one piece
+constexpr int kSplitThreads = 1024;     // threads of the splitter kernel
 constexpr int kSample = kSplitThreads * kSortItems;  // largest sample
 constexpr int kBucketAvg = 768;         // average bucket of a split segment
 constexpr int kMaxBuckets = 2048;       // buckets of one segment at most
@@ -924,7 +925,7 @@ __device__ __forceinline__ void seg_scan_decide(const uint64_t (&k)[IPT], int64_
         ts += w[j];
     }
     int64_t total;
-    const int64_t inc = block_incl_scan(ts, scan_lds, &total);
+    const int64_t inc = block_incl_scan<int64_t, kDecideThreads / 64>(ts, scan_lds, &total);
     int64_t run = carry + inc - ts;
     unsigned long long nacc = 0, ndeg = 0;
 #pragma unroll
@@ -966,7 +967,8 @@ __device__ __forceinline__ void seg_load_keys(uint64_t (&k)[kSortItems], const u
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_seg_decide(GraphView g, Blocks bk, SegWs ws, int idb,
+__global__ __launch_bounds__(kDecideThreads) void k_seg_decide(GraphView g, Blocks bk, SegWs ws,
+                                                               int idb,
                                                        const int64_t *__restrict__ gp,
                                                        const int64_t *__restrict__ W,
                                                        const int64_t *__restrict__ cb, int mode,
@@ -975,7 +977,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_decide(GraphView g, Blocks bk, S
                                                        unsigned long long *counters)
 {
     __shared__ uint64_t lds[2 * kRun];
-    __shared__ int64_t scan_lds[4];
+    __shared__ int64_t scan_lds[kDecideThreads / 64];
     __shared__ int64_t s_cb[kSlots], s_pen[kSlots];
     __shared__ unsigned long long acc_lds, deg_lds;
     const int K = bk.total();
@@ -1015,7 +1017,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_decide(GraphView g, Blocks bk, S
     if (m <= kRun) {
         const int64_t pos0 = (int64_t)threadIdx.x * kSortItems;
         seg_load_keys(k, src, pos0, m);
-        block_sort_keys<kBlock>(k, lds, m);
+        block_sort_keys<kDecideThreads>(k, lds, m);
         seg_scan_decide<kSortItems>(k, pos0, m, carry, d, scan_lds, &acc_lds, &deg_lds);
     } else if (m <= 2 * kRun) {
         // each half sorted with the upper half of the buffer as scratch, then
@@ -1023,7 +1025,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_decide(GraphView g, Blocks bk, S
         for (int hf = 0; hf < 2; ++hf) {
             const int64_t pos0 = (int64_t)hf * kRun + (int64_t)threadIdx.x * kSortItems;
             seg_load_keys(k, src, pos0, m);
-            block_sort_keys<kBlock>(k, lds + kRun, hf == 0 ? (int64_t)kRun : m - kRun);
+            block_sort_keys<kDecideThreads>(k, lds + kRun, hf == 0 ? (int64_t)kRun : m - kRun);
 #pragma unroll
             for (int j = 0; j < kSortItems; ++j) lds[pos0 + j] = k[j];
             __syncthreads();
@@ -1063,7 +1065,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_decide(GraphView g, Blocks bk, S
         for (int64_t r0 = 0; r0 < m; r0 += kRun) {
             const int64_t pos0 = r0 + (int64_t)threadIdx.x * kSortItems;
             seg_load_keys(k, src, pos0, m);
-            block_sort_keys<kBlock>(k, lds, m - r0 < kRun ? m - r0 : (int64_t)kRun);
+            block_sort_keys<kDecideThreads>(k, lds, m - r0 < kRun ? m - r0 : (int64_t)kRun);
 #pragma unroll
             for (int j = 0; j < kSortItems; ++j)
                 if (pos0 + j < m) src[pos0 + j] = k[j];
@@ -1071,7 +1073,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_decide(GraphView g, Blocks bk, S
         }
         // pairwise merges of runs of width w
         for (int64_t w = kRun; w < m; w <<= 1) {
-            for (int64_t o0 = 0; o0 < m; o0 += (int64_t)kBlock * kSegMergeItems) {
+            for (int64_t o0 = 0; o0 < m; o0 += (int64_t)kDecideThreads * kSegMergeItems) {
                 const int64_t d0 = o0 + (int64_t)threadIdx.x * kSegMergeItems;
                 if (d0 >= m) continue;
                 const int64_t a0 = (d0 / (2 * w)) * (2 * w);
@@ -1165,7 +1167,7 @@ hipError_t launch_seq_segments(const GraphView &g, const Blocks &bk, const int64
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_seg_bucket<true>, dim3(chunks), dim3(kBlock), 0, s, g, K, ws, idb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_seg_decide, dim3((unsigned)seq_bucket_bound(g.n, K)), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL(k_seg_decide, dim3((unsigned)seq_bucket_bound(g.n, K)), dim3(kDecideThreads), 0, s,
                        g, bk, ws, idb, gp, W, cb, mode, hub_t, mvto, accflag, counters);
     return hipGetLastError();
 }

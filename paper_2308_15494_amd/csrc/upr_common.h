@@ -303,19 +303,24 @@ __device__ __forceinline__ T wave_incl_scan(T x)
     return x;
 }
 
-// Block-wide inclusive scan (blockDim.x == kBlock); returns the inclusive
-// prefix of the calling thread and the block total in *total.
-template <typename T>
-__device__ __forceinline__ T block_incl_scan(T x, T *lds /* >= 4 */, T *total)
+// Block-wide inclusive scan (blockDim.x == 64 * NW, kBlock by default);
+// returns the inclusive prefix of the calling thread and the block total in
+// *total.
+template <typename T, int NW = kBlock / 64>
+__device__ __forceinline__ T block_incl_scan(T x, T *lds /* >= NW */, T *total)
 {
     T inc = wave_incl_scan(x);
     const int w = threadIdx.x >> 6;
     __syncthreads();
     if (lane_id() == 63) lds[w] = inc;
     __syncthreads();
-    T base = 0;
-    for (int i = 0; i < w; ++i) base += lds[i];
-    *total = lds[0] + lds[1] + lds[2] + lds[3];
+    T base = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        if (i < w) base += lds[i];
+        all += lds[i];
+    }
+    *total = all;
     __syncthreads();
     return base + inc;
 }

@@ -40,11 +40,11 @@ def exact_segment_sizes(g, k, part0, odbg):
 
 
 @pytest.mark.parametrize("n,k,lo,hi", [
-    (6000, 64, 1, 256),          # one key per thread
-    (30000, 64, 257, 1024),      # 4 keys per thread
-    (60000, 16, 1025, 4096),     # 16 keys per thread
-    (60000, 4, 2049, 8192),      # 32 keys per thread
-    (250000, 2, 16385, None),    # runs of 8192 merged over at least two passes
+    (6000, 64, 1, 256),          # within one wave's sorted run (256 keys)
+    (30000, 64, 257, 1024),      # the workgroup sort with merge rounds in LDS
+    (60000, 16, 1025, 4096),     # up to two workgroup runs (2048 keys): one bucket or split
+    (60000, 4, 2049, 8192),      # split into buckets by sampled splitters
+    (250000, 2, 16385, None),    # many buckets of one segment
 ], ids=["s1", "s4", "s16", "s32", "merge"])
 def test_segment_size_classes(upr, ctx, n, k, lo, hi):
     g = gg.chung_lu(n, 8.0, 2.3, seed=n + k)
