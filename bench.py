@@ -381,8 +381,10 @@ def oracle_pool(spec, workers, what, eps=(3, 100), rounds=10):
 def batched_vs_plain(ctx, spec, eps=(3, 100), rounds=10, tune_batches=True):
     """The many-graphs workload refined twice: plain (one graph after the
     other, upr_refine_round per graph and round) and batched (one batch per k,
-    upr_batch_refine_round per round), then batched once more with the move
-    phases replayed from captured HIP graphs (upr_capture_enable). Each batch's traversal thresholds are
+    upr_batch_refine_round per round), then with every batch on a context,
+    stream and host thread of its own (the batches run concurrently), then
+    batched once more with the move phases replayed from captured HIP graphs
+    (upr_capture_enable). Each batch's traversal thresholds are
     picked by the autotuner first (timed trial rounds; the plain graphs keep
     the defaults: 512 tunings would cost more than they save). Plans and
     batches are built and warmed up before the timed regions; both start
@@ -443,11 +445,51 @@ def batched_vs_plain(ctx, spec, eps=(3, 100), rounds=10, tune_batches=True):
         fn()
         torch.cuda.synchronize()
         out[name] = time.perf_counter() - t0
+    # the batches again, each on a context and stream of its own and driven
+    # by a host thread of its own, so that their launches and the host waits
+    # of their rebalancing overlap
+    import threading
+    conc = {k: upr.Batch(upr.Context(ctx.device), [refs[i].dg for i in idx], k, eps,
+                         opts=opts.get(k)) for k, idx in groups.items()}
+    streams = {k: torch.cuda.Stream() for k in conc}
+
+    def reset_conc():
+        for k, idx in groups.items():
+            conc[k].set_partitions([gg.random_partition(spec[i][0].n, k, spec[i][2]) for i in idx])
+        torch.cuda.synchronize()
+
+    def run_conc():
+        errors = []
+
+        def work(k, b):
+            try:
+                for i in range(1, rounds + 1):
+                    b.round(upr.params(k, eps, tau=gg.tau_schedule(i, rounds)), stream=streams[k])
+            except Exception as e:  # reported after the join
+                errors.append(e)
+
+        threads = [threading.Thread(target=work, args=(k, b)) for k, b in conc.items()]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        torch.cuda.synchronize()
+        if errors:
+            raise errors[0]
+
+    reset_conc()
+    run_conc()  # warm-up pass
+    reset_conc()
+    t0 = time.perf_counter()
+    run_conc()
+    out["concurrent"] = time.perf_counter() - t0
+
     # identical results, graph by graph
-    def same_as_plain():
+    def same_as_plain(bs=None):
+        bs = batches if bs is None else bs
         same = True
         for k, idx in groups.items():
-            b = batches[k]
+            b = bs[k]
             parts = b.local_partitions()
             st = b.stats.cpu().numpy().reshape(b.ng, upr.STATS_LEN)
             for j, i in enumerate(idx):
@@ -456,6 +498,10 @@ def batched_vs_plain(ctx, spec, eps=(3, 100), rounds=10, tune_batches=True):
         return same
 
     same = same_as_plain()
+    same_conc = same_as_plain(conc)
+    for b in conc.values():
+        b.close()
+        b.ctx.close()
     # the batched rounds again with their move phases replayed from HIP graphs
     # (one per batch, captured in the warm-up pass)
     ctx.capture(True)
@@ -477,6 +523,7 @@ def batched_vs_plain(ctx, spec, eps=(3, 100), rounds=10, tune_batches=True):
             "plain_s": out["plain"], "batched_s": out["batched"],
             "speedup": out["plain"] / out["batched"], "identical_results": same,
             "captured_graphs_per_s": ng / out["captured"], "captured_identical_results": same_captured,
+            "concurrent_graphs_per_s": ng / out["concurrent"], "concurrent_identical_results": same_conc,
             "thresholds": {str(k): v for k, v in chosen.items()} if chosen else "default",
             "tune_s": tune_s}
 
@@ -484,50 +531,57 @@ def batched_vs_plain(ctx, spec, eps=(3, 100), rounds=10, tune_batches=True):
 def serving(ctx, spec, eps=(3, 100), rounds=10, load=0.7, budget_gb=200.0, check=4, seed=7):
     """Poisson stream of refinement requests through the continuous-batching
     server. The capacity is measured first with every request arriving at
-    time 0, then again on the context with its move phases captured in HIP
-    graphs; the stream then arrives at `load` times the eager rate. Reports
-    latency percentiles (completion minus arrival) and throughput; a few
-    requests are also refined alone and must give the same result."""
+    time 0: with the groups stepped one after the other, then on a context
+    with the move phases captured in HIP graphs, then with every (k, eps)
+    group on a context, stream and host thread of its own (the groups'
+    rounds of a step run concurrently). The stream then arrives at `load`
+    times the concurrent server's capacity and runs through that server.
+    Reports latency percentiles (completion minus arrival) and throughput; a
+    few requests of every run are also refined alone and must give the same
+    result."""
     from paper_2308_15494_amd import serve
     reqs0 = [serve.Request(j, g, k, eps, rounds=rounds, arrival=0.0, part_seed=s)
              for j, (g, k, s) in enumerate(spec)]
     budget = int(budget_gb * (1 << 30))
-    srv = serve.Server(ctx, budget)
-    srv.run(reqs0[: min(8, len(reqs0))])  # warm-up
-    t0 = time.perf_counter()
-    srv.run(reqs0)
-    cap = len(reqs0) / (time.perf_counter() - t0)
-    # the same capacity run on a context that replays its move phases from
-    # captured HIP graphs (a batch whose membership changed is a new plan,
-    # captured on its first round)
+
+    def same_as_alone(res, reqs):
+        same = True
+        for r in res[:check]:
+            part, stats = serve.refine_alone(ctx, reqs[r.rid])
+            same &= bool(np.array_equal(part, r.part)) and stats == r.stats
+        return same
+
+    def capacity(srv):
+        srv.run(reqs0[: min(8, len(reqs0))])  # warm-up
+        t0 = time.perf_counter()
+        res = srv.run(reqs0)
+        return len(reqs0) / (time.perf_counter() - t0), same_as_alone(res, reqs0)
+
+    cap, same0 = capacity(serve.Server(ctx, budget))
+    # a batch whose membership changed is a new plan, captured on its first round
     ctx.capture(True)
     try:
-        srv.run(reqs0[: min(8, len(reqs0))])
-        t0 = time.perf_counter()
-        res_c = srv.run(reqs0)
-        cap_c = len(reqs0) / (time.perf_counter() - t0)
+        cap_c, same_c = capacity(serve.Server(ctx, budget))
     finally:
         ctx.capture(False)
-    same_c = True
-    for r in res_c[:check]:
-        part, stats = serve.refine_alone(ctx, reqs0[r.rid])
-        same_c &= bool(np.array_equal(part, r.part)) and stats == r.stats
-    rate = load * cap
+    conc = serve.Server(ctx, budget, concurrent=True)
+    cap_cc, same_cc = capacity(conc)
+    rate = load * cap_cc
     arr = serve.poisson_arrivals(len(spec), rate, seed)
     reqs = [serve.Request(j, g, k, eps, rounds=rounds, arrival=float(arr[j]), part_seed=s)
             for j, (g, k, s) in enumerate(spec)]
-    srv.timings = {}
+    conc.timings = {}
     t0 = time.perf_counter()
-    res = srv.run(reqs)
+    res = conc.run(reqs)
     span = time.perf_counter() - t0
-    tim = {k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in srv.timings.items()}
+    tim = {k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in conc.timings.items()}
     lat = [r.latency for r in res]
-    same = True
-    for r in res[:check]:
-        part, stats = serve.refine_alone(ctx, reqs[r.rid])
-        same &= bool(np.array_equal(part, r.part)) and stats == r.stats
+    same = same_as_alone(res, reqs)
     return {"requests": len(spec), "rounds": rounds, "capacity_graphs_per_s": cap,
+            "capacity_same_as_alone": same0,
             "captured_capacity_graphs_per_s": cap_c, "captured_same_as_alone": same_c,
+            "concurrent_capacity_graphs_per_s": cap_cc, "concurrent_same_as_alone": same_cc,
+            "stream_server": "concurrent groups",
             "arrival_rate_per_s": rate, "graphs_per_s": len(res) / span,
             "p50_latency_ms": 1e3 * float(np.percentile(lat, 50)),
             "p99_latency_ms": 1e3 * float(np.percentile(lat, 99)),

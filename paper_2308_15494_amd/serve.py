@@ -17,7 +17,11 @@ does the next step rebuild the tables (a table is a function of the
 partition, so the result is the same either way).
 
 Because no kernel lets two graphs of a batch interact, each request's result
-is exactly what it gets when refined alone.
+is exactly what it gets when refined alone. With `concurrent`, every group
+has a context and stream of its own and the groups' rounds of a step run
+from host threads of their own at the same time (their launches and the host
+waits of their rebalancing overlap); each group still goes through its own
+rebuilds and rounds in the same order, so the results are the same.
 
 The refinement arithmetic runs in libupr (upr_batch_*); this module only
 schedules, moves partitions between batches and measures latency.
@@ -25,6 +29,7 @@ schedules, moves partitions between batches and measures latency.
 from __future__ import annotations
 
 import dataclasses
+import threading
 import time
 
 import numpy as np
@@ -80,8 +85,8 @@ class _Job:
 class _Group:
     """The batch of the admitted requests with one (k, eps)."""
 
-    def __init__(self, ctx, k, eps):
-        self.ctx, self.k, self.eps = ctx, k, eps
+    def __init__(self, ctx, k, eps, stream=None):
+        self.ctx, self.k, self.eps, self.stream = ctx, k, eps, stream
         self.jobs: list[_Job] = []
         self.members: list[_Job] = []
         self.batch = None
@@ -115,14 +120,25 @@ class _Group:
         self.dirty = False
         return any(s < 0 for s in src)
 
-    def step(self):
-        """One round of every member; returns the members that finished."""
+    def launch(self):
+        """Enqueue one round of every member (on the group's stream)."""
         b = self.batch
         rebuild = 1 if self.fresh else 0
         taus = [gg.tau_schedule(j.round + 1, j.req.rounds) for j in self.members]
-        b.round(upr.params(self.k, self.eps, tau=(1, 1), rebuild_table=rebuild), taus=taus)
+        b.round(upr.params(self.k, self.eps, tau=(1, 1), rebuild_table=rebuild), taus=taus,
+                stream=self.stream)
         self.fresh = False
-        st = b.stats.cpu().numpy().reshape(b.ng, upr.STATS_LEN)  # synchronises
+
+    def step(self):
+        """One round of every member; returns the members that finished."""
+        self.launch()
+        return self.finish()
+
+    def finish(self):
+        """After the round has completed (the group's stream synchronised):
+        count it for every member; returns the members that finished."""
+        b = self.batch
+        st = b.stats.cpu().numpy().reshape(b.ng, upr.STATS_LEN)
         finished = []
         for i, j in enumerate(self.members):
             j.round += 1
@@ -135,10 +151,12 @@ class _Group:
 class Server:
     """Admission by footprint, continuous batching, latency bookkeeping."""
 
-    def __init__(self, ctx: upr.Context, budget_bytes: int, admit_every: int = 3):
+    def __init__(self, ctx: upr.Context, budget_bytes: int, admit_every: int = 3,
+                 concurrent: bool = False):
         self.ctx = ctx
         self.budget = budget_bytes
         self.admit_every = max(int(admit_every), 1)
+        self.concurrent = bool(concurrent)
         self.timings = {}
 
     def _tick(self, name, t):
@@ -153,6 +171,26 @@ class Server:
         t0 = clock()
         pi = 0
         active = 0
+
+        def settle(grp, finished):
+            # results of the requests that finished this step; the batch
+            # is rebuilt without them at the next step
+            nonlocal used, active
+            grp.since_rebuild += 1
+            if not finished:
+                return
+            parts = grp.batch.local_partitions()
+            done = clock() - t0
+            for i, j in finished:
+                res = Result(j.req.rid, parts[i], j.stats, j.req.arrival, j.admitted, done)
+                results.append(res)
+                if on_done:
+                    on_done(res)
+                grp.jobs.remove(j)
+                used -= j.req.footprint()
+                active -= 1
+            grp.dirty = True
+
         while pi < len(pending) or active:
             now = clock() - t0
             # admission: arrived requests in arrival order while they fit
@@ -170,7 +208,11 @@ class Server:
                 upr.validate_graph(self.ctx, dg)
                 self._tick("admit_s", clock() - t1)
                 if grp is None:
-                    grp = groups[key] = _Group(self.ctx, req.k, req.eps)
+                    if self.concurrent:
+                        grp = _Group(upr.Context(self.ctx.device), req.k, req.eps, torch.cuda.Stream())
+                    else:
+                        grp = _Group(self.ctx, req.k, req.eps)
+                    groups[key] = grp
                 grp.waiting.append(_Job(req, dg, clock() - t0))
                 used += need
                 active += 1
@@ -182,6 +224,7 @@ class Server:
                 if wait > 0:
                     time.sleep(min(wait, 0.01))
                 continue
+            stepping = []
             for grp in groups.values():
                 # newcomers join an idle batch at once, a running one every
                 # admit_every steps or whenever it is rebuilt anyway (each
@@ -200,26 +243,46 @@ class Server:
                     self._tick("rebuilds", 1)
                 if not grp.members:
                     continue
+                if self.concurrent:
+                    stepping.append(grp)
+                    continue
                 t1 = clock()
                 finished = grp.step()
-                grp.since_rebuild += 1
                 self._tick("step_s", clock() - t1)
                 self._tick("steps", 1)
-                if finished:
-                    parts = grp.batch.local_partitions()
-                    done = clock() - t0
-                    for i, j in finished:
-                        res = Result(j.req.rid, parts[i], j.stats, j.req.arrival, j.admitted, done)
-                        results.append(res)
-                        if on_done:
-                            on_done(res)
-                        grp.jobs.remove(j)
-                        used -= j.req.footprint()
-                        active -= 1
-                    grp.dirty = True
+                settle(grp, finished)
+            if stepping:
+                # every group's round from a thread of its own, on its own
+                # context and stream; the uploads, rebuilds and carries made
+                # on the current stream complete first
+                t1 = clock()
+                torch.cuda.synchronize()
+                errors = []
+
+                def launch(grp):
+                    try:
+                        grp.launch()
+                    except Exception as e:  # raised after the join
+                        errors.append(e)
+
+                threads = [threading.Thread(target=launch, args=(grp,)) for grp in stepping]
+                for th in threads:
+                    th.start()
+                for th in threads:
+                    th.join()
+                torch.cuda.synchronize()
+                if errors:
+                    raise errors[0]
+                finished_by = [(grp, grp.finish()) for grp in stepping]
+                self._tick("step_s", clock() - t1)
+                self._tick("steps", len(stepping))
+                for grp, finished in finished_by:
+                    settle(grp, finished)
         for grp in groups.values():
             if grp.batch is not None:
                 grp.batch.close()
+            if grp.ctx is not self.ctx:
+                grp.ctx.close()
         return sorted(results, key=lambda r: r.rid)
 
 

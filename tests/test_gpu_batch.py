@@ -266,3 +266,59 @@ def test_batch_carry_state(upr, ctx):
         assert np.array_equal(c.conn.cpu().numpy()[c.off[g] * k:(c.off[g] + n) * k], conn), g
     a.close()
     c.close()
+
+
+def test_concurrent_batches_in_threads(upr, ctx):
+    """Batches with different k, each on a context and stream of its own and
+    refined from host threads of their own at the same time, give what the
+    same batches give one after the other on one context."""
+    import threading
+    import torch
+    groups = {k: [gg.chung_lu(2500 + 300 * i, 8.0, 2.3, seed=40 + k + i) if i % 2 == 0 else
+                  gg.rmat(10, 12, seed=50 + k + i) for i in range(4)] for k in (4, 8, 16)}
+    parts = {k: [skewed_partition(g.n, k, i, 0.3) for i, g in enumerate(gs)] for k, gs in groups.items()}
+    R = 5
+
+    def run(b, k, stream=None):
+        for r in range(1, R + 1):
+            b.round(upr.params(k, tau=gg.tau_schedule(r, R)), stream=stream)
+
+    # one after the other, one context
+    seq = {}
+    for k, gs in groups.items():
+        b = upr.Batch(ctx, gs, k)
+        b.set_partitions(parts[k])
+        run(b, k)
+        seq[k] = (b.local_partitions(), b.stats.cpu().numpy().copy(), b.W.cpu().numpy().copy())
+        b.close()
+    # concurrently: a context, stream and thread per batch
+    conc = {k: upr.Batch(upr.Context(0), gs, k) for k, gs in groups.items()}
+    streams = {k: torch.cuda.Stream() for k in conc}
+    for k, b in conc.items():
+        b.set_partitions(parts[k])
+    torch.cuda.synchronize()
+    errors = []
+
+    def work(k, b):
+        try:
+            run(b, k, streams[k])
+        except Exception as e:
+            errors.append(e)
+
+    say("concurrent batches k=" + ",".join(str(k) for k in conc))
+    threads = [threading.Thread(target=work, args=(k, b)) for k, b in conc.items()]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+    for k, b in conc.items():
+        p_seq, st_seq, w_seq = seq[k]
+        for j, (x, y) in enumerate(zip(b.local_partitions(), p_seq)):
+            assert np.array_equal(x, y), f"k={k} graph {j}: partition"
+        assert np.array_equal(b.stats.cpu().numpy(), st_seq), f"k={k}: statistics"
+        assert np.array_equal(b.W.cpu().numpy(), w_seq), f"k={k}: block weights"
+        c = b.ctx
+        b.close()
+        c.close()

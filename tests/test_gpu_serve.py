@@ -1,7 +1,7 @@
 """Serving with continuous batching: every request's result (final partition
 and per-round statistics) is the same in the mix as alone, and the same as
 the oracle's, also when the server's context replays its move phases from
-captured HIP graphs."""
+captured HIP graphs and when its groups run concurrently."""
 import sys
 
 import numpy as np
@@ -56,15 +56,17 @@ def make_requests(serve, count, seed, rate):
     return reqs
 
 
-@pytest.mark.parametrize("captured", [False, True])
+@pytest.mark.parametrize("mode", ["plain", "captured", "concurrent"])
 @pytest.mark.parametrize("budget_mb", [1, 4096])
-def test_serve_results_same_alone_and_in_mix(env, cap_ctx, budget_mb, captured):
+def test_serve_results_same_alone_and_in_mix(env, cap_ctx, budget_mb, mode):
     upr, serve, ctx = env
     reqs = make_requests(serve, 14, 5, rate=400.0)
-    say(f"serve budget={budget_mb}MB captured={captured} sizes={[r.graph.n for r in reqs]} "
+    say(f"serve budget={budget_mb}MB mode={mode} sizes={[r.graph.n for r in reqs]} "
         f"k={[r.k for r in reqs]}")
-    # requests refined alone run on the eager context
-    srv = serve.Server(cap_ctx if captured else ctx, budget_mb << 20)
+    # requests refined alone run on the eager context; the concurrent server
+    # gives every (k, eps) group a context, stream and thread of its own
+    srv = serve.Server(cap_ctx if mode == "captured" else ctx, budget_mb << 20,
+                       concurrent=mode == "concurrent")
     res = srv.run(reqs)
     assert [r.rid for r in res] == list(range(len(reqs)))
     for req, r in zip(reqs, res):
