@@ -577,6 +577,7 @@ def serving(ctx, spec, eps=(3, 100), rounds=10, load=0.7, budget_gb=200.0, check
     tim = {k_: (round(v, 4) if isinstance(v, float) else v) for k_, v in conc.timings.items()}
     lat = [r.latency for r in res]
     same = same_as_alone(res, reqs)
+    conc.close()
     return {"requests": len(spec), "rounds": rounds, "capacity_graphs_per_s": cap,
             "capacity_same_as_alone": same0,
             "captured_capacity_graphs_per_s": cap_c, "captured_same_as_alone": same_c,

@@ -158,6 +158,21 @@ class Server:
         self.admit_every = max(int(admit_every), 1)
         self.concurrent = bool(concurrent)
         self.timings = {}
+        # concurrent: a context and stream per (k, eps), kept across runs so
+        # that their workspaces are allocated once
+        self._group_ctx = {}
+
+    def _context_for(self, key):
+        import torch
+        if key not in self._group_ctx:
+            self._group_ctx[key] = (upr.Context(self.ctx.device), torch.cuda.Stream())
+        return self._group_ctx[key]
+
+    def close(self):
+        """Release the groups' contexts (concurrent server)."""
+        for c, _ in self._group_ctx.values():
+            c.close()
+        self._group_ctx = {}
 
     def _tick(self, name, t):
         self.timings[name] = self.timings.get(name, 0.0) + t
@@ -209,7 +224,8 @@ class Server:
                 self._tick("admit_s", clock() - t1)
                 if grp is None:
                     if self.concurrent:
-                        grp = _Group(upr.Context(self.ctx.device), req.k, req.eps, torch.cuda.Stream())
+                        gctx, gstream = self._context_for(key)
+                        grp = _Group(gctx, req.k, req.eps, gstream)
                     else:
                         grp = _Group(self.ctx, req.k, req.eps)
                     groups[key] = grp
@@ -281,8 +297,6 @@ class Server:
         for grp in groups.values():
             if grp.batch is not None:
                 grp.batch.close()
-            if grp.ctx is not self.ctx:
-                grp.ctx.close()
         return sorted(results, key=lambda r: r.rid)
 
 

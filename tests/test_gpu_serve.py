@@ -68,6 +68,10 @@ def test_serve_results_same_alone_and_in_mix(env, cap_ctx, budget_mb, mode):
     srv = serve.Server(cap_ctx if mode == "captured" else ctx, budget_mb << 20,
                        concurrent=mode == "concurrent")
     res = srv.run(reqs)
+    res2 = srv.run(reqs) if mode == "concurrent" else res  # the groups' contexts are reused
+    srv.close()
+    assert [(r.rid, r.stats) for r in res2] == [(r.rid, r.stats) for r in res]
+    assert all(np.array_equal(a.part, b.part) for a, b in zip(res, res2))
     assert [r.rid for r in res] == list(range(len(reqs)))
     for req, r in zip(reqs, res):
         part, stats = serve.refine_alone(ctx, req)
