@@ -534,8 +534,10 @@ def serving(ctx, spec, eps=(3, 100), rounds=10, load=0.7, budget_gb=200.0, check
     time 0: with the groups stepped one after the other, then on a context
     with the move phases captured in HIP graphs, then with every (k, eps)
     group on a context, stream and host thread of its own (the groups'
-    rounds of a step run concurrently). The stream then arrives at `load`
-    times the concurrent server's capacity and runs through that server.
+    rounds of a step run concurrently) and the arrived requests' graphs
+    uploaded and validated by a thread of its own, up to 16 ahead. The
+    stream then arrives at `load` times the concurrent server's capacity and
+    runs through that server.
     Reports latency percentiles (completion minus arrival) and throughput; a
     few requests of every run are also refined alone and must give the same
     result."""
@@ -564,7 +566,7 @@ def serving(ctx, spec, eps=(3, 100), rounds=10, load=0.7, budget_gb=200.0, check
         cap_c, same_c = capacity(serve.Server(ctx, budget))
     finally:
         ctx.capture(False)
-    conc = serve.Server(ctx, budget, concurrent=True)
+    conc = serve.Server(ctx, budget, concurrent=True, uploads_ahead=16)
     cap_cc, same_cc = capacity(conc)
     rate = load * cap_cc
     arr = serve.poisson_arrivals(len(spec), rate, seed)

@@ -29,6 +29,7 @@ schedules, moves partitions between batches and measures latency.
 from __future__ import annotations
 
 import dataclasses
+import queue
 import threading
 import time
 
@@ -152,12 +153,19 @@ class Server:
     """Admission by footprint, continuous batching, latency bookkeeping."""
 
     def __init__(self, ctx: upr.Context, budget_bytes: int, admit_every: int = 3,
-                 concurrent: bool = False):
+                 concurrent: bool = False, uploads_ahead: int = 0):
+        """concurrent: every (k, eps) group on a context, stream and thread of
+        its own. uploads_ahead > 0: a thread uploads and validates the graphs
+        of arrived requests (on a stream and context of its own), at most that
+        many ahead of admission, while the steps run; those graphs are held
+        on the device beyond the footprint budget until admitted."""
         self.ctx = ctx
         self.budget = budget_bytes
         self.admit_every = max(int(admit_every), 1)
         self.concurrent = bool(concurrent)
+        self.uploads_ahead = max(int(uploads_ahead), 0)
         self.timings = {}
+        self._upload = None  # (context, stream) of the upload thread
         # concurrent: a context and stream per (k, eps), kept across runs so
         # that their workspaces are allocated once
         self._group_ctx = {}
@@ -169,10 +177,47 @@ class Server:
         return self._group_ctx[key]
 
     def close(self):
-        """Release the groups' contexts (concurrent server)."""
+        """Release the contexts of the groups and of the upload thread."""
         for c, _ in self._group_ctx.values():
             c.close()
         self._group_ctx = {}
+        if self._upload is not None:
+            self._upload[0].close()
+            self._upload = None
+
+    def _uploader(self, pending, t0, clock, out, stop):
+        """Upload and validate the graphs of `pending` in order, each once it
+        has arrived; hand (request, graph) or (None, error) to `out`."""
+        import torch
+        uctx, ustream = self._upload
+        dev = torch.device("cuda", self.ctx.device)
+
+        def put(item):
+            while not stop.is_set():
+                try:
+                    out.put(item, timeout=0.01)
+                    return True
+                except queue.Full:
+                    pass
+            return False
+
+        try:
+            for req in pending:
+                while not stop.is_set():
+                    wait = req.arrival - (clock() - t0)
+                    if wait <= 0:
+                        break
+                    time.sleep(min(wait, 0.002))
+                if stop.is_set():
+                    return
+                with torch.cuda.stream(ustream):
+                    dg = upr.DeviceGraph(req.graph, dev)
+                    upr.validate_graph(uctx, dg, stream=ustream)
+                ustream.synchronize()
+                if not put((req, dg)):
+                    return
+        except Exception as e:  # re-raised by the admission loop
+            put((None, e))
 
     def _tick(self, name, t):
         self.timings[name] = self.timings.get(name, 0.0) + t
@@ -206,98 +251,126 @@ class Server:
                 active -= 1
             grp.dirty = True
 
-        while pi < len(pending) or active:
-            now = clock() - t0
-            # admission: arrived requests in arrival order while they fit
-            while pi < len(pending) and pending[pi].arrival <= now:
-                req = pending[pi]
-                need = req.footprint()
-                if active and used + need > self.budget:
-                    break  # wait for memory to free up (arrival order is kept)
-                key = (req.k, tuple(req.eps))
-                grp = groups.get(key)
-                if grp is not None and (len(grp.jobs) + len(grp.waiting) + 1) * req.k > upr.MAX_BATCH_BLOCKS:
-                    break  # the batch has as many graphs as its block ids allow
-                t1 = clock()
-                dg = upr.DeviceGraph(req.graph, torch.device("cuda", self.ctx.device))
-                upr.validate_graph(self.ctx, dg)
-                self._tick("admit_s", clock() - t1)
-                if grp is None:
-                    if self.concurrent:
-                        gctx, gstream = self._context_for(key)
-                        grp = _Group(gctx, req.k, req.eps, gstream)
-                    else:
-                        grp = _Group(self.ctx, req.k, req.eps)
-                    groups[key] = grp
-                grp.waiting.append(_Job(req, dg, clock() - t0))
-                used += need
-                active += 1
-                pi += 1
+        uploads = stop = uploader = None
+        if self.uploads_ahead:
+            if self._upload is None:
+                self._upload = (upr.Context(self.ctx.device), torch.cuda.Stream())
+            uploads = queue.Queue(maxsize=self.uploads_ahead)
+            stop = threading.Event()
+            uploader = threading.Thread(target=self._uploader,
+                                        args=(pending, t0, clock, uploads, stop), daemon=True)
+            uploader.start()
+        try:
+            while pi < len(pending) or active:
                 now = clock() - t0
-            if not active:
-                # idle until the next arrival
-                wait = pending[pi].arrival - (clock() - t0)
-                if wait > 0:
-                    time.sleep(min(wait, 0.01))
-                continue
-            stepping = []
-            for grp in groups.values():
-                # newcomers join an idle batch at once, a running one every
-                # admit_every steps or whenever it is rebuilt anyway (each
-                # change of membership rebuilds the batch)
-                if grp.waiting and (not grp.members or grp.dirty
-                                    or grp.since_rebuild >= self.admit_every):
-                    grp.jobs.extend(grp.waiting)
-                    grp.waiting = []
-                    grp.dirty = True
-                if grp.dirty:
+                # admission: arrived requests in arrival order while they fit
+                while pi < len(pending) and pending[pi].arrival <= now:
+                    req = pending[pi]
+                    need = req.footprint()
+                    if active and used + need > self.budget:
+                        break  # wait for memory to free up (arrival order is kept)
+                    key = (req.k, tuple(req.eps))
+                    grp = groups.get(key)
+                    if grp is not None and (len(grp.jobs) + len(grp.waiting) + 1) * req.k > upr.MAX_BATCH_BLOCKS:
+                        break  # the batch has as many graphs as its block ids allow
                     t1 = clock()
-                    # resident state carried over unless newcomers joined
-                    grp.fresh = grp.rebuild()
-                    grp.since_rebuild = 0
-                    self._tick("rebuild_s", clock() - t1)
-                    self._tick("rebuilds", 1)
-                if not grp.members:
+                    if uploads is not None:
+                        # uploaded and validated by the upload thread, in order
+                        got, dg = uploads.get()
+                        if got is None:
+                            raise dg
+                        assert got is req
+                    else:
+                        dg = upr.DeviceGraph(req.graph, torch.device("cuda", self.ctx.device))
+                        upr.validate_graph(self.ctx, dg)
+                    self._tick("admit_s", clock() - t1)
+                    if grp is None:
+                        if self.concurrent:
+                            gctx, gstream = self._context_for(key)
+                            grp = _Group(gctx, req.k, req.eps, gstream)
+                        else:
+                            grp = _Group(self.ctx, req.k, req.eps)
+                        groups[key] = grp
+                    grp.waiting.append(_Job(req, dg, clock() - t0))
+                    used += need
+                    active += 1
+                    pi += 1
+                    now = clock() - t0
+                if not active:
+                    # idle until the next arrival
+                    wait = pending[pi].arrival - (clock() - t0)
+                    if wait > 0:
+                        time.sleep(min(wait, 0.01))
                     continue
-                if self.concurrent:
-                    stepping.append(grp)
-                    continue
-                t1 = clock()
-                finished = grp.step()
-                self._tick("step_s", clock() - t1)
-                self._tick("steps", 1)
-                settle(grp, finished)
-            if stepping:
-                # every group's round from a thread of its own, on its own
-                # context and stream; the uploads, rebuilds and carries made
-                # on the current stream complete first
-                t1 = clock()
-                torch.cuda.synchronize()
-                errors = []
-
-                def launch(grp):
-                    try:
-                        grp.launch()
-                    except Exception as e:  # raised after the join
-                        errors.append(e)
-
-                threads = [threading.Thread(target=launch, args=(grp,)) for grp in stepping]
-                for th in threads:
-                    th.start()
-                for th in threads:
-                    th.join()
-                torch.cuda.synchronize()
-                if errors:
-                    raise errors[0]
-                finished_by = [(grp, grp.finish()) for grp in stepping]
-                self._tick("step_s", clock() - t1)
-                self._tick("steps", len(stepping))
-                for grp, finished in finished_by:
-                    settle(grp, finished)
-        for grp in groups.values():
-            if grp.batch is not None:
-                grp.batch.close()
+                self._step_groups(groups, clock, settle)
+        finally:
+            if uploader is not None:
+                stop.set()
+                uploader.join()
+            for grp in groups.values():
+                if grp.batch is not None:
+                    grp.batch.close()
         return sorted(results, key=lambda r: r.rid)
+
+    def _step_groups(self, groups, clock, settle):
+        """Rebuild the groups whose membership changes, then one round of
+        every group with members (concurrently with `concurrent`)."""
+        import torch
+        stepping = []
+        for grp in groups.values():
+            # newcomers join an idle batch at once, a running one every
+            # admit_every steps or whenever it is rebuilt anyway (each
+            # change of membership rebuilds the batch)
+            if grp.waiting and (not grp.members or grp.dirty
+                                or grp.since_rebuild >= self.admit_every):
+                grp.jobs.extend(grp.waiting)
+                grp.waiting = []
+                grp.dirty = True
+            if grp.dirty:
+                t1 = clock()
+                # resident state carried over unless newcomers joined
+                grp.fresh = grp.rebuild()
+                grp.since_rebuild = 0
+                self._tick("rebuild_s", clock() - t1)
+                self._tick("rebuilds", 1)
+            if not grp.members:
+                continue
+            if self.concurrent:
+                stepping.append(grp)
+                continue
+            t1 = clock()
+            finished = grp.step()
+            self._tick("step_s", clock() - t1)
+            self._tick("steps", 1)
+            settle(grp, finished)
+        if not stepping:
+            return
+        # every group's round from a thread of its own, on its own context
+        # and stream; the uploads, rebuilds and carries made on the current
+        # stream complete first
+        t1 = clock()
+        torch.cuda.synchronize()
+        errors = []
+
+        def launch(grp):
+            try:
+                grp.launch()
+            except Exception as e:  # raised after the join
+                errors.append(e)
+
+        threads = [threading.Thread(target=launch, args=(grp,)) for grp in stepping]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+        torch.cuda.synchronize()
+        if errors:
+            raise errors[0]
+        finished_by = [(grp, grp.finish()) for grp in stepping]
+        self._tick("step_s", clock() - t1)
+        self._tick("steps", len(stepping))
+        for grp, finished in finished_by:
+            settle(grp, finished)
 
 
 def refine_alone(ctx, req: Request):

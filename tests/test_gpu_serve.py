@@ -56,7 +56,7 @@ def make_requests(serve, count, seed, rate):
     return reqs
 
 
-@pytest.mark.parametrize("mode", ["plain", "captured", "concurrent"])
+@pytest.mark.parametrize("mode", ["plain", "captured", "concurrent", "uploads_ahead"])
 @pytest.mark.parametrize("budget_mb", [1, 4096])
 def test_serve_results_same_alone_and_in_mix(env, cap_ctx, budget_mb, mode):
     upr, serve, ctx = env
@@ -64,11 +64,14 @@ def test_serve_results_same_alone_and_in_mix(env, cap_ctx, budget_mb, mode):
     say(f"serve budget={budget_mb}MB mode={mode} sizes={[r.graph.n for r in reqs]} "
         f"k={[r.k for r in reqs]}")
     # requests refined alone run on the eager context; the concurrent server
-    # gives every (k, eps) group a context, stream and thread of its own
+    # gives every (k, eps) group a context, stream and thread of its own, and
+    # may upload the arrived requests' graphs from a thread of its own
     srv = serve.Server(cap_ctx if mode == "captured" else ctx, budget_mb << 20,
-                       concurrent=mode == "concurrent")
+                       concurrent=mode in ("concurrent", "uploads_ahead"),
+                       uploads_ahead=4 if mode == "uploads_ahead" else 0)
     res = srv.run(reqs)
-    res2 = srv.run(reqs) if mode == "concurrent" else res  # the groups' contexts are reused
+    # the contexts of the groups and of the upload thread are reused
+    res2 = srv.run(reqs) if mode in ("concurrent", "uploads_ahead") else res
     srv.close()
     assert [(r.rid, r.stats) for r in res2] == [(r.rid, r.stats) for r in res]
     assert all(np.array_equal(a.part, b.part) for a, b in zip(res, res2))
@@ -92,13 +95,15 @@ def test_serve_results_same_alone_and_in_mix(env, cap_ctx, budget_mb, mode):
         assert np.array_equal(p, r.part)
 
 
-def test_serve_admission_respects_budget(env):
+@pytest.mark.parametrize("uploads", [0, 3])
+def test_serve_admission_respects_budget(env, uploads):
     upr, serve, ctx = env
     reqs = make_requests(serve, 8, 9, rate=1e4)
     budget = max(r.footprint() for r in reqs) + 1
     seen = []
-    srv = serve.Server(ctx, budget)
+    srv = serve.Server(ctx, budget, uploads_ahead=uploads)
     res = srv.run(reqs, on_done=lambda r: seen.append(r.rid))
+    srv.close()
     assert sorted(seen) == list(range(len(reqs)))
     by_id = {r.rid: r for r in res}
     # at every admission, the requests then in the server fit the budget
