@@ -110,9 +110,9 @@ class _Group:
             # admitted graphs were validated on admission
             self.batch = upr.Batch(self.ctx, [j.dg for j in self.members], self.k, self.eps,
                                    trusted=True)
-            # newcomers start from their own partition; carried slices are
-            # overwritten on the device
-            self.batch.set_partitions([j.part if s < 0 else np.zeros(j.req.graph.n, np.int32)
+            # newcomers start from their own partition (uploaded); carried
+            # slices are filled on the device
+            self.batch.set_partitions([j.part if s < 0 else None
                                        for j, s in zip(self.members, src)])
             if old is not None and any(s >= 0 for s in src):
                 self.batch.carry_from(old, src)
@@ -239,10 +239,10 @@ class Server:
             grp.since_rebuild += 1
             if not finished:
                 return
-            parts = grp.batch.local_partitions()
+            parts = grp.batch.local_partitions([i for i, _ in finished])
             done = clock() - t0
-            for i, j in finished:
-                res = Result(j.req.rid, parts[i], j.stats, j.req.arrival, j.admitted, done)
+            for (i, j), part in zip(finished, parts):
+                res = Result(j.req.rid, part, j.stats, j.req.arrival, j.admitted, done)
                 results.append(res)
                 if on_done:
                     on_done(res)

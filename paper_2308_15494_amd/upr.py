@@ -462,14 +462,29 @@ class Batch:
         self.part = None
 
     def set_partitions(self, parts):
-        """parts: one local partition (values in [0, k)) per graph."""
+        """parts: one local partition (values in [0, k)) per graph, or None for
+        a graph whose slice is filled on the device afterwards (carry_from);
+        then only the given slices are uploaded."""
         import torch
+        if any(p is None for p in parts):
+            self.part = torch.zeros(self.n, dtype=torch.int32, device=self.dev)
+            for g, p in enumerate(parts):
+                if p is None or self.off[g + 1] == self.off[g]:
+                    continue
+                glob = (np.asarray(p, np.int64) + g * self.k).astype(np.int32)
+                self.part[self.off[g]:self.off[g + 1]].copy_(torch.from_numpy(glob))
+            return
         glob = np.zeros(max(self.n, 1), np.int32)
         for g, p in enumerate(parts):
             glob[self.off[g]:self.off[g + 1]] = np.asarray(p, np.int64) + g * self.k
         self.part = torch.from_numpy(glob[: self.n] if self.n else glob[:0]).to(self.dev)
 
-    def local_partitions(self):
+    def local_partitions(self, graphs=None):
+        """Local partitions of every graph, or only of the graphs listed (in
+        that order, each slice downloaded by itself)."""
+        if graphs is not None:
+            return [(self.part[self.off[g]:self.off[g + 1]].cpu().numpy().astype(np.int64)
+                     - g * self.k).astype(np.int32) for g in graphs]
         p = self.part.cpu().numpy().astype(np.int64)
         return [(p[self.off[g]:self.off[g + 1]] - g * self.k).astype(np.int32)
                 for g in range(self.ng)]

@@ -223,10 +223,14 @@ def test_batch_carry_state(upr, ctx):
     order = [3, None, 0, 2]
     b = upr.Batch(ctx, [graphs[i] if i is not None else newcomer for i in order], k)
     start = gg.random_partition(newcomer.n, k, 99)
-    b.set_partitions([start if i is None else np.zeros(graphs[i].n, np.int32) for i in order])
+    # carried slices: None (filled on the device by the carry, only the
+    # newcomer's slice is uploaded)
+    b.set_partitions([start if i is None else None for i in order])
     b.carry_from(a, [i if i is not None else -1 for i in order])
     torch.cuda.synchronize()
     got = b.local_partitions()
+    # single slices, in the order asked
+    assert all(np.array_equal(x, got[g]) for x, g in zip(b.local_partitions([2, 0, 3]), [2, 0, 3]))
     b_conn = b.conn.cpu().numpy()
     b_W = b.W.cpu().numpy().reshape(len(order), k)
     for g, i in enumerate(order):
