@@ -32,6 +32,7 @@ import dataclasses
 import queue
 import threading
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -169,6 +170,7 @@ class Server:
         # concurrent: a context and stream per (k, eps), kept across runs so
         # that their workspaces are allocated once
         self._group_ctx = {}
+        self._pool, self._pool_size = None, 0  # the threads that run the groups' rounds
 
     def _context_for(self, key):
         import torch
@@ -178,6 +180,9 @@ class Server:
 
     def close(self):
         """Release the contexts of the groups and of the upload thread."""
+        if self._pool is not None:
+            self._pool.shutdown()
+            self._pool, self._pool_size = None, 0
         for c, _ in self._group_ctx.values():
             c.close()
         self._group_ctx = {}
@@ -350,22 +355,17 @@ class Server:
         # stream complete first
         t1 = clock()
         torch.cuda.synchronize()
-        errors = []
-
-        def launch(grp):
-            try:
-                grp.launch()
-            except Exception as e:  # raised after the join
-                errors.append(e)
-
-        threads = [threading.Thread(target=launch, args=(grp,)) for grp in stepping]
-        for th in threads:
-            th.start()
-        for th in threads:
-            th.join()
+        if self._pool_size < len(stepping):
+            if self._pool is not None:
+                self._pool.shutdown()
+            self._pool_size = max(len(stepping), 8)
+            self._pool = ThreadPoolExecutor(max_workers=self._pool_size)
+        futures = [self._pool.submit(grp.launch) for grp in stepping]
+        errors = [f.exception() for f in futures]  # waits for every round to be enqueued
         torch.cuda.synchronize()
-        if errors:
-            raise errors[0]
+        for e in errors:
+            if e is not None:
+                raise e
         finished_by = [(grp, grp.finish()) for grp in stepping]
         self._tick("step_s", clock() - t1)
         self._tick("steps", len(stepping))
