@@ -21,7 +21,9 @@ is exactly what it gets when refined alone. With `concurrent`, every group
 has a context and stream of its own and the groups' rounds of a step run
 from host threads of their own at the same time (their launches and the host
 waits of their rebalancing overlap); each group still goes through its own
-rebuilds and rounds in the same order, so the results are the same.
+rebuilds and rounds in the same order, so the results are the same. With
+`uploads_ahead`, a thread uploads and validates every arrived request's graph
+while the steps run, so that admission no longer waits for the copies.
 
 The refinement arithmetic runs in libupr (upr_batch_*); this module only
 schedules, moves partitions between batches and measures latency.
