@@ -1423,6 +1423,9 @@ hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, con
 
 // ----------------------------------------------------------------- stats --
 
+// iters < 0: the statistics follow one speculative rebalancing sub-iteration
+// that no other followed: one sub-iteration counts if blocks were overloaded
+// when rebalancing began, and the status is 1 iff some still are.
 __global__ void k_stats_final(int64_t *stats, const unsigned long long *c, int64_t lmax,
                               int64_t iters, int64_t status)
 {
@@ -1433,6 +1436,12 @@ __global__ void k_stats_final(int64_t *stats, const unsigned long long *c, int64
     const int64_t nc = (int64_t)wave_cnt_get(c, CNT_CAND);
     const int64_t na = (int64_t)wave_cnt_get(c, CNT_ACC);
     const int64_t nr = (int64_t)wave_cnt_get(c, CNT_REBAL_MOVES);
+    const unsigned long long over0 = wave_cnt_get(c, CNT_OVER0);
+    const unsigned long long over = wave_cnt_get(c, CNT_OVER);
+    if (iters < 0) {
+        iters = over0 != 0 ? 1 : 0;
+        status = over != 0 ? 1 : 0;
+    }
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     stats[0] = lmax;
     stats[1] = cb;
@@ -1455,6 +1464,18 @@ __global__ void k_cnt_copy(unsigned long long *c, int dst, int src)
 hipError_t launch_cnt_copy(unsigned long long *counters, int dst, int src, hipStream_t s)
 {
     hipLaunchKernelGGL(k_cnt_copy, dim3(1), dim3(64), 0, s, counters, dst, src);
+    return hipGetLastError();
+}
+
+__global__ void k_cnt_set(unsigned long long *c, int slot, unsigned long long v)
+{
+    wave_cnt_set(c, slot, v);
+}
+
+hipError_t launch_cnt_set(unsigned long long *counters, int slot, unsigned long long v,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cnt_set, dim3(1), dim3(64), 0, s, counters, slot, v);
     return hipGetLastError();
 }
 

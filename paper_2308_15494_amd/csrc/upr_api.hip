@@ -578,10 +578,14 @@ static hipError_t apply_moves(upr_ctx *c, const upr_plan *p, const Blocks &bk, i
 }
 
 // S5: the host loop over synchronous sub-iterations (one graph).
+// early_tail (may be null): enqueued right after the speculative first
+// sub-iteration, before the host waits for its counts; *tail_kept tells
+// whether no sub-iteration followed it.
 int rebalance_loop(upr_ctx *c, const upr_plan *p, const Blocks &bk, int plain, int32_t *part,
                    const PartView &pv, int32_t *conn, int64_t *W, int64_t it_max,
                    int64_t *iters_out, int64_t *status_out, hipStream_t s, bool speculate,
-                   int32_t *rbrec, bool cut_delta)
+                   int32_t *rbrec, bool cut_delta, const std::function<int()> *early_tail,
+                   bool *tail_kept)
 {
     int32_t launched = 0;  // sub-iterations launched (numbers the records in rbrec)
     const HubView h = p->hubs();
@@ -606,11 +610,14 @@ int rebalance_loop(upr_ctx *c, const upr_plan *p, const Blocks &bk, int plain, i
     };
     int rc;
     if ((rc = begin(1))) return rc;
+    const bool early = speculate && early_tail;
     if (speculate) {
         // the first sub-iteration without waiting for the count of overloaded
         // blocks: with none it finds no movable node and changes nothing
         if ((rc = sub_iteration())) return rc;
+        if (early && (rc = (*early_tail)())) return rc;
     }
+    if (tail_kept) *tail_kept = early;
     rc = sync();
     if (rc) return rc;
     if (c->cnt[CNT_BAD_INPUT]) return fail(c, UPR_E_ARG, "part holds values outside [0, k)");
@@ -626,6 +633,7 @@ int rebalance_loop(upr_ctx *c, const upr_plan *p, const Blocks &bk, int plain, i
             break;
         }
         ++iters;
+        if (tail_kept) *tail_kept = false;
         if ((rc = sub_iteration())) return rc;
         rc = sync();
         if (rc) return rc;
@@ -1385,6 +1393,21 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
     }
     if (rc) return rc;
     int64_t iters = 0, status = 0;
+    // the cut after rebalancing and the statistics (iters < 0: derived on the device)
+    const auto cut_after = [&]() -> int {
+        PhaseTimer t(c, 6, s);
+        HIP_TRY(c, launch_node_stats(p->g, bk, sg, part, conn, p->wdeg, nullptr, nullptr, 0, 1,
+                                     c->counters, CNT_CUT2_AFTER, nullptr, gstat, GS_CUT2_AFTER, s,
+                                     nullptr, nullptr, cut_delta));
+        return UPR_OK;
+    };
+    const std::function<int()> tail = [&]() -> int {
+        const int r = cut_after();
+        if (r) return r;
+        HIP_TRY(c, launch_stats_final(stats, c->counters, lmax, -1, -1, s));
+        return UPR_OK;
+    };
+    bool early = false, tail_kept = false;
     {
         PhaseTimer t(c, 5, s);
         if (b) {
@@ -1392,11 +1415,23 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
         } else {
             const int64_t it_max =
                 q->max_rebalance_iters > 0 ? q->max_rebalance_iters : default_iters(p, k);
-            // moves can overload a block except in constrained rounds
+            // moves can overload a block except in constrained rounds. Their
+            // speculative first sub-iteration is usually the only one: the
+            // round's closing kernels are then enqueued before the host waits
+            // for its counts, so that the device runs them while the host
+            // turns round (not while the rebalancing or cut phase is timed)
+            const bool spec = moves && q->mode != 1;
+            early = spec && !prefix && (c->timing.mask & (3u << 5)) == 0;
             rc = rebalance_loop(c, p, bk, plain, part, pv, conn, W, it_max, &iters, &status, s,
-                                moves && q->mode != 1, prefix ? c->bp.rbrec : nullptr, cut_delta);
+                                spec, prefix ? c->bp.rbrec : nullptr, cut_delta,
+                                early ? &tail : nullptr, &tail_kept);
         }
         if (rc) return rc;
+    }
+    if (tail_kept) {
+        // what the device derived, from the counts the host decided on
+        if (iters == (c->cnt[CNT_OVER0] != 0 ? 1 : 0) && status == (c->cnt[CNT_OVER] != 0 ? 1 : 0))
+            return UPR_OK;
     }
     if (prefix) {
         PhaseTimer t(c, 5, s);
@@ -1410,12 +1445,9 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
             return fail(c, UPR_E_HIP, "best prefix failed: %s", hipGetErrorString(e));
         }
     }
-    {
-        PhaseTimer t(c, 6, s);
-        HIP_TRY(c, launch_node_stats(p->g, bk, sg, part, conn, p->wdeg, nullptr, nullptr, 0, 1,
-                                     c->counters, CNT_CUT2_AFTER, nullptr, gstat, GS_CUT2_AFTER, s,
-                                     nullptr, nullptr, cut_delta));
-    }
+    // an early tail that did not stand: its recount (if any) is undone
+    if (early) HIP_TRY(c, launch_cnt_set(c->counters, CNT_CUT2_AFTER, 0, s));
+    if ((rc = cut_after())) return rc;
     if (b) {
         HIP_TRY(c, hipMemcpyAsync(b->host3_d, b->host3_h, sizeof(int64_t) * 3 * ng,
                                   hipMemcpyHostToDevice, s));

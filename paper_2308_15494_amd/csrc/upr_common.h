@@ -558,6 +558,9 @@ hipError_t launch_store_half(const unsigned long long *counters, int slot, int64
                              hipStream_t s);
 // Spread counter dst = src.
 hipError_t launch_cnt_copy(unsigned long long *counters, int dst, int src, hipStream_t s);
+// Spread counter slot = v.
+hipError_t launch_cnt_set(unsigned long long *counters, int slot, unsigned long long v,
+                          hipStream_t s);
 hipError_t launch_check_part(int64_t n, int32_t k, const int32_t *part,
                              unsigned long long *counters, hipStream_t s);
 
@@ -682,6 +685,8 @@ hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, con
                         int64_t dirty_threshold, uint8_t *dirty, const GraphView &tg,
                         const PartView &tpv, void *pc2, const int32_t *perm,
                         int64_t all_threshold, hipStream_t s, bool cut_delta = false);
+// iters < 0: iters and status derived on the device for a rebalancing that
+// ended after its speculative first sub-iteration.
 hipError_t launch_stats_final(int64_t *stats, const unsigned long long *counters, int64_t lmax,
                               int64_t iters, int64_t status, hipStream_t s);
 hipError_t launch_export_moves(int64_t n, const int64_t *key, const int64_t *pen,

@@ -561,7 +561,10 @@ def test_cut_from_apply_deltas(upr, ctx, monkeypatch):
     (above a forced threshold of 64) whose 300 leaves sit in the other block
     is the only node with a positive pessimistic gain: its move is summed by
     the hub-chunk walk; later rounds and a skewed start move ordinary nodes
-    (the tile walk) and, in the first rounds, enough to be recounted. Every
+    (the tile walk) and, in the first rounds, enough to be recounted. Their
+    rebalancing ends after its first sub-iteration in some rounds (the closing
+    statistics enqueued before the host's wait stand) and needs more in
+    others (they are taken again), with and without a recount. Every
     statistic equals the oracle's."""
     monkeypatch.setenv("UPR_HUB_THRESHOLD", "64")
     monkeypatch.setenv("UPR_DIRTY_DIV", "1")
@@ -582,9 +585,12 @@ def test_cut_from_apply_deltas(upr, ctx, monkeypatch):
     for name, g2, k in [("cl", gg.chung_lu(6000, 8.0, 2.3, seed=3), 8),
                         ("rmat_w", gg.with_weights(gg.rmat(12, 16, seed=4), 4, wmax=5), 16)]:
         pr = Pair(upr, ctx, g2, k, skewed_partition(g2.n, k, 5, 0.4))
+        iters = set()
         for r in range(1, 7):
             ost, odbg = pr.round(tau=gg.tau_schedule(r, 6))
             pr.compare(ost, odbg, f"{name} round {r}")
+            iters.add(int(O.stats_dict(ost)["rebalance_iters"]))
+        assert 1 in iters and max(iters) >= 2, iters
         ost = pr.rebalance()
         pr.compare(ost, None, f"{name} standalone rebalance")
 
