@@ -595,6 +595,26 @@ def test_cut_from_apply_deltas(upr, ctx, monkeypatch):
         pr.compare(ost, None, f"{name} standalone rebalance")
 
 
+def test_rounds_with_one_rebalancing_iteration(upr, ctx):
+    """Rounds with moves whose rebalancing may run one sub-iteration: it is
+    the speculative one, so the round's closing statistics enqueued before
+    the host's wait stand, with the status derived on the device (1 while
+    blocks stay overloaded, 0 once balanced). Every statistic, the
+    partition, W and the table equal the oracle's."""
+    for name, g2, k in [("cl", gg.chung_lu(6000, 8.0, 2.3, seed=3), 8),
+                        ("rmat_w", gg.with_weights(gg.rmat(12, 16, seed=4), 4, wmax=5), 16)]:
+        say(f"one rebalancing iteration case={name} n={g2.n} k={k}")
+        pr = Pair(upr, ctx, g2, k, skewed_partition(g2.n, k, 5, 0.4))
+        seen = set()
+        for r in range(1, 5):
+            ost, odbg = pr.round(tau=gg.tau_schedule(r, 4), max_rebalance_iters=1)
+            pr.compare(ost, odbg, f"{name} round {r}")
+            st = O.stats_dict(ost)
+            seen.add((int(st["rebalance_iters"]), int(st["status"])))
+        if name == "cl":
+            assert {(1, 0), (1, 1)} <= seen, seen
+
+
 # ------------------------------------------------------------ driver --
 
 @pytest.mark.parametrize("case", [("cl", 8), ("rgg", 16), ("rmat", 8), ("cl_w", 4)])
