@@ -301,6 +301,8 @@ def single_graph(ctx, g, k, eps, rounds, part0, steps, warmup, resident, hub_t=4
     bm_s = sum(x["phases"]["best_move_kernel"] for x in rec) / 1e3
     fl_bytes = sum(ew * x["cand_edges"] + 17 * n for x in rec)
     fl_s = sum(x["phases"]["filter_kernel"] for x in rec) / 1e3
+    if opts is not None and opts.dirty_div > 0:
+        dirty_div = opts.dirty_div  # the plan's own threshold
     dirty_threshold = nnz // dirty_div
     delta = [x for x in rec if x["acc_edges"] <= dirty_threshold and x["acc_edges"] > 0]
     ap_bytes = sum((ew + 16) * x["acc_edges"] for x in delta)
@@ -593,24 +595,35 @@ def serving(ctx, spec, eps=(3, 100), rounds=10, load=0.7, budget_gb=200.0, check
             "server_time_s": tim}
 
 
-def extra_workload(ctx, name, steps, warmup, cpu_seconds, oracle_rounds, no_cpu):
+def extra_workload(ctx, name, steps, warmup, cpu_seconds, oracle_rounds, no_cpu, tune_it=True):
     """One more single-graph workload: edges/s over its rounds, its kernel
     rooflines, and the oracle's first rounds for the baseline and parity
-    (statistics, partition and block weights)."""
+    (statistics, partition and block weights). tune_it: the plan's
+    thresholds are picked by timed trial rounds first (they never change a
+    result)."""
     from paper_2308_15494_amd import graphgen as gg
     t0 = time.perf_counter()
     g, k, eps, rounds, seed = gg.workload(name)
     part0 = gg.random_partition(g.n, k, seed)
     log(f"workload {name}: n={g.n} m={g.m} k={k} max_deg={g.meta['max_degree']} "
         f"gen {time.perf_counter() - t0:.1f}s")
+    opts, chosen, tune_s = None, "default", None
+    if tune_it:
+        from paper_2308_15494_amd import tune
+        t0 = time.perf_counter()
+        opts, tune_rep = tune.tune_graph(ctx, g, k, part0, eps, rounds=3, repeats=2,
+                                         total_rounds=rounds)
+        chosen, tune_s = tune_rep["chosen"], round(time.perf_counter() - t0, 2)
+        log(f"{name}: tuned thresholds {chosen} in {tune_s}s")
     res = single_graph(ctx, g, k, eps, rounds, part0, steps, warmup, False,
-                       phase_rounds=max(oracle_rounds, 3))
+                       phase_rounds=max(oracle_rounds, 3), opts=opts)
     res.pop("refiner").plan.close()
     out = {"value": res["value"], "unit": "edges/s", "ms_per_step": res["ms_per_step"],
            "steps": steps, "config": {"n": g.n, "m": g.m, "k": k, "eps": f"{eps[0]}/{eps[1]}",
                                       "rounds": rounds, "weighted": g.adjwgt is not None,
                                       "max_degree": res["info"]["max_degree"],
-                                      "hubs": res["info"]["num_hubs"], "form": "rebuild"},
+                                      "hubs": res["info"]["num_hubs"], "form": "rebuild",
+                                      "thresholds": chosen, "tune_s": tune_s},
            "roofline": res["rooflines"]["k_gain_tile"], "rooflines": res["rooflines"],
            "phases_ms_per_round": res["phases"], "final_stats": res["final"]}
     log(f"{name}: {out['value']:.3e} edges/s, {out['ms_per_step']:.3f} ms per round")
@@ -740,6 +753,9 @@ def main():
                     help="comma-separated further single-graph workloads ('' skips them)")
     ap.add_argument("--extra-oracle-rounds", type=int, default=1,
                     help="oracle rounds per further workload (baseline and parity)")
+    ap.add_argument("--extra-default-thresholds", action="store_true",
+                    help="run the further workloads with the default plan thresholds "
+                         "(default: tuned by trial rounds)")
     ap.add_argument("--prefix-oracle-rounds", type=int, default=4,
                     help="oracle rounds checked for the best-prefix leg (0 skips the leg)")
     ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1))
@@ -881,7 +897,8 @@ def main():
         out["workloads"] = {}
         for name in extra:
             out["workloads"][name] = extra_workload(ctx, name, args.steps, 2, args.cpu_seconds,
-                                                    args.extra_oracle_rounds, args.no_cpu)
+                                                    args.extra_oracle_rounds, args.no_cpu,
+                                                    tune_it=not args.extra_default_thresholds)
             torch.cuda.empty_cache()
 
     print(json.dumps(out), flush=True)
