@@ -120,6 +120,15 @@ hipError_t launch_rb_begin(const Blocks &bk, const int64_t *W, const RebalWs &r,
     return hipGetLastError();
 }
 
+// This workgroup's copy of a rebalancing histogram (copy blockIdx.x mod
+// hist_copies, each K * kRbBuckets entries): with few blocks the workgroups
+// of a node scan add to the same few entries, and atomics on one address
+// are serialised.
+__device__ __forceinline__ int64_t *rb_hist_copy(int64_t *h, const RebalWs &r, int32_t K)
+{
+    return h + (int64_t)(blockIdx.x % (unsigned)r.hist_copies) * K * kRbBuckets;
+}
+
 // ---------------------------------------------------------------- prepare --
 
 constexpr int kHistLdsBytes = 49152;
@@ -336,7 +345,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
                         if (h_lds) {
                             if (push) atomicAdd(&sH[hkey], (uint32_t)cv);
                         } else {
-                            wave_hist_add(r.hist_tgt, hkey, cv, push);
+                            wave_hist_add(rb_hist_copy(r.hist_tgt, r, K), hkey, cv, push);
                         }
                     }
                 }
@@ -347,8 +356,9 @@ __global__ __launch_bounds__(kBlock) void k_rb_prepare(GraphView g, Blocks bk,
     else scan_nodes(r.W0);
     if (h_lds) {
         __syncthreads();
+        int64_t *hT = rb_hist_copy(r.hist_tgt, r, K);
         for (int j = threadIdx.x; j < K * kRbBuckets; j += kBlock)
-            if (sH[j]) atomic_add_i64(&r.hist_tgt[j], (int64_t)sH[j]);
+            if (sH[j]) atomic_add_i64(&hT[j], (int64_t)sH[j]);
     }
 }
 
@@ -385,10 +395,24 @@ __global__ __launch_bounds__(kBlock) void k_rb_cutoffs(Blocks bk, RebalWs r, int
     int64_t *h = (target_side ? r.hist_tgt : r.hist_src) + (int64_t)j * kRbBuckets;
     const int64_t limit = !target_side ? w0 - lmax : lmax - w0;  // excess or capacity
     const int b1 = lane + 64;
-    const int64_t x0 = h[lane];
-    const int64_t x1 = b1 < kRbBuckets ? h[b1] : 0;
-    if (x0) h[lane] = 0;
-    if (x1) h[b1] = 0;
+    // the row summed over the histogram's copies (all loads issued first),
+    // each copy cleared after reading
+    const int64_t cstride = (int64_t)bk.total() * kRbBuckets;
+    int64_t y0[kRbHistCopiesMax], y1[kRbHistCopiesMax];
+#pragma unroll
+    for (int c = 0; c < kRbHistCopiesMax; ++c) {
+        const bool in = c < r.hist_copies;
+        y0[c] = in ? h[c * cstride + lane] : 0;
+        y1[c] = (in && b1 < kRbBuckets) ? h[c * cstride + b1] : 0;
+    }
+    int64_t x0 = 0, x1 = 0;
+#pragma unroll
+    for (int c = 0; c < kRbHistCopiesMax; ++c) {
+        x0 += y0[c];
+        x1 += y1[c];
+        if (y0[c]) h[c * cstride + lane] = 0;
+        if (y1[c]) h[c * cstride + b1] = 0;
+    }
     const int64_t c0 = wave_incl_scan(x0);
     const int64_t t0 = __shfl(c0, 63);
     const int64_t c1 = t0 + wave_incl_scan(x1);
@@ -512,14 +536,15 @@ __global__ __launch_bounds__(kBlock) void k_rb_src_hist(GraphView g, Blocks bk, 
             if (h_lds) {
                 if (sel) atomicAdd(&sH[hkey], (uint32_t)x.cv[i]);
             } else {
-                wave_hist_add(r.hist_src, hkey, sel ? x.cv[i] : 0, sel);
+                wave_hist_add(rb_hist_copy(r.hist_src, r, K), hkey, sel ? x.cv[i] : 0, sel);
             }
         }
     }
     if (h_lds) {
         __syncthreads();
+        int64_t *hS = rb_hist_copy(r.hist_src, r, K);
         for (int j = threadIdx.x; j < K * kRbBuckets; j += kBlock)
-            if (sH[j]) atomic_add_i64(&r.hist_src[j], (int64_t)sH[j]);
+            if (sH[j]) atomic_add_i64(&hS[j], (int64_t)sH[j]);
     }
 }
 

@@ -321,8 +321,8 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
               dalloc(&c->bucket, K * kSlots) == hipSuccess && dalloc(&c->pen1, K) == hipSuccess &&
               dalloc(&c->rb.rtgt, N) == hipSuccess && dalloc(&c->rb.rbeta, N) == hipSuccess &&
               dalloc(&c->rb.W0, K) == hipSuccess &&
-              dalloc(&c->rb.hist_src, K * kRbBuckets) == hipSuccess &&
-              dalloc(&c->rb.hist_tgt, K * kRbBuckets) == hipSuccess &&
+              dalloc(&c->rb.hist_src, rb_hist_copies(K) * K * kRbBuckets) == hipSuccess &&
+              dalloc(&c->rb.hist_tgt, rb_hist_copies(K) * K * kRbBuckets) == hipSuccess &&
               dalloc(&c->rb.cbeta_src, K) == hipSuccess && dalloc(&c->rb.cbeta_tgt, K) == hipSuccess &&
               dalloc(&c->rb.need_src, K) == hipSuccess && dalloc(&c->rb.room_tgt, K) == hipSuccess &&
               dalloc(&c->rb.theta_src, K) == hipSuccess && dalloc(&c->rb.theta_tgt, K) == hipSuccess &&
@@ -334,8 +334,9 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
         return fail(c, UPR_E_NOMEM, "workspace allocation failed for n=%lld k=%lld", (long long)N,
                     (long long)K);
     }
-    HIP_TRY(c, hipMemset(c->rb.hist_src, 0, sizeof(int64_t) * K * kRbBuckets));
-    HIP_TRY(c, hipMemset(c->rb.hist_tgt, 0, sizeof(int64_t) * K * kRbBuckets));
+    c->rb.hist_copies = rb_hist_copies(K);
+    HIP_TRY(c, hipMemset(c->rb.hist_src, 0, sizeof(int64_t) * c->rb.hist_copies * K * kRbBuckets));
+    HIP_TRY(c, hipMemset(c->rb.hist_tgt, 0, sizeof(int64_t) * c->rb.hist_copies * K * kRbBuckets));
     HIP_TRY(c, hipMemset(c->rb.chunk_src, 0, sizeof(int64_t) * kChunkEntries));
     HIP_TRY(c, hipMemset(c->rb.chunk_tgt, 0, sizeof(int64_t) * kChunkEntries));
     HIP_TRY(c, hipMemset(c->key, 0xff, sizeof(int64_t) * N));

@@ -699,8 +699,8 @@ struct RebalWs {
     int32_t *rtgt;       // [n] target block of a node of an overloaded block, -1 if none
     uint8_t *rbeta;      // [n] its priority bucket
     int64_t *W0;         // [K] block weights at sub-iteration start
-    int64_t *hist_src;   // [K * kRbBuckets]
-    int64_t *hist_tgt;   // [K * kRbBuckets]
+    int64_t *hist_src;   // [hist_copies * K * kRbBuckets]: copy c from c * K * kRbBuckets on
+    int64_t *hist_tgt;   // [hist_copies * K * kRbBuckets]
     int32_t *cbeta_src;  // [K] cutoff bucket per source block
     int32_t *cbeta_tgt;  // [K] cutoff bucket per target block
     int64_t *need_src;   // [K] weight still needed inside the cutoff bucket
@@ -712,7 +712,15 @@ struct RebalWs {
     int chunk_shift;     // a chunk holds 2^chunk_shift consecutive node ids of one graph
     int64_t nchunks;
     const int64_t *goff;  // batch: node offset of each graph (ng + 1 entries); null: one graph
+    int hist_copies;      // copies of each histogram (a node scan's workgroup adds to one)
 };
+
+// Copies of the rebalancing histograms for up to K blocks (their sum is read).
+constexpr int kRbHistCopiesMax = 8;
+inline int rb_hist_copies(int64_t K)
+{
+    return K * kRbBuckets * kRbHistCopiesMax <= ((int64_t)1 << 20) ? kRbHistCopiesMax : 1;
+}
 
 // Snapshot W and count the source blocks (weight above src_lmax): in total
 // (counters[CNT_OVER]) and, for a batch, per graph (gstat[g][GS_OVER]).
