@@ -126,7 +126,8 @@ hipError_t launch_rb_begin(const Blocks &bk, const int64_t *W, const RebalWs &r,
 // are serialised.
 __device__ __forceinline__ int64_t *rb_hist_copy(int64_t *h, const RebalWs &r, int32_t K)
 {
-    return h + (int64_t)(blockIdx.x % (unsigned)r.hist_copies) * K * kRbBuckets;
+    const unsigned c = r.hist_copies > 0 ? (unsigned)r.hist_copies : 1u;
+    return h + (int64_t)(blockIdx.x % c) * K * kRbBuckets;
 }
 
 // ---------------------------------------------------------------- prepare --
