@@ -243,7 +243,8 @@ __global__ __launch_bounds__(kBlock) void k_node_stats(GraphView g, Blocks bk,
                                                         int gs_slot,
                                                         const int32_t *__restrict__ inner,
                                                         const uint32_t *__restrict__ hub_bits,
-                                                        int cut_cond)
+                                                        int cut_cond, int64_t *wsp, int64_t *bsp,
+                                                        int ncopies)
 {
     if (cut_cond && wave_cnt_get(counters, CNT_CUT_STALE) == 0) {
         // every apply since the first pass summed its change of the cut
@@ -269,6 +270,11 @@ __global__ __launch_bounds__(kBlock) void k_node_stats(GraphView g, Blocks bk,
     __syncthreads();
     const int32_t B0 = win[0], nb = win[1];
     const int32_t g0 = bk.graph(B0);
+    // with copies (wsp / bsp) the sums go to this workgroup's copy, which the
+    // bucket prefix pass adds into W and the histogram
+    const unsigned cp = ncopies > 1 ? blockIdx.x % (unsigned)ncopies : 0u;
+    int64_t *Wd = (W && wsp) ? wsp + (int64_t)cp * K : W;
+    int64_t *Bd = (bucket && bsp) ? bsp + (int64_t)cp * K * kSlots : bucket;
     const bool w_lds = W && nb <= cap_w;
     const bool b_lds = bucket && nb <= cap_b;
     const bool s_lds = gstat && (nb + k - 1) / k <= kStatsGraphs;
@@ -334,8 +340,8 @@ __global__ __launch_bounds__(kBlock) void k_node_stats(GraphView g, Blocks bk,
             }
             if (W) {
                 if (w_lds && inw) atomicAdd((unsigned long long *)&lw[x], (unsigned long long)cv);
-                if (!w_lds) wave_hist_add(W, a, cv, ok);
-                else wave_hist_add(W, a, cv, ok && !inw);
+                if (!w_lds) wave_hist_add(Wd, a, cv, ok);
+                else wave_hist_add(Wd, a, cv, ok && !inw);
             }
             if (bucket) {
                 const bool avail = ok && (int64_t)t_den * inner >= (int64_t)t_num * wd;
@@ -344,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_node_stats(GraphView g, Blocks bk,
                 if (b_lds && avail && inw)
                     atomicAdd((unsigned long long *)&lb[(int64_t)x * kSlots + l],
                               (unsigned long long)cv);
-                wave_hist_add(bucket, (int64_t)a * kSlots + l, cv, avail && !(b_lds && inw));
+                wave_hist_add(Bd, (int64_t)a * kSlots + l, cv, avail && !(b_lds && inw));
             }
         }
     }
@@ -356,10 +362,10 @@ __global__ __launch_bounds__(kBlock) void k_node_stats(GraphView g, Blocks bk,
     __syncthreads();
     if (w_lds)
         for (int j = threadIdx.x; j < nb; j += kBlock)
-            if (lw[j]) atomic_add_i64(&W[B0 + j], lw[j]);
+            if (lw[j]) atomic_add_i64(&Wd[B0 + j], lw[j]);
     if (b_lds)
         for (int j = threadIdx.x; j < nb * kSlots; j += kBlock)
-            if (lb[j]) atomic_add_i64(&bucket[(int64_t)B0 * kSlots + j], lb[j]);
+            if (lb[j]) atomic_add_i64(&Bd[(int64_t)B0 * kSlots + j], lb[j]);
     if (s_lds)
         for (int j = threadIdx.x; j < kStatsGraphs; j += kBlock)
             if (gsl[j]) atomic_add_i64(&gstat[(int64_t)(g0 + j) * GS_COUNT + gs_slot], gsl[j]);
@@ -384,7 +390,8 @@ hipError_t launch_node_stats(const GraphView &g, const Blocks &bk, const StatsGe
                              int64_t *W, int64_t *bucket, int32_t t_num, int32_t t_den,
                              unsigned long long *counters, int cut_slot, uint8_t *avail,
                              int64_t *gstat, int gs_slot, hipStream_t s, const int32_t *inner,
-                             const uint32_t *hub_bits, bool cut_cond)
+                             const uint32_t *hub_bits, bool cut_cond, int64_t *wsp, int64_t *bsp,
+                             int ncopies)
 {
     if (g.n <= 0) return hipSuccess;
     const int64_t span = sg.span > 0 ? sg.span : stats_span(g.n, 0);
@@ -396,7 +403,7 @@ hipError_t launch_node_stats(const GraphView &g, const Blocks &bk, const StatsGe
     hipLaunchKernelGGL(k_node_stats, dim3((unsigned)rows), dim3(kBlock), lds, s, g, bk, sg.goff,
                        span, W ? cap_w : 0, bucket ? cap_b : 0, part, conn, wdeg, W, bucket, t_num,
                        t_den, counters, cut_slot, avail, gstat, gs_slot, inner, hub_bits,
-                       cut_cond && !W && !bucket && !gstat ? 1 : 0);
+                       cut_cond && !W && !bucket && !gstat ? 1 : 0, wsp, bsp, ncopies);
     return hipGetLastError();
 }
 

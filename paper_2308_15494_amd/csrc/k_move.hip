@@ -71,18 +71,42 @@ hipError_t launch_round_init(const Blocks &bk, int64_t *bucket, int64_t *W, cons
 // the least covering slot l, -1 if none.
 // One wave per block j: lane l holds slot l, a wave scan turns the slot
 // weights into cumulative ones, and the least slot that covers the excess is
-// the lowest lane of a ballot.
-__global__ __launch_bounds__(kBlock) void k_cb_prefix(Blocks bk, int64_t *bucket, const int64_t *W,
-                                                       int mode, int64_t *pen1)
+// the lowest lane of a ballot. With the statistics pass's copies (wsp, bsp),
+// block j's entries of every copy are first added into W[j] and its slot
+// weights, and cleared.
+__global__ __launch_bounds__(kBlock) void k_cb_prefix(Blocks bk, int64_t *bucket, int64_t *W,
+                                                       int mode, int64_t *pen1, int64_t *wsp,
+                                                       int64_t *bsp, int ncopies)
 {
     static_assert(kSlots <= 64, "one slot per lane");
+    static_assert(kStatsCopiesMax <= 64, "one copy per lane");
     const int64_t j = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
-    if (j >= bk.total()) return;  // whole waves
+    const int64_t K = bk.total();
+    if (j >= K) return;  // whole waves
     const int l = lane_id();
     int64_t *b = bucket + j * kSlots;
-    const int64_t run = wave_incl_scan(l < kSlots ? b[l] : (int64_t)0);
+    int64_t own = l < kSlots ? b[l] : (int64_t)0;
+    int64_t wj = W[j];
+    if (wsp) {
+        // every copy's entries loaded first, then summed and cleared
+        int64_t yb[kStatsCopiesMax];
+#pragma unroll
+        for (int c = 0; c < kStatsCopiesMax; ++c)
+            yb[c] = (c < ncopies && l < kSlots) ? bsp[((int64_t)c * K + j) * kSlots + l] : 0;
+        const int64_t yw = l < ncopies ? wsp[(int64_t)l * K + j] : 0;
+#pragma unroll
+        for (int c = 0; c < kStatsCopiesMax; ++c) {
+            own += yb[c];
+            if (yb[c]) bsp[((int64_t)c * K + j) * kSlots + l] = 0;
+        }
+        if (yw) wsp[(int64_t)l * K + j] = 0;
+        const int64_t sw = wave_sum(yw);
+        wj += sw;
+        if (l == 0 && sw) W[j] = wj;
+    }
+    const int64_t run = wave_incl_scan(own);
     if (l < kSlots) b[l] = run;
-    const int64_t x = W[j] + 1 - bk.move_lmax_of((int32_t)j);
+    const int64_t x = wj + 1 - bk.move_lmax_of((int32_t)j);
     const uint64_t cov = __ballot(l < kSlots && run >= x);
     if (l != 0) return;
     int64_t p = 0;
@@ -96,11 +120,12 @@ __global__ __launch_bounds__(kBlock) void k_cb_prefix(Blocks bk, int64_t *bucket
     pen1[j] = p;
 }
 
-hipError_t launch_cb_prefix(const Blocks &bk, int64_t *bucket, const int64_t *W, int mode,
-                            int64_t *pen1, hipStream_t s)
+hipError_t launch_cb_prefix(const Blocks &bk, int64_t *bucket, int64_t *W, int mode,
+                            int64_t *pen1, hipStream_t s, int64_t *wsp, int64_t *bsp, int ncopies)
 {
+    if (!wsp || !bsp || ncopies < 2) wsp = bsp = nullptr;
     hipLaunchKernelGGL(k_cb_prefix, dim3((unsigned)(((int64_t)bk.total() * 64 + kBlock - 1) / kBlock)),
-                       dim3(kBlock), 0, s, bk, bucket, W, mode, pen1);
+                       dim3(kBlock), 0, s, bk, bucket, W, mode, pen1, wsp, bsp, ncopies);
     return hipGetLastError();
 }
 

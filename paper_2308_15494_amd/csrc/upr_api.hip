@@ -96,6 +96,9 @@ struct upr_ctx {
     unsigned long long *counters = nullptr;
     unsigned long long *flags = nullptr;  // validation flags [4]
     RebalWs rb{};
+    int64_t *stat_wsp = nullptr;  // [stat_copies * K] copies of the statistics pass's W sums
+    int64_t *stat_bsp = nullptr;  // [stat_copies * K * kSlots] and of its slot histogram
+    int stat_copies = 1;
     unsigned long long *pinned = nullptr;  // host mirror of the counters' copies
     unsigned long long cnt[CNT_COUNT] = {0};  // their sums, after sync_counters
     // host-coherent [1 + CNT_COUNT]: a sequence number, then the counter sums
@@ -275,6 +278,8 @@ void free_workspace(upr_ctx *c)
     dfree(c->rb.rbeta);
     dfree(c->rb.W0);
     dfree(c->rb.hist_src);
+    dfree(c->stat_wsp);
+    dfree(c->stat_bsp);
     dfree(c->rb.hist_tgt);
     dfree(c->rb.cbeta_src);
     dfree(c->rb.cbeta_tgt);
@@ -322,6 +327,8 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
               dalloc(&c->rb.rtgt, N) == hipSuccess && dalloc(&c->rb.rbeta, N) == hipSuccess &&
               dalloc(&c->rb.W0, K) == hipSuccess &&
               dalloc(&c->rb.hist_src, rb_hist_copies(K) * K * kRbBuckets) == hipSuccess &&
+              dalloc(&c->stat_wsp, stats_copies(K) * K) == hipSuccess &&
+              dalloc(&c->stat_bsp, stats_copies(K) * K * kSlots) == hipSuccess &&
               dalloc(&c->rb.hist_tgt, rb_hist_copies(K) * K * kRbBuckets) == hipSuccess &&
               dalloc(&c->rb.cbeta_src, K) == hipSuccess && dalloc(&c->rb.cbeta_tgt, K) == hipSuccess &&
               dalloc(&c->rb.need_src, K) == hipSuccess && dalloc(&c->rb.room_tgt, K) == hipSuccess &&
@@ -335,6 +342,9 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
                     (long long)K);
     }
     c->rb.hist_copies = rb_hist_copies(K);
+    c->stat_copies = stats_copies(K);
+    HIP_TRY(c, hipMemset(c->stat_wsp, 0, sizeof(int64_t) * c->stat_copies * K));
+    HIP_TRY(c, hipMemset(c->stat_bsp, 0, sizeof(int64_t) * c->stat_copies * K * kSlots));
     HIP_TRY(c, hipMemset(c->rb.hist_src, 0, sizeof(int64_t) * c->rb.hist_copies * K * kRbBuckets));
     HIP_TRY(c, hipMemset(c->rb.hist_tgt, 0, sizeof(int64_t) * c->rb.hist_copies * K * kRbBuckets));
     HIP_TRY(c, hipMemset(c->rb.chunk_src, 0, sizeof(int64_t) * kChunkEntries));
@@ -1287,6 +1297,10 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
             HIP_TRY(c, launch_gain_table(tg, k, tpv, conn, p->hub_t, h, s, c->inner, pv));
         }
     }
+    // one graph with moves and without the best prefix: the statistics pass
+    // adds into copies that the bucket prefix pass, its first reader, sums
+    const bool spread = moves && !b && !prefix && c->stat_copies > 1;
+    int64_t *wsp = spread ? c->stat_wsp : nullptr, *bsp = spread ? c->stat_bsp : nullptr;
     {
         PhaseTimer t(c, 1, s);
         // the rebuilt table's own entries come from the tile build
@@ -1294,13 +1308,15 @@ static int round_core(upr_ctx *c, const upr_plan *p, upr_batch *b, const upr_par
                                      moves ? c->bucket : nullptr, q->t_num, q->t_den, c->counters,
                                      CNT_CUT2_BEFORE, moves && q->seq_penalty ? c->avail : nullptr,
                                      gstat, GS_CUT2_BEFORE, s, q->rebuild_table ? c->inner : nullptr,
-                                     p->nh > 0 ? p->hub_bits : nullptr));
+                                     p->nh > 0 ? p->hub_bits : nullptr, false, wsp, bsp,
+                                     c->stat_copies));
     }
     if (prefix) HIP_TRY(c, launch_bp_record_start(n, K, part, W, c->bp, s));
     if (moves) {
         {
             PhaseTimer t(c, 2, s);
-            HIP_TRY(c, launch_cb_prefix(bk, c->bucket, W, q->mode, c->pen1, s));
+            HIP_TRY(c, launch_cb_prefix(bk, c->bucket, W, q->mode, c->pen1, s, wsp, bsp,
+                                        c->stat_copies));
             // with the degree order, the flags and keys also in label order
             const bool rl = pv.flagged && pv.bytes == 1 && p->order;
             PhaseTimer tk(c, 8, s);

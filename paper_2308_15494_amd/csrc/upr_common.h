@@ -548,7 +548,18 @@ hipError_t launch_node_stats(const GraphView &g, const Blocks &bk, const StatsGe
                              unsigned long long *counters, int cut_slot, uint8_t *avail,
                              int64_t *gstat, int gs_slot, hipStream_t s,
                              const int32_t *inner = nullptr, const uint32_t *hub_bits = nullptr,
-                             bool cut_cond = false);
+                             bool cut_cond = false, int64_t *wsp = nullptr,
+                             int64_t *bsp = nullptr, int ncopies = 1);
+// Copies of the statistics pass's block weights and slot histogram for K
+// blocks (wsp [ncopies * K], bsp [ncopies * K * kSlots]; a workgroup adds to
+// copy blockIdx.x mod ncopies, so that the pass's workgroups do not all add
+// to the same entries): launch_cb_prefix with the same copies adds their sums
+// into W and the histogram and clears them. 1: no copies.
+constexpr int kStatsCopiesMax = 8;
+inline int stats_copies(int64_t K)
+{
+    return K * kSlots * kStatsCopiesMax <= ((int64_t)1 << 20) ? kStatsCopiesMax : 1;
+}
 hipError_t launch_block_weights(const GraphView &g, int32_t k, const int32_t *part, int64_t *W,
                                 unsigned long long *counters, hipStream_t s);
 // 2 * cut from the adjacency into the spread counter `slot`; out = that / 2.
@@ -576,8 +587,9 @@ hipError_t launch_round_init(const Blocks &bk, int64_t *bucket, int64_t *W, cons
                              int32_t k = 0);
 // Prefix sums of the buckets; pen1[B] = penalty of a unit-weight node moving
 // into B (0 if it fits, -1 if forbidden).
-hipError_t launch_cb_prefix(const Blocks &bk, int64_t *bucket, const int64_t *W, int mode,
-                            int64_t *pen1, hipStream_t s);
+hipError_t launch_cb_prefix(const Blocks &bk, int64_t *bucket, int64_t *W, int mode,
+                            int64_t *pen1, hipStream_t s, int64_t *wsp = nullptr,
+                            int64_t *bsp = nullptr, int ncopies = 1);
 // active (may be null: every node): only nodes with active[v] != 0 look for
 // a move. cflag (may be null): the compact partition copy whose bit 7 marks
 // the candidates; cflag2 / key2 / perm (may be null): the flagged copy and
