@@ -1117,7 +1117,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, Blocks bk, int32_
                                                    const unsigned long long *counters,
                                                    int64_t dirty_threshold, uint8_t *dirty_flags,
                                                    int T, void *pc2, const int32_t *perm,
-                                                   int64_t all_threshold)
+                                                   int64_t all_threshold, int64_t *wcp,
+                                                   int ncopies)
 {
     __shared__ int32_t vstart[kApplyTile + 1];
     __shared__ int64_t estart[kApplyTile];
@@ -1237,9 +1238,12 @@ __global__ __launch_bounds__(kBlock) void k_apply(GraphView g, Blocks bk, int32_
         }
     }
     if (use_lds) {
+        // with copies (wcp) into this workgroup's copy, which the next
+        // rebalancing begin adds into W
+        int64_t *Wd = wcp ? wcp + (int64_t)(blockIdx.x % (unsigned)ncopies) * K : W;
         __syncthreads();
         for (int j = threadIdx.x; j < K; j += kBlock)
-            if (wloc[j]) atomic_add_i64(&W[j], wloc[j]);
+            if (wloc[j]) atomic_add_i64(&Wd[j], wloc[j]);
     }
 }
 
@@ -1410,9 +1414,11 @@ hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, con
                         const HubView &h, unsigned long long *counters,
                         int64_t dirty_threshold, uint8_t *dirty, const GraphView &tg,
                         const PartView &tpv, void *pc2, const int32_t *perm,
-                        int64_t all_threshold, hipStream_t s, bool cut_delta)
+                        int64_t all_threshold, hipStream_t s, bool cut_delta, int64_t *wcp,
+                        int ncopies)
 {
     if (g.n <= 0) return hipSuccess;
+    if (!wcp || ncopies < 2) wcp = nullptr;
     const int32_t k = bk.k;
     const int T = gain_tile_nodes(k, g.n);
     const size_t lds = bk.total() <= 2048 ? (size_t)bk.total() * 8 : 0;
@@ -1435,11 +1441,11 @@ hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, con
     if (bk.total() <= 2048)
         hipLaunchKernelGGL(k_apply<true>, dim3((unsigned)tiles), dim3(kBlock), lds, s, g, bk, part,
                            pv, conn, W, mvto, hub_t, counters, dirty_threshold, dirty, T, pc2, perm,
-                           all_threshold);
+                           all_threshold, wcp, ncopies);
     else
         hipLaunchKernelGGL(k_apply<false>, dim3((unsigned)tiles), dim3(kBlock), lds, s, g, bk, part,
                            pv, conn, W, mvto, hub_t, counters, dirty_threshold, dirty, T, pc2, perm,
-                           all_threshold);
+                           all_threshold, nullptr, 1);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // rebuild the marked tiles and the hub rows (nothing in the delta mode)
     return launch_gain_refresh(tg, k, tpv, conn, hub_t, h, dirty, counters, dirty_threshold,

@@ -65,11 +65,14 @@ __device__ __forceinline__ bool rb_kept(const RbView &r, int64_t v, int32_t a, i
 // ------------------------------------------------------------------ begin --
 
 // Count source blocks and snapshot W (one workgroup). For a batch, also per
-// graph: gstat[g][GS_OVER]. first: the count also goes to CNT_OVER0.
-__global__ __launch_bounds__(kBlock) void k_rb_begin(Blocks bk, const int64_t *W, int64_t *W0,
+// graph: gstat[g][GS_OVER]. first: the count also goes to CNT_OVER0. wcp
+// (may be null): the apply's copies of its block-weight sums, added into W
+// first and cleared.
+__global__ __launch_bounds__(kBlock) void k_rb_begin(Blocks bk, int64_t *W, int64_t *W0,
                                                       unsigned long long *counters, int64_t *gstat,
                                                       int first, unsigned long long *pub,
-                                                      unsigned long long seq)
+                                                      unsigned long long seq, int64_t *wcp,
+                                                      int ncopies)
 {
     __shared__ unsigned long long red[4];
     const int32_t K = bk.total();
@@ -79,7 +82,21 @@ __global__ __launch_bounds__(kBlock) void k_rb_begin(Blocks bk, const int64_t *W
     }
     unsigned long long over = 0;
     for (int j = threadIdx.x; j < K; j += kBlock) {
-        const int64_t w = W[j];
+        int64_t w = W[j];
+        if (wcp) {
+            int64_t y[kApplyCopiesMax];
+#pragma unroll
+            for (int c = 0; c < kApplyCopiesMax; ++c)
+                y[c] = c < ncopies ? wcp[(int64_t)c * K + j] : 0;
+            int64_t d = 0;
+#pragma unroll
+            for (int c = 0; c < kApplyCopiesMax; ++c) {
+                d += y[c];
+                if (y[c]) wcp[(int64_t)c * K + j] = 0;
+            }
+            if (d) W[j] = w + d;
+            w += d;
+        }
         W0[j] = w;
         const bool o = w > bk.src_lmax_of(j);
         over += o;
@@ -111,12 +128,14 @@ __global__ __launch_bounds__(kBlock) void k_rb_begin(Blocks bk, const int64_t *W
     if (threadIdx.x == 0) __hip_atomic_store(&pub[0], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-hipError_t launch_rb_begin(const Blocks &bk, const int64_t *W, const RebalWs &r,
+hipError_t launch_rb_begin(const Blocks &bk, int64_t *W, const RebalWs &r,
                            unsigned long long *counters, int64_t *gstat, hipStream_t s, int first,
-                           unsigned long long *pub, unsigned long long seq)
+                           unsigned long long *pub, unsigned long long seq, int64_t *wcp,
+                           int ncopies)
 {
+    if (!wcp || ncopies < 2) wcp = nullptr;
     hipLaunchKernelGGL(k_rb_begin, dim3(1), dim3(kBlock), 0, s, bk, W, r.W0, counters, gstat,
-                       first, pub, seq);
+                       first, pub, seq, wcp, ncopies);
     return hipGetLastError();
 }
 

@@ -99,6 +99,7 @@ struct upr_ctx {
     int64_t *stat_wsp = nullptr;  // [stat_copies * K] copies of the statistics pass's W sums
     int64_t *stat_bsp = nullptr;  // [stat_copies * K * kSlots] and of its slot histogram
     int stat_copies = 1;
+    int64_t *apply_wcp = nullptr;  // [kApplyCopiesMax * K] copies of the applies' W sums
     unsigned long long *pinned = nullptr;  // host mirror of the counters' copies
     unsigned long long cnt[CNT_COUNT] = {0};  // their sums, after sync_counters
     // host-coherent [1 + CNT_COUNT]: a sequence number, then the counter sums
@@ -279,6 +280,7 @@ void free_workspace(upr_ctx *c)
     dfree(c->rb.W0);
     dfree(c->rb.hist_src);
     dfree(c->stat_wsp);
+    dfree(c->apply_wcp);
     dfree(c->stat_bsp);
     dfree(c->rb.hist_tgt);
     dfree(c->rb.cbeta_src);
@@ -328,6 +330,7 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
               dalloc(&c->rb.W0, K) == hipSuccess &&
               dalloc(&c->rb.hist_src, rb_hist_copies(K) * K * kRbBuckets) == hipSuccess &&
               dalloc(&c->stat_wsp, stats_copies(K) * K) == hipSuccess &&
+              dalloc(&c->apply_wcp, (int64_t)kApplyCopiesMax * K) == hipSuccess &&
               dalloc(&c->stat_bsp, stats_copies(K) * K * kSlots) == hipSuccess &&
               dalloc(&c->rb.hist_tgt, rb_hist_copies(K) * K * kRbBuckets) == hipSuccess &&
               dalloc(&c->rb.cbeta_src, K) == hipSuccess && dalloc(&c->rb.cbeta_tgt, K) == hipSuccess &&
@@ -344,6 +347,7 @@ int ensure_workspace(upr_ctx *c, int64_t n, int32_t k)
     c->rb.hist_copies = rb_hist_copies(K);
     c->stat_copies = stats_copies(K);
     HIP_TRY(c, hipMemset(c->stat_wsp, 0, sizeof(int64_t) * c->stat_copies * K));
+    HIP_TRY(c, hipMemset(c->apply_wcp, 0, sizeof(int64_t) * kApplyCopiesMax * K));
     HIP_TRY(c, hipMemset(c->stat_bsp, 0, sizeof(int64_t) * c->stat_copies * K * kSlots));
     HIP_TRY(c, hipMemset(c->rb.hist_src, 0, sizeof(int64_t) * c->rb.hist_copies * K * kRbBuckets));
     HIP_TRY(c, hipMemset(c->rb.hist_tgt, 0, sizeof(int64_t) * c->rb.hist_copies * K * kRbBuckets));
@@ -576,8 +580,10 @@ static PartView table_part(const upr_ctx *c, const upr_plan *p, const PartView &
 }
 
 // S4 for the moves marked in mvto; rebuilt tiles and hub rows are built from
-// the table build's views. cut_delta: the apply also sums its change of the
-// cut (one graph), which spares the statistics pass after it.
+// the table build's views. cut_delta (one graph without the best prefix): the
+// apply also sums its change of the cut, which spares the statistics pass
+// after it, and adds its block-weight sums into copies that the rebalancing
+// begin after it (W's next reader) adds into W.
 static hipError_t apply_moves(upr_ctx *c, const upr_plan *p, const Blocks &bk, int32_t *part,
                               const PartView &pv, int32_t *conn, int64_t *W, hipStream_t s,
                               bool cut_delta)
@@ -585,7 +591,7 @@ static hipError_t apply_moves(upr_ctx *c, const upr_plan *p, const Blocks &bk, i
     return launch_apply(p->g, bk, part, pv, conn, W, c->mvto, p->hub_t, p->hubs(), c->counters,
                         p->dirty_threshold, c->dirty, p->table_graph(), table_part(c, p, pv),
                         p->order ? (void *)c->pc2 : nullptr, p->perm, p->all_threshold, s,
-                        cut_delta);
+                        cut_delta, cut_delta ? c->apply_wcp : nullptr, kApplyCopiesMax);
 }
 
 // S5: the host loop over synchronous sub-iterations (one graph).
@@ -607,7 +613,8 @@ int rebalance_loop(upr_ctx *c, const upr_plan *p, const Blocks &bk, int plain, i
     // host waits for the last one's
     auto begin = [&](int first) -> int {
         HIP_TRY(c, launch_rb_begin(bk, W, c->rb, c->counters, nullptr, s, first, c->pub_d,
-                                   ++c->pub_seq));
+                                   ++c->pub_seq, cut_delta ? c->apply_wcp : nullptr,
+                                   kApplyCopiesMax));
         return UPR_OK;
     };
     auto sync = [&]() -> int {

@@ -696,7 +696,12 @@ hipError_t launch_apply(const GraphView &g, const Blocks &bk, int32_t *part, con
                         const HubView &h, unsigned long long *counters,
                         int64_t dirty_threshold, uint8_t *dirty, const GraphView &tg,
                         const PartView &tpv, void *pc2, const int32_t *perm,
-                        int64_t all_threshold, hipStream_t s, bool cut_delta = false);
+                        int64_t all_threshold, hipStream_t s, bool cut_delta = false,
+                        int64_t *wcp = nullptr, int ncopies = 1);
+// Copies of the apply's block-weight sums (wcp [ncopies * K]; a workgroup
+// adds to copy blockIdx.x mod ncopies instead of all of them to W): the next
+// launch_rb_begin with the same copies adds them into W and clears them.
+constexpr int kApplyCopiesMax = 8;
 // iters < 0: iters and status derived on the device for a rebalancing that
 // ended after its speculative first sub-iteration.
 hipError_t launch_stats_final(int64_t *stats, const unsigned long long *counters, int64_t lmax,
@@ -739,10 +744,10 @@ inline int rb_hist_copies(int64_t K)
 // pub (host-coherent memory, may be null): the sums of all CNT_COUNT counters
 // go to pub[1 + slot], then pub[0] = seq with a system-scope release, so the
 // host can read them without waiting for the stream.
-hipError_t launch_rb_begin(const Blocks &bk, const int64_t *W, const RebalWs &r,
+hipError_t launch_rb_begin(const Blocks &bk, int64_t *W, const RebalWs &r,
                            unsigned long long *counters, int64_t *gstat, hipStream_t s,
                            int first = 0, unsigned long long *pub = nullptr,
-                           unsigned long long seq = 0);
+                           unsigned long long seq = 0, int64_t *wcp = nullptr, int ncopies = 1);
 // One sub-iteration up to the move marks: targets and buckets, source and
 // target selection; accepted nodes get mvto[v] = target. hist32: the
 // per-workgroup histograms may use 32-bit LDS counters (no overflow).
